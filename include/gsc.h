@@ -1,0 +1,199 @@
+/*
+ * gsc.h -- C ABI of the MI355X (gfx950) Gaussian-frame codec: the per-frame hot path of GS-NFS
+ * (arXiv 2606.05650) -- positions as octree occupancy bytes, attributes as quantized RAHT
+ * coefficients.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Pointers named d_* are device pointers (HIP device memory of the current device); all
+ *   others are host pointers. The caller owns every buffer; the library never allocates or
+ *   frees memory, and never synchronizes the stream.
+ * - `stream` is a hipStream_t passed as void* (NULL = the null stream). Every call only
+ *   enqueues work on that stream and returns; results are valid once the stream has been
+ *   synchronized. Calls are re-entrant as long as concurrent calls use distinct workspaces.
+ * - Argument errors are returned synchronously as a gsc_status and nothing is enqueued.
+ *   Errors found on the device (a corrupt stream, a capacity overflow) are written as a
+ *   gsc_status code to the device info word of the call (see gsc_info) and every later kernel
+ *   of the same call returns without writing outputs.
+ * - Integers in device buffers are little-endian. Float attributes are IEEE binary32.
+ *
+ * Octree depth J is 1..21 (Morton codes are 3J <= 63 bits, Sec. 2.2), channels C are 1..64.
+ */
+#ifndef GSC_H
+#define GSC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GSC_MAX_DEPTH 21
+#define GSC_MAX_CHANNELS 64
+#define GSC_MAX_BATCH 64
+#define GSC_HEADER_BYTES 1024u
+#define GSC_MAGIC 0x31435347u /* "GSC1" */
+#define GSC_VERSION 1u
+
+typedef enum gsc_status {
+    GSC_OK = 0,
+    GSC_ERR_INVALID_ARG = 1,    /* null pointer, negative size, bad step or tau          */
+    GSC_ERR_DEPTH = 2,          /* J outside 1..21 or C outside 1..64                    */
+    GSC_ERR_WORKSPACE = 3,      /* workspace smaller than gsc_workspace_size()           */
+    GSC_ERR_CAPACITY = 4,       /* output buffer smaller than required                   */
+    GSC_ERR_CORRUPT_STREAM = 5, /* header or occupancy bytes inconsistent (device-side)  */
+    GSC_ERR_HIP = 6,            /* a HIP launch failed                                   */
+    GSC_ERR_INTERNAL = 7        /* a device-side invariant failed (a bug; please report) */
+} gsc_status;
+
+/* Coding parameters of one frame.
+ * quant_step[c] > 0 is the uniform quantization step of channel c, used for every RAHT
+ * coefficient of that channel (Sec. 3.4); q = sgn(y) floor(|y|/step + tau), y^ = q * step.
+ * tau in [0, 1): 0.5 rounds half away from zero; smaller values widen the dead zone.
+ * bbox_mode 0 voxelizes inside the cube bounding the frame (per-axis minimum, cell =
+ * largest extent / 2^J, Sec. 2.1); bbox_mode 1 uses bbox_min and cell as given (points
+ * outside the box are clamped into it), which keeps the grid fixed across a sequence. */
+typedef struct gsc_params {
+    int32_t J;
+    int32_t C;
+    float quant_step[GSC_MAX_CHANNELS];
+    float tau;
+    int32_t bbox_mode;
+    double bbox_min[3];
+    double cell;
+} gsc_params;
+
+/* Layout of the encoded stream (the first GSC_HEADER_BYTES of every stream).
+ * Byte layout: [header][occupancy bytes: levels 0..J-1, each in Morton order, one byte per
+ * internal node, bit i set <=> child (p << 3) + i occupied (Sec. 2.2, Alg. 1)][zero padding
+ * to a multiple of 256][coefficients: int32, Nv rows x C channels, row-major; row 0 holds the
+ * DC, row i > 0 the high-pass coefficient stored at voxel i (Sec. 3.1, Alg. 6)]. */
+typedef struct gsc_header {
+    uint32_t magic;          /* GSC_MAGIC                                      */
+    uint32_t version;        /* GSC_VERSION                                    */
+    uint32_t J, C;           /* octree depth and channel count                 */
+    uint32_t n_in;           /* Gaussians in the encoded frame                 */
+    uint32_t n_vox;          /* occupied voxels Nv = |L_J|                     */
+    uint32_t level_sizes[22];/* |L_0| .. |L_J| (Alg. 1 step 3), rest zero      */
+    uint32_t error;          /* 0, or the gsc_status the encoder failed with   */
+    uint32_t reserved0;
+    double bbox_min[3];      /* voxel grid origin                              */
+    double cell;             /* voxel edge length                              */
+    float quant_step[64];    /* per-channel steps, C used                      */
+    float tau;
+    uint32_t reserved1;
+    uint64_t occ_offset;     /* = GSC_HEADER_BYTES                             */
+    uint64_t occ_bytes;      /* sum of |L_d| for d < J                         */
+    uint64_t coef_offset;    /* 256-byte aligned                               */
+    uint64_t coef_bytes;     /* Nv * C * 4                                     */
+    uint64_t total_bytes;    /* coef_offset + coef_bytes                       */
+} gsc_header;
+
+/* Device info words written by every call: [0] gsc_status of the device side (0 = ok),
+ * [1] Nv, [2..3] stream bytes (encode) as uint64, [4] number of RAHT tiling levels used. */
+#define GSC_INFO_WORDS 8
+
+/* ------------------------------------------------------------------------------------------
+ * Sizes.
+ * gsc_workspace_size: device scratch bytes needed by one call on frames of at most n_max
+ *   Gaussians (encode) or voxels (decode) at depth J with C channels. Returns GSC_OK.
+ * gsc_stream_capacity: worst-case encoded stream bytes for such a frame (header + one byte
+ *   per possible internal node + padding + n_max * C coefficients).
+ * ---------------------------------------------------------------------------------------- */
+gsc_status gsc_workspace_size(int64_t n_max, int32_t J, int32_t C, size_t *bytes);
+gsc_status gsc_stream_capacity(int64_t n_max, int32_t J, int32_t C, size_t *bytes);
+
+/* ------------------------------------------------------------------------------------------
+ * gsc_encode_frame -- encode one frame (Sec. 2.2 voxelization, octree construction and
+ * bitstream generation, Alg. 1; Sec. 3.2-3.4 RAHT prelude, transform and quantization,
+ * Alg. 4-6).
+ *   d_pos    [n][3] float positions, d_attr [n][C] float attributes (row-major).
+ *   d_stream output stream of stream_cap bytes (>= gsc_stream_capacity(n, J, C)).
+ *   d_ws     workspace of ws_bytes (>= gsc_workspace_size(n, J, C)).
+ *   d_info   device int32[GSC_INFO_WORDS] written with the device status and sizes.
+ *   d_coef_f32 optional [n][C] float: the unquantized coefficients (rows 0..Nv-1), or NULL.
+ *   d_leaf_codes optional [n] uint64: the sorted voxel Morton codes L_J, or NULL.
+ * Positions must be finite. n may be 0 (an empty stream). Duplicates (Gaussians in one
+ * voxel) are replaced by one voxel whose attributes are their mean (Sec. 2.1).
+ * ---------------------------------------------------------------------------------------- */
+gsc_status gsc_encode_frame(const float *d_pos, const float *d_attr, int64_t n,
+                            const gsc_params *params, void *d_stream, size_t stream_cap,
+                            void *d_ws, size_t ws_bytes, int32_t *d_info, float *d_coef_f32,
+                            uint64_t *d_leaf_codes, void *stream);
+
+/* ------------------------------------------------------------------------------------------
+ * gsc_decode_frame -- decode one stream (Sec. 2.3 and Alg. 2-3 octree expansion and Morton
+ * decode; Alg. 6 inverse RAHT after dequantization).
+ *   d_stream, stream_bytes: an encoded stream on the device.
+ *   J, C: the depth and channel count the caller expects; the header must agree.
+ *   n_cap: capacity in voxels of the outputs (>= the stream's Nv).
+ *   d_pos_out [n_cap][3] float voxel centres (bbox_min + (v + 1/2) * cell, in FP64 then
+ *     rounded to float); d_vox_out optional [n_cap][3] uint32 voxel coordinates;
+ *   d_attr_out [n_cap][C] float attributes; d_leaf_codes optional [n_cap] uint64.
+ *   Rows are in Morton order; Nv is written to d_info[1].
+ * A stream whose occupancy bytes do not reproduce its level sizes, or that has a zero byte,
+ * is reported as GSC_ERR_CORRUPT_STREAM in d_info[0].
+ * ---------------------------------------------------------------------------------------- */
+gsc_status gsc_decode_frame(const void *d_stream, size_t stream_bytes, int32_t J, int32_t C,
+                            int64_t n_cap, float *d_pos_out, uint32_t *d_vox_out,
+                            float *d_attr_out, uint64_t *d_leaf_codes, void *d_ws,
+                            size_t ws_bytes, int32_t *d_info, void *stream);
+
+/* ------------------------------------------------------------------------------------------
+ * gsc_encode_batch -- encode F frames (F <= GSC_MAX_BATCH) of uneven sizes with one launch
+ * per pipeline stage for the whole batch (every kernel covers the tiles of all frames).
+ * frames[f] gives frame f's inputs and outputs (host array of descriptors holding device
+ * pointers); each frame needs its own workspace of gsc_workspace_size(n_f, J, C) bytes.
+ * The results are identical, byte for byte, to F calls of gsc_encode_frame.
+ * ---------------------------------------------------------------------------------------- */
+typedef struct gsc_frame_desc {
+    const float *d_pos;
+    const float *d_attr;
+    int64_t n;
+    void *d_stream;
+    size_t stream_cap;
+    void *d_ws;
+    size_t ws_bytes;
+    int32_t *d_info;
+} gsc_frame_desc;
+
+gsc_status gsc_encode_batch(const gsc_frame_desc *frames, int32_t F, const gsc_params *params,
+                            void *stream);
+
+/* gsc_decode_batch -- decode F streams with one launch per stage (see gsc_encode_batch). */
+typedef struct gsc_stream_desc {
+    const void *d_stream;
+    size_t stream_bytes;
+    int64_t n_cap;
+    float *d_pos_out;
+    float *d_attr_out;
+    void *d_ws;
+    size_t ws_bytes;
+    int32_t *d_info;
+} gsc_stream_desc;
+
+gsc_status gsc_decode_batch(const gsc_stream_desc *streams, int32_t F, int32_t J, int32_t C,
+                            void *stream);
+
+/* ------------------------------------------------------------------------------------------
+ * gsc_raht_forward / gsc_raht_adjoint -- the orthonormal transform alone, on float
+ * attributes of voxels already in Morton order (Eq. 1 and Alg. 4-6 on all 3J levels):
+ *   Y = T A (forward) and A = T^T Y (adjoint, which is the inverse since T is orthonormal).
+ *   d_codes [nv] sorted distinct Morton codes; d_in, d_out [nv][C] float (may not alias).
+ * Used by the straight-through differentiable coder: its backward pass is the adjoint.
+ * ---------------------------------------------------------------------------------------- */
+gsc_status gsc_raht_forward(const uint64_t *d_codes, int64_t nv, int32_t J, int32_t C,
+                            const float *d_in, float *d_out, void *d_ws, size_t ws_bytes,
+                            int32_t *d_info, void *stream);
+gsc_status gsc_raht_adjoint(const uint64_t *d_codes, int64_t nv, int32_t J, int32_t C,
+                            const float *d_in, float *d_out, void *d_ws, size_t ws_bytes,
+                            int32_t *d_info, void *stream);
+
+/* Human-readable name of a status code (static string). */
+const char *gsc_status_string(gsc_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GSC_H */

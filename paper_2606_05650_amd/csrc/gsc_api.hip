@@ -1,0 +1,419 @@
+// Host side of the C ABI declared in include/gsc.h: argument checks, workspace layout, and the
+// launch sequence of every entry point. Nothing here allocates device memory or synchronizes.
+#include <math.h>
+#include <string.h>
+
+#include "gsc_internal.h"
+
+namespace gsc {
+uint32_t bbox_blocks(uint32_t n);
+uint32_t voxelize_blocks(uint32_t n);
+}  // namespace gsc
+
+using namespace gsc;
+
+namespace {
+
+// ------------------------------------------------------------------------ checks
+gsc_status check_shape(int32_t J, int32_t C)
+{
+    if (J < 1 || J > GSC_MAX_DEPTH || C < 1 || C > GSC_MAX_CHANNELS) return GSC_ERR_DEPTH;
+    return GSC_OK;
+}
+
+gsc_status check_params(const gsc_params *p)
+{
+    if (!p) return GSC_ERR_INVALID_ARG;
+    gsc_status st = check_shape(p->J, p->C);
+    if (st != GSC_OK) return st;
+    for (int c = 0; c < p->C; ++c)
+        if (!(p->quant_step[c] > 0.0f) || !isfinite(p->quant_step[c])) return GSC_ERR_INVALID_ARG;
+    if (!(p->tau >= 0.0f && p->tau < 1.0f)) return GSC_ERR_INVALID_ARG;
+    if (p->bbox_mode != 0 && p->bbox_mode != 1) return GSC_ERR_INVALID_ARG;
+    if (p->bbox_mode == 1) {
+        if (!(p->cell > 0.0) || !isfinite(p->cell)) return GSC_ERR_INVALID_ARG;
+        for (int a = 0; a < 3; ++a)
+            if (!isfinite(p->bbox_min[a])) return GSC_ERR_INVALID_ARG;
+    }
+    return GSC_OK;
+}
+
+constexpr int64_t N_LIMIT = (1ll << 30) - 1;  // sort status words hold 30-bit counts
+
+uint64_t stream_capacity(int64_t n, int J, int C)
+{
+    uint64_t occ = 0;
+    for (int d = 0; d < J; ++d) occ += level_cap(d, (uint64_t)n);
+    if (n == 0) occ = 0;
+    return align_up(GSC_HEADER_BYTES + occ, 256) + (uint64_t)n * (uint64_t)C * 4u;
+}
+
+// ------------------------------------------------------------------- launch plumbing
+struct Frame {
+    Layout L;
+    FrameArgs a;
+};
+
+// Builds the tile map of one kernel: frame f gets blocks(f) workgroups.
+template <class Fn>
+TileMap make_map(const Frame *fr, int F, Fn blocks)
+{
+    TileMap m;
+    memset(&m, 0, sizeof(m));
+    m.F = (uint32_t)F;
+    m.start[0] = 0;
+    for (int f = 0; f < F; ++f) {
+        m.start[f + 1] = m.start[f] + blocks(fr[f]);
+        m.fd[f] = reinterpret_cast<FrameDesc *>(fr[f].a.ws + DESC_OFF);
+    }
+    return m;
+}
+
+#define GSC_LAUNCH(expr)                                    \
+    do {                                                    \
+        if ((expr) != hipSuccess) return GSC_ERR_HIP;       \
+    } while (0)
+
+gsc_status run_setup(const Frame *fr, int F, const SetupArgs &proto, hipStream_t s)
+{
+    for (int f0 = 0; f0 < F; f0 += SETUP_MAX) {
+        SetupArgs a = proto;
+        a.count = (uint32_t)((F - f0) < SETUP_MAX ? (F - f0) : SETUP_MAX);
+        uint64_t zmax = 0;
+        for (uint32_t i = 0; i < a.count; ++i) {
+            a.f[i] = fr[f0 + i].a;
+            if (fr[f0 + i].L.zero_bytes > zmax) zmax = fr[f0 + i].L.zero_bytes;
+        }
+        uint32_t zb = ceil_div(zmax / 16 + 1, 256 * 4);
+        if (zb < 1) zb = 1;
+        if (zb > 1024) zb = 1024;
+        GSC_LAUNCH(launch_setup(a, zb, s));
+    }
+    return GSC_OK;
+}
+
+SetupArgs make_proto(uint32_t J, uint32_t C, uint32_t mode, const gsc_params *p)
+{
+    SetupArgs a;
+    memset(&a, 0, sizeof(a));
+    a.J = J;
+    a.C = C;
+    a.mode = mode;
+    if (p) {
+        a.bbox_mode = (uint32_t)p->bbox_mode;
+        a.tau = p->tau;
+        for (int i = 0; i < 3; ++i) a.bbox_min[i] = p->bbox_min[i];
+        a.cell = p->cell;
+        for (int c = 0; c < GSC_MAX_CHANNELS; ++c) a.step[c] = c < (int)C ? p->quant_step[c] : 1.0f;
+    } else {
+        for (int c = 0; c < GSC_MAX_CHANNELS; ++c) a.step[c] = 1.0f;
+    }
+    return a;
+}
+
+int max_K(const Frame *fr, int F)
+{
+    int K = 0;
+    for (int f = 0; f < F; ++f)
+        if ((int)fr[f].L.K > K) K = (int)fr[f].L.K;
+    return K;
+}
+
+gsc_status run_prelude(const Frame *fr, int F, hipStream_t s)
+{
+    const int K = max_K(fr, F);
+    for (int k = 1; k <= K; ++k) {
+        TileMap m = make_map(fr, F, [k](const Frame &x) { return (int)x.L.K >= k ? x.L.tiles[k] : 0u; });
+        if (m.start[F] == 0) continue;
+        GSC_LAUNCH(launch_prelude(m, k, s));
+    }
+    return GSC_OK;
+}
+
+gsc_status run_forward(const Frame *fr, int F, int C4, hipStream_t s)
+{
+    const int K = max_K(fr, F);
+    for (int k = 1; k <= K; ++k) {
+        TileMap m = make_map(fr, F, [k](const Frame &x) { return (int)x.L.K >= k ? x.L.tiles[k] : 0u; });
+        if (m.start[F] == 0) continue;
+        GSC_LAUNCH(launch_raht_fwd(m, k, C4, s));
+    }
+    return GSC_OK;
+}
+
+gsc_status run_inverse(const Frame *fr, int F, int C4, hipStream_t s)
+{
+    const int K = max_K(fr, F);
+    for (int k = K; k >= 1; --k) {
+        TileMap m = make_map(fr, F, [k](const Frame &x) { return (int)x.L.K >= k ? x.L.tiles[k] : 0u; });
+        if (m.start[F] == 0) continue;
+        GSC_LAUNCH(launch_raht_inv(m, k, C4, s));
+    }
+    return GSC_OK;
+}
+
+gsc_status run_finish(const Frame *fr, int F, hipStream_t s)
+{
+    TileMap m = make_map(fr, F, [](const Frame &) { return 1u; });
+    GSC_LAUNCH(launch_finish(m, s));
+    return GSC_OK;
+}
+
+// Encode F frames (already validated) with one launch per stage.
+gsc_status encode_frames(const Frame *fr, int F, const gsc_params *p, hipStream_t s)
+{
+    const SetupArgs proto = make_proto((uint32_t)p->J, (uint32_t)p->C, MODE_ENCODE, p);
+    gsc_status st = run_setup(fr, F, proto, s);
+    if (st != GSC_OK) return st;
+    if (p->bbox_mode == 0) {
+        TileMap m = make_map(fr, F, [](const Frame &x) { return bbox_blocks(x.a.n); });
+        GSC_LAUNCH(launch_bbox(m, s));
+    }
+    {
+        TileMap m = make_map(fr, F, [](const Frame &x) { return voxelize_blocks(x.a.n); });
+        GSC_LAUNCH(launch_voxelize(m, s));
+    }
+    const int P = sort_passes(p->J);
+    {
+        TileMap m = make_map(fr, F, [](const Frame &x) { return x.a.n ? x.L.sort_tiles : 0u; });
+        if (m.start[F] > 0)
+            for (int pass = 0; pass < P; ++pass) GSC_LAUNCH(launch_sort_pass(m, pass, s));
+    }
+    {
+        TileMap m = make_map(fr, F, [](const Frame &x) { return x.a.n ? x.L.dedup_tiles : 0u; });
+        if (m.start[F] > 0) GSC_LAUNCH(launch_dedup(m, s));
+    }
+    {
+        TileMap m = make_map(fr, F, [](const Frame &x) { return x.a.n ? x.L.occ_tiles : 0u; });
+        if (m.start[F] > 0) GSC_LAUNCH(launch_occupancy(m, s));
+    }
+    const int C4 = (p->C + 3) / 4;
+    if ((st = run_prelude(fr, F, s)) != GSC_OK) return st;
+    if ((st = run_forward(fr, F, C4, s)) != GSC_OK) return st;
+    return run_finish(fr, F, s);
+}
+
+gsc_status decode_frames(const Frame *fr, int F, int J, int C, hipStream_t s)
+{
+    const SetupArgs proto = make_proto((uint32_t)J, (uint32_t)C, MODE_DECODE, nullptr);
+    gsc_status st = run_setup(fr, F, proto, s);
+    if (st != GSC_OK) return st;
+    {
+        TileMap m = make_map(fr, F, [](const Frame &) { return 1u; });
+        GSC_LAUNCH(launch_dec_top(m, s));
+    }
+    for (int d = 0; d < J; ++d) {
+        // a level can outgrow the top kernel only if its child level can exceed its capacity
+        TileMap m = make_map(fr, F, [d](const Frame &x) {
+            return level_cap(d + 1, x.a.n ? x.a.n : 1) > (uint64_t)DEC_TOP_CAP ? x.L.dec_tiles[d] : 0u;
+        });
+        if (m.start[F] == 0) continue;
+        GSC_LAUNCH(launch_dec_level(m, d, s));
+    }
+    const int C4 = (C + 3) / 4;
+    if ((st = run_prelude(fr, F, s)) != GSC_OK) return st;
+    if ((st = run_inverse(fr, F, C4, s)) != GSC_OK) return st;
+    return run_finish(fr, F, s);
+}
+
+bool layout_for(int64_t n, int J, int C, Layout *L) { return make_layout(n, J, C, L); }
+
+}  // namespace
+
+// =============================================================================== ABI
+extern "C" {
+
+const char *gsc_status_string(gsc_status s)
+{
+    switch (s) {
+    case GSC_OK: return "ok";
+    case GSC_ERR_INVALID_ARG: return "invalid argument";
+    case GSC_ERR_DEPTH: return "depth or channel count out of range";
+    case GSC_ERR_WORKSPACE: return "workspace too small";
+    case GSC_ERR_CAPACITY: return "output capacity too small";
+    case GSC_ERR_CORRUPT_STREAM: return "corrupt stream";
+    case GSC_ERR_HIP: return "HIP launch failed";
+    case GSC_ERR_INTERNAL: return "internal error";
+    }
+    return "unknown status";
+}
+
+gsc_status gsc_workspace_size(int64_t n_max, int32_t J, int32_t C, size_t *bytes)
+{
+    if (!bytes) return GSC_ERR_INVALID_ARG;
+    gsc_status st = check_shape(J, C);
+    if (st != GSC_OK) return st;
+    if (n_max < 0 || n_max > N_LIMIT) return GSC_ERR_INVALID_ARG;
+    Layout L;
+    if (!layout_for(n_max, J, C, &L)) return GSC_ERR_INVALID_ARG;
+    *bytes = L.total;
+    return GSC_OK;
+}
+
+gsc_status gsc_stream_capacity(int64_t n_max, int32_t J, int32_t C, size_t *bytes)
+{
+    if (!bytes) return GSC_ERR_INVALID_ARG;
+    gsc_status st = check_shape(J, C);
+    if (st != GSC_OK) return st;
+    if (n_max < 0 || n_max > N_LIMIT) return GSC_ERR_INVALID_ARG;
+    *bytes = (size_t)stream_capacity(n_max, J, C);
+    return GSC_OK;
+}
+
+gsc_status gsc_encode_batch(const gsc_frame_desc *frames, int32_t F, const gsc_params *params,
+                            void *stream)
+{
+    if (!frames || F < 1 || F > GSC_MAX_BATCH) return GSC_ERR_INVALID_ARG;
+    gsc_status st = check_params(params);
+    if (st != GSC_OK) return st;
+    static thread_local Frame fr[GSC_MAX_BATCH];
+    for (int f = 0; f < F; ++f) {
+        const gsc_frame_desc &d = frames[f];
+        if (d.n < 0 || d.n > N_LIMIT) return GSC_ERR_INVALID_ARG;
+        if (!d.d_stream || !d.d_ws || !d.d_info) return GSC_ERR_INVALID_ARG;
+        if (d.n > 0 && (!d.d_pos || !d.d_attr)) return GSC_ERR_INVALID_ARG;
+        if (!layout_for(d.n, params->J, params->C, &fr[f].L)) return GSC_ERR_INVALID_ARG;
+        if (d.ws_bytes < fr[f].L.total) return GSC_ERR_WORKSPACE;
+        if (d.stream_cap < stream_capacity(d.n, params->J, params->C)) return GSC_ERR_CAPACITY;
+        FrameArgs &a = fr[f].a;
+        memset(&a, 0, sizeof(a));
+        a.n = (uint32_t)d.n;
+        a.pos = d.d_pos;
+        a.attr = d.d_attr;
+        a.stream = static_cast<uint8_t *>(d.d_stream);
+        a.stream_cap = d.stream_cap;
+        a.ws = static_cast<uint8_t *>(d.d_ws);
+        a.info = d.d_info;
+    }
+    return encode_frames(fr, F, params, static_cast<hipStream_t>(stream));
+}
+
+gsc_status gsc_encode_frame(const float *d_pos, const float *d_attr, int64_t n,
+                            const gsc_params *params, void *d_stream, size_t stream_cap,
+                            void *d_ws, size_t ws_bytes, int32_t *d_info, float *d_coef_f32,
+                            uint64_t *d_leaf_codes, void *stream)
+{
+    gsc_status st = check_params(params);
+    if (st != GSC_OK) return st;
+    if (n < 0 || n > N_LIMIT) return GSC_ERR_INVALID_ARG;
+    if (!d_stream || !d_ws || !d_info) return GSC_ERR_INVALID_ARG;
+    if (n > 0 && (!d_pos || !d_attr)) return GSC_ERR_INVALID_ARG;
+    Frame fr;
+    if (!layout_for(n, params->J, params->C, &fr.L)) return GSC_ERR_INVALID_ARG;
+    if (ws_bytes < fr.L.total) return GSC_ERR_WORKSPACE;
+    if (stream_cap < stream_capacity(n, params->J, params->C)) return GSC_ERR_CAPACITY;
+    memset(&fr.a, 0, sizeof(fr.a));
+    fr.a.n = (uint32_t)n;
+    fr.a.pos = d_pos;
+    fr.a.attr = d_attr;
+    fr.a.stream = static_cast<uint8_t *>(d_stream);
+    fr.a.stream_cap = stream_cap;
+    fr.a.ws = static_cast<uint8_t *>(d_ws);
+    fr.a.info = d_info;
+    fr.a.coef_f32 = d_coef_f32;
+    fr.a.codes_out = d_leaf_codes;
+    return encode_frames(&fr, 1, params, static_cast<hipStream_t>(stream));
+}
+
+gsc_status gsc_decode_batch(const gsc_stream_desc *streams, int32_t F, int32_t J, int32_t C,
+                            void *stream)
+{
+    if (!streams || F < 1 || F > GSC_MAX_BATCH) return GSC_ERR_INVALID_ARG;
+    gsc_status st = check_shape(J, C);
+    if (st != GSC_OK) return st;
+    static thread_local Frame fr[GSC_MAX_BATCH];
+    for (int f = 0; f < F; ++f) {
+        const gsc_stream_desc &d = streams[f];
+        if (d.n_cap < 0 || d.n_cap > N_LIMIT) return GSC_ERR_INVALID_ARG;
+        if (!d.d_stream || !d.d_ws || !d.d_info || !d.d_pos_out || !d.d_attr_out)
+            return GSC_ERR_INVALID_ARG;
+        if (!layout_for(d.n_cap, J, C, &fr[f].L)) return GSC_ERR_INVALID_ARG;
+        if (d.ws_bytes < fr[f].L.total) return GSC_ERR_WORKSPACE;
+        FrameArgs &a = fr[f].a;
+        memset(&a, 0, sizeof(a));
+        a.n = (uint32_t)d.n_cap;
+        a.in_stream = static_cast<const uint8_t *>(d.d_stream);
+        a.in_bytes = d.stream_bytes;
+        a.ws = static_cast<uint8_t *>(d.d_ws);
+        a.info = d.d_info;
+        a.pos_out = d.d_pos_out;
+        a.attr_out = d.d_attr_out;
+    }
+    return decode_frames(fr, F, J, C, static_cast<hipStream_t>(stream));
+}
+
+gsc_status gsc_decode_frame(const void *d_stream, size_t stream_bytes, int32_t J, int32_t C,
+                            int64_t n_cap, float *d_pos_out, uint32_t *d_vox_out,
+                            float *d_attr_out, uint64_t *d_leaf_codes, void *d_ws,
+                            size_t ws_bytes, int32_t *d_info, void *stream)
+{
+    gsc_status st = check_shape(J, C);
+    if (st != GSC_OK) return st;
+    if (n_cap < 0 || n_cap > N_LIMIT) return GSC_ERR_INVALID_ARG;
+    if (!d_stream || !d_ws || !d_info || !d_pos_out || !d_attr_out) return GSC_ERR_INVALID_ARG;
+    Frame fr;
+    if (!layout_for(n_cap, J, C, &fr.L)) return GSC_ERR_INVALID_ARG;
+    if (ws_bytes < fr.L.total) return GSC_ERR_WORKSPACE;
+    memset(&fr.a, 0, sizeof(fr.a));
+    fr.a.n = (uint32_t)n_cap;
+    fr.a.in_stream = static_cast<const uint8_t *>(d_stream);
+    fr.a.in_bytes = stream_bytes;
+    fr.a.ws = static_cast<uint8_t *>(d_ws);
+    fr.a.info = d_info;
+    fr.a.pos_out = d_pos_out;
+    fr.a.vox_out = d_vox_out;
+    fr.a.attr_out = d_attr_out;
+    fr.a.codes_out = d_leaf_codes;
+    return decode_frames(&fr, 1, J, C, static_cast<hipStream_t>(stream));
+}
+
+static gsc_status raht_f32(const uint64_t *d_codes, int64_t nv, int32_t J, int32_t C,
+                           const float *d_in, float *d_out, void *d_ws, size_t ws_bytes,
+                           int32_t *d_info, void *stream, bool adjoint)
+{
+    gsc_status st = check_shape(J, C);
+    if (st != GSC_OK) return st;
+    if (nv < 0 || nv > N_LIMIT) return GSC_ERR_INVALID_ARG;
+    if (!d_ws || !d_info) return GSC_ERR_INVALID_ARG;
+    if (nv > 0 && (!d_codes || !d_in || !d_out)) return GSC_ERR_INVALID_ARG;
+    if (nv > 0 && (const void *)d_in == (const void *)d_out) return GSC_ERR_INVALID_ARG;
+    Frame fr;
+    if (!layout_for(nv, J, C, &fr.L)) return GSC_ERR_INVALID_ARG;
+    if (ws_bytes < fr.L.total) return GSC_ERR_WORKSPACE;
+    memset(&fr.a, 0, sizeof(fr.a));
+    fr.a.n = (uint32_t)nv;
+    fr.a.codes_in = d_codes;
+    fr.a.attr = d_in;
+    fr.a.coef_f32 = d_out;
+    fr.a.ws = static_cast<uint8_t *>(d_ws);
+    fr.a.info = d_info;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const SetupArgs proto = make_proto((uint32_t)J, (uint32_t)C, adjoint ? MODE_ADJ_F32 : MODE_FWD_F32, nullptr);
+    if ((st = run_setup(&fr, 1, proto, s)) != GSC_OK) return st;
+    if (nv > 0) {
+        if ((st = run_prelude(&fr, 1, s)) != GSC_OK) return st;
+        const int C4 = (C + 3) / 4;
+        if (adjoint)
+            st = run_inverse(&fr, 1, C4, s);
+        else
+            st = run_forward(&fr, 1, C4, s);
+        if (st != GSC_OK) return st;
+    }
+    return run_finish(&fr, 1, s);
+}
+
+gsc_status gsc_raht_forward(const uint64_t *d_codes, int64_t nv, int32_t J, int32_t C,
+                            const float *d_in, float *d_out, void *d_ws, size_t ws_bytes,
+                            int32_t *d_info, void *stream)
+{
+    return raht_f32(d_codes, nv, J, C, d_in, d_out, d_ws, ws_bytes, d_info, stream, false);
+}
+
+gsc_status gsc_raht_adjoint(const uint64_t *d_codes, int64_t nv, int32_t J, int32_t C,
+                            const float *d_in, float *d_out, void *d_ws, size_t ws_bytes,
+                            int32_t *d_info, void *stream)
+{
+    return raht_f32(d_codes, nv, J, C, d_in, d_out, d_ws, ws_bytes, d_info, stream, true);
+}
+
+}  // extern "C"

@@ -1,0 +1,238 @@
+// Device helpers shared by the kernels: frame lookup, error flag, wave primitives,
+// single-pass decoupled look-back, Morton bit spreading, and the quantizer decision.
+#pragma once
+
+#include "gsc_internal.h"
+
+namespace gsc {
+
+// ------------------------------------------------------------------------- frame lookup
+__device__ inline uint32_t frame_of(const TileMap &m, uint32_t b)
+{
+    uint32_t f = 0;
+    while (f + 1 < m.F && b >= m.start[f + 1]) ++f;
+    return f;
+}
+
+__device__ inline void set_error(Ctrl *c, uint32_t code)
+{
+    atomicCAS(&c->error, 0u, code);
+}
+
+__device__ inline uint32_t load_error(const Ctrl *c)
+{
+    return __hip_atomic_load(&c->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// --------------------------------------------------------------------- wave primitives
+__device__ inline uint32_t lane_id() { return __lane_id(); }
+__device__ inline uint64_t lanemask_lt() { return (1ull << lane_id()) - 1ull; }
+
+__device__ inline uint32_t wave_incl_scan(uint32_t v)
+{
+    const uint32_t lane = lane_id();
+#pragma unroll
+    for (int o = 1; o < WAVE; o <<= 1) {
+        uint32_t t = __shfl_up(v, o, WAVE);
+        if (lane >= (uint32_t)o) v += t;
+    }
+    return v;
+}
+
+// Exclusive scan over the NT threads of a block. `tmp` holds NT/64 + 1 words of LDS.
+// Returns the exclusive prefix of v; *total receives the block total. Ends with a barrier.
+template <int NT>
+__device__ inline uint32_t block_excl_scan(uint32_t v, uint32_t *tmp, uint32_t *total)
+{
+    constexpr int NW = NT / WAVE;
+    const uint32_t inc = wave_incl_scan(v);
+    const uint32_t w = threadIdx.x / WAVE;
+    if (lane_id() == WAVE - 1) tmp[w] = inc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t run = 0;
+        for (int i = 0; i < NW; ++i) {
+            uint32_t t = tmp[i];
+            tmp[i] = run;
+            run += t;
+        }
+        tmp[NW] = run;
+    }
+    __syncthreads();
+    const uint32_t r = tmp[w] + inc - v;
+    if (total) *total = tmp[NW];
+    __syncthreads();
+    return r;
+}
+
+// ------------------------------------------------------------ decoupled look-back scan
+// A tile publishes its aggregate, walks back over its predecessors' status words until it
+// meets an inclusive prefix, then publishes its own inclusive prefix. Tiles take their index
+// from an atomic counter in launch order, so every tile waited on has already started and
+// never waits on a later one. A spin limit turns a (never expected) stall into an error.
+constexpr uint32_t SPIN_LIMIT = 1u << 22;
+
+// 64-bit status word: [63:62] flag (0 none, 1 aggregate, 2 inclusive), [61:0] value.
+constexpr uint64_t LB_AGG = 1ull << 62;
+constexpr uint64_t LB_INC = 2ull << 62;
+constexpr uint64_t LB_VAL = (1ull << 62) - 1ull;
+
+__device__ inline void st_rel(uint64_t *p, uint64_t v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline uint64_t ld_acq(const uint64_t *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline void st_rel32(uint32_t *p, uint32_t v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline uint32_t ld_acq32(const uint32_t *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+struct OpSum {
+    __device__ static uint64_t identity() { return 0; }
+    __device__ static uint64_t combine(uint64_t older, uint64_t newer) { return older + newer; }
+};
+
+// (count, byte): value = count << 8 | byte. Combining appends a segment: counts add, and the
+// byte restarts at the newer part when it contains a segment head (count > 0).
+struct OpSegOr {
+    __device__ static uint64_t identity() { return 0; }
+    __device__ static uint64_t combine(uint64_t older, uint64_t newer)
+    {
+        const uint64_t cnt = (older >> 8) + (newer >> 8);
+        const uint64_t byte = (newer >> 8) ? (newer & 0xFF) : ((older | newer) & 0xFF);
+        return (cnt << 8) | byte;
+    }
+};
+
+// Exclusive prefix (under Op) of tile `tile`'s aggregate over status[0 .. tile-1]; status
+// words of consecutive tiles are `stride` words apart. Called by one thread per sequence.
+template <class Op>
+__device__ inline uint64_t lookback(uint64_t *status, uint32_t stride, uint32_t tile, uint64_t agg,
+                                    Ctrl *ctrl)
+{
+    if (tile == 0) {
+        st_rel(&status[0], LB_INC | agg);
+        return Op::identity();
+    }
+    st_rel(&status[(size_t)tile * stride], LB_AGG | agg);
+    uint64_t acc = Op::identity();
+    int64_t j = (int64_t)tile - 1;
+    uint32_t spins = 0;
+    while (j >= 0) {
+        const uint64_t w = ld_acq(&status[(size_t)j * stride]);
+        const uint64_t flag = w >> 62;
+        if (flag == 0) {
+            if (++spins > SPIN_LIMIT) {
+                set_error(ctrl, GSC_ERR_INTERNAL);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+            continue;
+        }
+        acc = Op::combine(w & LB_VAL, acc);
+        if (flag == 2) break;
+        --j;
+    }
+    st_rel(&status[(size_t)tile * stride], LB_INC | Op::combine(acc, agg));
+    return acc;
+}
+
+// 32-bit status words for the radix sort: [31:30] flag, [29:0] count (n < 2^30).
+__device__ inline uint32_t lookback_sum32(uint32_t *status, uint32_t stride, uint32_t tile,
+                                          uint32_t agg, Ctrl *ctrl)
+{
+    constexpr uint32_t AGG = 1u << 30, INC = 2u << 30, VAL = (1u << 30) - 1u;
+    if (tile == 0) {
+        st_rel32(&status[0], INC | agg);
+        return 0;
+    }
+    st_rel32(&status[(size_t)tile * stride], AGG | agg);
+    uint32_t acc = 0;
+    int64_t j = (int64_t)tile - 1;
+    uint32_t spins = 0;
+    while (j >= 0) {
+        const uint32_t w = ld_acq32(&status[(size_t)j * stride]);
+        const uint32_t flag = w >> 30;
+        if (flag == 0) {
+            if (++spins > SPIN_LIMIT) {
+                set_error(ctrl, GSC_ERR_INTERNAL);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+            continue;
+        }
+        acc += w & VAL;
+        if (flag == 2) break;
+        --j;
+    }
+    st_rel32(&status[(size_t)tile * stride], INC | (acc + agg));
+    return acc;
+}
+
+// ------------------------------------------------------------------------ Morton bits
+// Spread the low 21 bits of v to every third bit (bit b -> bit 3b).
+__device__ inline uint64_t spread3(uint32_t v)
+{
+    uint64_t x = v & 0x1FFFFFu;
+    x = (x | (x << 32)) & 0x1F00000000FFFFull;
+    x = (x | (x << 16)) & 0x1F0000FF0000FFull;
+    x = (x | (x << 8)) & 0x100F00F00F00F00Full;
+    x = (x | (x << 4)) & 0x10C30C30C30C30C3ull;
+    x = (x | (x << 2)) & 0x1249249249249249ull;
+    return x;
+}
+// Inverse of spread3: gather every third bit (bit 3b -> bit b).
+__device__ inline uint32_t compact3(uint64_t x)
+{
+    x &= 0x1249249249249249ull;
+    x = (x ^ (x >> 2)) & 0x10C30C30C30C30C3ull;
+    x = (x ^ (x >> 4)) & 0x100F00F00F00F00Full;
+    x = (x ^ (x >> 8)) & 0x1F0000FF0000FFull;
+    x = (x ^ (x >> 16)) & 0x1F00000000FFFFull;
+    x = (x ^ (x >> 32)) & 0x1FFFFFull;
+    return (uint32_t)x;
+}
+// Code z_{J-1} y_{J-1} x_{J-1} ... z_0 y_0 x_0 (x least significant), Sec. 2.2.
+__device__ inline uint64_t morton3(uint32_t x, uint32_t y, uint32_t z)
+{
+    return spread3(x) | (spread3(y) << 1) | (spread3(z) << 2);
+}
+
+__device__ inline int msb64(uint64_t x) { return 63 - __clzll((long long)x); }
+
+// Binary level at which leaf i (i > 0) becomes a right sibling: one more than the highest bit
+// in which its code differs from leaf i-1's.
+__device__ inline uint8_t merge_level(uint64_t prev, uint64_t cur)
+{
+    return (uint8_t)(msb64(prev ^ cur) + 1);
+}
+
+// ------------------------------------------------------------------------- quantizer
+// q = sgn(y) floor(|y|/step + tau), taken exactly for the given float y: the quotient is exact
+// when the step is a power of two (a multiply by its exact reciprocal), else it is the
+// correctly rounded FP64 quotient; floor(t + tau) is floor(t) plus one when the exact
+// fractional part reaches 1 - tau (compared in FP64, where 1 - tau is exact).
+__device__ inline int32_t quantize(float y, float step, float inv_step, double omt, bool pow2)
+{
+    const float ay = fabsf(y);
+    int32_t q;
+    if (pow2) {
+        const float t = ay * inv_step;
+        const float f = floorf(t);
+        q = (int32_t)f + (((double)(t - f)) >= omt ? 1 : 0);
+    } else {
+        const double t = (double)ay / (double)step;
+        const double f = floor(t);
+        q = (int32_t)f + ((t - f) >= omt ? 1 : 0);
+    }
+    return y < 0.0f ? -q : q;
+}
+
+}  // namespace gsc

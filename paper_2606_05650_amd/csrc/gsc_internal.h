@@ -1,0 +1,299 @@
+// Internal definitions shared by the host side and the kernels of libgsc: tile sizes, the
+// per-call control block that lives at the start of every workspace, the per-frame descriptor
+// the kernels read, and the workspace layout.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/gsc.h"
+
+namespace gsc {
+
+// ---------------------------------------------------------------------------- tile sizes
+constexpr int WAVE = 64;
+
+constexpr int SORT_BITS = 8;            // radix digit width
+constexpr int SORT_BINS = 1 << SORT_BITS;
+constexpr int SORT_THREADS = 256;       // 4 waves
+constexpr int SORT_KPT = 16;            // keys per thread
+constexpr int SORT_TILE = SORT_THREADS * SORT_KPT;
+constexpr int SORT_MAX_PASSES = 8;      // ceil(63 / 8)
+
+constexpr int DEDUP_THREADS = 256;
+constexpr int DEDUP_KPT = 16;
+constexpr int DEDUP_TILE = DEDUP_THREADS * DEDUP_KPT;
+
+constexpr int OCC_THREADS = 256;
+constexpr int OCC_VPT = 8;              // voxels per thread
+constexpr int OCC_TILE = OCC_THREADS * OCC_VPT;
+
+constexpr int DEC_TOP_CAP = 4096;       // octree levels this small are expanded in one workgroup
+constexpr int DEC_THREADS = 256;
+constexpr int DEC_PPT = 8;              // parents per thread
+constexpr int DEC_TILE = DEC_THREADS * DEC_PPT;
+
+constexpr int RT = 512;                 // RAHT tile: entries per workgroup
+constexpr int RAHT_THREADS = 512;
+constexpr int OPEN_CAP = 128;           // >= 6J + 2 open entries per tile for J <= 21
+constexpr int NLVL = 64;                // binary levels 1..63 fit in a 64-bit mask
+constexpr uint8_t LVL_NONE = 127;       // level of entry 0: it never merges as a right sibling
+constexpr int MAXK = 24;                // RAHT tiling levels (sequences S_1 .. S_MAXK)
+constexpr int LSTART_N = NLVL + 2;      // per-tile level segment starts (u16)
+
+constexpr uint32_t BBOX_SENTINEL_MIN = 0xFFFFFFFFu;
+
+// --------------------------------------------------------------- per-call control block
+// Zero-initialised by the first kernel of every call (except the bbox minima).
+struct Ctrl {
+    uint32_t error;              // first device error (gsc_status), 0 = ok
+    uint32_t n_vox;              // Nv
+    uint32_t dec_start;          // decoder: first level handled by the per-level kernels
+    uint32_t n_in;
+    uint32_t bbox_ord[6];        // order-preserving uint of float: min x,y,z, max x,y,z
+    uint32_t tile_ctr[96];       // dynamic tile counters (see TC_*)
+    uint32_t hist_D[32];         // voxels whose new-node depth is D, D = 0..J
+    uint32_t lvl_n[MAXK + 2];    // sizes of the RAHT entry sequences, index k = 1..MAXK+1
+    uint32_t level_sizes[32];    // |L_d|
+    uint64_t occ_off[32];        // stream offset of level d's occupancy bytes
+    uint64_t occ_bytes, coef_offset, total_bytes;
+    double bbox_min[3];
+    double cell;
+    uint32_t sort_hist[SORT_MAX_PASSES * SORT_BINS];
+};
+constexpr size_t CTRL_BYTES = 16384;
+static_assert(sizeof(Ctrl) <= CTRL_BYTES, "control block too large");
+
+// dynamic tile counter slots
+constexpr int TC_SORT = 0;        // + pass
+constexpr int TC_DEDUP = 8;
+constexpr int TC_OCC = 9;
+constexpr int TC_PRELUDE = 10;    // + level k (1..MAXK)
+constexpr int TC_DEC = 40;        // + octree level d (0..20)
+
+// ------------------------------------------------------------- kernel-side frame view
+enum : uint32_t {
+    MODE_ENCODE = 0,    // gather + average input rows, quantize coefficients into the stream
+    MODE_DECODE = 1,    // dequantize from the stream, write output rows
+    MODE_FWD_F32 = 2,   // float rows in, float coefficients out
+    MODE_ADJ_F32 = 3,   // float coefficients in, float rows out
+};
+
+struct RahtLevel {
+    uint32_t *s_idx;     // k >= 2: voxel index of each entry of S_k
+    uint8_t *s_lvl;      // k >= 2: binary level of each entry
+    uint32_t *rec;       // per tile: RT merge records, sorted by level
+    uint16_t *lstart;    // per tile: LSTART_N segment starts (record index of level x)
+    uint16_t *opos;      // per tile: OPEN_CAP positions of open entries
+    uint32_t *obase;     // per tile: index in S_{k+1} of its first open entry
+    uint32_t *ocnt;      // per tile: open entries
+    uint64_t *status;    // per tile: lookback status of the open-entry compaction
+    float *vbuf;         // rows (C4 float4 each) of the entries of S_{k+1}
+    uint32_t tiles;      // worst-case tiles of this level
+    uint32_t cap;        // worst-case entries of S_k
+};
+
+struct FrameDesc {
+    // shape and coding parameters
+    uint32_t n;          // encode: Gaussians; decode / transform: voxel capacity
+    uint32_t J, C, C4, P;   // depth, channels, channels/4 rounded up, sort passes
+    uint32_t mode;
+    uint32_t bbox_mode;
+    float tau;
+    double bbox_min[3];
+    double cell;
+    float step[GSC_MAX_CHANNELS];
+    float inv_step[GSC_MAX_CHANNELS];
+    uint64_t pow2_steps;     // bit c set: step[c] is a power of two
+    // workspace
+    Ctrl *ctrl;
+    uint8_t *zero_begin;
+    uint64_t zero_bytes;
+    // encode
+    const float *pos;
+    const float *attr;       // also MODE_FWD_F32 / MODE_ADJ_F32 input rows
+    uint8_t *stream;
+    uint64_t stream_cap;
+    float *coef_f32;         // optional unquantized coefficients / transform output rows
+    uint64_t *codes_out;     // optional leaf codes
+    // decode
+    const uint8_t *in_stream;
+    uint64_t in_bytes;
+    float *pos_out;
+    uint32_t *vox_out;
+    float *attr_out;
+    int32_t *info;           // device info words
+    const uint64_t *codes_in;   // MODE_FWD_F32 / MODE_ADJ_F32: leaf codes
+    // workspace buffers
+    uint64_t *keys_a, *keys_b;
+    uint32_t *vals_a, *vals_b;
+    uint64_t *leaf;
+    uint32_t *vh;
+    uint32_t *sort_status;   // P x sort tiles x SORT_BINS
+    uint64_t *dedup_status;
+    uint64_t *occ_status;    // occ tiles x J
+    uint64_t *dec_status;    // per octree level d: dec_status + dec_status_off[d]
+    uint32_t dec_status_off[GSC_MAX_DEPTH + 1];
+    uint32_t sort_tiles, dedup_tiles, occ_tiles;
+    uint32_t K;              // RAHT tiling levels
+    RahtLevel lv[MAXK + 1];  // index 1..K
+};
+
+// Tile-to-frame map passed by value to every batched kernel: frame f owns the workgroups
+// [start[f], start[f+1]) and its descriptor lives at fd[f] (inside frame f's workspace).
+struct TileMap {
+    uint32_t F;
+    uint32_t start[GSC_MAX_BATCH + 1];
+    FrameDesc *fd[GSC_MAX_BATCH];
+};
+
+// Per-frame arguments of the setup kernel (user pointers and sizes).
+struct FrameArgs {
+    uint32_t n;
+    const float *pos;
+    const float *attr;
+    uint8_t *stream;
+    uint64_t stream_cap;
+    uint8_t *ws;
+    int32_t *info;
+    float *coef_f32;
+    uint64_t *codes_out;
+    const uint8_t *in_stream;
+    uint64_t in_bytes;
+    float *pos_out;
+    uint32_t *vox_out;
+    float *attr_out;
+    const uint64_t *codes_in;
+};
+constexpr int SETUP_MAX = 16;
+struct SetupArgs {
+    uint32_t count;
+    uint32_t J, C, mode, bbox_mode;
+    float tau;
+    double bbox_min[3];
+    double cell;
+    float step[GSC_MAX_CHANNELS];
+    FrameArgs f[SETUP_MAX];
+};
+
+// ------------------------------------------------------------------ workspace layout
+// [Ctrl][FrameDesc][zero region: lookback status words][buffers ...]
+constexpr size_t DESC_OFF = CTRL_BYTES;
+constexpr size_t DESC_BYTES = 8192;
+static_assert(sizeof(FrameDesc) <= DESC_BYTES, "descriptor too large");
+
+struct Layout {
+    size_t total;
+    size_t zero_off, zero_bytes;
+    size_t keys_a, keys_b, vals_a, vals_b, leaf, vh;
+    size_t sort_status, dedup_status, occ_status, dec_status;
+    uint32_t dec_status_off[GSC_MAX_DEPTH + 1];
+    uint32_t dec_tiles[GSC_MAX_DEPTH + 1];
+    uint32_t sort_tiles, dedup_tiles, occ_tiles, P, K;
+    size_t s_idx[MAXK + 1], s_lvl[MAXK + 1], rec[MAXK + 1], lstart[MAXK + 1], opos[MAXK + 1],
+        obase[MAXK + 1], ocnt[MAXK + 1], status[MAXK + 1], vbuf[MAXK + 1];
+    uint32_t tiles[MAXK + 1], cap[MAXK + 1];
+};
+
+__host__ __device__ inline uint32_t ceil_div(uint64_t a, uint64_t b)
+{
+    return (uint32_t)((a + b - 1) / b);
+}
+__host__ __device__ inline int sort_passes(int J) { return (3 * J + SORT_BITS - 1) / SORT_BITS; }
+__host__ __device__ inline uint32_t open_max(int J) { return 6u * (uint32_t)J + 2u; }
+__host__ __device__ inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// Worst-case number of octree nodes at depth d for n leaves: min(8^d, n).
+__host__ __device__ inline uint64_t level_cap(int d, uint64_t n)
+{
+    return d >= 21 ? n : ((1ull << (3 * d)) < n ? (1ull << (3 * d)) : n);
+}
+
+// Layout of a workspace for frames of at most n entries (Gaussians or voxels) at depth J with
+// C channels. Every region is 256-byte aligned. Returns false if the sizes are out of range.
+__host__ __device__ inline bool make_layout(int64_t n, int J, int C, Layout *L)
+{
+    if (n < 0 || n > 0x7FFFFFFFll || J < 1 || J > GSC_MAX_DEPTH || C < 1 ||
+        C > GSC_MAX_CHANNELS)
+        return false;
+    const uint64_t N = (uint64_t)(n > 0 ? n : 1);
+    const int C4 = (C + 3) / 4;
+    const uint32_t om = open_max(J);
+    L->P = (uint32_t)sort_passes(J);
+    L->sort_tiles = ceil_div(N, SORT_TILE);
+    L->dedup_tiles = ceil_div(N, DEDUP_TILE);
+    L->occ_tiles = ceil_div(N, OCC_TILE);
+    // RAHT tiling levels: S_1 has N entries; a tile of RT entries leaves at most 6J+2 open.
+    uint32_t K = 0;
+    uint64_t s = N;
+    for (int k = 1; k <= MAXK; ++k) {
+        L->cap[k] = (uint32_t)s;
+        L->tiles[k] = ceil_div(s, RT);
+        K = (uint32_t)k;
+        if (s <= (uint64_t)RT) break;
+        uint64_t nxt = (uint64_t)L->tiles[k] * om;
+        s = nxt < s ? nxt : s;
+    }
+    if (L->cap[K] > (uint32_t)RT) return false;
+    L->K = K;
+    size_t off = DESC_OFF + DESC_BYTES;
+    // zero region: every lookback status word and nothing else
+    L->zero_off = off;
+    L->sort_status = off;
+    off = align_up(off + (size_t)L->P * L->sort_tiles * SORT_BINS * 4, 256);
+    L->dedup_status = off;
+    off = align_up(off + (size_t)L->dedup_tiles * 8, 256);
+    L->occ_status = off;
+    off = align_up(off + (size_t)L->occ_tiles * J * 8, 256);
+    L->dec_status = off;
+    uint32_t dsum = 0;
+    for (int d = 0; d <= GSC_MAX_DEPTH; ++d) {
+        L->dec_status_off[d] = dsum;
+        L->dec_tiles[d] = d < J ? ceil_div(level_cap(d, N), DEC_TILE) : 0;
+        dsum += L->dec_tiles[d];
+    }
+    off = align_up(off + (size_t)dsum * 8, 256);
+    for (uint32_t k = 1; k <= K; ++k) {
+        L->status[k] = off;
+        off = align_up(off + (size_t)L->tiles[k] * 8, 256);
+    }
+    L->zero_bytes = off - L->zero_off;
+    // plain buffers
+    L->keys_a = off; off = align_up(off + N * 8, 256);
+    L->keys_b = off; off = align_up(off + N * 8, 256);
+    L->vals_a = off; off = align_up(off + N * 4, 256);
+    L->vals_b = off; off = align_up(off + N * 4, 256);
+    L->leaf = off; off = align_up(off + N * 8, 256);
+    L->vh = off; off = align_up(off + (N + 1) * 4, 256);
+    for (uint32_t k = 1; k <= K; ++k) {
+        const uint32_t t = L->tiles[k];
+        L->s_idx[k] = off; off = align_up(off + (size_t)L->cap[k] * 4, 256);
+        L->s_lvl[k] = off; off = align_up(off + (size_t)L->cap[k], 256);
+        L->rec[k] = off; off = align_up(off + (size_t)t * RT * 4, 256);
+        L->lstart[k] = off; off = align_up(off + (size_t)t * LSTART_N * 2, 256);
+        L->opos[k] = off; off = align_up(off + (size_t)t * OPEN_CAP * 2, 256);
+        L->obase[k] = off; off = align_up(off + (size_t)t * 4, 256);
+        L->ocnt[k] = off; off = align_up(off + (size_t)t * 4, 256);
+        const uint64_t nxt = k < K ? L->cap[k + 1] : 1;
+        L->vbuf[k] = off; off = align_up(off + (size_t)nxt * C4 * 16, 256);
+    }
+    L->total = off;
+    return true;
+}
+
+// Launch helpers (defined next to their kernels). Each returns the launch status.
+hipError_t launch_setup(const SetupArgs &a, uint32_t zero_blocks, hipStream_t s);
+hipError_t launch_bbox(const TileMap &m, hipStream_t s);
+hipError_t launch_voxelize(const TileMap &m, hipStream_t s);
+hipError_t launch_sort_pass(const TileMap &m, int pass, hipStream_t s);
+hipError_t launch_dedup(const TileMap &m, hipStream_t s);
+hipError_t launch_occupancy(const TileMap &m, hipStream_t s);
+hipError_t launch_dec_top(const TileMap &m, hipStream_t s);
+hipError_t launch_dec_level(const TileMap &m, int d, hipStream_t s);
+hipError_t launch_prelude(const TileMap &m, int k, hipStream_t s);
+hipError_t launch_raht_fwd(const TileMap &m, int k, int C4, hipStream_t s);
+hipError_t launch_raht_inv(const TileMap &m, int k, int C4, hipStream_t s);
+hipError_t launch_finish(const TileMap &m, hipStream_t s);
+
+}  // namespace gsc

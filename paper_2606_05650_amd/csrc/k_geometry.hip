@@ -1,0 +1,854 @@
+// Geometry kernels of the codec: per-call setup, bounding cube, voxelization + Morton codes +
+// radix histograms, one-sweep radix sort passes, duplicate merge (unique), octree occupancy
+// bytes for all levels in one pass, level-synchronous octree decoding, and the final
+// header/info write. Every kernel takes a TileMap so that one launch serves a batch of frames.
+#include "gsc_device.h"
+
+namespace gsc {
+
+// ====================================================================== setup / finish
+// grid (zero_blocks, F): block (b, f) zeroes its share of frame f's look-back status words;
+// block (0, f) also builds the frame descriptor and initialises the control block.
+__global__ __launch_bounds__(256) void k_setup(SetupArgs a)
+{
+    const uint32_t f = blockIdx.y;
+    if (f >= a.count) return;
+    const FrameArgs &fa = a.f[f];
+    __shared__ size_t s_zero_off, s_zero_bytes;
+    __shared__ Layout s_L;
+    if (threadIdx.x == 0) {
+        make_layout((int64_t)fa.n, (int)a.J, (int)a.C, &s_L);
+        s_zero_off = s_L.zero_off;
+        s_zero_bytes = s_L.zero_bytes;
+    }
+    __syncthreads();
+    // zero the look-back status region (16-byte stores; the region is 256-byte aligned)
+    {
+        uint4 *z = reinterpret_cast<uint4 *>(fa.ws + s_zero_off);
+        const size_t nq = s_zero_bytes / 16;
+        const size_t stride = (size_t)gridDim.x * blockDim.x;
+        for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < nq; i += stride)
+            z[i] = make_uint4(0, 0, 0, 0);
+    }
+    if (blockIdx.x != 0) return;
+    Ctrl *ctrl = reinterpret_cast<Ctrl *>(fa.ws);
+    uint32_t *cw = reinterpret_cast<uint32_t *>(ctrl);
+    for (uint32_t i = threadIdx.x; i < CTRL_BYTES / 4; i += blockDim.x) cw[i] = 0;
+    if (fa.info)
+        for (uint32_t i = threadIdx.x; i < GSC_INFO_WORDS; i += blockDim.x) fa.info[i] = 0;
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    for (int a3 = 0; a3 < 3; ++a3) ctrl->bbox_ord[a3] = BBOX_SENTINEL_MIN;
+    ctrl->n_in = fa.n;
+    if (a.mode == MODE_FWD_F32 || a.mode == MODE_ADJ_F32) ctrl->n_vox = fa.n;
+
+    const Layout &L = s_L;
+    FrameDesc *fd = reinterpret_cast<FrameDesc *>(fa.ws + DESC_OFF);
+    fd->n = fa.n;
+    fd->J = a.J;
+    fd->C = a.C;
+    fd->C4 = (a.C + 3) / 4;
+    fd->P = L.P;
+    fd->mode = a.mode;
+    fd->bbox_mode = a.bbox_mode;
+    fd->tau = a.tau;
+    for (int i = 0; i < 3; ++i) fd->bbox_min[i] = a.bbox_min[i];
+    fd->cell = a.cell;
+    uint64_t pow2 = 0;
+    for (uint32_t c = 0; c < GSC_MAX_CHANNELS; ++c) {
+        const float st = c < a.C ? a.step[c] : 1.0f;
+        fd->step[c] = st;
+        int e;
+        const float mant = frexpf(st, &e);
+        const bool p2 = (mant == 0.5f);
+        fd->inv_step[c] = p2 ? 1.0f / st : 0.0f;
+        if (p2) pow2 |= 1ull << c;
+    }
+    fd->pow2_steps = pow2;
+    fd->ctrl = ctrl;
+    fd->zero_begin = fa.ws + L.zero_off;
+    fd->zero_bytes = L.zero_bytes;
+    fd->pos = fa.pos;
+    fd->attr = fa.attr;
+    fd->stream = fa.stream;
+    fd->stream_cap = fa.stream_cap;
+    fd->coef_f32 = fa.coef_f32;
+    fd->codes_out = fa.codes_out;
+    fd->in_stream = fa.in_stream;
+    fd->in_bytes = fa.in_bytes;
+    fd->pos_out = fa.pos_out;
+    fd->vox_out = fa.vox_out;
+    fd->attr_out = fa.attr_out;
+    fd->info = fa.info;
+    fd->codes_in = fa.codes_in;
+    fd->keys_a = reinterpret_cast<uint64_t *>(fa.ws + L.keys_a);
+    fd->keys_b = reinterpret_cast<uint64_t *>(fa.ws + L.keys_b);
+    fd->vals_a = reinterpret_cast<uint32_t *>(fa.ws + L.vals_a);
+    fd->vals_b = reinterpret_cast<uint32_t *>(fa.ws + L.vals_b);
+    fd->leaf = reinterpret_cast<uint64_t *>(fa.ws + L.leaf);
+    fd->vh = reinterpret_cast<uint32_t *>(fa.ws + L.vh);
+    fd->sort_status = reinterpret_cast<uint32_t *>(fa.ws + L.sort_status);
+    fd->dedup_status = reinterpret_cast<uint64_t *>(fa.ws + L.dedup_status);
+    fd->occ_status = reinterpret_cast<uint64_t *>(fa.ws + L.occ_status);
+    fd->dec_status = reinterpret_cast<uint64_t *>(fa.ws + L.dec_status);
+    for (int d = 0; d <= GSC_MAX_DEPTH; ++d) fd->dec_status_off[d] = L.dec_status_off[d];
+    fd->sort_tiles = L.sort_tiles;
+    fd->dedup_tiles = L.dedup_tiles;
+    fd->occ_tiles = L.occ_tiles;
+    fd->K = L.K;
+    for (uint32_t k = 0; k <= MAXK; ++k) {
+        RahtLevel &lv = fd->lv[k];
+        if (k >= 1 && k <= L.K) {
+            lv.s_idx = reinterpret_cast<uint32_t *>(fa.ws + L.s_idx[k]);
+            lv.s_lvl = reinterpret_cast<uint8_t *>(fa.ws + L.s_lvl[k]);
+            lv.rec = reinterpret_cast<uint32_t *>(fa.ws + L.rec[k]);
+            lv.lstart = reinterpret_cast<uint16_t *>(fa.ws + L.lstart[k]);
+            lv.opos = reinterpret_cast<uint16_t *>(fa.ws + L.opos[k]);
+            lv.obase = reinterpret_cast<uint32_t *>(fa.ws + L.obase[k]);
+            lv.ocnt = reinterpret_cast<uint32_t *>(fa.ws + L.ocnt[k]);
+            lv.status = reinterpret_cast<uint64_t *>(fa.ws + L.status[k]);
+            lv.vbuf = reinterpret_cast<float *>(fa.ws + L.vbuf[k]);
+            lv.tiles = L.tiles[k];
+            lv.cap = L.cap[k];
+        } else {
+            lv.s_idx = nullptr;
+            lv.s_lvl = nullptr;
+            lv.rec = nullptr;
+            lv.lstart = nullptr;
+            lv.opos = nullptr;
+            lv.obase = nullptr;
+            lv.ocnt = nullptr;
+            lv.status = nullptr;
+            lv.vbuf = nullptr;
+            lv.tiles = 0;
+            lv.cap = 0;
+        }
+    }
+}
+
+hipError_t launch_setup(const SetupArgs &a, uint32_t zero_blocks, hipStream_t s)
+{
+    dim3 grid(zero_blocks, a.count);
+    hipLaunchKernelGGL(k_setup, grid, dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+// Stream geometry from the new-node depth histogram: |L_d| = #{v : D_v <= d}; level d's bytes
+// start at GSC_HEADER_BYTES + sum_{d' < d} |L_d'|; the coefficients at the next multiple of 256.
+struct StreamGeom {
+    uint32_t level_sizes[GSC_MAX_DEPTH + 1];
+    uint64_t occ_off[GSC_MAX_DEPTH + 1];
+    uint64_t occ_bytes, coef_offset, total;
+};
+__device__ inline void stream_geom(const Ctrl *ctrl, uint32_t J, uint32_t C, StreamGeom *g)
+{
+    uint32_t run = 0;
+    uint64_t off = GSC_HEADER_BYTES;
+    for (uint32_t d = 0; d <= J; ++d) {
+        run += ctrl->hist_D[d];
+        g->level_sizes[d] = run;
+        g->occ_off[d] = off;
+        if (d < J) off += run;
+    }
+    g->occ_bytes = off - GSC_HEADER_BYTES;
+    g->coef_offset = align_up(off, 256);
+    g->total = g->coef_offset + (uint64_t)ctrl->n_vox * C * 4;
+}
+
+// One block per frame: copy the device status to the info words, and (encode) write the
+// stream header.
+__global__ __launch_bounds__(64) void k_finish(TileMap m)
+{
+    const uint32_t f = blockIdx.x;
+    if (f >= m.F) return;
+    const FrameDesc &fd = *m.fd[f];
+    Ctrl *ctrl = fd.ctrl;
+    if (fd.mode == MODE_ENCODE)  // the header's unused tail
+        for (uint32_t b = sizeof(gsc_header) + threadIdx.x; b < GSC_HEADER_BYTES; b += blockDim.x)
+            fd.stream[b] = 0;
+    if (threadIdx.x != 0) return;
+    const uint32_t err = load_error(ctrl);
+    uint64_t total = 0;
+    if (fd.mode == MODE_ENCODE) {
+        StreamGeom g;
+        stream_geom(ctrl, fd.J, fd.C, &g);
+        total = g.total;
+        gsc_header *h = reinterpret_cast<gsc_header *>(fd.stream);
+        h->magic = GSC_MAGIC;
+        h->version = GSC_VERSION;
+        h->J = fd.J;
+        h->C = fd.C;
+        h->n_in = fd.n;
+        h->n_vox = ctrl->n_vox;
+        for (int d = 0; d < 22; ++d) h->level_sizes[d] = d <= (int)fd.J ? g.level_sizes[d] : 0u;
+        h->error = err;
+        h->reserved0 = 0;
+        for (int a = 0; a < 3; ++a) h->bbox_min[a] = ctrl->bbox_min[a];
+        h->cell = ctrl->cell;
+        for (int c = 0; c < 64; ++c) h->quant_step[c] = c < (int)fd.C ? fd.step[c] : 0.0f;
+        h->tau = fd.tau;
+        h->reserved1 = 0;
+        h->occ_offset = GSC_HEADER_BYTES;
+        h->occ_bytes = g.occ_bytes;
+        h->coef_offset = g.coef_offset;
+        h->coef_bytes = (uint64_t)ctrl->n_vox * fd.C * 4;
+        h->total_bytes = g.total;
+        // zero the padding between the occupancy bytes and the coefficients
+        for (uint64_t b = GSC_HEADER_BYTES + g.occ_bytes; b < g.coef_offset; ++b) fd.stream[b] = 0;
+    }
+    if (fd.info) {
+        fd.info[0] = (int32_t)err;
+        fd.info[1] = (int32_t)ctrl->n_vox;
+        fd.info[2] = (int32_t)(uint32_t)(total & 0xFFFFFFFFu);
+        fd.info[3] = (int32_t)(uint32_t)(total >> 32);
+        uint32_t used = 0;
+        for (uint32_t k = 1; k <= fd.K; ++k)
+            if (k == 1 ? ctrl->n_vox >= 1 : ctrl->lvl_n[k] >= 2) used = k;
+        fd.info[4] = (int32_t)used;
+    }
+}
+
+hipError_t launch_finish(const TileMap &m, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_finish, dim3(m.F), dim3(64), 0, s, m);
+    return hipGetLastError();
+}
+
+// ========================================================================= bounding box
+__device__ inline uint32_t f2ord(float f)
+{
+    const uint32_t u = __float_as_uint(f);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__device__ inline float ord2f(uint32_t o)
+{
+    const uint32_t u = (o & 0x80000000u) ? (o & 0x7FFFFFFFu) : ~o;
+    return __uint_as_float(u);
+}
+
+constexpr int BBOX_THREADS = 256;
+constexpr int BBOX_PPB = 8192;  // points per block
+
+__global__ __launch_bounds__(BBOX_THREADS) void k_bbox(TileMap m)
+{
+    const uint32_t f = frame_of(m, blockIdx.x);
+    const FrameDesc &fd = *m.fd[f];
+    Ctrl *ctrl = fd.ctrl;
+    const uint32_t b = blockIdx.x - m.start[f];
+    const uint32_t n = fd.n;
+    float mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
+    bool bad = false;
+    const uint32_t p0 = b * BBOX_PPB, p1 = min(n, p0 + BBOX_PPB);
+    for (uint32_t i = p0 + threadIdx.x; i < p1; i += BBOX_THREADS) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const float v = fd.pos[(size_t)i * 3 + a];
+            bad |= !isfinite(v);
+            mn[a] = fminf(mn[a], v);
+            mx[a] = fmaxf(mx[a], v);
+        }
+    }
+    if (__ballot(bad) && lane_id() == 0) set_error(ctrl, GSC_ERR_INVALID_ARG);
+    __shared__ uint32_t s_o[6];
+    if (threadIdx.x < 6) s_o[threadIdx.x] = threadIdx.x < 3 ? 0xFFFFFFFFu : 0u;
+    __syncthreads();
+    if (p0 + threadIdx.x < p1) {
+        for (int a = 0; a < 3; ++a) {
+            atomicMin(&s_o[a], f2ord(mn[a]));
+            atomicMax(&s_o[3 + a], f2ord(mx[a]));
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < 3 && p0 < p1) atomicMin(&ctrl->bbox_ord[threadIdx.x], s_o[threadIdx.x]);
+    else if (threadIdx.x >= 3 && threadIdx.x < 6 && p0 < p1)
+        atomicMax(&ctrl->bbox_ord[threadIdx.x], s_o[threadIdx.x]);
+}
+
+hipError_t launch_bbox(const TileMap &m, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_bbox, dim3(m.start[m.F]), dim3(BBOX_THREADS), 0, s, m);
+    return hipGetLastError();
+}
+uint32_t bbox_blocks(uint32_t n) { return n ? ceil_div(n, BBOX_PPB) : 1u; }
+
+// ===================================================== voxelize + Morton + digit histograms
+// Voxelization (Sec. 2.1, Sec. 2.2 step (a)): v = min(2^J - 1, floor((p - min) / cell)) per axis
+// in FP64 (bounding cube: per-axis minimum, cell = largest extent / 2^J, or 1 when the frame
+// has no extent), then the Morton code of (x, y, z). The histograms of every radix digit of
+// the codes are accumulated for the sort passes.
+constexpr int VOX_THREADS = 256;
+constexpr int VOX_PPT = 4;
+constexpr int VOX_TILE = VOX_THREADS * VOX_PPT;
+
+__global__ __launch_bounds__(VOX_THREADS) void k_voxelize(TileMap m)
+{
+    const uint32_t f = frame_of(m, blockIdx.x);
+    const FrameDesc &fd = *m.fd[f];
+    Ctrl *ctrl = fd.ctrl;
+    if (load_error(ctrl)) return;
+    const uint32_t b = blockIdx.x - m.start[f];
+    const uint32_t n = fd.n, J = fd.J, P = fd.P;
+    __shared__ uint32_t s_hist[SORT_MAX_PASSES * SORT_BINS];
+    for (uint32_t i = threadIdx.x; i < P * SORT_BINS; i += VOX_THREADS) s_hist[i] = 0;
+    double lo[3], cell;
+    if (fd.bbox_mode == 0) {
+        double ext = 0.0;
+        for (int a = 0; a < 3; ++a) {
+            if (n == 0) {
+                lo[a] = 0.0;
+                continue;
+            }
+            lo[a] = (double)ord2f(ctrl->bbox_ord[a]);
+            const double hi = (double)ord2f(ctrl->bbox_ord[3 + a]);
+            ext = fmax(ext, hi - lo[a]);
+        }
+        cell = ext > 0.0 ? ldexp(ext, -(int)J) : 1.0;
+    } else {
+        for (int a = 0; a < 3; ++a) lo[a] = fd.bbox_min[a];
+        cell = fd.cell;
+    }
+    if (b == 0 && threadIdx.x == 0) {
+        for (int a = 0; a < 3; ++a) ctrl->bbox_min[a] = lo[a];
+        ctrl->cell = cell;
+    }
+    __syncthreads();
+    const double top = (double)((1u << J) - 1u);
+    const uint32_t p0 = b * VOX_TILE;
+#pragma unroll
+    for (int r = 0; r < VOX_PPT; ++r) {
+        const uint32_t i = p0 + r * VOX_THREADS + threadIdx.x;
+        if (i >= n) break;
+        uint32_t v[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const double p = (double)fd.pos[(size_t)i * 3 + a];
+            double t = floor(__ddiv_rn(__dsub_rn(p, lo[a]), cell));
+            t = t < 0.0 ? 0.0 : (t > top ? top : t);
+            v[a] = (uint32_t)t;
+        }
+        const uint64_t key = morton3(v[0], v[1], v[2]);
+        fd.keys_a[i] = key;
+        for (uint32_t p = 0; p < P; ++p)
+            atomicAdd(&s_hist[p * SORT_BINS + ((key >> (p * SORT_BITS)) & (SORT_BINS - 1))], 1u);
+    }
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < P * SORT_BINS; i += VOX_THREADS)
+        if (s_hist[i]) atomicAdd(&ctrl->sort_hist[i], s_hist[i]);
+}
+
+hipError_t launch_voxelize(const TileMap &m, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_voxelize, dim3(m.start[m.F]), dim3(VOX_THREADS), 0, s, m);
+    return hipGetLastError();
+}
+uint32_t voxelize_blocks(uint32_t n) { return n ? ceil_div(n, VOX_TILE) : 1u; }
+
+// ============================================================ one-sweep radix sort pass
+// Stable LSD pass over digit `pass` of (key, index) pairs. Each workgroup ranks a tile of
+// SORT_TILE keys in LDS: wave w owns a contiguous quarter of the tile and walks it in order,
+// 64 keys at a time; lanes holding the same digit are found with SORT_BITS ballots and ranked
+// among themselves, so equal digits keep input order. The tile's digit counts are combined
+// with its predecessors' through a per-digit decoupled look-back, keys are staged in LDS in
+// digit order and written out in runs.
+__device__ inline uint64_t match_digit(uint32_t d)
+{
+    uint64_t peers = ~0ull;
+#pragma unroll
+    for (int bit = 0; bit < SORT_BITS; ++bit) {
+        const bool on = (d >> bit) & 1u;
+        const uint64_t mm = __ballot(on);
+        peers &= on ? mm : ~mm;
+    }
+    return peers;
+}
+
+__global__ __launch_bounds__(SORT_THREADS) void k_sort_pass(TileMap m, int pass)
+{
+    constexpr int NW = SORT_THREADS / WAVE;
+    __shared__ uint32_t s_tile;
+    __shared__ uint32_t s_wcnt[NW][SORT_BINS];
+    __shared__ uint32_t s_gbase[SORT_BINS];
+    __shared__ uint32_t s_lstart[SORT_BINS];
+    __shared__ uint32_t s_tmp[NW + 1];
+    __shared__ uint64_t s_keys[SORT_TILE];
+    __shared__ uint32_t s_vals[SORT_TILE];
+
+    const uint32_t f = frame_of(m, blockIdx.x);
+    const FrameDesc &fd = *m.fd[f];
+    Ctrl *ctrl = fd.ctrl;
+    if (load_error(ctrl)) return;
+    const uint32_t n = fd.n;
+    const uint32_t tid = threadIdx.x, w = tid / WAVE, lane = lane_id();
+    if (tid == 0) s_tile = atomicAdd(&ctrl->tile_ctr[TC_SORT + pass], 1u);
+    for (uint32_t i = tid; i < NW * SORT_BINS; i += SORT_THREADS) (&s_wcnt[0][0])[i] = 0;
+    __syncthreads();
+    const uint32_t tile = s_tile;
+    const uint32_t base = tile * SORT_TILE;
+    if (base >= n) return;
+    const uint64_t *kin = (pass & 1) ? fd.keys_b : fd.keys_a;
+    const uint32_t *vin = (pass & 1) ? fd.vals_b : fd.vals_a;
+    uint64_t *kout = (pass & 1) ? fd.keys_a : fd.keys_b;
+    uint32_t *vout = (pass & 1) ? fd.vals_a : fd.vals_b;
+    const uint32_t shift = (uint32_t)pass * SORT_BITS;
+
+    uint64_t key[SORT_KPT];
+    uint32_t val[SORT_KPT];
+    uint32_t rank[SORT_KPT];
+    const uint32_t wbase = base + w * (SORT_KPT * WAVE);
+#pragma unroll
+    for (int j = 0; j < SORT_KPT; ++j) {
+        const uint32_t p = wbase + j * WAVE + lane;
+        const bool valid = p < n;
+        key[j] = valid ? kin[p] : ~0ull;
+        val[j] = pass == 0 ? p : (valid ? vin[p] : 0u);
+    }
+#pragma unroll
+    for (int j = 0; j < SORT_KPT; ++j) {
+        const uint32_t d = (uint32_t)(key[j] >> shift) & (SORT_BINS - 1);
+        const uint64_t peers = match_digit(d);
+        const uint32_t cnt = s_wcnt[w][d];
+        __builtin_amdgcn_wave_barrier();
+        const bool leader = lane == (uint32_t)(__ffsll((long long)peers) - 1);
+        if (leader) s_wcnt[w][d] = cnt + (uint32_t)__popcll(peers);
+        rank[j] = cnt + (uint32_t)__popcll(peers & lanemask_lt());
+        __builtin_amdgcn_wave_barrier();
+    }
+    __syncthreads();
+    // per digit (one thread per digit): wave prefixes, tile count, look-back, global base
+    {
+        const uint32_t d = tid;
+        uint32_t run = 0;
+#pragma unroll
+        for (int ww = 0; ww < NW; ++ww) {
+            const uint32_t c = s_wcnt[ww][d];
+            s_wcnt[ww][d] = run;
+            run += c;
+        }
+        const uint32_t tile_cnt = run;
+        const uint32_t excl = lookback_sum32(fd.sort_status + (size_t)pass * fd.sort_tiles * SORT_BINS + d,
+                                             SORT_BINS, tile, tile_cnt, ctrl);
+        const uint32_t hist_excl =
+            block_excl_scan<SORT_THREADS>(ctrl->sort_hist[pass * SORT_BINS + d], s_tmp, nullptr);
+        s_gbase[d] = hist_excl + excl;
+        s_lstart[d] = block_excl_scan<SORT_THREADS>(tile_cnt, s_tmp, nullptr);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < SORT_KPT; ++j) {
+        const uint32_t d = (uint32_t)(key[j] >> shift) & (SORT_BINS - 1);
+        const uint32_t q = s_lstart[d] + s_wcnt[w][d] + rank[j];
+        s_keys[q] = key[j];
+        s_vals[q] = val[j];
+    }
+    __syncthreads();
+    const uint32_t nvalid = min((uint32_t)SORT_TILE, n - base);
+    for (uint32_t q = tid; q < nvalid; q += SORT_THREADS) {
+        const uint64_t k = s_keys[q];
+        const uint32_t d = (uint32_t)(k >> shift) & (SORT_BINS - 1);
+        const uint32_t o = s_gbase[d] + (q - s_lstart[d]);
+        if (o < n) {
+            kout[o] = k;
+            vout[o] = s_vals[q];
+        }
+    }
+}
+
+hipError_t launch_sort_pass(const TileMap &m, int pass, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_sort_pass, dim3(m.start[m.F]), dim3(SORT_THREADS), 0, s, m, pass);
+    return hipGetLastError();
+}
+
+// ================================================================= unique + merge map
+// Sorted keys -> occupied voxels: a run of equal keys is one voxel (Alg. 1 step 1, Unique).
+// Writes the voxel codes L_J, the first sorted position of every voxel (vh, with vh[Nv] = n),
+// Nv, and the histogram of new-node depths D_v (the shallowest octree depth at which voxel v
+// starts a node of its own: J - floor(msb(L[v-1] xor L[v]) / 3), and 0 for v = 0), from which
+// every level size follows: |L_d| = #{v : D_v <= d}.
+__global__ __launch_bounds__(DEDUP_THREADS) void k_dedup(TileMap m)
+{
+    __shared__ uint32_t s_tile;
+    __shared__ uint32_t s_tmp[DEDUP_THREADS / WAVE + 1];
+    __shared__ uint32_t s_hist[32];
+    __shared__ uint32_t s_base;
+    const uint32_t f = frame_of(m, blockIdx.x);
+    const FrameDesc &fd = *m.fd[f];
+    Ctrl *ctrl = fd.ctrl;
+    if (load_error(ctrl)) return;
+    const uint32_t n = fd.n, J = fd.J;
+    const uint32_t tid = threadIdx.x;
+    if (tid == 0) s_tile = atomicAdd(&ctrl->tile_ctr[TC_DEDUP], 1u);
+    if (tid < 32) s_hist[tid] = 0;
+    __syncthreads();
+    const uint32_t tile = s_tile;
+    const uint32_t base = tile * DEDUP_TILE;
+    if (base >= n) return;
+    const uint64_t *K = (fd.P & 1) ? fd.keys_b : fd.keys_a;  // output of the last sort pass
+    const uint32_t p0 = base + tid * DEDUP_KPT;
+    uint32_t heads = 0;  // bit j: position p0 + j starts a voxel
+    uint64_t prev = (p0 > 0 && p0 < n) ? K[p0 - 1] : 0ull;
+#pragma unroll
+    for (int j = 0; j < DEDUP_KPT; ++j) {
+        const uint32_t p = p0 + j;
+        if (p < n) {
+            const uint64_t k = K[p];
+            const bool h = (p == 0) || (k != prev);
+            if (h) {
+                heads |= 1u << j;
+                const uint32_t D = p == 0 ? 0u : J - (uint32_t)msb64(prev ^ k) / 3u;
+                atomicAdd(&s_hist[D], 1u);
+            }
+            prev = k;
+        }
+    }
+    uint32_t tile_total;
+    const uint32_t texcl = block_excl_scan<DEDUP_THREADS>((uint32_t)__popc(heads), s_tmp, &tile_total);
+    if (tid == 0) s_base = (uint32_t)lookback<OpSum>(fd.dedup_status, 1, tile, tile_total, ctrl);
+    __syncthreads();
+    uint32_t v = s_base + texcl;
+#pragma unroll
+    for (int j = 0; j < DEDUP_KPT; ++j) {
+        if ((heads >> j & 1u) && v < n) {
+            const uint32_t p = p0 + j;
+            const uint64_t k = K[p];
+            fd.leaf[v] = k;
+            if (fd.codes_out) fd.codes_out[v] = k;
+            fd.vh[v] = p;
+            ++v;
+        }
+    }
+    if (tid < 32 && s_hist[tid]) atomicAdd(&ctrl->hist_D[tid], s_hist[tid]);
+    if (tid == 0 && base + DEDUP_TILE >= n) {
+        const uint32_t nv = s_base + tile_total;
+        ctrl->n_vox = nv;
+        fd.vh[nv] = n;
+    }
+}
+
+hipError_t launch_dedup(const TileMap &m, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_dedup, dim3(m.start[m.F]), dim3(DEDUP_THREADS), 0, s, m);
+    return hipGetLastError();
+}
+
+// ======================================================================== occupancy
+// All occupancy bytes (Sec. 2.2 "Bitstream generation", Alg. 1 OccKernel) in one pass over the
+// sorted voxel codes. Voxel v is the first leaf of its depth-d node exactly when D_v <= d; the
+// byte of such a node collects bit ((L[u] >> 3(J-d-1)) & 7) of every voxel u of the node with
+// D_u <= d+1 (the first leaves of its children). A tile of voxels ORs these bits in LDS per
+// depth; the byte of a node that straddles tile boundaries is finished by the tile holding the
+// next node's head, which learns the node's partial byte (and the node's rank) from a
+// per-depth decoupled look-back over (head count, open byte).
+__global__ __launch_bounds__(OCC_THREADS) void k_occupancy(TileMap m)
+{
+    __shared__ uint32_t s_tile;
+    __shared__ uint64_t s_code[OCC_TILE + 1];
+    __shared__ uint32_t s_bytes[GSC_MAX_DEPTH][OCC_TILE / 4];
+    __shared__ uint32_t s_carry[GSC_MAX_DEPTH];
+    __shared__ uint32_t s_cnt[GSC_MAX_DEPTH];
+    __shared__ uint64_t s_pref[GSC_MAX_DEPTH];
+    __shared__ uint32_t s_tmp[OCC_THREADS / WAVE + 1];
+
+    const uint32_t f = frame_of(m, blockIdx.x);
+    const FrameDesc &fd = *m.fd[f];
+    Ctrl *ctrl = fd.ctrl;
+    if (load_error(ctrl)) return;
+    const uint32_t J = fd.J, nv = ctrl->n_vox;
+    const uint32_t tid = threadIdx.x;
+    if (tid == 0) s_tile = atomicAdd(&ctrl->tile_ctr[TC_OCC], 1u);
+    for (uint32_t i = tid; i < GSC_MAX_DEPTH * (OCC_TILE / 4); i += OCC_THREADS)
+        (&s_bytes[0][0])[i] = 0;
+    if (tid < GSC_MAX_DEPTH) s_carry[tid] = 0;
+    __syncthreads();
+    const uint32_t tile = s_tile;
+    const uint32_t s = tile * OCC_TILE;
+    if (s >= nv) return;
+    const uint32_t e = min(nv, s + OCC_TILE);
+    // s_code[j] = L[s - 1 + j]
+    for (uint32_t j = tid; j < e - s + 1; j += OCC_THREADS)
+        s_code[j] = (s + j >= 1) ? fd.leaf[s + j - 1] : 0ull;
+    __syncthreads();
+
+    uint32_t Dv[OCC_VPT];
+    uint64_t cv[OCC_VPT];
+#pragma unroll
+    for (int i = 0; i < OCC_VPT; ++i) {
+        const uint32_t v = s + tid * OCC_VPT + i;
+        const uint32_t j = v - s + 1;
+        if (v < e) {
+            cv[i] = s_code[j];
+            Dv[i] = v == 0 ? 0u : J - (uint32_t)msb64(s_code[j - 1] ^ cv[i]) / 3u;
+        } else {
+            cv[i] = 0;
+            Dv[i] = 0xFFFFu;  // not a voxel: never a head, never contributes
+        }
+    }
+    for (uint32_t d = 0; d < J; ++d) {
+        uint32_t my = 0;
+#pragma unroll
+        for (int i = 0; i < OCC_VPT; ++i) my += Dv[i] <= d ? 1u : 0u;
+        uint32_t total;
+        uint32_t run = block_excl_scan<OCC_THREADS>(my, s_tmp, &total);
+        const uint32_t sh = 3u * (J - d - 1u);
+#pragma unroll
+        for (int i = 0; i < OCC_VPT; ++i) {
+            if (Dv[i] <= d) ++run;
+            if (Dv[i] <= d + 1u) {
+                const uint32_t bit = 1u << (uint32_t)((cv[i] >> sh) & 7u);
+                if (run == 0) {
+                    atomicOr(&s_carry[d], bit);
+                } else {
+                    const uint32_t k = run - 1u;
+                    atomicOr(&s_bytes[d][k >> 2], bit << (8u * (k & 3u)));
+                }
+            }
+        }
+        if (tid == 0) s_cnt[d] = total;
+    }
+    __syncthreads();
+    if (tid < J) {
+        const uint32_t d = tid;
+        const uint32_t cnt = s_cnt[d];
+        const uint32_t byte = cnt ? (s_bytes[d][(cnt - 1) >> 2] >> (8u * ((cnt - 1) & 3u))) & 0xFFu
+                                  : s_carry[d];
+        const uint64_t agg = ((uint64_t)cnt << 8) | byte;
+        s_pref[d] = lookback<OpSegOr>(fd.occ_status + d, J, tile, agg, ctrl);
+    }
+    __shared__ uint64_t s_off[GSC_MAX_DEPTH + 1];
+    __shared__ int s_fits;
+    if (tid == 0) {
+        StreamGeom g;
+        stream_geom(ctrl, J, fd.C, &g);
+        for (uint32_t d = 0; d <= J; ++d) s_off[d] = g.occ_off[d];
+        s_fits = g.total <= fd.stream_cap;
+        if (!s_fits) set_error(ctrl, GSC_ERR_CAPACITY);
+    }
+    __syncthreads();
+    if (!s_fits) return;
+    const bool last = (e == nv);
+    uint8_t *out = fd.stream;
+    for (uint32_t d = 0; d < J; ++d) {
+        const uint64_t pref = s_pref[d];
+        const uint32_t pc = (uint32_t)(pref >> 8), por = (uint32_t)(pref & 0xFF);
+        const uint32_t cnt = s_cnt[d];
+        const uint64_t off = s_off[d];
+        const uint32_t nw = cnt ? (last ? cnt : cnt - 1u) : 0u;
+        const uint64_t lim = s_off[d + 1 < J ? d + 1 : J];  // end of level d's bytes
+        for (uint32_t k = tid; k < nw; k += OCC_THREADS)
+            if (off + pc + k < lim)
+                out[off + pc + k] = (uint8_t)((s_bytes[d][k >> 2] >> (8u * (k & 3u))) & 0xFFu);
+        if (tid == 0 && pc > 0 && (cnt > 0 || last) && off + pc - 1 < lim)
+            out[off + pc - 1] = (uint8_t)(por | s_carry[d]);
+    }
+}
+
+hipError_t launch_occupancy(const TileMap &m, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_occupancy, dim3(m.start[m.F]), dim3(OCC_THREADS), 0, s, m);
+    return hipGetLastError();
+}
+
+// ===================================================================== octree decoding
+// Decoding (Sec. 2.3, Alg. 2-3): L_0 = [0]; level d's |L_d| bytes give each parent's child
+// count (population count), an exclusive prefix sum gives each parent's first child slot, and
+// every parent writes (p << 3) + i for each set bit i in ascending order. The leaves are then
+// turned back into voxel coordinates and voxel centres.
+
+// Writes leaf v: its code, voxel coordinates and centre min + (v + 1/2) * cell (FP64, rounded
+// once to float).
+__device__ inline void emit_leaf(const FrameDesc &fd, const gsc_header *h, uint32_t v,
+                                 uint64_t code)
+{
+    fd.leaf[v] = code;
+    if (fd.codes_out) fd.codes_out[v] = code;
+    const uint32_t xyz[3] = {compact3(code), compact3(code >> 1), compact3(code >> 2)};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (fd.vox_out) fd.vox_out[(size_t)v * 3 + a] = xyz[a];
+        const double c = __dadd_rn(h->bbox_min[a], __dmul_rn(__dadd_rn((double)xyz[a], 0.5), h->cell));
+        fd.pos_out[(size_t)v * 3 + a] = (float)c;
+    }
+}
+
+// Header checks: everything the decoder relies on must be self-consistent and fit the caller's
+// buffers. Returns true when the header is usable.
+__device__ inline bool header_ok(const FrameDesc &fd, const gsc_header *h)
+{
+    if (fd.in_bytes < GSC_HEADER_BYTES) return false;
+    if (h->magic != GSC_MAGIC || h->version != GSC_VERSION) return false;
+    if (h->J != fd.J || h->C != fd.C || h->error != 0) return false;
+    const uint32_t J = fd.J, nv = h->n_vox;
+    if (nv > fd.n) return false;
+    if (h->level_sizes[J] != nv) return false;
+    if (h->level_sizes[0] != (nv > 0 ? 1u : 0u)) return false;
+    uint64_t occ = 0;
+    for (uint32_t d = 0; d < J; ++d) {
+        const uint64_t a = h->level_sizes[d], b = h->level_sizes[d + 1];
+        if (b < a || b > 8 * a) return false;
+        occ += a;
+    }
+    if (h->occ_offset != GSC_HEADER_BYTES || h->occ_bytes != occ) return false;
+    const uint64_t co = align_up(GSC_HEADER_BYTES + occ, 256);
+    if (h->coef_offset != co || h->coef_bytes != (uint64_t)nv * fd.C * 4) return false;
+    if (h->total_bytes != co + h->coef_bytes || h->total_bytes > fd.in_bytes) return false;
+    for (uint32_t c = 0; c < fd.C; ++c)
+        if (!(h->quant_step[c] > 0.0f) || !isfinite(h->quant_step[c])) return false;
+    if (!(h->cell > 0.0)) return false;
+    return true;
+}
+
+constexpr int DEC_TOP_THREADS = 1024;
+
+// One workgroup per frame: checks the header, then expands the top levels in LDS while the
+// next level has at most DEC_TOP_CAP nodes. Leaves the last level it built in the ping-pong
+// buffer of that level (or emits the leaves when it reached depth J).
+__global__ __launch_bounds__(DEC_TOP_THREADS) void k_dec_top(TileMap m)
+{
+    __shared__ uint64_t s_lv[2][DEC_TOP_CAP];
+    __shared__ uint32_t s_tmp[DEC_TOP_THREADS / WAVE + 1];
+    __shared__ int s_ok;
+    const uint32_t f = blockIdx.x;
+    if (f >= m.F) return;
+    const FrameDesc &fd = *m.fd[f];
+    Ctrl *ctrl = fd.ctrl;
+    const gsc_header *h = reinterpret_cast<const gsc_header *>(fd.in_stream);
+    const uint32_t tid = threadIdx.x;
+    if (tid == 0) {
+        s_ok = header_ok(fd, h) ? 1 : 0;
+        if (!s_ok) {
+            set_error(ctrl, GSC_ERR_CORRUPT_STREAM);
+        } else {
+            ctrl->n_vox = h->n_vox;
+            for (uint32_t d = 0; d <= fd.J; ++d) ctrl->level_sizes[d] = h->level_sizes[d];
+        }
+    }
+    __syncthreads();
+    if (!s_ok) return;
+    const uint32_t J = fd.J, nv = h->n_vox;
+    if (nv == 0) {
+        if (tid == 0) ctrl->dec_start = J;
+        return;
+    }
+    const uint8_t *occ = fd.in_stream + GSC_HEADER_BYTES;
+    if (tid == 0) s_lv[0][0] = 0;
+    __syncthreads();
+    uint32_t d = 0, cur = 0;
+    uint64_t off = 0;
+    bool bad = false;
+    for (; d < J; ++d) {
+        const uint32_t M = h->level_sizes[d], Mn = h->level_sizes[d + 1];
+        if (Mn > (uint32_t)DEC_TOP_CAP) break;
+        // each thread takes up to 4 consecutive parents
+        constexpr int PPT = DEC_TOP_CAP / DEC_TOP_THREADS;
+        uint32_t bytes[PPT], cnt = 0;
+#pragma unroll
+        for (int i = 0; i < PPT; ++i) {
+            const uint32_t p = tid * PPT + i;
+            bytes[i] = p < M ? occ[off + p] : 0u;
+            if (p < M && bytes[i] == 0) bad = true;
+            cnt += __popc(bytes[i]);
+        }
+        uint32_t total;
+        uint32_t w = block_excl_scan<DEC_TOP_THREADS>(cnt, s_tmp, &total);
+        if (total != Mn) {
+            bad = true;
+        } else {
+#pragma unroll
+            for (int i = 0; i < PPT; ++i) {
+                const uint32_t p = tid * PPT + i;
+                if (p >= M) break;
+                const uint64_t base = s_lv[cur][p] << 3;
+                for (uint32_t c = 0; c < 8; ++c)
+                    if (bytes[i] >> c & 1u) s_lv[cur ^ 1][w++] = base + c;
+            }
+        }
+        if (__syncthreads_or(bad)) {
+            if (tid == 0) set_error(ctrl, GSC_ERR_CORRUPT_STREAM);
+            return;
+        }
+        off += M;
+        cur ^= 1;
+    }
+    const uint32_t Md = h->level_sizes[d];
+    if (d == J) {
+        for (uint32_t v = tid; v < Md; v += DEC_TOP_THREADS) emit_leaf(fd, h, v, s_lv[cur][v]);
+    } else {
+        uint64_t *dst = (d & 1) ? fd.keys_b : fd.keys_a;
+        for (uint32_t v = tid; v < Md; v += DEC_TOP_THREADS) dst[v] = s_lv[cur][v];
+    }
+    if (tid == 0) ctrl->dec_start = d;
+}
+
+hipError_t launch_dec_top(const TileMap &m, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_dec_top, dim3(m.F), dim3(DEC_TOP_THREADS), 0, s, m);
+    return hipGetLastError();
+}
+
+// Expansion of one level d >= the top kernel's stopping level, for all parents at once.
+__global__ __launch_bounds__(DEC_THREADS) void k_dec_level(TileMap m, int d)
+{
+    __shared__ uint32_t s_tile;
+    __shared__ uint32_t s_tmp[DEC_THREADS / WAVE + 1];
+    __shared__ uint32_t s_base;
+    const uint32_t f = frame_of(m, blockIdx.x);
+    const FrameDesc &fd = *m.fd[f];
+    Ctrl *ctrl = fd.ctrl;
+    if (load_error(ctrl)) return;
+    if ((uint32_t)d >= fd.J || (uint32_t)d < ctrl->dec_start) return;
+    const gsc_header *h = reinterpret_cast<const gsc_header *>(fd.in_stream);
+    const uint32_t J = fd.J;
+    const uint32_t M = ctrl->level_sizes[d], Mn = ctrl->level_sizes[d + 1];
+    const uint32_t tid = threadIdx.x;
+    if (tid == 0) s_tile = atomicAdd(&ctrl->tile_ctr[TC_DEC + d], 1u);
+    __syncthreads();
+    const uint32_t tile = s_tile;
+    const uint32_t s = tile * DEC_TILE;
+    if (s >= M) return;
+    uint64_t off = 0;
+    for (int dd = 0; dd < d; ++dd) off += ctrl->level_sizes[dd];
+    const uint8_t *occ = fd.in_stream + GSC_HEADER_BYTES + off;
+    const uint64_t *src = (d & 1) ? fd.keys_b : fd.keys_a;
+    uint64_t *dst = (d & 1) ? fd.keys_a : fd.keys_b;
+    uint32_t bytes[DEC_PPT], cnt = 0;
+    bool bad = false;
+#pragma unroll
+    for (int i = 0; i < DEC_PPT; ++i) {
+        const uint32_t p = s + tid * DEC_PPT + i;
+        bytes[i] = p < M ? occ[p] : 0u;
+        if (p < M && bytes[i] == 0) bad = true;
+        cnt += __popc(bytes[i]);
+    }
+    uint32_t total;
+    uint32_t w = block_excl_scan<DEC_THREADS>(cnt, s_tmp, &total);
+    if (tid == 0) s_base = (uint32_t)lookback<OpSum>(fd.dec_status + fd.dec_status_off[d], 1, tile, total, ctrl);
+    __syncthreads();
+    w += s_base;
+#pragma unroll
+    for (int i = 0; i < DEC_PPT; ++i) {
+        const uint32_t p = s + tid * DEC_PPT + i;
+        if (p >= M) break;
+        const uint64_t base = src[p] << 3;
+        for (uint32_t c = 0; c < 8; ++c) {
+            if (bytes[i] >> c & 1u) {
+                if (w < Mn) {
+                    if ((uint32_t)d + 1 == J) emit_leaf(fd, h, w, base + c);
+                    else dst[w] = base + c;
+                } else {
+                    bad = true;
+                }
+                ++w;
+            }
+        }
+    }
+    if (bad) set_error(ctrl, GSC_ERR_CORRUPT_STREAM);
+    if (tid == 0 && s + DEC_TILE >= M && s_base + total != Mn) set_error(ctrl, GSC_ERR_CORRUPT_STREAM);
+}
+
+hipError_t launch_dec_level(const TileMap &m, int d, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_dec_level, dim3(m.start[m.F]), dim3(DEC_THREADS), 0, s, m, d);
+    return hipGetLastError();
+}
+
+}  // namespace gsc

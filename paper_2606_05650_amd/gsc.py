@@ -1,0 +1,348 @@
+"""Python binding of libgsc (include/gsc.h): argument marshalling only.
+
+Every step of the codec runs in the HIP kernels of libgsc.so; this module only allocates device
+buffers with PyTorch, passes raw pointers and the current HIP stream through ctypes, and reads
+back the device status words. It fails loudly when the library is not built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgsc.so")
+HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "gsc.h")
+
+MAX_DEPTH = 21
+MAX_CHANNELS = 64
+MAX_BATCH = 64
+HEADER_BYTES = 1024
+INFO_WORDS = 8
+
+STATUS = {0: "GSC_OK", 1: "GSC_ERR_INVALID_ARG", 2: "GSC_ERR_DEPTH", 3: "GSC_ERR_WORKSPACE",
+          4: "GSC_ERR_CAPACITY", 5: "GSC_ERR_CORRUPT_STREAM", 6: "GSC_ERR_HIP",
+          7: "GSC_ERR_INTERNAL"}
+
+
+class GscError(RuntimeError):
+    def __init__(self, code, where):
+        self.code = int(code)
+        super().__init__(f"{where}: {STATUS.get(self.code, self.code)}")
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("J", ctypes.c_int32), ("C", ctypes.c_int32),
+                ("quant_step", ctypes.c_float * MAX_CHANNELS), ("tau", ctypes.c_float),
+                ("bbox_mode", ctypes.c_int32), ("bbox_min", ctypes.c_double * 3),
+                ("cell", ctypes.c_double)]
+
+
+class FrameDescC(ctypes.Structure):
+    _fields_ = [("d_pos", ctypes.c_void_p), ("d_attr", ctypes.c_void_p), ("n", ctypes.c_int64),
+                ("d_stream", ctypes.c_void_p), ("stream_cap", ctypes.c_size_t),
+                ("d_ws", ctypes.c_void_p), ("ws_bytes", ctypes.c_size_t),
+                ("d_info", ctypes.c_void_p)]
+
+
+class StreamDescC(ctypes.Structure):
+    _fields_ = [("d_stream", ctypes.c_void_p), ("stream_bytes", ctypes.c_size_t),
+                ("n_cap", ctypes.c_int64), ("d_pos_out", ctypes.c_void_p),
+                ("d_attr_out", ctypes.c_void_p), ("d_ws", ctypes.c_void_p),
+                ("ws_bytes", ctypes.c_size_t), ("d_info", ctypes.c_void_p)]
+
+
+# Byte layout of the stream header (gsc_header in include/gsc.h), little-endian.
+HEADER_DTYPE = np.dtype([
+    ("magic", "<u4"), ("version", "<u4"), ("J", "<u4"), ("C", "<u4"), ("n_in", "<u4"),
+    ("n_vox", "<u4"), ("level_sizes", "<u4", (22,)), ("error", "<u4"), ("reserved0", "<u4"),
+    ("bbox_min", "<f8", (3,)), ("cell", "<f8"), ("quant_step", "<f4", (64,)), ("tau", "<f4"),
+    ("reserved1", "<u4"), ("occ_offset", "<u8"), ("occ_bytes", "<u8"), ("coef_offset", "<u8"),
+    ("coef_bytes", "<u8"), ("total_bytes", "<u8")])
+
+_lib = None
+
+
+def lib():
+    """The loaded libgsc.so. Raises if it has not been built (no fallback exists)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"libgsc.so is not built ({LIB_PATH}); run __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, i64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+        L.gsc_workspace_size.restype = i32
+        L.gsc_workspace_size.argtypes = [i64, i32, i32, ctypes.POINTER(sz)]
+        L.gsc_stream_capacity.restype = i32
+        L.gsc_stream_capacity.argtypes = [i64, i32, i32, ctypes.POINTER(sz)]
+        L.gsc_encode_frame.restype = i32
+        L.gsc_encode_frame.argtypes = [vp, vp, i64, ctypes.POINTER(Params), vp, sz, vp, sz, vp, vp,
+                                       vp, vp]
+        L.gsc_decode_frame.restype = i32
+        L.gsc_decode_frame.argtypes = [vp, sz, i32, i32, i64, vp, vp, vp, vp, vp, sz, vp, vp]
+        L.gsc_encode_batch.restype = i32
+        L.gsc_encode_batch.argtypes = [ctypes.POINTER(FrameDescC), i32, ctypes.POINTER(Params), vp]
+        L.gsc_decode_batch.restype = i32
+        L.gsc_decode_batch.argtypes = [ctypes.POINTER(StreamDescC), i32, i32, i32, vp]
+        L.gsc_raht_forward.restype = i32
+        L.gsc_raht_forward.argtypes = [vp, i64, i32, i32, vp, vp, vp, sz, vp, vp]
+        L.gsc_raht_adjoint.restype = i32
+        L.gsc_raht_adjoint.argtypes = [vp, i64, i32, i32, vp, vp, vp, sz, vp, vp]
+        L.gsc_status_string.restype = ctypes.c_char_p
+        L.gsc_status_string.argtypes = [i32]
+        _lib = L
+    return _lib
+
+
+def declared_symbols(header_path=HEADER_PATH):
+    """Names of the functions declared in include/gsc.h."""
+    text = open(header_path).read()
+    return sorted(set(re.findall(r"^(?:gsc_status|const char \*)\s*(gsc_\w+)\(", text, re.M)))
+
+
+def status_string(code):
+    return lib().gsc_status_string(int(code)).decode()
+
+
+def _check(code, where):
+    if code != 0:
+        raise GscError(code, where)
+
+
+def workspace_size(n, J, C):
+    out = ctypes.c_size_t()
+    _check(lib().gsc_workspace_size(int(n), int(J), int(C), ctypes.byref(out)), "workspace_size")
+    return out.value
+
+
+def stream_capacity(n, J, C):
+    out = ctypes.c_size_t()
+    _check(lib().gsc_stream_capacity(int(n), int(J), int(C), ctypes.byref(out)),
+           "stream_capacity")
+    return out.value
+
+
+def make_params(J, C, steps, tau=0.5, bbox=None):
+    p = Params()
+    p.J, p.C = int(J), int(C)
+    steps = np.broadcast_to(np.asarray(steps, dtype=np.float32), (C,))
+    for c in range(C):
+        p.quant_step[c] = float(steps[c])
+    p.tau = float(tau)
+    if bbox is None:
+        p.bbox_mode = 0
+    else:
+        p.bbox_mode = 1
+        for a in range(3):
+            p.bbox_min[a] = float(bbox[0][a])
+        p.cell = float(bbox[1])
+    return p
+
+
+def parse_header(stream_bytes):
+    """Decode the 1024-byte header of a stream held in host memory (bytes or uint8 array)."""
+    buf = np.frombuffer(bytes(stream_bytes[:HEADER_BYTES]), dtype=np.uint8)
+    return np.frombuffer(buf[:HEADER_DTYPE.itemsize].tobytes(), dtype=HEADER_DTYPE)[0]
+
+
+# ------------------------------------------------------------------------- torch glue
+def _torch():
+    import torch
+    return torch
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dev_u8(nbytes, device):
+    torch = _torch()
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+
+
+@dataclass
+class Encoded:
+    stream: "object"     # uint8 device tensor holding the stream (capacity bytes)
+    info: "object"       # int32 device tensor [GSC_INFO_WORDS]
+    J: int
+    C: int
+
+    def host_info(self):
+        return self.info.cpu().numpy()
+
+    def total_bytes(self):
+        i = self.host_info()
+        return int(np.uint32(i[2])) | (int(np.uint32(i[3])) << 32)
+
+    def n_vox(self):
+        return int(self.host_info()[1])
+
+    def check(self):
+        i = self.host_info()
+        if i[0] != 0:
+            raise GscError(i[0], "device")
+        return self
+
+    def to_bytes(self):
+        """The stream's used bytes, copied to the host."""
+        return self.stream[:self.total_bytes()].cpu().numpy().tobytes()
+
+
+class Workspace:
+    """A reusable device workspace sized for frames of up to n_max entries."""
+
+    def __init__(self, n_max, J, C, device="cuda"):
+        self.n_max, self.J, self.C = int(n_max), int(J), int(C)
+        self.bytes = workspace_size(n_max, J, C)
+        self.buf = _dev_u8(self.bytes, device)
+
+    def fits(self, n, J, C):
+        return n <= self.n_max and J == self.J and C == self.C
+
+
+def encode_frame(pos, attr, params, *, ws=None, stream_buf=None, info=None, coef_f32=None,
+                 leaf_codes=None, stream=None):
+    """Encode one frame. pos: [n,3] float32 cuda, attr: [n,C] float32 cuda (contiguous)."""
+    torch = _torch()
+    n = int(pos.shape[0])
+    C = int(params.C)
+    dev = pos.device
+    if ws is None:
+        ws = Workspace(max(n, 1), params.J, C, dev)
+    cap = stream_capacity(n, params.J, C)
+    if stream_buf is None:
+        stream_buf = _dev_u8(cap, dev)
+    if info is None:
+        info = torch.zeros(INFO_WORDS, dtype=torch.int32, device=dev)
+    rc = lib().gsc_encode_frame(_ptr(pos), _ptr(attr), n, ctypes.byref(params), _ptr(stream_buf),
+                                stream_buf.numel(), _ptr(ws.buf), ws.bytes, _ptr(info),
+                                _ptr(coef_f32), _ptr(leaf_codes), _stream(stream))
+    _check(rc, "gsc_encode_frame")
+    return Encoded(stream_buf, info, int(params.J), C)
+
+
+@dataclass
+class Decoded:
+    pos: "object"
+    attr: "object"
+    vox: "object"
+    codes: "object"
+    info: "object"
+
+    def n_vox(self):
+        return int(self.info[1].item())
+
+    def check(self):
+        i = self.info.cpu().numpy()
+        if i[0] != 0:
+            raise GscError(i[0], "device")
+        return self
+
+
+def decode_frame(stream_buf, J, C, n_cap, *, stream_bytes=None, ws=None, want_vox=False,
+                 want_codes=False, pos_out=None, attr_out=None, info=None, stream=None):
+    """Decode one device stream into voxel centres and attributes (Morton order)."""
+    torch = _torch()
+    dev = stream_buf.device
+    n_cap = int(n_cap)
+    if ws is None:
+        ws = Workspace(max(n_cap, 1), J, C, dev)
+    if pos_out is None:
+        pos_out = torch.empty((max(n_cap, 1), 3), dtype=torch.float32, device=dev)
+    if attr_out is None:
+        attr_out = torch.empty((max(n_cap, 1), C), dtype=torch.float32, device=dev)
+    vox = torch.empty((max(n_cap, 1), 3), dtype=torch.int32, device=dev) if want_vox else None
+    codes = torch.empty(max(n_cap, 1), dtype=torch.int64, device=dev) if want_codes else None
+    if info is None:
+        info = torch.zeros(INFO_WORDS, dtype=torch.int32, device=dev)
+    nbytes = stream_buf.numel() if stream_bytes is None else int(stream_bytes)
+    rc = lib().gsc_decode_frame(_ptr(stream_buf), nbytes, int(J), int(C), n_cap, _ptr(pos_out),
+                                _ptr(vox), _ptr(attr_out), _ptr(codes), _ptr(ws.buf), ws.bytes,
+                                _ptr(info), _stream(stream))
+    _check(rc, "gsc_decode_frame")
+    return Decoded(pos_out, attr_out, vox, codes, info)
+
+
+def encode_batch(frames, params, *, workspaces=None, stream=None):
+    """frames: list of (pos, attr) device tensors. Returns a list of Encoded."""
+    torch = _torch()
+    F = len(frames)
+    if F < 1 or F > MAX_BATCH:
+        raise ValueError("1..64 frames per batch")
+    descs = (FrameDescC * F)()
+    outs = []
+    for f, (pos, attr) in enumerate(frames):
+        n = int(pos.shape[0])
+        dev = pos.device
+        ws = workspaces[f] if workspaces is not None else Workspace(max(n, 1), params.J, params.C,
+                                                                    dev)
+        cap = stream_capacity(n, params.J, params.C)
+        sb = _dev_u8(cap, dev)
+        info = torch.zeros(INFO_WORDS, dtype=torch.int32, device=dev)
+        d = descs[f]
+        d.d_pos, d.d_attr, d.n = pos.data_ptr(), attr.data_ptr(), n
+        d.d_stream, d.stream_cap = sb.data_ptr(), sb.numel()
+        d.d_ws, d.ws_bytes, d.d_info = ws.buf.data_ptr(), ws.bytes, info.data_ptr()
+        outs.append(Encoded(sb, info, int(params.J), int(params.C)))
+    _check(lib().gsc_encode_batch(descs, F, ctypes.byref(params), _stream(stream)),
+           "gsc_encode_batch")
+    return outs
+
+
+def decode_batch(encoded, n_caps, *, workspaces=None, stream=None):
+    """encoded: list of Encoded. Returns a list of Decoded (pos, attr only)."""
+    torch = _torch()
+    F = len(encoded)
+    descs = (StreamDescC * F)()
+    outs = []
+    J, C = encoded[0].J, encoded[0].C
+    for f, e in enumerate(encoded):
+        dev = e.stream.device
+        n_cap = int(n_caps[f])
+        ws = workspaces[f] if workspaces is not None else Workspace(max(n_cap, 1), J, C, dev)
+        pos = torch.empty((max(n_cap, 1), 3), dtype=torch.float32, device=dev)
+        attr = torch.empty((max(n_cap, 1), C), dtype=torch.float32, device=dev)
+        info = torch.zeros(INFO_WORDS, dtype=torch.int32, device=dev)
+        d = descs[f]
+        d.d_stream, d.stream_bytes, d.n_cap = e.stream.data_ptr(), e.stream.numel(), n_cap
+        d.d_pos_out, d.d_attr_out = pos.data_ptr(), attr.data_ptr()
+        d.d_ws, d.ws_bytes, d.d_info = ws.buf.data_ptr(), ws.bytes, info.data_ptr()
+        outs.append(Decoded(pos, attr, None, None, info))
+    _check(lib().gsc_decode_batch(descs, F, int(J), int(C), _stream(stream)), "gsc_decode_batch")
+    return outs
+
+
+def raht_forward(codes, A, J, *, ws=None, out=None, info=None, stream=None):
+    """Y = T A for float rows A [nv, C] of voxels with sorted codes [nv] (int64 view of u64)."""
+    return _raht(codes, A, J, ws, out, info, stream, adjoint=False)
+
+
+def raht_adjoint(codes, Y, J, *, ws=None, out=None, info=None, stream=None):
+    """A = T^T Y (the inverse transform)."""
+    return _raht(codes, Y, J, ws, out, info, stream, adjoint=True)
+
+
+def _raht(codes, X, J, ws, out, info, stream, adjoint):
+    torch = _torch()
+    nv, C = int(X.shape[0]), int(X.shape[1])
+    dev = X.device
+    if ws is None:
+        ws = Workspace(max(nv, 1), J, C, dev)
+    if out is None:
+        out = torch.empty_like(X)
+    if info is None:
+        info = torch.zeros(INFO_WORDS, dtype=torch.int32, device=dev)
+    fn = lib().gsc_raht_adjoint if adjoint else lib().gsc_raht_forward
+    rc = fn(_ptr(codes), nv, int(J), C, _ptr(X), _ptr(out), _ptr(ws.buf), ws.bytes, _ptr(info),
+            _stream(stream))
+    _check(rc, "gsc_raht_adjoint" if adjoint else "gsc_raht_forward")
+    return out, info

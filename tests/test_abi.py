@@ -1,0 +1,98 @@
+"""The C ABI library loads and exports every symbol include/gsc.h declares; host-side argument
+checks and size queries behave as documented. No call here reaches the GPU: every checked call
+returns before enqueueing work."""
+import ctypes
+
+import numpy as np
+import pytest
+
+from paper_2606_05650_amd import gsc
+
+
+def test_library_exports_every_declared_symbol():
+    L = gsc.lib()
+    names = gsc.declared_symbols()
+    assert {"gsc_encode_frame", "gsc_decode_frame", "gsc_encode_batch", "gsc_workspace_size",
+            "gsc_stream_capacity", "gsc_status_string", "gsc_decode_batch", "gsc_raht_forward",
+            "gsc_raht_adjoint"} <= set(names)
+    for name in names:
+        assert hasattr(L, name), name
+
+
+def test_status_strings():
+    assert gsc.status_string(0) == "ok"
+    assert gsc.status_string(5) == "corrupt stream"
+    assert gsc.status_string(99) == "unknown status"
+
+
+def test_size_queries():
+    # the stream holds a 1 KiB header, at most min(8^d, n) bytes per level d < J, padding to
+    # 256 bytes, and n * C int32 coefficients
+    n, J, C = 1000, 5, 56
+    occ = sum(min(8 ** d, n) for d in range(J))
+    want = ((1024 + occ + 255) // 256) * 256 + n * C * 4
+    assert gsc.stream_capacity(n, J, C) == want
+    assert gsc.stream_capacity(0, J, C) == 1024
+    ws = [gsc.workspace_size(k, 12, 56) for k in (0, 1, 1000, 10 ** 6)]
+    assert ws == sorted(ws) and ws[0] > 0
+    with pytest.raises(gsc.GscError) as e:
+        gsc.workspace_size(10, 22, 56)
+    assert e.value.code == 2
+    with pytest.raises(gsc.GscError):
+        gsc.workspace_size(10, 12, 65)
+    with pytest.raises(gsc.GscError):
+        gsc.workspace_size(-1, 12, 56)
+
+
+def _encode_rc(n=10, J=5, C=4, steps=0.1, tau=0.5, ws_bytes=None, cap=None, null_ws=False,
+               params=True, **kw):
+    L = gsc.lib()
+    p = gsc.make_params(J, C, steps, tau, **kw) if params else None
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced: every case fails validation first
+    ws_need = gsc.workspace_size(max(n, 0), min(J, 21), min(C, 64)) if 1 <= J <= 21 and 1 <= C <= 64 else 0
+    return L.gsc_encode_frame(fake, fake, n, ctypes.byref(p) if p else None, fake,
+                              cap if cap is not None else 1 << 40, None if null_ws else fake,
+                              ws_bytes if ws_bytes is not None else ws_need, fake, None, None,
+                              None)
+
+
+def test_encode_argument_checks():
+    assert _encode_rc(J=0) == 2
+    assert _encode_rc(J=22) == 2
+    assert _encode_rc(steps=0.0) == 1
+    assert _encode_rc(steps=np.inf) == 1
+    assert _encode_rc(tau=1.0) == 1
+    assert _encode_rc(tau=-0.1) == 1
+    assert _encode_rc(n=-1) == 1
+    assert _encode_rc(null_ws=True) == 1
+    assert _encode_rc(params=False) == 1
+    assert _encode_rc(ws_bytes=100) == 3
+    assert _encode_rc(cap=100) == 4
+    assert _encode_rc(bbox=((0, 0, 0), 0.0)) == 1
+
+
+def test_decode_and_transform_argument_checks():
+    L = gsc.lib()
+    fake = ctypes.c_void_p(0x1000)
+    ws = gsc.workspace_size(100, 8, 3)
+    assert L.gsc_decode_frame(fake, 4096, 0, 3, 100, fake, None, fake, None, fake, ws, fake, None) == 2
+    assert L.gsc_decode_frame(fake, 4096, 8, 3, 100, None, None, fake, None, fake, ws, fake, None) == 1
+    assert L.gsc_decode_frame(fake, 4096, 8, 3, 100, fake, None, fake, None, fake, 10, fake, None) == 3
+    assert L.gsc_raht_forward(fake, 100, 8, 3, fake, fake, fake, ws, fake, None) == 1  # aliasing
+    assert L.gsc_raht_adjoint(fake, 100, 8, 70, fake, ctypes.c_void_p(0x2000), fake, ws, fake,
+                              None) == 2
+    descs = (gsc.FrameDescC * 1)()
+    assert L.gsc_encode_batch(descs, 0, None, None) == 1
+    assert L.gsc_encode_batch(descs, 65, None, None) == 1
+
+
+def test_header_layout_matches_c_struct():
+    # offsets of gsc_header fields as laid out by a C compiler (natural alignment)
+    d = gsc.HEADER_DTYPE
+    assert d.fields["level_sizes"][1] == 24
+    assert d.fields["error"][1] == 112
+    assert d.fields["bbox_min"][1] == 120
+    assert d.fields["quant_step"][1] == 152
+    assert d.fields["occ_offset"][1] == 416
+    assert d.itemsize == 456 <= gsc.HEADER_BYTES
+    assert ctypes.sizeof(gsc.Params) == 304
