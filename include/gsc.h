@@ -190,6 +190,29 @@ gsc_status gsc_raht_adjoint(const uint64_t *d_codes, int64_t nv, int32_t J, int3
                             const float *d_in, float *d_out, void *d_ws, size_t ws_bytes,
                             int32_t *d_info, void *stream);
 
+/* ------------------------------------------------------------------------------------------
+ * Diagnostics: gsc_profile_events -- record caller-created HIP events around one stage of every
+ * later call on the calling process (all threads share this setting). `events` holds n_pairs
+ * (start, end) pairs of hipEvent_t (as void*); the i-th launch of the stage records pair
+ * i % n_pairs on the call's stream, immediately before and after the stage. n_pairs = 0 (or
+ * events = NULL) switches the stage off. Not for concurrent use with other profiling.
+ * ---------------------------------------------------------------------------------------- */
+typedef enum gsc_stage {
+    GSC_STAGE_ENCODE = 0,      /* a whole gsc_encode_frame / gsc_encode_batch call           */
+    GSC_STAGE_DECODE = 1,      /* a whole gsc_decode_frame / gsc_decode_batch call           */
+    GSC_STAGE_SORT = 2,        /* voxelize + all radix sort passes + unique                  */
+    GSC_STAGE_OCCUPANCY = 3,   /* the occupancy-byte kernel                                  */
+    GSC_STAGE_PRELUDE = 4,     /* all RAHT prelude launches of a call                        */
+    GSC_STAGE_RAHT_FWD1 = 5,   /* first-level forward RAHT (merge + transform + quantize)    */
+    GSC_STAGE_RAHT_FWD_TOP = 6,/* forward RAHT of the upper tiling levels                    */
+    GSC_STAGE_RAHT_INV1 = 7,   /* first-level inverse RAHT (dequantize + transform + rows)   */
+    GSC_STAGE_RAHT_INV_TOP = 8,/* inverse RAHT of the upper tiling levels                    */
+    GSC_STAGE_OCTREE_DEC = 9,  /* octree expansion + Morton decode + voxel centres           */
+    GSC_STAGE_COUNT = 10
+} gsc_stage;
+
+gsc_status gsc_profile_events(int32_t stage, void *const *events, int32_t n_pairs);
+
 /* Human-readable name of a status code (static string). */
 const char *gsc_status_string(gsc_status s);
 

@@ -48,6 +48,31 @@ uint64_t stream_capacity(int64_t n, int J, int C)
     return align_up(GSC_HEADER_BYTES + occ, 256) + (uint64_t)n * (uint64_t)C * 4u;
 }
 
+// ---------------------------------------------------------------- profiling hooks
+struct StageHook {
+    const void *const *events = nullptr;
+    int n_pairs = 0;
+    uint64_t count = 0;
+};
+StageHook g_hooks[GSC_STAGE_COUNT];
+
+struct StageScope {
+    StageHook *h;
+    hipStream_t s;
+    int pair;
+    StageScope(int stage, hipStream_t st) : h(&g_hooks[stage]), s(st), pair(-1)
+    {
+        if (h->n_pairs > 0) {
+            pair = (int)(h->count++ % (uint64_t)h->n_pairs);
+            (void)hipEventRecord((hipEvent_t)h->events[2 * pair], s);
+        }
+    }
+    ~StageScope()
+    {
+        if (pair >= 0) (void)hipEventRecord((hipEvent_t)h->events[2 * pair + 1], s);
+    }
+};
+
 // ------------------------------------------------------------------- launch plumbing
 struct Frame {
     Layout L;
@@ -121,6 +146,7 @@ int max_K(const Frame *fr, int F)
 
 gsc_status run_prelude(const Frame *fr, int F, hipStream_t s)
 {
+    StageScope sc(GSC_STAGE_PRELUDE, s);
     const int K = max_K(fr, F);
     for (int k = 1; k <= K; ++k) {
         TileMap m = make_map(fr, F, [k](const Frame &x) { return (int)x.L.K >= k ? x.L.tiles[k] : 0u; });
@@ -136,7 +162,22 @@ gsc_status run_forward(const Frame *fr, int F, int C4, hipStream_t s)
     for (int k = 1; k <= K; ++k) {
         TileMap m = make_map(fr, F, [k](const Frame &x) { return (int)x.L.K >= k ? x.L.tiles[k] : 0u; });
         if (m.start[F] == 0) continue;
-        GSC_LAUNCH(launch_raht_fwd(m, k, C4, s));
+        if (k == 1) {
+            StageScope sc(GSC_STAGE_RAHT_FWD1, s);
+            GSC_LAUNCH(launch_raht_fwd(m, k, C4, s));
+        } else {
+            if (k == 2 && g_hooks[GSC_STAGE_RAHT_FWD_TOP].n_pairs > 0) {
+                // one scope over all upper levels
+                StageScope sc(GSC_STAGE_RAHT_FWD_TOP, s);
+                for (int kk = 2; kk <= K; ++kk) {
+                    TileMap mm = make_map(fr, F, [kk](const Frame &x) { return (int)x.L.K >= kk ? x.L.tiles[kk] : 0u; });
+                    if (mm.start[F] == 0) continue;
+                    GSC_LAUNCH(launch_raht_fwd(mm, kk, C4, s));
+                }
+                break;
+            }
+            GSC_LAUNCH(launch_raht_fwd(m, k, C4, s));
+        }
     }
     return GSC_OK;
 }
@@ -144,10 +185,18 @@ gsc_status run_forward(const Frame *fr, int F, int C4, hipStream_t s)
 gsc_status run_inverse(const Frame *fr, int F, int C4, hipStream_t s)
 {
     const int K = max_K(fr, F);
-    for (int k = K; k >= 1; --k) {
-        TileMap m = make_map(fr, F, [k](const Frame &x) { return (int)x.L.K >= k ? x.L.tiles[k] : 0u; });
-        if (m.start[F] == 0) continue;
-        GSC_LAUNCH(launch_raht_inv(m, k, C4, s));
+    {
+        StageScope sc(GSC_STAGE_RAHT_INV_TOP, s);
+        for (int k = K; k >= 2; --k) {
+            TileMap m = make_map(fr, F, [k](const Frame &x) { return (int)x.L.K >= k ? x.L.tiles[k] : 0u; });
+            if (m.start[F] == 0) continue;
+            GSC_LAUNCH(launch_raht_inv(m, k, C4, s));
+        }
+    }
+    TileMap m = make_map(fr, F, [](const Frame &x) { return x.L.tiles[1]; });
+    if (m.start[F] > 0) {
+        StageScope sc(GSC_STAGE_RAHT_INV1, s);
+        GSC_LAUNCH(launch_raht_inv(m, 1, C4, s));
     }
     return GSC_OK;
 }
@@ -162,28 +211,33 @@ gsc_status run_finish(const Frame *fr, int F, hipStream_t s)
 // Encode F frames (already validated) with one launch per stage.
 gsc_status encode_frames(const Frame *fr, int F, const gsc_params *p, hipStream_t s)
 {
+    StageScope whole(GSC_STAGE_ENCODE, s);
     const SetupArgs proto = make_proto((uint32_t)p->J, (uint32_t)p->C, MODE_ENCODE, p);
     gsc_status st = run_setup(fr, F, proto, s);
     if (st != GSC_OK) return st;
-    if (p->bbox_mode == 0) {
-        TileMap m = make_map(fr, F, [](const Frame &x) { return bbox_blocks(x.a.n); });
-        GSC_LAUNCH(launch_bbox(m, s));
+    {
+        StageScope sc(GSC_STAGE_SORT, s);
+        if (p->bbox_mode == 0) {
+            TileMap m = make_map(fr, F, [](const Frame &x) { return bbox_blocks(x.a.n); });
+            GSC_LAUNCH(launch_bbox(m, s));
+        }
+        {
+            TileMap m = make_map(fr, F, [](const Frame &x) { return voxelize_blocks(x.a.n); });
+            GSC_LAUNCH(launch_voxelize(m, s));
+        }
+        const int P = sort_passes(p->J);
+        {
+            TileMap m = make_map(fr, F, [](const Frame &x) { return x.a.n ? x.L.sort_tiles : 0u; });
+            if (m.start[F] > 0)
+                for (int pass = 0; pass < P; ++pass) GSC_LAUNCH(launch_sort_pass(m, pass, s));
+        }
+        {
+            TileMap m = make_map(fr, F, [](const Frame &x) { return x.a.n ? x.L.dedup_tiles : 0u; });
+            if (m.start[F] > 0) GSC_LAUNCH(launch_dedup(m, s));
+        }
     }
     {
-        TileMap m = make_map(fr, F, [](const Frame &x) { return voxelize_blocks(x.a.n); });
-        GSC_LAUNCH(launch_voxelize(m, s));
-    }
-    const int P = sort_passes(p->J);
-    {
-        TileMap m = make_map(fr, F, [](const Frame &x) { return x.a.n ? x.L.sort_tiles : 0u; });
-        if (m.start[F] > 0)
-            for (int pass = 0; pass < P; ++pass) GSC_LAUNCH(launch_sort_pass(m, pass, s));
-    }
-    {
-        TileMap m = make_map(fr, F, [](const Frame &x) { return x.a.n ? x.L.dedup_tiles : 0u; });
-        if (m.start[F] > 0) GSC_LAUNCH(launch_dedup(m, s));
-    }
-    {
+        StageScope sc(GSC_STAGE_OCCUPANCY, s);
         TileMap m = make_map(fr, F, [](const Frame &x) { return x.a.n ? x.L.occ_tiles : 0u; });
         if (m.start[F] > 0) GSC_LAUNCH(launch_occupancy(m, s));
     }
@@ -195,20 +249,24 @@ gsc_status encode_frames(const Frame *fr, int F, const gsc_params *p, hipStream_
 
 gsc_status decode_frames(const Frame *fr, int F, int J, int C, hipStream_t s)
 {
+    StageScope whole(GSC_STAGE_DECODE, s);
     const SetupArgs proto = make_proto((uint32_t)J, (uint32_t)C, MODE_DECODE, nullptr);
     gsc_status st = run_setup(fr, F, proto, s);
     if (st != GSC_OK) return st;
     {
-        TileMap m = make_map(fr, F, [](const Frame &) { return 1u; });
-        GSC_LAUNCH(launch_dec_top(m, s));
-    }
-    for (int d = 0; d < J; ++d) {
-        // a level can outgrow the top kernel only if its child level can exceed its capacity
-        TileMap m = make_map(fr, F, [d](const Frame &x) {
-            return level_cap(d + 1, x.a.n ? x.a.n : 1) > (uint64_t)DEC_TOP_CAP ? x.L.dec_tiles[d] : 0u;
-        });
-        if (m.start[F] == 0) continue;
-        GSC_LAUNCH(launch_dec_level(m, d, s));
+        StageScope sc(GSC_STAGE_OCTREE_DEC, s);
+        {
+            TileMap m = make_map(fr, F, [](const Frame &) { return 1u; });
+            GSC_LAUNCH(launch_dec_top(m, s));
+        }
+        for (int d = 0; d < J; ++d) {
+            // a level can outgrow the top kernel only if its child level can exceed its capacity
+            TileMap m = make_map(fr, F, [d](const Frame &x) {
+                return level_cap(d + 1, x.a.n ? x.a.n : 1) > (uint64_t)DEC_TOP_CAP ? x.L.dec_tiles[d] : 0u;
+            });
+            if (m.start[F] == 0) continue;
+            GSC_LAUNCH(launch_dec_level(m, d, s));
+        }
     }
     const int C4 = (C + 3) / 4;
     if ((st = run_prelude(fr, F, s)) != GSC_OK) return st;
@@ -236,6 +294,21 @@ const char *gsc_status_string(gsc_status s)
     case GSC_ERR_INTERNAL: return "internal error";
     }
     return "unknown status";
+}
+
+gsc_status gsc_profile_events(int32_t stage, void *const *events, int32_t n_pairs)
+{
+    if (stage < 0 || stage >= GSC_STAGE_COUNT || n_pairs < 0) return GSC_ERR_INVALID_ARG;
+    StageHook &h = g_hooks[stage];
+    if (!events || n_pairs == 0) {
+        h.events = nullptr;
+        h.n_pairs = 0;
+    } else {
+        h.events = events;
+        h.n_pairs = n_pairs;
+    }
+    h.count = 0;
+    return GSC_OK;
 }
 
 gsc_status gsc_workspace_size(int64_t n_max, int32_t J, int32_t C, size_t *bytes)

@@ -70,28 +70,34 @@ __device__ inline uint32_t block_excl_scan(uint32_t v, uint32_t *tmp, uint32_t *
 // meets an inclusive prefix, then publishes its own inclusive prefix. Tiles take their index
 // from an atomic counter in launch order, so every tile waited on has already started and
 // never waits on a later one. A spin limit turns a (never expected) stall into an error.
+//
+// A status word carries its value in the same atomic word as its flag, and a tile uses nothing
+// but those values, so relaxed device-scope atomics suffice (no cache-wide acquire/release).
+// The walk issues LB_WINDOW predecessor loads at a time: all tiles are resident together and
+// publish at about the same time, so the walk is long and its latency is what matters.
 constexpr uint32_t SPIN_LIMIT = 1u << 22;
+constexpr int LB_WINDOW = 16;
 
 // 64-bit status word: [63:62] flag (0 none, 1 aggregate, 2 inclusive), [61:0] value.
 constexpr uint64_t LB_AGG = 1ull << 62;
 constexpr uint64_t LB_INC = 2ull << 62;
 constexpr uint64_t LB_VAL = (1ull << 62) - 1ull;
 
-__device__ inline void st_rel(uint64_t *p, uint64_t v)
+__device__ inline void st_relaxed(uint64_t *p, uint64_t v)
 {
-    __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ inline uint64_t ld_acq(const uint64_t *p)
+__device__ inline uint64_t ld_relaxed(const uint64_t *p)
 {
-    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ inline void st_rel32(uint32_t *p, uint32_t v)
+__device__ inline void st_relaxed32(uint32_t *p, uint32_t v)
 {
-    __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ inline uint32_t ld_acq32(const uint32_t *p)
+__device__ inline uint32_t ld_relaxed32(const uint32_t *p)
 {
-    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 struct OpSum {
@@ -118,29 +124,45 @@ __device__ inline uint64_t lookback(uint64_t *status, uint32_t stride, uint32_t 
                                     Ctrl *ctrl)
 {
     if (tile == 0) {
-        st_rel(&status[0], LB_INC | agg);
+        st_relaxed(&status[0], LB_INC | agg);
         return Op::identity();
     }
-    st_rel(&status[(size_t)tile * stride], LB_AGG | agg);
+    st_relaxed(&status[(size_t)tile * stride], LB_AGG | agg);
     uint64_t acc = Op::identity();
-    int64_t j = (int64_t)tile - 1;
+    int64_t j = (int64_t)tile - 1;  // nearest predecessor not yet combined
     uint32_t spins = 0;
-    while (j >= 0) {
-        const uint64_t w = ld_acq(&status[(size_t)j * stride]);
-        const uint64_t flag = w >> 62;
-        if (flag == 0) {
+    bool done = false;
+    while (!done) {
+        uint64_t w[LB_WINDOW];
+#pragma unroll
+        for (int i = 0; i < LB_WINDOW; ++i)
+            w[i] = (j - i >= 0) ? ld_relaxed(&status[(size_t)(j - i) * stride]) : (LB_INC | Op::identity());
+        int used = 0;
+        bool stalled = false, stop = false;
+#pragma unroll
+        for (int i = 0; i < LB_WINDOW; ++i) {  // predicated (no break) so w stays in registers
+            const uint64_t flag = w[i] >> 62;
+            const bool take = !stop && flag != 0;
+            if (take) {
+                acc = Op::combine(w[i] & LB_VAL, acc);
+                ++used;
+            }
+            if (!stop && flag == 0) stalled = true;
+            if (!stop && flag != 1) {
+                done = done || flag == 2;
+                stop = true;
+            }
+        }
+        j -= used;
+        if (stalled) {
             if (++spins > SPIN_LIMIT) {
                 set_error(ctrl, GSC_ERR_INTERNAL);
                 break;
             }
             __builtin_amdgcn_s_sleep(1);
-            continue;
         }
-        acc = Op::combine(w & LB_VAL, acc);
-        if (flag == 2) break;
-        --j;
     }
-    st_rel(&status[(size_t)tile * stride], LB_INC | Op::combine(acc, agg));
+    st_relaxed(&status[(size_t)tile * stride], LB_INC | Op::combine(acc, agg));
     return acc;
 }
 
@@ -150,29 +172,44 @@ __device__ inline uint32_t lookback_sum32(uint32_t *status, uint32_t stride, uin
 {
     constexpr uint32_t AGG = 1u << 30, INC = 2u << 30, VAL = (1u << 30) - 1u;
     if (tile == 0) {
-        st_rel32(&status[0], INC | agg);
+        st_relaxed32(&status[0], INC | agg);
         return 0;
     }
-    st_rel32(&status[(size_t)tile * stride], AGG | agg);
+    st_relaxed32(&status[(size_t)tile * stride], AGG | agg);
     uint32_t acc = 0;
     int64_t j = (int64_t)tile - 1;
     uint32_t spins = 0;
-    while (j >= 0) {
-        const uint32_t w = ld_acq32(&status[(size_t)j * stride]);
-        const uint32_t flag = w >> 30;
-        if (flag == 0) {
+    bool done = false;
+    while (!done) {
+        uint32_t w[LB_WINDOW];
+#pragma unroll
+        for (int i = 0; i < LB_WINDOW; ++i)
+            w[i] = (j - i >= 0) ? ld_relaxed32(&status[(size_t)(j - i) * stride]) : INC;
+        int used = 0;
+        bool stalled = false, stop = false;
+#pragma unroll
+        for (int i = 0; i < LB_WINDOW; ++i) {  // predicated (no break) so w stays in registers
+            const uint32_t flag = w[i] >> 30;
+            if (!stop && flag != 0) {
+                acc += w[i] & VAL;
+                ++used;
+            }
+            if (!stop && flag == 0) stalled = true;
+            if (!stop && flag != 1) {
+                done = done || flag == 2;
+                stop = true;
+            }
+        }
+        j -= used;
+        if (stalled) {
             if (++spins > SPIN_LIMIT) {
                 set_error(ctrl, GSC_ERR_INTERNAL);
                 break;
             }
             __builtin_amdgcn_s_sleep(1);
-            continue;
         }
-        acc += w & VAL;
-        if (flag == 2) break;
-        --j;
     }
-    st_rel32(&status[(size_t)tile * stride], INC | (acc + agg));
+    st_relaxed32(&status[(size_t)tile * stride], INC | (acc + agg));
     return acc;
 }
 

@@ -34,8 +34,8 @@ constexpr int DEC_THREADS = 256;
 constexpr int DEC_PPT = 8;              // parents per thread
 constexpr int DEC_TILE = DEC_THREADS * DEC_PPT;
 
-constexpr int RT = 512;                 // RAHT tile: entries per workgroup
-constexpr int RAHT_THREADS = 512;
+constexpr int RT = 256;                 // RAHT tile: entries per workgroup
+constexpr int RAHT_THREADS = 256;
 constexpr int OPEN_CAP = 128;           // >= 6J + 2 open entries per tile for J <= 21
 constexpr int NLVL = 64;                // binary levels 1..63 fit in a 64-bit mask
 constexpr uint8_t LVL_NONE = 127;       // level of entry 0: it never merges as a right sibling

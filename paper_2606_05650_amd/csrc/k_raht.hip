@@ -328,6 +328,8 @@ __global__ __launch_bounds__(RAHT_THREADS) void k_raht_fwd(TileMap m, int k)
     __shared__ uint16_t s_lst[LSTART_N];
     __shared__ uint16_t s_opos[OPEN_CAP];
     __shared__ uint32_t s_idx[RT + 1];
+    __shared__ uint32_t s_m0[RT + 1];
+    __shared__ uint32_t s_first[RT];
 
     const uint32_t f = frame_of(m, blockIdx.x);
     const FrameDesc &fd = *m.fd[f];
@@ -344,29 +346,45 @@ __global__ __launch_bounds__(RAHT_THREADS) void k_raht_fwd(TileMap m, int k)
     // ---- load the entries' values
     if (k == 1 && fd.mode == MODE_ENCODE) {
         // merge duplicates: the mean of the rows of the Gaussians in the voxel (Sec. 2.1),
-        // summed in input order (the sort is stable)
+        // summed in input order (the sort is stable). The run starts and the first member's
+        // row are staged in LDS so that the row loads below are independent of each other.
         const uint32_t *perm = (fd.P & 1) ? fd.vals_b : fd.vals_a;
+        for (int j = tid; j <= ts.mlen; j += RAHT_THREADS) s_m0[j] = fd.vh[ts.s + j];
+        __syncthreads();
+        for (int j = tid; j < ts.mlen; j += RAHT_THREADS) s_first[j] = perm[s_m0[j]];
+        __syncthreads();
         const bool vec = (C % 4 == 0) && aligned16(fd.attr);
-        for (uint32_t t = tid; t < nvals; t += RAHT_THREADS) {
-            const uint32_t j = t / C4, c4 = t % C4;
-            const uint32_t v = ts.s + j;
-            const uint32_t m0 = fd.vh[v], m1 = fd.vh[v + 1];
-            float4 acc = load_row4(fd.attr, perm[m0], C, c4, vec);
-            for (uint32_t mm = m0 + 1; mm < m1; ++mm) {
-                const float4 x = load_row4(fd.attr, perm[mm], C, c4, vec);
-                acc.x += x.x;
-                acc.y += x.y;
-                acc.z += x.z;
-                acc.w += x.w;
+        constexpr int U = 4;
+        for (uint32_t t0 = tid; t0 < nvals; t0 += U * RAHT_THREADS) {
+            float4 v[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const uint32_t t = t0 + u * RAHT_THREADS;
+                if (t < nvals) v[u] = load_row4(fd.attr, s_first[t / C4], C, t % C4, vec);
             }
-            if (m1 - m0 > 1) {
-                const float cnt = (float)(m1 - m0);
-                acc.x /= cnt;
-                acc.y /= cnt;
-                acc.z /= cnt;
-                acc.w /= cnt;
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const uint32_t t = t0 + u * RAHT_THREADS;
+                if (t >= nvals) break;
+                const uint32_t j = t / C4, c4 = t % C4;
+                const uint32_t m0 = s_m0[j], m1 = s_m0[j + 1];
+                float4 acc = v[u];
+                if (m1 - m0 > 1) {
+                    for (uint32_t mm = m0 + 1; mm < m1; ++mm) {
+                        const float4 x = load_row4(fd.attr, perm[mm], C, c4, vec);
+                        acc.x += x.x;
+                        acc.y += x.y;
+                        acc.z += x.z;
+                        acc.w += x.w;
+                    }
+                    const float cnt = (float)(m1 - m0);
+                    acc.x /= cnt;
+                    acc.y /= cnt;
+                    acc.z /= cnt;
+                    acc.w /= cnt;
+                }
+                s_y[j * C4 + c4] = acc;
             }
-            s_y[j * C4 + c4] = acc;
         }
     } else if (k == 1) {
         const bool vec = (C % 4 == 0) && aligned16(fd.attr);
@@ -472,27 +490,41 @@ __global__ __launch_bounds__(RAHT_THREADS) void k_raht_inv(TileMap m, int k)
         const gsc_header *h = reinterpret_cast<const gsc_header *>(fd.in_stream);
         const int32_t *coef = reinterpret_cast<const int32_t *>(fd.in_stream + h->coef_offset);
         const bool vec = (C % 4 == 0);
-        for (uint32_t t = tid; t < nvals; t += RAHT_THREADS) {
-            const uint32_t j = t / C4, c4 = t % C4;
-            const uint64_t row = entry_index(k, s_idx, ts.s, (int)j);
-            const int32_t *p = coef + row * C + 4 * c4;
-            int4 q = make_int4(0, 0, 0, 0);
-            if (vec) {
-                q = *reinterpret_cast<const int4 *>(p);
-            } else {
-                const uint32_t c = 4 * c4;
-                if (c + 0 < C) q.x = p[0];
-                if (c + 1 < C) q.y = p[1];
-                if (c + 2 < C) q.z = p[2];
-                if (c + 3 < C) q.w = p[3];
+        constexpr int U = 4;
+        for (uint32_t t0 = tid; t0 < nvals; t0 += U * RAHT_THREADS) {
+            int4 qv[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const uint32_t t = t0 + u * RAHT_THREADS;
+                if (t >= nvals) break;
+                const uint32_t j = t / C4, c4 = t % C4;
+                const uint64_t row = entry_index(k, s_idx, ts.s, (int)j);
+                const int32_t *p = coef + row * C + 4 * c4;
+                int4 q = make_int4(0, 0, 0, 0);
+                if (vec) {
+                    q = *reinterpret_cast<const int4 *>(p);
+                } else {
+                    const uint32_t c = 4 * c4;
+                    if (c + 0 < C) q.x = p[0];
+                    if (c + 1 < C) q.y = p[1];
+                    if (c + 2 < C) q.z = p[2];
+                    if (c + 3 < C) q.w = p[3];
+                }
+                qv[u] = q;
             }
-            const uint32_t c = 4 * c4;
-            float4 y;
-            y.x = (float)q.x * (c + 0 < C ? h->quant_step[c + 0] : 0.f);
-            y.y = (float)q.y * (c + 1 < C ? h->quant_step[c + 1] : 0.f);
-            y.z = (float)q.z * (c + 2 < C ? h->quant_step[c + 2] : 0.f);
-            y.w = (float)q.w * (c + 3 < C ? h->quant_step[c + 3] : 0.f);
-            s_y[j * C4 + c4] = y;
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const uint32_t t = t0 + u * RAHT_THREADS;
+                if (t >= nvals) break;
+                const uint32_t j = t / C4, c4 = t % C4;
+                const uint32_t c = 4 * c4;
+                float4 y;
+                y.x = (float)qv[u].x * (c + 0 < C ? h->quant_step[c + 0] : 0.f);
+                y.y = (float)qv[u].y * (c + 1 < C ? h->quant_step[c + 1] : 0.f);
+                y.z = (float)qv[u].z * (c + 2 < C ? h->quant_step[c + 2] : 0.f);
+                y.w = (float)qv[u].w * (c + 3 < C ? h->quant_step[c + 3] : 0.f);
+                s_y[j * C4 + c4] = y;
+            }
         }
     } else {  // MODE_ADJ_F32: float coefficient rows
         const bool vec = (C % 4 == 0) && aligned16(fd.attr);

@@ -164,6 +164,18 @@ def _stream(stream=None):
     return ctypes.c_void_p(s.cuda_stream)
 
 
+def assert_disjoint(ranges):
+    """Raise if any two device ranges (pointer, bytes) of one launch overlap."""
+    rs = sorted((int(p), int(n)) for p, n in ranges if n > 0)
+    for (p0, n0), (p1, _) in zip(rs, rs[1:]):
+        if p0 + n0 > p1:
+            raise ValueError(f"device buffers of one batch overlap at {p1:#x}")
+
+
+def _nbytes(t):
+    return t.numel() * t.element_size()
+
+
 def _dev_u8(nbytes, device):
     torch = _torch()
     return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
@@ -175,6 +187,7 @@ class Encoded:
     info: "object"       # int32 device tensor [GSC_INFO_WORDS]
     J: int
     C: int
+    ws: "object" = None  # the workspace the call used (kept alive with the result)
 
     def host_info(self):
         return self.info.cpu().numpy()
@@ -227,7 +240,7 @@ def encode_frame(pos, attr, params, *, ws=None, stream_buf=None, info=None, coef
                                 stream_buf.numel(), _ptr(ws.buf), ws.bytes, _ptr(info),
                                 _ptr(coef_f32), _ptr(leaf_codes), _stream(stream))
     _check(rc, "gsc_encode_frame")
-    return Encoded(stream_buf, info, int(params.J), C)
+    return Encoded(stream_buf, info, int(params.J), C, ws)
 
 
 @dataclass
@@ -237,6 +250,7 @@ class Decoded:
     vox: "object"
     codes: "object"
     info: "object"
+    ws: "object" = None
 
     def n_vox(self):
         return int(self.info[1].item())
@@ -269,7 +283,7 @@ def decode_frame(stream_buf, J, C, n_cap, *, stream_bytes=None, ws=None, want_vo
                                 _ptr(vox), _ptr(attr_out), _ptr(codes), _ptr(ws.buf), ws.bytes,
                                 _ptr(info), _stream(stream))
     _check(rc, "gsc_decode_frame")
-    return Decoded(pos_out, attr_out, vox, codes, info)
+    return Decoded(pos_out, attr_out, vox, codes, info, ws)
 
 
 def encode_batch(frames, params, *, workspaces=None, stream=None):
@@ -280,6 +294,9 @@ def encode_batch(frames, params, *, workspaces=None, stream=None):
         raise ValueError("1..64 frames per batch")
     descs = (FrameDescC * F)()
     outs = []
+    # Every buffer of every frame stays referenced (in `outs`) until after the launch: a
+    # workspace released inside this loop could be handed by the caching allocator to the next
+    # frame's buffers of the same batch, and one launch would then see overlapping buffers.
     for f, (pos, attr) in enumerate(frames):
         n = int(pos.shape[0])
         dev = pos.device
@@ -292,7 +309,10 @@ def encode_batch(frames, params, *, workspaces=None, stream=None):
         d.d_pos, d.d_attr, d.n = pos.data_ptr(), attr.data_ptr(), n
         d.d_stream, d.stream_cap = sb.data_ptr(), sb.numel()
         d.d_ws, d.ws_bytes, d.d_info = ws.buf.data_ptr(), ws.bytes, info.data_ptr()
-        outs.append(Encoded(sb, info, int(params.J), int(params.C)))
+        outs.append(Encoded(sb, info, int(params.J), int(params.C), ws))
+    assert_disjoint([(o.stream.data_ptr(), _nbytes(o.stream)) for o in outs] +
+                    [(o.info.data_ptr(), _nbytes(o.info)) for o in outs] +
+                    [(o.ws.buf.data_ptr(), o.ws.bytes) for o in outs])
     _check(lib().gsc_encode_batch(descs, F, ctypes.byref(params), _stream(stream)),
            "gsc_encode_batch")
     return outs
@@ -305,6 +325,7 @@ def decode_batch(encoded, n_caps, *, workspaces=None, stream=None):
     descs = (StreamDescC * F)()
     outs = []
     J, C = encoded[0].J, encoded[0].C
+    # buffers stay referenced until after the launch (see encode_batch)
     for f, e in enumerate(encoded):
         dev = e.stream.device
         n_cap = int(n_caps[f])
@@ -316,7 +337,11 @@ def decode_batch(encoded, n_caps, *, workspaces=None, stream=None):
         d.d_stream, d.stream_bytes, d.n_cap = e.stream.data_ptr(), e.stream.numel(), n_cap
         d.d_pos_out, d.d_attr_out = pos.data_ptr(), attr.data_ptr()
         d.d_ws, d.ws_bytes, d.d_info = ws.buf.data_ptr(), ws.bytes, info.data_ptr()
-        outs.append(Decoded(pos, attr, None, None, info))
+        outs.append(Decoded(pos, attr, None, None, info, ws))
+    assert_disjoint([(o.pos.data_ptr(), _nbytes(o.pos)) for o in outs] +
+                    [(o.attr.data_ptr(), _nbytes(o.attr)) for o in outs] +
+                    [(o.info.data_ptr(), _nbytes(o.info)) for o in outs] +
+                    [(o.ws.buf.data_ptr(), o.ws.bytes) for o in outs])
     _check(lib().gsc_decode_batch(descs, F, int(J), int(C), _stream(stream)), "gsc_decode_batch")
     return outs
 

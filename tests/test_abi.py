@@ -96,3 +96,11 @@ def test_header_layout_matches_c_struct():
     assert d.fields["occ_offset"][1] == 416
     assert d.itemsize == 456 <= gsc.HEADER_BYTES
     assert ctypes.sizeof(gsc.Params) == 304
+
+
+def test_batch_buffer_overlap_is_rejected():
+    # a batch launch must never see two frames' buffers overlap (e.g. a workspace released
+    # early and handed to another frame's output by the allocator)
+    gsc.assert_disjoint([(0x1000, 0x100), (0x1100, 0x10), (0x2000, 0x1000)])
+    with pytest.raises(ValueError):
+        gsc.assert_disjoint([(0x1000, 0x200), (0x1100, 0x10)])
