@@ -8,6 +8,7 @@
 namespace gsc {
 uint32_t bbox_blocks(uint32_t n);
 uint32_t voxelize_blocks(uint32_t n);
+uint32_t prelude_blocks(uint32_t tiles);
 }  // namespace gsc
 
 using namespace gsc;
@@ -149,14 +150,16 @@ gsc_status run_prelude(const Frame *fr, int F, hipStream_t s)
     StageScope sc(GSC_STAGE_PRELUDE, s);
     const int K = max_K(fr, F);
     for (int k = 1; k <= K; ++k) {
-        TileMap m = make_map(fr, F, [k](const Frame &x) { return (int)x.L.K >= k ? x.L.tiles[k] : 0u; });
+        TileMap m = make_map(fr, F, [k](const Frame &x) {
+            return (int)x.L.K >= k ? prelude_blocks(x.L.tiles[k]) : 0u;
+        });
         if (m.start[F] == 0) continue;
         GSC_LAUNCH(launch_prelude(m, k, s));
     }
     return GSC_OK;
 }
 
-gsc_status run_forward(const Frame *fr, int F, int C4, hipStream_t s)
+gsc_status run_forward(const Frame *fr, int F, const RahtCfg &cfg, hipStream_t s)
 {
     const int K = max_K(fr, F);
     for (int k = 1; k <= K; ++k) {
@@ -164,7 +167,7 @@ gsc_status run_forward(const Frame *fr, int F, int C4, hipStream_t s)
         if (m.start[F] == 0) continue;
         if (k == 1) {
             StageScope sc(GSC_STAGE_RAHT_FWD1, s);
-            GSC_LAUNCH(launch_raht_fwd(m, k, C4, s));
+            GSC_LAUNCH(launch_raht_fwd(m, k, cfg, s));
         } else {
             if (k == 2 && g_hooks[GSC_STAGE_RAHT_FWD_TOP].n_pairs > 0) {
                 // one scope over all upper levels
@@ -172,17 +175,17 @@ gsc_status run_forward(const Frame *fr, int F, int C4, hipStream_t s)
                 for (int kk = 2; kk <= K; ++kk) {
                     TileMap mm = make_map(fr, F, [kk](const Frame &x) { return (int)x.L.K >= kk ? x.L.tiles[kk] : 0u; });
                     if (mm.start[F] == 0) continue;
-                    GSC_LAUNCH(launch_raht_fwd(mm, kk, C4, s));
+                    GSC_LAUNCH(launch_raht_fwd(mm, kk, cfg, s));
                 }
                 break;
             }
-            GSC_LAUNCH(launch_raht_fwd(m, k, C4, s));
+            GSC_LAUNCH(launch_raht_fwd(m, k, cfg, s));
         }
     }
     return GSC_OK;
 }
 
-gsc_status run_inverse(const Frame *fr, int F, int C4, hipStream_t s)
+gsc_status run_inverse(const Frame *fr, int F, const RahtCfg &cfg, hipStream_t s)
 {
     const int K = max_K(fr, F);
     {
@@ -190,13 +193,13 @@ gsc_status run_inverse(const Frame *fr, int F, int C4, hipStream_t s)
         for (int k = K; k >= 2; --k) {
             TileMap m = make_map(fr, F, [k](const Frame &x) { return (int)x.L.K >= k ? x.L.tiles[k] : 0u; });
             if (m.start[F] == 0) continue;
-            GSC_LAUNCH(launch_raht_inv(m, k, C4, s));
+            GSC_LAUNCH(launch_raht_inv(m, k, cfg, s));
         }
     }
     TileMap m = make_map(fr, F, [](const Frame &x) { return x.L.tiles[1]; });
     if (m.start[F] > 0) {
         StageScope sc(GSC_STAGE_RAHT_INV1, s);
-        GSC_LAUNCH(launch_raht_inv(m, 1, C4, s));
+        GSC_LAUNCH(launch_raht_inv(m, 1, cfg, s));
     }
     return GSC_OK;
 }
@@ -206,6 +209,33 @@ gsc_status run_finish(const Frame *fr, int F, hipStream_t s)
     TileMap m = make_map(fr, F, [](const Frame &) { return 1u; });
     GSC_LAUNCH(launch_finish(m, s));
     return GSC_OK;
+}
+
+bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
+
+bool all_pow2(const float *step, int C)
+{
+    for (int c = 0; c < C; ++c) {
+        int e;
+        if (frexpf(step[c], &e) != 0.5f) return false;
+    }
+    return true;
+}
+
+// Specialization of the transform kernels for a batch: vectorized rows when C % 4 == 0 and
+// every row pointer the kernels touch is 16-byte aligned.
+RahtCfg raht_cfg(const Frame *fr, int F, int C, const float *steps)
+{
+    RahtCfg cfg;
+    cfg.C4 = (C + 3) / 4;
+    cfg.vec = (C % 4 == 0);
+    for (int f = 0; f < F && cfg.vec; ++f) {
+        const FrameArgs &a = fr[f].a;
+        cfg.vec = aligned16(a.attr) && aligned16(a.stream) && aligned16(a.coef_f32) &&
+                  aligned16(a.in_stream) && aligned16(a.attr_out);
+    }
+    cfg.pow2 = steps ? all_pow2(steps, C) : false;
+    return cfg;
 }
 
 // Encode F frames (already validated) with one launch per stage.
@@ -241,9 +271,9 @@ gsc_status encode_frames(const Frame *fr, int F, const gsc_params *p, hipStream_
         TileMap m = make_map(fr, F, [](const Frame &x) { return x.a.n ? x.L.occ_tiles : 0u; });
         if (m.start[F] > 0) GSC_LAUNCH(launch_occupancy(m, s));
     }
-    const int C4 = (p->C + 3) / 4;
+    const RahtCfg cfg = raht_cfg(fr, F, p->C, p->quant_step);
     if ((st = run_prelude(fr, F, s)) != GSC_OK) return st;
-    if ((st = run_forward(fr, F, C4, s)) != GSC_OK) return st;
+    if ((st = run_forward(fr, F, cfg, s)) != GSC_OK) return st;
     return run_finish(fr, F, s);
 }
 
@@ -268,9 +298,9 @@ gsc_status decode_frames(const Frame *fr, int F, int J, int C, hipStream_t s)
             GSC_LAUNCH(launch_dec_level(m, d, s));
         }
     }
-    const int C4 = (C + 3) / 4;
+    const RahtCfg cfg = raht_cfg(fr, F, C, nullptr);
     if ((st = run_prelude(fr, F, s)) != GSC_OK) return st;
-    if ((st = run_inverse(fr, F, C4, s)) != GSC_OK) return st;
+    if ((st = run_inverse(fr, F, cfg, s)) != GSC_OK) return st;
     return run_finish(fr, F, s);
 }
 
@@ -465,11 +495,11 @@ static gsc_status raht_f32(const uint64_t *d_codes, int64_t nv, int32_t J, int32
     if ((st = run_setup(&fr, 1, proto, s)) != GSC_OK) return st;
     if (nv > 0) {
         if ((st = run_prelude(&fr, 1, s)) != GSC_OK) return st;
-        const int C4 = (C + 3) / 4;
+        const RahtCfg cfg = raht_cfg(&fr, 1, C, nullptr);
         if (adjoint)
-            st = run_inverse(&fr, 1, C4, s);
+            st = run_inverse(&fr, 1, cfg, s);
         else
-            st = run_forward(&fr, 1, C4, s);
+            st = run_forward(&fr, 1, cfg, s);
         if (st != GSC_OK) return st;
     }
     return run_finish(&fr, 1, s);

@@ -6,6 +6,48 @@
 
 namespace gsc {
 
+// Pointers read from a frame descriptor are generic; accesses through them compile to flat
+// instructions, which also count against the LDS wait counter, so an LDS wait in a loop would
+// also wait for every outstanding global store. Hot paths cast them to the global address space.
+#define GAS __attribute__((address_space(1)))
+template <class T>
+__device__ inline GAS T *gp(T *p)
+{
+    return (GAS T *)p;
+}
+// 16-byte global accesses through clang's native vectors (HIP's float4/int4 classes cannot bind
+// to global-address-space references).
+typedef float gf4 __attribute__((ext_vector_type(4)));
+typedef int gi4 __attribute__((ext_vector_type(4)));
+__device__ inline float4 gload4(const GAS float *p)
+{
+    const gf4 v = *reinterpret_cast<const GAS gf4 *>(p);
+    return make_float4(v.x, v.y, v.z, v.w);
+}
+__device__ inline void gstore4(GAS float *p, const float4 &v)
+{
+    gf4 t;
+    t.x = v.x;
+    t.y = v.y;
+    t.z = v.z;
+    t.w = v.w;
+    *reinterpret_cast<GAS gf4 *>(p) = t;
+}
+__device__ inline int4 gload4i(const GAS int32_t *p)
+{
+    const gi4 v = *reinterpret_cast<const GAS gi4 *>(p);
+    return make_int4(v.x, v.y, v.z, v.w);
+}
+__device__ inline void gstore4i(GAS int32_t *p, const int4 &v)
+{
+    gi4 t;
+    t.x = v.x;
+    t.y = v.y;
+    t.z = v.z;
+    t.w = v.w;
+    *reinterpret_cast<GAS gi4 *>(p) = t;
+}
+
 // ------------------------------------------------------------------------- frame lookup
 __device__ inline uint32_t frame_of(const TileMap &m, uint32_t b)
 {
@@ -63,6 +105,28 @@ __device__ inline uint32_t block_excl_scan(uint32_t v, uint32_t *tmp, uint32_t *
     if (total) *total = tmp[NW];
     __syncthreads();
     return r;
+}
+
+// Exclusive scan within groups of GS consecutive threads (GS a multiple of 64) of an NT-thread
+// block. `tmp` holds NT/64 words of LDS. Returns the exclusive prefix of v inside its group;
+// *total receives the group total. Every thread of the block must call it; ends with a barrier.
+template <int NT, int GS>
+__device__ inline uint32_t group_excl_scan(uint32_t v, uint32_t *tmp, uint32_t *total)
+{
+    const uint32_t inc = wave_incl_scan(v);
+    const uint32_t w = threadIdx.x / WAVE;
+    if (lane_id() == WAVE - 1) tmp[w] = inc;
+    __syncthreads();
+    const uint32_t g0 = (threadIdx.x / GS) * (GS / WAVE);
+    uint32_t pre = 0, tot = 0;
+    for (uint32_t i = g0; i < g0 + GS / WAVE; ++i) {
+        const uint32_t t = tmp[i];
+        if (i < w) pre += t;
+        tot += t;
+    }
+    if (total) *total = tot;
+    __syncthreads();
+    return pre + inc - v;
 }
 
 // ------------------------------------------------------------ decoupled look-back scan
@@ -163,6 +227,63 @@ __device__ inline uint64_t lookback(uint64_t *status, uint32_t stride, uint32_t 
         }
     }
     st_relaxed(&status[(size_t)tile * stride], LB_INC | Op::combine(acc, agg));
+    return acc;
+}
+
+// Ordered combination of lanes [0, cnt) of a wave under Op, lane 0 being the newest value and
+// higher lanes older ones; the result is returned to every lane.
+template <class Op>
+__device__ inline uint64_t wave_combine_ordered(uint64_t v, uint32_t cnt)
+{
+    const uint32_t lane = lane_id();
+#pragma unroll
+    for (int k = 1; k < WAVE; k <<= 1) {
+        const uint64_t older = __shfl_down(v, k, WAVE);
+        if (lane + k < cnt) v = Op::combine(older, v);
+    }
+    return __shfl(v, 0, WAVE);
+}
+
+// The same look-back performed by a whole wave: each step reads the 64 nearest predecessors at
+// once, so the inclusive prefix frontier advances 64 tiles per load latency. Every lane of the
+// calling wave must call it; the result is returned to every lane.
+template <class Op>
+__device__ inline uint64_t lookback_wave(uint64_t *status, uint32_t stride, uint32_t tile,
+                                         uint64_t agg, Ctrl *ctrl)
+{
+    const uint32_t lane = lane_id();
+    if (tile == 0) {
+        if (lane == 0) st_relaxed(&status[0], LB_INC | agg);
+        return Op::identity();
+    }
+    if (lane == 0) st_relaxed(&status[(size_t)tile * stride], LB_AGG | agg);
+    uint64_t acc = Op::identity();
+    int64_t j = (int64_t)tile - 1;  // nearest predecessor not yet combined (uniform)
+    uint32_t spins = 0;
+    while (true) {
+        const int64_t idx = j - (int64_t)lane;
+        const uint64_t w = idx >= 0 ? ld_relaxed(&status[(size_t)idx * stride]) : (LB_INC | Op::identity());
+        const uint32_t flag = (uint32_t)(w >> 62);
+        const uint64_t inc_mask = __ballot(flag == 2);
+        const uint64_t zero_mask = __ballot(flag == 0);
+        const uint32_t cut = inc_mask ? (uint32_t)(__ffsll((long long)inc_mask) - 1) : (uint32_t)(WAVE - 1);
+        const uint64_t need = cut == WAVE - 1 ? ~0ull : ((2ull << cut) - 1ull);
+        const uint64_t blocked = zero_mask & need;
+        // lanes before the first one that is not ready can always be combined
+        const uint32_t cnt = blocked ? (uint32_t)(__ffsll((long long)blocked) - 1) : cut + 1;
+        if (cnt > 0) acc = Op::combine(wave_combine_ordered<Op>(w & LB_VAL, cnt), acc);
+        j -= (int64_t)cnt;
+        if (!blocked) {
+            if (inc_mask) break;
+            continue;
+        }
+        if (++spins > SPIN_LIMIT) {
+            if (lane == 0) set_error(ctrl, GSC_ERR_INTERNAL);
+            break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+    }
+    if (lane == 0) st_relaxed(&status[(size_t)tile * stride], LB_INC | Op::combine(acc, agg));
     return acc;
 }
 

@@ -40,7 +40,9 @@ constexpr int OPEN_CAP = 128;           // >= 6J + 2 open entries per tile for J
 constexpr int NLVL = 64;                // binary levels 1..63 fit in a 64-bit mask
 constexpr uint8_t LVL_NONE = 127;       // level of entry 0: it never merges as a right sibling
 constexpr int MAXK = 24;                // RAHT tiling levels (sequences S_1 .. S_MAXK)
-constexpr int LSTART_N = NLVL + 2;      // per-tile level segment starts (u16)
+constexpr int NCLS = RT / 64 + 1;       // merge classes: local to wave chunk 0..3, or crossing
+constexpr int SEG_N = NLVL * NCLS + 1;  // per-tile (level, class) segment starts + total
+constexpr int LSTART_N = SEG_N + 1;     // padded to an even count of u16
 
 constexpr uint32_t BBOX_SENTINEL_MIN = 0xFFFFFFFFu;
 
@@ -84,7 +86,7 @@ struct RahtLevel {
     uint32_t *s_idx;     // k >= 2: voxel index of each entry of S_k
     uint8_t *s_lvl;      // k >= 2: binary level of each entry
     uint32_t *rec;       // per tile: RT merge records, sorted by level
-    uint16_t *lstart;    // per tile: LSTART_N segment starts (record index of level x)
+    uint16_t *lstart;    // per tile: LSTART_N starts of the (level, class) record segments
     uint16_t *opos;      // per tile: OPEN_CAP positions of open entries
     uint32_t *obase;     // per tile: index in S_{k+1} of its first open entry
     uint32_t *ocnt;      // per tile: open entries
@@ -292,8 +294,14 @@ hipError_t launch_occupancy(const TileMap &m, hipStream_t s);
 hipError_t launch_dec_top(const TileMap &m, hipStream_t s);
 hipError_t launch_dec_level(const TileMap &m, int d, hipStream_t s);
 hipError_t launch_prelude(const TileMap &m, int k, hipStream_t s);
-hipError_t launch_raht_fwd(const TileMap &m, int k, int C4, hipStream_t s);
-hipError_t launch_raht_inv(const TileMap &m, int k, int C4, hipStream_t s);
+// Compile-time specializations of the transform kernels: vec = C % 4 == 0 and every row
+// pointer 16-byte aligned; pow2 = every quantization step a power of two.
+struct RahtCfg {
+    int C4;
+    bool vec, pow2;
+};
+hipError_t launch_raht_fwd(const TileMap &m, int k, const RahtCfg &cfg, hipStream_t s);
+hipError_t launch_raht_inv(const TileMap &m, int k, const RahtCfg &cfg, hipStream_t s);
 hipError_t launch_finish(const TileMap &m, hipStream_t s);
 
 }  // namespace gsc

@@ -242,7 +242,7 @@ __global__ __launch_bounds__(BBOX_THREADS) void k_bbox(TileMap m)
     for (uint32_t i = p0 + threadIdx.x; i < p1; i += BBOX_THREADS) {
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            const float v = fd.pos[(size_t)i * 3 + a];
+            const float v = gp(fd.pos)[(size_t)i * 3 + a];
             bad |= !isfinite(v);
             mn[a] = fminf(mn[a], v);
             mx[a] = fmaxf(mx[a], v);
@@ -321,13 +321,13 @@ __global__ __launch_bounds__(VOX_THREADS) void k_voxelize(TileMap m)
         uint32_t v[3];
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            const double p = (double)fd.pos[(size_t)i * 3 + a];
+            const double p = (double)gp(fd.pos)[(size_t)i * 3 + a];
             double t = floor(__ddiv_rn(__dsub_rn(p, lo[a]), cell));
             t = t < 0.0 ? 0.0 : (t > top ? top : t);
             v[a] = (uint32_t)t;
         }
         const uint64_t key = morton3(v[0], v[1], v[2]);
-        fd.keys_a[i] = key;
+        gp(fd.keys_a)[i] = key;
         for (uint32_t p = 0; p < P; ++p)
             atomicAdd(&s_hist[p * SORT_BINS + ((key >> (p * SORT_BITS)) & (SORT_BINS - 1))], 1u);
     }
@@ -385,10 +385,10 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_pass(TileMap m, int pass)
     const uint32_t tile = s_tile;
     const uint32_t base = tile * SORT_TILE;
     if (base >= n) return;
-    const uint64_t *kin = (pass & 1) ? fd.keys_b : fd.keys_a;
-    const uint32_t *vin = (pass & 1) ? fd.vals_b : fd.vals_a;
-    uint64_t *kout = (pass & 1) ? fd.keys_a : fd.keys_b;
-    uint32_t *vout = (pass & 1) ? fd.vals_a : fd.vals_b;
+    const GAS uint64_t *kin = gp((pass & 1) ? fd.keys_b : fd.keys_a);
+    const GAS uint32_t *vin = gp((pass & 1) ? fd.vals_b : fd.vals_a);
+    GAS uint64_t *kout = gp((pass & 1) ? fd.keys_a : fd.keys_b);
+    GAS uint32_t *vout = gp((pass & 1) ? fd.vals_a : fd.vals_b);
     const uint32_t shift = (uint32_t)pass * SORT_BITS;
 
     uint64_t key[SORT_KPT];
@@ -483,7 +483,7 @@ __global__ __launch_bounds__(DEDUP_THREADS) void k_dedup(TileMap m)
     const uint32_t tile = s_tile;
     const uint32_t base = tile * DEDUP_TILE;
     if (base >= n) return;
-    const uint64_t *K = (fd.P & 1) ? fd.keys_b : fd.keys_a;  // output of the last sort pass
+    const GAS uint64_t *K = gp((fd.P & 1) ? fd.keys_b : fd.keys_a);  // output of the last sort pass
     const uint32_t p0 = base + tid * DEDUP_KPT;
     uint32_t heads = 0;  // bit j: position p0 + j starts a voxel
     uint64_t prev = (p0 > 0 && p0 < n) ? K[p0 - 1] : 0ull;
@@ -503,7 +503,10 @@ __global__ __launch_bounds__(DEDUP_THREADS) void k_dedup(TileMap m)
     }
     uint32_t tile_total;
     const uint32_t texcl = block_excl_scan<DEDUP_THREADS>((uint32_t)__popc(heads), s_tmp, &tile_total);
-    if (tid == 0) s_base = (uint32_t)lookback<OpSum>(fd.dedup_status, 1, tile, tile_total, ctrl);
+    if (tid < WAVE) {
+        const uint32_t b = (uint32_t)lookback_wave<OpSum>(fd.dedup_status, 1, tile, tile_total, ctrl);
+        if (tid == 0) s_base = b;
+    }
     __syncthreads();
     uint32_t v = s_base + texcl;
 #pragma unroll
@@ -511,9 +514,9 @@ __global__ __launch_bounds__(DEDUP_THREADS) void k_dedup(TileMap m)
         if ((heads >> j & 1u) && v < n) {
             const uint32_t p = p0 + j;
             const uint64_t k = K[p];
-            fd.leaf[v] = k;
-            if (fd.codes_out) fd.codes_out[v] = k;
-            fd.vh[v] = p;
+            gp(fd.leaf)[v] = k;
+            if (fd.codes_out) gp(fd.codes_out)[v] = k;
+            gp(fd.vh)[v] = p;
             ++v;
         }
     }
@@ -565,8 +568,9 @@ __global__ __launch_bounds__(OCC_THREADS) void k_occupancy(TileMap m)
     if (s >= nv) return;
     const uint32_t e = min(nv, s + OCC_TILE);
     // s_code[j] = L[s - 1 + j]
+    const GAS uint64_t *leaf = gp(fd.leaf);
     for (uint32_t j = tid; j < e - s + 1; j += OCC_THREADS)
-        s_code[j] = (s + j >= 1) ? fd.leaf[s + j - 1] : 0ull;
+        s_code[j] = (s + j >= 1) ? leaf[s + j - 1] : 0ull;
     __syncthreads();
 
     uint32_t Dv[OCC_VPT];
@@ -606,13 +610,14 @@ __global__ __launch_bounds__(OCC_THREADS) void k_occupancy(TileMap m)
         if (tid == 0) s_cnt[d] = total;
     }
     __syncthreads();
-    if (tid < J) {
-        const uint32_t d = tid;
+    // one wave per depth (waves take depths w, w + 4, ...)
+    for (uint32_t d = tid / WAVE; d < J; d += OCC_THREADS / WAVE) {
         const uint32_t cnt = s_cnt[d];
         const uint32_t byte = cnt ? (s_bytes[d][(cnt - 1) >> 2] >> (8u * ((cnt - 1) & 3u))) & 0xFFu
                                   : s_carry[d];
         const uint64_t agg = ((uint64_t)cnt << 8) | byte;
-        s_pref[d] = lookback<OpSegOr>(fd.occ_status + d, J, tile, agg, ctrl);
+        const uint64_t pref = lookback_wave<OpSegOr>(fd.occ_status + d, J, tile, agg, ctrl);
+        if (lane_id() == 0) s_pref[d] = pref;
     }
     __shared__ uint64_t s_off[GSC_MAX_DEPTH + 1];
     __shared__ int s_fits;
@@ -626,7 +631,7 @@ __global__ __launch_bounds__(OCC_THREADS) void k_occupancy(TileMap m)
     __syncthreads();
     if (!s_fits) return;
     const bool last = (e == nv);
-    uint8_t *out = fd.stream;
+    GAS uint8_t *out = gp(fd.stream);
     for (uint32_t d = 0; d < J; ++d) {
         const uint64_t pref = s_pref[d];
         const uint32_t pc = (uint32_t)(pref >> 8), por = (uint32_t)(pref & 0xFF);
@@ -659,14 +664,14 @@ hipError_t launch_occupancy(const TileMap &m, hipStream_t s)
 __device__ inline void emit_leaf(const FrameDesc &fd, const gsc_header *h, uint32_t v,
                                  uint64_t code)
 {
-    fd.leaf[v] = code;
-    if (fd.codes_out) fd.codes_out[v] = code;
+    gp(fd.leaf)[v] = code;
+    if (fd.codes_out) gp(fd.codes_out)[v] = code;
     const uint32_t xyz[3] = {compact3(code), compact3(code >> 1), compact3(code >> 2)};
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        if (fd.vox_out) fd.vox_out[(size_t)v * 3 + a] = xyz[a];
+        if (fd.vox_out) gp(fd.vox_out)[(size_t)v * 3 + a] = xyz[a];
         const double c = __dadd_rn(h->bbox_min[a], __dmul_rn(__dadd_rn((double)xyz[a], 0.5), h->cell));
-        fd.pos_out[(size_t)v * 3 + a] = (float)c;
+        gp(fd.pos_out)[(size_t)v * 3 + a] = (float)c;
     }
 }
 
@@ -807,9 +812,9 @@ __global__ __launch_bounds__(DEC_THREADS) void k_dec_level(TileMap m, int d)
     if (s >= M) return;
     uint64_t off = 0;
     for (int dd = 0; dd < d; ++dd) off += ctrl->level_sizes[dd];
-    const uint8_t *occ = fd.in_stream + GSC_HEADER_BYTES + off;
-    const uint64_t *src = (d & 1) ? fd.keys_b : fd.keys_a;
-    uint64_t *dst = (d & 1) ? fd.keys_a : fd.keys_b;
+    const GAS uint8_t *occ = gp(fd.in_stream + GSC_HEADER_BYTES + off);
+    const GAS uint64_t *src = gp((d & 1) ? fd.keys_b : fd.keys_a);
+    GAS uint64_t *dst = gp((d & 1) ? fd.keys_a : fd.keys_b);
     uint32_t bytes[DEC_PPT], cnt = 0;
     bool bad = false;
 #pragma unroll
@@ -821,7 +826,10 @@ __global__ __launch_bounds__(DEC_THREADS) void k_dec_level(TileMap m, int d)
     }
     uint32_t total;
     uint32_t w = block_excl_scan<DEC_THREADS>(cnt, s_tmp, &total);
-    if (tid == 0) s_base = (uint32_t)lookback<OpSum>(fd.dec_status + fd.dec_status_off[d], 1, tile, total, ctrl);
+    if (tid < WAVE) {
+        const uint32_t b = (uint32_t)lookback_wave<OpSum>(fd.dec_status + fd.dec_status_off[d], 1, tile, total, ctrl);
+        if (tid == 0) s_base = b;
+    }
     __syncthreads();
     w += s_base;
 #pragma unroll

@@ -6,22 +6,30 @@
 //   [lo; hi] = [a b; -b a] [y0; y1],  a = sqrt(w0/(w0+w1)), b = sqrt(w1/(w0+w1)),
 // the low-pass staying at the left entry and the high-pass at the right one. An entry i > 0 is
 // removed from the active list (merged as a right sibling) exactly at level
-// l_i = msb(M[i-1] xor M[i]) + 1, so I_l = {i : l_i >= l} and the pairs of level l are the
-// entries with l_i = l and their active neighbours.
+// l_i = msb(M[i-1] xor M[i]) + 1, so I_l = {i : l_i >= l}: the pair of entry i is its nearest
+// entries with level >= l_i on either side (its left partner, and the end of its own node).
 //
 // Tiling. A workgroup owns a tile of RT consecutive entries and performs every merge whose two
-// operands lie inside the tile, all levels in LDS. A merge whose left neighbour lies before the
+// operands lie inside the tile, all levels in LDS. A merge whose left partner lies before the
 // tile, or whose right operand extends past it, is deferred: its entry is "open" and moves, with
 // its partial low-pass, to the next sequence S_{k+1}. The merges among open entries are exactly
 // the deferred merges (an open entry's neighbours in the active list are open too), so the same
 // kernels run again on S_{k+1}, until one tile holds the whole sequence. At most 6J entries of a
 // tile are open (the merges whose parent straddles one of its two boundaries: one per level).
+//
+// Inside a tile, a merge whose two operands lie in one 64-entry chunk depends only on merges of
+// that chunk. Each wave first performs the merges of its own chunk, level by level, ordered by
+// the wave's own instruction stream; then the few merges that cross chunks run level by level
+// with workgroup barriers (the inverse runs the two phases in the opposite order).
 #include "gsc_device.h"
 
 namespace gsc {
 
+static_assert(RT == 4 * WAVE, "a tile is four 64-entry wave chunks");
 static_assert(RT < 1024, "merge records pack three 10-bit positions");
-constexpr int PRE_THREADS = 256;
+constexpr int PRE_THREADS = RT;
+constexpr int NCHUNK = RT / WAVE;
+constexpr int CROSS = NCHUNK;  // class of merges that cross chunks
 
 // Size of the entry sequence S_k; a size beyond its allocation (impossible when every tile
 // leaves at most 6J + 2 entries open) is reported and treated as empty.
@@ -37,26 +45,25 @@ __device__ inline uint32_t seq_size(const FrameDesc &fd, Ctrl *ctrl, int k)
 __device__ inline bool seq_active(uint32_t nk, int k) { return k == 1 ? nk >= 1 : nk >= 2; }
 
 // ============================================================================ prelude
-// Per tile: the binary level of every entry, then the levels present, in increasing order; at
-// level x every entry with l = x looks at its current neighbours in a doubly linked active
-// list, records a local merge (left neighbour inside the tile, right operand ending inside the
-// tile or at the next entry after it when that entry survives to a higher level) or marks
-// itself open, and unlinks itself. Entries of one level are never adjacent in the active list,
-// so the unlinks of a level do not conflict. Local merges are stored sorted by level; open
-// entries are compacted, in order, into S_{k+1} with a decoupled look-back.
-__global__ __launch_bounds__(PRE_THREADS) void k_prelude(TileMap m, int k)
+// Per tile, one thread per entry: the entry's binary level l; the tile's active lists as one
+// 64-bit ballot per (level, wave chunk); the entry's left partner and node end as the nearest
+// set bits of its level's ballots. A merge is local when both lie inside the tile (the node may
+// also end exactly at the tile end when the next entry survives to a higher level); otherwise
+// the entry is open. Local merges are stored sorted by (level, class), the class being the
+// wave chunk holding the whole merge or CROSS. Open entries are compacted in order into S_{k+1}
+// with a decoupled look-back; a workgroup handles PRE_TILES consecutive tiles so that the
+// look-back chain has PRE_TILES times fewer links.
+constexpr int PRE_TILES = 4;
+constexpr int PRE_BLOCK = PRE_TILES * PRE_THREADS;
+
+__global__ __launch_bounds__(PRE_BLOCK) void k_prelude(TileMap m, int k)
 {
-    __shared__ uint32_t s_tile;
-    __shared__ uint8_t s_lvl[RT];
-    __shared__ uint8_t s_state[RT];  // 0 = untouched, 1 = local merge, 2 = open
-    __shared__ int16_t s_left[RT], s_right[RT];
-    __shared__ int16_t s_l[RT], s_r[RT];
-    __shared__ unsigned long long s_mask;
-    __shared__ uint32_t s_lcnt[NLVL], s_lfill[NLVL];
-    __shared__ uint16_t s_lstart[LSTART_N];
-    __shared__ uint32_t s_tmp[PRE_THREADS / WAVE + 1];
-    __shared__ uint32_t s_base;
-    __shared__ uint32_t s_lvl_e;
+    __shared__ uint32_t s_blk, s_base;
+    __shared__ uint32_t s_lvl_e[PRE_TILES];
+    __shared__ uint64_t s_mask[PRE_TILES][NLVL][NCHUNK];
+    __shared__ uint32_t s_cnt[PRE_TILES][SEG_N], s_fill[PRE_TILES][SEG_N];
+    __shared__ uint32_t s_tmp[PRE_BLOCK / WAVE + 1];
+    __shared__ uint32_t s_tile_excl[PRE_TILES], s_tile_cnt[PRE_TILES];
 
     const uint32_t f = frame_of(m, blockIdx.x);
     const FrameDesc &fd = *m.fd[f];
@@ -67,125 +74,138 @@ __global__ __launch_bounds__(PRE_THREADS) void k_prelude(TileMap m, int k)
     if (!seq_active(nk, k)) return;
     const RahtLevel &lv = fd.lv[k];
     const uint32_t tid = threadIdx.x;
-    if (tid == 0) s_tile = atomicAdd(&ctrl->tile_ctr[TC_PRELUDE + k], 1u);
+    if (tid == 0) s_blk = atomicAdd(&ctrl->tile_ctr[TC_PRELUDE + k], 1u);
     __syncthreads();
-    const uint32_t tile = s_tile;
+    const uint32_t blk = s_blk;
+    if (blk * PRE_TILES * RT >= nk) return;            // uniform: the whole block is past the end
+    const uint32_t g = tid / PRE_THREADS;              // tile of this thread inside the block
+    const uint32_t tile = blk * PRE_TILES + g;
     const uint32_t s = tile * RT;
-    if (s >= nk) return;
-    const uint32_t e = min(nk, s + RT);
+    const uint32_t e = s < nk ? min(nk, s + RT) : s;   // an empty tile past the end
     const int mlen = (int)(e - s);
-    const uint64_t *codes = (fd.mode == MODE_FWD_F32 || fd.mode == MODE_ADJ_F32) ? fd.codes_in : fd.leaf;
+    const GAS uint64_t *codes = gp((fd.mode == MODE_FWD_F32 || fd.mode == MODE_ADJ_F32) ? fd.codes_in : fd.leaf);
+    const GAS uint8_t *slvl = gp(lv.s_lvl);
 
-    for (int j = tid; j < RT; j += PRE_THREADS) {
-        if (j < mlen) {
-            const uint32_t i = s + j;
-            s_lvl[j] = k == 1 ? (i == 0 ? LVL_NONE : merge_level(codes[i - 1], codes[i])) : lv.s_lvl[i];
-        }
-        s_left[j] = (int16_t)(j - 1);
-        s_right[j] = (int16_t)(j + 1);
-        s_state[j] = 0;
+    const int j = (int)(tid % PRE_THREADS);
+    const uint32_t w = (uint32_t)j / WAVE, lane = lane_id();
+    uint32_t lvl = 0;  // 0: no entry
+    if (j < mlen) {
+        const uint32_t i = s + j;
+        lvl = k == 1 ? (i == 0 ? LVL_NONE : merge_level(codes[i - 1], codes[i])) : slvl[i];
     }
-    if (tid < NLVL) {
-        s_lcnt[tid] = 0;
-        s_lfill[tid] = 0;
+    for (uint32_t x = j; x < (uint32_t)SEG_N; x += PRE_THREADS) {
+        s_cnt[g][x] = 0;
+        s_fill[g][x] = 0;
     }
-    if (tid == 0) {
-        s_mask = 0;
-        s_lvl_e = e < nk ? (k == 1 ? merge_level(codes[e - 1], codes[e]) : lv.s_lvl[e]) : LVL_NONE;
+    if (j == 0)
+        s_lvl_e[g] = e < nk ? (k == 1 ? merge_level(codes[e - 1], codes[e]) : slvl[e]) : LVL_NONE;
+    for (uint32_t x = 1; x < (uint32_t)NLVL; ++x) {
+        const uint64_t b = __ballot(lvl >= x);
+        if (lane == 0) s_mask[g][x][w] = b;
     }
     __syncthreads();
-    for (int j = tid; j < mlen; j += PRE_THREADS)
-        if (s_lvl[j] < NLVL) atomicOr(&s_mask, 1ull << s_lvl[j]);
-    __syncthreads();
-    uint64_t mask = s_mask;
-    const uint32_t lvl_e = s_lvl_e;
-    while (mask) {
-        const uint32_t x = (uint32_t)(__ffsll((long long)mask) - 1);
-        mask &= mask - 1;
-        for (int j = tid; j < mlen; j += PRE_THREADS) {
-            if (s_lvl[j] != x) continue;
-            const int l = s_left[j], r = s_right[j];
-            const bool local = (l >= 0) && (r < mlen || lvl_e > x);
-            if (local) {
-                s_state[j] = 1;
-                s_l[j] = (int16_t)l;
-                s_r[j] = (int16_t)r;
-                atomicAdd(&s_lcnt[x], 1u);
+
+    const uint32_t lvl_e = s_lvl_e[g];
+    bool is_local = false, is_open = false;
+    int left = -1, right = mlen;
+    uint32_t cls = CROSS;
+    if (j < mlen) {
+        if (lvl >= 1 && lvl < (uint32_t)NLVL) {
+            const uint64_t below = lanemask_lt();
+            const uint64_t above = ~below & ~(1ull << lane);
+            uint64_t mm = s_mask[g][lvl][w] & below;
+            if (mm) {
+                left = (int)(w * WAVE) + msb64(mm);
             } else {
-                s_state[j] = 2;
+                for (int ww = (int)w - 1; ww >= 0; --ww) {
+                    const uint64_t t = s_mask[g][lvl][ww];
+                    if (t) {
+                        left = ww * WAVE + msb64(t);
+                        break;
+                    }
+                }
             }
-            if (l >= 0) s_right[l] = (int16_t)r;
-            if (r < mlen) s_left[r] = (int16_t)l;
+            mm = s_mask[g][lvl][w] & above;
+            if (mm) {
+                right = (int)(w * WAVE) + (__ffsll((long long)mm) - 1);
+            } else {
+                for (int ww = (int)w + 1; ww < NCHUNK; ++ww) {
+                    const uint64_t t = s_mask[g][lvl][ww];
+                    if (t) {
+                        right = ww * WAVE + (__ffsll((long long)t) - 1);
+                        break;
+                    }
+                }
+            }
+            is_local = left >= 0 && (right < mlen || lvl_e > lvl);
+            is_open = !is_local;
+            if (is_local && left / WAVE == (int)w && (right - 1) / WAVE == (int)w) cls = w;
+        } else {
+            is_open = true;  // entry 0 of the sequence never merges as a right sibling
         }
-        __syncthreads();
     }
-    for (int j = tid; j < mlen; j += PRE_THREADS)
-        if (s_state[j] == 0) s_state[j] = 2;  // entry 0 of the sequence: never merged here
-    if (tid == 0) {
-        uint32_t run = 0;
-        for (int x = 0; x < NLVL; ++x) {
-            s_lstart[x] = (uint16_t)run;
-            run += s_lcnt[x];
-        }
-        s_lstart[NLVL] = (uint16_t)run;
-        s_lstart[NLVL + 1] = (uint16_t)run;
+    if (is_local) atomicAdd(&s_cnt[g][lvl * NCLS + cls], 1u);
+    __syncthreads();
+    {   // segment starts of each tile: exclusive scan of its SEG_N counts (two per thread)
+        const uint32_t i0 = 2 * j, i1 = 2 * j + 1;
+        const uint32_t a0 = i0 < (uint32_t)SEG_N ? s_cnt[g][i0] : 0u;
+        const uint32_t a1 = i1 < (uint32_t)SEG_N ? s_cnt[g][i1] : 0u;
+        const uint32_t ex = group_excl_scan<PRE_BLOCK, PRE_THREADS>(a0 + a1, s_tmp, nullptr);
+        if (i0 < (uint32_t)SEG_N) s_cnt[g][i0] = ex;
+        if (i1 < (uint32_t)SEG_N) s_cnt[g][i1] = ex + a0;
     }
     __syncthreads();
-    for (int j = tid; j < mlen; j += PRE_THREADS) {
-        if (s_state[j] != 1) continue;
-        const uint32_t x = s_lvl[j];
-        const uint32_t slot = s_lstart[x] + atomicAdd(&s_lfill[x], 1u);
+    const bool tile_live = s < nk;
+    if (is_local) {
+        const uint32_t seg = lvl * NCLS + cls;
+        const uint32_t slot = s_cnt[g][seg] + atomicAdd(&s_fill[g][seg], 1u);
         if (slot < (uint32_t)RT)
-            lv.rec[(size_t)tile * RT + slot] =
-            (uint32_t)j | ((uint32_t)s_l[j] << 10) | ((uint32_t)s_r[j] << 20);
+            gp(lv.rec)[(size_t)tile * RT + slot] =
+                (uint32_t)j | ((uint32_t)left << 10) | ((uint32_t)right << 20);
     }
-    for (int x = tid; x < LSTART_N; x += PRE_THREADS) lv.lstart[(size_t)tile * LSTART_N + x] = s_lstart[x];
+    if (tile_live)
+        for (uint32_t x = j; x < (uint32_t)LSTART_N; x += PRE_THREADS)
+            gp(lv.lstart)[(size_t)tile * LSTART_N + x] = x < (uint32_t)SEG_N ? (uint16_t)s_cnt[g][x] : 0;
 
-    // open entries, in order: thread t owns entries 2t and 2t+1
-    constexpr int EPT = RT / PRE_THREADS;
-    uint32_t my = 0;
-#pragma unroll
-    for (int i = 0; i < EPT; ++i) {
-        const int j = tid * EPT + i;
-        if (j < mlen && s_state[j] == 2) ++my;
-    }
+    // open entries, in order: ranks within the block, then one look-back per block
     uint32_t total;
-    uint32_t rank = block_excl_scan<PRE_THREADS>(my, s_tmp, &total);
-    if (tid == 0) {
-        if (total > open_max((int)fd.J)) set_error(ctrl, GSC_ERR_INTERNAL);
-        s_base = (uint32_t)lookback<OpSum>(lv.status, 1, tile, total, ctrl);
+    const uint32_t rank = block_excl_scan<PRE_BLOCK>(is_open ? 1u : 0u, s_tmp, &total);
+    if (j == 0) s_tile_excl[g] = rank;
+    __syncthreads();
+    if (j == PRE_THREADS - 1) s_tile_cnt[g] = rank + (is_open ? 1u : 0u) - s_tile_excl[g];
+    if (tid < WAVE) {
+        const uint32_t b = (uint32_t)lookback_wave<OpSum>(lv.status, 1, blk, total, ctrl);
+        if (tid == 0) s_base = b;
     }
     __syncthreads();
     const uint32_t base = s_base;
-    const bool has_next = (uint32_t)k < fd.K;
-#pragma unroll
-    for (int i = 0; i < EPT; ++i) {
-        const int j = tid * EPT + i;
-        if (j < mlen && s_state[j] == 2) {
-            if (rank < (uint32_t)OPEN_CAP) lv.opos[(size_t)tile * OPEN_CAP + rank] = (uint16_t)j;
-            if (has_next) {
-                const RahtLevel &nx = fd.lv[k + 1];
-                const uint32_t o = base + rank;
-                if (o < nx.cap) {
-                    nx.s_idx[o] = k == 1 ? s + j : lv.s_idx[s + j];
-                    nx.s_lvl[o] = s_lvl[j];
-                }
+    const uint32_t trank = rank - s_tile_excl[g];
+    if (is_open) {
+        if (trank < (uint32_t)OPEN_CAP) gp(lv.opos)[(size_t)tile * OPEN_CAP + trank] = (uint16_t)j;
+        if ((uint32_t)k < fd.K) {
+            const RahtLevel &nx = fd.lv[k + 1];
+            const uint32_t o = base + rank;
+            if (o < nx.cap) {
+                gp(nx.s_idx)[o] = k == 1 ? s + j : gp(lv.s_idx)[s + j];
+                gp(nx.s_lvl)[o] = (uint8_t)lvl;
             }
-            ++rank;
         }
     }
-    if (tid == 0) {
-        lv.obase[tile] = base;
-        lv.ocnt[tile] = min(total, (uint32_t)OPEN_CAP);
+    if (j == 0 && tile_live) {
+        const uint32_t tc = s_tile_cnt[g];
+        if (tc > open_max((int)fd.J)) set_error(ctrl, GSC_ERR_INTERNAL);
+        lv.obase[tile] = base + s_tile_excl[g];
+        lv.ocnt[tile] = min(tc, (uint32_t)OPEN_CAP);
         if (e == nk) ctrl->lvl_n[k + 1] = base + total;
     }
 }
 
 hipError_t launch_prelude(const TileMap &m, int k, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_prelude, dim3(m.start[m.F]), dim3(PRE_THREADS), 0, s, m, k);
+    hipLaunchKernelGGL(k_prelude, dim3(m.start[m.F]), dim3(PRE_BLOCK), 0, s, m, k);
     return hipGetLastError();
 }
+uint32_t prelude_blocks(uint32_t tiles) { return ceil_div(tiles, PRE_TILES); }
 
 // =========================================================== shared transform pieces
 struct TileSched {
@@ -214,16 +234,18 @@ __device__ inline bool load_schedule(const FrameDesc &fd, Ctrl *ctrl, int k, uin
     ts.final_level = nk <= (uint32_t)RT;
     ts.obase = lv.obase[tile];
     ts.ocnt = lv.ocnt[tile];
-    for (uint32_t x = tid; x < LSTART_N; x += NT) s_lst[x] = lv.lstart[(size_t)tile * LSTART_N + x];
-    for (uint32_t o = tid; o < ts.ocnt; o += NT) s_opos[o] = lv.opos[(size_t)tile * OPEN_CAP + o];
+    const GAS uint16_t *lstart = gp(lv.lstart), *opos = gp(lv.opos);
+    const GAS uint32_t *sidx = gp(lv.s_idx), *recs = gp(lv.rec);
+    for (uint32_t x = tid; x < (uint32_t)LSTART_N; x += NT) s_lst[x] = lstart[(size_t)tile * LSTART_N + x];
+    for (uint32_t o = tid; o < ts.ocnt; o += NT) s_opos[o] = opos[(size_t)tile * OPEN_CAP + o];
     if (k >= 2) {
-        for (int j = tid; j < ts.mlen; j += NT) s_idx[j] = lv.s_idx[s + j];
-        if (tid == 0) s_idx[ts.mlen] = ts.e < nk ? lv.s_idx[ts.e] : ctrl->n_vox;
+        for (int j = tid; j < ts.mlen; j += NT) s_idx[j] = sidx[s + j];
+        if (tid == 0) s_idx[ts.mlen] = ts.e < nk ? sidx[ts.e] : ctrl->n_vox;
     }
     __syncthreads();
-    ts.nrec = s_lst[NLVL];
+    ts.nrec = s_lst[SEG_N - 1];
     for (uint32_t q = tid; q < ts.nrec; q += NT) {
-        const uint32_t rec = lv.rec[(size_t)tile * RT + q];
+        const uint32_t rec = recs[(size_t)tile * RT + q];
         s_rec[q] = rec;
         const uint32_t j = rec & 1023u, l = (rec >> 10) & 1023u, r = rec >> 20;
         uint32_t ij, il, ir;
@@ -248,38 +270,103 @@ __device__ inline uint32_t entry_index(int k, const uint32_t *s_idx, uint32_t s,
     return k == 1 ? s + (uint32_t)j : s_idx[j];
 }
 
-__device__ inline void butterfly_level(float4 *s_y, uint32_t C4, const uint32_t *s_rec,
-                                       const float2 *s_ab, uint32_t q0, uint32_t q1, bool inverse)
+// One butterfly on channels [4*c4, 4*c4+4) of merge record `rec`.
+__device__ inline void butterfly(float4 *s_y, uint32_t C4, uint32_t rec, float2 ab, uint32_t c4,
+                                 bool inverse)
 {
-    const uint32_t n = (q1 - q0) * C4;
-    for (uint32_t t = threadIdx.x; t < n; t += blockDim.x) {
-        const uint32_t q = q0 + t / C4, c4 = t % C4;
-        const uint32_t rec = s_rec[q];
-        const uint32_t j = rec & 1023u, l = (rec >> 10) & 1023u;
-        const float2 ab = s_ab[q];
-        const float4 y0 = s_y[l * C4 + c4], y1 = s_y[j * C4 + c4];
-        float4 lo, hi;
-        if (!inverse) {
-            lo.x = ab.x * y0.x + ab.y * y1.x;
-            lo.y = ab.x * y0.y + ab.y * y1.y;
-            lo.z = ab.x * y0.z + ab.y * y1.z;
-            lo.w = ab.x * y0.w + ab.y * y1.w;
-            hi.x = -ab.y * y0.x + ab.x * y1.x;
-            hi.y = -ab.y * y0.y + ab.x * y1.y;
-            hi.z = -ab.y * y0.z + ab.x * y1.z;
-            hi.w = -ab.y * y0.w + ab.x * y1.w;
-        } else {
-            lo.x = ab.x * y0.x - ab.y * y1.x;
-            lo.y = ab.x * y0.y - ab.y * y1.y;
-            lo.z = ab.x * y0.z - ab.y * y1.z;
-            lo.w = ab.x * y0.w - ab.y * y1.w;
-            hi.x = ab.y * y0.x + ab.x * y1.x;
-            hi.y = ab.y * y0.y + ab.x * y1.y;
-            hi.z = ab.y * y0.z + ab.x * y1.z;
-            hi.w = ab.y * y0.w + ab.x * y1.w;
-        }
-        s_y[l * C4 + c4] = lo;
-        s_y[j * C4 + c4] = hi;
+    const uint32_t j = rec & 1023u, l = (rec >> 10) & 1023u;
+    const float4 y0 = s_y[l * C4 + c4], y1 = s_y[j * C4 + c4];
+    float4 lo, hi;
+    if (!inverse) {
+        lo.x = ab.x * y0.x + ab.y * y1.x;
+        lo.y = ab.x * y0.y + ab.y * y1.y;
+        lo.z = ab.x * y0.z + ab.y * y1.z;
+        lo.w = ab.x * y0.w + ab.y * y1.w;
+        hi.x = -ab.y * y0.x + ab.x * y1.x;
+        hi.y = -ab.y * y0.y + ab.x * y1.y;
+        hi.z = -ab.y * y0.z + ab.x * y1.z;
+        hi.w = -ab.y * y0.w + ab.x * y1.w;
+    } else {
+        lo.x = ab.x * y0.x - ab.y * y1.x;
+        lo.y = ab.x * y0.y - ab.y * y1.y;
+        lo.z = ab.x * y0.z - ab.y * y1.z;
+        lo.w = ab.x * y0.w - ab.y * y1.w;
+        hi.x = ab.y * y0.x + ab.x * y1.x;
+        hi.y = ab.y * y0.y + ab.x * y1.y;
+        hi.z = ab.y * y0.z + ab.x * y1.z;
+        hi.w = ab.y * y0.w + ab.x * y1.w;
+    }
+    s_y[l * C4 + c4] = lo;
+    s_y[j * C4 + c4] = hi;
+}
+
+// Per-thread roles: in a workgroup step, thread t handles channel chunk t % C4 of row t / C4
+// (RPB rows per step); in a wave step, lane L handles chunk L % C4 of merge L / C4 (MPW
+// merges per step). C4 <= 16, so RPB >= 16 and MPW >= 4.
+struct Roles {
+    uint32_t C4, RPB, row0, c4, MPW, wq, wc4, w;
+    bool act, wact;
+    __device__ explicit Roles(uint32_t C4_) : C4(C4_)
+    {
+        const uint32_t tid = threadIdx.x, lane = lane_id();
+        RPB = RAHT_THREADS / C4;
+        row0 = tid / C4;
+        c4 = tid % C4;
+        act = row0 < RPB;
+        MPW = WAVE / C4;
+        wq = lane / C4;
+        wc4 = lane % C4;
+        wact = wq < MPW;
+        w = tid / WAVE;
+    }
+};
+
+// Non-empty (level, class) segments of the tile as one 64-bit level mask per class, so that the
+// merge phases visit only the levels that hold merges.
+__device__ inline void level_masks(const uint16_t *s_lst, unsigned long long *s_lmask)
+{
+    const uint32_t tid = threadIdx.x;
+    if (tid < (uint32_t)NCLS) s_lmask[tid] = 0;
+    __syncthreads();
+    for (uint32_t i = tid; i < (uint32_t)(NLVL * NCLS); i += blockDim.x)
+        if (s_lst[i] != s_lst[i + 1]) atomicOr(&s_lmask[i % NCLS], 1ull << (i / NCLS));
+    __syncthreads();
+}
+
+// Merges local to this wave's chunk, levels ascending (forward) or descending (inverse). The
+// wave's own LDS accesses are performed in program order; the fence keeps the compiler from
+// moving one level's accesses across the next level's. Only channel chunks below nch are live.
+__device__ inline void wave_phase(float4 *s_y, const Roles &R, const uint32_t *s_rec,
+                                  const float2 *s_ab, const uint16_t *s_lst, uint64_t mask,
+                                  uint32_t nch, bool inverse)
+{
+    const bool live = R.wact && R.wc4 < nch;
+    while (mask) {
+        const uint32_t x = inverse ? (uint32_t)msb64(mask) : (uint32_t)(__ffsll((long long)mask) - 1);
+        mask &= ~(1ull << x);
+        const uint32_t q0 = s_lst[x * NCLS + R.w], q1 = s_lst[x * NCLS + R.w + 1];
+        if (live)
+            for (uint32_t q = q0 + R.wq; q < q1; q += R.MPW)
+                butterfly(s_y, R.C4, s_rec[q], s_ab[q], R.wc4, inverse);
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
+// Merges crossing chunks, level by level with workgroup barriers.
+__device__ inline void block_phase(float4 *s_y, const Roles &R, const uint32_t *s_rec,
+                                   const float2 *s_ab, const uint16_t *s_lst, uint64_t mask,
+                                   uint32_t nch, bool inverse)
+{
+    const bool live = R.act && R.c4 < nch;
+    while (mask) {
+        const uint32_t x = inverse ? (uint32_t)msb64(mask) : (uint32_t)(__ffsll((long long)mask) - 1);
+        mask &= ~(1ull << x);
+        const uint32_t q0 = s_lst[x * NCLS + CROSS], q1 = s_lst[x * NCLS + CROSS + 1];
+        if (live)
+            for (uint32_t q = q0 + R.row0; q < q1; q += R.RPB)
+                butterfly(s_y, R.C4, s_rec[q], s_ab[q], R.c4, inverse);
+        __syncthreads();
     }
 }
 
@@ -288,26 +375,46 @@ __device__ inline float get4(const float4 &v, int i)
     return i == 0 ? v.x : (i == 1 ? v.y : (i == 2 ? v.z : v.w));
 }
 
-// Loads channels [4*c4, 4*c4+4) of row `row` of a row-major float matrix with C columns.
-__device__ inline float4 load_row4(const float *base, uint64_t row, uint32_t C, uint32_t c4,
-                                   bool vec)
+// Channels [4*c4, 4*c4+4) of row `row` of a row-major matrix with C columns. VEC: C % 4 == 0
+// and 16-byte aligned base, one 16-byte access; otherwise element accesses guarded by C.
+template <bool VEC>
+__device__ inline float4 ld4(const GAS float *base, uint64_t row, uint32_t C, uint32_t c4)
 {
-    const float *p = base + row * C + 4 * c4;
-    if (vec) return *reinterpret_cast<const float4 *>(p);
-    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+    const GAS float *p = base + row * C + 4 * c4;
+    if (VEC) return gload4(p);
     const uint32_t c = 4 * c4;
-    if (c + 0 < C) v.x = p[0];
-    if (c + 1 < C) v.y = p[1];
-    if (c + 2 < C) v.z = p[2];
-    if (c + 3 < C) v.w = p[3];
-    return v;
+    return make_float4(c + 0 < C ? p[0] : 0.f, c + 1 < C ? p[1] : 0.f, c + 2 < C ? p[2] : 0.f,
+                       c + 3 < C ? p[3] : 0.f);
 }
-__device__ inline void store_row4(float *base, uint64_t row, uint32_t C, uint32_t c4,
-                                  const float4 &v, bool vec)
+template <bool VEC>
+__device__ inline int4 ldq4(const GAS int32_t *base, uint64_t row, uint32_t C, uint32_t c4)
 {
-    float *p = base + row * C + 4 * c4;
-    if (vec) {
-        *reinterpret_cast<float4 *>(p) = v;
+    const GAS int32_t *p = base + row * C + 4 * c4;
+    if (VEC) return gload4i(p);
+    const uint32_t c = 4 * c4;
+    return make_int4(c + 0 < C ? p[0] : 0, c + 1 < C ? p[1] : 0, c + 2 < C ? p[2] : 0,
+                     c + 3 < C ? p[3] : 0);
+}
+template <bool VEC>
+__device__ inline void st4(GAS float *base, uint64_t row, uint32_t C, uint32_t c4, const float4 &v)
+{
+    GAS float *p = base + row * C + 4 * c4;
+    if (VEC) {
+        gstore4(p, v);
+        return;
+    }
+    const uint32_t c = 4 * c4;
+    if (c + 0 < C) p[0] = v.x;
+    if (c + 1 < C) p[1] = v.y;
+    if (c + 2 < C) p[2] = v.z;
+    if (c + 3 < C) p[3] = v.w;
+}
+template <bool VEC>
+__device__ inline void stq4(GAS int32_t *base, uint64_t row, uint32_t C, uint32_t c4, const int4 &v)
+{
+    GAS int32_t *p = base + row * C + 4 * c4;
+    if (VEC) {
+        gstore4i(p, v);
         return;
     }
     const uint32_t c = 4 * c4;
@@ -317,9 +424,50 @@ __device__ inline void store_row4(float *base, uint64_t row, uint32_t C, uint32_
     if (c + 3 < C) p[3] = v.w;
 }
 
-__device__ inline bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
+// q = sgn(y) floor(|y|/step + tau) with the exact decision of `quantize` (gsc_device.h);
+// POW2: every step is a power of two, so the quotient is an exact float multiply.
+template <bool POW2>
+__device__ inline int32_t quant1(float y, float step, float inv_step, double omt)
+{
+    return quantize(y, step, inv_step, omt, POW2);
+}
+
+constexpr int UNROLL = 8;  // independent row loads in flight per thread
+
+// The channels are transformed in passes of at most CH4_MAX float4 chunks (32 channels), so a
+// tile's slice in LDS stays at 32 KB and several workgroups share a CU.
+constexpr uint32_t CH4_MAX = 8;
+__host__ __device__ inline uint32_t channel_passes(uint32_t C4) { return (C4 + CH4_MAX - 1) / CH4_MAX; }
+__host__ __device__ inline uint32_t pass_chunks(uint32_t C4)
+{
+    const uint32_t np = channel_passes(C4);
+    return (C4 + np - 1) / np;
+}
+
+// Loads rows j = row0, row0 + RPB, ... (< mlen) of one channel chunk into the LDS slice. The
+// UNROLL loads of a batch are issued back to back: a row past the end re-reads the last valid
+// row and is discarded.
+template <class RowLoad>
+__device__ inline void load_slice(float4 *s_y, const Roles &R, uint32_t CH4, uint32_t mlen,
+                                  RowLoad rowload)
+{
+    for (uint32_t jb = R.row0; jb < mlen; jb += UNROLL * R.RPB) {
+        float4 v[UNROLL];
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u) {
+            const uint32_t j = min(jb + u * R.RPB, mlen - 1);
+            v[u] = rowload(j);
+        }
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u) {
+            const uint32_t j = jb + u * R.RPB;
+            if (j < mlen) s_y[j * CH4 + R.c4] = v[u];
+        }
+    }
+}
 
 // ==================================================================== forward transform
+template <bool VEC, bool POW2>
 __global__ __launch_bounds__(RAHT_THREADS) void k_raht_fwd(TileMap m, int k)
 {
     extern __shared__ float4 s_y[];
@@ -330,6 +478,7 @@ __global__ __launch_bounds__(RAHT_THREADS) void k_raht_fwd(TileMap m, int k)
     __shared__ uint32_t s_idx[RT + 1];
     __shared__ uint32_t s_m0[RT + 1];
     __shared__ uint32_t s_first[RT];
+    __shared__ unsigned long long s_lmask[NCLS];
 
     const uint32_t f = frame_of(m, blockIdx.x);
     const FrameDesc &fd = *m.fd[f];
@@ -339,39 +488,53 @@ __global__ __launch_bounds__(RAHT_THREADS) void k_raht_fwd(TileMap m, int k)
     TileSched ts;
     if (!load_schedule(fd, ctrl, k, blockIdx.x - m.start[f], ts, s_rec, s_ab, s_lst, s_opos, s_idx))
         return;
-    const uint32_t C = fd.C, C4 = fd.C4, J = fd.J;
+    const uint32_t C = fd.C, C4 = fd.C4;
     const uint32_t tid = threadIdx.x;
-    const uint32_t nvals = (uint32_t)ts.mlen * C4;
+    const uint32_t NP = channel_passes(C4), CH4 = pass_chunks(C4);
+    const Roles R(CH4);
+    const uint32_t mlen = (uint32_t)ts.mlen;
+    const bool encode1 = (k == 1 && fd.mode == MODE_ENCODE);
+    const GAS uint32_t *perm = gp((fd.P & 1) ? fd.vals_b : fd.vals_a);
+    const GAS float *attr = gp(fd.attr);
+    if (encode1) {
+        // the run starts and the first member's row, staged so that row loads are independent
+        const GAS uint32_t *vh = gp(fd.vh);
+        for (uint32_t j = tid; j <= mlen; j += RAHT_THREADS) s_m0[j] = vh[ts.s + j];
+        __syncthreads();
+        for (uint32_t j = tid; j < mlen; j += RAHT_THREADS) s_first[j] = perm[s_m0[j]];
+    }
+    level_masks(s_lst, s_lmask);
+    const uint64_t wmask = s_lmask[R.w], xmask = s_lmask[CROSS];
+    GAS int32_t *coef = nullptr;
+    if (fd.mode == MODE_ENCODE) {
+        uint64_t off = GSC_HEADER_BYTES, run = 0;
+        for (uint32_t d = 0; d < fd.J; ++d) {
+            run += ctrl->hist_D[d];
+            off += run;
+        }
+        coef = gp(reinterpret_cast<int32_t *>(fd.stream + align_up(off, 256)));
+    }
+    const GAS float *vsrc = k >= 2 ? gp(fd.lv[k - 1].vbuf) : nullptr;
+    GAS float *coef_f32 = gp(fd.coef_f32);
 
-    // ---- load the entries' values
-    if (k == 1 && fd.mode == MODE_ENCODE) {
-        // merge duplicates: the mean of the rows of the Gaussians in the voxel (Sec. 2.1),
-        // summed in input order (the sort is stable). The run starts and the first member's
-        // row are staged in LDS so that the row loads below are independent of each other.
-        const uint32_t *perm = (fd.P & 1) ? fd.vals_b : fd.vals_a;
-        for (int j = tid; j <= ts.mlen; j += RAHT_THREADS) s_m0[j] = fd.vh[ts.s + j];
-        __syncthreads();
-        for (int j = tid; j < ts.mlen; j += RAHT_THREADS) s_first[j] = perm[s_m0[j]];
-        __syncthreads();
-        const bool vec = (C % 4 == 0) && aligned16(fd.attr);
-        constexpr int U = 4;
-        for (uint32_t t0 = tid; t0 < nvals; t0 += U * RAHT_THREADS) {
-            float4 v[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const uint32_t t = t0 + u * RAHT_THREADS;
-                if (t < nvals) v[u] = load_row4(fd.attr, s_first[t / C4], C, t % C4, vec);
-            }
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const uint32_t t = t0 + u * RAHT_THREADS;
-                if (t >= nvals) break;
-                const uint32_t j = t / C4, c4 = t % C4;
-                const uint32_t m0 = s_m0[j], m1 = s_m0[j + 1];
-                float4 acc = v[u];
-                if (m1 - m0 > 1) {
+    for (uint32_t p = 0; p < NP; ++p) {
+        const uint32_t cb = p * CH4;
+        const uint32_t nch = min(CH4, C4 - cb);
+        const uint32_t c4 = cb + R.c4;  // this thread's global channel chunk
+        const bool live = R.act && R.c4 < nch;
+        if (p > 0) __syncthreads();  // the previous pass has finished reading the slice
+        // ---- load the entries' values of this channel slice
+        if (live) {
+            if (encode1) {
+                load_slice(s_y, R, CH4, mlen, [&](uint32_t j) { return ld4<VEC>(attr, s_first[j], C, c4); });
+                // merge duplicates: the mean of the rows of the Gaussians in the voxel
+                // (Sec. 2.1), summed in input order (the sort is stable)
+                for (uint32_t j = R.row0; j < mlen; j += R.RPB) {
+                    const uint32_t m0 = s_m0[j], m1 = s_m0[j + 1];
+                    if (m1 - m0 <= 1) continue;
+                    float4 acc = s_y[j * CH4 + R.c4];
                     for (uint32_t mm = m0 + 1; mm < m1; ++mm) {
-                        const float4 x = load_row4(fd.attr, perm[mm], C, c4, vec);
+                        const float4 x = ld4<VEC>(attr, perm[mm], C, c4);
                         acc.x += x.x;
                         acc.y += x.y;
                         acc.z += x.z;
@@ -382,88 +545,54 @@ __global__ __launch_bounds__(RAHT_THREADS) void k_raht_fwd(TileMap m, int k)
                     acc.y /= cnt;
                     acc.z /= cnt;
                     acc.w /= cnt;
+                    s_y[j * CH4 + R.c4] = acc;
                 }
-                s_y[j * C4 + c4] = acc;
+            } else if (k == 1) {
+                load_slice(s_y, R, CH4, mlen, [&](uint32_t j) { return ld4<VEC>(attr, ts.s + j, C, c4); });
+            } else {
+                load_slice(s_y, R, CH4, mlen, [&](uint32_t j) { return gload4(vsrc + ((size_t)(ts.s + j) * C4 + c4) * 4); });
             }
         }
-    } else if (k == 1) {
-        const bool vec = (C % 4 == 0) && aligned16(fd.attr);
-        for (uint32_t t = tid; t < nvals; t += RAHT_THREADS) {
-            const uint32_t j = t / C4, c4 = t % C4;
-            s_y[j * C4 + c4] = load_row4(fd.attr, ts.s + j, C, c4, vec);
-        }
-    } else {
-        const float4 *src = reinterpret_cast<const float4 *>(fd.lv[k - 1].vbuf);
-        for (uint32_t t = tid; t < nvals; t += RAHT_THREADS) {
-            const uint32_t j = t / C4, c4 = t % C4;
-            s_y[j * C4 + c4] = src[(size_t)(ts.s + j) * C4 + c4];
-        }
-    }
-    __syncthreads();
-
-    // ---- all local merges, level by level (bottom-up)
-    for (uint32_t x = 1; x <= 3 * J; ++x) {
-        const uint32_t q0 = s_lst[x], q1 = s_lst[x + 1];
-        if (q0 == q1) continue;
-        butterfly_level(s_y, C4, s_rec, s_ab, q0, q1, false);
         __syncthreads();
-    }
-
-    // ---- outputs: coefficient rows of every entry (an open entry's row is rewritten by the
-    // level that completes its merge), open entries' partial low-passes to S_{k+1}
-    if (fd.mode == MODE_ENCODE) {
-        int32_t *coef = reinterpret_cast<int32_t *>(fd.stream + (size_t)0);
-        // coefficient offset from the level sizes (same formula as the header)
-        uint64_t off = GSC_HEADER_BYTES, run = 0;
-        for (uint32_t d = 0; d < J; ++d) {
-            run += ctrl->hist_D[d];
-            off += run;
-        }
-        coef = reinterpret_cast<int32_t *>(fd.stream + align_up(off, 256));
-        const double omt = 1.0 - (double)fd.tau;
-        const bool vec = (C % 4 == 0);
-        float *cf = fd.coef_f32;
-        const bool vecf = vec && cf && aligned16(cf);
-        for (uint32_t t = tid; t < nvals; t += RAHT_THREADS) {
-            const uint32_t j = t / C4, c4 = t % C4;
-            const float4 y = s_y[j * C4 + c4];
-            const uint64_t row = entry_index(k, s_idx, ts.s, (int)j);
-            int32_t q[4];
+        // ---- all local merges: within wave chunks, then across chunks (levels ascending)
+        wave_phase(s_y, R, s_rec, s_ab, s_lst, wmask, nch, false);
+        __syncthreads();
+        block_phase(s_y, R, s_rec, s_ab, s_lst, xmask, nch, false);
+        // ---- outputs: coefficient rows of every entry (an open entry's row is rewritten by the
+        // level that completes its merge), open entries' partial low-passes to S_{k+1}
+        if (!live) continue;
+        if (fd.mode == MODE_ENCODE) {
+            const double omt = 1.0 - (double)fd.tau;
+            GAS float *cf = coef_f32;
+            float st[4], ist[4];
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                const uint32_t c = 4 * c4 + i;
-                q[i] = c < C ? quantize(get4(y, i), fd.step[c], fd.inv_step[c], omt,
-                                        (fd.pow2_steps >> c) & 1ull)
-                             : 0;
+                const uint32_t c = min(4 * c4 + i, C - 1);
+                st[i] = fd.step[c];
+                ist[i] = fd.inv_step[c];
             }
-            int32_t *p = coef + row * C + 4 * c4;
-            if (vec) {
-                *reinterpret_cast<int4 *>(p) = make_int4(q[0], q[1], q[2], q[3]);
-            } else {
-                for (int i = 0; i < 4; ++i)
-                    if (4 * c4 + i < C) p[i] = q[i];
+            for (uint32_t j = R.row0; j < mlen; j += R.RPB) {
+                const float4 y = s_y[j * CH4 + R.c4];
+                const uint64_t row = entry_index(k, s_idx, ts.s, (int)j);
+                const int4 q = make_int4(quant1<POW2>(y.x, st[0], ist[0], omt), quant1<POW2>(y.y, st[1], ist[1], omt),
+                                         quant1<POW2>(y.z, st[2], ist[2], omt), quant1<POW2>(y.w, st[3], ist[3], omt));
+                stq4<VEC>(coef, row, C, c4, q);
+                if (cf) st4<VEC>(cf, row, C, c4, y);
             }
-            if (cf) store_row4(cf, row, C, c4, y, vecf);
+        } else {  // MODE_FWD_F32: float coefficient rows
+            for (uint32_t j = R.row0; j < mlen; j += R.RPB)
+                st4<VEC>(coef_f32, entry_index(k, s_idx, ts.s, (int)j), C, c4, s_y[j * CH4 + R.c4]);
         }
-    } else {  // MODE_FWD_F32: float coefficient rows
-        float *cf = fd.coef_f32;
-        const bool vecf = (C % 4 == 0) && aligned16(cf);
-        for (uint32_t t = tid; t < nvals; t += RAHT_THREADS) {
-            const uint32_t j = t / C4, c4 = t % C4;
-            store_row4(cf, entry_index(k, s_idx, ts.s, (int)j), C, c4, s_y[j * C4 + c4], vecf);
-        }
-    }
-    if (!ts.final_level) {
-        float4 *dst = reinterpret_cast<float4 *>(fd.lv[k].vbuf);
-        const uint32_t n = ts.ocnt * C4;
-        for (uint32_t t = tid; t < n; t += RAHT_THREADS) {
-            const uint32_t o = t / C4, c4 = t % C4;
-            dst[(size_t)(ts.obase + o) * C4 + c4] = s_y[s_opos[o] * C4 + c4];
+        if (!ts.final_level) {
+            GAS float *dst = gp(fd.lv[k].vbuf);
+            for (uint32_t o = R.row0; o < ts.ocnt; o += R.RPB)
+                gstore4(dst + ((size_t)(ts.obase + o) * C4 + c4) * 4, s_y[s_opos[o] * CH4 + R.c4]);
         }
     }
 }
 
 // ==================================================================== inverse transform
+template <bool VEC>
 __global__ __launch_bounds__(RAHT_THREADS) void k_raht_inv(TileMap m, int k)
 {
     extern __shared__ float4 s_y[];
@@ -472,6 +601,7 @@ __global__ __launch_bounds__(RAHT_THREADS) void k_raht_inv(TileMap m, int k)
     __shared__ uint16_t s_lst[LSTART_N];
     __shared__ uint16_t s_opos[OPEN_CAP];
     __shared__ uint32_t s_idx[RT + 1];
+    __shared__ unsigned long long s_lmask[NCLS];
 
     const uint32_t f = frame_of(m, blockIdx.x);
     const FrameDesc &fd = *m.fd[f];
@@ -481,118 +611,87 @@ __global__ __launch_bounds__(RAHT_THREADS) void k_raht_inv(TileMap m, int k)
     TileSched ts;
     if (!load_schedule(fd, ctrl, k, blockIdx.x - m.start[f], ts, s_rec, s_ab, s_lst, s_opos, s_idx))
         return;
-    const uint32_t C = fd.C, C4 = fd.C4, J = fd.J;
-    const uint32_t tid = threadIdx.x;
-    const uint32_t nvals = (uint32_t)ts.mlen * C4;
+    const uint32_t C = fd.C, C4 = fd.C4;
+    const uint32_t NP = channel_passes(C4), CH4 = pass_chunks(C4);
+    const Roles R(CH4);
+    const uint32_t mlen = (uint32_t)ts.mlen;
+    level_masks(s_lst, s_lmask);
+    const uint64_t wmask = s_lmask[R.w], xmask = s_lmask[CROSS];
+    const gsc_header *h = reinterpret_cast<const gsc_header *>(fd.in_stream);
+    const GAS int32_t *coef = fd.mode == MODE_DECODE
+                                  ? gp(reinterpret_cast<const int32_t *>(fd.in_stream + h->coef_offset))
+                                  : nullptr;
+    const GAS float *attr = gp(fd.attr);
 
-    // ---- coefficients of every entry (the high-pass stored at it, or the DC at entry 0)
-    if (fd.mode == MODE_DECODE) {
-        const gsc_header *h = reinterpret_cast<const gsc_header *>(fd.in_stream);
-        const int32_t *coef = reinterpret_cast<const int32_t *>(fd.in_stream + h->coef_offset);
-        const bool vec = (C % 4 == 0);
-        constexpr int U = 4;
-        for (uint32_t t0 = tid; t0 < nvals; t0 += U * RAHT_THREADS) {
-            int4 qv[U];
+    for (uint32_t p = 0; p < NP; ++p) {
+        const uint32_t cb = p * CH4;
+        const uint32_t nch = min(CH4, C4 - cb);
+        const uint32_t c4 = cb + R.c4;
+        const bool live = R.act && R.c4 < nch;
+        if (p > 0) __syncthreads();
+        // ---- coefficients of every entry (the high-pass stored at it, or the DC at entry 0)
+        if (live) {
+            if (fd.mode == MODE_DECODE) {
+                float st[4];
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const uint32_t t = t0 + u * RAHT_THREADS;
-                if (t >= nvals) break;
-                const uint32_t j = t / C4, c4 = t % C4;
-                const uint64_t row = entry_index(k, s_idx, ts.s, (int)j);
-                const int32_t *p = coef + row * C + 4 * c4;
-                int4 q = make_int4(0, 0, 0, 0);
-                if (vec) {
-                    q = *reinterpret_cast<const int4 *>(p);
-                } else {
-                    const uint32_t c = 4 * c4;
-                    if (c + 0 < C) q.x = p[0];
-                    if (c + 1 < C) q.y = p[1];
-                    if (c + 2 < C) q.z = p[2];
-                    if (c + 3 < C) q.w = p[3];
-                }
-                qv[u] = q;
-            }
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const uint32_t t = t0 + u * RAHT_THREADS;
-                if (t >= nvals) break;
-                const uint32_t j = t / C4, c4 = t % C4;
-                const uint32_t c = 4 * c4;
-                float4 y;
-                y.x = (float)qv[u].x * (c + 0 < C ? h->quant_step[c + 0] : 0.f);
-                y.y = (float)qv[u].y * (c + 1 < C ? h->quant_step[c + 1] : 0.f);
-                y.z = (float)qv[u].z * (c + 2 < C ? h->quant_step[c + 2] : 0.f);
-                y.w = (float)qv[u].w * (c + 3 < C ? h->quant_step[c + 3] : 0.f);
-                s_y[j * C4 + c4] = y;
+                for (int i = 0; i < 4; ++i) st[i] = 4 * c4 + i < C ? h->quant_step[4 * c4 + i] : 0.0f;
+                load_slice(s_y, R, CH4, mlen, [&](uint32_t j) {
+                    const int4 q = ldq4<VEC>(coef, entry_index(k, s_idx, ts.s, (int)j), C, c4);
+                    return make_float4((float)q.x * st[0], (float)q.y * st[1], (float)q.z * st[2],
+                                       (float)q.w * st[3]);
+                });
+            } else {  // MODE_ADJ_F32: float coefficient rows
+                load_slice(s_y, R, CH4, mlen, [&](uint32_t j) {
+                    return ld4<VEC>(attr, entry_index(k, s_idx, ts.s, (int)j), C, c4);
+                });
             }
         }
-    } else {  // MODE_ADJ_F32: float coefficient rows
-        const bool vec = (C % 4 == 0) && aligned16(fd.attr);
-        for (uint32_t t = tid; t < nvals; t += RAHT_THREADS) {
-            const uint32_t j = t / C4, c4 = t % C4;
-            s_y[j * C4 + c4] = load_row4(fd.attr, entry_index(k, s_idx, ts.s, (int)j), C, c4, vec);
-        }
-    }
-    __syncthreads();
-    // ---- open entries take the low-pass handed down by the next sequence
-    if (!ts.final_level) {
-        const float4 *src = reinterpret_cast<const float4 *>(fd.lv[k].vbuf);
-        const uint32_t n = ts.ocnt * C4;
-        for (uint32_t t = tid; t < n; t += RAHT_THREADS) {
-            const uint32_t o = t / C4, c4 = t % C4;
-            s_y[s_opos[o] * C4 + c4] = src[(size_t)(ts.obase + o) * C4 + c4];
-        }
         __syncthreads();
-    }
-    // ---- all local merges undone, level by level (top-down)
-    for (uint32_t x = 3 * J; x >= 1; --x) {
-        const uint32_t q0 = s_lst[x], q1 = s_lst[x + 1];
-        if (q0 == q1) continue;
-        butterfly_level(s_y, C4, s_rec, s_ab, q0, q1, true);
-        __syncthreads();
-    }
-    // ---- outputs
-    if (k >= 2) {
-        float4 *dst = reinterpret_cast<float4 *>(fd.lv[k - 1].vbuf);
-        for (uint32_t t = tid; t < nvals; t += RAHT_THREADS) {
-            const uint32_t j = t / C4, c4 = t % C4;
-            dst[(size_t)(ts.s + j) * C4 + c4] = s_y[j * C4 + c4];
+        // ---- open entries take the low-pass handed down by the next sequence
+        if (!ts.final_level) {
+            if (live) {
+                const GAS float *src = gp(fd.lv[k].vbuf);
+                for (uint32_t o = R.row0; o < ts.ocnt; o += R.RPB)
+                    s_y[s_opos[o] * CH4 + R.c4] = gload4(src + ((size_t)(ts.obase + o) * C4 + c4) * 4);
+            }
+            __syncthreads();
         }
-    } else {
-        float *out = fd.mode == MODE_DECODE ? fd.attr_out : fd.coef_f32;
-        const bool vec = (C % 4 == 0) && aligned16(out);
-        for (uint32_t t = tid; t < nvals; t += RAHT_THREADS) {
-            const uint32_t j = t / C4, c4 = t % C4;
-            store_row4(out, ts.s + j, C, c4, s_y[j * C4 + c4], vec);
+        // ---- all local merges undone: across chunks, then within chunks (levels descending)
+        block_phase(s_y, R, s_rec, s_ab, s_lst, xmask, nch, true);
+        wave_phase(s_y, R, s_rec, s_ab, s_lst, wmask, nch, true);
+        __syncthreads();
+        // ---- outputs
+        if (!live) continue;
+        if (k >= 2) {
+            GAS float *dst = gp(fd.lv[k - 1].vbuf);
+            for (uint32_t j = R.row0; j < mlen; j += R.RPB)
+                gstore4(dst + ((size_t)(ts.s + j) * C4 + c4) * 4, s_y[j * CH4 + R.c4]);
+        } else {
+            GAS float *out = gp(fd.mode == MODE_DECODE ? fd.attr_out : fd.coef_f32);
+            for (uint32_t j = R.row0; j < mlen; j += R.RPB) st4<VEC>(out, ts.s + j, C, c4, s_y[j * CH4 + R.c4]);
         }
     }
 }
 
-size_t raht_lds_bytes(int C4) { return (size_t)RT * C4 * sizeof(float4); }
+size_t raht_lds_bytes(int C4) { return (size_t)RT * pass_chunks((uint32_t)C4) * sizeof(float4); }
 
-hipError_t launch_raht_fwd(const TileMap &m, int k, int C4, hipStream_t s)
+hipError_t launch_raht_fwd(const TileMap &m, int k, const RahtCfg &cfg, hipStream_t s)
 {
-    const size_t lds = raht_lds_bytes(C4);
-    static bool attr_set = false;
-    if (!attr_set) {
-        (void)hipFuncSetAttribute((const void *)k_raht_fwd, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)raht_lds_bytes(GSC_MAX_CHANNELS / 4));
-        attr_set = true;
-    }
-    hipLaunchKernelGGL(k_raht_fwd, dim3(m.start[m.F]), dim3(RAHT_THREADS), lds, s, m, k);
+    const dim3 grid(m.start[m.F]), block(RAHT_THREADS);
+    const size_t lds = raht_lds_bytes(cfg.C4);
+    if (cfg.vec && cfg.pow2) hipLaunchKernelGGL((k_raht_fwd<true, true>), grid, block, lds, s, m, k);
+    else if (cfg.vec) hipLaunchKernelGGL((k_raht_fwd<true, false>), grid, block, lds, s, m, k);
+    else if (cfg.pow2) hipLaunchKernelGGL((k_raht_fwd<false, true>), grid, block, lds, s, m, k);
+    else hipLaunchKernelGGL((k_raht_fwd<false, false>), grid, block, lds, s, m, k);
     return hipGetLastError();
 }
 
-hipError_t launch_raht_inv(const TileMap &m, int k, int C4, hipStream_t s)
+hipError_t launch_raht_inv(const TileMap &m, int k, const RahtCfg &cfg, hipStream_t s)
 {
-    const size_t lds = raht_lds_bytes(C4);
-    static bool attr_set = false;
-    if (!attr_set) {
-        (void)hipFuncSetAttribute((const void *)k_raht_inv, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)raht_lds_bytes(GSC_MAX_CHANNELS / 4));
-        attr_set = true;
-    }
-    hipLaunchKernelGGL(k_raht_inv, dim3(m.start[m.F]), dim3(RAHT_THREADS), lds, s, m, k);
+    const dim3 grid(m.start[m.F]), block(RAHT_THREADS);
+    const size_t lds = raht_lds_bytes(cfg.C4);
+    if (cfg.vec) hipLaunchKernelGGL((k_raht_inv<true>), grid, block, lds, s, m, k);
+    else hipLaunchKernelGGL((k_raht_inv<false>), grid, block, lds, s, m, k);
     return hipGetLastError();
 }
 
