@@ -9,6 +9,14 @@ inputs resident in HBM. The default workload is the 1M-Gaussian frame at octree 
 Prints one JSON line: whole-job throughput in M Gaussians/s (encode + decode), the roofline
 figure of the dominant kernel (timed live with HIP events on the library's stream), and the
 FP64 CPU oracle timed on the host on the same workload.
+
+Other workloads (--workload):
+  frame100k_J10, frame4M_J14   single frames as above (4M adds per-phase GB/s; --errors adds
+                               the FP32-versus-FP64 coefficient error per channel group)
+  seq30_J12                    the 30-frame sequence: per-frame launches, one batch, the batch
+                               as a replayed HIP graph, and the graph with autotuned sort tiles
+  diff500k_J11                 the straight-through differentiable coder: forward + rate-
+                               distortion loss + backward, next to a plain encode + decode
 """
 from __future__ import annotations
 
@@ -24,12 +32,18 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+METRIC = "M Gaussians/s encode+decode (and frames/s at 1M), % HBM roofline vs CPU oracle"
+STAGES = {"encode": 0, "decode": 1, "sort": 2, "occupancy": 3, "prelude": 4, "raht_fwd1": 5,
+          "raht_fwd_top": 6, "raht_inv1": 7, "raht_inv_top": 8, "octree_dec": 9}
 
-# Algorithmic bytes per voxel of the two level-1 RAHT kernels (C = 56 channels, float32/int32):
-#   forward : read the attribute rows (4C) + the sort permutation (4) + the voxel run start (4)
-#             + one merge record (4); write the quantized coefficient row (4C)   = 8C + 12
-#   inverse : read the coefficient row (4C) + one merge record (4); write the attribute row (4C)
-#             = 8C + 4
+
+# Algorithmic bytes (each input read once, each output written once; float32/int32 rows of C
+# channels), per launch:
+#   raht_fwd1 : attribute rows of the n Gaussians (4C) + the sort permutation (4) for each
+#               Gaussian; per voxel its run start (4), one merge record (4) and the quantized
+#               coefficient row written (4C)
+#   raht_inv1 : per voxel the coefficient row (4C) + one merge record (4) read, the attribute
+#               row written (4C)
 def alg_bytes(stage, n, nv, C):
     if stage == "raht_fwd1":
         return n * (4 * C + 4) + nv * (4 + 4 + 4 * C)
@@ -38,42 +52,62 @@ def alg_bytes(stage, n, nv, C):
     raise KeyError(stage)
 
 
-STAGES = {"encode": 0, "decode": 1, "sort": 2, "occupancy": 3, "prelude": 4, "raht_fwd1": 5,
-          "raht_fwd_top": 6, "raht_inv1": 7, "raht_inv_top": 8, "octree_dec": 9}
+def phase_bytes(n, nv, J, occ_bytes):
+    """Algorithmic bytes of the sort stage (bounding box, voxelize, radix sort passes, unique)
+    and of the occupancy stage."""
+    P = (3 * J + 7) // 8
+    sort = 12 * n + (12 * n + 8 * n) + (P * 24 * n - 4 * n) + (8 * n + 12 * nv)
+    occ = 8 * nv + occ_bytes
+    return sort, occ
 
 
-def cpu_baseline(pos, attr, J, steps, reps):
-    from oracle import oracle as orc
+class StageTimer:
+    """HIP event pairs recorded by the library around each stage, one pair per step."""
+
+    def __init__(self, gsc, torch, K, names=STAGES):
+        self.gsc, self.K, self.events = gsc, K, {}
+        for name in names:
+            evs = [torch.cuda.Event(enable_timing=True) for _ in range(2 * K)]
+            for e in evs:  # torch creates the HIP event on first record
+                e.record()
+            arr = (ctypes.c_void_p * (2 * K))(*[e.cuda_event for e in evs])
+            gsc.lib().gsc_profile_events(STAGES[name], arr, K)
+            self.events[name] = (evs, arr)
+
+    def stop(self):
+        import numpy as np
+        for name in self.events:
+            self.gsc.lib().gsc_profile_events(STAGES[name], None, 0)
+        out = {}
+        for name, (evs, _) in self.events.items():
+            out[name] = float(np.mean([evs[2 * i].elapsed_time(evs[2 * i + 1])
+                                       for i in range(self.K)]))
+        return out
+
+
+def timed(fn, K, torch):
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(reps):
-        ref = orc.encode_frame(pos, attr, J, steps, 0.5)
-        orc.decode_frame(ref["occ"], ref["level_sizes"], J, ref["Q"], steps, ref["bbox_min"],
-                         ref["cell"])
-    dt = time.perf_counter() - t0
-    return pos.shape[0] * reps / dt / 1e6, dt
+    for _ in range(K):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / K
 
 
-def main():
-    ap = argparse.ArgumentParser(description=__doc__)
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="frame1M_J12")
-    ap.add_argument("--cpu-reps", type=int, default=2)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print("bench.py measures one GPU: this codec shards by frame (see the design notes), and "
-              "this build runs on a single MI355X, so --gpus must be 1.", file=sys.stderr)
-        sys.exit(2)
+def base_record(args, value, ms, config, dtype="f32"):
+    return {"metric": METRIC, "value": round(value, 3), "unit": "M Gaussians/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": dtype,
+            "data": "synthetic", "config": config}
 
+
+# ------------------------------------------------------------------------ single frame
+def frame_bench(args):
     import numpy as np
     import torch
     from paper_2606_05650_amd import gsc, synth
 
     n, J, table = synth.WORKLOADS[args.workload]
-    if n is None:
-        raise SystemExit("the sequence workload is benchmarked by the batch test, not here")
     steps_q = synth.quant_steps(table)
     pos, attr = synth.make_frame(n, seed=2)
     C = attr.shape[1]
@@ -94,63 +128,250 @@ def main():
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    gsc.Encoded(sbuf, info_e, J, C).check()
+    enc = gsc.Encoded(sbuf, info_e, J, C).check()
     gsc.Decoded(pos_out, attr_out, None, None, info_d).check()
-    nv = int(info_e[1].item())
+    nv = enc.n_vox()
+    occ_bytes = int(gsc.parse_header(sbuf[:gsc.HEADER_BYTES].cpu().numpy())["occ_bytes"])
 
-    # live stage timing: HIP event pairs recorded by the library around each stage, one pair
-    # per step, on the stream the kernels run on
     K = args.steps
-    events = {}
-    for name, sid in STAGES.items():
-        evs = [torch.cuda.Event(enable_timing=True) for _ in range(2 * K)]
-        for e in evs:  # torch creates the HIP event on first record
-            e.record()
-        arr = (ctypes.c_void_p * (2 * K))(*[e.cuda_event for e in evs])
-        gsc.lib().gsc_profile_events(sid, arr, K)
-        events[name] = (evs, arr)
+    timer = StageTimer(gsc, torch, K)
+    dt = timed(step, K, torch)
+    stage_ms = timer.stop()
 
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(K):
-        step()
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    for sid in STAGES.values():
-        gsc.lib().gsc_profile_events(sid, None, 0)
-    stage_ms = {}
-    for name, (evs, _) in events.items():
-        ts = [evs[2 * i].elapsed_time(evs[2 * i + 1]) for i in range(K)]
-        stage_ms[name] = float(np.mean(ts))
-
-    ms = dt / K * 1e3
-    value = n / (dt / K) / 1e6
-    cands = {s: alg_bytes(s, n, nv, C) / (stage_ms[s] * 1e-3) / 1e9 for s in ("raht_fwd1", "raht_inv1")}
+    ms = dt * 1e3
+    value = n / dt / 1e6
     dom = max(("raht_fwd1", "raht_inv1"), key=lambda s: stage_ms[s])
-    achieved = cands[dom]
+    achieved = alg_bytes(dom, n, nv, C) / (stage_ms[dom] * 1e-3) / 1e9
     roof = {"bound": "hbm", "kernel": {"raht_fwd1": "k_raht_fwd (level 1)",
                                         "raht_inv1": "k_raht_inv (level 1)"}[dom],
             "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
             "alg_bytes_per_launch": alg_bytes(dom, n, nv, C),
             "avg_launch_ms": round(stage_ms[dom], 4)}
-
-    out = {"metric": "M Gaussians/s encode+decode (and frames/s at 1M), % HBM roofline vs CPU oracle",
-           "value": round(value, 3), "unit": "M Gaussians/s", "n_gpus": 1, "steps": K,
-           "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True,
-           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-           "config": {"workload": args.workload, "gaussians": n, "voxels": nv, "depth": J,
-                      "channels": C, "parallelism": "single GPU"},
-           "frames_per_s": round(1e3 / ms, 2),
-           "stage_ms": {k: round(v, 4) for k, v in stage_ms.items()},
-           "roofline": roof}
+    cfg = {"workload": args.workload, "gaussians": n, "voxels": nv, "depth": J, "channels": C,
+           "parallelism": "single GPU"}
+    out = base_record(args, value, ms, cfg)
+    out["frames_per_s"] = round(1e3 / ms, 2)
+    out["stage_ms"] = {k: round(v, 4) for k, v in stage_ms.items()}
+    out["roofline"] = roof
+    sort_b, occ_b = phase_bytes(n, nv, J, occ_bytes)
+    raht_b = alg_bytes("raht_fwd1", n, nv, C) + alg_bytes("raht_inv1", n, nv, C)
+    raht_ms = sum(stage_ms[s] for s in ("raht_fwd1", "raht_fwd_top", "raht_inv1", "raht_inv_top"))
+    out["phase_gbs"] = {"sort": round(sort_b / stage_ms["sort"] / 1e6, 1),
+                        "occupancy": round(occ_b / stage_ms["occupancy"] / 1e6, 1),
+                        "raht": round(raht_b / raht_ms / 1e6, 1)}
+    if args.errors:
+        out["coef_error"] = coefficient_errors(tp, ta, pos, attr, p, J, steps_q, nv)
     if not args.no_cpu_baseline:
-        v, t = cpu_baseline(pos, attr, J, steps_q, args.cpu_reps)
-        out["cpu_baseline"] = {"value": round(v, 4), "unit": "M Gaussians/s", "cores": 1,
-                               "kind": "oracle",
+        from oracle import oracle as orc
+        t0 = time.perf_counter()
+        for _ in range(args.cpu_reps):
+            ref = orc.encode_frame(pos, attr, J, steps_q, 0.5)
+            orc.decode_frame(ref["occ"], ref["level_sizes"], J, ref["Q"], steps_q,
+                             ref["bbox_min"], ref["cell"])
+        t = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": round(n * args.cpu_reps / t / 1e6, 4),
+                               "unit": "M Gaussians/s", "cores": 1, "kind": "oracle",
                                "sample": f"{args.cpu_reps} encode+decode of the same {n}-Gaussian "
                                          f"frame ({t:.1f} s, single-threaded FP64 C)"}
     print(json.dumps(out))
+
+
+def coefficient_errors(tp, ta, pos, attr, p, J, steps_q, nv):
+    """Max over the channels of a group of max_i |y32 - y64| / max_i |y64| (and in steps)."""
+    import numpy as np
+    import torch
+    from oracle import oracle as orc
+    from paper_2606_05650_amd import gsc, synth
+    C = attr.shape[1]
+    coef = torch.empty((tp.shape[0], C), dtype=torch.float32, device=tp.device)
+    gsc.encode_frame(tp, ta, p, coef_f32=coef).check()
+    y32 = coef[:nv].cpu().numpy().astype(np.float64)
+    y64 = orc.encode_frame(pos, attr, J, steps_q, 0.5, want_y=True)["Y"]
+    err = np.abs(y32 - y64).max(axis=0)
+    rel = err / np.maximum(np.abs(y64).max(axis=0), 1e-300)
+    out = {}
+    for name, sl in synth.channel_group_slices().items():
+        out[name] = {"max_rel": float(rel[sl].max()),
+                     "max_abs_in_steps": float((err[sl] / steps_q[sl]).max())}
+    return out
+
+
+# ---------------------------------------------------------------------------- sequence
+def seq_bench(args):
+    import numpy as np
+    import torch
+    from paper_2606_05650_amd import gsc, synth
+
+    _, J, table = synth.WORKLOADS["seq30_J12"]
+    steps_q = synth.quant_steps(table)
+    dev = torch.device("cuda:0")
+    frames = []
+    for t, (pos, attr) in enumerate(synth.make_sequence()):
+        if t == 0:
+            pos0, attr0 = pos, attr   # the CPU baseline's sample
+        frames.append((torch.from_numpy(pos).to(dev), torch.from_numpy(attr).to(dev)))
+    F = len(frames)
+    C = frames[0][1].shape[1]
+    ns = [int(f[0].shape[0]) for f in frames]
+    ntot = sum(ns)
+    p = gsc.make_params(J, C, steps_q, bbox=(np.zeros(3), 1.0 / (1 << J)))
+    wse = [gsc.Workspace(n, J, C, dev) for n in ns]
+    wsd = [gsc.Workspace(n, J, C, dev) for n in ns]
+    sb = [torch.empty(gsc.stream_capacity(n, J, C), dtype=torch.uint8, device=dev) for n in ns]
+    ie = [torch.zeros(gsc.INFO_WORDS, dtype=torch.int32, device=dev) for _ in ns]
+    idd = [torch.zeros(gsc.INFO_WORDS, dtype=torch.int32, device=dev) for _ in ns]
+    po = [torch.empty((n, 3), dtype=torch.float32, device=dev) for n in ns]
+    ao = [torch.empty((n, C), dtype=torch.float32, device=dev) for n in ns]
+
+    def per_frame():
+        for f in range(F):
+            gsc.encode_frame(frames[f][0], frames[f][1], p, ws=wse[f], stream_buf=sb[f],
+                             info=ie[f])
+            gsc.decode_frame(sb[f], J, C, ns[f], ws=wsd[f], pos_out=po[f], attr_out=ao[f],
+                             info=idd[f])
+
+    def batch():
+        outs = gsc.encode_batch(frames, p, workspaces=wse)
+        gsc.decode_batch(outs, ns, workspaces=wsd)
+
+    def capture():
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            batch()
+        torch.cuda.current_stream().wait_stream(s)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            outs = gsc.encode_batch(frames, p, workspaces=wse)
+            decs = gsc.decode_batch(outs, ns, workspaces=wsd)
+        return g, outs, decs
+
+    K, W = args.steps, args.warmup
+    res = {}
+    for name, fn in (("per_frame", per_frame), ("batch", batch)):
+        for _ in range(W):
+            fn()
+        res[name] = timed(fn, K, torch)
+    for f in range(F):
+        gsc.Encoded(sb[f], ie[f], J, C).check()
+    g, outs, decs = capture()
+    for _ in range(W):
+        g.replay()
+    res["graph"] = timed(g.replay, K, torch)
+    ref_bytes = [o.check().to_bytes() for o in outs[:2]]
+    chosen, vt, _ = gsc.autotune(frames, p, reps=2, workspaces=wse)
+    g2, outs2, decs2 = capture()
+    for _ in range(W):
+        g2.replay()
+    res["graph_autotuned"] = timed(g2.replay, K, torch)
+    torch.cuda.synchronize()
+    same = all(o.check().to_bytes() == b for o, b in zip(outs2[:2], ref_bytes))
+    for d in decs2:
+        d.check()
+    dt = res["graph_autotuned"]
+    cfg = {"workload": "seq30_J12", "frames": F, "gaussians": ntot, "depth": J, "channels": C,
+           "parallelism": "single GPU"}
+    out = base_record(args, ntot / dt / 1e6, dt * 1e3, cfg)
+    out["frames_per_s"] = round(F / dt, 2)
+    out["modes_ms_per_sequence"] = {k: round(v * 1e3, 3) for k, v in res.items()}
+    out["modes_m_gaussians_per_s"] = {k: round(ntot / v / 1e6, 2) for k, v in res.items()}
+    out["autotune"] = {"chosen_variant": chosen, "encode_ms_per_variant": [round(t, 3) for t in vt],
+                       "streams_identical": same}
+    if not args.no_cpu_baseline:
+        from oracle import oracle as orc
+        t0 = time.perf_counter()
+        ref = orc.encode_frame(pos0, attr0, J, steps_q, 0.5, bbox=(np.zeros(3), 1.0 / (1 << J)))
+        orc.decode_frame(ref["occ"], ref["level_sizes"], J, ref["Q"], steps_q, ref["bbox_min"],
+                         ref["cell"])
+        t = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": round(pos0.shape[0] / t / 1e6, 4), "unit": "M Gaussians/s",
+                               "cores": 1, "kind": "oracle",
+                               "sample": f"encode+decode of frame 0 ({pos0.shape[0]} Gaussians, "
+                                         f"{t:.1f} s, single-threaded FP64 C)"}
+    print(json.dumps(out))
+
+
+# ------------------------------------------------------------------- differentiable coder
+def ste_bench(args):
+    import torch
+    from paper_2606_05650_amd import gsc, synth
+    from paper_2606_05650_amd.ste import SteCoder, rd_loss
+
+    n, J, table = synth.WORKLOADS["diff500k_J11"]
+    lam = 0.01
+    steps_q = synth.quant_steps(table)
+    pos, attr = synth.make_frame(n, seed=4)
+    C = attr.shape[1]
+    dev = torch.device("cuda:0")
+    tp = torch.from_numpy(pos).to(dev)
+    ta = torch.from_numpy(attr).to(dev).requires_grad_(True)
+    steps_t = torch.from_numpy(steps_q).to(dev)
+    p = gsc.make_params(J, C, steps_q)
+
+    def ste_step():
+        ta.grad = None
+        yhat, ahat, aref = SteCoder.apply(ta, tp, p)
+        loss, _, _ = rd_loss(yhat, ahat, aref, steps_t, lam)
+        loss.backward()
+
+    ws = gsc.Workspace(n, J, C, dev)
+    sbuf = torch.empty(gsc.stream_capacity(n, J, C), dtype=torch.uint8, device=dev)
+    pos_out = torch.empty((n, 3), dtype=torch.float32, device=dev)
+    attr_out = torch.empty((n, C), dtype=torch.float32, device=dev)
+    tad = ta.detach()
+
+    def plain():
+        gsc.encode_frame(tp, tad, p, ws=ws, stream_buf=sbuf)
+        gsc.decode_frame(sbuf, J, C, n, ws=ws, pos_out=pos_out, attr_out=attr_out)
+
+    K, W = args.steps, args.warmup
+    for _ in range(W):
+        ste_step()
+        plain()
+    t_ste = timed(ste_step, K, torch)
+    t_plain = timed(plain, K, torch)
+    cfg = {"workload": "diff500k_J11", "gaussians": n, "depth": J, "channels": C,
+           "lambda": lam, "parallelism": "single GPU"}
+    out = base_record(args, n / t_ste / 1e6, t_ste * 1e3, cfg)
+    out["step"] = "straight-through forward + rate-distortion loss + backward to the attributes"
+    out["plain_encode_decode_ms"] = round(t_plain * 1e3, 4)
+    out["plain_m_gaussians_per_s"] = round(n / t_plain / 1e6, 2)
+    if not args.no_cpu_baseline:
+        from oracle import oracle as orc
+        t0 = time.perf_counter()
+        orc.ste_grad(pos, attr, J, steps_q, 0.5, lam)
+        t = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": round(n / t / 1e6, 4), "unit": "M Gaussians/s",
+                               "cores": 1, "kind": "oracle",
+                               "sample": f"one loss + gradient of the {n}-Gaussian frame "
+                                         f"({t:.1f} s, single-threaded FP64 C)"}
+    print(json.dumps(out))
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__,
+                                 formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="frame1M_J12")
+    ap.add_argument("--cpu-reps", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--errors", action="store_true",
+                    help="single frames: FP32-versus-FP64 coefficient error per channel group")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this codec shards by frame (see the design notes), and "
+              "this build runs on a single MI355X, so --gpus must be 1.", file=sys.stderr)
+        sys.exit(2)
+    if args.workload == "seq30_J12":
+        seq_bench(args)
+    elif args.workload == "diff500k_J11":
+        ste_bench(args)
+    else:
+        frame_bench(args)
 
 
 if __name__ == "__main__":

@@ -177,11 +177,37 @@ gsc_status gsc_decode_batch(const gsc_stream_desc *streams, int32_t F, int32_t J
                             void *stream);
 
 /* ------------------------------------------------------------------------------------------
+ * Autotuning of the sort tiling (the Morton-code sort of Sec. 2.2 / Alg. 1 step 1).
+ *
+ * The radix sort of an encode call runs one of GSC_SORT_VARIANTS tilings (keys per workgroup
+ * and look-back window width). Which one is fastest depends on the frame size: few large tiles
+ * shorten the chain of tiles whose prefixes must be resolved, many small tiles fill more
+ * compute units. The choice is kept in a process-wide table keyed by the depth J and the size
+ * class ceil(log2(n_max)) of the largest frame of a call; untuned entries use the default.
+ * All variants produce identical streams.
+ *
+ * gsc_autotune -- times every variant on the caller's batch (each timed as reps encodes of the
+ *   whole batch after one warm-up, exactly as gsc_encode_batch runs it, on `stream`), stores
+ *   the fastest in the table for this batch's key and returns it in *chosen (optional);
+ *   times_ms (optional, GSC_SORT_VARIANTS floats) receives the mean time of each. Arguments
+ *   and buffers as for gsc_encode_batch; the frames are encoded (the outputs of the last run
+ *   remain). SYNCHRONOUS: it waits for the stream, so it must not be called while the stream
+ *   is being captured into a graph. Allocates no device memory.
+ * gsc_tune_set -- sets the entry for (J, size class of n) to `variant`, or clears it with -1.
+ * gsc_tune_get -- the variant an encode call whose largest frame has n entries would use.
+ * ---------------------------------------------------------------------------------------- */
+#define GSC_SORT_VARIANTS 4
+gsc_status gsc_autotune(const gsc_frame_desc *frames, int32_t F, const gsc_params *params,
+                        int32_t reps, int32_t *chosen, float *times_ms, void *stream);
+gsc_status gsc_tune_set(int32_t J, int64_t n, int32_t variant);
+gsc_status gsc_tune_get(int32_t J, int64_t n, int32_t *variant);
+
+/* ------------------------------------------------------------------------------------------
  * gsc_raht_forward / gsc_raht_adjoint -- the orthonormal transform alone, on float
  * attributes of voxels already in Morton order (Eq. 1 and Alg. 4-6 on all 3J levels):
  *   Y = T A (forward) and A = T^T Y (adjoint, which is the inverse since T is orthonormal).
  *   d_codes [nv] sorted distinct Morton codes; d_in, d_out [nv][C] float (may not alias).
- * Used by the straight-through differentiable coder: its backward pass is the adjoint.
+ * The adjoint is the backward pass of the forward transform as a differentiable operation.
  * ---------------------------------------------------------------------------------------- */
 gsc_status gsc_raht_forward(const uint64_t *d_codes, int64_t nv, int32_t J, int32_t C,
                             const float *d_in, float *d_out, void *d_ws, size_t ws_bytes,
@@ -189,6 +215,40 @@ gsc_status gsc_raht_forward(const uint64_t *d_codes, int64_t nv, int32_t J, int3
 gsc_status gsc_raht_adjoint(const uint64_t *d_codes, int64_t nv, int32_t J, int32_t C,
                             const float *d_in, float *d_out, void *d_ws, size_t ws_bytes,
                             int32_t *d_info, void *stream);
+
+/* ------------------------------------------------------------------------------------------
+ * Straight-through (STE) attribute coding: the codec as a differentiable layer. The paper's
+ * coder (Sec. 3: RAHT of Eq. 1 / Alg. 6 and the uniform quantizer of Sec. 3.4) has a
+ * piecewise-constant quantizer; the straight-through form passes gradients through it as if it
+ * were the identity, so a rate-distortion loss of the decoded attributes can be backpropagated
+ * to the Gaussian attributes.
+ *
+ * gsc_ste_forward -- gsc_encode_frame (same arguments, same stream written) plus, for the Nv
+ *   occupied voxels in Morton order:
+ *     d_aref [n][C] (optional)   a = voxel means of the input rows (the rows RAHT transforms)
+ *     d_yhat [n][C]              yhat = q * step (the dequantized coefficients, Alg. 6 layout:
+ *                                row 0 the DC, row i > 0 the high-pass stored at voxel i)
+ *     d_ahat [n][C]              ahat = T^T yhat (the attributes the decoder reconstructs)
+ *   Rows Nv..n-1 are not written; Nv is d_info[1] after the call completes. d_yhat, d_ahat and
+ *   d_attr must not alias. The workspace afterwards holds the transform schedule that
+ *   gsc_ste_backward uses.
+ *
+ * gsc_ste_backward -- given dL/dyhat and dL/dahat ([Nv][C] float rows each, both required;
+ *   pass zeros for a term the loss does not use), writes dL/dattr [n][C] for every input row:
+ *     g_vox = dL/dahat + T^T dL/dyhat,  dL/dattr[i] = g_vox[voxel of i] / (Gaussians in it).
+ *   This is T^T (T dL/dahat + dL/dyhat) with T^T T = I (T is orthonormal), the straight-through
+ *   gradient (dyhat/dy taken as the identity) chained through the voxel mean. d_ws must be the
+ *   workspace of a gsc_ste_forward call with the same n, J and C, not used by any other call
+ *   since; otherwise d_info[0] reports GSC_ERR_INVALID_ARG. It may be called several times
+ *   for the same forward. d_grad_attr must not alias the gradient inputs.
+ * ---------------------------------------------------------------------------------------- */
+gsc_status gsc_ste_forward(const float *d_pos, const float *d_attr, int64_t n,
+                           const gsc_params *params, void *d_stream, size_t stream_cap, void *d_ws,
+                           size_t ws_bytes, int32_t *d_info, float *d_yhat, float *d_ahat,
+                           float *d_aref, uint64_t *d_leaf_codes, void *stream);
+gsc_status gsc_ste_backward(int64_t n, int32_t J, int32_t C, const float *d_grad_yhat,
+                            const float *d_grad_ahat, float *d_grad_attr, void *d_ws,
+                            size_t ws_bytes, int32_t *d_info, void *stream);
 
 /* ------------------------------------------------------------------------------------------
  * Diagnostics: gsc_profile_events -- record caller-created HIP events around one stage of every

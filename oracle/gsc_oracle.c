@@ -19,6 +19,9 @@
  *       context: the root keeps the low-pass; Alg. 4 builds 3J levels).
  *   R6  quantization q = sgn(y) * floor(|y| / step + tau), reconstruction q * step (Sec. 3.4).
  *   R7  the voxel-depth shift of Alg. 2 is zero (voxel depth equals octree depth).
+ *   R8  (differentiable extension, not in the paper) the straight-through loss measures the
+ *       decoded voxel rows against the voxel means over Nv*C values, the rate proxy sums
+ *       log2(1 + |yhat|/step) over every coefficient, DC included, and sgn(0) = 0.
  *
  * Every function returns a negative value on a bad argument or a capacity overflow.
  */
@@ -542,4 +545,86 @@ int64_t orc_decode_frame(const uint8_t *occ, int64_t occ_bytes, const int64_t *l
     int rc = orc_raht_inverse(leaf_out, nv, J, attr_out, C);
     if (rc) return rc;
     return nv;
+}
+
+/* ---------------------------------------------------------------------------------------- */
+/* Straight-through coding loss and its gradient: the coder of Sec. 3 (the transform of       */
+/* Eq. (1) / Alg. 6 and the quantizer of Sec. 3.4) used as a differentiable layer, with the   */
+/* quantizer's derivative taken as the identity (R8):                                          */
+/*   a     = voxel means of the input rows (R3); a_ref = a, held constant                      */
+/*   y     = T a,  yhat = Q(y) * step,  ahat = T^T yhat (the decoder's reconstruction)         */
+/*   L     = 1/(Nv C) sum (ahat - a_ref)^2 + lambda sum log2(1 + |yhat| / step)                */
+/*   g_ahat = 2/(Nv C) (ahat - a_ref),  g_yhat = lambda sgn(yhat) / (ln 2 (step + |yhat|))     */
+/*   g_y = T g_ahat + g_yhat,  g_a = T^T g_y,  dL/dattr[i] = g_a[voxel of i] / |voxel of i|    */
+/* Outputs (capacity n rows): leaf[n], voxel_of[n], aref, yhat, ahat [Nv][C], grad [n][C];    */
+/* loss[0] = L, loss[1] = distortion term, loss[2] = rate term; res[0] = Nv.                  */
+/* Returns 0 or a negative error.                                                             */
+/* ---------------------------------------------------------------------------------------- */
+int orc_ste_grad(const float *pos, const float *attr, int64_t n, int J, int C, const float *step,
+                 double tau, double lambda, int bbox_mode, double *bbox_min, double *cell,
+                 uint64_t *leaf, int64_t *voxel_of, double *aref, double *yhat, double *ahat,
+                 double *grad, double *loss, int64_t *res)
+{
+    if (n < 0 || C < 1) return -1;
+    loss[0] = loss[1] = loss[2] = 0.0;
+    res[0] = 0;
+    if (n == 0) return 0;
+    uint32_t *vox = (uint32_t *)malloc((size_t)n * 3 * sizeof(uint32_t));
+    uint64_t *keys = (uint64_t *)malloc((size_t)n * sizeof(uint64_t));
+    int64_t *count = (int64_t *)calloc((size_t)n, sizeof(int64_t));
+    double *G = (double *)malloc((size_t)n * (size_t)C * sizeof(double));
+    if (!vox || !keys || !count || !G) return -2;
+    int rc = orc_voxelize(pos, n, J, bbox_mode, bbox_min, cell, vox);
+    if (rc) return rc;
+    for (int64_t i = 0; i < n; ++i)
+        keys[i] = orc_morton_encode(vox[i * 3], vox[i * 3 + 1], vox[i * 3 + 2], J);
+    int64_t nv = orc_sort_merge(keys, attr, n, C, leaf, aref, NULL, voxel_of);
+    if (nv < 0) return (int)nv;
+    for (int64_t i = 0; i < n; ++i) count[voxel_of[i]] += 1;
+    const size_t rows = (size_t)nv * (size_t)C;
+
+    /* y = T a, yhat = Q(y) step, ahat = T^T yhat */
+    memcpy(yhat, aref, rows * sizeof(double));
+    if ((rc = orc_raht_forward(leaf, nv, J, yhat, C))) return rc;
+    for (int64_t v = 0; v < nv; ++v)
+        for (int c = 0; c < C; ++c) {
+            const double st = (double)step[c];
+            yhat[v * C + c] = (double)orc_quantize1(yhat[v * C + c], st, tau) * st;
+        }
+    memcpy(ahat, yhat, rows * sizeof(double));
+    if ((rc = orc_raht_inverse(leaf, nv, J, ahat, C))) return rc;
+
+    /* the loss */
+    const double inv_nc = 1.0 / ((double)nv * (double)C);
+    double dist = 0.0, rate = 0.0;
+    for (size_t k = 0; k < rows; ++k) {
+        const double e = ahat[k] - aref[k];
+        dist += e * e;
+        rate += log2(1.0 + fabs(yhat[k]) / (double)step[k % (size_t)C]);
+    }
+    loss[1] = dist * inv_nc;
+    loss[2] = lambda * rate;
+    loss[0] = loss[1] + loss[2];
+
+    /* g_y = T g_ahat + g_yhat, g_a = T^T g_y */
+    for (size_t k = 0; k < rows; ++k) G[k] = 2.0 * inv_nc * (ahat[k] - aref[k]);
+    if ((rc = orc_raht_forward(leaf, nv, J, G, C))) return rc;
+    for (size_t k = 0; k < rows; ++k) {
+        const double yh = yhat[k], st = (double)step[k % (size_t)C];
+        const double sg = yh > 0.0 ? 1.0 : (yh < 0.0 ? -1.0 : 0.0);
+        G[k] += lambda * sg / (log(2.0) * (st + fabs(yh)));
+    }
+    if ((rc = orc_raht_inverse(leaf, nv, J, G, C))) return rc;
+
+    /* back through the voxel mean */
+    for (int64_t i = 0; i < n; ++i) {
+        const int64_t v = voxel_of[i];
+        for (int c = 0; c < C; ++c) grad[i * C + c] = G[v * C + c] / (double)count[v];
+    }
+    res[0] = nv;
+    free(vox);
+    free(keys);
+    free(count);
+    free(G);
+    return 0;
 }

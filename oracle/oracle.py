@@ -73,6 +73,9 @@ def lib():
         L.orc_decode_frame.restype = i64
         L.orc_decode_frame.argtypes = [vp, i64, vp, i32, i32, vp, vp, vp, dbl, i64, vp, vp, vp,
                                        vp]
+        L.orc_ste_grad.restype = i32
+        L.orc_ste_grad.argtypes = [vp, vp, i64, i32, i32, vp, dbl, dbl, i32, vp, vp, vp, vp, vp,
+                                   vp, vp, vp, vp, vp]
         _lib = L
     return _lib
 
@@ -297,3 +300,35 @@ def decode_frame(occ, level_sizes, J, Q, step, bbox_min, cell):
         raise ValueError("corrupt occupancy stream")
     _check(r, "decode_frame")
     return dict(leaf=leaf[:r], vox=vox[:r], pos=pos[:r], attr=attr[:r])
+
+
+def ste_grad(pos, attr, J, step, tau=0.5, lam=0.01, bbox=None):
+    """Straight-through coding loss and its gradient (R8). Returns a dict with nv, leaf,
+    voxel_of, aref, yhat, ahat (Nv x C, FP64), grad (n x C, FP64), loss, dist, rate."""
+    pos = _c(pos, np.float32).reshape(-1, 3)
+    attr = _c(attr, np.float32)
+    n, C = attr.shape
+    step = _c(step, np.float32)
+    m = max(n, 1)
+    leaf = np.zeros(m, dtype=np.uint64)
+    vof = np.zeros(m, dtype=np.int64)
+    aref = np.zeros((m, C), dtype=np.float64)
+    yhat = np.zeros((m, C), dtype=np.float64)
+    ahat = np.zeros((m, C), dtype=np.float64)
+    grad = np.zeros((m, C), dtype=np.float64)
+    loss = np.zeros(3, dtype=np.float64)
+    res = np.zeros(1, dtype=np.int64)
+    bmin = np.zeros(3, dtype=np.float64)
+    cell = np.zeros(1, dtype=np.float64)
+    mode = 0
+    if bbox is not None:
+        mode = 1
+        bmin[:] = bbox[0]
+        cell[0] = bbox[1]
+    _check(lib().orc_ste_grad(_p(pos), _p(attr), n, J, C, _p(step), float(tau), float(lam), mode,
+                              _p(bmin), _p(cell), _p(leaf), _p(vof), _p(aref), _p(yhat),
+                              _p(ahat), _p(grad), _p(loss), _p(res)), "ste_grad")
+    nv = int(res[0])
+    return dict(nv=nv, leaf=leaf[:nv], voxel_of=vof[:n], aref=aref[:nv], yhat=yhat[:nv],
+                ahat=ahat[:nv], grad=grad[:n], loss=float(loss[0]), dist=float(loss[1]),
+                rate=float(loss[2]), bbox_min=bmin, cell=float(cell[0]))

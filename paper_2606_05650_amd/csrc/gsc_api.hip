@@ -3,6 +3,8 @@
 #include <math.h>
 #include <string.h>
 
+#include <atomic>
+
 #include "gsc_internal.h"
 
 namespace gsc {
@@ -73,6 +75,26 @@ struct StageScope {
         if (pair >= 0) (void)hipEventRecord((hipEvent_t)h->events[2 * pair + 1], s);
     }
 };
+
+// ------------------------------------------------------------------ autotuning table
+// The sort tiling of an encode call is looked up by depth and by the size class (ceil(log2))
+// of the largest frame of the call; entries hold variant + 1 (0 = not tuned: the default).
+std::atomic<int> g_tune[GSC_MAX_DEPTH + 1][32];
+thread_local int g_force_variant = -1;  // set while the tuner times a variant
+
+int size_class(uint64_t n)
+{
+    int c = 0;
+    while (c < 31 && (1ull << c) < n) ++c;
+    return c;
+}
+
+int sort_variant_for(int J, uint64_t nmax)
+{
+    if (g_force_variant >= 0) return g_force_variant;
+    const int v = g_tune[J][size_class(nmax)].load(std::memory_order_relaxed);
+    return v > 0 ? v - 1 : SORT_DEFAULT_VARIANT;
+}
 
 // ------------------------------------------------------------------- launch plumbing
 struct Frame {
@@ -232,17 +254,20 @@ RahtCfg raht_cfg(const Frame *fr, int F, int C, const float *steps)
     for (int f = 0; f < F && cfg.vec; ++f) {
         const FrameArgs &a = fr[f].a;
         cfg.vec = aligned16(a.attr) && aligned16(a.stream) && aligned16(a.coef_f32) &&
-                  aligned16(a.in_stream) && aligned16(a.attr_out);
+                  aligned16(a.in_stream) && aligned16(a.attr_out) && aligned16(a.aref) &&
+                  aligned16(a.grad_add);
     }
     cfg.pow2 = steps ? all_pow2(steps, C) : false;
     return cfg;
 }
 
-// Encode F frames (already validated) with one launch per stage.
-gsc_status encode_frames(const Frame *fr, int F, const gsc_params *p, hipStream_t s)
+// Encode F frames (already validated) with one launch per stage. With ste, also synthesize
+// the decoded rows from the dequantized coefficients (straight-through forward).
+gsc_status encode_frames(const Frame *fr, int F, const gsc_params *p, hipStream_t s, bool ste = false)
 {
     StageScope whole(GSC_STAGE_ENCODE, s);
-    const SetupArgs proto = make_proto((uint32_t)p->J, (uint32_t)p->C, MODE_ENCODE, p);
+    SetupArgs proto = make_proto((uint32_t)p->J, (uint32_t)p->C, MODE_ENCODE, p);
+    proto.ste = ste ? STE_FORWARD : STE_NONE;
     gsc_status st = run_setup(fr, F, proto, s);
     if (st != GSC_OK) return st;
     {
@@ -257,9 +282,13 @@ gsc_status encode_frames(const Frame *fr, int F, const gsc_params *p, hipStream_
         }
         const int P = sort_passes(p->J);
         {
-            TileMap m = make_map(fr, F, [](const Frame &x) { return x.a.n ? x.L.sort_tiles : 0u; });
+            uint64_t nmax = 0;
+            for (int f = 0; f < F; ++f) nmax = fr[f].a.n > nmax ? fr[f].a.n : nmax;
+            const int var = sort_variant_for(p->J, nmax);
+            const uint32_t tile = (uint32_t)sort_tile(var);
+            TileMap m = make_map(fr, F, [tile](const Frame &x) { return ceil_div(x.a.n, tile); });
             if (m.start[F] > 0)
-                for (int pass = 0; pass < P; ++pass) GSC_LAUNCH(launch_sort_pass(m, pass, s));
+                for (int pass = 0; pass < P; ++pass) GSC_LAUNCH(launch_sort_pass(m, pass, var, s));
         }
         {
             TileMap m = make_map(fr, F, [](const Frame &x) { return x.a.n ? x.L.dedup_tiles : 0u; });
@@ -274,6 +303,7 @@ gsc_status encode_frames(const Frame *fr, int F, const gsc_params *p, hipStream_
     const RahtCfg cfg = raht_cfg(fr, F, p->C, p->quant_step);
     if ((st = run_prelude(fr, F, s)) != GSC_OK) return st;
     if ((st = run_forward(fr, F, cfg, s)) != GSC_OK) return st;
+    if (ste && (st = run_inverse(fr, F, cfg, s)) != GSC_OK) return st;
     return run_finish(fr, F, s);
 }
 
@@ -363,13 +393,15 @@ gsc_status gsc_stream_capacity(int64_t n_max, int32_t J, int32_t C, size_t *byte
     return GSC_OK;
 }
 
-gsc_status gsc_encode_batch(const gsc_frame_desc *frames, int32_t F, const gsc_params *params,
-                            void *stream)
+}  // extern "C"
+
+namespace {
+gsc_status prepare_encode_batch(const gsc_frame_desc *frames, int32_t F, const gsc_params *params,
+                                Frame *fr)
 {
     if (!frames || F < 1 || F > GSC_MAX_BATCH) return GSC_ERR_INVALID_ARG;
     gsc_status st = check_params(params);
     if (st != GSC_OK) return st;
-    static thread_local Frame fr[GSC_MAX_BATCH];
     for (int f = 0; f < F; ++f) {
         const gsc_frame_desc &d = frames[f];
         if (d.n < 0 || d.n > N_LIMIT) return GSC_ERR_INVALID_ARG;
@@ -388,7 +420,77 @@ gsc_status gsc_encode_batch(const gsc_frame_desc *frames, int32_t F, const gsc_p
         a.ws = static_cast<uint8_t *>(d.d_ws);
         a.info = d.d_info;
     }
+    return GSC_OK;
+}
+}  // namespace
+
+extern "C" {
+
+gsc_status gsc_encode_batch(const gsc_frame_desc *frames, int32_t F, const gsc_params *params,
+                            void *stream)
+{
+    static thread_local Frame fr[GSC_MAX_BATCH];
+    gsc_status st = prepare_encode_batch(frames, F, params, fr);
+    if (st != GSC_OK) return st;
     return encode_frames(fr, F, params, static_cast<hipStream_t>(stream));
+}
+
+gsc_status gsc_autotune(const gsc_frame_desc *frames, int32_t F, const gsc_params *params,
+                        int32_t reps, int32_t *chosen, float *times_ms, void *stream)
+{
+    static thread_local Frame fr[GSC_MAX_BATCH];
+    gsc_status st = prepare_encode_batch(frames, F, params, fr);
+    if (st != GSC_OK) return st;
+    if (reps < 1 || reps > 1000) return GSC_ERR_INVALID_ARG;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return GSC_ERR_HIP;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return GSC_ERR_HIP;
+    }
+    float best = 0.0f;
+    int best_v = -1;
+    for (int v = 0; v < SORT_VARIANTS && st == GSC_OK; ++v) {
+        g_force_variant = v;
+        st = encode_frames(fr, F, params, s);  // warm-up
+        if (st == GSC_OK && hipEventRecord(e0, s) != hipSuccess) st = GSC_ERR_HIP;
+        for (int r = 0; r < reps && st == GSC_OK; ++r) st = encode_frames(fr, F, params, s);
+        if (st == GSC_OK && hipEventRecord(e1, s) != hipSuccess) st = GSC_ERR_HIP;
+        float ms = 0.0f;
+        if (st == GSC_OK && (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+            st = GSC_ERR_HIP;
+        ms /= (float)reps;
+        if (times_ms) times_ms[v] = ms;
+        if (st == GSC_OK && (best_v < 0 || ms < best)) {
+            best = ms;
+            best_v = v;
+        }
+    }
+    g_force_variant = -1;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != GSC_OK) return st;
+    uint64_t nmax = 0;
+    for (int f = 0; f < F; ++f) nmax = fr[f].a.n > nmax ? fr[f].a.n : nmax;
+    g_tune[params->J][size_class(nmax)].store(best_v + 1, std::memory_order_relaxed);
+    if (chosen) *chosen = best_v;
+    return GSC_OK;
+}
+
+gsc_status gsc_tune_set(int32_t J, int64_t n, int32_t variant)
+{
+    if (J < 1 || J > GSC_MAX_DEPTH || n < 0 || n > N_LIMIT) return GSC_ERR_INVALID_ARG;
+    if (variant < -1 || variant >= SORT_VARIANTS) return GSC_ERR_INVALID_ARG;
+    g_tune[J][size_class((uint64_t)n)].store(variant + 1, std::memory_order_relaxed);
+    return GSC_OK;
+}
+
+gsc_status gsc_tune_get(int32_t J, int64_t n, int32_t *variant)
+{
+    if (J < 1 || J > GSC_MAX_DEPTH || n < 0 || n > N_LIMIT || !variant) return GSC_ERR_INVALID_ARG;
+    *variant = sort_variant_for(J, (uint64_t)n);
+    return GSC_OK;
 }
 
 gsc_status gsc_encode_frame(const float *d_pos, const float *d_attr, int64_t n,
@@ -501,6 +603,72 @@ static gsc_status raht_f32(const uint64_t *d_codes, int64_t nv, int32_t J, int32
         else
             st = run_forward(&fr, 1, cfg, s);
         if (st != GSC_OK) return st;
+    }
+    return run_finish(&fr, 1, s);
+}
+
+gsc_status gsc_ste_forward(const float *d_pos, const float *d_attr, int64_t n,
+                           const gsc_params *params, void *d_stream, size_t stream_cap, void *d_ws,
+                           size_t ws_bytes, int32_t *d_info, float *d_yhat, float *d_ahat,
+                           float *d_aref, uint64_t *d_leaf_codes, void *stream)
+{
+    gsc_status st = check_params(params);
+    if (st != GSC_OK) return st;
+    if (n < 0 || n > N_LIMIT) return GSC_ERR_INVALID_ARG;
+    if (!d_stream || !d_ws || !d_info) return GSC_ERR_INVALID_ARG;
+    if (n > 0 && (!d_pos || !d_attr || !d_yhat || !d_ahat)) return GSC_ERR_INVALID_ARG;
+    if (n > 0 && ((const void *)d_yhat == (const void *)d_ahat || (const void *)d_yhat == (const void *)d_attr ||
+                  (const void *)d_ahat == (const void *)d_attr))
+        return GSC_ERR_INVALID_ARG;
+    Frame fr;
+    if (!layout_for(n, params->J, params->C, &fr.L)) return GSC_ERR_INVALID_ARG;
+    if (ws_bytes < fr.L.total) return GSC_ERR_WORKSPACE;
+    if (stream_cap < stream_capacity(n, params->J, params->C)) return GSC_ERR_CAPACITY;
+    memset(&fr.a, 0, sizeof(fr.a));
+    fr.a.n = (uint32_t)n;
+    fr.a.pos = d_pos;
+    fr.a.attr = d_attr;
+    fr.a.stream = static_cast<uint8_t *>(d_stream);
+    fr.a.stream_cap = stream_cap;
+    fr.a.ws = static_cast<uint8_t *>(d_ws);
+    fr.a.info = d_info;
+    fr.a.coef_f32 = d_yhat;
+    fr.a.attr_out = d_ahat;
+    fr.a.aref = d_aref;
+    fr.a.codes_out = d_leaf_codes;
+    return encode_frames(&fr, 1, params, static_cast<hipStream_t>(stream), true);
+}
+
+gsc_status gsc_ste_backward(int64_t n, int32_t J, int32_t C, const float *d_grad_yhat,
+                            const float *d_grad_ahat, float *d_grad_attr, void *d_ws,
+                            size_t ws_bytes, int32_t *d_info, void *stream)
+{
+    gsc_status st = check_shape(J, C);
+    if (st != GSC_OK) return st;
+    if (n < 0 || n > N_LIMIT) return GSC_ERR_INVALID_ARG;
+    if (!d_ws || !d_info) return GSC_ERR_INVALID_ARG;
+    if (n > 0 && (!d_grad_yhat || !d_grad_ahat || !d_grad_attr)) return GSC_ERR_INVALID_ARG;
+    if (n > 0 && ((const void *)d_grad_attr == (const void *)d_grad_yhat ||
+                  (const void *)d_grad_attr == (const void *)d_grad_ahat))
+        return GSC_ERR_INVALID_ARG;
+    Frame fr;
+    if (!layout_for(n, J, C, &fr.L)) return GSC_ERR_INVALID_ARG;
+    if (ws_bytes < fr.L.total) return GSC_ERR_WORKSPACE;
+    memset(&fr.a, 0, sizeof(fr.a));
+    fr.a.n = (uint32_t)n;
+    fr.a.attr = d_grad_yhat;
+    fr.a.grad_add = d_grad_ahat;
+    fr.a.attr_out = d_grad_attr;
+    fr.a.ws = static_cast<uint8_t *>(d_ws);
+    fr.a.info = d_info;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    SetupArgs proto = make_proto((uint32_t)J, (uint32_t)C, MODE_STE_BWD, nullptr);
+    proto.ste = STE_FORWARD;  // the workspace keeps holding the forward's schedule
+    proto.keep = 1;
+    if ((st = run_setup(&fr, 1, proto, s)) != GSC_OK) return st;
+    if (n > 0) {
+        const RahtCfg cfg = raht_cfg(&fr, 1, C, nullptr);
+        if ((st = run_inverse(&fr, 1, cfg, s)) != GSC_OK) return st;
     }
     return run_finish(&fr, 1, s);
 }

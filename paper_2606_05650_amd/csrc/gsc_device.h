@@ -287,32 +287,39 @@ __device__ inline uint64_t lookback_wave(uint64_t *status, uint32_t stride, uint
     return acc;
 }
 
-// 32-bit status words for the radix sort: [31:30] flag, [29:0] count (n < 2^30).
-__device__ inline uint32_t lookback_sum32(uint32_t *status, uint32_t stride, uint32_t tile,
-                                          uint32_t agg, Ctrl *ctrl)
+// 32-bit status words for the radix sort: [31:30] flag, [29:0] count (n < 2^30). A tile first
+// publishes its aggregate (tile 0 its inclusive count), then resolves its exclusive prefix.
+// Each thread reads WIN predecessors per round, so the look-back of the last of T tiles needs
+// about T/WIN dependent rounds of device-scope loads when every predecessor has only its
+// aggregate.
+constexpr uint32_t LB32_AGG = 1u << 30, LB32_INC = 2u << 30, LB32_VAL = (1u << 30) - 1u;
+
+__device__ inline void lookback32_publish(uint32_t *status, uint32_t stride, uint32_t tile, uint32_t agg)
 {
-    constexpr uint32_t AGG = 1u << 30, INC = 2u << 30, VAL = (1u << 30) - 1u;
-    if (tile == 0) {
-        st_relaxed32(&status[0], INC | agg);
-        return 0;
-    }
-    st_relaxed32(&status[(size_t)tile * stride], AGG | agg);
+    st_relaxed32(&status[(size_t)tile * stride], (tile == 0 ? LB32_INC : LB32_AGG) | agg);
+}
+
+template <int WIN>
+__device__ inline uint32_t lookback32_resolve(uint32_t *status, uint32_t stride, uint32_t tile,
+                                              uint32_t agg, Ctrl *ctrl)
+{
+    if (tile == 0) return 0;
     uint32_t acc = 0;
     int64_t j = (int64_t)tile - 1;
     uint32_t spins = 0;
     bool done = false;
     while (!done) {
-        uint32_t w[LB_WINDOW];
+        uint32_t w[WIN];
 #pragma unroll
-        for (int i = 0; i < LB_WINDOW; ++i)
-            w[i] = (j - i >= 0) ? ld_relaxed32(&status[(size_t)(j - i) * stride]) : INC;
+        for (int i = 0; i < WIN; ++i)
+            w[i] = (j - i >= 0) ? ld_relaxed32(&status[(size_t)(j - i) * stride]) : LB32_INC;
         int used = 0;
         bool stalled = false, stop = false;
 #pragma unroll
-        for (int i = 0; i < LB_WINDOW; ++i) {  // predicated (no break) so w stays in registers
+        for (int i = 0; i < WIN; ++i) {  // predicated (no break) so w stays in registers
             const uint32_t flag = w[i] >> 30;
             if (!stop && flag != 0) {
-                acc += w[i] & VAL;
+                acc += w[i] & LB32_VAL;
                 ++used;
             }
             if (!stop && flag == 0) stalled = true;
@@ -330,7 +337,7 @@ __device__ inline uint32_t lookback_sum32(uint32_t *status, uint32_t stride, uin
             __builtin_amdgcn_s_sleep(1);
         }
     }
-    st_relaxed32(&status[(size_t)tile * stride], INC | (acc + agg));
+    st_relaxed32(&status[(size_t)tile * stride], LB32_INC | (acc + agg));
     return acc;
 }
 

@@ -17,8 +17,16 @@ constexpr int WAVE = 64;
 constexpr int SORT_BITS = 8;            // radix digit width
 constexpr int SORT_BINS = 1 << SORT_BITS;
 constexpr int SORT_THREADS = 256;       // 4 waves
-constexpr int SORT_KPT = 16;            // keys per thread
-constexpr int SORT_TILE = SORT_THREADS * SORT_KPT;
+// Tiling variants of a sort pass (keys per thread, look-back window), chosen per call by the
+// autotuner's table; the workspace is laid out for the smallest tile.
+struct SortVariant {
+    int kpt, win;
+};
+constexpr int SORT_VARIANTS = GSC_SORT_VARIANTS;
+constexpr SortVariant SORT_VARIANT[SORT_VARIANTS] = {{16, 32}, {8, 32}, {16, 64}, {16, 16}};
+constexpr int SORT_DEFAULT_VARIANT = 0;
+constexpr int SORT_KPT_MIN = 8;
+__host__ __device__ constexpr int sort_tile(int variant) { return SORT_THREADS * SORT_VARIANT[variant].kpt; }
 constexpr int SORT_MAX_PASSES = 8;      // ceil(63 / 8)
 
 constexpr int DEDUP_THREADS = 256;
@@ -80,7 +88,13 @@ enum : uint32_t {
     MODE_DECODE = 1,    // dequantize from the stream, write output rows
     MODE_FWD_F32 = 2,   // float rows in, float coefficients out
     MODE_ADJ_F32 = 3,   // float coefficients in, float rows out
+    MODE_STE_BWD = 4,   // gradient of the straight-through coder: float coefficient rows in,
+                        // inverse transform, plus a voxel-row term, scattered to the Gaussians
 };
+
+// Straight-through coding: an encode that also writes the voxel means and the dequantized
+// coefficients, then synthesizes the decoded rows with the same schedule.
+enum : uint32_t { STE_NONE = 0, STE_FORWARD = 1 };
 
 struct RahtLevel {
     uint32_t *s_idx;     // k >= 2: voxel index of each entry of S_k
@@ -101,6 +115,7 @@ struct FrameDesc {
     uint32_t n;          // encode: Gaussians; decode / transform: voxel capacity
     uint32_t J, C, C4, P;   // depth, channels, channels/4 rounded up, sort passes
     uint32_t mode;
+    uint32_t ste;        // STE_FORWARD: the workspace holds (or is building) a straight-through forward
     uint32_t bbox_mode;
     float tau;
     double bbox_min[3];
@@ -127,6 +142,8 @@ struct FrameDesc {
     float *attr_out;
     int32_t *info;           // device info words
     const uint64_t *codes_in;   // MODE_FWD_F32 / MODE_ADJ_F32: leaf codes
+    float *aref;                // STE forward: voxel means of the input rows
+    const float *grad_add;      // MODE_STE_BWD: gradient rows added per voxel before the scatter
     // workspace buffers
     uint64_t *keys_a, *keys_b;
     uint32_t *vals_a, *vals_b;
@@ -167,11 +184,15 @@ struct FrameArgs {
     uint32_t *vox_out;
     float *attr_out;
     const uint64_t *codes_in;
+    float *aref;
+    const float *grad_add;
 };
 constexpr int SETUP_MAX = 16;
 struct SetupArgs {
     uint32_t count;
     uint32_t J, C, mode, bbox_mode;
+    uint32_t ste;
+    uint32_t keep;       // reuse the workspace state of a previous call (no zeroing)
     float tau;
     double bbox_min[3];
     double cell;
@@ -223,7 +244,7 @@ __host__ __device__ inline bool make_layout(int64_t n, int J, int C, Layout *L)
     const int C4 = (C + 3) / 4;
     const uint32_t om = open_max(J);
     L->P = (uint32_t)sort_passes(J);
-    L->sort_tiles = ceil_div(N, SORT_TILE);
+    L->sort_tiles = ceil_div(N, SORT_THREADS * SORT_KPT_MIN);
     L->dedup_tiles = ceil_div(N, DEDUP_TILE);
     L->occ_tiles = ceil_div(N, OCC_TILE);
     // RAHT tiling levels: S_1 has N entries; a tile of RT entries leaves at most 6J+2 open.
@@ -288,7 +309,7 @@ __host__ __device__ inline bool make_layout(int64_t n, int J, int C, Layout *L)
 hipError_t launch_setup(const SetupArgs &a, uint32_t zero_blocks, hipStream_t s);
 hipError_t launch_bbox(const TileMap &m, hipStream_t s);
 hipError_t launch_voxelize(const TileMap &m, hipStream_t s);
-hipError_t launch_sort_pass(const TileMap &m, int pass, hipStream_t s);
+hipError_t launch_sort_pass(const TileMap &m, int pass, int variant, hipStream_t s);
 hipError_t launch_dedup(const TileMap &m, hipStream_t s);
 hipError_t launch_occupancy(const TileMap &m, hipStream_t s);
 hipError_t launch_dec_top(const TileMap &m, hipStream_t s);

@@ -23,7 +23,7 @@ __global__ __launch_bounds__(256) void k_setup(SetupArgs a)
     }
     __syncthreads();
     // zero the look-back status region (16-byte stores; the region is 256-byte aligned)
-    {
+    if (!a.keep) {
         uint4 *z = reinterpret_cast<uint4 *>(fa.ws + s_zero_off);
         const size_t nq = s_zero_bytes / 16;
         const size_t stride = (size_t)gridDim.x * blockDim.x;
@@ -32,24 +32,36 @@ __global__ __launch_bounds__(256) void k_setup(SetupArgs a)
     }
     if (blockIdx.x != 0) return;
     Ctrl *ctrl = reinterpret_cast<Ctrl *>(fa.ws);
-    uint32_t *cw = reinterpret_cast<uint32_t *>(ctrl);
-    for (uint32_t i = threadIdx.x; i < CTRL_BYTES / 4; i += blockDim.x) cw[i] = 0;
+    FrameDesc *fd = reinterpret_cast<FrameDesc *>(fa.ws + DESC_OFF);
+    __shared__ uint32_t s_prev_ok;
+    if (a.keep && threadIdx.x == 0) {
+        // the workspace must hold a straight-through forward of the same shape
+        s_prev_ok = (fd->ste == STE_FORWARD && fd->n == fa.n && fd->J == a.J && fd->C == a.C) ? 1u : 0u;
+    }
+    if (!a.keep) {
+        uint32_t *cw = reinterpret_cast<uint32_t *>(ctrl);
+        for (uint32_t i = threadIdx.x; i < CTRL_BYTES / 4; i += blockDim.x) cw[i] = 0;
+    }
     if (fa.info)
         for (uint32_t i = threadIdx.x; i < GSC_INFO_WORDS; i += blockDim.x) fa.info[i] = 0;
     __syncthreads();
     if (threadIdx.x != 0) return;
-    for (int a3 = 0; a3 < 3; ++a3) ctrl->bbox_ord[a3] = BBOX_SENTINEL_MIN;
-    ctrl->n_in = fa.n;
-    if (a.mode == MODE_FWD_F32 || a.mode == MODE_ADJ_F32) ctrl->n_vox = fa.n;
+    if (a.keep) {
+        if (!s_prev_ok) set_error(ctrl, GSC_ERR_INVALID_ARG);
+    } else {
+        for (int a3 = 0; a3 < 3; ++a3) ctrl->bbox_ord[a3] = BBOX_SENTINEL_MIN;
+        ctrl->n_in = fa.n;
+        if (a.mode == MODE_FWD_F32 || a.mode == MODE_ADJ_F32) ctrl->n_vox = fa.n;
+    }
 
     const Layout &L = s_L;
-    FrameDesc *fd = reinterpret_cast<FrameDesc *>(fa.ws + DESC_OFF);
     fd->n = fa.n;
     fd->J = a.J;
     fd->C = a.C;
     fd->C4 = (a.C + 3) / 4;
     fd->P = L.P;
     fd->mode = a.mode;
+    fd->ste = (a.keep && !s_prev_ok) ? STE_NONE : a.ste;
     fd->bbox_mode = a.bbox_mode;
     fd->tau = a.tau;
     for (int i = 0; i < 3; ++i) fd->bbox_min[i] = a.bbox_min[i];
@@ -81,6 +93,8 @@ __global__ __launch_bounds__(256) void k_setup(SetupArgs a)
     fd->attr_out = fa.attr_out;
     fd->info = fa.info;
     fd->codes_in = fa.codes_in;
+    fd->aref = fa.aref;
+    fd->grad_add = fa.grad_add;
     fd->keys_a = reinterpret_cast<uint64_t *>(fa.ws + L.keys_a);
     fd->keys_b = reinterpret_cast<uint64_t *>(fa.ws + L.keys_b);
     fd->vals_a = reinterpret_cast<uint32_t *>(fa.ws + L.vals_a);
@@ -345,7 +359,7 @@ uint32_t voxelize_blocks(uint32_t n) { return n ? ceil_div(n, VOX_TILE) : 1u; }
 
 // ============================================================ one-sweep radix sort pass
 // Stable LSD pass over digit `pass` of (key, index) pairs. Each workgroup ranks a tile of
-// SORT_TILE keys in LDS: wave w owns a contiguous quarter of the tile and walks it in order,
+// SORT_THREADS * KPT keys in LDS: wave w owns a contiguous quarter of the tile and walks it in order,
 // 64 keys at a time; lanes holding the same digit are found with SORT_BITS ballots and ranked
 // among themselves, so equal digits keep input order. The tile's digit counts are combined
 // with its predecessors' through a per-digit decoupled look-back, keys are staged in LDS in
@@ -362,16 +376,18 @@ __device__ inline uint64_t match_digit(uint32_t d)
     return peers;
 }
 
+template <int KPT, int WIN>
 __global__ __launch_bounds__(SORT_THREADS) void k_sort_pass(TileMap m, int pass)
 {
+    constexpr int TILE = SORT_THREADS * KPT;
     constexpr int NW = SORT_THREADS / WAVE;
     __shared__ uint32_t s_tile;
     __shared__ uint32_t s_wcnt[NW][SORT_BINS];
     __shared__ uint32_t s_gbase[SORT_BINS];
     __shared__ uint32_t s_lstart[SORT_BINS];
     __shared__ uint32_t s_tmp[NW + 1];
-    __shared__ uint64_t s_keys[SORT_TILE];
-    __shared__ uint32_t s_vals[SORT_TILE];
+    __shared__ uint64_t s_keys[TILE];
+    __shared__ uint32_t s_vals[TILE];
 
     const uint32_t f = frame_of(m, blockIdx.x);
     const FrameDesc &fd = *m.fd[f];
@@ -383,7 +399,7 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_pass(TileMap m, int pass)
     for (uint32_t i = tid; i < NW * SORT_BINS; i += SORT_THREADS) (&s_wcnt[0][0])[i] = 0;
     __syncthreads();
     const uint32_t tile = s_tile;
-    const uint32_t base = tile * SORT_TILE;
+    const uint32_t base = tile * TILE;
     if (base >= n) return;
     const GAS uint64_t *kin = gp((pass & 1) ? fd.keys_b : fd.keys_a);
     const GAS uint32_t *vin = gp((pass & 1) ? fd.vals_b : fd.vals_a);
@@ -391,19 +407,19 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_pass(TileMap m, int pass)
     GAS uint32_t *vout = gp((pass & 1) ? fd.vals_a : fd.vals_b);
     const uint32_t shift = (uint32_t)pass * SORT_BITS;
 
-    uint64_t key[SORT_KPT];
-    uint32_t val[SORT_KPT];
-    uint32_t rank[SORT_KPT];
-    const uint32_t wbase = base + w * (SORT_KPT * WAVE);
+    uint64_t key[KPT];
+    uint32_t val[KPT];
+    uint32_t rank[KPT];
+    const uint32_t wbase = base + w * (KPT * WAVE);
 #pragma unroll
-    for (int j = 0; j < SORT_KPT; ++j) {
+    for (int j = 0; j < KPT; ++j) {
         const uint32_t p = wbase + j * WAVE + lane;
         const bool valid = p < n;
         key[j] = valid ? kin[p] : ~0ull;
         val[j] = pass == 0 ? p : (valid ? vin[p] : 0u);
     }
 #pragma unroll
-    for (int j = 0; j < SORT_KPT; ++j) {
+    for (int j = 0; j < KPT; ++j) {
         const uint32_t d = (uint32_t)(key[j] >> shift) & (SORT_BINS - 1);
         const uint64_t peers = match_digit(d);
         const uint32_t cnt = s_wcnt[w][d];
@@ -414,7 +430,10 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_pass(TileMap m, int pass)
         __builtin_amdgcn_wave_barrier();
     }
     __syncthreads();
-    // per digit (one thread per digit): wave prefixes, tile count, look-back, global base
+    // per digit (one thread per digit): wave prefixes, tile count (published at once), digit
+    // start in the tile, digit start in the output
+    uint32_t *status_d = fd.sort_status + (size_t)pass * fd.sort_tiles * SORT_BINS + tid;
+    uint32_t tile_cnt, hist_excl;
     {
         const uint32_t d = tid;
         uint32_t run = 0;
@@ -424,24 +443,24 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_pass(TileMap m, int pass)
             s_wcnt[ww][d] = run;
             run += c;
         }
-        const uint32_t tile_cnt = run;
-        const uint32_t excl = lookback_sum32(fd.sort_status + (size_t)pass * fd.sort_tiles * SORT_BINS + d,
-                                             SORT_BINS, tile, tile_cnt, ctrl);
-        const uint32_t hist_excl =
-            block_excl_scan<SORT_THREADS>(ctrl->sort_hist[pass * SORT_BINS + d], s_tmp, nullptr);
-        s_gbase[d] = hist_excl + excl;
+        tile_cnt = run;
+        lookback32_publish(status_d, SORT_BINS, tile, tile_cnt);
+        hist_excl = block_excl_scan<SORT_THREADS>(ctrl->sort_hist[pass * SORT_BINS + d], s_tmp, nullptr);
         s_lstart[d] = block_excl_scan<SORT_THREADS>(tile_cnt, s_tmp, nullptr);
     }
     __syncthreads();
+    // keys to LDS in tile-local digit order: the keys leave the registers before the look-back,
+    // whose window takes their place
 #pragma unroll
-    for (int j = 0; j < SORT_KPT; ++j) {
+    for (int j = 0; j < KPT; ++j) {
         const uint32_t d = (uint32_t)(key[j] >> shift) & (SORT_BINS - 1);
         const uint32_t q = s_lstart[d] + s_wcnt[w][d] + rank[j];
         s_keys[q] = key[j];
         s_vals[q] = val[j];
     }
+    s_gbase[tid] = hist_excl + lookback32_resolve<WIN>(status_d, SORT_BINS, tile, tile_cnt, ctrl);
     __syncthreads();
-    const uint32_t nvalid = min((uint32_t)SORT_TILE, n - base);
+    const uint32_t nvalid = min((uint32_t)TILE, n - base);
     for (uint32_t q = tid; q < nvalid; q += SORT_THREADS) {
         const uint64_t k = s_keys[q];
         const uint32_t d = (uint32_t)(k >> shift) & (SORT_BINS - 1);
@@ -453,9 +472,16 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_pass(TileMap m, int pass)
     }
 }
 
-hipError_t launch_sort_pass(const TileMap &m, int pass, hipStream_t s)
+hipError_t launch_sort_pass(const TileMap &m, int pass, int variant, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_sort_pass, dim3(m.start[m.F]), dim3(SORT_THREADS), 0, s, m, pass);
+    const dim3 grid(m.start[m.F]), block(SORT_THREADS);
+    switch (variant) {
+    case 0: hipLaunchKernelGGL((k_sort_pass<SORT_VARIANT[0].kpt, SORT_VARIANT[0].win>), grid, block, 0, s, m, pass); break;
+    case 1: hipLaunchKernelGGL((k_sort_pass<SORT_VARIANT[1].kpt, SORT_VARIANT[1].win>), grid, block, 0, s, m, pass); break;
+    case 2: hipLaunchKernelGGL((k_sort_pass<SORT_VARIANT[2].kpt, SORT_VARIANT[2].win>), grid, block, 0, s, m, pass); break;
+    case 3: hipLaunchKernelGGL((k_sort_pass<SORT_VARIANT[3].kpt, SORT_VARIANT[3].win>), grid, block, 0, s, m, pass); break;
+    default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

@@ -547,6 +547,12 @@ __global__ __launch_bounds__(RAHT_THREADS) void k_raht_fwd(TileMap m, int k)
                     acc.w /= cnt;
                     s_y[j * CH4 + R.c4] = acc;
                 }
+                if (fd.ste == STE_FORWARD && fd.aref) {
+                    // the voxel means (this thread's own rows of the slice)
+                    GAS float *ar = gp(fd.aref);
+                    for (uint32_t j = R.row0; j < mlen; j += R.RPB)
+                        st4<VEC>(ar, ts.s + j, C, c4, s_y[j * CH4 + R.c4]);
+                }
             } else if (k == 1) {
                 load_slice(s_y, R, CH4, mlen, [&](uint32_t j) { return ld4<VEC>(attr, ts.s + j, C, c4); });
             } else {
@@ -563,6 +569,7 @@ __global__ __launch_bounds__(RAHT_THREADS) void k_raht_fwd(TileMap m, int k)
         if (!live) continue;
         if (fd.mode == MODE_ENCODE) {
             const double omt = 1.0 - (double)fd.tau;
+            const bool deq = fd.ste == STE_FORWARD;  // float output: q * step instead of y
             GAS float *cf = coef_f32;
             float st[4], ist[4];
 #pragma unroll
@@ -577,7 +584,11 @@ __global__ __launch_bounds__(RAHT_THREADS) void k_raht_fwd(TileMap m, int k)
                 const int4 q = make_int4(quant1<POW2>(y.x, st[0], ist[0], omt), quant1<POW2>(y.y, st[1], ist[1], omt),
                                          quant1<POW2>(y.z, st[2], ist[2], omt), quant1<POW2>(y.w, st[3], ist[3], omt));
                 stq4<VEC>(coef, row, C, c4, q);
-                if (cf) st4<VEC>(cf, row, C, c4, y);
+                if (cf)
+                    st4<VEC>(cf, row, C, c4,
+                             deq ? make_float4((float)q.x * st[0], (float)q.y * st[1], (float)q.z * st[2],
+                                               (float)q.w * st[3])
+                                 : y);
             }
         } else {  // MODE_FWD_F32: float coefficient rows
             for (uint32_t j = R.row0; j < mlen; j += R.RPB)
@@ -621,7 +632,9 @@ __global__ __launch_bounds__(RAHT_THREADS) void k_raht_inv(TileMap m, int k)
     const GAS int32_t *coef = fd.mode == MODE_DECODE
                                   ? gp(reinterpret_cast<const int32_t *>(fd.in_stream + h->coef_offset))
                                   : nullptr;
-    const GAS float *attr = gp(fd.attr);
+    // float coefficient rows: the straight-through forward synthesizes from its dequantized
+    // coefficients; the transform and gradient modes read the caller's rows
+    const GAS float *fin = gp(fd.mode == MODE_ENCODE ? fd.coef_f32 : fd.attr);
 
     for (uint32_t p = 0; p < NP; ++p) {
         const uint32_t cb = p * CH4;
@@ -640,9 +653,9 @@ __global__ __launch_bounds__(RAHT_THREADS) void k_raht_inv(TileMap m, int k)
                     return make_float4((float)q.x * st[0], (float)q.y * st[1], (float)q.z * st[2],
                                        (float)q.w * st[3]);
                 });
-            } else {  // MODE_ADJ_F32: float coefficient rows
+            } else {  // float coefficient rows
                 load_slice(s_y, R, CH4, mlen, [&](uint32_t j) {
-                    return ld4<VEC>(attr, entry_index(k, s_idx, ts.s, (int)j), C, c4);
+                    return ld4<VEC>(fin, entry_index(k, s_idx, ts.s, (int)j), C, c4);
                 });
             }
         }
@@ -666,8 +679,25 @@ __global__ __launch_bounds__(RAHT_THREADS) void k_raht_inv(TileMap m, int k)
             GAS float *dst = gp(fd.lv[k - 1].vbuf);
             for (uint32_t j = R.row0; j < mlen; j += R.RPB)
                 gstore4(dst + ((size_t)(ts.s + j) * C4 + c4) * 4, s_y[j * CH4 + R.c4]);
+        } else if (fd.mode == MODE_STE_BWD) {
+            // voxel gradient = synthesized rows + the added rows; each member Gaussian receives
+            // it divided by the member count (the voxel row is the members' mean)
+            GAS float *out = gp(fd.attr_out);
+            const GAS float *ga = gp(fd.grad_add);
+            const GAS uint32_t *vh = gp(fd.vh);
+            const GAS uint32_t *perm = gp((fd.P & 1) ? fd.vals_b : fd.vals_a);
+            for (uint32_t j = R.row0; j < mlen; j += R.RPB) {
+                const uint32_t v = ts.s + j;
+                const float4 a = s_y[j * CH4 + R.c4];
+                const float4 b = ld4<VEC>(ga, v, C, c4);
+                const uint32_t m0 = vh[v], m1 = vh[v + 1];
+                const float cnt = (float)(m1 - m0);
+                const float4 g = make_float4((a.x + b.x) / cnt, (a.y + b.y) / cnt, (a.z + b.z) / cnt,
+                                             (a.w + b.w) / cnt);
+                for (uint32_t mm = m0; mm < m1; ++mm) st4<VEC>(out, perm[mm], C, c4, g);
+            }
         } else {
-            GAS float *out = gp(fd.mode == MODE_DECODE ? fd.attr_out : fd.coef_f32);
+            GAS float *out = gp(fd.mode == MODE_ADJ_F32 ? fd.coef_f32 : fd.attr_out);
             for (uint32_t j = R.row0; j < mlen; j += R.RPB) st4<VEC>(out, ts.s + j, C, c4, s_y[j * CH4 + R.c4]);
         }
     }

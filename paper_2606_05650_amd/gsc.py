@@ -87,6 +87,18 @@ def lib():
         L.gsc_encode_batch.argtypes = [ctypes.POINTER(FrameDescC), i32, ctypes.POINTER(Params), vp]
         L.gsc_decode_batch.restype = i32
         L.gsc_decode_batch.argtypes = [ctypes.POINTER(StreamDescC), i32, i32, i32, vp]
+        L.gsc_autotune.restype = i32
+        L.gsc_autotune.argtypes = [ctypes.POINTER(FrameDescC), i32, ctypes.POINTER(Params), i32,
+                                   ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_float), vp]
+        L.gsc_tune_set.restype = i32
+        L.gsc_tune_set.argtypes = [i32, i64, i32]
+        L.gsc_tune_get.restype = i32
+        L.gsc_tune_get.argtypes = [i32, i64, ctypes.POINTER(i32)]
+        L.gsc_ste_forward.restype = i32
+        L.gsc_ste_forward.argtypes = [vp, vp, i64, ctypes.POINTER(Params), vp, sz, vp, sz, vp, vp,
+                                      vp, vp, vp, vp]
+        L.gsc_ste_backward.restype = i32
+        L.gsc_ste_backward.argtypes = [i64, i32, i32, vp, vp, vp, vp, sz, vp, vp]
         L.gsc_raht_forward.restype = i32
         L.gsc_raht_forward.argtypes = [vp, i64, i32, i32, vp, vp, vp, sz, vp, vp]
         L.gsc_raht_adjoint.restype = i32
@@ -286,8 +298,7 @@ def decode_frame(stream_buf, J, C, n_cap, *, stream_bytes=None, ws=None, want_vo
     return Decoded(pos_out, attr_out, vox, codes, info, ws)
 
 
-def encode_batch(frames, params, *, workspaces=None, stream=None):
-    """frames: list of (pos, attr) device tensors. Returns a list of Encoded."""
+def _encode_descs(frames, params, workspaces):
     torch = _torch()
     F = len(frames)
     if F < 1 or F > MAX_BATCH:
@@ -313,9 +324,40 @@ def encode_batch(frames, params, *, workspaces=None, stream=None):
     assert_disjoint([(o.stream.data_ptr(), _nbytes(o.stream)) for o in outs] +
                     [(o.info.data_ptr(), _nbytes(o.info)) for o in outs] +
                     [(o.ws.buf.data_ptr(), o.ws.bytes) for o in outs])
-    _check(lib().gsc_encode_batch(descs, F, ctypes.byref(params), _stream(stream)),
+    return descs, outs
+
+
+def encode_batch(frames, params, *, workspaces=None, stream=None):
+    """frames: list of (pos, attr) device tensors. Returns a list of Encoded."""
+    descs, outs = _encode_descs(frames, params, workspaces)
+    _check(lib().gsc_encode_batch(descs, len(frames), ctypes.byref(params), _stream(stream)),
            "gsc_encode_batch")
     return outs
+
+
+SORT_VARIANTS = 4
+
+
+def autotune(frames, params, *, reps=3, workspaces=None, stream=None):
+    """Times every sort tiling on this batch and keeps the fastest for batches of its size
+    class and depth. Synchronous. Returns (chosen variant, mean ms per variant, outputs)."""
+    descs, outs = _encode_descs(frames, params, workspaces)
+    chosen = ctypes.c_int32(-1)
+    times = (ctypes.c_float * SORT_VARIANTS)()
+    _check(lib().gsc_autotune(descs, len(frames), ctypes.byref(params), int(reps),
+                              ctypes.byref(chosen), times, _stream(stream)), "gsc_autotune")
+    return chosen.value, [float(t) for t in times], outs
+
+
+def tune_set(J, n, variant):
+    """Sets (variant >= 0) or clears (-1) the sort tiling used for depth J and frames of n."""
+    _check(lib().gsc_tune_set(int(J), int(n), int(variant)), "gsc_tune_set")
+
+
+def tune_get(J, n):
+    v = ctypes.c_int32(-1)
+    _check(lib().gsc_tune_get(int(J), int(n), ctypes.byref(v)), "gsc_tune_get")
+    return v.value
 
 
 def decode_batch(encoded, n_caps, *, workspaces=None, stream=None):
@@ -370,4 +412,55 @@ def _raht(codes, X, J, ws, out, info, stream, adjoint):
     rc = fn(_ptr(codes), nv, int(J), C, _ptr(X), _ptr(out), _ptr(ws.buf), ws.bytes, _ptr(info),
             _stream(stream))
     _check(rc, "gsc_raht_adjoint" if adjoint else "gsc_raht_forward")
+    return out, info
+
+
+@dataclass
+class SteForward:
+    """Result of ste_forward: rows [:nv] of yhat, ahat, aref are valid once the call completes."""
+    yhat: "object"       # [n, C] float32: dequantized coefficients q * step
+    ahat: "object"       # [n, C] float32: T^T yhat, the decoded voxel attributes
+    aref: "object"       # [n, C] float32: voxel means of the input rows
+    encoded: Encoded     # the stream, info words and the workspace holding the schedule
+    n: int
+
+
+def ste_forward(pos, attr, params, *, ws=None, stream_buf=None, info=None, yhat=None, ahat=None,
+                aref=None, leaf_codes=None, stream=None):
+    """Straight-through forward: encode (stream written) + voxel means, dequantized
+    coefficients and their synthesis."""
+    torch = _torch()
+    n = int(pos.shape[0])
+    C = int(params.C)
+    dev = pos.device
+    if ws is None:
+        ws = Workspace(max(n, 1), params.J, C, dev)
+    cap = stream_capacity(n, params.J, C)
+    if stream_buf is None:
+        stream_buf = _dev_u8(cap, dev)
+    if info is None:
+        info = torch.zeros(INFO_WORDS, dtype=torch.int32, device=dev)
+    rows = (max(n, 1), C)
+    yhat = torch.empty(rows, dtype=torch.float32, device=dev) if yhat is None else yhat
+    ahat = torch.empty(rows, dtype=torch.float32, device=dev) if ahat is None else ahat
+    aref = torch.empty(rows, dtype=torch.float32, device=dev) if aref is None else aref
+    rc = lib().gsc_ste_forward(_ptr(pos), _ptr(attr), n, ctypes.byref(params), _ptr(stream_buf),
+                               stream_buf.numel(), _ptr(ws.buf), ws.bytes, _ptr(info), _ptr(yhat),
+                               _ptr(ahat), _ptr(aref), _ptr(leaf_codes), _stream(stream))
+    _check(rc, "gsc_ste_forward")
+    return SteForward(yhat, ahat, aref, Encoded(stream_buf, info, int(params.J), C, ws), n)
+
+
+def ste_backward(fwd, grad_yhat, grad_ahat, *, out=None, info=None, stream=None):
+    """dL/dattr [n, C] from dL/dyhat and dL/dahat ([nv, C] contiguous float32 each)."""
+    torch = _torch()
+    e = fwd.encoded
+    dev = e.stream.device
+    if out is None:
+        out = torch.empty((max(fwd.n, 1), e.C), dtype=torch.float32, device=dev)
+    if info is None:
+        info = torch.zeros(INFO_WORDS, dtype=torch.int32, device=dev)
+    rc = lib().gsc_ste_backward(fwd.n, e.J, e.C, _ptr(grad_yhat), _ptr(grad_ahat), _ptr(out),
+                                _ptr(e.ws.buf), e.ws.bytes, _ptr(info), _stream(stream))
+    _check(rc, "gsc_ste_backward")
     return out, info

@@ -14,7 +14,8 @@ def test_library_exports_every_declared_symbol():
     names = gsc.declared_symbols()
     assert {"gsc_encode_frame", "gsc_decode_frame", "gsc_encode_batch", "gsc_workspace_size",
             "gsc_stream_capacity", "gsc_status_string", "gsc_decode_batch", "gsc_raht_forward",
-            "gsc_raht_adjoint"} <= set(names)
+            "gsc_raht_adjoint", "gsc_ste_forward", "gsc_ste_backward",
+            "gsc_profile_events"} <= set(names)
     for name in names:
         assert hasattr(L, name), name
 
@@ -84,6 +85,28 @@ def test_decode_and_transform_argument_checks():
     descs = (gsc.FrameDescC * 1)()
     assert L.gsc_encode_batch(descs, 0, None, None) == 1
     assert L.gsc_encode_batch(descs, 65, None, None) == 1
+
+
+def test_straight_through_argument_checks():
+    L = gsc.lib()
+    a, b, c = (ctypes.c_void_p(x) for x in (0x1000, 0x2000, 0x3000))
+    J, C, n = 8, 4, 100
+    p = gsc.make_params(J, C, 0.1)
+    ws = gsc.workspace_size(n, J, C)
+    cap = gsc.stream_capacity(n, J, C)
+
+    def fwd(yhat=b, ahat=c, ws_bytes=ws, attr=a, params=p):
+        return L.gsc_ste_forward(a, attr, n, ctypes.byref(params), a, cap, a, ws_bytes, a, yhat,
+                                 ahat, None, None, None)
+    assert fwd(yhat=None) == 1
+    assert fwd(ahat=b) == 1            # yhat and ahat alias
+    assert fwd(attr=b) == 1            # input aliases yhat
+    assert fwd(ws_bytes=10) == 3
+    assert fwd(params=gsc.make_params(J, C, 0.0)) == 1
+    assert L.gsc_ste_backward(n, J, C, a, b, a, c, ws, c, None) == 1   # output aliases input
+    assert L.gsc_ste_backward(n, J, C, None, b, c, a, ws, a, None) == 1
+    assert L.gsc_ste_backward(n, 0, C, a, b, c, a, ws, a, None) == 2
+    assert L.gsc_ste_backward(n, J, C, a, b, c, a, 10, a, None) == 3
 
 
 def test_header_layout_matches_c_struct():

@@ -1,109 +1,21 @@
 """Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
 
-Bars: Morton codes, level sizes, occupancy bytes and decoded positions bit-exact; FP32
-coefficients within 1e-5 of the per-channel maximum of the FP64 ones; quantized coefficients
-equal to the oracle's except at rounding ties (at most 1e-4 of them, off by one, each within the
-FP32 error of a decision boundary), and exactly equal to the oracle's quantizer applied to the
-GPU's own coefficients; decoded attributes within 1e-5 of the per-channel maximum of the FP64
-decode of the same quantized coefficients.
+Bars: Morton codes, level sizes, occupancy bytes, header fields and decoded positions
+bit-exact; FP32 coefficients within 1e-5 of the per-channel maximum of the FP64 ones; quantized
+coefficients equal to the oracle's except at rounding ties (at most 1e-4 of them, off by one,
+each within the FP32 error of a decision boundary), and equal to the decision rule applied to
+the GPU's own coefficients; attributes decoded by the GPU from the oracle's stream within 1e-5
+of the per-channel maximum of the oracle's FP64 decode of the same stream.
 """
 import numpy as np
 import pytest
 
 from oracle import oracle as orc
 from paper_2606_05650_amd import gsc, synth
+from gpucheck import REL_TOL, _dev, gpu_encode, roundtrip
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
-
-REL_TOL = 1e-5
-TIE_FRAC = 1e-4
-
-
-def _dev():
-    if not torch.cuda.is_available():
-        pytest.skip("no GPU")
-    return torch.device("cuda:0")
-
-
-def gpu_encode(pos, attr, J, steps, tau=0.5, bbox=None):
-    dev = _dev()
-    n, C = attr.shape
-    p = gsc.make_params(J, C, steps, tau, bbox)
-    coef = torch.full((max(n, 1), C), np.nan, dtype=torch.float32, device=dev)
-    codes = torch.zeros(max(n, 1), dtype=torch.int64, device=dev)
-    enc = gsc.encode_frame(torch.from_numpy(pos).to(dev), torch.from_numpy(attr).to(dev), p,
-                           coef_f32=coef, leaf_codes=codes)
-    torch.cuda.synchronize()
-    enc.check()
-    blob = np.frombuffer(enc.to_bytes(), dtype=np.uint8)
-    h = gsc.parse_header(blob)
-    nv = int(h["n_vox"])
-    return dict(enc=enc, h=h, nv=nv, blob=blob,
-                occ=blob[1024:1024 + int(h["occ_bytes"])],
-                Q=blob[int(h["coef_offset"]):int(h["total_bytes"])].view(np.int32).reshape(nv, C),
-                Y=coef[:nv].cpu().numpy().astype(np.float64),
-                codes=codes[:nv].cpu().numpy().view(np.uint64))
-
-
-def check_encode(g, ref, J, steps, tau=0.5):
-    nv = ref["nv"]
-    assert g["nv"] == nv
-    assert np.array_equal(g["codes"], ref["leaf"]), "Morton codes differ"
-    assert list(g["h"]["level_sizes"][:J + 1]) == list(ref["level_sizes"])
-    assert np.array_equal(g["occ"], ref["occ"]), "occupancy bytes differ"
-    assert np.array_equal(g["h"]["bbox_min"], ref["bbox_min"]) and g["h"]["cell"] == ref["cell"]
-    if nv == 0:
-        return
-    Y64, Y32 = ref["Y"], g["Y"]
-    scale = np.abs(Y64).max(axis=0)
-    scale[scale == 0] = 1.0
-    rel = np.abs(Y32 - Y64).max(axis=0) / scale
-    assert rel.max() <= REL_TOL, f"coefficient error {rel.max():.3g} (channel {rel.argmax()})"
-    # the GPU's decision on its own coefficients is the oracle's quantizer, exactly
-    assert np.array_equal(g["Q"], orc.quantize(Y32, steps, tau))
-    diff = g["Q"] != ref["Q"]
-    assert diff.mean() <= TIE_FRAC, f"{diff.sum()} quantized coefficients differ"
-    if diff.any():
-        assert np.abs(g["Q"] - ref["Q"])[diff].max() == 1
-        cols = np.nonzero(diff)[1]
-        t = np.abs(Y64[diff]) / steps[cols].astype(np.float64) + tau
-        dist = np.abs(t - np.round(t))  # distance of the FP64 decision to its boundary
-        bound = np.abs(Y32 - Y64)[diff] / steps[cols] + 1e-12
-        assert np.all(dist <= bound)
-
-
-def check_decode(g, ref, J, steps):
-    dev = _dev()
-    nv, C = g["nv"], g["Q"].shape[1] if g["nv"] else 0
-    dec = gsc.decode_frame(g["enc"].stream, J, g["enc"].C, max(nv, 1), want_vox=True,
-                           want_codes=True)
-    torch.cuda.synchronize()
-    dec.check()
-    assert dec.n_vox() == nv
-    if nv == 0:
-        return
-    assert np.array_equal(dec.codes[:nv].cpu().numpy().view(np.uint64), ref["leaf"])
-    vox, cen = orc.voxel_centres(ref["leaf"], J, ref["bbox_min"], ref["cell"])
-    assert np.array_equal(dec.vox[:nv].cpu().numpy().astype(np.uint32), vox)
-    assert np.array_equal(dec.pos[:nv].cpu().numpy(), cen.astype(np.float32)), "positions differ"
-    want = orc.decode_frame(ref["occ"], ref["level_sizes"], J, g["Q"], steps, ref["bbox_min"],
-                            ref["cell"])["attr"]
-    got = dec.attr[:nv].cpu().numpy().astype(np.float64)
-    scale = np.abs(want).max(axis=0)
-    scale[scale == 0] = 1.0
-    rel = np.abs(got - want).max(axis=0) / scale
-    assert rel.max() <= REL_TOL, f"decoded attribute error {rel.max():.3g}"
-
-
-def roundtrip(pos, attr, J, steps, tau=0.5, bbox=None):
-    print(f"case n={pos.shape[0]} C={attr.shape[1]} J={J} tau={tau} bbox={bbox is not None}",
-          flush=True)
-    ref = orc.encode_frame(pos, attr, J, steps, tau, bbox=bbox, want_y=True)
-    g = gpu_encode(pos, attr, J, steps, tau, bbox)
-    check_encode(g, ref, J, steps, tau)
-    check_decode(g, ref, J, steps)
-    return g, ref
 
 
 GROUPED = synth.quant_steps(synth.STEPS_GROUPED)
