@@ -287,6 +287,79 @@ __device__ inline uint64_t lookback_wave(uint64_t *status, uint32_t stride, uint
     return acc;
 }
 
+// LDS scratch of lookback_block for a workgroup of NWV waves.
+template <int NWV>
+struct LbScratch {
+    uint32_t inc[NWV], zero[NWV];
+    uint64_t part[NWV];
+};
+
+// The look-back performed by a whole workgroup of NT threads: each round reads the NT nearest
+// predecessors at once (thread t reads tile j - t), so tiles whose predecessors have all
+// published their aggregates resolve in about one round per NT tiles instead of one per 64.
+// Every thread of the workgroup must call it (it contains barriers); the exclusive prefix is
+// returned to every thread.
+template <class Op, int NT>
+__device__ inline uint64_t lookback_block(uint64_t *status, uint32_t stride, uint32_t tile,
+                                          uint64_t agg, Ctrl *ctrl, LbScratch<NT / WAVE> &sc)
+{
+    constexpr int NWV = NT / WAVE;
+    const uint32_t tid = threadIdx.x, lane = lane_id(), w = tid / WAVE;
+    if (tile == 0) {
+        if (tid == 0) st_relaxed(&status[0], LB_INC | agg);
+        return Op::identity();
+    }
+    if (tid == 0) st_relaxed(&status[(size_t)tile * stride], LB_AGG | agg);
+    uint64_t acc = Op::identity();
+    int64_t j = (int64_t)tile - 1;  // nearest predecessor not yet combined (uniform)
+    uint32_t spins = 0;
+    while (true) {
+        const int64_t idx = j - (int64_t)tid;
+        const uint64_t v = idx >= 0 ? ld_relaxed(&status[(size_t)idx * stride]) : (LB_INC | Op::identity());
+        const uint32_t flag = (uint32_t)(v >> 62);
+        const uint64_t inc_m = __ballot(flag == 2), zero_m = __ballot(flag == 0);
+        if (lane == 0) {
+            sc.inc[w] = inc_m ? w * WAVE + (uint32_t)(__ffsll((long long)inc_m) - 1) : (uint32_t)NT;
+            sc.zero[w] = zero_m ? w * WAVE + (uint32_t)(__ffsll((long long)zero_m) - 1) : (uint32_t)NT;
+        }
+        __syncthreads();
+        uint32_t first_inc = NT, first_zero = NT;
+#pragma unroll
+        for (int ww = 0; ww < NWV; ++ww) {
+            first_inc = min(first_inc, sc.inc[ww]);
+            first_zero = min(first_zero, sc.zero[ww]);
+        }
+        const bool found = first_inc < (uint32_t)NT;
+        const uint32_t cut = found ? first_inc : (uint32_t)(NT - 1);
+        const bool blocked = first_zero <= cut;
+        // reads [0, cnt) are combined: up to the nearest inclusive one, or up to the first that
+        // is not ready
+        const uint32_t cnt = blocked ? first_zero : cut + 1;
+        const uint32_t wb = w * WAVE;
+        const uint32_t wcnt = cnt > wb ? min(cnt - wb, (uint32_t)WAVE) : 0u;
+        const uint64_t part = wcnt ? wave_combine_ordered<Op>(v & LB_VAL, wcnt) : Op::identity();
+        if (lane == 0) sc.part[w] = part;
+        __syncthreads();
+        uint64_t win = Op::identity();
+#pragma unroll
+        for (int ww = NWV - 1; ww >= 0; --ww) win = Op::combine(win, sc.part[ww]);  // older first
+        acc = Op::combine(win, acc);
+        j -= (int64_t)cnt;
+        __syncthreads();  // scratch is rewritten by the next round
+        if (!blocked) {
+            if (found) break;
+            continue;
+        }
+        if (++spins > SPIN_LIMIT) {
+            if (tid == 0) set_error(ctrl, GSC_ERR_INTERNAL);
+            break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+    }
+    if (tid == 0) st_relaxed(&status[(size_t)tile * stride], LB_INC | Op::combine(acc, agg));
+    return acc;
+}
+
 // 32-bit status words for the radix sort: [31:30] flag, [29:0] count (n < 2^30). A tile first
 // publishes its aggregate (tile 0 its inclusive count), then resolves its exclusive prefix.
 // Each thread reads WIN predecessors per round, so the look-back of the last of T tiles needs

@@ -33,8 +33,8 @@ constexpr int DEDUP_THREADS = 256;
 constexpr int DEDUP_KPT = 16;
 constexpr int DEDUP_TILE = DEDUP_THREADS * DEDUP_KPT;
 
-constexpr int OCC_THREADS = 256;
-constexpr int OCC_VPT = 8;              // voxels per thread
+constexpr int OCC_THREADS = 1024;        // 16 waves: the per-depth look-backs run side by side
+constexpr int OCC_VPT = 2;              // voxels per thread
 constexpr int OCC_TILE = OCC_THREADS * OCC_VPT;
 
 constexpr int DEC_TOP_CAP = 4096;       // octree levels this small are expanded in one workgroup

@@ -180,11 +180,11 @@ __global__ __launch_bounds__(64) void k_finish(TileMap m)
     if (fd.mode == MODE_ENCODE)  // the header's unused tail
         for (uint32_t b = sizeof(gsc_header) + threadIdx.x; b < GSC_HEADER_BYTES; b += blockDim.x)
             fd.stream[b] = 0;
+    __shared__ StreamGeom g;  // in LDS: indexed by depth, it would otherwise live in scratch
     if (threadIdx.x != 0) return;
     const uint32_t err = load_error(ctrl);
     uint64_t total = 0;
     if (fd.mode == MODE_ENCODE) {
-        StreamGeom g;
         stream_geom(ctrl, fd.J, fd.C, &g);
         total = g.total;
         gsc_header *h = reinterpret_cast<gsc_header *>(fd.stream);
@@ -496,7 +496,6 @@ __global__ __launch_bounds__(DEDUP_THREADS) void k_dedup(TileMap m)
     __shared__ uint32_t s_tile;
     __shared__ uint32_t s_tmp[DEDUP_THREADS / WAVE + 1];
     __shared__ uint32_t s_hist[32];
-    __shared__ uint32_t s_base;
     const uint32_t f = frame_of(m, blockIdx.x);
     const FrameDesc &fd = *m.fd[f];
     Ctrl *ctrl = fd.ctrl;
@@ -529,12 +528,9 @@ __global__ __launch_bounds__(DEDUP_THREADS) void k_dedup(TileMap m)
     }
     uint32_t tile_total;
     const uint32_t texcl = block_excl_scan<DEDUP_THREADS>((uint32_t)__popc(heads), s_tmp, &tile_total);
-    if (tid < WAVE) {
-        const uint32_t b = (uint32_t)lookback_wave<OpSum>(fd.dedup_status, 1, tile, tile_total, ctrl);
-        if (tid == 0) s_base = b;
-    }
-    __syncthreads();
-    uint32_t v = s_base + texcl;
+    __shared__ LbScratch<DEDUP_THREADS / WAVE> s_lb;
+    const uint32_t vbase = (uint32_t)lookback_block<OpSum, DEDUP_THREADS>(fd.dedup_status, 1, tile, tile_total, ctrl, s_lb);
+    uint32_t v = vbase + texcl;
 #pragma unroll
     for (int j = 0; j < DEDUP_KPT; ++j) {
         if ((heads >> j & 1u) && v < n) {
@@ -548,7 +544,7 @@ __global__ __launch_bounds__(DEDUP_THREADS) void k_dedup(TileMap m)
     }
     if (tid < 32 && s_hist[tid]) atomicAdd(&ctrl->hist_D[tid], s_hist[tid]);
     if (tid == 0 && base + DEDUP_TILE >= n) {
-        const uint32_t nv = s_base + tile_total;
+        const uint32_t nv = vbase + tile_total;
         ctrl->n_vox = nv;
         fd.vh[nv] = n;
     }
@@ -636,7 +632,8 @@ __global__ __launch_bounds__(OCC_THREADS) void k_occupancy(TileMap m)
         if (tid == 0) s_cnt[d] = total;
     }
     __syncthreads();
-    // one wave per depth (waves take depths w, w + 4, ...)
+    // one wave per depth (wave w takes depths w, w + 16, ...): the look-backs of all depths
+    // proceed side by side
     for (uint32_t d = tid / WAVE; d < J; d += OCC_THREADS / WAVE) {
         const uint32_t cnt = s_cnt[d];
         const uint32_t byte = cnt ? (s_bytes[d][(cnt - 1) >> 2] >> (8u * ((cnt - 1) & 3u))) & 0xFFu
@@ -647,8 +644,9 @@ __global__ __launch_bounds__(OCC_THREADS) void k_occupancy(TileMap m)
     }
     __shared__ uint64_t s_off[GSC_MAX_DEPTH + 1];
     __shared__ int s_fits;
+    __shared__ StreamGeom s_geom;
     if (tid == 0) {
-        StreamGeom g;
+        StreamGeom &g = s_geom;
         stream_geom(ctrl, J, fd.C, &g);
         for (uint32_t d = 0; d <= J; ++d) s_off[d] = g.occ_off[d];
         s_fits = g.total <= fd.stream_cap;
@@ -821,7 +819,6 @@ __global__ __launch_bounds__(DEC_THREADS) void k_dec_level(TileMap m, int d)
 {
     __shared__ uint32_t s_tile;
     __shared__ uint32_t s_tmp[DEC_THREADS / WAVE + 1];
-    __shared__ uint32_t s_base;
     const uint32_t f = frame_of(m, blockIdx.x);
     const FrameDesc &fd = *m.fd[f];
     Ctrl *ctrl = fd.ctrl;
@@ -852,12 +849,9 @@ __global__ __launch_bounds__(DEC_THREADS) void k_dec_level(TileMap m, int d)
     }
     uint32_t total;
     uint32_t w = block_excl_scan<DEC_THREADS>(cnt, s_tmp, &total);
-    if (tid < WAVE) {
-        const uint32_t b = (uint32_t)lookback_wave<OpSum>(fd.dec_status + fd.dec_status_off[d], 1, tile, total, ctrl);
-        if (tid == 0) s_base = b;
-    }
-    __syncthreads();
-    w += s_base;
+    __shared__ LbScratch<DEC_THREADS / WAVE> s_lb;
+    const uint32_t wbase = (uint32_t)lookback_block<OpSum, DEC_THREADS>(fd.dec_status + fd.dec_status_off[d], 1, tile, total, ctrl, s_lb);
+    w += wbase;
 #pragma unroll
     for (int i = 0; i < DEC_PPT; ++i) {
         const uint32_t p = s + tid * DEC_PPT + i;
@@ -876,7 +870,7 @@ __global__ __launch_bounds__(DEC_THREADS) void k_dec_level(TileMap m, int d)
         }
     }
     if (bad) set_error(ctrl, GSC_ERR_CORRUPT_STREAM);
-    if (tid == 0 && s + DEC_TILE >= M && s_base + total != Mn) set_error(ctrl, GSC_ERR_CORRUPT_STREAM);
+    if (tid == 0 && s + DEC_TILE >= M && wbase + total != Mn) set_error(ctrl, GSC_ERR_CORRUPT_STREAM);
 }
 
 hipError_t launch_dec_level(const TileMap &m, int d, hipStream_t s)

@@ -58,7 +58,7 @@ constexpr int PRE_BLOCK = PRE_TILES * PRE_THREADS;
 
 __global__ __launch_bounds__(PRE_BLOCK) void k_prelude(TileMap m, int k)
 {
-    __shared__ uint32_t s_blk, s_base;
+    __shared__ uint32_t s_blk;
     __shared__ uint32_t s_lvl_e[PRE_TILES];
     __shared__ uint64_t s_mask[PRE_TILES][NLVL][NCHUNK];
     __shared__ uint32_t s_cnt[PRE_TILES][SEG_N], s_fill[PRE_TILES][SEG_N];
@@ -173,12 +173,8 @@ __global__ __launch_bounds__(PRE_BLOCK) void k_prelude(TileMap m, int k)
     if (j == 0) s_tile_excl[g] = rank;
     __syncthreads();
     if (j == PRE_THREADS - 1) s_tile_cnt[g] = rank + (is_open ? 1u : 0u) - s_tile_excl[g];
-    if (tid < WAVE) {
-        const uint32_t b = (uint32_t)lookback_wave<OpSum>(lv.status, 1, blk, total, ctrl);
-        if (tid == 0) s_base = b;
-    }
-    __syncthreads();
-    const uint32_t base = s_base;
+    __shared__ LbScratch<PRE_BLOCK / WAVE> s_lb;
+    const uint32_t base = (uint32_t)lookback_block<OpSum, PRE_BLOCK>(lv.status, 1, blk, total, ctrl, s_lb);
     const uint32_t trank = rank - s_tile_excl[g];
     if (is_open) {
         if (trank < (uint32_t)OPEN_CAP) gp(lv.opos)[(size_t)tile * OPEN_CAP + trank] = (uint16_t)j;
@@ -434,13 +430,18 @@ __device__ inline int32_t quant1(float y, float step, float inv_step, double omt
 
 constexpr int UNROLL = 8;  // independent row loads in flight per thread
 
-// The channels are transformed in passes of at most CH4_MAX float4 chunks (32 channels), so a
-// tile's slice in LDS stays at 32 KB and several workgroups share a CU.
+// On the first tiling level (many tiles) the channels are transformed in passes of at most
+// CH4_MAX float4 chunks (32 channels), so a tile's slice in LDS stays at 32 KB and several
+// workgroups share a CU. The upper levels have few tiles, and their time is the chain of
+// per-level barriers of a tile: they take all channels (at most 64 KB) in one pass.
 constexpr uint32_t CH4_MAX = 8;
-__host__ __device__ inline uint32_t channel_passes(uint32_t C4) { return (C4 + CH4_MAX - 1) / CH4_MAX; }
-__host__ __device__ inline uint32_t pass_chunks(uint32_t C4)
+__host__ __device__ inline uint32_t channel_passes(uint32_t C4, int k)
 {
-    const uint32_t np = channel_passes(C4);
+    return k == 1 ? (C4 + CH4_MAX - 1) / CH4_MAX : 1u;
+}
+__host__ __device__ inline uint32_t pass_chunks(uint32_t C4, int k)
+{
+    const uint32_t np = channel_passes(C4, k);
     return (C4 + np - 1) / np;
 }
 
@@ -490,7 +491,7 @@ __global__ __launch_bounds__(RAHT_THREADS) void k_raht_fwd(TileMap m, int k)
         return;
     const uint32_t C = fd.C, C4 = fd.C4;
     const uint32_t tid = threadIdx.x;
-    const uint32_t NP = channel_passes(C4), CH4 = pass_chunks(C4);
+    const uint32_t NP = channel_passes(C4, k), CH4 = pass_chunks(C4, k);
     const Roles R(CH4);
     const uint32_t mlen = (uint32_t)ts.mlen;
     const bool encode1 = (k == 1 && fd.mode == MODE_ENCODE);
@@ -623,7 +624,7 @@ __global__ __launch_bounds__(RAHT_THREADS) void k_raht_inv(TileMap m, int k)
     if (!load_schedule(fd, ctrl, k, blockIdx.x - m.start[f], ts, s_rec, s_ab, s_lst, s_opos, s_idx))
         return;
     const uint32_t C = fd.C, C4 = fd.C4;
-    const uint32_t NP = channel_passes(C4), CH4 = pass_chunks(C4);
+    const uint32_t NP = channel_passes(C4, k), CH4 = pass_chunks(C4, k);
     const Roles R(CH4);
     const uint32_t mlen = (uint32_t)ts.mlen;
     level_masks(s_lst, s_lmask);
@@ -703,12 +704,12 @@ __global__ __launch_bounds__(RAHT_THREADS) void k_raht_inv(TileMap m, int k)
     }
 }
 
-size_t raht_lds_bytes(int C4) { return (size_t)RT * pass_chunks((uint32_t)C4) * sizeof(float4); }
+size_t raht_lds_bytes(int C4, int k) { return (size_t)RT * pass_chunks((uint32_t)C4, k) * sizeof(float4); }
 
 hipError_t launch_raht_fwd(const TileMap &m, int k, const RahtCfg &cfg, hipStream_t s)
 {
     const dim3 grid(m.start[m.F]), block(RAHT_THREADS);
-    const size_t lds = raht_lds_bytes(cfg.C4);
+    const size_t lds = raht_lds_bytes(cfg.C4, k);
     if (cfg.vec && cfg.pow2) hipLaunchKernelGGL((k_raht_fwd<true, true>), grid, block, lds, s, m, k);
     else if (cfg.vec) hipLaunchKernelGGL((k_raht_fwd<true, false>), grid, block, lds, s, m, k);
     else if (cfg.pow2) hipLaunchKernelGGL((k_raht_fwd<false, true>), grid, block, lds, s, m, k);
@@ -719,7 +720,7 @@ hipError_t launch_raht_fwd(const TileMap &m, int k, const RahtCfg &cfg, hipStrea
 hipError_t launch_raht_inv(const TileMap &m, int k, const RahtCfg &cfg, hipStream_t s)
 {
     const dim3 grid(m.start[m.F]), block(RAHT_THREADS);
-    const size_t lds = raht_lds_bytes(cfg.C4);
+    const size_t lds = raht_lds_bytes(cfg.C4, k);
     if (cfg.vec) hipLaunchKernelGGL((k_raht_inv<true>), grid, block, lds, s, m, k);
     else hipLaunchKernelGGL((k_raht_inv<false>), grid, block, lds, s, m, k);
     return hipGetLastError();
