@@ -56,6 +56,13 @@ __device__ inline uint32_t frame_of(const TileMap &m, uint32_t b)
     return f;
 }
 
+// Tile of this workgroup inside its frame. Kernels with a decoupled look-back use it directly
+// (no atomic tile counter: same-address atomics serialize at about 11 ns each, 11 us for a
+// thousand workgroups). A tile waits only on lower tiles, and workgroups of a frame are
+// dispatched to each XCD in index order, so the lowest unfinished tile is always resident;
+// every wait is also bounded by SPIN_LIMIT, which turns a stall into GSC_ERR_INTERNAL.
+__device__ inline uint32_t tile_index(const TileMap &m, uint32_t f) { return blockIdx.x - m.start[f]; }
+
 __device__ inline void set_error(Ctrl *c, uint32_t code)
 {
     atomicCAS(&c->error, 0u, code);
@@ -131,16 +138,15 @@ __device__ inline uint32_t group_excl_scan(uint32_t v, uint32_t *tmp, uint32_t *
 
 // ------------------------------------------------------------ decoupled look-back scan
 // A tile publishes its aggregate, walks back over its predecessors' status words until it
-// meets an inclusive prefix, then publishes its own inclusive prefix. Tiles take their index
-// from an atomic counter in launch order, so every tile waited on has already started and
-// never waits on a later one. A spin limit turns a (never expected) stall into an error.
+// meets an inclusive prefix, then publishes its own inclusive prefix. A tile is its workgroup's
+// index within the frame (tile_index): it never waits on a later tile, and a spin limit turns
+// a (never expected) stall into an error.
 //
 // A status word carries its value in the same atomic word as its flag, and a tile uses nothing
 // but those values, so relaxed device-scope atomics suffice (no cache-wide acquire/release).
-// The walk issues LB_WINDOW predecessor loads at a time: all tiles are resident together and
-// publish at about the same time, so the walk is long and its latency is what matters.
+// The walk issues several predecessor loads at a time (a window per thread, per wave or per
+// workgroup); one dependent round costs about half a microsecond.
 constexpr uint32_t SPIN_LIMIT = 1u << 22;
-constexpr int LB_WINDOW = 16;
 
 // 64-bit status word: [63:62] flag (0 none, 1 aggregate, 2 inclusive), [61:0] value.
 constexpr uint64_t LB_AGG = 1ull << 62;
@@ -180,55 +186,6 @@ struct OpSegOr {
         return (cnt << 8) | byte;
     }
 };
-
-// Exclusive prefix (under Op) of tile `tile`'s aggregate over status[0 .. tile-1]; status
-// words of consecutive tiles are `stride` words apart. Called by one thread per sequence.
-template <class Op>
-__device__ inline uint64_t lookback(uint64_t *status, uint32_t stride, uint32_t tile, uint64_t agg,
-                                    Ctrl *ctrl)
-{
-    if (tile == 0) {
-        st_relaxed(&status[0], LB_INC | agg);
-        return Op::identity();
-    }
-    st_relaxed(&status[(size_t)tile * stride], LB_AGG | agg);
-    uint64_t acc = Op::identity();
-    int64_t j = (int64_t)tile - 1;  // nearest predecessor not yet combined
-    uint32_t spins = 0;
-    bool done = false;
-    while (!done) {
-        uint64_t w[LB_WINDOW];
-#pragma unroll
-        for (int i = 0; i < LB_WINDOW; ++i)
-            w[i] = (j - i >= 0) ? ld_relaxed(&status[(size_t)(j - i) * stride]) : (LB_INC | Op::identity());
-        int used = 0;
-        bool stalled = false, stop = false;
-#pragma unroll
-        for (int i = 0; i < LB_WINDOW; ++i) {  // predicated (no break) so w stays in registers
-            const uint64_t flag = w[i] >> 62;
-            const bool take = !stop && flag != 0;
-            if (take) {
-                acc = Op::combine(w[i] & LB_VAL, acc);
-                ++used;
-            }
-            if (!stop && flag == 0) stalled = true;
-            if (!stop && flag != 1) {
-                done = done || flag == 2;
-                stop = true;
-            }
-        }
-        j -= used;
-        if (stalled) {
-            if (++spins > SPIN_LIMIT) {
-                set_error(ctrl, GSC_ERR_INTERNAL);
-                break;
-            }
-            __builtin_amdgcn_s_sleep(1);
-        }
-    }
-    st_relaxed(&status[(size_t)tile * stride], LB_INC | Op::combine(acc, agg));
-    return acc;
-}
 
 // Ordered combination of lanes [0, cnt) of a wave under Op, lane 0 being the newest value and
 // higher lanes older ones; the result is returned to every lane.

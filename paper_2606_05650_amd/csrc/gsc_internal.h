@@ -23,7 +23,7 @@ struct SortVariant {
     int kpt, win;
 };
 constexpr int SORT_VARIANTS = GSC_SORT_VARIANTS;
-constexpr SortVariant SORT_VARIANT[SORT_VARIANTS] = {{16, 32}, {8, 32}, {16, 64}, {16, 16}};
+constexpr SortVariant SORT_VARIANT[SORT_VARIANTS] = {{16, 16}, {8, 16}, {24, 16}, {16, 64}};
 constexpr int SORT_DEFAULT_VARIANT = 0;
 constexpr int SORT_KPT_MIN = 8;
 __host__ __device__ constexpr int sort_tile(int variant) { return SORT_THREADS * SORT_VARIANT[variant].kpt; }
@@ -41,6 +41,7 @@ constexpr int DEC_TOP_CAP = 4096;       // octree levels this small are expanded
 constexpr int DEC_THREADS = 256;
 constexpr int DEC_PPT = 8;              // parents per thread
 constexpr int DEC_TILE = DEC_THREADS * DEC_PPT;
+constexpr int DEC_CHUNK = 4096;         // children staged in LDS per round
 
 constexpr int RT = 256;                 // RAHT tile: entries per workgroup
 constexpr int RAHT_THREADS = 256;
@@ -62,7 +63,7 @@ struct Ctrl {
     uint32_t dec_start;          // decoder: first level handled by the per-level kernels
     uint32_t n_in;
     uint32_t bbox_ord[6];        // order-preserving uint of float: min x,y,z, max x,y,z
-    uint32_t tile_ctr[96];       // dynamic tile counters (see TC_*)
+    uint32_t tile_ctr[96];       // reserved
     uint32_t hist_D[32];         // voxels whose new-node depth is D, D = 0..J
     uint32_t lvl_n[MAXK + 2];    // sizes of the RAHT entry sequences, index k = 1..MAXK+1
     uint32_t level_sizes[32];    // |L_d|
@@ -75,12 +76,6 @@ struct Ctrl {
 constexpr size_t CTRL_BYTES = 16384;
 static_assert(sizeof(Ctrl) <= CTRL_BYTES, "control block too large");
 
-// dynamic tile counter slots
-constexpr int TC_SORT = 0;        // + pass
-constexpr int TC_DEDUP = 8;
-constexpr int TC_OCC = 9;
-constexpr int TC_PRELUDE = 10;    // + level k (1..MAXK)
-constexpr int TC_DEC = 40;        // + octree level d (0..20)
 
 // ------------------------------------------------------------- kernel-side frame view
 enum : uint32_t {
@@ -261,10 +256,11 @@ __host__ __device__ inline bool make_layout(int64_t n, int J, int C, Layout *L)
     if (L->cap[K] > (uint32_t)RT) return false;
     L->K = K;
     size_t off = DESC_OFF + DESC_BYTES;
-    // zero region: every lookback status word and nothing else
-    L->zero_off = off;
+    // the sort's status words (zeroed by the voxelize kernel of an encode, which precedes the
+    // sort), then the zero region: every other look-back status word and nothing else
     L->sort_status = off;
     off = align_up(off + (size_t)L->P * L->sort_tiles * SORT_BINS * 4, 256);
+    L->zero_off = off;
     L->dedup_status = off;
     off = align_up(off + (size_t)L->dedup_tiles * 8, 256);
     L->occ_status = off;

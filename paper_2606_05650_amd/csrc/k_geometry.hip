@@ -45,72 +45,29 @@ __global__ __launch_bounds__(256) void k_setup(SetupArgs a)
     if (fa.info)
         for (uint32_t i = threadIdx.x; i < GSC_INFO_WORDS; i += blockDim.x) fa.info[i] = 0;
     __syncthreads();
-    if (threadIdx.x != 0) return;
-    if (a.keep) {
-        if (!s_prev_ok) set_error(ctrl, GSC_ERR_INVALID_ARG);
-    } else {
-        for (int a3 = 0; a3 < 3; ++a3) ctrl->bbox_ord[a3] = BBOX_SENTINEL_MIN;
-        ctrl->n_in = fa.n;
-        if (a.mode == MODE_FWD_F32 || a.mode == MODE_ADJ_F32) ctrl->n_vox = fa.n;
-    }
-
+    const uint32_t t = threadIdx.x;
     const Layout &L = s_L;
-    fd->n = fa.n;
-    fd->J = a.J;
-    fd->C = a.C;
-    fd->C4 = (a.C + 3) / 4;
-    fd->P = L.P;
-    fd->mode = a.mode;
-    fd->ste = (a.keep && !s_prev_ok) ? STE_NONE : a.ste;
-    fd->bbox_mode = a.bbox_mode;
-    fd->tau = a.tau;
-    for (int i = 0; i < 3; ++i) fd->bbox_min[i] = a.bbox_min[i];
-    fd->cell = a.cell;
-    uint64_t pow2 = 0;
-    for (uint32_t c = 0; c < GSC_MAX_CHANNELS; ++c) {
-        const float st = c < a.C ? a.step[c] : 1.0f;
-        fd->step[c] = st;
-        int e;
-        const float mant = frexpf(st, &e);
-        const bool p2 = (mant == 0.5f);
-        fd->inv_step[c] = p2 ? 1.0f / st : 0.0f;
-        if (p2) pow2 |= 1ull << c;
+    if (t == 0) {
+        if (a.keep) {
+            if (!s_prev_ok) set_error(ctrl, GSC_ERR_INVALID_ARG);
+        } else {
+            for (int a3 = 0; a3 < 3; ++a3) ctrl->bbox_ord[a3] = BBOX_SENTINEL_MIN;
+            ctrl->n_in = fa.n;
+            if (a.mode == MODE_FWD_F32 || a.mode == MODE_ADJ_F32) ctrl->n_vox = fa.n;
+        }
     }
-    fd->pow2_steps = pow2;
-    fd->ctrl = ctrl;
-    fd->zero_begin = fa.ws + L.zero_off;
-    fd->zero_bytes = L.zero_bytes;
-    fd->pos = fa.pos;
-    fd->attr = fa.attr;
-    fd->stream = fa.stream;
-    fd->stream_cap = fa.stream_cap;
-    fd->coef_f32 = fa.coef_f32;
-    fd->codes_out = fa.codes_out;
-    fd->in_stream = fa.in_stream;
-    fd->in_bytes = fa.in_bytes;
-    fd->pos_out = fa.pos_out;
-    fd->vox_out = fa.vox_out;
-    fd->attr_out = fa.attr_out;
-    fd->info = fa.info;
-    fd->codes_in = fa.codes_in;
-    fd->aref = fa.aref;
-    fd->grad_add = fa.grad_add;
-    fd->keys_a = reinterpret_cast<uint64_t *>(fa.ws + L.keys_a);
-    fd->keys_b = reinterpret_cast<uint64_t *>(fa.ws + L.keys_b);
-    fd->vals_a = reinterpret_cast<uint32_t *>(fa.ws + L.vals_a);
-    fd->vals_b = reinterpret_cast<uint32_t *>(fa.ws + L.vals_b);
-    fd->leaf = reinterpret_cast<uint64_t *>(fa.ws + L.leaf);
-    fd->vh = reinterpret_cast<uint32_t *>(fa.ws + L.vh);
-    fd->sort_status = reinterpret_cast<uint32_t *>(fa.ws + L.sort_status);
-    fd->dedup_status = reinterpret_cast<uint64_t *>(fa.ws + L.dedup_status);
-    fd->occ_status = reinterpret_cast<uint64_t *>(fa.ws + L.occ_status);
-    fd->dec_status = reinterpret_cast<uint64_t *>(fa.ws + L.dec_status);
-    for (int d = 0; d <= GSC_MAX_DEPTH; ++d) fd->dec_status_off[d] = L.dec_status_off[d];
-    fd->sort_tiles = L.sort_tiles;
-    fd->dedup_tiles = L.dedup_tiles;
-    fd->occ_tiles = L.occ_tiles;
-    fd->K = L.K;
-    for (uint32_t k = 0; k <= MAXK; ++k) {
+    // the descriptor, built by several threads at once: wave 0 the per-channel steps, threads
+    // 64.. the tiling levels, 96.. the octree-decoding status offsets, 128 the scalars
+    if (t < GSC_MAX_CHANNELS) {
+        const float st = t < a.C ? a.step[t] : 1.0f;
+        fd->step[t] = st;
+        int e;
+        const bool p2 = frexpf(st, &e) == 0.5f;
+        fd->inv_step[t] = p2 ? 1.0f / st : 0.0f;
+        const uint64_t pow2 = __ballot(p2);
+        if (t == 0) fd->pow2_steps = pow2;
+    } else if (t >= 64 && t <= 64 + MAXK) {
+        const uint32_t k = t - 64;
         RahtLevel &lv = fd->lv[k];
         if (k >= 1 && k <= L.K) {
             lv.s_idx = reinterpret_cast<uint32_t *>(fa.ws + L.s_idx[k]);
@@ -137,6 +94,52 @@ __global__ __launch_bounds__(256) void k_setup(SetupArgs a)
             lv.tiles = 0;
             lv.cap = 0;
         }
+    } else if (t >= 96 && t <= 96 + GSC_MAX_DEPTH) {
+        fd->dec_status_off[t - 96] = L.dec_status_off[t - 96];
+    } else if (t == 128) {
+        fd->n = fa.n;
+        fd->J = a.J;
+        fd->C = a.C;
+        fd->C4 = (a.C + 3) / 4;
+        fd->P = L.P;
+        fd->mode = a.mode;
+        fd->ste = (a.keep && !s_prev_ok) ? STE_NONE : a.ste;
+        fd->bbox_mode = a.bbox_mode;
+        fd->tau = a.tau;
+        for (int i = 0; i < 3; ++i) fd->bbox_min[i] = a.bbox_min[i];
+        fd->cell = a.cell;
+        fd->ctrl = ctrl;
+        fd->zero_begin = fa.ws + L.zero_off;
+        fd->zero_bytes = L.zero_bytes;
+        fd->pos = fa.pos;
+        fd->attr = fa.attr;
+        fd->stream = fa.stream;
+        fd->stream_cap = fa.stream_cap;
+        fd->coef_f32 = fa.coef_f32;
+        fd->codes_out = fa.codes_out;
+        fd->in_stream = fa.in_stream;
+        fd->in_bytes = fa.in_bytes;
+        fd->pos_out = fa.pos_out;
+        fd->vox_out = fa.vox_out;
+        fd->attr_out = fa.attr_out;
+        fd->info = fa.info;
+        fd->codes_in = fa.codes_in;
+        fd->aref = fa.aref;
+        fd->grad_add = fa.grad_add;
+        fd->keys_a = reinterpret_cast<uint64_t *>(fa.ws + L.keys_a);
+        fd->keys_b = reinterpret_cast<uint64_t *>(fa.ws + L.keys_b);
+        fd->vals_a = reinterpret_cast<uint32_t *>(fa.ws + L.vals_a);
+        fd->vals_b = reinterpret_cast<uint32_t *>(fa.ws + L.vals_b);
+        fd->leaf = reinterpret_cast<uint64_t *>(fa.ws + L.leaf);
+        fd->vh = reinterpret_cast<uint32_t *>(fa.ws + L.vh);
+        fd->sort_status = reinterpret_cast<uint32_t *>(fa.ws + L.sort_status);
+        fd->dedup_status = reinterpret_cast<uint64_t *>(fa.ws + L.dedup_status);
+        fd->occ_status = reinterpret_cast<uint64_t *>(fa.ws + L.occ_status);
+        fd->dec_status = reinterpret_cast<uint64_t *>(fa.ws + L.dec_status);
+        fd->sort_tiles = L.sort_tiles;
+        fd->dedup_tiles = L.dedup_tiles;
+        fd->occ_tiles = L.occ_tiles;
+        fd->K = L.K;
     }
 }
 
@@ -169,55 +172,78 @@ __device__ inline void stream_geom(const Ctrl *ctrl, uint32_t J, uint32_t C, Str
     g->total = g->coef_offset + (uint64_t)ctrl->n_vox * C * 4;
 }
 
-// One block per frame: copy the device status to the info words, and (encode) write the
-// stream header.
+// One block of 64 threads per frame: copy the device status to the info words, and (encode)
+// write the stream header. The counters are loaded by all threads at once and the header
+// fields written in parallel: a single thread would pay one memory latency per dependent step.
 __global__ __launch_bounds__(64) void k_finish(TileMap m)
 {
     const uint32_t f = blockIdx.x;
     if (f >= m.F) return;
     const FrameDesc &fd = *m.fd[f];
     Ctrl *ctrl = fd.ctrl;
-    if (fd.mode == MODE_ENCODE)  // the header's unused tail
-        for (uint32_t b = sizeof(gsc_header) + threadIdx.x; b < GSC_HEADER_BYTES; b += blockDim.x)
-            fd.stream[b] = 0;
+    const uint32_t t = threadIdx.x;
+    const uint32_t J = fd.J, K = fd.K;
+    __shared__ uint32_t s_hist[GSC_MAX_DEPTH + 2], s_lvl[MAXK + 2];
+    __shared__ uint32_t s_err, s_nv;
     __shared__ StreamGeom g;  // in LDS: indexed by depth, it would otherwise live in scratch
-    if (threadIdx.x != 0) return;
-    const uint32_t err = load_error(ctrl);
+    if (t <= GSC_MAX_DEPTH) s_hist[t] = t <= J ? ctrl->hist_D[t] : 0u;
+    if (t <= MAXK) s_lvl[t] = t <= K ? ctrl->lvl_n[t] : 0u;
+    if (t == 0) {
+        s_err = load_error(ctrl);
+        s_nv = ctrl->n_vox;
+    }
+    __syncthreads();
+    const uint32_t err = s_err, nv = s_nv;
     uint64_t total = 0;
     if (fd.mode == MODE_ENCODE) {
-        stream_geom(ctrl, fd.J, fd.C, &g);
+        if (t == 0) {
+            uint32_t run = 0;
+            uint64_t off = GSC_HEADER_BYTES;
+            for (uint32_t d = 0; d <= J; ++d) {
+                run += s_hist[d];
+                g.level_sizes[d] = run;
+                g.occ_off[d] = off;
+                if (d < J) off += run;
+            }
+            g.occ_bytes = off - GSC_HEADER_BYTES;
+            g.coef_offset = align_up(off, 256);
+            g.total = g.coef_offset + (uint64_t)nv * fd.C * 4;
+        }
+        __syncthreads();
         total = g.total;
         gsc_header *h = reinterpret_cast<gsc_header *>(fd.stream);
-        h->magic = GSC_MAGIC;
-        h->version = GSC_VERSION;
-        h->J = fd.J;
-        h->C = fd.C;
-        h->n_in = fd.n;
-        h->n_vox = ctrl->n_vox;
-        for (int d = 0; d < 22; ++d) h->level_sizes[d] = d <= (int)fd.J ? g.level_sizes[d] : 0u;
-        h->error = err;
-        h->reserved0 = 0;
-        for (int a = 0; a < 3; ++a) h->bbox_min[a] = ctrl->bbox_min[a];
-        h->cell = ctrl->cell;
-        for (int c = 0; c < 64; ++c) h->quant_step[c] = c < (int)fd.C ? fd.step[c] : 0.0f;
-        h->tau = fd.tau;
-        h->reserved1 = 0;
-        h->occ_offset = GSC_HEADER_BYTES;
-        h->occ_bytes = g.occ_bytes;
-        h->coef_offset = g.coef_offset;
-        h->coef_bytes = (uint64_t)ctrl->n_vox * fd.C * 4;
-        h->total_bytes = g.total;
-        // zero the padding between the occupancy bytes and the coefficients
-        for (uint64_t b = GSC_HEADER_BYTES + g.occ_bytes; b < g.coef_offset; ++b) fd.stream[b] = 0;
+        for (uint32_t b = sizeof(gsc_header) + t; b < GSC_HEADER_BYTES; b += 64) fd.stream[b] = 0;
+        for (uint64_t b = GSC_HEADER_BYTES + g.occ_bytes + t; b < g.coef_offset; b += 64) fd.stream[b] = 0;
+        if (t < 22) h->level_sizes[t] = t <= J ? g.level_sizes[t] : 0u;
+        h->quant_step[t] = t < fd.C ? fd.step[t] : 0.0f;
+        if (t < 3) h->bbox_min[t] = ctrl->bbox_min[t];
+        if (t == 0) {
+            h->magic = GSC_MAGIC;
+            h->version = GSC_VERSION;
+            h->J = J;
+            h->C = fd.C;
+            h->n_in = fd.n;
+            h->n_vox = nv;
+            h->error = err;
+            h->reserved0 = 0;
+            h->cell = ctrl->cell;
+            h->tau = fd.tau;
+            h->reserved1 = 0;
+            h->occ_offset = GSC_HEADER_BYTES;
+            h->occ_bytes = g.occ_bytes;
+            h->coef_offset = g.coef_offset;
+            h->coef_bytes = (uint64_t)nv * fd.C * 4;
+            h->total_bytes = g.total;
+        }
     }
-    if (fd.info) {
+    if (fd.info && t == 0) {
         fd.info[0] = (int32_t)err;
-        fd.info[1] = (int32_t)ctrl->n_vox;
+        fd.info[1] = (int32_t)nv;
         fd.info[2] = (int32_t)(uint32_t)(total & 0xFFFFFFFFu);
         fd.info[3] = (int32_t)(uint32_t)(total >> 32);
         uint32_t used = 0;
-        for (uint32_t k = 1; k <= fd.K; ++k)
-            if (k == 1 ? ctrl->n_vox >= 1 : ctrl->lvl_n[k] >= 2) used = k;
+        for (uint32_t k = 1; k <= K; ++k)
+            if (k == 1 ? nv >= 1 : s_lvl[k] >= 2) used = k;
         fd.info[4] = (int32_t)used;
     }
 }
@@ -241,40 +267,82 @@ __device__ inline float ord2f(uint32_t o)
 }
 
 constexpr int BBOX_THREADS = 256;
-constexpr int BBOX_PPB = 8192;  // points per block
+constexpr int BBOX_F4 = 16;  // float4 chunks per thread, all loaded before any is used
+constexpr uint32_t BBOX_CHUNKS = BBOX_THREADS * BBOX_F4;  // per workgroup
 
+// The positions are read as one flat array of 3n floats in float4 chunks (chunk q holds the
+// coordinates 4q .. 4q+3, whose axes are (q + i) mod 3 since 4 = 1 mod 3); each thread issues
+// all of its loads at once, so a workgroup costs one load latency.
 __global__ __launch_bounds__(BBOX_THREADS) void k_bbox(TileMap m)
 {
     const uint32_t f = frame_of(m, blockIdx.x);
     const FrameDesc &fd = *m.fd[f];
     Ctrl *ctrl = fd.ctrl;
     const uint32_t b = blockIdx.x - m.start[f];
-    const uint32_t n = fd.n;
+    const uint64_t nf = 3ull * fd.n;      // coordinates
+    const uint64_t nq = nf / 4;            // whole float4 chunks
+    const GAS float *pos = gp(fd.pos);
+    const bool vec = ((uintptr_t)fd.pos & 15u) == 0;
     float mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
     bool bad = false;
-    const uint32_t p0 = b * BBOX_PPB, p1 = min(n, p0 + BBOX_PPB);
-    for (uint32_t i = p0 + threadIdx.x; i < p1; i += BBOX_THREADS) {
+    const uint64_t q0 = (uint64_t)b * BBOX_CHUNKS + threadIdx.x;
+    float4 v[BBOX_F4];
+#pragma unroll
+    for (int r = 0; r < BBOX_F4; ++r) {
+        const uint64_t q = q0 + (uint64_t)r * BBOX_THREADS;
+        const uint64_t qc = q < nq ? q : (nq ? nq - 1 : 0);  // clamped: every load in bounds
+        if (nq == 0) {
+            v[r] = make_float4(0.f, 0.f, 0.f, 0.f);
+        } else if (vec) {
+            v[r] = gload4(pos + 4 * qc);
+        } else {
+            v[r] = make_float4(pos[4 * qc], pos[4 * qc + 1], pos[4 * qc + 2], pos[4 * qc + 3]);
+        }
+    }
+    // axes by selects on compile-time indices: a per-element axis index into mn/mx would move
+    // them to memory
+#pragma unroll
+    for (int r = 0; r < BBOX_F4; ++r) {
+        const uint64_t q = q0 + (uint64_t)r * BBOX_THREADS;
+        const bool ok = q < nq;
+        const uint32_t a0 = (uint32_t)(q % 3u);
+        const float e[4] = {v[r].x, v[r].y, v[r].z, v[r].w};
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            bad |= ok && !isfinite(e[i]);
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const bool mine = ok && (a0 + (uint32_t)i) % 3u == (uint32_t)a;
+                mn[a] = fminf(mn[a], mine ? e[i] : INFINITY);
+                mx[a] = fmaxf(mx[a], mine ? e[i] : -INFINITY);
+            }
+        }
+    }
+    // the last nf mod 4 coordinates
+    if (b == 0 && threadIdx.x < (uint32_t)(nf - 4 * nq)) {
+        const uint64_t k = 4 * nq + threadIdx.x;
+        const float e = pos[k];
+        const uint32_t ak = (uint32_t)(k % 3u);
+        bad |= !isfinite(e);
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            const float v = gp(fd.pos)[(size_t)i * 3 + a];
-            bad |= !isfinite(v);
-            mn[a] = fminf(mn[a], v);
-            mx[a] = fmaxf(mx[a], v);
+            mn[a] = fminf(mn[a], ak == (uint32_t)a ? e : INFINITY);
+            mx[a] = fmaxf(mx[a], ak == (uint32_t)a ? e : -INFINITY);
         }
     }
     if (__ballot(bad) && lane_id() == 0) set_error(ctrl, GSC_ERR_INVALID_ARG);
     __shared__ uint32_t s_o[6];
     if (threadIdx.x < 6) s_o[threadIdx.x] = threadIdx.x < 3 ? 0xFFFFFFFFu : 0u;
     __syncthreads();
-    if (p0 + threadIdx.x < p1) {
-        for (int a = 0; a < 3; ++a) {
+    for (int a = 0; a < 3; ++a) {
+        if (mn[a] <= mx[a]) {  // this thread saw a coordinate of axis a
             atomicMin(&s_o[a], f2ord(mn[a]));
             atomicMax(&s_o[3 + a], f2ord(mx[a]));
         }
     }
     __syncthreads();
-    if (threadIdx.x < 3 && p0 < p1) atomicMin(&ctrl->bbox_ord[threadIdx.x], s_o[threadIdx.x]);
-    else if (threadIdx.x >= 3 && threadIdx.x < 6 && p0 < p1)
+    if (threadIdx.x < 3 && s_o[threadIdx.x] != 0xFFFFFFFFu) atomicMin(&ctrl->bbox_ord[threadIdx.x], s_o[threadIdx.x]);
+    else if (threadIdx.x >= 3 && threadIdx.x < 6 && s_o[threadIdx.x - 3] != 0xFFFFFFFFu)
         atomicMax(&ctrl->bbox_ord[threadIdx.x], s_o[threadIdx.x]);
 }
 
@@ -283,7 +351,7 @@ hipError_t launch_bbox(const TileMap &m, hipStream_t s)
     hipLaunchKernelGGL(k_bbox, dim3(m.start[m.F]), dim3(BBOX_THREADS), 0, s, m);
     return hipGetLastError();
 }
-uint32_t bbox_blocks(uint32_t n) { return n ? ceil_div(n, BBOX_PPB) : 1u; }
+uint32_t bbox_blocks(uint32_t n) { return n ? (uint32_t)ceil_div(ceil_div(3ull * n, 4ull), (uint64_t)BBOX_CHUNKS) : 1u; }
 
 // ===================================================== voxelize + Morton + digit histograms
 // Voxelization (Sec. 2.1, Sec. 2.2 step (a)): v = min(2^J - 1, floor((p - min) / cell)) per axis
@@ -291,7 +359,7 @@ uint32_t bbox_blocks(uint32_t n) { return n ? ceil_div(n, BBOX_PPB) : 1u; }
 // has no extent), then the Morton code of (x, y, z). The histograms of every radix digit of
 // the codes are accumulated for the sort passes.
 constexpr int VOX_THREADS = 256;
-constexpr int VOX_PPT = 4;
+constexpr int VOX_PPT = 16;  // few workgroups: each merges its digit histograms into the global ones
 constexpr int VOX_TILE = VOX_THREADS * VOX_PPT;
 
 __global__ __launch_bounds__(VOX_THREADS) void k_voxelize(TileMap m)
@@ -325,18 +393,33 @@ __global__ __launch_bounds__(VOX_THREADS) void k_voxelize(TileMap m)
         for (int a = 0; a < 3; ++a) ctrl->bbox_min[a] = lo[a];
         ctrl->cell = cell;
     }
+    {   // this workgroup's share of the sort's look-back status words (they lie outside the
+        // region the setup kernel zeroes, since only an encode sorts)
+        const uint32_t nb = n ? (n + VOX_TILE - 1) / VOX_TILE : 1u;
+        const uint64_t nq = (uint64_t)P * fd.sort_tiles * SORT_BINS / 4;
+        uint4 *z = reinterpret_cast<uint4 *>(fd.sort_status);
+        for (uint64_t i = (uint64_t)b * VOX_THREADS + threadIdx.x; i < nq; i += (uint64_t)nb * VOX_THREADS)
+            z[i] = make_uint4(0, 0, 0, 0);
+    }
     __syncthreads();
     const double top = (double)((1u << J) - 1u);
     const uint32_t p0 = b * VOX_TILE;
+    // every coordinate of the thread's points is loaded before any is used (clamped indices)
+    float c[VOX_PPT][3];
+#pragma unroll
+    for (int r = 0; r < VOX_PPT; ++r) {
+        const uint32_t i = min(p0 + r * VOX_THREADS + threadIdx.x, n ? n - 1 : 0u);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) c[r][a] = n ? gp(fd.pos)[(size_t)i * 3 + a] : 0.0f;
+    }
 #pragma unroll
     for (int r = 0; r < VOX_PPT; ++r) {
         const uint32_t i = p0 + r * VOX_THREADS + threadIdx.x;
-        if (i >= n) break;
+        if (i >= n) continue;
         uint32_t v[3];
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            const double p = (double)gp(fd.pos)[(size_t)i * 3 + a];
-            double t = floor(__ddiv_rn(__dsub_rn(p, lo[a]), cell));
+            double t = floor(__ddiv_rn(__dsub_rn((double)c[r][a], lo[a]), cell));
             t = t < 0.0 ? 0.0 : (t > top ? top : t);
             v[a] = (uint32_t)t;
         }
@@ -395,7 +478,7 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_pass(TileMap m, int pass)
     if (load_error(ctrl)) return;
     const uint32_t n = fd.n;
     const uint32_t tid = threadIdx.x, w = tid / WAVE, lane = lane_id();
-    if (tid == 0) s_tile = atomicAdd(&ctrl->tile_ctr[TC_SORT + pass], 1u);
+    if (tid == 0) s_tile = tile_index(m, f);
     for (uint32_t i = tid; i < NW * SORT_BINS; i += SORT_THREADS) (&s_wcnt[0][0])[i] = 0;
     __syncthreads();
     const uint32_t tile = s_tile;
@@ -493,53 +576,74 @@ hipError_t launch_sort_pass(const TileMap &m, int pass, int variant, hipStream_t
 // every level size follows: |L_d| = #{v : D_v <= d}.
 __global__ __launch_bounds__(DEDUP_THREADS) void k_dedup(TileMap m)
 {
+    constexpr int NW = DEDUP_THREADS / WAVE;
+    static_assert(DEDUP_KPT * NW == WAVE, "one wave scans the (row, wave) head counts");
     __shared__ uint32_t s_tile;
-    __shared__ uint32_t s_tmp[DEDUP_THREADS / WAVE + 1];
+    __shared__ uint64_t s_k[DEDUP_TILE + 1];   // s_k[1 + i] = key base + i; s_k[0] = key base - 1
+    __shared__ uint32_t s_cnt[DEDUP_KPT * NW + 1];
     __shared__ uint32_t s_hist[32];
     const uint32_t f = frame_of(m, blockIdx.x);
     const FrameDesc &fd = *m.fd[f];
     Ctrl *ctrl = fd.ctrl;
     if (load_error(ctrl)) return;
     const uint32_t n = fd.n, J = fd.J;
-    const uint32_t tid = threadIdx.x;
-    if (tid == 0) s_tile = atomicAdd(&ctrl->tile_ctr[TC_DEDUP], 1u);
+    const uint32_t tid = threadIdx.x, w = tid / WAVE, lane = lane_id();
+    if (tid == 0) s_tile = tile_index(m, f);
     if (tid < 32) s_hist[tid] = 0;
     __syncthreads();
     const uint32_t tile = s_tile;
     const uint32_t base = tile * DEDUP_TILE;
     if (base >= n) return;
+    const uint32_t len = min((uint32_t)DEDUP_TILE, n - base);
     const GAS uint64_t *K = gp((fd.P & 1) ? fd.keys_b : fd.keys_a);  // output of the last sort pass
-    const uint32_t p0 = base + tid * DEDUP_KPT;
-    uint32_t heads = 0;  // bit j: position p0 + j starts a voxel
-    uint64_t prev = (p0 > 0 && p0 < n) ? K[p0 - 1] : 0ull;
+    // striped (coalesced) loads: position i = r * DEDUP_THREADS + tid
 #pragma unroll
-    for (int j = 0; j < DEDUP_KPT; ++j) {
-        const uint32_t p = p0 + j;
-        if (p < n) {
-            const uint64_t k = K[p];
-            const bool h = (p == 0) || (k != prev);
-            if (h) {
-                heads |= 1u << j;
-                const uint32_t D = p == 0 ? 0u : J - (uint32_t)msb64(prev ^ k) / 3u;
-                atomicAdd(&s_hist[D], 1u);
-            }
-            prev = k;
-        }
+    for (int r = 0; r < DEDUP_KPT; ++r) {
+        const uint32_t i = r * DEDUP_THREADS + tid;
+        s_k[1 + i] = K[base + min(i, len - 1)];
     }
-    uint32_t tile_total;
-    const uint32_t texcl = block_excl_scan<DEDUP_THREADS>((uint32_t)__popc(heads), s_tmp, &tile_total);
+    if (tid == 0) s_k[0] = base > 0 ? K[base - 1] : 0ull;
+    __syncthreads();
+    // heads: a position starts a voxel when its key differs from the previous one
+    uint32_t hbits = 0;
+#pragma unroll
+    for (int r = 0; r < DEDUP_KPT; ++r) {
+        const uint32_t i = r * DEDUP_THREADS + tid;
+        const uint64_t k = s_k[1 + i], pk = s_k[i];
+        const bool first = base + i == 0;
+        const bool h = i < len && (first || k != pk);
+        if (h) {
+            hbits |= 1u << r;
+            const uint32_t D = first ? 0u : J - (uint32_t)msb64(pk ^ k) / 3u;
+            atomicAdd(&s_hist[D], 1u);
+        }
+        const uint64_t bal = __ballot(h);
+        if (lane == 0) s_cnt[r * NW + w] = (uint32_t)__popcll(bal);
+    }
+    __syncthreads();
+    if (w == 0) {  // (row, wave) counts in position order -> exclusive offsets
+        const uint32_t c = s_cnt[lane];
+        const uint32_t inc = wave_incl_scan(c);
+        s_cnt[lane] = inc - c;
+        if (lane == WAVE - 1) s_cnt[WAVE] = inc;
+    }
+    __syncthreads();
+    const uint32_t tile_total = s_cnt[WAVE];
     __shared__ LbScratch<DEDUP_THREADS / WAVE> s_lb;
     const uint32_t vbase = (uint32_t)lookback_block<OpSum, DEDUP_THREADS>(fd.dedup_status, 1, tile, tile_total, ctrl, s_lb);
-    uint32_t v = vbase + texcl;
 #pragma unroll
-    for (int j = 0; j < DEDUP_KPT; ++j) {
-        if ((heads >> j & 1u) && v < n) {
-            const uint32_t p = p0 + j;
-            const uint64_t k = K[p];
-            gp(fd.leaf)[v] = k;
-            if (fd.codes_out) gp(fd.codes_out)[v] = k;
-            gp(fd.vh)[v] = p;
-            ++v;
+    for (int r = 0; r < DEDUP_KPT; ++r) {
+        const bool h = (hbits >> r) & 1u;
+        const uint64_t bal = __ballot(h);
+        if (h) {
+            const uint32_t i = r * DEDUP_THREADS + tid;
+            const uint32_t v = vbase + s_cnt[r * NW + w] + (uint32_t)__popcll(bal & lanemask_lt());
+            if (v < n) {
+                const uint64_t k = s_k[1 + i];
+                gp(fd.leaf)[v] = k;
+                if (fd.codes_out) gp(fd.codes_out)[v] = k;
+                gp(fd.vh)[v] = base + i;
+            }
         }
     }
     if (tid < 32 && s_hist[tid]) atomicAdd(&ctrl->hist_D[tid], s_hist[tid]);
@@ -580,7 +684,7 @@ __global__ __launch_bounds__(OCC_THREADS) void k_occupancy(TileMap m)
     if (load_error(ctrl)) return;
     const uint32_t J = fd.J, nv = ctrl->n_vox;
     const uint32_t tid = threadIdx.x;
-    if (tid == 0) s_tile = atomicAdd(&ctrl->tile_ctr[TC_OCC], 1u);
+    if (tid == 0) s_tile = tile_index(m, f);
     for (uint32_t i = tid; i < GSC_MAX_DEPTH * (OCC_TILE / 4); i += OCC_THREADS)
         (&s_bytes[0][0])[i] = 0;
     if (tid < GSC_MAX_DEPTH) s_carry[tid] = 0;
@@ -817,8 +921,10 @@ hipError_t launch_dec_top(const TileMap &m, hipStream_t s)
 // Expansion of one level d >= the top kernel's stopping level, for all parents at once.
 __global__ __launch_bounds__(DEC_THREADS) void k_dec_level(TileMap m, int d)
 {
+    constexpr int NW = DEC_THREADS / WAVE;
+    static_assert(DEC_PPT * NW <= WAVE, "one wave scans the (row, wave) child counts");
     __shared__ uint32_t s_tile;
-    __shared__ uint32_t s_tmp[DEC_THREADS / WAVE + 1];
+    __shared__ uint32_t s_cnt[WAVE + 1];
     const uint32_t f = frame_of(m, blockIdx.x);
     const FrameDesc &fd = *m.fd[f];
     Ctrl *ctrl = fd.ctrl;
@@ -827,8 +933,8 @@ __global__ __launch_bounds__(DEC_THREADS) void k_dec_level(TileMap m, int d)
     const gsc_header *h = reinterpret_cast<const gsc_header *>(fd.in_stream);
     const uint32_t J = fd.J;
     const uint32_t M = ctrl->level_sizes[d], Mn = ctrl->level_sizes[d + 1];
-    const uint32_t tid = threadIdx.x;
-    if (tid == 0) s_tile = atomicAdd(&ctrl->tile_ctr[TC_DEC + d], 1u);
+    const uint32_t tid = threadIdx.x, w = tid / WAVE, lane = lane_id();
+    if (tid == 0) s_tile = tile_index(m, f);
     __syncthreads();
     const uint32_t tile = s_tile;
     const uint32_t s = tile * DEC_TILE;
@@ -838,36 +944,71 @@ __global__ __launch_bounds__(DEC_THREADS) void k_dec_level(TileMap m, int d)
     const GAS uint8_t *occ = gp(fd.in_stream + GSC_HEADER_BYTES + off);
     const GAS uint64_t *src = gp((d & 1) ? fd.keys_b : fd.keys_a);
     GAS uint64_t *dst = gp((d & 1) ? fd.keys_a : fd.keys_b);
-    uint32_t bytes[DEC_PPT], cnt = 0;
+    // striped (coalesced) parents: parent p = s + r * DEC_THREADS + tid; its children follow
+    // those of the parents before it, so a wave's children are one contiguous run per row
+    uint32_t bytes[DEC_PPT], wex[DEC_PPT];
+    uint64_t parent[DEC_PPT];
     bool bad = false;
 #pragma unroll
-    for (int i = 0; i < DEC_PPT; ++i) {
-        const uint32_t p = s + tid * DEC_PPT + i;
-        bytes[i] = p < M ? occ[p] : 0u;
-        if (p < M && bytes[i] == 0) bad = true;
-        cnt += __popc(bytes[i]);
+    for (int r = 0; r < DEC_PPT; ++r) {
+        const uint32_t p = s + r * DEC_THREADS + tid;
+        bytes[r] = p < M ? occ[p] : 0u;
+        parent[r] = p < M ? src[p] : 0ull;
     }
-    uint32_t total;
-    uint32_t w = block_excl_scan<DEC_THREADS>(cnt, s_tmp, &total);
+#pragma unroll
+    for (int r = 0; r < DEC_PPT; ++r) {
+        const uint32_t p = s + r * DEC_THREADS + tid;
+        if (p < M && bytes[r] == 0) bad = true;
+        const uint32_t c = (uint32_t)__popc(bytes[r]);
+        const uint32_t inc = wave_incl_scan(c);
+        wex[r] = inc - c;
+        if (lane == WAVE - 1) s_cnt[r * NW + w] = inc;
+    }
+    __syncthreads();
+    if (w == 0) {  // (row, wave) totals in parent order -> exclusive offsets
+        const uint32_t c = lane < (uint32_t)(DEC_PPT * NW) ? s_cnt[lane] : 0u;
+        const uint32_t inc = wave_incl_scan(c);
+        if (lane < (uint32_t)(DEC_PPT * NW)) s_cnt[lane] = inc - c;
+        if (lane == WAVE - 1) s_cnt[WAVE] = inc;
+    }
+    __syncthreads();
+    const uint32_t total = s_cnt[WAVE];
     __shared__ LbScratch<DEC_THREADS / WAVE> s_lb;
     const uint32_t wbase = (uint32_t)lookback_block<OpSum, DEC_THREADS>(fd.dec_status + fd.dec_status_off[d], 1, tile, total, ctrl, s_lb);
-    w += wbase;
+    // children through LDS in output order, DEC_CHUNK at a time, so that the codes (or the
+    // leaves' positions) are written by consecutive threads to consecutive slots
+    __shared__ uint64_t s_child[DEC_CHUNK];
+    uint32_t first[DEC_PPT];
 #pragma unroll
-    for (int i = 0; i < DEC_PPT; ++i) {
-        const uint32_t p = s + tid * DEC_PPT + i;
-        if (p >= M) break;
-        const uint64_t base = src[p] << 3;
-        for (uint32_t c = 0; c < 8; ++c) {
-            if (bytes[i] >> c & 1u) {
-                if (w < Mn) {
-                    if ((uint32_t)d + 1 == J) emit_leaf(fd, h, w, base + c);
-                    else dst[w] = base + c;
-                } else {
-                    bad = true;
+    for (int r = 0; r < DEC_PPT; ++r) first[r] = s_cnt[r * NW + w] + wex[r];
+    const bool leaves = (uint32_t)d + 1 == J;
+    for (uint32_t c0 = 0; c0 < total; c0 += DEC_CHUNK) {
+        const uint32_t c1 = c0 + DEC_CHUNK;
+#pragma unroll
+        for (int r = 0; r < DEC_PPT; ++r) {
+            const uint32_t nc = (uint32_t)__popc(bytes[r]);
+            if (first[r] >= c1 || first[r] + nc <= c0) continue;
+            uint32_t j = first[r];
+            const uint64_t pc = parent[r] << 3;
+            for (uint32_t c = 0; c < 8; ++c) {
+                if (bytes[r] >> c & 1u) {
+                    if (j >= c0 && j < c1) s_child[j - c0] = pc + c;
+                    ++j;
                 }
-                ++w;
             }
         }
+        __syncthreads();
+        const uint32_t nh = min((uint32_t)DEC_CHUNK, total - c0);
+        for (uint32_t x = tid; x < nh; x += DEC_THREADS) {
+            const uint32_t o = wbase + c0 + x;
+            if (o < Mn) {
+                if (leaves) emit_leaf(fd, h, o, s_child[x]);
+                else dst[o] = s_child[x];
+            } else {
+                bad = true;
+            }
+        }
+        __syncthreads();
     }
     if (bad) set_error(ctrl, GSC_ERR_CORRUPT_STREAM);
     if (tid == 0 && s + DEC_TILE >= M && wbase + total != Mn) set_error(ctrl, GSC_ERR_CORRUPT_STREAM);

@@ -74,7 +74,7 @@ __global__ __launch_bounds__(PRE_BLOCK) void k_prelude(TileMap m, int k)
     if (!seq_active(nk, k)) return;
     const RahtLevel &lv = fd.lv[k];
     const uint32_t tid = threadIdx.x;
-    if (tid == 0) s_blk = atomicAdd(&ctrl->tile_ctr[TC_PRELUDE + k], 1u);
+    if (tid == 0) s_blk = tile_index(m, f);
     __syncthreads();
     const uint32_t blk = s_blk;
     if (blk * PRE_TILES * RT >= nk) return;            // uniform: the whole block is past the end
@@ -234,9 +234,11 @@ __device__ inline bool load_schedule(const FrameDesc &fd, Ctrl *ctrl, int k, uin
     const GAS uint32_t *sidx = gp(lv.s_idx), *recs = gp(lv.rec);
     for (uint32_t x = tid; x < (uint32_t)LSTART_N; x += NT) s_lst[x] = lstart[(size_t)tile * LSTART_N + x];
     for (uint32_t o = tid; o < ts.ocnt; o += NT) s_opos[o] = opos[(size_t)tile * OPEN_CAP + o];
-    if (k >= 2) {
-        for (int j = tid; j < ts.mlen; j += NT) s_idx[j] = sidx[s + j];
-        if (tid == 0) s_idx[ts.mlen] = ts.e < nk ? sidx[ts.e] : ctrl->n_vox;
+    if (k >= 2) {  // voxel indices, clamped to the frame's capacity like every row index read
+                   // from the workspace
+        const uint32_t cap = fd.n;
+        for (int j = tid; j < ts.mlen; j += NT) s_idx[j] = min(sidx[s + j], cap ? cap - 1 : 0u);
+        if (tid == 0) s_idx[ts.mlen] = min(ts.e < nk ? sidx[ts.e] : ctrl->n_vox, cap);
     }
     __syncthreads();
     ts.nrec = s_lst[SEG_N - 1];
@@ -363,6 +365,32 @@ __device__ inline void block_phase(float4 *s_y, const Roles &R, const uint32_t *
             for (uint32_t q = q0 + R.row0; q < q1; q += R.RPB)
                 butterfly(s_y, R.C4, s_rec[q], s_ab[q], R.c4, inverse);
         __syncthreads();
+    }
+}
+
+// Every merge of the tile, levels ascending (forward) or descending (inverse), with wave w
+// transforming the channel chunks w, w + NW, ... of the slice and one merge per lane. Waves
+// never touch the same LDS element, so no workgroup barrier is needed between levels; within a
+// wave the LDS accesses are performed in program order (the fence keeps the compiler from
+// moving one level's accesses across the next level's). The records of a level are contiguous
+// (sorted by level, then class), so all classes of level x are [lst[x*NCLS], lst[x*NCLS+NCLS]).
+__device__ inline void chan_phase(float4 *s_y, uint32_t CH4, const uint32_t *s_rec,
+                                  const float2 *s_ab, const uint16_t *s_lst, uint64_t mask,
+                                  uint32_t nch, bool inverse)
+{
+    constexpr uint32_t NW = RAHT_THREADS / WAVE;
+    const uint32_t w = threadIdx.x / WAVE, lane = lane_id();
+    while (mask) {
+        const uint32_t x = inverse ? (uint32_t)msb64(mask) : (uint32_t)(__ffsll((long long)mask) - 1);
+        mask &= ~(1ull << x);
+        const uint32_t q0 = s_lst[x * NCLS], q1 = s_lst[x * NCLS + NCLS];
+        for (uint32_t q = q0 + lane; q < q1; q += WAVE) {
+            const uint32_t rec = s_rec[q];
+            const float2 ab = s_ab[q];
+            for (uint32_t c = w; c < nch; c += NW) butterfly(s_y, CH4, rec, ab, c, inverse);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        __builtin_amdgcn_wave_barrier();
     }
 }
 
@@ -497,12 +525,14 @@ __global__ __launch_bounds__(RAHT_THREADS) void k_raht_fwd(TileMap m, int k)
     const bool encode1 = (k == 1 && fd.mode == MODE_ENCODE);
     const GAS uint32_t *perm = gp((fd.P & 1) ? fd.vals_b : fd.vals_a);
     const GAS float *attr = gp(fd.attr);
+    const uint32_t nlast = fd.n ? fd.n - 1 : 0u;  // row indices read from the workspace are
+                                                     // clamped: never an access outside the input
     if (encode1) {
         // the run starts and the first member's row, staged so that row loads are independent
         const GAS uint32_t *vh = gp(fd.vh);
-        for (uint32_t j = tid; j <= mlen; j += RAHT_THREADS) s_m0[j] = vh[ts.s + j];
+        for (uint32_t j = tid; j <= mlen; j += RAHT_THREADS) s_m0[j] = min(vh[ts.s + j], fd.n);
         __syncthreads();
-        for (uint32_t j = tid; j < mlen; j += RAHT_THREADS) s_first[j] = perm[s_m0[j]];
+        for (uint32_t j = tid; j < mlen; j += RAHT_THREADS) s_first[j] = min(perm[min(s_m0[j], nlast)], nlast);
     }
     level_masks(s_lst, s_lmask);
     const uint64_t wmask = s_lmask[R.w], xmask = s_lmask[CROSS];
@@ -535,7 +565,7 @@ __global__ __launch_bounds__(RAHT_THREADS) void k_raht_fwd(TileMap m, int k)
                     if (m1 - m0 <= 1) continue;
                     float4 acc = s_y[j * CH4 + R.c4];
                     for (uint32_t mm = m0 + 1; mm < m1; ++mm) {
-                        const float4 x = ld4<VEC>(attr, perm[mm], C, c4);
+                        const float4 x = ld4<VEC>(attr, min(perm[mm], nlast), C, c4);
                         acc.x += x.x;
                         acc.y += x.y;
                         acc.z += x.z;
@@ -687,15 +717,16 @@ __global__ __launch_bounds__(RAHT_THREADS) void k_raht_inv(TileMap m, int k)
             const GAS float *ga = gp(fd.grad_add);
             const GAS uint32_t *vh = gp(fd.vh);
             const GAS uint32_t *perm = gp((fd.P & 1) ? fd.vals_b : fd.vals_a);
+            const uint32_t nlast = fd.n ? fd.n - 1 : 0u;
             for (uint32_t j = R.row0; j < mlen; j += R.RPB) {
                 const uint32_t v = ts.s + j;
                 const float4 a = s_y[j * CH4 + R.c4];
                 const float4 b = ld4<VEC>(ga, v, C, c4);
-                const uint32_t m0 = vh[v], m1 = vh[v + 1];
+                const uint32_t m0 = min(vh[v], fd.n), m1 = min(vh[v + 1], fd.n);
                 const float cnt = (float)(m1 - m0);
                 const float4 g = make_float4((a.x + b.x) / cnt, (a.y + b.y) / cnt, (a.z + b.z) / cnt,
                                              (a.w + b.w) / cnt);
-                for (uint32_t mm = m0; mm < m1; ++mm) st4<VEC>(out, perm[mm], C, c4, g);
+                for (uint32_t mm = m0; mm < m1; ++mm) st4<VEC>(out, min(perm[mm], nlast), C, c4, g);
             }
         } else {
             GAS float *out = gp(fd.mode == MODE_ADJ_F32 ? fd.coef_f32 : fd.attr_out);
