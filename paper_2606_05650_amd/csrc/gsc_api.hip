@@ -185,7 +185,7 @@ gsc_status run_forward(const Frame *fr, int F, const RahtCfg &cfg, hipStream_t s
 {
     const int K = max_K(fr, F);
     for (int k = 1; k <= K; ++k) {
-        TileMap m = make_map(fr, F, [k](const Frame &x) { return (int)x.L.K >= k ? x.L.tiles[k] : 0u; });
+        TileMap m = make_map(fr, F, [k, &cfg](const Frame &x) { return (int)x.L.K >= k ? raht_blocks(x.L.tiles[k], k, cfg.C4) : 0u; });
         if (m.start[F] == 0) continue;
         if (k == 1) {
             StageScope sc(GSC_STAGE_RAHT_FWD1, s);
@@ -195,7 +195,7 @@ gsc_status run_forward(const Frame *fr, int F, const RahtCfg &cfg, hipStream_t s
                 // one scope over all upper levels
                 StageScope sc(GSC_STAGE_RAHT_FWD_TOP, s);
                 for (int kk = 2; kk <= K; ++kk) {
-                    TileMap mm = make_map(fr, F, [kk](const Frame &x) { return (int)x.L.K >= kk ? x.L.tiles[kk] : 0u; });
+                    TileMap mm = make_map(fr, F, [kk, &cfg](const Frame &x) { return (int)x.L.K >= kk ? raht_blocks(x.L.tiles[kk], kk, cfg.C4) : 0u; });
                     if (mm.start[F] == 0) continue;
                     GSC_LAUNCH(launch_raht_fwd(mm, kk, cfg, s));
                 }
@@ -213,12 +213,12 @@ gsc_status run_inverse(const Frame *fr, int F, const RahtCfg &cfg, hipStream_t s
     {
         StageScope sc(GSC_STAGE_RAHT_INV_TOP, s);
         for (int k = K; k >= 2; --k) {
-            TileMap m = make_map(fr, F, [k](const Frame &x) { return (int)x.L.K >= k ? x.L.tiles[k] : 0u; });
+            TileMap m = make_map(fr, F, [k, &cfg](const Frame &x) { return (int)x.L.K >= k ? raht_blocks(x.L.tiles[k], k, cfg.C4) : 0u; });
             if (m.start[F] == 0) continue;
             GSC_LAUNCH(launch_raht_inv(m, k, cfg, s));
         }
     }
-    TileMap m = make_map(fr, F, [](const Frame &x) { return x.L.tiles[1]; });
+    TileMap m = make_map(fr, F, [&cfg](const Frame &x) { return raht_blocks(x.L.tiles[1], 1, cfg.C4); });
     if (m.start[F] > 0) {
         StageScope sc(GSC_STAGE_RAHT_INV1, s);
         GSC_LAUNCH(launch_raht_inv(m, 1, cfg, s));

@@ -317,6 +317,7 @@ struct RahtCfg {
     int C4;
     bool vec, pow2;
 };
+uint32_t raht_blocks(uint32_t tiles, int k, int C4);  // workgroups of a transform launch
 hipError_t launch_raht_fwd(const TileMap &m, int k, const RahtCfg &cfg, hipStream_t s);
 hipError_t launch_raht_inv(const TileMap &m, int k, const RahtCfg &cfg, hipStream_t s);
 hipError_t launch_finish(const TileMap &m, hipStream_t s);

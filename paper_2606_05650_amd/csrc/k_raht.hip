@@ -495,6 +495,35 @@ __device__ inline void load_slice(float4 *s_y, const Roles &R, uint32_t CH4, uin
     }
 }
 
+// First-level tiles whose channels take two passes are split over two workgroups, one per
+// channel half: each makes one pass with the LDS of one half, and the grid has twice the
+// workgroups. The two halves of tile t are the blocks b and b + 8 of a group of 16, which land
+// on the same XCD (workgroups go to the 8 XCDs round-robin) one after the other, so the second
+// half's row reads find the rows' cache lines in that XCD's L2.
+struct HalfSplit {
+    uint32_t tile, p0, p1;
+};
+__host__ __device__ inline bool split_halves(int k, uint32_t NP) { return k == 1 && NP == 2; }
+__device__ inline HalfSplit half_split(uint32_t local, int k, uint32_t NP)
+{
+    HalfSplit h;
+    if (split_halves(k, NP)) {
+        const uint32_t g = local / 16, w = local % 16;
+        h.tile = g * 8 + (w % 8);
+        h.p0 = w / 8;
+        h.p1 = h.p0 + 1;
+    } else {
+        h.tile = local;
+        h.p0 = 0;
+        h.p1 = NP;
+    }
+    return h;
+}
+uint32_t raht_blocks(uint32_t tiles, int k, int C4)
+{
+    return split_halves(k, channel_passes((uint32_t)C4, k)) ? (tiles + 7) / 8 * 16 : tiles;
+}
+
 // ==================================================================== forward transform
 template <bool VEC, bool POW2>
 __global__ __launch_bounds__(RAHT_THREADS) void k_raht_fwd(TileMap m, int k)
@@ -515,11 +544,12 @@ __global__ __launch_bounds__(RAHT_THREADS) void k_raht_fwd(TileMap m, int k)
     if (load_error(ctrl)) return;
     if ((uint32_t)k > fd.K) return;
     TileSched ts;
-    if (!load_schedule(fd, ctrl, k, blockIdx.x - m.start[f], ts, s_rec, s_ab, s_lst, s_opos, s_idx))
-        return;
     const uint32_t C = fd.C, C4 = fd.C4;
-    const uint32_t tid = threadIdx.x;
     const uint32_t NP = channel_passes(C4, k), CH4 = pass_chunks(C4, k);
+    const HalfSplit hs = half_split(blockIdx.x - m.start[f], k, NP);
+    if (!load_schedule(fd, ctrl, k, hs.tile, ts, s_rec, s_ab, s_lst, s_opos, s_idx))
+        return;
+    const uint32_t tid = threadIdx.x;
     const Roles R(CH4);
     const uint32_t mlen = (uint32_t)ts.mlen;
     const bool encode1 = (k == 1 && fd.mode == MODE_ENCODE);
@@ -548,16 +578,22 @@ __global__ __launch_bounds__(RAHT_THREADS) void k_raht_fwd(TileMap m, int k)
     const GAS float *vsrc = k >= 2 ? gp(fd.lv[k - 1].vbuf) : nullptr;
     GAS float *coef_f32 = gp(fd.coef_f32);
 
-    for (uint32_t p = 0; p < NP; ++p) {
+    for (uint32_t p = hs.p0; p < hs.p1; ++p) {
         const uint32_t cb = p * CH4;
         const uint32_t nch = min(CH4, C4 - cb);
         const uint32_t c4 = cb + R.c4;  // this thread's global channel chunk
         const bool live = R.act && R.c4 < nch;
-        if (p > 0) __syncthreads();  // the previous pass has finished reading the slice
+        if (p > hs.p0) __syncthreads();  // the previous pass has finished reading the slice
         // ---- load the entries' values of this channel slice
         if (live) {
             if (encode1) {
                 load_slice(s_y, R, CH4, mlen, [&](uint32_t j) { return ld4<VEC>(attr, s_first[j], C, c4); });
+            } else if (k == 1) {
+                load_slice(s_y, R, CH4, mlen, [&](uint32_t j) { return ld4<VEC>(attr, ts.s + j, C, c4); });
+            } else {
+                load_slice(s_y, R, CH4, mlen, [&](uint32_t j) { return gload4(vsrc + ((size_t)(ts.s + j) * C4 + c4) * 4); });
+            }
+            if (encode1) {
                 // merge duplicates: the mean of the rows of the Gaussians in the voxel
                 // (Sec. 2.1), summed in input order (the sort is stable)
                 for (uint32_t j = R.row0; j < mlen; j += R.RPB) {
@@ -584,10 +620,6 @@ __global__ __launch_bounds__(RAHT_THREADS) void k_raht_fwd(TileMap m, int k)
                     for (uint32_t j = R.row0; j < mlen; j += R.RPB)
                         st4<VEC>(ar, ts.s + j, C, c4, s_y[j * CH4 + R.c4]);
                 }
-            } else if (k == 1) {
-                load_slice(s_y, R, CH4, mlen, [&](uint32_t j) { return ld4<VEC>(attr, ts.s + j, C, c4); });
-            } else {
-                load_slice(s_y, R, CH4, mlen, [&](uint32_t j) { return gload4(vsrc + ((size_t)(ts.s + j) * C4 + c4) * 4); });
             }
         }
         __syncthreads();
@@ -651,10 +683,11 @@ __global__ __launch_bounds__(RAHT_THREADS) void k_raht_inv(TileMap m, int k)
     if (load_error(ctrl)) return;
     if ((uint32_t)k > fd.K) return;
     TileSched ts;
-    if (!load_schedule(fd, ctrl, k, blockIdx.x - m.start[f], ts, s_rec, s_ab, s_lst, s_opos, s_idx))
-        return;
     const uint32_t C = fd.C, C4 = fd.C4;
     const uint32_t NP = channel_passes(C4, k), CH4 = pass_chunks(C4, k);
+    const HalfSplit hs = half_split(blockIdx.x - m.start[f], k, NP);
+    if (!load_schedule(fd, ctrl, k, hs.tile, ts, s_rec, s_ab, s_lst, s_opos, s_idx))
+        return;
     const Roles R(CH4);
     const uint32_t mlen = (uint32_t)ts.mlen;
     level_masks(s_lst, s_lmask);
@@ -667,12 +700,12 @@ __global__ __launch_bounds__(RAHT_THREADS) void k_raht_inv(TileMap m, int k)
     // coefficients; the transform and gradient modes read the caller's rows
     const GAS float *fin = gp(fd.mode == MODE_ENCODE ? fd.coef_f32 : fd.attr);
 
-    for (uint32_t p = 0; p < NP; ++p) {
+    for (uint32_t p = hs.p0; p < hs.p1; ++p) {
         const uint32_t cb = p * CH4;
         const uint32_t nch = min(CH4, C4 - cb);
         const uint32_t c4 = cb + R.c4;
         const bool live = R.act && R.c4 < nch;
-        if (p > 0) __syncthreads();
+        if (p > hs.p0) __syncthreads();
         // ---- coefficients of every entry (the high-pass stored at it, or the DC at entry 0)
         if (live) {
             if (fd.mode == MODE_DECODE) {
