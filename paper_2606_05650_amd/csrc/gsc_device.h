@@ -88,6 +88,21 @@ __device__ inline uint32_t wave_incl_scan(uint32_t v)
     return v;
 }
 
+// Wave-wide minimum / maximum, returned to every lane (a workgroup-wide reduction through
+// same-address LDS atomics serializes: measured 14 us for 1536 of them on 6 addresses).
+__device__ inline float wave_min(float v)
+{
+#pragma unroll
+    for (int o = 1; o < WAVE; o <<= 1) v = fminf(v, __shfl_xor(v, o, WAVE));
+    return v;
+}
+__device__ inline float wave_max(float v)
+{
+#pragma unroll
+    for (int o = 1; o < WAVE; o <<= 1) v = fmaxf(v, __shfl_xor(v, o, WAVE));
+    return v;
+}
+
 // Exclusive scan over the NT threads of a block. `tmp` holds NT/64 + 1 words of LDS.
 // Returns the exclusive prefix of v; *total receives the block total. Ends with a barrier.
 template <int NT>

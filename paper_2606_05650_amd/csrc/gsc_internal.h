@@ -37,11 +37,11 @@ constexpr int OCC_THREADS = 1024;        // 16 waves: the per-depth look-backs r
 constexpr int OCC_VPT = 2;              // voxels per thread
 constexpr int OCC_TILE = OCC_THREADS * OCC_VPT;
 
-constexpr int DEC_TOP_CAP = 4096;       // octree levels this small are expanded in one workgroup
+constexpr int DEC_TOP_CAP = 8192;       // octree levels this small are expanded in one workgroup
 constexpr int DEC_THREADS = 256;
 constexpr int DEC_PPT = 8;              // parents per thread
 constexpr int DEC_TILE = DEC_THREADS * DEC_PPT;
-constexpr int DEC_CHUNK = 4096;         // children staged in LDS per round
+constexpr int DEC_CHUNK = 8192;         // children staged in LDS per round (64 KB)
 
 constexpr int RT = 256;                 // RAHT tile: entries per workgroup
 constexpr int RAHT_THREADS = 256;

@@ -331,19 +331,31 @@ __global__ __launch_bounds__(BBOX_THREADS) void k_bbox(TileMap m)
         }
     }
     if (__ballot(bad) && lane_id() == 0) set_error(ctrl, GSC_ERR_INVALID_ARG);
-    __shared__ uint32_t s_o[6];
-    if (threadIdx.x < 6) s_o[threadIdx.x] = threadIdx.x < 3 ? 0xFFFFFFFFu : 0u;
-    __syncthreads();
+    // wave reductions (shuffles), then one value per wave in LDS: no contended LDS atomics
+    constexpr int NW = BBOX_THREADS / WAVE;
+    __shared__ float s_mn[NW][3], s_mx[NW][3];
+    const uint32_t w = threadIdx.x / WAVE;
+#pragma unroll
     for (int a = 0; a < 3; ++a) {
-        if (mn[a] <= mx[a]) {  // this thread saw a coordinate of axis a
-            atomicMin(&s_o[a], f2ord(mn[a]));
-            atomicMax(&s_o[3 + a], f2ord(mx[a]));
+        const float lo = wave_min(mn[a]), hi = wave_max(mx[a]);
+        if (lane_id() == 0) {
+            s_mn[w][a] = lo;
+            s_mx[w][a] = hi;
         }
     }
     __syncthreads();
-    if (threadIdx.x < 3 && s_o[threadIdx.x] != 0xFFFFFFFFu) atomicMin(&ctrl->bbox_ord[threadIdx.x], s_o[threadIdx.x]);
-    else if (threadIdx.x >= 3 && threadIdx.x < 6 && s_o[threadIdx.x - 3] != 0xFFFFFFFFu)
-        atomicMax(&ctrl->bbox_ord[threadIdx.x], s_o[threadIdx.x]);
+    if (threadIdx.x < 3) {
+        const uint32_t a = threadIdx.x;
+        float lo = INFINITY, hi = -INFINITY;
+        for (int ww = 0; ww < NW; ++ww) {
+            lo = fminf(lo, s_mn[ww][a]);
+            hi = fmaxf(hi, s_mx[ww][a]);
+        }
+        if (lo <= hi) {  // the workgroup saw a coordinate of axis a
+            atomicMin(&ctrl->bbox_ord[a], f2ord(lo));
+            atomicMax(&ctrl->bbox_ord[3 + a], f2ord(hi));
+        }
+    }
 }
 
 hipError_t launch_bbox(const TileMap &m, hipStream_t s)
@@ -871,7 +883,7 @@ __global__ __launch_bounds__(DEC_TOP_THREADS) void k_dec_top(TileMap m)
     for (; d < J; ++d) {
         const uint32_t M = h->level_sizes[d], Mn = h->level_sizes[d + 1];
         if (Mn > (uint32_t)DEC_TOP_CAP) break;
-        // each thread takes up to 4 consecutive parents
+        // each thread takes up to DEC_TOP_CAP / DEC_TOP_THREADS consecutive parents
         constexpr int PPT = DEC_TOP_CAP / DEC_TOP_THREADS;
         uint32_t bytes[PPT], cnt = 0;
 #pragma unroll

@@ -53,7 +53,7 @@ __device__ inline bool seq_active(uint32_t nk, int k) { return k == 1 ? nk >= 1 
 // wave chunk holding the whole merge or CROSS. Open entries are compacted in order into S_{k+1}
 // with a decoupled look-back; a workgroup handles PRE_TILES consecutive tiles so that the
 // look-back chain has PRE_TILES times fewer links.
-constexpr int PRE_TILES = 4;
+constexpr int PRE_TILES = 2;
 constexpr int PRE_BLOCK = PRE_TILES * PRE_THREADS;
 
 __global__ __launch_bounds__(PRE_BLOCK) void k_prelude(TileMap m, int k)
@@ -323,11 +323,15 @@ struct Roles {
 // merge phases visit only the levels that hold merges.
 __device__ inline void level_masks(const uint16_t *s_lst, unsigned long long *s_lmask)
 {
-    const uint32_t tid = threadIdx.x;
-    if (tid < (uint32_t)NCLS) s_lmask[tid] = 0;
-    __syncthreads();
-    for (uint32_t i = tid; i < (uint32_t)(NLVL * NCLS); i += blockDim.x)
-        if (s_lst[i] != s_lst[i + 1]) atomicOr(&s_lmask[i % NCLS], 1ull << (i / NCLS));
+    // wave 0: lane x tests level x of every class; one ballot per class gives its mask
+    if (threadIdx.x < WAVE) {
+        const uint32_t x = threadIdx.x;
+        for (uint32_t c = 0; c < (uint32_t)NCLS; ++c) {
+            const uint32_t i = x * NCLS + c;
+            const uint64_t b = __ballot(s_lst[i] != s_lst[i + 1]);
+            if (x == 0) s_lmask[c] = b;
+        }
+    }
     __syncthreads();
 }
 
