@@ -43,13 +43,13 @@ constexpr int DEC_PPT = 8;              // parents per thread
 constexpr int DEC_TILE = DEC_THREADS * DEC_PPT;
 constexpr int DEC_CHUNK = 8192;         // children staged in LDS per round (64 KB)
 
-constexpr int RT = 256;                 // RAHT tile: entries per workgroup
-constexpr int RAHT_THREADS = 256;
+constexpr int RT = 512;                 // RAHT tile: entries (eight 64-entry wave chunks)
+constexpr int RAHT_THREADS = 512;       // one wave per chunk
 constexpr int OPEN_CAP = 128;           // >= 6J + 2 open entries per tile for J <= 21
 constexpr int NLVL = 64;                // binary levels 1..63 fit in a 64-bit mask
 constexpr uint8_t LVL_NONE = 127;       // level of entry 0: it never merges as a right sibling
 constexpr int MAXK = 24;                // RAHT tiling levels (sequences S_1 .. S_MAXK)
-constexpr int NCLS = RT / 64 + 1;       // merge classes: local to wave chunk 0..3, or crossing
+constexpr int NCLS = RT / 64 + 1;       // merge classes: local to one wave chunk, or crossing
 constexpr int SEG_N = NLVL * NCLS + 1;  // per-tile (level, class) segment starts + total
 constexpr int LSTART_N = SEG_N + 1;     // padded to an even count of u16
 

@@ -25,7 +25,7 @@
 
 namespace gsc {
 
-static_assert(RT == 4 * WAVE, "a tile is four 64-entry wave chunks");
+static_assert(RT == RAHT_THREADS && RT % WAVE == 0, "a tile is one 64-entry chunk per wave");
 static_assert(RT < 1024, "merge records pack three 10-bit positions");
 constexpr int PRE_THREADS = RT;
 constexpr int NCHUNK = RT / WAVE;
@@ -53,7 +53,7 @@ __device__ inline bool seq_active(uint32_t nk, int k) { return k == 1 ? nk >= 1 
 // wave chunk holding the whole merge or CROSS. Open entries are compacted in order into S_{k+1}
 // with a decoupled look-back; a workgroup handles PRE_TILES consecutive tiles so that the
 // look-back chain has PRE_TILES times fewer links.
-constexpr int PRE_TILES = 2;
+constexpr int PRE_TILES = 1;
 constexpr int PRE_BLOCK = PRE_TILES * PRE_THREADS;
 
 __global__ __launch_bounds__(PRE_BLOCK) void k_prelude(TileMap m, int k)
@@ -300,7 +300,7 @@ __device__ inline void butterfly(float4 *s_y, uint32_t C4, uint32_t rec, float2 
 
 // Per-thread roles: in a workgroup step, thread t handles channel chunk t % C4 of row t / C4
 // (RPB rows per step); in a wave step, lane L handles chunk L % C4 of merge L / C4 (MPW
-// merges per step). C4 <= 16, so RPB >= 16 and MPW >= 4.
+// merges per step). A slice has C4 <= CH4_MAX = 4 chunks, so RPB >= 128 and MPW >= 16.
 struct Roles {
     uint32_t C4, RPB, row0, c4, MPW, wq, wc4, w;
     bool act, wact;
@@ -462,14 +462,16 @@ __device__ inline int32_t quant1(float y, float step, float inv_step, double omt
 
 constexpr int UNROLL = 8;  // independent row loads in flight per thread
 
-// On the first tiling level (many tiles) the channels are transformed in passes of at most
-// CH4_MAX float4 chunks (32 channels), so a tile's slice in LDS stays at 32 KB and several
-// workgroups share a CU. The upper levels have few tiles, and their time is the chain of
-// per-level barriers of a tile: they take all channels (at most 64 KB) in one pass.
-constexpr uint32_t CH4_MAX = 8;
+// The channels of a tile are transformed in slices taken by different workgroups (see
+// slice_split): on the upper levels slices of at most CH4_MAX float4 chunks (16 channels,
+// 32 KB of LDS), on the first level at most CH4_MAX1 (measured faster there: fewer, wider row
+// pieces per gathered row).
+constexpr uint32_t CH4_MAX = 4;
+constexpr uint32_t CH4_MAX1 = 8;  // the first level: two slices of up to 32 channels (112-byte row pieces)
 __host__ __device__ inline uint32_t channel_passes(uint32_t C4, int k)
 {
-    return k == 1 ? (C4 + CH4_MAX - 1) / CH4_MAX : 1u;
+    const uint32_t cm = k == 1 ? CH4_MAX1 : CH4_MAX;
+    return (C4 + cm - 1) / cm;
 }
 __host__ __device__ inline uint32_t pass_chunks(uint32_t C4, int k)
 {
@@ -499,33 +501,26 @@ __device__ inline void load_slice(float4 *s_y, const Roles &R, uint32_t CH4, uin
     }
 }
 
-// First-level tiles whose channels take two passes are split over two workgroups, one per
-// channel half: each makes one pass with the LDS of one half, and the grid has twice the
-// workgroups. The two halves of tile t are the blocks b and b + 8 of a group of 16, which land
-// on the same XCD (workgroups go to the 8 XCDs round-robin) one after the other, so the second
-// half's row reads find the rows' cache lines in that XCD's L2.
-struct HalfSplit {
+// The channel slices of a tile are taken by different workgroups, one slice each: a workgroup
+// makes one pass with the LDS of one slice. The NP workgroups of tile t are the blocks b,
+// b + 8, ..., b + 8 (NP - 1) of a group of 8 NP blocks, which land on the same XCD (workgroups
+// go to the 8 XCDs round-robin) one after the other, so the row reads of the later slices find
+// the rows' cache lines in that XCD's L2.
+struct SliceSplit {
     uint32_t tile, p0, p1;
 };
-__host__ __device__ inline bool split_halves(int k, uint32_t NP) { return k == 1 && NP == 2; }
-__device__ inline HalfSplit half_split(uint32_t local, int k, uint32_t NP)
+__device__ inline SliceSplit slice_split(uint32_t local, uint32_t NP)
 {
-    HalfSplit h;
-    if (split_halves(k, NP)) {
-        const uint32_t g = local / 16, w = local % 16;
-        h.tile = g * 8 + (w % 8);
-        h.p0 = w / 8;
-        h.p1 = h.p0 + 1;
-    } else {
-        h.tile = local;
-        h.p0 = 0;
-        h.p1 = NP;
-    }
+    SliceSplit h;
+    const uint32_t g = local / (8 * NP), w = local % (8 * NP);
+    h.tile = g * 8 + (w % 8);
+    h.p0 = w / 8;
+    h.p1 = h.p0 + 1;
     return h;
 }
 uint32_t raht_blocks(uint32_t tiles, int k, int C4)
 {
-    return split_halves(k, channel_passes((uint32_t)C4, k)) ? (tiles + 7) / 8 * 16 : tiles;
+    return (tiles + 7) / 8 * 8 * channel_passes((uint32_t)C4, k);
 }
 
 // ==================================================================== forward transform
@@ -550,7 +545,7 @@ __global__ __launch_bounds__(RAHT_THREADS) void k_raht_fwd(TileMap m, int k)
     TileSched ts;
     const uint32_t C = fd.C, C4 = fd.C4;
     const uint32_t NP = channel_passes(C4, k), CH4 = pass_chunks(C4, k);
-    const HalfSplit hs = half_split(blockIdx.x - m.start[f], k, NP);
+    const SliceSplit hs = slice_split(blockIdx.x - m.start[f], NP);
     if (!load_schedule(fd, ctrl, k, hs.tile, ts, s_rec, s_ab, s_lst, s_opos, s_idx))
         return;
     const uint32_t tid = threadIdx.x;
@@ -689,7 +684,7 @@ __global__ __launch_bounds__(RAHT_THREADS) void k_raht_inv(TileMap m, int k)
     TileSched ts;
     const uint32_t C = fd.C, C4 = fd.C4;
     const uint32_t NP = channel_passes(C4, k), CH4 = pass_chunks(C4, k);
-    const HalfSplit hs = half_split(blockIdx.x - m.start[f], k, NP);
+    const SliceSplit hs = slice_split(blockIdx.x - m.start[f], NP);
     if (!load_schedule(fd, ctrl, k, hs.tile, ts, s_rec, s_ab, s_lst, s_opos, s_idx))
         return;
     const Roles R(CH4);
