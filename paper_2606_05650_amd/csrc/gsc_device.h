@@ -15,6 +15,15 @@ __device__ inline GAS T *gp(T *p)
 {
     return (GAS T *)p;
 }
+// Memory that no thread writes while a kernel runs (a frame descriptor, sizes written by earlier
+// kernels) can be read through the constant address space: uniform reads then compile to scalar
+// loads, which wait on the LDS/scalar counter only and so never wait for vector loads in flight.
+#define CAS __attribute__((address_space(4)))
+template <class T>
+__device__ inline const CAS T *cp(const T *p)
+{
+    return (const CAS T *)p;
+}
 // 16-byte global accesses through clang's native vectors (HIP's float4/int4 classes cannot bind
 // to global-address-space references).
 typedef float gf4 __attribute__((ext_vector_type(4)));

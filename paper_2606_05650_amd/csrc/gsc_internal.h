@@ -144,6 +144,7 @@ struct FrameDesc {
     uint32_t *vals_a, *vals_b;
     uint64_t *leaf;
     uint32_t *vh;
+    uint32_t *first;         // encode: input row of every voxel's first member (sorted order)
     uint32_t *sort_status;   // P x sort tiles x SORT_BINS
     uint64_t *dedup_status;
     uint64_t *occ_status;    // occ tiles x J
@@ -204,7 +205,7 @@ static_assert(sizeof(FrameDesc) <= DESC_BYTES, "descriptor too large");
 struct Layout {
     size_t total;
     size_t zero_off, zero_bytes;
-    size_t keys_a, keys_b, vals_a, vals_b, leaf, vh;
+    size_t keys_a, keys_b, vals_a, vals_b, leaf, vh, first;
     size_t sort_status, dedup_status, occ_status, dec_status;
     uint32_t dec_status_off[GSC_MAX_DEPTH + 1];
     uint32_t dec_tiles[GSC_MAX_DEPTH + 1];
@@ -285,6 +286,7 @@ __host__ __device__ inline bool make_layout(int64_t n, int J, int C, Layout *L)
     L->vals_b = off; off = align_up(off + N * 4, 256);
     L->leaf = off; off = align_up(off + N * 8, 256);
     L->vh = off; off = align_up(off + (N + 1) * 4, 256);
+    L->first = off; off = align_up(off + N * 4, 256);
     for (uint32_t k = 1; k <= K; ++k) {
         const uint32_t t = L->tiles[k];
         L->s_idx[k] = off; off = align_up(off + (size_t)L->cap[k] * 4, 256);

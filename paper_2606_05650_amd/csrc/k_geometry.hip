@@ -132,6 +132,7 @@ __global__ __launch_bounds__(256) void k_setup(SetupArgs a)
         fd->vals_b = reinterpret_cast<uint32_t *>(fa.ws + L.vals_b);
         fd->leaf = reinterpret_cast<uint64_t *>(fa.ws + L.leaf);
         fd->vh = reinterpret_cast<uint32_t *>(fa.ws + L.vh);
+        fd->first = reinterpret_cast<uint32_t *>(fa.ws + L.first);
         fd->sort_status = reinterpret_cast<uint32_t *>(fa.ws + L.sort_status);
         fd->dedup_status = reinterpret_cast<uint64_t *>(fa.ws + L.dedup_status);
         fd->occ_status = reinterpret_cast<uint64_t *>(fa.ws + L.occ_status);
@@ -582,7 +583,8 @@ hipError_t launch_sort_pass(const TileMap &m, int pass, int variant, hipStream_t
 
 // ================================================================= unique + merge map
 // Sorted keys -> occupied voxels: a run of equal keys is one voxel (Alg. 1 step 1, Unique).
-// Writes the voxel codes L_J, the first sorted position of every voxel (vh, with vh[Nv] = n),
+// Writes the voxel codes L_J, the first sorted position of every voxel (vh, with vh[Nv] = n)
+// and the input row at that position (first),
 // Nv, and the histogram of new-node depths D_v (the shallowest octree depth at which voxel v
 // starts a node of its own: J - floor(msb(L[v-1] xor L[v]) / 3), and 0 for v = 0), from which
 // every level size follows: |L_d| = #{v : D_v <= d}.
@@ -608,11 +610,15 @@ __global__ __launch_bounds__(DEDUP_THREADS) void k_dedup(TileMap m)
     if (base >= n) return;
     const uint32_t len = min((uint32_t)DEDUP_TILE, n - base);
     const GAS uint64_t *K = gp((fd.P & 1) ? fd.keys_b : fd.keys_a);  // output of the last sort pass
-    // striped (coalesced) loads: position i = r * DEDUP_THREADS + tid
+    const GAS uint32_t *V = gp((fd.P & 1) ? fd.vals_b : fd.vals_a);
+    // striped (coalesced) loads: position i = r * DEDUP_THREADS + tid; the sorted input rows
+    // are kept for the voxels' first members
+    uint32_t pv[DEDUP_KPT];
 #pragma unroll
     for (int r = 0; r < DEDUP_KPT; ++r) {
         const uint32_t i = r * DEDUP_THREADS + tid;
         s_k[1 + i] = K[base + min(i, len - 1)];
+        pv[r] = V[base + min(i, len - 1)];
     }
     if (tid == 0) s_k[0] = base > 0 ? K[base - 1] : 0ull;
     __syncthreads();
@@ -655,6 +661,7 @@ __global__ __launch_bounds__(DEDUP_THREADS) void k_dedup(TileMap m)
                 gp(fd.leaf)[v] = k;
                 if (fd.codes_out) gp(fd.codes_out)[v] = k;
                 gp(fd.vh)[v] = base + i;
+                gp(fd.first)[v] = pv[r];
             }
         }
     }

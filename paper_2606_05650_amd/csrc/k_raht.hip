@@ -664,6 +664,459 @@ __global__ __launch_bounds__(RAHT_THREADS) void k_raht_fwd(TileMap m, int k)
     }
 }
 
+// ============================================================ first level, persistent forward
+// The first level carries almost all of the transform's bytes (every voxel row in, every
+// coefficient row out), and a workgroup that waits first for its schedule and then for its rows
+// leaves the memory system idle for much of its life. Here the workgroups are persistent:
+// workgroup b takes the items (tile, channel slice) b, b + G, b + 2G, ... of the launch
+// (G = gridDim.x, a multiple of 8 NP, so an item and its partner slice run at the same time on
+// one XCD), and while the merges and stores of one item run, the schedule and the row loads of
+// the next item are in flight in registers. The input row of every voxel's first member comes
+// from the dedup kernel's table and is read two items ahead, so the next item's row addresses
+// are known when its loads are issued.
+constexpr int NR1 = 8;  // rows of a slice per thread: ceil(RT / floor(RT / CH4)) <= 8 for CH4 <= 8
+static_assert(CH4_MAX1 <= 8 && RT == 512, "NR1 covers slices of at most 8 chunks of 512 entries");
+
+struct Item1 {
+    uint32_t f, tile, p, s, mlen;
+    bool ok, final_level;
+};
+typedef const CAS FrameDesc CFrame;
+
+// Values shared by the items of one frame, loaded when the first item of the frame is described.
+struct Frame1 {
+    uint32_t f;   // frame, ~0u before the first
+    uint32_t nk;  // entries of S_1; 0 when the frame has nothing to transform
+};
+
+__device__ inline Item1 item1(const TileMap &m, uint32_t i, Frame1 &fc)
+{
+    Item1 it;  // an item that is not ok still names frame 0, so that its fields index safely
+    it.f = it.tile = it.p = it.s = 0;
+    it.mlen = 1;
+    it.ok = it.final_level = false;
+    if (i >= m.start[m.F]) return it;
+    const uint32_t f = frame_of(m, i);
+    CFrame *d = cp(m.fd[f]);
+    if (f != fc.f) {
+        // the frame's values are the same in every lane; readfirstlane says so to the compiler
+        // (an atomic load's result counts as divergent), so that everything derived from them,
+        // down to the descriptor pointer, stays in scalar registers
+        fc.f = f;
+        uint32_t nk = 0;
+        if (!__builtin_amdgcn_readfirstlane(load_error(m.fd[f]->ctrl))) {
+            nk = seq_size(*m.fd[f], m.fd[f]->ctrl, 1);
+            if (!seq_active(nk, 1)) nk = 0;
+        }
+        fc.nk = __builtin_amdgcn_readfirstlane(nk);
+    }
+    const SliceSplit hs = slice_split(i - m.start[f], channel_passes(d->C4, 1));
+    it.f = f;
+    it.tile = hs.tile;
+    it.p = hs.p0;
+    it.s = hs.tile * RT;
+    if (it.s >= fc.nk) return it;
+    it.mlen = min(fc.nk, it.s + RT) - it.s;
+    it.final_level = fc.nk <= (uint32_t)RT;
+    it.ok = true;
+    return it;
+}
+
+// One item's schedule in registers: thread t holds merge record t, word t of the segment starts
+// and of the open positions (two u16 entries each) and run start t (thread 0 also the run start
+// after a full tile). Everything is loaded as 32-bit words: a narrower load's value would be
+// widened where the prefetch branch joins, which waits for it. Entries past the tile's counts
+// are never read from LDS.
+struct Sched1 {
+    uint32_t rec, lst, opos, m0, m_end, obase, ocnt;
+};
+static_assert(LSTART_N % 2 == 0 && OPEN_CAP % 2 == 0 && LSTART_N / 2 <= RT, "u16 pairs per thread");
+
+__device__ inline void load_sched1(CFrame *d, const Item1 &it, Sched1 &S)
+{
+    const uint32_t tid = threadIdx.x;
+    const size_t t = it.tile;
+    S.rec = gp(d->lv[1].rec)[t * RT + tid];
+    const GAS uint32_t *lw = reinterpret_cast<const GAS uint32_t *>(gp(d->lv[1].lstart) + t * LSTART_N);
+    const GAS uint32_t *ow = reinterpret_cast<const GAS uint32_t *>(gp(d->lv[1].opos) + t * OPEN_CAP);
+    S.lst = lw[min(tid, (uint32_t)LSTART_N / 2 - 1)];
+    S.opos = ow[min(tid, (uint32_t)OPEN_CAP / 2 - 1)];
+    // written by the prelude, constant here: scalar loads
+    S.obase = cp(d->lv[1].obase)[t];
+    S.ocnt = cp(d->lv[1].ocnt)[t];
+    // run starts (used by the encoder; the table exists in every workspace)
+    const GAS uint32_t *vh = gp(d->vh);
+    S.m0 = vh[it.s + min(tid, it.mlen)];
+    S.m_end = vh[it.s + it.mlen];
+}
+
+// Branch-free, so that every prefetched register is consumed here on every path (the compiler's
+// wait analysis would otherwise leave them pending and wait for them, and for every later load,
+// at their next write): threads without an entry to write store into the sink slot past the end
+// of each array.
+__device__ inline void commit_sched1(const Sched1 &S, const Item1 &it, uint32_t n, uint32_t *s_rec,
+                                     float2 *s_ab, uint32_t *s_lstw, uint32_t *s_oposw,
+                                     uint32_t *s_m0)
+{
+    const uint32_t tid = threadIdx.x;
+    s_rec[tid] = S.rec;
+    // (a, b) of the merge: at the first level an entry's weight is its position difference
+    const uint32_t j = S.rec & 1023u, l = (S.rec >> 10) & 1023u, r = S.rec >> 20;
+    const float w0 = (float)(j - l), w1 = (float)(r - j);
+    const float sum = w0 + w1;
+    s_ab[tid] = make_float2(sqrtf(w0 / sum), sqrtf(w1 / sum));
+    s_lstw[min(tid, (uint32_t)LSTART_N / 2)] = S.lst;
+    s_oposw[min(tid, (uint32_t)OPEN_CAP / 2)] = S.opos;
+    s_m0[tid <= it.mlen ? tid : RT + 1] = min(S.m0, n);
+    s_m0[tid == 0 ? it.mlen : RT + 1] = min(S.m_end, n);
+}
+
+// Issues the loads of this thread's rows of an item's channel slice: chunk c4 of rows
+// j = row0 + u RPB, row j of the input matrix being s_row[j] (gather) or s + j. Branch-free: a
+// row past the end re-reads the tile's last row and is discarded at commit.
+template <bool VEC>
+__device__ inline void load_rows1(const GAS float *src, uint32_t C, const Roles &R, uint32_t c4,
+                                  uint32_t mlen, bool gather, const uint32_t *s_row, uint32_t s,
+                                  float4 (&D)[NR1])
+{
+    uint32_t row[NR1];
+#pragma unroll
+    for (int u = 0; u < NR1; ++u) {
+        const uint32_t j = min(R.row0 + (uint32_t)u * R.RPB, mlen - 1);
+        row[u] = gather ? s_row[j] : s + j;
+    }
+#pragma unroll
+    for (int u = 0; u < NR1; ++u) D[u] = ld4<VEC>(src, row[u], C, c4);
+}
+
+template <bool VEC, bool POW2>
+__global__ __launch_bounds__(RAHT_THREADS) void k_raht_fwd1(TileMap m)
+{
+    extern __shared__ float4 s_y[];
+    __shared__ uint32_t s_rec[RT];
+    __shared__ float2 s_ab[RT];
+    __shared__ uint32_t s_lstw[LSTART_N / 2 + 1];   // u16 segment starts, in pairs; + sink
+    __shared__ uint32_t s_oposw[OPEN_CAP / 2 + 1];  // u16 open positions, in pairs; + sink
+    __shared__ uint32_t s_m0[RT + 2];               // run starts; + sink
+    __shared__ uint32_t s_row[RT];
+    __shared__ float s_st[GSC_MAX_CHANNELS], s_ist[GSC_MAX_CHANNELS];
+    __shared__ unsigned long long s_lmask[NCLS];
+    const uint16_t *s_lst = reinterpret_cast<const uint16_t *>(s_lstw);
+    const uint16_t *s_opos = reinterpret_cast<const uint16_t *>(s_oposw);
+
+    const uint32_t tid = threadIdx.x, G = gridDim.x, items = m.start[m.F];
+    Frame1 fc;
+    fc.f = ~0u;
+    fc.nk = 0;
+    // the first row of entry tid of an item (clamped where it is stored into s_row, so that
+    // nothing waits for the load before then)
+    auto first_row = [&](const Item1 &it) -> uint32_t {
+        return gp(cp(m.fd[it.f])->first)[it.s + min(tid, it.mlen - 1)];
+    };
+    // row indices read from the workspace are clamped: never an access outside the input
+    auto row_clamp = [&](const Item1 &it, uint32_t r) -> uint32_t {
+        const uint32_t n = cp(m.fd[it.f])->n;
+        return min(r, n ? n - 1 : 0u);
+    };
+    // the channel slice of an item: CH4 chunks per slice, nch of them in this one
+    auto slice = [&](const Item1 &it, uint32_t &CH4, uint32_t &nch) {
+        const uint32_t C4 = cp(m.fd[it.f])->C4;
+        CH4 = pass_chunks(C4, 1);
+        nch = min(CH4, C4 - it.p * CH4);
+    };
+    auto prefetch = [&](const Item1 &it, Sched1 &S, float4 (&D)[NR1]) {
+        CFrame *d = cp(m.fd[it.f]);
+        const bool enc = d->mode == MODE_ENCODE;
+        uint32_t CH4, nch;
+        slice(it, CH4, nch);
+        const Roles R(CH4);
+        load_sched1(d, it, S);
+        if (R.act && R.c4 < nch)
+            load_rows1<VEC>(gp(d->attr), d->C, R, it.p * CH4 + R.c4, it.mlen, enc, s_row, it.s, D);
+    };
+    Item1 it0 = item1(m, blockIdx.x, fc);
+    Item1 it1 = item1(m, blockIdx.x + G, fc);
+    Sched1 S;
+    float4 D[NR1];
+    uint32_t F1 = 0;
+    // prologue: the quantizer steps (shared by the frames of a launch) into LDS, the first
+    // item's rows, schedule and row loads
+    if (tid < GSC_MAX_CHANNELS) {
+        s_st[tid] = cp(m.fd[0])->step[tid];
+        s_ist[tid] = cp(m.fd[0])->inv_step[tid];
+    }
+    if (it0.ok && cp(m.fd[it0.f])->mode == MODE_ENCODE) s_row[tid] = row_clamp(it0, first_row(it0));
+    if (it1.ok && cp(m.fd[it1.f])->mode == MODE_ENCODE) F1 = first_row(it1);
+    __syncthreads();
+    if (it0.ok) prefetch(it0, S, D);
+
+    for (uint32_t i = blockIdx.x; i < items; i += G) {
+        CFrame *d = cp(m.fd[it0.f]);
+        const bool encode = d->mode == MODE_ENCODE;
+        uint32_t CH4, nch;
+        slice(it0, CH4, nch);
+        const Roles R(CH4);
+        const uint32_t c4 = it0.p * CH4 + R.c4;  // this thread's global channel chunk
+        const bool live = it0.ok && R.act && R.c4 < nch;
+        const uint32_t C = d->C, n = d->n;
+        const uint32_t obase = S.obase, ocnt = S.ocnt;
+        __syncthreads();  // the previous item is no longer read from LDS
+        // ---- the current item's schedule and rows into LDS, the next item's first rows; on
+        // every path, whether or not the item is ok (see commit_sched1)
+        commit_sched1(S, it0, n, s_rec, s_ab, s_lstw, s_oposw, s_m0);
+        const uint32_t sink = RT * CH4;
+#pragma unroll
+        for (int u = 0; u < NR1; ++u) {
+            const uint32_t j = R.row0 + (uint32_t)u * R.RPB;
+            s_y[live && j < it0.mlen ? j * CH4 + R.c4 : sink] = D[u];
+        }
+        s_row[tid] = row_clamp(it1, F1);
+        __syncthreads();
+        // ---- prefetch: the next item's schedule and rows, the first rows of the one after
+        const Item1 it2 = item1(m, i + 2 * G, fc);
+        if (it1.ok) prefetch(it1, S, D);
+        if (it2.ok && cp(m.fd[it2.f])->mode == MODE_ENCODE) F1 = first_row(it2);
+        // ---- the current item
+        if (it0.ok) {
+            const uint32_t mlen = it0.mlen, s = it0.s;
+            const uint32_t nlast = n ? n - 1 : 0u;
+            // this thread's rows j = row0 + t RPB sit at LDS index y0 + t ystep
+            const uint32_t y0 = R.row0 * CH4 + R.c4, ystep = R.RPB * CH4;
+            if (encode && live) {
+                // merge duplicates: the mean of the rows of the Gaussians in the voxel
+                // (Sec. 2.1), summed in input order (the sort is stable)
+                const GAS float *attr = gp(d->attr);
+                const GAS uint32_t *perm = gp((d->P & 1) ? d->vals_b : d->vals_a);
+                for (uint32_t j = R.row0, yi = y0; j < mlen; j += R.RPB, yi += ystep) {
+                    const uint32_t m0 = s_m0[j], m1 = s_m0[j + 1];
+                    if (m1 - m0 <= 1) continue;
+                    float4 acc = s_y[yi];
+                    for (uint32_t mm = m0 + 1; mm < m1; ++mm) {
+                        const float4 x = ld4<VEC>(attr, min(perm[mm], nlast), C, c4);
+                        acc.x += x.x;
+                        acc.y += x.y;
+                        acc.z += x.z;
+                        acc.w += x.w;
+                    }
+                    const float cnt = (float)(m1 - m0);
+                    acc.x /= cnt;
+                    acc.y /= cnt;
+                    acc.z /= cnt;
+                    acc.w /= cnt;
+                    s_y[yi] = acc;
+                }
+                if (d->ste == STE_FORWARD && d->aref) {
+                    GAS float *ar = gp(d->aref);
+                    for (uint32_t j = R.row0, yi = y0; j < mlen; j += R.RPB, yi += ystep)
+                        st4<VEC>(ar, s + j, C, c4, s_y[yi]);
+                }
+            }
+            level_masks(s_lst, s_lmask);
+            const uint64_t wmask = s_lmask[R.w], xmask = s_lmask[CROSS];
+            wave_phase(s_y, R, s_rec, s_ab, s_lst, wmask, nch, false);
+            __syncthreads();
+            block_phase(s_y, R, s_rec, s_ab, s_lst, xmask, nch, false);
+            if (live) {
+                GAS float *cf = gp(d->coef_f32);
+                if (encode) {
+                    const CAS Ctrl *ctrl = cp(d->ctrl);
+                    uint64_t off = GSC_HEADER_BYTES, run = 0;
+                    for (uint32_t dd = 0; dd < d->J; ++dd) {
+                        run += ctrl->hist_D[dd];
+                        off += run;
+                    }
+                    GAS int32_t *coef = gp(reinterpret_cast<int32_t *>(d->stream + align_up(off, 256)));
+                    const double omt = 1.0 - (double)d->tau;
+                    const bool deq = d->ste == STE_FORWARD;  // float output: q * step instead of y
+                    float st[4], ist[4];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const uint32_t c = min(4 * c4 + q, C - 1);
+                        st[q] = s_st[c];
+                        ist[q] = s_ist[c];
+                    }
+                    for (uint32_t j = R.row0, yi = y0; j < mlen; j += R.RPB, yi += ystep) {
+                        const float4 y = s_y[yi];
+                        const int4 q = make_int4(quant1<POW2>(y.x, st[0], ist[0], omt), quant1<POW2>(y.y, st[1], ist[1], omt),
+                                                 quant1<POW2>(y.z, st[2], ist[2], omt), quant1<POW2>(y.w, st[3], ist[3], omt));
+                        stq4<VEC>(coef, s + j, C, c4, q);
+                        if (cf)
+                            st4<VEC>(cf, s + j, C, c4,
+                                     deq ? make_float4((float)q.x * st[0], (float)q.y * st[1], (float)q.z * st[2],
+                                                       (float)q.w * st[3])
+                                         : y);
+                    }
+                } else {  // MODE_FWD_F32: float coefficient rows
+                    for (uint32_t j = R.row0, yi = y0; j < mlen; j += R.RPB, yi += ystep) st4<VEC>(cf, s + j, C, c4, s_y[yi]);
+                }
+                if (!it0.final_level) {
+                    GAS float *dst = gp(d->lv[1].vbuf);
+                    const uint32_t C4 = d->C4;
+                    for (uint32_t o = R.row0; o < ocnt; o += R.RPB)
+                        gstore4(dst + ((size_t)(obase + o) * C4 + c4) * 4, s_y[s_opos[o] * CH4 + R.c4]);
+                }
+            }
+        }
+        it0 = it1;
+        it1 = it2;
+    }
+}
+
+// ============================================================ first level, persistent inverse
+// The same persistent, prefetching scheme for the first level of the inverse: while one item's
+// merges are undone and its rows stored, the next item's schedule, coefficient rows (read as raw
+// 32-bit words, dequantized when they are committed to LDS) and the low-passes of its open
+// entries (from S_2) are in flight in registers.
+constexpr int NO1 = 2;  // open entries per thread: OPEN_CAP <= 2 RPB for slices of <= 8 chunks
+static_assert(OPEN_CAP <= NO1 * (RT / CH4_MAX1), "NO1 covers the open entries of a tile");
+
+template <bool VEC>
+__global__ __launch_bounds__(RAHT_THREADS) void k_raht_inv1(TileMap m)
+{
+    extern __shared__ float4 s_y[];
+    __shared__ uint32_t s_rec[RT];
+    __shared__ float2 s_ab[RT];
+    __shared__ uint32_t s_lstw[LSTART_N / 2 + 1];   // u16 segment starts, in pairs; + sink
+    __shared__ uint32_t s_oposw[OPEN_CAP / 2 + 1];  // u16 open positions, in pairs; + sink
+    __shared__ uint32_t s_m0[RT + 2];               // (written by the shared commit, unused)
+    __shared__ float s_st[GSC_MAX_CHANNELS];        // dequantization steps of the frame s_stf
+    __shared__ unsigned long long s_lmask[NCLS];
+    const uint16_t *s_lst = reinterpret_cast<const uint16_t *>(s_lstw);
+    const uint16_t *s_opos = reinterpret_cast<const uint16_t *>(s_oposw);
+
+    const uint32_t tid = threadIdx.x, G = gridDim.x, items = m.start[m.F];
+    Frame1 fc;
+    fc.f = ~0u;
+    fc.nk = 0;
+    auto slice = [&](const Item1 &it, uint32_t &CH4, uint32_t &nch) {
+        const uint32_t C4 = cp(m.fd[it.f])->C4;
+        CH4 = pass_chunks(C4, 1);
+        nch = min(CH4, C4 - it.p * CH4);
+    };
+    // the coefficient rows of an item: the stream's quantized rows (decode) or float rows
+    auto coef_rows = [&](CFrame *d) -> const GAS float * {
+        if (d->mode == MODE_DECODE) {
+            const CAS gsc_header *h = cp(reinterpret_cast<const gsc_header *>(d->in_stream));
+            return reinterpret_cast<const GAS float *>(gp(d->in_stream + h->coef_offset));
+        }
+        return gp(d->mode == MODE_ENCODE ? d->coef_f32 : d->attr);
+    };
+    auto prefetch = [&](const Item1 &it, Sched1 &S, float4 (&D)[NR1], float4 (&O)[NO1]) {
+        CFrame *d = cp(m.fd[it.f]);
+        uint32_t CH4, nch;
+        slice(it, CH4, nch);
+        const Roles R(CH4);
+        load_sched1(d, it, S);
+        if (R.act && R.c4 < nch) {
+            const uint32_t c4 = it.p * CH4 + R.c4;
+            load_rows1<VEC>(coef_rows(d), d->C, R, c4, it.mlen, false, nullptr, it.s, D);
+            if (!it.final_level && S.ocnt > 0) {
+                const GAS float *src = gp(d->lv[1].vbuf);
+#pragma unroll
+                for (int u = 0; u < NO1; ++u) {
+                    const uint32_t o = min(R.row0 + (uint32_t)u * R.RPB, S.ocnt - 1);
+                    O[u] = gload4(src + ((size_t)(S.obase + o) * d->C4 + c4) * 4);
+                }
+            }
+        }
+    };
+    Item1 it0 = item1(m, blockIdx.x, fc);
+    Item1 it1 = item1(m, blockIdx.x + G, fc);
+    Sched1 S;
+    float4 D[NR1], O[NO1];
+    uint32_t stf = ~0u;  // frame whose steps are in s_st
+    if (it0.ok) prefetch(it0, S, D, O);
+
+    for (uint32_t i = blockIdx.x; i < items; i += G) {
+        CFrame *d = cp(m.fd[it0.f]);
+        const bool decode = d->mode == MODE_DECODE;
+        uint32_t CH4, nch;
+        slice(it0, CH4, nch);
+        const Roles R(CH4);
+        const uint32_t c4 = it0.p * CH4 + R.c4;
+        const bool live = it0.ok && R.act && R.c4 < nch;
+        const uint32_t C = d->C;
+        const uint32_t ocnt = S.ocnt;
+        const bool has_open = it0.ok && !it0.final_level && ocnt > 0;
+        if (decode && it0.f != stf) {  // the frame's dequantization steps (once per frame)
+            stf = it0.f;
+            const CAS gsc_header *h = cp(reinterpret_cast<const gsc_header *>(d->in_stream));
+            if (tid < GSC_MAX_CHANNELS) s_st[tid] = h->quant_step[tid];
+        }
+        __syncthreads();  // the previous item is no longer read from LDS; s_st is written
+        // ---- the current item's schedule and coefficient rows into LDS (branch-free, see
+        // commit_sched1)
+        commit_sched1(S, it0, d->n, s_rec, s_ab, s_lstw, s_oposw, s_m0);
+        {
+            float st[4] = {1.f, 1.f, 1.f, 1.f};
+            if (decode)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) st[q] = s_st[min(4 * c4 + q, C - 1)];
+            const uint32_t sink = RT * CH4;
+#pragma unroll
+            for (int u = 0; u < NR1; ++u) {
+                const uint32_t j = R.row0 + (uint32_t)u * R.RPB;
+                float4 v = D[u];
+                if (decode)
+                    v = make_float4((float)__float_as_int(v.x) * st[0], (float)__float_as_int(v.y) * st[1],
+                                    (float)__float_as_int(v.z) * st[2], (float)__float_as_int(v.w) * st[3]);
+                s_y[live && j < it0.mlen ? j * CH4 + R.c4 : sink] = v;
+            }
+        }
+        __syncthreads();
+        // ---- open entries take the low-pass handed down by S_2 (also branch-free)
+        {
+            const uint32_t sink = RT * CH4;
+#pragma unroll
+            for (int u = 0; u < NO1; ++u) {
+                const uint32_t o = R.row0 + (uint32_t)u * R.RPB;
+                const bool w = live && has_open && o < ocnt;
+                s_y[w ? s_opos[min(o, (uint32_t)OPEN_CAP - 1)] * CH4 + R.c4 : sink] = O[u];
+            }
+        }
+        // ---- prefetch the next item
+        const Item1 it2 = item1(m, i + 2 * G, fc);
+        if (it1.ok) prefetch(it1, S, D, O);
+        // ---- the current item: all local merges undone, across chunks, then within chunks
+        if (it0.ok) {
+            level_masks(s_lst, s_lmask);  // (its barrier also orders the open-entry writes)
+            const uint64_t wmask = s_lmask[R.w], xmask = s_lmask[CROSS];
+            block_phase(s_y, R, s_rec, s_ab, s_lst, xmask, nch, true);
+            wave_phase(s_y, R, s_rec, s_ab, s_lst, wmask, nch, true);
+            __syncthreads();
+            if (live) {
+                const uint32_t mlen = it0.mlen, s = it0.s;
+                const uint32_t y0 = R.row0 * CH4 + R.c4, ystep = R.RPB * CH4;
+                if (d->mode == MODE_STE_BWD) {
+                    // voxel gradient = synthesized rows + the added rows; each member Gaussian
+                    // receives it divided by the member count (the voxel row is the members' mean)
+                    GAS float *out = gp(d->attr_out);
+                    const GAS float *ga = gp(d->grad_add);
+                    const GAS uint32_t *vh = gp(d->vh);
+                    const GAS uint32_t *perm = gp((d->P & 1) ? d->vals_b : d->vals_a);
+                    const uint32_t n = d->n, nlast = n ? n - 1 : 0u;
+                    for (uint32_t j = R.row0, yi = y0; j < mlen; j += R.RPB, yi += ystep) {
+                        const uint32_t v = s + j;
+                        const float4 a = s_y[yi];
+                        const float4 b = ld4<VEC>(ga, v, C, c4);
+                        const uint32_t m0 = min(vh[v], n), m1 = min(vh[v + 1], n);
+                        const float cnt = (float)(m1 - m0);
+                        const float4 g = make_float4((a.x + b.x) / cnt, (a.y + b.y) / cnt, (a.z + b.z) / cnt,
+                                                     (a.w + b.w) / cnt);
+                        for (uint32_t mm = m0; mm < m1; ++mm) st4<VEC>(out, min(perm[mm], nlast), C, c4, g);
+                    }
+                } else {
+                    GAS float *out = gp(d->mode == MODE_ADJ_F32 ? d->coef_f32 : d->attr_out);
+                    for (uint32_t j = R.row0, yi = y0; j < mlen; j += R.RPB, yi += ystep)
+                        st4<VEC>(out, s + j, C, c4, s_y[yi]);
+                }
+            }
+        }
+        it0 = it1;
+        it1 = it2;
+    }
+}
+
 // ==================================================================== inverse transform
 template <bool VEC>
 __global__ __launch_bounds__(RAHT_THREADS) void k_raht_inv(TileMap m, int k)
@@ -767,12 +1220,41 @@ __global__ __launch_bounds__(RAHT_THREADS) void k_raht_inv(TileMap m, int k)
     }
 }
 
-size_t raht_lds_bytes(int C4, int k) { return (size_t)RT * pass_chunks((uint32_t)C4, k) * sizeof(float4); }
+// Dynamic LDS of a transform launch: the slice of RT entries, plus one sink slot for writes that
+// are masked off by address rather than by branch.
+size_t raht_lds_bytes(int C4, int k) { return ((size_t)RT * pass_chunks((uint32_t)C4, k) + 1) * sizeof(float4); }
+
+// Workgroups of a persistent first-level launch over `items` items: at most two per CU (the
+// LDS of one item slice allows two), a multiple of 8 NP, and as few as give every workgroup
+// the same number of items, up to one.
+uint32_t persist_grid(uint32_t items, int C4)
+{
+    static int cus = 0;
+    if (cus == 0) {
+        int dev = 0, v = 0;
+        if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v <= 0)
+            v = 256;
+        cus = v;
+    }
+    const uint32_t unit = 8 * channel_passes((uint32_t)C4, 1);
+    const uint32_t gmax = (2u * (uint32_t)cus) / unit * unit;
+    if (items <= gmax) return items;
+    const uint32_t rounds = ceil_div(items, gmax);
+    return ceil_div(ceil_div(items, rounds), unit) * unit;
+}
 
 hipError_t launch_raht_fwd(const TileMap &m, int k, const RahtCfg &cfg, hipStream_t s)
 {
-    const dim3 grid(m.start[m.F]), block(RAHT_THREADS);
     const size_t lds = raht_lds_bytes(cfg.C4, k);
+    if (k == 1) {
+        const dim3 grid(persist_grid(m.start[m.F], cfg.C4)), block(RAHT_THREADS);
+        if (cfg.vec && cfg.pow2) hipLaunchKernelGGL((k_raht_fwd1<true, true>), grid, block, lds, s, m);
+        else if (cfg.vec) hipLaunchKernelGGL((k_raht_fwd1<true, false>), grid, block, lds, s, m);
+        else if (cfg.pow2) hipLaunchKernelGGL((k_raht_fwd1<false, true>), grid, block, lds, s, m);
+        else hipLaunchKernelGGL((k_raht_fwd1<false, false>), grid, block, lds, s, m);
+        return hipGetLastError();
+    }
+    const dim3 grid(m.start[m.F]), block(RAHT_THREADS);
     if (cfg.vec && cfg.pow2) hipLaunchKernelGGL((k_raht_fwd<true, true>), grid, block, lds, s, m, k);
     else if (cfg.vec) hipLaunchKernelGGL((k_raht_fwd<true, false>), grid, block, lds, s, m, k);
     else if (cfg.pow2) hipLaunchKernelGGL((k_raht_fwd<false, true>), grid, block, lds, s, m, k);
@@ -782,8 +1264,14 @@ hipError_t launch_raht_fwd(const TileMap &m, int k, const RahtCfg &cfg, hipStrea
 
 hipError_t launch_raht_inv(const TileMap &m, int k, const RahtCfg &cfg, hipStream_t s)
 {
-    const dim3 grid(m.start[m.F]), block(RAHT_THREADS);
     const size_t lds = raht_lds_bytes(cfg.C4, k);
+    if (k == 1) {
+        const dim3 grid(persist_grid(m.start[m.F], cfg.C4)), block(RAHT_THREADS);
+        if (cfg.vec) hipLaunchKernelGGL((k_raht_inv1<true>), grid, block, lds, s, m);
+        else hipLaunchKernelGGL((k_raht_inv1<false>), grid, block, lds, s, m);
+        return hipGetLastError();
+    }
+    const dim3 grid(m.start[m.F]), block(RAHT_THREADS);
     if (cfg.vec) hipLaunchKernelGGL((k_raht_inv<true>), grid, block, lds, s, m, k);
     else hipLaunchKernelGGL((k_raht_inv<false>), grid, block, lds, s, m, k);
     return hipGetLastError();
