@@ -454,4 +454,23 @@ __device__ inline int32_t quantize(float y, float step, float inv_step, double o
     return y < 0.0f ? -q : q;
 }
 
+// The smallest float not below x > 0: for a float f, f >= x exactly when f >= ceil_float(x).
+__device__ inline float ceil_float(double x)
+{
+    float f = (float)x;
+    if ((double)f < x) f = __uint_as_float(__float_as_uint(f) + 1u);
+    return f;
+}
+
+// The power-of-two case of `quantize` with the FP64 comparison replaced by the equivalent float
+// one: the fractional part t - floor(t) is a float, so it reaches 1 - tau exactly when it reaches
+// thr = ceil_float(1 - tau).
+__device__ inline int32_t quantize_pow2(float y, float inv_step, float thr)
+{
+    const float t = fabsf(y) * inv_step;
+    const float f = floorf(t);
+    const int32_t q = (int32_t)f + ((t - f) >= thr ? 1 : 0);
+    return y < 0.0f ? -q : q;
+}
+
 }  // namespace gsc

@@ -63,7 +63,7 @@ struct Ctrl {
     uint32_t dec_start;          // decoder: first level handled by the per-level kernels
     uint32_t n_in;
     uint32_t bbox_ord[6];        // order-preserving uint of float: min x,y,z, max x,y,z
-    uint32_t tile_ctr[96];       // reserved
+    uint32_t reserved[96];
     uint32_t hist_D[32];         // voxels whose new-node depth is D, D = 0..J
     uint32_t lvl_n[MAXK + 2];    // sizes of the RAHT entry sequences, index k = 1..MAXK+1
     uint32_t level_sizes[32];    // |L_d|
@@ -96,6 +96,7 @@ struct RahtLevel {
     uint8_t *s_lvl;      // k >= 2: binary level of each entry
     uint32_t *rec;       // per tile: RT merge records, sorted by level
     uint16_t *lstart;    // per tile: LSTART_N starts of the (level, class) record segments
+    uint64_t *lmask;     // per tile: NCLS masks, bit x of mask c set when segment (x, c) is non-empty
     uint16_t *opos;      // per tile: OPEN_CAP positions of open entries
     uint32_t *obase;     // per tile: index in S_{k+1} of its first open entry
     uint32_t *ocnt;      // per tile: open entries
@@ -210,7 +211,7 @@ struct Layout {
     uint32_t dec_status_off[GSC_MAX_DEPTH + 1];
     uint32_t dec_tiles[GSC_MAX_DEPTH + 1];
     uint32_t sort_tiles, dedup_tiles, occ_tiles, P, K;
-    size_t s_idx[MAXK + 1], s_lvl[MAXK + 1], rec[MAXK + 1], lstart[MAXK + 1], opos[MAXK + 1],
+    size_t s_idx[MAXK + 1], s_lvl[MAXK + 1], rec[MAXK + 1], lstart[MAXK + 1], lmask[MAXK + 1], opos[MAXK + 1],
         obase[MAXK + 1], ocnt[MAXK + 1], status[MAXK + 1], vbuf[MAXK + 1];
     uint32_t tiles[MAXK + 1], cap[MAXK + 1];
 };
@@ -293,6 +294,7 @@ __host__ __device__ inline bool make_layout(int64_t n, int J, int C, Layout *L)
         L->s_lvl[k] = off; off = align_up(off + (size_t)L->cap[k], 256);
         L->rec[k] = off; off = align_up(off + (size_t)t * RT * 4, 256);
         L->lstart[k] = off; off = align_up(off + (size_t)t * LSTART_N * 2, 256);
+        L->lmask[k] = off; off = align_up(off + (size_t)t * NCLS * 8, 256);
         L->opos[k] = off; off = align_up(off + (size_t)t * OPEN_CAP * 2, 256);
         L->obase[k] = off; off = align_up(off + (size_t)t * 4, 256);
         L->ocnt[k] = off; off = align_up(off + (size_t)t * 4, 256);

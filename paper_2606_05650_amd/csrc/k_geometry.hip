@@ -74,6 +74,7 @@ __global__ __launch_bounds__(256) void k_setup(SetupArgs a)
             lv.s_lvl = reinterpret_cast<uint8_t *>(fa.ws + L.s_lvl[k]);
             lv.rec = reinterpret_cast<uint32_t *>(fa.ws + L.rec[k]);
             lv.lstart = reinterpret_cast<uint16_t *>(fa.ws + L.lstart[k]);
+            lv.lmask = reinterpret_cast<uint64_t *>(fa.ws + L.lmask[k]);
             lv.opos = reinterpret_cast<uint16_t *>(fa.ws + L.opos[k]);
             lv.obase = reinterpret_cast<uint32_t *>(fa.ws + L.obase[k]);
             lv.ocnt = reinterpret_cast<uint32_t *>(fa.ws + L.ocnt[k]);
@@ -86,6 +87,7 @@ __global__ __launch_bounds__(256) void k_setup(SetupArgs a)
             lv.s_lvl = nullptr;
             lv.rec = nullptr;
             lv.lstart = nullptr;
+            lv.lmask = nullptr;
             lv.opos = nullptr;
             lv.obase = nullptr;
             lv.ocnt = nullptr;

@@ -146,6 +146,13 @@ __global__ __launch_bounds__(PRE_BLOCK) void k_prelude(TileMap m, int k)
     }
     if (is_local) atomicAdd(&s_cnt[g][lvl * NCLS + cls], 1u);
     __syncthreads();
+    if (j < WAVE && s < nk) {  // level masks of the classes: lane x tests level x
+#pragma unroll
+        for (uint32_t c = 0; c < (uint32_t)NCLS; ++c) {
+            const uint64_t b = __ballot(s_cnt[g][j * NCLS + c] != 0);
+            if (j == 0) gp(lv.lmask)[(size_t)tile * NCLS + c] = b;
+        }
+    }
     {   // segment starts of each tile: exclusive scan of its SEG_N counts (two per thread)
         const uint32_t i0 = 2 * j, i1 = 2 * j + 1;
         const uint32_t a0 = i0 < (uint32_t)SEG_N ? s_cnt[g][i0] : 0u;
@@ -210,11 +217,13 @@ struct TileSched {
     bool final_level;
 };
 
-// Loads the tile's schedule into LDS and computes (a, b) of every local merge. Returns false if
-// the workgroup has nothing to do.
+// Loads the schedule of a tile of an upper level (k >= 2) into LDS: segment starts, level masks,
+// open positions, voxel indices of the entries, and the records with (a, b) of every local merge.
+// Returns false if the workgroup has nothing to do.
 __device__ inline bool load_schedule(const FrameDesc &fd, Ctrl *ctrl, int k, uint32_t tile,
                                      TileSched &ts, uint32_t *s_rec, float2 *s_ab,
-                                     uint16_t *s_lst, uint16_t *s_opos, uint32_t *s_idx)
+                                     uint16_t *s_lst, uint16_t *s_opos, uint32_t *s_idx,
+                                     unsigned long long *s_lmask)
 {
     const uint32_t nk = seq_size(fd, ctrl, k);
     if (!seq_active(nk, k)) return false;
@@ -234,38 +243,22 @@ __device__ inline bool load_schedule(const FrameDesc &fd, Ctrl *ctrl, int k, uin
     const GAS uint32_t *sidx = gp(lv.s_idx), *recs = gp(lv.rec);
     for (uint32_t x = tid; x < (uint32_t)LSTART_N; x += NT) s_lst[x] = lstart[(size_t)tile * LSTART_N + x];
     for (uint32_t o = tid; o < ts.ocnt; o += NT) s_opos[o] = opos[(size_t)tile * OPEN_CAP + o];
-    if (k >= 2) {  // voxel indices, clamped to the frame's capacity like every row index read
-                   // from the workspace
-        const uint32_t cap = fd.n;
-        for (int j = tid; j < ts.mlen; j += NT) s_idx[j] = min(sidx[s + j], cap ? cap - 1 : 0u);
-        if (tid == 0) s_idx[ts.mlen] = min(ts.e < nk ? sidx[ts.e] : ctrl->n_vox, cap);
-    }
+    if (tid < (uint32_t)NCLS) s_lmask[tid] = gp(lv.lmask)[(size_t)tile * NCLS + tid];
+    // voxel indices, clamped to the frame's capacity like every row index read from the workspace
+    const uint32_t cap = fd.n;
+    for (int j = tid; j < ts.mlen; j += NT) s_idx[j] = min(sidx[s + j], cap ? cap - 1 : 0u);
+    if (tid == 0) s_idx[ts.mlen] = min(ts.e < nk ? sidx[ts.e] : ctrl->n_vox, cap);
     __syncthreads();
     ts.nrec = s_lst[SEG_N - 1];
     for (uint32_t q = tid; q < ts.nrec; q += NT) {
         const uint32_t rec = recs[(size_t)tile * RT + q];
         s_rec[q] = rec;
-        const uint32_t j = rec & 1023u, l = (rec >> 10) & 1023u, r = rec >> 20;
-        uint32_t ij, il, ir;
-        if (k == 1) {
-            ij = j;
-            il = l;
-            ir = r;
-        } else {
-            ij = s_idx[j];
-            il = s_idx[l];
-            ir = s_idx[r];
-        }
+        const uint32_t ij = s_idx[rec & 1023u], il = s_idx[(rec >> 10) & 1023u], ir = s_idx[rec >> 20];
         const float w0 = (float)(ij - il), w1 = (float)(ir - ij);
         const float sum = w0 + w1;
         s_ab[q] = make_float2(sqrtf(w0 / sum), sqrtf(w1 / sum));
     }
     return true;
-}
-
-__device__ inline uint32_t entry_index(int k, const uint32_t *s_idx, uint32_t s, int j)
-{
-    return k == 1 ? s + (uint32_t)j : s_idx[j];
 }
 
 // One butterfly on channels [4*c4, 4*c4+4) of merge record `rec`.
@@ -319,82 +312,106 @@ struct Roles {
     }
 };
 
-// Non-empty (level, class) segments of the tile as one 64-bit level mask per class, so that the
-// merge phases visit only the levels that hold merges.
-__device__ inline void level_masks(const uint16_t *s_lst, unsigned long long *s_lmask)
+// The next level to visit in a mask of levels: ascending (forward) or descending (inverse).
+__device__ inline uint32_t next_level(uint64_t mask, bool inverse)
 {
-    // wave 0: lane x tests level x of every class; one ballot per class gives its mask
-    if (threadIdx.x < WAVE) {
-        const uint32_t x = threadIdx.x;
-        for (uint32_t c = 0; c < (uint32_t)NCLS; ++c) {
-            const uint32_t i = x * NCLS + c;
-            const uint64_t b = __ballot(s_lst[i] != s_lst[i + 1]);
-            if (x == 0) s_lmask[c] = b;
-        }
-    }
-    __syncthreads();
+    return inverse ? (uint32_t)msb64(mask) : (uint32_t)(__ffsll((long long)mask) - 1);
 }
 
-// Merges local to this wave's chunk, levels ascending (forward) or descending (inverse). The
-// wave's own LDS accesses are performed in program order; the fence keeps the compiler from
+// A value that is the same in every lane, said so to the compiler, so that a loop over its bits
+// runs on the scalar unit.
+__device__ inline uint64_t uniform64(uint64_t v)
+{
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// Merges local to this wave's chunk, levels ascending (forward) or descending (inverse). Lane x
+// holds the record range of level x in registers (read out with readlane), and each level's first
+// record of a lane is loaded while the previous level runs, so a level costs one LDS round trip.
+// The wave's own LDS accesses are performed in program order; the fence keeps the compiler from
 // moving one level's accesses across the next level's. Only channel chunks below nch are live.
 __device__ inline void wave_phase(float4 *s_y, const Roles &R, const uint32_t *s_rec,
                                   const float2 *s_ab, const uint16_t *s_lst, uint64_t mask,
                                   uint32_t nch, bool inverse)
 {
     const bool live = R.wact && R.wc4 < nch;
+    const uint32_t lane = lane_id();
+    const uint32_t lq0 = s_lst[lane * NCLS + R.w], lq1 = s_lst[lane * NCLS + R.w + 1];
+    mask = uniform64(mask);  // the wave's own class: one mask per wave
+    uint32_t x = mask ? next_level(mask, inverse) : 0u;
+    uint32_t q0 = __builtin_amdgcn_readlane(lq0, x), q1 = __builtin_amdgcn_readlane(lq1, x);
+    uint32_t rec = 0;
+    float2 ab = make_float2(0.f, 0.f);
+    if (live && q0 + R.wq < q1) {
+        rec = s_rec[q0 + R.wq];
+        ab = s_ab[q0 + R.wq];
+    }
     while (mask) {
-        const uint32_t x = inverse ? (uint32_t)msb64(mask) : (uint32_t)(__ffsll((long long)mask) - 1);
         mask &= ~(1ull << x);
-        const uint32_t q0 = s_lst[x * NCLS + R.w], q1 = s_lst[x * NCLS + R.w + 1];
-        if (live)
-            for (uint32_t q = q0 + R.wq; q < q1; q += R.MPW)
+        const uint32_t xn = mask ? next_level(mask, inverse) : 0u;
+        const uint32_t q0n = __builtin_amdgcn_readlane(lq0, xn), q1n = __builtin_amdgcn_readlane(lq1, xn);
+        uint32_t recn = 0;
+        float2 abn = make_float2(0.f, 0.f);
+        if (mask && live && q0n + R.wq < q1n) {
+            recn = s_rec[q0n + R.wq];
+            abn = s_ab[q0n + R.wq];
+        }
+        if (live && q0 + R.wq < q1) {
+            butterfly(s_y, R.C4, rec, ab, R.wc4, inverse);
+            for (uint32_t q = q0 + R.wq + R.MPW; q < q1; q += R.MPW)
                 butterfly(s_y, R.C4, s_rec[q], s_ab[q], R.wc4, inverse);
+        }
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
         __builtin_amdgcn_wave_barrier();
+        x = xn;
+        q0 = q0n;
+        q1 = q1n;
+        rec = recn;
+        ab = abn;
     }
 }
 
-// Merges crossing chunks, level by level with workgroup barriers.
+// Merges crossing chunks, level by level with workgroup barriers; record ranges in registers and
+// each level's first records loaded one level ahead, as in wave_phase.
 __device__ inline void block_phase(float4 *s_y, const Roles &R, const uint32_t *s_rec,
                                    const float2 *s_ab, const uint16_t *s_lst, uint64_t mask,
                                    uint32_t nch, bool inverse)
 {
     const bool live = R.act && R.c4 < nch;
-    while (mask) {
-        const uint32_t x = inverse ? (uint32_t)msb64(mask) : (uint32_t)(__ffsll((long long)mask) - 1);
-        mask &= ~(1ull << x);
-        const uint32_t q0 = s_lst[x * NCLS + CROSS], q1 = s_lst[x * NCLS + CROSS + 1];
-        if (live)
-            for (uint32_t q = q0 + R.row0; q < q1; q += R.RPB)
-                butterfly(s_y, R.C4, s_rec[q], s_ab[q], R.c4, inverse);
-        __syncthreads();
+    const uint32_t lane = lane_id();
+    const uint32_t lq0 = s_lst[lane * NCLS + CROSS], lq1 = s_lst[lane * NCLS + CROSS + 1];
+    mask = uniform64(mask);
+    uint32_t x = mask ? next_level(mask, inverse) : 0u;
+    uint32_t q0 = __builtin_amdgcn_readlane(lq0, x), q1 = __builtin_amdgcn_readlane(lq1, x);
+    uint32_t rec = 0;
+    float2 ab = make_float2(0.f, 0.f);
+    if (live && q0 + R.row0 < q1) {
+        rec = s_rec[q0 + R.row0];
+        ab = s_ab[q0 + R.row0];
     }
-}
-
-// Every merge of the tile, levels ascending (forward) or descending (inverse), with wave w
-// transforming the channel chunks w, w + NW, ... of the slice and one merge per lane. Waves
-// never touch the same LDS element, so no workgroup barrier is needed between levels; within a
-// wave the LDS accesses are performed in program order (the fence keeps the compiler from
-// moving one level's accesses across the next level's). The records of a level are contiguous
-// (sorted by level, then class), so all classes of level x are [lst[x*NCLS], lst[x*NCLS+NCLS]).
-__device__ inline void chan_phase(float4 *s_y, uint32_t CH4, const uint32_t *s_rec,
-                                  const float2 *s_ab, const uint16_t *s_lst, uint64_t mask,
-                                  uint32_t nch, bool inverse)
-{
-    constexpr uint32_t NW = RAHT_THREADS / WAVE;
-    const uint32_t w = threadIdx.x / WAVE, lane = lane_id();
     while (mask) {
-        const uint32_t x = inverse ? (uint32_t)msb64(mask) : (uint32_t)(__ffsll((long long)mask) - 1);
         mask &= ~(1ull << x);
-        const uint32_t q0 = s_lst[x * NCLS], q1 = s_lst[x * NCLS + NCLS];
-        for (uint32_t q = q0 + lane; q < q1; q += WAVE) {
-            const uint32_t rec = s_rec[q];
-            const float2 ab = s_ab[q];
-            for (uint32_t c = w; c < nch; c += NW) butterfly(s_y, CH4, rec, ab, c, inverse);
+        const uint32_t xn = mask ? next_level(mask, inverse) : 0u;
+        const uint32_t q0n = __builtin_amdgcn_readlane(lq0, xn), q1n = __builtin_amdgcn_readlane(lq1, xn);
+        uint32_t recn = 0;
+        float2 abn = make_float2(0.f, 0.f);
+        if (mask && live && q0n + R.row0 < q1n) {
+            recn = s_rec[q0n + R.row0];
+            abn = s_ab[q0n + R.row0];
         }
-        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-        __builtin_amdgcn_wave_barrier();
+        if (live && q0 + R.row0 < q1) {
+            butterfly(s_y, R.C4, rec, ab, R.c4, inverse);
+            for (uint32_t q = q0 + R.row0 + R.RPB; q < q1; q += R.RPB)
+                butterfly(s_y, R.C4, s_rec[q], s_ab[q], R.c4, inverse);
+        }
+        __syncthreads();
+        x = xn;
+        q0 = q0n;
+        q1 = q1n;
+        rec = recn;
+        ab = abn;
     }
 }
 
@@ -453,11 +470,12 @@ __device__ inline void stq4(GAS int32_t *base, uint64_t row, uint32_t C, uint32_
 }
 
 // q = sgn(y) floor(|y|/step + tau) with the exact decision of `quantize` (gsc_device.h);
-// POW2: every step is a power of two, so the quotient is an exact float multiply.
+// POW2: every step is a power of two, so the quotient is an exact float multiply and the decision
+// a float comparison with thr = ceil_float(1 - tau).
 template <bool POW2>
-__device__ inline int32_t quant1(float y, float step, float inv_step, double omt)
+__device__ inline int32_t quant1(float y, float step, float inv_step, double omt, float thr)
 {
-    return quantize(y, step, inv_step, omt, POW2);
+    return POW2 ? quantize_pow2(y, inv_step, thr) : quantize(y, step, inv_step, omt, false);
 }
 
 constexpr int UNROLL = 8;  // independent row loads in flight per thread
@@ -523,9 +541,11 @@ uint32_t raht_blocks(uint32_t tiles, int k, int C4)
     return (tiles + 7) / 8 * 8 * channel_passes((uint32_t)C4, k);
 }
 
-// ==================================================================== forward transform
+// ============================================================== upper levels, forward
+// One workgroup per (tile, channel slice) of S_k, k >= 2: the entries' partial low-passes come
+// from S_{k-1}'s open-entry rows, each entry's coefficient row goes to its voxel's row.
 template <bool VEC, bool POW2>
-__global__ __launch_bounds__(RAHT_THREADS) void k_raht_fwd(TileMap m, int k)
+__global__ __launch_bounds__(RAHT_THREADS) void k_raht_fwd_up(TileMap m, int k)
 {
     extern __shared__ float4 s_y[];
     __shared__ uint32_t s_rec[RT];
@@ -533,8 +553,6 @@ __global__ __launch_bounds__(RAHT_THREADS) void k_raht_fwd(TileMap m, int k)
     __shared__ uint16_t s_lst[LSTART_N];
     __shared__ uint16_t s_opos[OPEN_CAP];
     __shared__ uint32_t s_idx[RT + 1];
-    __shared__ uint32_t s_m0[RT + 1];
-    __shared__ uint32_t s_first[RT];
     __shared__ unsigned long long s_lmask[NCLS];
 
     const uint32_t f = frame_of(m, blockIdx.x);
@@ -546,121 +564,66 @@ __global__ __launch_bounds__(RAHT_THREADS) void k_raht_fwd(TileMap m, int k)
     const uint32_t C = fd.C, C4 = fd.C4;
     const uint32_t NP = channel_passes(C4, k), CH4 = pass_chunks(C4, k);
     const SliceSplit hs = slice_split(blockIdx.x - m.start[f], NP);
-    if (!load_schedule(fd, ctrl, k, hs.tile, ts, s_rec, s_ab, s_lst, s_opos, s_idx))
+    if (!load_schedule(fd, ctrl, k, hs.tile, ts, s_rec, s_ab, s_lst, s_opos, s_idx, s_lmask))
         return;
-    const uint32_t tid = threadIdx.x;
     const Roles R(CH4);
     const uint32_t mlen = (uint32_t)ts.mlen;
-    const bool encode1 = (k == 1 && fd.mode == MODE_ENCODE);
-    const GAS uint32_t *perm = gp((fd.P & 1) ? fd.vals_b : fd.vals_a);
-    const GAS float *attr = gp(fd.attr);
-    const uint32_t nlast = fd.n ? fd.n - 1 : 0u;  // row indices read from the workspace are
-                                                     // clamped: never an access outside the input
-    if (encode1) {
-        // the run starts and the first member's row, staged so that row loads are independent
-        const GAS uint32_t *vh = gp(fd.vh);
-        for (uint32_t j = tid; j <= mlen; j += RAHT_THREADS) s_m0[j] = min(vh[ts.s + j], fd.n);
-        __syncthreads();
-        for (uint32_t j = tid; j < mlen; j += RAHT_THREADS) s_first[j] = min(perm[min(s_m0[j], nlast)], nlast);
+    const uint32_t cb = hs.p0 * CH4, nch = min(CH4, C4 - cb);
+    const uint32_t c4 = cb + R.c4;  // this thread's global channel chunk
+    const bool live = R.act && R.c4 < nch;
+    // ---- the entries' values of this channel slice
+    if (live) {
+        const GAS float *vsrc = gp(fd.lv[k - 1].vbuf);
+        load_slice(s_y, R, CH4, mlen, [&](uint32_t j) { return gload4(vsrc + ((size_t)(ts.s + j) * C4 + c4) * 4); });
     }
-    level_masks(s_lst, s_lmask);
+    __syncthreads();
+    // ---- all local merges: within wave chunks, then across chunks (levels ascending)
     const uint64_t wmask = s_lmask[R.w], xmask = s_lmask[CROSS];
-    GAS int32_t *coef = nullptr;
+    wave_phase(s_y, R, s_rec, s_ab, s_lst, wmask, nch, false);
+    __syncthreads();
+    block_phase(s_y, R, s_rec, s_ab, s_lst, xmask, nch, false);
+    // ---- outputs: coefficient rows of every entry at its voxel (an open entry's row is
+    // rewritten by the level that completes its merge), open entries' partial low-passes to
+    // S_{k+1}
+    if (!live) return;
+    GAS float *coef_f32 = gp(fd.coef_f32);
     if (fd.mode == MODE_ENCODE) {
         uint64_t off = GSC_HEADER_BYTES, run = 0;
         for (uint32_t d = 0; d < fd.J; ++d) {
             run += ctrl->hist_D[d];
             off += run;
         }
-        coef = gp(reinterpret_cast<int32_t *>(fd.stream + align_up(off, 256)));
-    }
-    const GAS float *vsrc = k >= 2 ? gp(fd.lv[k - 1].vbuf) : nullptr;
-    GAS float *coef_f32 = gp(fd.coef_f32);
-
-    for (uint32_t p = hs.p0; p < hs.p1; ++p) {
-        const uint32_t cb = p * CH4;
-        const uint32_t nch = min(CH4, C4 - cb);
-        const uint32_t c4 = cb + R.c4;  // this thread's global channel chunk
-        const bool live = R.act && R.c4 < nch;
-        if (p > hs.p0) __syncthreads();  // the previous pass has finished reading the slice
-        // ---- load the entries' values of this channel slice
-        if (live) {
-            if (encode1) {
-                load_slice(s_y, R, CH4, mlen, [&](uint32_t j) { return ld4<VEC>(attr, s_first[j], C, c4); });
-            } else if (k == 1) {
-                load_slice(s_y, R, CH4, mlen, [&](uint32_t j) { return ld4<VEC>(attr, ts.s + j, C, c4); });
-            } else {
-                load_slice(s_y, R, CH4, mlen, [&](uint32_t j) { return gload4(vsrc + ((size_t)(ts.s + j) * C4 + c4) * 4); });
-            }
-            if (encode1) {
-                // merge duplicates: the mean of the rows of the Gaussians in the voxel
-                // (Sec. 2.1), summed in input order (the sort is stable)
-                for (uint32_t j = R.row0; j < mlen; j += R.RPB) {
-                    const uint32_t m0 = s_m0[j], m1 = s_m0[j + 1];
-                    if (m1 - m0 <= 1) continue;
-                    float4 acc = s_y[j * CH4 + R.c4];
-                    for (uint32_t mm = m0 + 1; mm < m1; ++mm) {
-                        const float4 x = ld4<VEC>(attr, min(perm[mm], nlast), C, c4);
-                        acc.x += x.x;
-                        acc.y += x.y;
-                        acc.z += x.z;
-                        acc.w += x.w;
-                    }
-                    const float cnt = (float)(m1 - m0);
-                    acc.x /= cnt;
-                    acc.y /= cnt;
-                    acc.z /= cnt;
-                    acc.w /= cnt;
-                    s_y[j * CH4 + R.c4] = acc;
-                }
-                if (fd.ste == STE_FORWARD && fd.aref) {
-                    // the voxel means (this thread's own rows of the slice)
-                    GAS float *ar = gp(fd.aref);
-                    for (uint32_t j = R.row0; j < mlen; j += R.RPB)
-                        st4<VEC>(ar, ts.s + j, C, c4, s_y[j * CH4 + R.c4]);
-                }
-            }
-        }
-        __syncthreads();
-        // ---- all local merges: within wave chunks, then across chunks (levels ascending)
-        wave_phase(s_y, R, s_rec, s_ab, s_lst, wmask, nch, false);
-        __syncthreads();
-        block_phase(s_y, R, s_rec, s_ab, s_lst, xmask, nch, false);
-        // ---- outputs: coefficient rows of every entry (an open entry's row is rewritten by the
-        // level that completes its merge), open entries' partial low-passes to S_{k+1}
-        if (!live) continue;
-        if (fd.mode == MODE_ENCODE) {
-            const double omt = 1.0 - (double)fd.tau;
-            const bool deq = fd.ste == STE_FORWARD;  // float output: q * step instead of y
-            GAS float *cf = coef_f32;
-            float st[4], ist[4];
+        GAS int32_t *coef = gp(reinterpret_cast<int32_t *>(fd.stream + align_up(off, 256)));
+        const double omt = 1.0 - (double)fd.tau;
+        const float thr = ceil_float(omt);
+        const bool deq = fd.ste == STE_FORWARD;  // float output: q * step instead of y
+        float st[4], ist[4];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const uint32_t c = min(4 * c4 + i, C - 1);
-                st[i] = fd.step[c];
-                ist[i] = fd.inv_step[c];
-            }
-            for (uint32_t j = R.row0; j < mlen; j += R.RPB) {
-                const float4 y = s_y[j * CH4 + R.c4];
-                const uint64_t row = entry_index(k, s_idx, ts.s, (int)j);
-                const int4 q = make_int4(quant1<POW2>(y.x, st[0], ist[0], omt), quant1<POW2>(y.y, st[1], ist[1], omt),
-                                         quant1<POW2>(y.z, st[2], ist[2], omt), quant1<POW2>(y.w, st[3], ist[3], omt));
-                stq4<VEC>(coef, row, C, c4, q);
-                if (cf)
-                    st4<VEC>(cf, row, C, c4,
-                             deq ? make_float4((float)q.x * st[0], (float)q.y * st[1], (float)q.z * st[2],
-                                               (float)q.w * st[3])
-                                 : y);
-            }
-        } else {  // MODE_FWD_F32: float coefficient rows
-            for (uint32_t j = R.row0; j < mlen; j += R.RPB)
-                st4<VEC>(coef_f32, entry_index(k, s_idx, ts.s, (int)j), C, c4, s_y[j * CH4 + R.c4]);
+        for (int i = 0; i < 4; ++i) {
+            const uint32_t c = min(4 * c4 + i, C - 1);
+            st[i] = fd.step[c];
+            ist[i] = fd.inv_step[c];
         }
-        if (!ts.final_level) {
-            GAS float *dst = gp(fd.lv[k].vbuf);
-            for (uint32_t o = R.row0; o < ts.ocnt; o += R.RPB)
-                gstore4(dst + ((size_t)(ts.obase + o) * C4 + c4) * 4, s_y[s_opos[o] * CH4 + R.c4]);
+        for (uint32_t j = R.row0; j < mlen; j += R.RPB) {
+            const float4 y = s_y[j * CH4 + R.c4];
+            const uint64_t row = s_idx[j];
+            const int4 q = make_int4(quant1<POW2>(y.x, st[0], ist[0], omt, thr), quant1<POW2>(y.y, st[1], ist[1], omt, thr),
+                                     quant1<POW2>(y.z, st[2], ist[2], omt, thr), quant1<POW2>(y.w, st[3], ist[3], omt, thr));
+            stq4<VEC>(coef, row, C, c4, q);
+            if (coef_f32)
+                st4<VEC>(coef_f32, row, C, c4,
+                         deq ? make_float4((float)q.x * st[0], (float)q.y * st[1], (float)q.z * st[2],
+                                           (float)q.w * st[3])
+                             : y);
         }
+    } else {  // MODE_FWD_F32: float coefficient rows
+        for (uint32_t j = R.row0; j < mlen; j += R.RPB)
+            st4<VEC>(coef_f32, s_idx[j], C, c4, s_y[j * CH4 + R.c4]);
+    }
+    if (!ts.final_level) {
+        GAS float *dst = gp(fd.lv[k].vbuf);
+        for (uint32_t o = R.row0; o < ts.ocnt; o += R.RPB)
+            gstore4(dst + ((size_t)(ts.obase + o) * C4 + c4) * 4, s_y[s_opos[o] * CH4 + R.c4]);
     }
 }
 
@@ -674,13 +637,25 @@ __global__ __launch_bounds__(RAHT_THREADS) void k_raht_fwd(TileMap m, int k)
 // the next item are in flight in registers. The input row of every voxel's first member comes
 // from the dedup kernel's table and is read two items ahead, so the next item's row addresses
 // are known when its loads are issued.
-constexpr int NR1 = 8;  // rows of a slice per thread: ceil(RT / floor(RT / CH4)) <= 8 for CH4 <= 8
-static_assert(CH4_MAX1 <= 8 && RT == 512, "NR1 covers slices of at most 8 chunks of 512 entries");
+// rows of a slice per thread: ceil(RT / floor(RT / CH4)), at most this for CH4 <= CH4_MAX1
+__host__ __device__ constexpr int rows_per_thread_max(int ch4max)
+{
+    int r = 0;
+    for (int c = 1; c <= ch4max; ++c) {
+        const int rpb = RT / c, t = (RT + rpb - 1) / rpb;
+        r = t > r ? t : r;
+    }
+    return r;
+}
+constexpr int NR1 = rows_per_thread_max((int)CH4_MAX1);
+// persistent first-level workgroups per CU (as many as the LDS of a slice and the registers allow)
+constexpr int PERSIST_PER_CU = 2;
 
 struct Item1 {
     uint32_t f, tile, p, s, mlen;
     bool ok, final_level;
 };
+
 typedef const CAS FrameDesc CFrame;
 
 // Values shared by the items of one frame, loaded when the first item of the frame is described.
@@ -728,7 +703,9 @@ __device__ inline Item1 item1(const TileMap &m, uint32_t i, Frame1 &fc)
 // widened where the prefetch branch joins, which waits for it. Entries past the tile's counts
 // are never read from LDS.
 struct Sched1 {
-    uint32_t rec, lst, opos, m0, m_end, obase, ocnt;
+    uint32_t rec, lst, opos, m0;
+    uint64_t lm;                         // thread c < NCLS: level mask of class c
+    uint32_t m_beg, m_end, obase, ocnt;  // the same in every lane (scalar loads)
 };
 static_assert(LSTART_N % 2 == 0 && OPEN_CAP % 2 == 0 && LSTART_N / 2 <= RT, "u16 pairs per thread");
 
@@ -741,13 +718,14 @@ __device__ inline void load_sched1(CFrame *d, const Item1 &it, Sched1 &S)
     const GAS uint32_t *ow = reinterpret_cast<const GAS uint32_t *>(gp(d->lv[1].opos) + t * OPEN_CAP);
     S.lst = lw[min(tid, (uint32_t)LSTART_N / 2 - 1)];
     S.opos = ow[min(tid, (uint32_t)OPEN_CAP / 2 - 1)];
-    // written by the prelude, constant here: scalar loads
+    // written by the prelude (and run starts by the dedup kernel), constant here: scalar loads
     S.obase = cp(d->lv[1].obase)[t];
     S.ocnt = cp(d->lv[1].ocnt)[t];
+    S.lm = gp(d->lv[1].lmask)[t * NCLS + min(tid, (uint32_t)NCLS - 1)];
     // run starts (used by the encoder; the table exists in every workspace)
-    const GAS uint32_t *vh = gp(d->vh);
-    S.m0 = vh[it.s + min(tid, it.mlen)];
-    S.m_end = vh[it.s + it.mlen];
+    S.m0 = gp(d->vh)[it.s + min(tid, it.mlen)];
+    S.m_beg = cp(d->vh)[it.s];
+    S.m_end = cp(d->vh)[it.s + it.mlen];
 }
 
 // Branch-free, so that every prefetched register is consumed here on every path (the compiler's
@@ -756,9 +734,10 @@ __device__ inline void load_sched1(CFrame *d, const Item1 &it, Sched1 &S)
 // of each array.
 __device__ inline void commit_sched1(const Sched1 &S, const Item1 &it, uint32_t n, uint32_t *s_rec,
                                      float2 *s_ab, uint32_t *s_lstw, uint32_t *s_oposw,
-                                     uint32_t *s_m0)
+                                     uint32_t *s_m0, unsigned long long *s_lmask)
 {
     const uint32_t tid = threadIdx.x;
+    s_lmask[min(tid, (uint32_t)NCLS)] = S.lm;
     s_rec[tid] = S.rec;
     // (a, b) of the merge: at the first level an entry's weight is its position difference
     const uint32_t j = S.rec & 1023u, l = (S.rec >> 10) & 1023u, r = S.rec >> 20;
@@ -768,7 +747,7 @@ __device__ inline void commit_sched1(const Sched1 &S, const Item1 &it, uint32_t 
     s_lstw[min(tid, (uint32_t)LSTART_N / 2)] = S.lst;
     s_oposw[min(tid, (uint32_t)OPEN_CAP / 2)] = S.opos;
     s_m0[tid <= it.mlen ? tid : RT + 1] = min(S.m0, n);
-    s_m0[tid == 0 ? it.mlen : RT + 1] = min(S.m_end, n);
+    if (tid == 0) s_m0[it.mlen] = min(S.m_end, n);
 }
 
 // Issues the loads of this thread's rows of an item's channel slice: chunk c4 of rows
@@ -790,7 +769,7 @@ __device__ inline void load_rows1(const GAS float *src, uint32_t C, const Roles 
 }
 
 template <bool VEC, bool POW2>
-__global__ __launch_bounds__(RAHT_THREADS) void k_raht_fwd1(TileMap m)
+__global__ __launch_bounds__(RAHT_THREADS) __attribute__((amdgpu_waves_per_eu(PERSIST_PER_CU * RAHT_THREADS / WAVE / 4))) void k_raht_fwd1(TileMap m)
 {
     extern __shared__ float4 s_y[];
     __shared__ uint32_t s_rec[RT];
@@ -800,7 +779,7 @@ __global__ __launch_bounds__(RAHT_THREADS) void k_raht_fwd1(TileMap m)
     __shared__ uint32_t s_m0[RT + 2];               // run starts; + sink
     __shared__ uint32_t s_row[RT];
     __shared__ float s_st[GSC_MAX_CHANNELS], s_ist[GSC_MAX_CHANNELS];
-    __shared__ unsigned long long s_lmask[NCLS];
+    __shared__ unsigned long long s_lmask[NCLS + 1];  // + sink
     const uint16_t *s_lst = reinterpret_cast<const uint16_t *>(s_lstw);
     const uint16_t *s_opos = reinterpret_cast<const uint16_t *>(s_oposw);
 
@@ -860,10 +839,11 @@ __global__ __launch_bounds__(RAHT_THREADS) void k_raht_fwd1(TileMap m)
         const bool live = it0.ok && R.act && R.c4 < nch;
         const uint32_t C = d->C, n = d->n;
         const uint32_t obase = S.obase, ocnt = S.ocnt;
+        const bool dup = S.m_end - S.m_beg != it0.mlen;  // a voxel of the tile has several Gaussians
         __syncthreads();  // the previous item is no longer read from LDS
         // ---- the current item's schedule and rows into LDS, the next item's first rows; on
         // every path, whether or not the item is ok (see commit_sched1)
-        commit_sched1(S, it0, n, s_rec, s_ab, s_lstw, s_oposw, s_m0);
+        commit_sched1(S, it0, n, s_rec, s_ab, s_lstw, s_oposw, s_m0, s_lmask);
         const uint32_t sink = RT * CH4;
 #pragma unroll
         for (int u = 0; u < NR1; ++u) {
@@ -882,12 +862,12 @@ __global__ __launch_bounds__(RAHT_THREADS) void k_raht_fwd1(TileMap m)
             const uint32_t nlast = n ? n - 1 : 0u;
             // this thread's rows j = row0 + t RPB sit at LDS index y0 + t ystep
             const uint32_t y0 = R.row0 * CH4 + R.c4, ystep = R.RPB * CH4;
-            if (encode && live) {
+            if (encode && dup) {
                 // merge duplicates: the mean of the rows of the Gaussians in the voxel
                 // (Sec. 2.1), summed in input order (the sort is stable)
                 const GAS float *attr = gp(d->attr);
                 const GAS uint32_t *perm = gp((d->P & 1) ? d->vals_b : d->vals_a);
-                for (uint32_t j = R.row0, yi = y0; j < mlen; j += R.RPB, yi += ystep) {
+                for (uint32_t j = R.row0, yi = y0; live && j < mlen; j += R.RPB, yi += ystep) {
                     const uint32_t m0 = s_m0[j], m1 = s_m0[j + 1];
                     if (m1 - m0 <= 1) continue;
                     float4 acc = s_y[yi];
@@ -905,13 +885,18 @@ __global__ __launch_bounds__(RAHT_THREADS) void k_raht_fwd1(TileMap m)
                     acc.w /= cnt;
                     s_y[yi] = acc;
                 }
-                if (d->ste == STE_FORWARD && d->aref) {
+                __syncthreads();  // the merged rows are read by other waves' merges
+            }
+            if (encode && d->ste == STE_FORWARD && d->aref) {
+                // the voxel means (this thread's own rows of the slice), read before any merge
+                // changes them
+                if (live) {
                     GAS float *ar = gp(d->aref);
                     for (uint32_t j = R.row0, yi = y0; j < mlen; j += R.RPB, yi += ystep)
                         st4<VEC>(ar, s + j, C, c4, s_y[yi]);
                 }
+                __syncthreads();
             }
-            level_masks(s_lst, s_lmask);
             const uint64_t wmask = s_lmask[R.w], xmask = s_lmask[CROSS];
             wave_phase(s_y, R, s_rec, s_ab, s_lst, wmask, nch, false);
             __syncthreads();
@@ -927,6 +912,7 @@ __global__ __launch_bounds__(RAHT_THREADS) void k_raht_fwd1(TileMap m)
                     }
                     GAS int32_t *coef = gp(reinterpret_cast<int32_t *>(d->stream + align_up(off, 256)));
                     const double omt = 1.0 - (double)d->tau;
+                    const float thr = ceil_float(omt);
                     const bool deq = d->ste == STE_FORWARD;  // float output: q * step instead of y
                     float st[4], ist[4];
 #pragma unroll
@@ -937,8 +923,8 @@ __global__ __launch_bounds__(RAHT_THREADS) void k_raht_fwd1(TileMap m)
                     }
                     for (uint32_t j = R.row0, yi = y0; j < mlen; j += R.RPB, yi += ystep) {
                         const float4 y = s_y[yi];
-                        const int4 q = make_int4(quant1<POW2>(y.x, st[0], ist[0], omt), quant1<POW2>(y.y, st[1], ist[1], omt),
-                                                 quant1<POW2>(y.z, st[2], ist[2], omt), quant1<POW2>(y.w, st[3], ist[3], omt));
+                        const int4 q = make_int4(quant1<POW2>(y.x, st[0], ist[0], omt, thr), quant1<POW2>(y.y, st[1], ist[1], omt, thr),
+                                                 quant1<POW2>(y.z, st[2], ist[2], omt, thr), quant1<POW2>(y.w, st[3], ist[3], omt, thr));
                         stq4<VEC>(coef, s + j, C, c4, q);
                         if (cf)
                             st4<VEC>(cf, s + j, C, c4,
@@ -967,11 +953,11 @@ __global__ __launch_bounds__(RAHT_THREADS) void k_raht_fwd1(TileMap m)
 // merges are undone and its rows stored, the next item's schedule, coefficient rows (read as raw
 // 32-bit words, dequantized when they are committed to LDS) and the low-passes of its open
 // entries (from S_2) are in flight in registers.
-constexpr int NO1 = 2;  // open entries per thread: OPEN_CAP <= 2 RPB for slices of <= 8 chunks
-static_assert(OPEN_CAP <= NO1 * (RT / CH4_MAX1), "NO1 covers the open entries of a tile");
+// open entries per thread: ceil(OPEN_CAP / RPB) for the narrowest rows per step
+constexpr int NO1 = (OPEN_CAP + RT / (int)CH4_MAX1 - 1) / (RT / (int)CH4_MAX1);
 
 template <bool VEC>
-__global__ __launch_bounds__(RAHT_THREADS) void k_raht_inv1(TileMap m)
+__global__ __launch_bounds__(RAHT_THREADS) __attribute__((amdgpu_waves_per_eu(PERSIST_PER_CU * RAHT_THREADS / WAVE / 4))) void k_raht_inv1(TileMap m)
 {
     extern __shared__ float4 s_y[];
     __shared__ uint32_t s_rec[RT];
@@ -980,7 +966,7 @@ __global__ __launch_bounds__(RAHT_THREADS) void k_raht_inv1(TileMap m)
     __shared__ uint32_t s_oposw[OPEN_CAP / 2 + 1];  // u16 open positions, in pairs; + sink
     __shared__ uint32_t s_m0[RT + 2];               // (written by the shared commit, unused)
     __shared__ float s_st[GSC_MAX_CHANNELS];        // dequantization steps of the frame s_stf
-    __shared__ unsigned long long s_lmask[NCLS];
+    __shared__ unsigned long long s_lmask[NCLS + 1];  // + sink
     const uint16_t *s_lst = reinterpret_cast<const uint16_t *>(s_lstw);
     const uint16_t *s_opos = reinterpret_cast<const uint16_t *>(s_oposw);
 
@@ -1046,7 +1032,7 @@ __global__ __launch_bounds__(RAHT_THREADS) void k_raht_inv1(TileMap m)
         __syncthreads();  // the previous item is no longer read from LDS; s_st is written
         // ---- the current item's schedule and coefficient rows into LDS (branch-free, see
         // commit_sched1)
-        commit_sched1(S, it0, d->n, s_rec, s_ab, s_lstw, s_oposw, s_m0);
+        commit_sched1(S, it0, d->n, s_rec, s_ab, s_lstw, s_oposw, s_m0, s_lmask);
         {
             float st[4] = {1.f, 1.f, 1.f, 1.f};
             if (decode)
@@ -1079,7 +1065,7 @@ __global__ __launch_bounds__(RAHT_THREADS) void k_raht_inv1(TileMap m)
         if (it1.ok) prefetch(it1, S, D, O);
         // ---- the current item: all local merges undone, across chunks, then within chunks
         if (it0.ok) {
-            level_masks(s_lst, s_lmask);  // (its barrier also orders the open-entry writes)
+            __syncthreads();  // the open-entry writes
             const uint64_t wmask = s_lmask[R.w], xmask = s_lmask[CROSS];
             block_phase(s_y, R, s_rec, s_ab, s_lst, xmask, nch, true);
             wave_phase(s_y, R, s_rec, s_ab, s_lst, wmask, nch, true);
@@ -1117,9 +1103,12 @@ __global__ __launch_bounds__(RAHT_THREADS) void k_raht_inv1(TileMap m)
     }
 }
 
-// ==================================================================== inverse transform
+// ============================================================== upper levels, inverse
+// One workgroup per (tile, channel slice) of S_k, k >= 2: coefficient rows from the entries'
+// voxels, open entries' low-passes from S_{k+1}; the entries' synthesized low-passes go to S_{k-1}'s
+// open-entry rows.
 template <bool VEC>
-__global__ __launch_bounds__(RAHT_THREADS) void k_raht_inv(TileMap m, int k)
+__global__ __launch_bounds__(RAHT_THREADS) void k_raht_inv_up(TileMap m, int k)
 {
     extern __shared__ float4 s_y[];
     __shared__ uint32_t s_rec[RT];
@@ -1138,95 +1127,59 @@ __global__ __launch_bounds__(RAHT_THREADS) void k_raht_inv(TileMap m, int k)
     const uint32_t C = fd.C, C4 = fd.C4;
     const uint32_t NP = channel_passes(C4, k), CH4 = pass_chunks(C4, k);
     const SliceSplit hs = slice_split(blockIdx.x - m.start[f], NP);
-    if (!load_schedule(fd, ctrl, k, hs.tile, ts, s_rec, s_ab, s_lst, s_opos, s_idx))
+    if (!load_schedule(fd, ctrl, k, hs.tile, ts, s_rec, s_ab, s_lst, s_opos, s_idx, s_lmask))
         return;
     const Roles R(CH4);
     const uint32_t mlen = (uint32_t)ts.mlen;
-    level_masks(s_lst, s_lmask);
-    const uint64_t wmask = s_lmask[R.w], xmask = s_lmask[CROSS];
-    const gsc_header *h = reinterpret_cast<const gsc_header *>(fd.in_stream);
-    const GAS int32_t *coef = fd.mode == MODE_DECODE
-                                  ? gp(reinterpret_cast<const int32_t *>(fd.in_stream + h->coef_offset))
-                                  : nullptr;
-    // float coefficient rows: the straight-through forward synthesizes from its dequantized
-    // coefficients; the transform and gradient modes read the caller's rows
-    const GAS float *fin = gp(fd.mode == MODE_ENCODE ? fd.coef_f32 : fd.attr);
-
-    for (uint32_t p = hs.p0; p < hs.p1; ++p) {
-        const uint32_t cb = p * CH4;
-        const uint32_t nch = min(CH4, C4 - cb);
-        const uint32_t c4 = cb + R.c4;
-        const bool live = R.act && R.c4 < nch;
-        if (p > hs.p0) __syncthreads();
-        // ---- coefficients of every entry (the high-pass stored at it, or the DC at entry 0)
-        if (live) {
-            if (fd.mode == MODE_DECODE) {
-                float st[4];
+    const uint32_t cb = hs.p0 * CH4, nch = min(CH4, C4 - cb);
+    const uint32_t c4 = cb + R.c4;
+    const bool live = R.act && R.c4 < nch;
+    // ---- coefficients of every entry (the high-pass stored at it)
+    if (live) {
+        if (fd.mode == MODE_DECODE) {
+            const gsc_header *h = reinterpret_cast<const gsc_header *>(fd.in_stream);
+            const GAS int32_t *coef = gp(reinterpret_cast<const int32_t *>(fd.in_stream + h->coef_offset));
+            float st[4];
 #pragma unroll
-                for (int i = 0; i < 4; ++i) st[i] = 4 * c4 + i < C ? h->quant_step[4 * c4 + i] : 0.0f;
-                load_slice(s_y, R, CH4, mlen, [&](uint32_t j) {
-                    const int4 q = ldq4<VEC>(coef, entry_index(k, s_idx, ts.s, (int)j), C, c4);
-                    return make_float4((float)q.x * st[0], (float)q.y * st[1], (float)q.z * st[2],
-                                       (float)q.w * st[3]);
-                });
-            } else {  // float coefficient rows
-                load_slice(s_y, R, CH4, mlen, [&](uint32_t j) {
-                    return ld4<VEC>(fin, entry_index(k, s_idx, ts.s, (int)j), C, c4);
-                });
-            }
-        }
-        __syncthreads();
-        // ---- open entries take the low-pass handed down by the next sequence
-        if (!ts.final_level) {
-            if (live) {
-                const GAS float *src = gp(fd.lv[k].vbuf);
-                for (uint32_t o = R.row0; o < ts.ocnt; o += R.RPB)
-                    s_y[s_opos[o] * CH4 + R.c4] = gload4(src + ((size_t)(ts.obase + o) * C4 + c4) * 4);
-            }
-            __syncthreads();
-        }
-        // ---- all local merges undone: across chunks, then within chunks (levels descending)
-        block_phase(s_y, R, s_rec, s_ab, s_lst, xmask, nch, true);
-        wave_phase(s_y, R, s_rec, s_ab, s_lst, wmask, nch, true);
-        __syncthreads();
-        // ---- outputs
-        if (!live) continue;
-        if (k >= 2) {
-            GAS float *dst = gp(fd.lv[k - 1].vbuf);
-            for (uint32_t j = R.row0; j < mlen; j += R.RPB)
-                gstore4(dst + ((size_t)(ts.s + j) * C4 + c4) * 4, s_y[j * CH4 + R.c4]);
-        } else if (fd.mode == MODE_STE_BWD) {
-            // voxel gradient = synthesized rows + the added rows; each member Gaussian receives
-            // it divided by the member count (the voxel row is the members' mean)
-            GAS float *out = gp(fd.attr_out);
-            const GAS float *ga = gp(fd.grad_add);
-            const GAS uint32_t *vh = gp(fd.vh);
-            const GAS uint32_t *perm = gp((fd.P & 1) ? fd.vals_b : fd.vals_a);
-            const uint32_t nlast = fd.n ? fd.n - 1 : 0u;
-            for (uint32_t j = R.row0; j < mlen; j += R.RPB) {
-                const uint32_t v = ts.s + j;
-                const float4 a = s_y[j * CH4 + R.c4];
-                const float4 b = ld4<VEC>(ga, v, C, c4);
-                const uint32_t m0 = min(vh[v], fd.n), m1 = min(vh[v + 1], fd.n);
-                const float cnt = (float)(m1 - m0);
-                const float4 g = make_float4((a.x + b.x) / cnt, (a.y + b.y) / cnt, (a.z + b.z) / cnt,
-                                             (a.w + b.w) / cnt);
-                for (uint32_t mm = m0; mm < m1; ++mm) st4<VEC>(out, min(perm[mm], nlast), C, c4, g);
-            }
-        } else {
-            GAS float *out = gp(fd.mode == MODE_ADJ_F32 ? fd.coef_f32 : fd.attr_out);
-            for (uint32_t j = R.row0; j < mlen; j += R.RPB) st4<VEC>(out, ts.s + j, C, c4, s_y[j * CH4 + R.c4]);
+            for (int i = 0; i < 4; ++i) st[i] = 4 * c4 + i < C ? h->quant_step[4 * c4 + i] : 0.0f;
+            load_slice(s_y, R, CH4, mlen, [&](uint32_t j) {
+                const int4 q = ldq4<VEC>(coef, s_idx[j], C, c4);
+                return make_float4((float)q.x * st[0], (float)q.y * st[1], (float)q.z * st[2],
+                                   (float)q.w * st[3]);
+            });
+        } else {  // float coefficient rows: the straight-through forward synthesizes from its
+                  // dequantized coefficients; the transform and gradient modes read the caller's
+            const GAS float *fin = gp(fd.mode == MODE_ENCODE ? fd.coef_f32 : fd.attr);
+            load_slice(s_y, R, CH4, mlen, [&](uint32_t j) { return ld4<VEC>(fin, s_idx[j], C, c4); });
         }
     }
+    __syncthreads();
+    // ---- open entries take the low-pass handed down by the next sequence
+    if (!ts.final_level) {
+        if (live) {
+            const GAS float *src = gp(fd.lv[k].vbuf);
+            for (uint32_t o = R.row0; o < ts.ocnt; o += R.RPB)
+                s_y[s_opos[o] * CH4 + R.c4] = gload4(src + ((size_t)(ts.obase + o) * C4 + c4) * 4);
+        }
+        __syncthreads();
+    }
+    // ---- all local merges undone: across chunks, then within chunks (levels descending)
+    const uint64_t wmask = s_lmask[R.w], xmask = s_lmask[CROSS];
+    block_phase(s_y, R, s_rec, s_ab, s_lst, xmask, nch, true);
+    wave_phase(s_y, R, s_rec, s_ab, s_lst, wmask, nch, true);
+    __syncthreads();
+    if (!live) return;
+    GAS float *dst = gp(fd.lv[k - 1].vbuf);
+    for (uint32_t j = R.row0; j < mlen; j += R.RPB)
+        gstore4(dst + ((size_t)(ts.s + j) * C4 + c4) * 4, s_y[j * CH4 + R.c4]);
 }
 
 // Dynamic LDS of a transform launch: the slice of RT entries, plus one sink slot for writes that
 // are masked off by address rather than by branch.
 size_t raht_lds_bytes(int C4, int k) { return ((size_t)RT * pass_chunks((uint32_t)C4, k) + 1) * sizeof(float4); }
 
-// Workgroups of a persistent first-level launch over `items` items: at most two per CU (the
-// LDS of one item slice allows two), a multiple of 8 NP, and as few as give every workgroup
-// the same number of items, up to one.
+// Workgroups of a persistent first-level launch over `items` items: at most PERSIST_PER_CU per
+// CU, a multiple of 8 NP, and as few as give every workgroup the same number of items, up to one.
 uint32_t persist_grid(uint32_t items, int C4)
 {
     static int cus = 0;
@@ -1237,7 +1190,7 @@ uint32_t persist_grid(uint32_t items, int C4)
         cus = v;
     }
     const uint32_t unit = 8 * channel_passes((uint32_t)C4, 1);
-    const uint32_t gmax = (2u * (uint32_t)cus) / unit * unit;
+    const uint32_t gmax = ((uint32_t)PERSIST_PER_CU * (uint32_t)cus) / unit * unit;
     if (items <= gmax) return items;
     const uint32_t rounds = ceil_div(items, gmax);
     return ceil_div(ceil_div(items, rounds), unit) * unit;
@@ -1255,10 +1208,10 @@ hipError_t launch_raht_fwd(const TileMap &m, int k, const RahtCfg &cfg, hipStrea
         return hipGetLastError();
     }
     const dim3 grid(m.start[m.F]), block(RAHT_THREADS);
-    if (cfg.vec && cfg.pow2) hipLaunchKernelGGL((k_raht_fwd<true, true>), grid, block, lds, s, m, k);
-    else if (cfg.vec) hipLaunchKernelGGL((k_raht_fwd<true, false>), grid, block, lds, s, m, k);
-    else if (cfg.pow2) hipLaunchKernelGGL((k_raht_fwd<false, true>), grid, block, lds, s, m, k);
-    else hipLaunchKernelGGL((k_raht_fwd<false, false>), grid, block, lds, s, m, k);
+    if (cfg.vec && cfg.pow2) hipLaunchKernelGGL((k_raht_fwd_up<true, true>), grid, block, lds, s, m, k);
+    else if (cfg.vec) hipLaunchKernelGGL((k_raht_fwd_up<true, false>), grid, block, lds, s, m, k);
+    else if (cfg.pow2) hipLaunchKernelGGL((k_raht_fwd_up<false, true>), grid, block, lds, s, m, k);
+    else hipLaunchKernelGGL((k_raht_fwd_up<false, false>), grid, block, lds, s, m, k);
     return hipGetLastError();
 }
 
@@ -1272,8 +1225,8 @@ hipError_t launch_raht_inv(const TileMap &m, int k, const RahtCfg &cfg, hipStrea
         return hipGetLastError();
     }
     const dim3 grid(m.start[m.F]), block(RAHT_THREADS);
-    if (cfg.vec) hipLaunchKernelGGL((k_raht_inv<true>), grid, block, lds, s, m, k);
-    else hipLaunchKernelGGL((k_raht_inv<false>), grid, block, lds, s, m, k);
+    if (cfg.vec) hipLaunchKernelGGL((k_raht_inv_up<true>), grid, block, lds, s, m, k);
+    else hipLaunchKernelGGL((k_raht_inv_up<false>), grid, block, lds, s, m, k);
     return hipGetLastError();
 }
 
