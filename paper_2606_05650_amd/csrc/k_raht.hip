@@ -44,15 +44,30 @@ __device__ inline uint32_t seq_size(const FrameDesc &fd, Ctrl *ctrl, int k)
 }
 __device__ inline bool seq_active(uint32_t nk, int k) { return k == 1 ? nk >= 1 : nk >= 2; }
 
+// A value that is the same in every lane, said so to the compiler, so that a loop over its bits
+// runs on the scalar unit.
+__device__ inline uint64_t uniform64(uint64_t v)
+{
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
 // ============================================================================ prelude
 // Per tile, one thread per entry: the entry's binary level l; the tile's active lists as one
 // 64-bit ballot per (level, wave chunk); the entry's left partner and node end as the nearest
 // set bits of its level's ballots. A merge is local when both lie inside the tile (the node may
 // also end exactly at the tile end when the next entry survives to a higher level); otherwise
-// the entry is open. Local merges are stored sorted by (level, class), the class being the
-// wave chunk holding the whole merge or CROSS. Open entries are compacted in order into S_{k+1}
-// with a decoupled look-back; a workgroup handles PRE_TILES consecutive tiles so that the
-// look-back chain has PRE_TILES times fewer links.
+// the entry is open. Local merges are stored sorted by (round, class), the class being the
+// wave chunk holding the whole merge or CROSS. A merge's round is one more than the rounds of the
+// merges of its chunk that produced its two operands (0 for an operand not produced yet); a
+// crossing merge's round is its binary level (crossing merges run after every chunk's own
+// merges). The transforms take the rounds in order, so merges of a chunk that do not depend on
+// one another run together, and a chunk takes as many steps as its merge tree is deep instead of
+// one per binary level that holds a merge. The order of the merges that read or write any one
+// entry is unchanged, so the results are the same. Open entries are compacted in order into S_{k+1} with a
+// decoupled look-back; a workgroup handles PRE_TILES consecutive tiles so that the look-back chain
+// has PRE_TILES times fewer links.
 constexpr int PRE_TILES = 1;
 constexpr int PRE_BLOCK = PRE_TILES * PRE_THREADS;
 
@@ -64,6 +79,7 @@ __global__ __launch_bounds__(PRE_BLOCK) void k_prelude(TileMap m, int k)
     __shared__ uint32_t s_cnt[PRE_TILES][SEG_N], s_fill[PRE_TILES][SEG_N];
     __shared__ uint32_t s_tmp[PRE_BLOCK / WAVE + 1];
     __shared__ uint32_t s_tile_excl[PRE_TILES], s_tile_cnt[PRE_TILES];
+    __shared__ uint8_t s_rdl[PRE_TILES][RT];  // round of the chunk merge that last wrote an entry
 
     const uint32_t f = frame_of(m, blockIdx.x);
     const FrameDesc &fd = *m.fd[f];
@@ -97,6 +113,7 @@ __global__ __launch_bounds__(PRE_BLOCK) void k_prelude(TileMap m, int k)
         s_cnt[g][x] = 0;
         s_fill[g][x] = 0;
     }
+    s_rdl[g][j] = 0;
     if (j == 0)
         s_lvl_e[g] = e < nk ? (k == 1 ? merge_level(codes[e - 1], codes[e]) : slvl[e]) : LVL_NONE;
     for (uint32_t x = 1; x < (uint32_t)NLVL; ++x) {
@@ -144,7 +161,29 @@ __global__ __launch_bounds__(PRE_BLOCK) void k_prelude(TileMap m, int k)
             is_open = true;  // entry 0 of the sequence never merges as a right sibling
         }
     }
-    if (is_local) atomicAdd(&s_cnt[g][lvl * NCLS + cls], 1u);
+    // ---- rounds: the chunk's own merges by its wave (levels ascending, no workgroup barrier)
+    uint32_t rnd = 0;
+    {
+        const bool mine = is_local && cls != CROSS;  // (then cls is this thread's own chunk)
+        uint64_t lm = mine ? 1ull << lvl : 0ull;
+#pragma unroll
+        for (int o = 1; o < WAVE; o <<= 1) lm |= __shfl_xor(lm, o, WAVE);
+        lm = uniform64(lm);
+        while (lm) {
+            const uint32_t x = (uint32_t)(__ffsll((long long)lm) - 1);
+            lm &= ~(1ull << x);
+            if (mine && lvl == x) {
+                rnd = 1u + max((uint32_t)s_rdl[g][left], (uint32_t)s_rdl[g][j]);
+                s_rdl[g][left] = (uint8_t)rnd;
+            }
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+        }
+    }
+    // crossing merges keep their binary level as their round (a round of their own would cost a
+    // workgroup barrier per level here)
+    if (is_local && cls == CROSS) rnd = lvl;
+    if (is_local) atomicAdd(&s_cnt[g][rnd * NCLS + cls], 1u);
     __syncthreads();
     if (j < WAVE && s < nk) {  // level masks of the classes: lane x tests level x
 #pragma unroll
@@ -164,7 +203,7 @@ __global__ __launch_bounds__(PRE_BLOCK) void k_prelude(TileMap m, int k)
     __syncthreads();
     const bool tile_live = s < nk;
     if (is_local) {
-        const uint32_t seg = lvl * NCLS + cls;
+        const uint32_t seg = rnd * NCLS + cls;
         const uint32_t slot = s_cnt[g][seg] + atomicAdd(&s_fill[g][seg], 1u);
         if (slot < (uint32_t)RT)
             gp(lv.rec)[(size_t)tile * RT + slot] =
@@ -318,14 +357,6 @@ __device__ inline uint32_t next_level(uint64_t mask, bool inverse)
     return inverse ? (uint32_t)msb64(mask) : (uint32_t)(__ffsll((long long)mask) - 1);
 }
 
-// A value that is the same in every lane, said so to the compiler, so that a loop over its bits
-// runs on the scalar unit.
-__device__ inline uint64_t uniform64(uint64_t v)
-{
-    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
-    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
-    return ((uint64_t)hi << 32) | lo;
-}
 
 // Merges local to this wave's chunk, levels ascending (forward) or descending (inverse). Lane x
 // holds the record range of level x in registers (read out with readlane), and each level's first
