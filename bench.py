@@ -39,17 +39,45 @@ STAGES = {"encode": 0, "decode": 1, "sort": 2, "occupancy": 3, "prelude": 4, "ra
 
 # Algorithmic bytes (each input read once, each output written once; float32/int32 rows of C
 # channels), per launch:
-#   raht_fwd1 : attribute rows of the n Gaussians (4C) + the sort permutation (4) for each
-#               Gaussian; per voxel its run start (4), one merge record (4) and the quantized
+#   raht_fwd1 : the attribute rows of the n Gaussians (4C each); per voxel the input row of its
+#               first member (4), its run start (4), one merge record (4) and the quantized
 #               coefficient row written (4C)
 #   raht_inv1 : per voxel the coefficient row (4C) + one merge record (4) read, the attribute
 #               row written (4C)
 def alg_bytes(stage, n, nv, C):
     if stage == "raht_fwd1":
-        return n * (4 * C + 4) + nv * (4 + 4 + 4 * C)
+        return n * 4 * C + nv * (4 + 4 + 4 + 4 * C)
     if stage == "raht_inv1":
         return nv * (4 * C + 4 + 4 * C)
     raise KeyError(stage)
+
+
+# HBM bytes per launch of the first-level transforms on the 1M-Gaussian frame, from two
+# rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), each scaled by what the
+# same counter reads for a 512 MiB copy (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0); see
+# profiles/k_raht_transforms_frame1M_J12_pmc.md. They hold for the kernel sources they were
+# taken on: with any other sources the figure is reported as null.
+KERNEL_SOURCES = ("paper_2606_05650_amd/csrc/k_raht.hip", "paper_2606_05650_amd/csrc/gsc_device.h",
+                  "paper_2606_05650_amd/csrc/gsc_internal.h")
+PMC_TRAFFIC = {"workload": "frame1M_J12",
+               "sources_sha256": "5e082999cec9d88b8d739d76d2087f7e7108d3689e2f2680526923db9a97a2ac",
+               "raht_fwd1": 573368800, "raht_inv1": 468547229}
+KERNEL_NAMES = {"raht_fwd1": "k_raht_fwd1", "raht_inv1": "k_raht_inv1"}
+
+
+def sources_sha256():
+    import hashlib
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def pmc_traffic(stage, workload):
+    if workload != PMC_TRAFFIC["workload"] or sources_sha256() != PMC_TRAFFIC["sources_sha256"]:
+        return None
+    return PMC_TRAFFIC[stage]
 
 
 def phase_bytes(n, nv, J, occ_bytes):
@@ -152,10 +180,9 @@ def frame_bench(args):
     value = n / dt / 1e6
     dom = max(("raht_fwd1", "raht_inv1"), key=lambda s: cold_ms[s])
     achieved = alg_bytes(dom, n, nv, C) / (cold_ms[dom] * 1e-3) / 1e9
-    roof = {"bound": "hbm", "kernel": {"raht_fwd1": "k_raht_fwd (level 1)",
-                                        "raht_inv1": "k_raht_inv (level 1)"}[dom],
+    roof = {"bound": "hbm", "kernel": KERNEL_NAMES[dom],
             "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": pmc_traffic(dom, args.workload),
             "alg_bytes_per_launch": alg_bytes(dom, n, nv, C),
             "avg_launch_ms": round(cold_ms[dom], 4),
             "avg_launch_ms_back_to_back": round(stage_ms[dom], 4),
