@@ -280,17 +280,22 @@ struct LbScratch {
 // published their aggregates resolve in about one round per NT tiles instead of one per 64.
 // Every thread of the workgroup must call it (it contains barriers); the exclusive prefix is
 // returned to every thread.
+// The look-back in two halves, so that a workgroup can publish its aggregate as soon as it is
+// known and resolve its prefix after other work: lookback_block_publish (one store by thread 0;
+// tile 0 publishes its inclusive value), then lookback_block_resolve with the same aggregate.
+template <class Op>
+__device__ inline void lookback_block_publish(uint64_t *status, uint32_t stride, uint32_t tile, uint64_t agg)
+{
+    if (threadIdx.x == 0) st_relaxed(&status[(size_t)tile * stride], (tile == 0 ? LB_INC : LB_AGG) | agg);
+}
+
 template <class Op, int NT>
-__device__ inline uint64_t lookback_block(uint64_t *status, uint32_t stride, uint32_t tile,
-                                          uint64_t agg, Ctrl *ctrl, LbScratch<NT / WAVE> &sc)
+__device__ inline uint64_t lookback_block_resolve(uint64_t *status, uint32_t stride, uint32_t tile,
+                                                  uint64_t agg, Ctrl *ctrl, LbScratch<NT / WAVE> &sc)
 {
     constexpr int NWV = NT / WAVE;
     const uint32_t tid = threadIdx.x, lane = lane_id(), w = tid / WAVE;
-    if (tile == 0) {
-        if (tid == 0) st_relaxed(&status[0], LB_INC | agg);
-        return Op::identity();
-    }
-    if (tid == 0) st_relaxed(&status[(size_t)tile * stride], LB_AGG | agg);
+    if (tile == 0) return Op::identity();
     uint64_t acc = Op::identity();
     int64_t j = (int64_t)tile - 1;  // nearest predecessor not yet combined (uniform)
     uint32_t spins = 0;
@@ -339,6 +344,14 @@ __device__ inline uint64_t lookback_block(uint64_t *status, uint32_t stride, uin
     }
     if (tid == 0) st_relaxed(&status[(size_t)tile * stride], LB_INC | Op::combine(acc, agg));
     return acc;
+}
+
+template <class Op, int NT>
+__device__ inline uint64_t lookback_block(uint64_t *status, uint32_t stride, uint32_t tile,
+                                          uint64_t agg, Ctrl *ctrl, LbScratch<NT / WAVE> &sc)
+{
+    lookback_block_publish<Op>(status, stride, tile, agg);
+    return lookback_block_resolve<Op, NT>(status, stride, tile, agg, ctrl, sc);
 }
 
 // 32-bit status words for the radix sort: [31:30] flag, [29:0] count (n < 2^30). A tile first

@@ -65,21 +65,21 @@ __device__ inline uint64_t uniform64(uint64_t v)
 // merges). The transforms take the rounds in order, so merges of a chunk that do not depend on
 // one another run together, and a chunk takes as many steps as its merge tree is deep instead of
 // one per binary level that holds a merge. The order of the merges that read or write any one
-// entry is unchanged, so the results are the same. Open entries are compacted in order into S_{k+1} with a
-// decoupled look-back; a workgroup handles PRE_TILES consecutive tiles so that the look-back chain
-// has PRE_TILES times fewer links.
-constexpr int PRE_TILES = 1;
+// entry is unchanged, so the results are the same. Open entries are compacted in order into
+// S_{k+1} with a decoupled look-back whose aggregate is published as soon as the tile's open
+// entries are known and whose prefix is resolved after the rest of the tile's work.
+constexpr int PRE_TILES = 1;  // tiles per workgroup
 constexpr int PRE_BLOCK = PRE_TILES * PRE_THREADS;
 
 __global__ __launch_bounds__(PRE_BLOCK) void k_prelude(TileMap m, int k)
 {
-    __shared__ uint32_t s_blk;
-    __shared__ uint32_t s_lvl_e[PRE_TILES];
-    __shared__ uint64_t s_mask[PRE_TILES][NLVL][NCHUNK];
-    __shared__ uint32_t s_cnt[PRE_TILES][SEG_N], s_fill[PRE_TILES][SEG_N];
+    static_assert(PRE_TILES == 1, "one tile per workgroup");
+    __shared__ uint32_t s_lvl_e;
+    __shared__ uint64_t s_mask[NLVL][NCHUNK];
+    __shared__ uint32_t s_cnt[SEG_N], s_fill[SEG_N];
     __shared__ uint32_t s_tmp[PRE_BLOCK / WAVE + 1];
-    __shared__ uint32_t s_tile_excl[PRE_TILES], s_tile_cnt[PRE_TILES];
-    __shared__ uint8_t s_rdl[PRE_TILES][RT];  // round of the chunk merge that last wrote an entry
+    __shared__ uint8_t s_rdl[RT];  // round of the chunk merge that last wrote an entry
+    __shared__ LbScratch<PRE_BLOCK / WAVE> s_lb;
 
     const uint32_t f = frame_of(m, blockIdx.x);
     const FrameDesc &fd = *m.fd[f];
@@ -89,20 +89,15 @@ __global__ __launch_bounds__(PRE_BLOCK) void k_prelude(TileMap m, int k)
     const uint32_t nk = seq_size(fd, ctrl, k);
     if (!seq_active(nk, k)) return;
     const RahtLevel &lv = fd.lv[k];
-    const uint32_t tid = threadIdx.x;
-    if (tid == 0) s_blk = tile_index(m, f);
-    __syncthreads();
-    const uint32_t blk = s_blk;
-    if (blk * PRE_TILES * RT >= nk) return;            // uniform: the whole block is past the end
-    const uint32_t g = tid / PRE_THREADS;              // tile of this thread inside the block
-    const uint32_t tile = blk * PRE_TILES + g;
+    const uint32_t tile = tile_index(m, f);
     const uint32_t s = tile * RT;
-    const uint32_t e = s < nk ? min(nk, s + RT) : s;   // an empty tile past the end
+    if (s >= nk) return;  // uniform: the tile is past the end
+    const uint32_t e = min(nk, s + RT);
     const int mlen = (int)(e - s);
     const GAS uint64_t *codes = gp((fd.mode == MODE_FWD_F32 || fd.mode == MODE_ADJ_F32) ? fd.codes_in : fd.leaf);
     const GAS uint8_t *slvl = gp(lv.s_lvl);
 
-    const int j = (int)(tid % PRE_THREADS);
+    const int j = (int)threadIdx.x;
     const uint32_t w = (uint32_t)j / WAVE, lane = lane_id();
     uint32_t lvl = 0;  // 0: no entry
     if (j < mlen) {
@@ -110,19 +105,18 @@ __global__ __launch_bounds__(PRE_BLOCK) void k_prelude(TileMap m, int k)
         lvl = k == 1 ? (i == 0 ? LVL_NONE : merge_level(codes[i - 1], codes[i])) : slvl[i];
     }
     for (uint32_t x = j; x < (uint32_t)SEG_N; x += PRE_THREADS) {
-        s_cnt[g][x] = 0;
-        s_fill[g][x] = 0;
+        s_cnt[x] = 0;
+        s_fill[x] = 0;
     }
-    s_rdl[g][j] = 0;
-    if (j == 0)
-        s_lvl_e[g] = e < nk ? (k == 1 ? merge_level(codes[e - 1], codes[e]) : slvl[e]) : LVL_NONE;
+    s_rdl[j] = 0;
+    if (j == 0) s_lvl_e = e < nk ? (k == 1 ? merge_level(codes[e - 1], codes[e]) : slvl[e]) : LVL_NONE;
     for (uint32_t x = 1; x < (uint32_t)NLVL; ++x) {
         const uint64_t b = __ballot(lvl >= x);
-        if (lane == 0) s_mask[g][x][w] = b;
+        if (lane == 0) s_mask[x][w] = b;
     }
     __syncthreads();
 
-    const uint32_t lvl_e = s_lvl_e[g];
+    const uint32_t lvl_e = s_lvl_e;
     bool is_local = false, is_open = false;
     int left = -1, right = mlen;
     uint32_t cls = CROSS;
@@ -130,24 +124,24 @@ __global__ __launch_bounds__(PRE_BLOCK) void k_prelude(TileMap m, int k)
         if (lvl >= 1 && lvl < (uint32_t)NLVL) {
             const uint64_t below = lanemask_lt();
             const uint64_t above = ~below & ~(1ull << lane);
-            uint64_t mm = s_mask[g][lvl][w] & below;
+            uint64_t mm = s_mask[lvl][w] & below;
             if (mm) {
                 left = (int)(w * WAVE) + msb64(mm);
             } else {
                 for (int ww = (int)w - 1; ww >= 0; --ww) {
-                    const uint64_t t = s_mask[g][lvl][ww];
+                    const uint64_t t = s_mask[lvl][ww];
                     if (t) {
                         left = ww * WAVE + msb64(t);
                         break;
                     }
                 }
             }
-            mm = s_mask[g][lvl][w] & above;
+            mm = s_mask[lvl][w] & above;
             if (mm) {
                 right = (int)(w * WAVE) + (__ffsll((long long)mm) - 1);
             } else {
                 for (int ww = (int)w + 1; ww < NCHUNK; ++ww) {
-                    const uint64_t t = s_mask[g][lvl][ww];
+                    const uint64_t t = s_mask[lvl][ww];
                     if (t) {
                         right = ww * WAVE + (__ffsll((long long)t) - 1);
                         break;
@@ -161,10 +155,15 @@ __global__ __launch_bounds__(PRE_BLOCK) void k_prelude(TileMap m, int k)
             is_open = true;  // entry 0 of the sequence never merges as a right sibling
         }
     }
+    // ---- open entries in order: ranks in the tile, the tile's count published at once (its
+    // prefix is resolved at the end, after the rest of the work)
+    uint32_t total;
+    const uint32_t rank = block_excl_scan<PRE_BLOCK>(is_open ? 1u : 0u, s_tmp, &total);
+    lookback_block_publish<OpSum>(lv.status, 1, tile, total);
     // ---- rounds: the chunk's own merges by its wave (levels ascending, no workgroup barrier)
+    const bool mine = is_local && cls != CROSS;  // (then cls is this thread's own chunk)
     uint32_t rnd = 0;
     {
-        const bool mine = is_local && cls != CROSS;  // (then cls is this thread's own chunk)
         uint64_t lm = mine ? 1ull << lvl : 0ull;
 #pragma unroll
         for (int o = 1; o < WAVE; o <<= 1) lm |= __shfl_xor(lm, o, WAVE);
@@ -173,57 +172,66 @@ __global__ __launch_bounds__(PRE_BLOCK) void k_prelude(TileMap m, int k)
             const uint32_t x = (uint32_t)(__ffsll((long long)lm) - 1);
             lm &= ~(1ull << x);
             if (mine && lvl == x) {
-                rnd = 1u + max((uint32_t)s_rdl[g][left], (uint32_t)s_rdl[g][j]);
-                s_rdl[g][left] = (uint8_t)rnd;
+                rnd = 1u + max((uint32_t)s_rdl[left], (uint32_t)s_rdl[j]);
+                s_rdl[left] = (uint8_t)rnd;
             }
             __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
             __builtin_amdgcn_wave_barrier();
         }
     }
+    // ---- segment counts: a chunk's merges are counted by its own wave with ballots (only wave w
+    // holds class-w merges; the rank in the ballot is the record's place in its segment);
     // crossing merges keep their binary level as their round (a round of their own would cost a
-    // workgroup barrier per level here)
-    if (is_local && cls == CROSS) rnd = lvl;
-    if (is_local) atomicAdd(&s_cnt[g][rnd * NCLS + cls], 1u);
+    // workgroup barrier per level) and are counted with LDS atomics
+    uint32_t wrank = 0;
+    {
+        uint64_t rm = mine ? 1ull << rnd : 0ull;
+#pragma unroll
+        for (int o = 1; o < WAVE; o <<= 1) rm |= __shfl_xor(rm, o, WAVE);
+        rm = uniform64(rm);
+        while (rm) {
+            const uint32_t r = (uint32_t)(__ffsll((long long)rm) - 1);
+            rm &= ~(1ull << r);
+            const uint64_t bal = __ballot(mine && rnd == r);
+            if (mine && rnd == r) wrank = (uint32_t)__popcll(bal & lanemask_lt());
+            if (lane == 0) s_cnt[r * NCLS + w] = (uint32_t)__popcll(bal);
+        }
+    }
+    if (is_local && cls == CROSS) {
+        rnd = lvl;
+        atomicAdd(&s_cnt[rnd * NCLS + CROSS], 1u);
+    }
     __syncthreads();
-    if (j < WAVE && s < nk) {  // level masks of the classes: lane x tests level x
+    if (j < WAVE) {  // round masks of the classes: lane x tests round x
 #pragma unroll
         for (uint32_t c = 0; c < (uint32_t)NCLS; ++c) {
-            const uint64_t b = __ballot(s_cnt[g][j * NCLS + c] != 0);
+            const uint64_t b = __ballot(s_cnt[j * NCLS + c] != 0);
             if (j == 0) gp(lv.lmask)[(size_t)tile * NCLS + c] = b;
         }
     }
-    {   // segment starts of each tile: exclusive scan of its SEG_N counts (two per thread)
+    {   // segment starts: exclusive scan of the SEG_N counts (two per thread)
         const uint32_t i0 = 2 * j, i1 = 2 * j + 1;
-        const uint32_t a0 = i0 < (uint32_t)SEG_N ? s_cnt[g][i0] : 0u;
-        const uint32_t a1 = i1 < (uint32_t)SEG_N ? s_cnt[g][i1] : 0u;
+        const uint32_t a0 = i0 < (uint32_t)SEG_N ? s_cnt[i0] : 0u;
+        const uint32_t a1 = i1 < (uint32_t)SEG_N ? s_cnt[i1] : 0u;
         const uint32_t ex = group_excl_scan<PRE_BLOCK, PRE_THREADS>(a0 + a1, s_tmp, nullptr);
-        if (i0 < (uint32_t)SEG_N) s_cnt[g][i0] = ex;
-        if (i1 < (uint32_t)SEG_N) s_cnt[g][i1] = ex + a0;
+        if (i0 < (uint32_t)SEG_N) s_cnt[i0] = ex;
+        if (i1 < (uint32_t)SEG_N) s_cnt[i1] = ex + a0;
     }
     __syncthreads();
-    const bool tile_live = s < nk;
     if (is_local) {
         const uint32_t seg = rnd * NCLS + cls;
-        const uint32_t slot = s_cnt[g][seg] + atomicAdd(&s_fill[g][seg], 1u);
+        const uint32_t slot = s_cnt[seg] + (mine ? wrank : atomicAdd(&s_fill[seg], 1u));
         if (slot < (uint32_t)RT)
             gp(lv.rec)[(size_t)tile * RT + slot] =
                 (uint32_t)j | ((uint32_t)left << 10) | ((uint32_t)right << 20);
     }
-    if (tile_live)
-        for (uint32_t x = j; x < (uint32_t)LSTART_N; x += PRE_THREADS)
-            gp(lv.lstart)[(size_t)tile * LSTART_N + x] = x < (uint32_t)SEG_N ? (uint16_t)s_cnt[g][x] : 0;
+    for (uint32_t x = j; x < (uint32_t)LSTART_N; x += PRE_THREADS)
+        gp(lv.lstart)[(size_t)tile * LSTART_N + x] = x < (uint32_t)SEG_N ? (uint16_t)s_cnt[x] : 0;
 
-    // open entries, in order: ranks within the block, then one look-back per block
-    uint32_t total;
-    const uint32_t rank = block_excl_scan<PRE_BLOCK>(is_open ? 1u : 0u, s_tmp, &total);
-    if (j == 0) s_tile_excl[g] = rank;
-    __syncthreads();
-    if (j == PRE_THREADS - 1) s_tile_cnt[g] = rank + (is_open ? 1u : 0u) - s_tile_excl[g];
-    __shared__ LbScratch<PRE_BLOCK / WAVE> s_lb;
-    const uint32_t base = (uint32_t)lookback_block<OpSum, PRE_BLOCK>(lv.status, 1, blk, total, ctrl, s_lb);
-    const uint32_t trank = rank - s_tile_excl[g];
+    // ---- the open entries' places in S_{k+1}
+    const uint32_t base = (uint32_t)lookback_block_resolve<OpSum, PRE_BLOCK>(lv.status, 1, tile, total, ctrl, s_lb);
     if (is_open) {
-        if (trank < (uint32_t)OPEN_CAP) gp(lv.opos)[(size_t)tile * OPEN_CAP + trank] = (uint16_t)j;
+        if (rank < (uint32_t)OPEN_CAP) gp(lv.opos)[(size_t)tile * OPEN_CAP + rank] = (uint16_t)j;
         if ((uint32_t)k < fd.K) {
             const RahtLevel &nx = fd.lv[k + 1];
             const uint32_t o = base + rank;
@@ -233,11 +241,10 @@ __global__ __launch_bounds__(PRE_BLOCK) void k_prelude(TileMap m, int k)
             }
         }
     }
-    if (j == 0 && tile_live) {
-        const uint32_t tc = s_tile_cnt[g];
-        if (tc > open_max((int)fd.J)) set_error(ctrl, GSC_ERR_INTERNAL);
-        lv.obase[tile] = base + s_tile_excl[g];
-        lv.ocnt[tile] = min(tc, (uint32_t)OPEN_CAP);
+    if (j == 0) {
+        if (total > open_max((int)fd.J)) set_error(ctrl, GSC_ERR_INTERNAL);
+        lv.obase[tile] = base;
+        lv.ocnt[tile] = min(total, (uint32_t)OPEN_CAP);
         if (e == nk) ctrl->lvl_n[k + 1] = base + total;
     }
 }
