@@ -316,16 +316,12 @@ gsc_status decode_frames(const Frame *fr, int F, int J, int C, hipStream_t s)
     {
         StageScope sc(GSC_STAGE_OCTREE_DEC, s);
         {
-            TileMap m = make_map(fr, F, [](const Frame &) { return 1u; });
-            GSC_LAUNCH(launch_dec_top(m, s));
+            TileMap m = make_map(fr, F, [](const Frame &x) { return x.L.dec_tiles; });
+            GSC_LAUNCH(launch_dec_expand(m, s));
         }
-        for (int d = 0; d < J; ++d) {
-            // a level can outgrow the top kernel only if its child level can exceed its capacity
-            TileMap m = make_map(fr, F, [d](const Frame &x) {
-                return level_cap(d + 1, x.a.n ? x.a.n : 1) > (uint64_t)DEC_TOP_CAP ? x.L.dec_tiles[d] : 0u;
-            });
-            if (m.start[F] == 0) continue;
-            GSC_LAUNCH(launch_dec_level(m, d, s));
+        {
+            TileMap m = make_map(fr, F, [](const Frame &x) { return ceil_div(x.a.n ? x.a.n : 1, LEAF_THREADS); });
+            GSC_LAUNCH(launch_dec_leaves(m, s));
         }
     }
     const RahtCfg cfg = raht_cfg(fr, F, C, nullptr);

@@ -37,11 +37,10 @@ constexpr int OCC_THREADS = 1024;        // 16 waves: the per-depth look-backs r
 constexpr int OCC_VPT = 2;              // voxels per thread
 constexpr int OCC_TILE = OCC_THREADS * OCC_VPT;
 
-constexpr int DEC_TOP_CAP = 8192;       // octree levels this small are expanded in one workgroup
 constexpr int DEC_THREADS = 256;
-constexpr int DEC_PPT = 8;              // parents per thread
+constexpr int DEC_PPT = 8;              // occupancy bytes per thread
 constexpr int DEC_TILE = DEC_THREADS * DEC_PPT;
-constexpr int DEC_CHUNK = 8192;         // children staged in LDS per round (64 KB)
+constexpr int LEAF_THREADS = 256;       // one leaf per thread
 
 constexpr int RT = 512;                 // RAHT tile: entries (eight 64-entry wave chunks)
 constexpr int RAHT_THREADS = 512;       // one wave per chunk
@@ -60,7 +59,7 @@ constexpr uint32_t BBOX_SENTINEL_MIN = 0xFFFFFFFFu;
 struct Ctrl {
     uint32_t error;              // first device error (gsc_status), 0 = ok
     uint32_t n_vox;              // Nv
-    uint32_t dec_start;          // decoder: first level handled by the per-level kernels
+    uint32_t dec_unused;
     uint32_t n_in;
     uint32_t bbox_ord[6];        // order-preserving uint of float: min x,y,z, max x,y,z
     uint32_t reserved[96];
@@ -149,8 +148,9 @@ struct FrameDesc {
     uint32_t *sort_status;   // P x sort tiles x SORT_BINS
     uint64_t *dedup_status;
     uint64_t *occ_status;    // occ tiles x J
-    uint64_t *dec_status;    // per octree level d: dec_status + dec_status_off[d]
-    uint32_t dec_status_off[GSC_MAX_DEPTH + 1];
+    uint64_t *dec_status;    // decoder: look-back status of the occupancy-byte tiles
+    uint32_t *dec_par;       // decoder: each node's parent (index in its parent's level); the
+    uint8_t *dec_cbit;       //   nodes of levels 1..J one after the other; its child bit
     uint32_t sort_tiles, dedup_tiles, occ_tiles;
     uint32_t K;              // RAHT tiling levels
     RahtLevel lv[MAXK + 1];  // index 1..K
@@ -207,9 +207,9 @@ struct Layout {
     size_t total;
     size_t zero_off, zero_bytes;
     size_t keys_a, keys_b, vals_a, vals_b, leaf, vh, first;
-    size_t sort_status, dedup_status, occ_status, dec_status;
-    uint32_t dec_status_off[GSC_MAX_DEPTH + 1];
-    uint32_t dec_tiles[GSC_MAX_DEPTH + 1];
+    size_t sort_status, dedup_status, occ_status, dec_status, dec_par, dec_cbit;
+    uint32_t dec_tiles;      // decoder: tiles of DEC_TILE occupancy bytes (all levels together)
+    uint64_t dec_nodes;      // decoder: worst-case nodes of levels 1..J
     uint32_t sort_tiles, dedup_tiles, occ_tiles, P, K;
     size_t s_idx[MAXK + 1], s_lvl[MAXK + 1], rec[MAXK + 1], lstart[MAXK + 1], lmask[MAXK + 1], opos[MAXK + 1],
         obase[MAXK + 1], ocnt[MAXK + 1], status[MAXK + 1], vbuf[MAXK + 1];
@@ -268,13 +268,12 @@ __host__ __device__ inline bool make_layout(int64_t n, int J, int C, Layout *L)
     L->occ_status = off;
     off = align_up(off + (size_t)L->occ_tiles * J * 8, 256);
     L->dec_status = off;
-    uint32_t dsum = 0;
-    for (int d = 0; d <= GSC_MAX_DEPTH; ++d) {
-        L->dec_status_off[d] = dsum;
-        L->dec_tiles[d] = d < J ? ceil_div(level_cap(d, N), DEC_TILE) : 0;
-        dsum += L->dec_tiles[d];
-    }
-    off = align_up(off + (size_t)dsum * 8, 256);
+    uint64_t occ_cap = 0, nodes = 0;
+    for (int d = 0; d < J; ++d) occ_cap += level_cap(d, N);
+    for (int d = 1; d <= J; ++d) nodes += level_cap(d, N);
+    L->dec_tiles = ceil_div(occ_cap, DEC_TILE);
+    L->dec_nodes = nodes;
+    off = align_up(off + (size_t)L->dec_tiles * 8, 256);
     for (uint32_t k = 1; k <= K; ++k) {
         L->status[k] = off;
         off = align_up(off + (size_t)L->tiles[k] * 8, 256);
@@ -287,6 +286,8 @@ __host__ __device__ inline bool make_layout(int64_t n, int J, int C, Layout *L)
     L->vals_b = off; off = align_up(off + N * 4, 256);
     L->leaf = off; off = align_up(off + N * 8, 256);
     L->vh = off; off = align_up(off + (N + 1) * 4, 256);
+    L->dec_par = off; off = align_up(off + nodes * 4, 256);
+    L->dec_cbit = off; off = align_up(off + nodes, 256);
     L->first = off; off = align_up(off + N * 4, 256);
     for (uint32_t k = 1; k <= K; ++k) {
         const uint32_t t = L->tiles[k];
@@ -312,8 +313,8 @@ hipError_t launch_voxelize(const TileMap &m, hipStream_t s);
 hipError_t launch_sort_pass(const TileMap &m, int pass, int variant, hipStream_t s);
 hipError_t launch_dedup(const TileMap &m, hipStream_t s);
 hipError_t launch_occupancy(const TileMap &m, hipStream_t s);
-hipError_t launch_dec_top(const TileMap &m, hipStream_t s);
-hipError_t launch_dec_level(const TileMap &m, int d, hipStream_t s);
+hipError_t launch_dec_expand(const TileMap &m, hipStream_t s);
+hipError_t launch_dec_leaves(const TileMap &m, hipStream_t s);
 hipError_t launch_prelude(const TileMap &m, int k, hipStream_t s);
 // Compile-time specializations of the transform kernels: vec = C % 4 == 0 and every row
 // pointer 16-byte aligned; pow2 = every quantization step a power of two.

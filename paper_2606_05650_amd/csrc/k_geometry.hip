@@ -96,8 +96,9 @@ __global__ __launch_bounds__(256) void k_setup(SetupArgs a)
             lv.tiles = 0;
             lv.cap = 0;
         }
-    } else if (t >= 96 && t <= 96 + GSC_MAX_DEPTH) {
-        fd->dec_status_off[t - 96] = L.dec_status_off[t - 96];
+    } else if (t == 96) {
+        fd->dec_par = reinterpret_cast<uint32_t *>(fa.ws + L.dec_par);
+        fd->dec_cbit = reinterpret_cast<uint8_t *>(fa.ws + L.dec_cbit);
     } else if (t == 128) {
         fd->n = fa.n;
         fd->J = a.J;
@@ -807,6 +808,15 @@ hipError_t launch_occupancy(const TileMap &m, hipStream_t s)
 // count (population count), an exclusive prefix sum gives each parent's first child slot, and
 // every parent writes (p << 3) + i for each set bit i in ascending order. The leaves are then
 // turned back into voxel coordinates and voxel centres.
+//
+// Every level's bytes are in the stream from the start, so the decoder does not go level by
+// level. Numbering the nodes of levels 1..J one after the other (level L's from
+// Q(L) = |L_1| + ... + |L_{L-1}|), the first child of the node whose byte is the q-th byte of the
+// stream is node P(q), the number of set bits in the bytes before it: one prefix sum over all
+// bytes places every child. `k_dec_expand` writes for every node its parent's index in the
+// parent's level and its child bit i (its code is the parent's code times 8 plus i);
+// `k_dec_leaves` then builds each leaf's code from the child bits along its path to the root,
+// most significant first, which is the code the level-by-level expansion produces.
 
 // Writes leaf v: its code, voxel coordinates and centre min + (v + 1/2) * cell (FP64, rounded
 // once to float).
@@ -826,7 +836,8 @@ __device__ inline void emit_leaf(const FrameDesc &fd, const gsc_header *h, uint3
 
 // Header checks: everything the decoder relies on must be self-consistent and fit the caller's
 // buffers. Returns true when the header is usable.
-__device__ inline bool header_ok(const FrameDesc &fd, const gsc_header *h)
+template <class HeaderPtr>
+__device__ inline bool header_ok(const FrameDesc &fd, HeaderPtr h)
 {
     if (fd.in_bytes < GSC_HEADER_BYTES) return false;
     if (h->magic != GSC_MAGIC || h->version != GSC_VERSION) return false;
@@ -851,142 +862,70 @@ __device__ inline bool header_ok(const FrameDesc &fd, const gsc_header *h)
     return true;
 }
 
-constexpr int DEC_TOP_THREADS = 1024;
-
-// One workgroup per frame: checks the header, then expands the top levels in LDS while the
-// next level has at most DEC_TOP_CAP nodes. Leaves the last level it built in the ping-pong
-// buffer of that level (or emits the leaves when it reached depth J).
-__global__ __launch_bounds__(DEC_TOP_THREADS) void k_dec_top(TileMap m)
+// The level of the q-th occupancy byte and that level's first byte: levels are contiguous, so a
+// scan over the (at most 21) level starts from the previous answer finds it.
+struct LevelCursor {
+    uint32_t d, start, end;  // level, its first byte, one past its last byte
+};
+__device__ inline void level_seek(const CAS gsc_header *h, uint32_t J, uint64_t q, LevelCursor &lc)
 {
-    __shared__ uint64_t s_lv[2][DEC_TOP_CAP];
-    __shared__ uint32_t s_tmp[DEC_TOP_THREADS / WAVE + 1];
-    __shared__ int s_ok;
-    const uint32_t f = blockIdx.x;
-    if (f >= m.F) return;
-    const FrameDesc &fd = *m.fd[f];
-    Ctrl *ctrl = fd.ctrl;
-    const gsc_header *h = reinterpret_cast<const gsc_header *>(fd.in_stream);
-    const uint32_t tid = threadIdx.x;
-    if (tid == 0) {
-        s_ok = header_ok(fd, h) ? 1 : 0;
-        if (!s_ok) {
-            set_error(ctrl, GSC_ERR_CORRUPT_STREAM);
-        } else {
-            ctrl->n_vox = h->n_vox;
-            for (uint32_t d = 0; d <= fd.J; ++d) ctrl->level_sizes[d] = h->level_sizes[d];
-        }
+    while (lc.d + 1 < J && q >= lc.end) {
+        ++lc.d;
+        lc.start = lc.end;
+        lc.end += h->level_sizes[lc.d];
     }
-    __syncthreads();
-    if (!s_ok) return;
-    const uint32_t J = fd.J, nv = h->n_vox;
-    if (nv == 0) {
-        if (tid == 0) ctrl->dec_start = J;
-        return;
-    }
-    const uint8_t *occ = fd.in_stream + GSC_HEADER_BYTES;
-    if (tid == 0) s_lv[0][0] = 0;
-    __syncthreads();
-    uint32_t d = 0, cur = 0;
-    uint64_t off = 0;
-    bool bad = false;
-    for (; d < J; ++d) {
-        const uint32_t M = h->level_sizes[d], Mn = h->level_sizes[d + 1];
-        if (Mn > (uint32_t)DEC_TOP_CAP) break;
-        // each thread takes up to DEC_TOP_CAP / DEC_TOP_THREADS consecutive parents
-        constexpr int PPT = DEC_TOP_CAP / DEC_TOP_THREADS;
-        uint32_t bytes[PPT], cnt = 0;
-#pragma unroll
-        for (int i = 0; i < PPT; ++i) {
-            const uint32_t p = tid * PPT + i;
-            bytes[i] = p < M ? occ[off + p] : 0u;
-            if (p < M && bytes[i] == 0) bad = true;
-            cnt += __popc(bytes[i]);
-        }
-        uint32_t total;
-        uint32_t w = block_excl_scan<DEC_TOP_THREADS>(cnt, s_tmp, &total);
-        if (total != Mn) {
-            bad = true;
-        } else {
-#pragma unroll
-            for (int i = 0; i < PPT; ++i) {
-                const uint32_t p = tid * PPT + i;
-                if (p >= M) break;
-                const uint64_t base = s_lv[cur][p] << 3;
-                for (uint32_t c = 0; c < 8; ++c)
-                    if (bytes[i] >> c & 1u) s_lv[cur ^ 1][w++] = base + c;
-            }
-        }
-        if (__syncthreads_or(bad)) {
-            if (tid == 0) set_error(ctrl, GSC_ERR_CORRUPT_STREAM);
-            return;
-        }
-        off += M;
-        cur ^= 1;
-    }
-    const uint32_t Md = h->level_sizes[d];
-    if (d == J) {
-        for (uint32_t v = tid; v < Md; v += DEC_TOP_THREADS) emit_leaf(fd, h, v, s_lv[cur][v]);
-    } else {
-        uint64_t *dst = (d & 1) ? fd.keys_b : fd.keys_a;
-        for (uint32_t v = tid; v < Md; v += DEC_TOP_THREADS) dst[v] = s_lv[cur][v];
-    }
-    if (tid == 0) ctrl->dec_start = d;
 }
 
-hipError_t launch_dec_top(const TileMap &m, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_dec_top, dim3(m.F), dim3(DEC_TOP_THREADS), 0, s, m);
-    return hipGetLastError();
-}
-
-// Expansion of one level d >= the top kernel's stopping level, for all parents at once.
-__global__ __launch_bounds__(DEC_THREADS) void k_dec_level(TileMap m, int d)
+// One pass over all occupancy bytes: tile t holds bytes [t DEC_TILE, (t + 1) DEC_TILE) of the
+// stream's occupancy section, striped (byte s + r DEC_THREADS + tid), and finds each byte's
+// child slots with a decoupled look-back over the tiles' set-bit counts. Checks: no byte is 0,
+// and the first byte of every level is the parent of the first node of the next level (its prefix
+// equals Q(d + 1)), and the bytes hold exactly |L_1| + ... + |L_J| set bits.
+__global__ __launch_bounds__(DEC_THREADS) void k_dec_expand(TileMap m)
 {
     constexpr int NW = DEC_THREADS / WAVE;
     static_assert(DEC_PPT * NW <= WAVE, "one wave scans the (row, wave) child counts");
-    __shared__ uint32_t s_tile;
     __shared__ uint32_t s_cnt[WAVE + 1];
+    __shared__ LbScratch<DEC_THREADS / WAVE> s_lb;
     const uint32_t f = frame_of(m, blockIdx.x);
     const FrameDesc &fd = *m.fd[f];
     Ctrl *ctrl = fd.ctrl;
-    if (load_error(ctrl)) return;
-    if ((uint32_t)d >= fd.J || (uint32_t)d < ctrl->dec_start) return;
-    const gsc_header *h = reinterpret_cast<const gsc_header *>(fd.in_stream);
-    const uint32_t J = fd.J;
-    const uint32_t M = ctrl->level_sizes[d], Mn = ctrl->level_sizes[d + 1];
-    const uint32_t tid = threadIdx.x, w = tid / WAVE, lane = lane_id();
-    if (tid == 0) s_tile = tile_index(m, f);
-    __syncthreads();
-    const uint32_t tile = s_tile;
-    const uint32_t s = tile * DEC_TILE;
-    if (s >= M) return;
-    uint64_t off = 0;
-    for (int dd = 0; dd < d; ++dd) off += ctrl->level_sizes[dd];
-    const GAS uint8_t *occ = gp(fd.in_stream + GSC_HEADER_BYTES + off);
-    const GAS uint64_t *src = gp((d & 1) ? fd.keys_b : fd.keys_a);
-    GAS uint64_t *dst = gp((d & 1) ? fd.keys_a : fd.keys_b);
-    // striped (coalesced) parents: parent p = s + r * DEC_THREADS + tid; its children follow
-    // those of the parents before it, so a wave's children are one contiguous run per row
+    const uint32_t tile = tile_index(m, f), tid = threadIdx.x, w = tid / WAVE, lane = lane_id();
+    const gsc_header *hg = reinterpret_cast<const gsc_header *>(fd.in_stream);
+    const CAS gsc_header *h = cp(hg);  // (the stream is not written while it is decoded)
+    if (!header_ok(fd, h)) {
+        if (tile == 0 && tid == 0) set_error(ctrl, GSC_ERR_CORRUPT_STREAM);
+        return;
+    }
+    const uint32_t J = fd.J, nv = h->n_vox;
+    const uint64_t B = h->occ_bytes;
+    if (tile == 0 && tid == 0) {
+        ctrl->n_vox = nv;
+        for (uint32_t d = 0; d <= J; ++d) ctrl->level_sizes[d] = h->level_sizes[d];
+    }
+    const uint64_t s = (uint64_t)tile * DEC_TILE;
+    if (s >= B) return;
+    uint64_t total_nodes = 0;  // |L_1| + ... + |L_J|
+    for (uint32_t d = 1; d <= J; ++d) total_nodes += h->level_sizes[d];
+    const GAS uint8_t *occ = gp(fd.in_stream + GSC_HEADER_BYTES);
     uint32_t bytes[DEC_PPT], wex[DEC_PPT];
-    uint64_t parent[DEC_PPT];
     bool bad = false;
 #pragma unroll
     for (int r = 0; r < DEC_PPT; ++r) {
-        const uint32_t p = s + r * DEC_THREADS + tid;
-        bytes[r] = p < M ? occ[p] : 0u;
-        parent[r] = p < M ? src[p] : 0ull;
+        const uint64_t q = s + r * DEC_THREADS + tid;
+        bytes[r] = q < B ? occ[q] : 0u;
     }
 #pragma unroll
     for (int r = 0; r < DEC_PPT; ++r) {
-        const uint32_t p = s + r * DEC_THREADS + tid;
-        if (p < M && bytes[r] == 0) bad = true;
+        const uint64_t q = s + r * DEC_THREADS + tid;
+        if (q < B && bytes[r] == 0) bad = true;
         const uint32_t c = (uint32_t)__popc(bytes[r]);
         const uint32_t inc = wave_incl_scan(c);
         wex[r] = inc - c;
         if (lane == WAVE - 1) s_cnt[r * NW + w] = inc;
     }
     __syncthreads();
-    if (w == 0) {  // (row, wave) totals in parent order -> exclusive offsets
+    if (w == 0) {  // (row, wave) totals in byte order -> exclusive offsets
         const uint32_t c = lane < (uint32_t)(DEC_PPT * NW) ? s_cnt[lane] : 0u;
         const uint32_t inc = wave_incl_scan(c);
         if (lane < (uint32_t)(DEC_PPT * NW)) s_cnt[lane] = inc - c;
@@ -994,50 +933,79 @@ __global__ __launch_bounds__(DEC_THREADS) void k_dec_level(TileMap m, int d)
     }
     __syncthreads();
     const uint32_t total = s_cnt[WAVE];
-    __shared__ LbScratch<DEC_THREADS / WAVE> s_lb;
-    const uint32_t wbase = (uint32_t)lookback_block<OpSum, DEC_THREADS>(fd.dec_status + fd.dec_status_off[d], 1, tile, total, ctrl, s_lb);
-    // children through LDS in output order, DEC_CHUNK at a time, so that the codes (or the
-    // leaves' positions) are written by consecutive threads to consecutive slots
-    __shared__ uint64_t s_child[DEC_CHUNK];
-    uint32_t first[DEC_PPT];
+    const uint64_t base = lookback_block<OpSum, DEC_THREADS>(fd.dec_status, 1, tile, total, ctrl, s_lb);
+    GAS uint32_t *par = gp(fd.dec_par);
+    GAS uint8_t *cbit = gp(fd.dec_cbit);
+    LevelCursor lc;
+    lc.d = 0;
+    lc.start = 0;
+    lc.end = h->level_sizes[0];
+    uint64_t q_level_next = 0;  // Q(d + 1) of the cursor's level d: nodes of levels 1..d
+    uint32_t qd = 0;
 #pragma unroll
-    for (int r = 0; r < DEC_PPT; ++r) first[r] = s_cnt[r * NW + w] + wex[r];
-    const bool leaves = (uint32_t)d + 1 == J;
-    for (uint32_t c0 = 0; c0 < total; c0 += DEC_CHUNK) {
-        const uint32_t c1 = c0 + DEC_CHUNK;
-#pragma unroll
-        for (int r = 0; r < DEC_PPT; ++r) {
-            const uint32_t nc = (uint32_t)__popc(bytes[r]);
-            if (first[r] >= c1 || first[r] + nc <= c0) continue;
-            uint32_t j = first[r];
-            const uint64_t pc = parent[r] << 3;
-            for (uint32_t c = 0; c < 8; ++c) {
-                if (bytes[r] >> c & 1u) {
-                    if (j >= c0 && j < c1) s_child[j - c0] = pc + c;
-                    ++j;
+    for (int r = 0; r < DEC_PPT; ++r) {
+        const uint64_t q = s + r * DEC_THREADS + tid;
+        if (q >= B) break;
+        level_seek(h, J, q, lc);
+        while (qd < lc.d) q_level_next += h->level_sizes[++qd];
+        const uint64_t P = base + s_cnt[r * NW + w] + wex[r];  // set bits before byte q
+        if (q == lc.start && P != q_level_next) bad = true;    // the level's first child
+        if (q + 1 == B && P + (uint64_t)__popc(bytes[r]) != total_nodes) bad = true;
+        const uint32_t p = (uint32_t)(q - lc.start);            // the parent's index in its level
+        uint64_t c = P;
+        for (uint32_t i = 0; i < 8; ++i) {
+            if (bytes[r] >> i & 1u) {
+                if (c < total_nodes) {
+                    par[c] = p;
+                    cbit[c] = (uint8_t)i;
+                } else {
+                    bad = true;
                 }
+                ++c;
             }
         }
-        __syncthreads();
-        const uint32_t nh = min((uint32_t)DEC_CHUNK, total - c0);
-        for (uint32_t x = tid; x < nh; x += DEC_THREADS) {
-            const uint32_t o = wbase + c0 + x;
-            if (o < Mn) {
-                if (leaves) emit_leaf(fd, h, o, s_child[x]);
-                else dst[o] = s_child[x];
-            } else {
-                bad = true;
-            }
-        }
-        __syncthreads();
     }
     if (bad) set_error(ctrl, GSC_ERR_CORRUPT_STREAM);
-    if (tid == 0 && s + DEC_TILE >= M && wbase + total != Mn) set_error(ctrl, GSC_ERR_CORRUPT_STREAM);
 }
 
-hipError_t launch_dec_level(const TileMap &m, int d, hipStream_t s)
+hipError_t launch_dec_expand(const TileMap &m, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_dec_level, dim3(m.start[m.F]), dim3(DEC_THREADS), 0, s, m, d);
+    hipLaunchKernelGGL(k_dec_expand, dim3(m.start[m.F]), dim3(DEC_THREADS), 0, s, m);
+    return hipGetLastError();
+}
+
+// One thread per leaf: the leaf's code from the child bits on its path to the root (level J's bit
+// least significant), then its voxel coordinates and centre.
+__global__ __launch_bounds__(LEAF_THREADS) void k_dec_leaves(TileMap m)
+{
+    const uint32_t f = frame_of(m, blockIdx.x);
+    const FrameDesc &fd = *m.fd[f];
+    Ctrl *ctrl = fd.ctrl;
+    if (__builtin_amdgcn_readfirstlane(load_error(ctrl))) return;
+    const gsc_header *hg = reinterpret_cast<const gsc_header *>(fd.in_stream);
+    const CAS gsc_header *h = cp(hg);
+    const uint32_t J = fd.J, nv = h->n_vox;
+    const uint32_t v = tile_index(m, f) * LEAF_THREADS + threadIdx.x;
+    if (v >= nv) return;
+    const GAS uint32_t *par = gp(fd.dec_par);
+    const GAS uint8_t *cbit = gp(fd.dec_cbit);
+    uint64_t qL = 0;  // Q(L): nodes of levels 1..L-1
+    for (uint32_t L = 1; L < J; ++L) qL += h->level_sizes[L];
+    uint64_t code = 0;
+    uint32_t x = v;
+    for (uint32_t L = J; L >= 1; --L) {
+        const uint32_t size = h->level_sizes[L];
+        const uint64_t g = qL + min(x, size - 1);  // (clamped: never an access outside the nodes)
+        code |= (uint64_t)cbit[g] << (3 * (J - L));
+        x = par[g];
+        if (L > 1) qL -= h->level_sizes[L - 1];
+    }
+    emit_leaf(fd, hg, v, code);
+}
+
+hipError_t launch_dec_leaves(const TileMap &m, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_dec_leaves, dim3(m.start[m.F]), dim3(LEAF_THREADS), 0, s, m);
     return hipGetLastError();
 }
 
