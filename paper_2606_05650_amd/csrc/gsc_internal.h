@@ -38,7 +38,7 @@ constexpr int OCC_VPT = 2;              // voxels per thread
 constexpr int OCC_TILE = OCC_THREADS * OCC_VPT;
 
 constexpr int DEC_THREADS = 256;
-constexpr int DEC_PPT = 8;              // occupancy bytes per thread
+constexpr int DEC_PPT = 16;             // occupancy bytes per thread
 constexpr int DEC_TILE = DEC_THREADS * DEC_PPT;
 constexpr int LEAF_THREADS = 256;       // one leaf per thread
 

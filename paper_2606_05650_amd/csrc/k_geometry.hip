@@ -835,30 +835,38 @@ __device__ inline void emit_leaf(const FrameDesc &fd, const gsc_header *h, uint3
 }
 
 // Header checks: everything the decoder relies on must be self-consistent and fit the caller's
-// buffers. Returns true when the header is usable.
-template <class HeaderPtr>
-__device__ inline bool header_ok(const FrameDesc &fd, HeaderPtr h)
+// buffers. Performed by one wave, lane l checking level l's size against the next one and the
+// quantizer step of channel l; returns true (in every lane) when the header is usable.
+__device__ inline bool header_ok_wave(const FrameDesc &fd, const CAS gsc_header *h)
 {
+    const uint32_t lane = lane_id();
     if (fd.in_bytes < GSC_HEADER_BYTES) return false;
     if (h->magic != GSC_MAGIC || h->version != GSC_VERSION) return false;
     if (h->J != fd.J || h->C != fd.C || h->error != 0) return false;
-    const uint32_t J = fd.J, nv = h->n_vox;
+    const uint32_t J = fd.J, C = fd.C, nv = h->n_vox;
     if (nv > fd.n) return false;
     if (h->level_sizes[J] != nv) return false;
     if (h->level_sizes[0] != (nv > 0 ? 1u : 0u)) return false;
-    uint64_t occ = 0;
-    for (uint32_t d = 0; d < J; ++d) {
-        const uint64_t a = h->level_sizes[d], b = h->level_sizes[d + 1];
-        if (b < a || b > 8 * a) return false;
-        occ += a;
+    if (!(h->cell > 0.0)) return false;
+    bool bad = false;
+    uint64_t a = 0;
+    if (lane < J) {
+        a = h->level_sizes[lane];
+        const uint64_t b = h->level_sizes[lane + 1];
+        bad = b < a || b > 8 * a;
     }
+    if (lane < C) {
+        const float st = h->quant_step[lane];
+        bad = bad || !(st > 0.0f) || !isfinite(st);
+    }
+    uint64_t occ = a;  // the occupancy bytes: sizes of levels 0..J-1
+#pragma unroll
+    for (int o = 1; o < WAVE; o <<= 1) occ += __shfl_xor(occ, o, WAVE);
+    if (__ballot(bad) != 0ull) return false;
     if (h->occ_offset != GSC_HEADER_BYTES || h->occ_bytes != occ) return false;
     const uint64_t co = align_up(GSC_HEADER_BYTES + occ, 256);
-    if (h->coef_offset != co || h->coef_bytes != (uint64_t)nv * fd.C * 4) return false;
+    if (h->coef_offset != co || h->coef_bytes != (uint64_t)nv * C * 4) return false;
     if (h->total_bytes != co + h->coef_bytes || h->total_bytes > fd.in_bytes) return false;
-    for (uint32_t c = 0; c < fd.C; ++c)
-        if (!(h->quant_step[c] > 0.0f) || !isfinite(h->quant_step[c])) return false;
-    if (!(h->cell > 0.0)) return false;
     return true;
 }
 
@@ -893,7 +901,13 @@ __global__ __launch_bounds__(DEC_THREADS) void k_dec_expand(TileMap m)
     const uint32_t tile = tile_index(m, f), tid = threadIdx.x, w = tid / WAVE, lane = lane_id();
     const gsc_header *hg = reinterpret_cast<const gsc_header *>(fd.in_stream);
     const CAS gsc_header *h = cp(hg);  // (the stream is not written while it is decoded)
-    if (!header_ok(fd, h)) {
+    __shared__ int s_ok;
+    if (w == 0) {
+        const bool ok = header_ok_wave(fd, h);
+        if (lane == 0) s_ok = ok ? 1 : 0;
+    }
+    __syncthreads();
+    if (!s_ok) {
         if (tile == 0 && tid == 0) set_error(ctrl, GSC_ERR_CORRUPT_STREAM);
         return;
     }
