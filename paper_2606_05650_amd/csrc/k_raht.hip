@@ -372,12 +372,12 @@ __device__ inline uint32_t next_level(uint64_t mask, bool inverse)
 // moving one level's accesses across the next level's. Only channel chunks below nch are live.
 __device__ inline void wave_phase(float4 *s_y, const Roles &R, const uint32_t *s_rec,
                                   const float2 *s_ab, const uint16_t *s_lst, uint64_t mask,
-                                  uint32_t nch, bool inverse)
+                                  uint32_t nch, bool inverse, uint32_t cls)
 {
     const bool live = R.wact && R.wc4 < nch;
     const uint32_t lane = lane_id();
-    const uint32_t lq0 = s_lst[lane * NCLS + R.w], lq1 = s_lst[lane * NCLS + R.w + 1];
-    mask = uniform64(mask);  // the wave's own class: one mask per wave
+    const uint32_t lq0 = s_lst[lane * NCLS + cls], lq1 = s_lst[lane * NCLS + cls + 1];
+    mask = uniform64(mask);  // one class per wave: one mask per wave
     uint32_t x = mask ? next_level(mask, inverse) : 0u;
     uint32_t q0 = __builtin_amdgcn_readlane(lq0, x), q1 = __builtin_amdgcn_readlane(lq1, x);
     uint32_t rec = 0;
@@ -411,46 +411,16 @@ __device__ inline void wave_phase(float4 *s_y, const Roles &R, const uint32_t *s
     }
 }
 
-// Merges crossing chunks, level by level with workgroup barriers; record ranges in registers and
-// each level's first records loaded one level ahead, as in wave_phase.
-__device__ inline void block_phase(float4 *s_y, const Roles &R, const uint32_t *s_rec,
+// Merges crossing chunks: few per level (a node crosses a chunk boundary only where it holds
+// one), so wave 0 performs them all, level by level in its own instruction order, and the
+// workgroup waits at one barrier instead of one per level.
+__device__ inline void cross_phase(float4 *s_y, const Roles &R, const uint32_t *s_rec,
                                    const float2 *s_ab, const uint16_t *s_lst, uint64_t mask,
                                    uint32_t nch, bool inverse)
 {
-    const bool live = R.act && R.c4 < nch;
-    const uint32_t lane = lane_id();
-    const uint32_t lq0 = s_lst[lane * NCLS + CROSS], lq1 = s_lst[lane * NCLS + CROSS + 1];
-    mask = uniform64(mask);
-    uint32_t x = mask ? next_level(mask, inverse) : 0u;
-    uint32_t q0 = __builtin_amdgcn_readlane(lq0, x), q1 = __builtin_amdgcn_readlane(lq1, x);
-    uint32_t rec = 0;
-    float2 ab = make_float2(0.f, 0.f);
-    if (live && q0 + R.row0 < q1) {
-        rec = s_rec[q0 + R.row0];
-        ab = s_ab[q0 + R.row0];
-    }
-    while (mask) {
-        mask &= ~(1ull << x);
-        const uint32_t xn = mask ? next_level(mask, inverse) : 0u;
-        const uint32_t q0n = __builtin_amdgcn_readlane(lq0, xn), q1n = __builtin_amdgcn_readlane(lq1, xn);
-        uint32_t recn = 0;
-        float2 abn = make_float2(0.f, 0.f);
-        if (mask && live && q0n + R.row0 < q1n) {
-            recn = s_rec[q0n + R.row0];
-            abn = s_ab[q0n + R.row0];
-        }
-        if (live && q0 + R.row0 < q1) {
-            butterfly(s_y, R.C4, rec, ab, R.c4, inverse);
-            for (uint32_t q = q0 + R.row0 + R.RPB; q < q1; q += R.RPB)
-                butterfly(s_y, R.C4, s_rec[q], s_ab[q], R.c4, inverse);
-        }
-        __syncthreads();
-        x = xn;
-        q0 = q0n;
-        q1 = q1n;
-        rec = recn;
-        ab = abn;
-    }
+    if (__builtin_amdgcn_readfirstlane(R.w) == 0)
+        wave_phase(s_y, R, s_rec, s_ab, s_lst, mask, nch, inverse, CROSS);
+    __syncthreads();
 }
 
 __device__ inline float get4(const float4 &v, int i)
@@ -617,9 +587,9 @@ __global__ __launch_bounds__(RAHT_THREADS) void k_raht_fwd_up(TileMap m, int k)
     __syncthreads();
     // ---- all local merges: within wave chunks, then across chunks (levels ascending)
     const uint64_t wmask = s_lmask[R.w], xmask = s_lmask[CROSS];
-    wave_phase(s_y, R, s_rec, s_ab, s_lst, wmask, nch, false);
+    wave_phase(s_y, R, s_rec, s_ab, s_lst, wmask, nch, false, R.w);
     __syncthreads();
-    block_phase(s_y, R, s_rec, s_ab, s_lst, xmask, nch, false);
+    cross_phase(s_y, R, s_rec, s_ab, s_lst, xmask, nch, false);
     // ---- outputs: coefficient rows of every entry at its voxel (an open entry's row is
     // rewritten by the level that completes its merge), open entries' partial low-passes to
     // S_{k+1}
@@ -936,9 +906,9 @@ __global__ __launch_bounds__(RAHT_THREADS) __attribute__((amdgpu_waves_per_eu(PE
                 __syncthreads();
             }
             const uint64_t wmask = s_lmask[R.w], xmask = s_lmask[CROSS];
-            wave_phase(s_y, R, s_rec, s_ab, s_lst, wmask, nch, false);
+            wave_phase(s_y, R, s_rec, s_ab, s_lst, wmask, nch, false, R.w);
             __syncthreads();
-            block_phase(s_y, R, s_rec, s_ab, s_lst, xmask, nch, false);
+            cross_phase(s_y, R, s_rec, s_ab, s_lst, xmask, nch, false);
             if (live) {
                 GAS float *cf = gp(d->coef_f32);
                 if (encode) {
@@ -1105,8 +1075,8 @@ __global__ __launch_bounds__(RAHT_THREADS) __attribute__((amdgpu_waves_per_eu(PE
         if (it0.ok) {
             __syncthreads();  // the open-entry writes
             const uint64_t wmask = s_lmask[R.w], xmask = s_lmask[CROSS];
-            block_phase(s_y, R, s_rec, s_ab, s_lst, xmask, nch, true);
-            wave_phase(s_y, R, s_rec, s_ab, s_lst, wmask, nch, true);
+            cross_phase(s_y, R, s_rec, s_ab, s_lst, xmask, nch, true);
+            wave_phase(s_y, R, s_rec, s_ab, s_lst, wmask, nch, true, R.w);
             __syncthreads();
             if (live) {
                 const uint32_t mlen = it0.mlen, s = it0.s;
@@ -1203,8 +1173,8 @@ __global__ __launch_bounds__(RAHT_THREADS) void k_raht_inv_up(TileMap m, int k)
     }
     // ---- all local merges undone: across chunks, then within chunks (levels descending)
     const uint64_t wmask = s_lmask[R.w], xmask = s_lmask[CROSS];
-    block_phase(s_y, R, s_rec, s_ab, s_lst, xmask, nch, true);
-    wave_phase(s_y, R, s_rec, s_ab, s_lst, wmask, nch, true);
+    cross_phase(s_y, R, s_rec, s_ab, s_lst, xmask, nch, true);
+    wave_phase(s_y, R, s_rec, s_ab, s_lst, wmask, nch, true, R.w);
     __syncthreads();
     if (!live) return;
     GAS float *dst = gp(fd.lv[k - 1].vbuf);
