@@ -257,6 +257,14 @@ hipError_t launch_prelude(const TileMap &m, int k, hipStream_t s)
 uint32_t prelude_blocks(uint32_t tiles) { return ceil_div(tiles, PRE_TILES); }
 
 // =========================================================== shared transform pieces
+// A merge record (entry j | left partner l << 10 | node end r << 20, positions in the tile) as
+// kept in LDS for the transforms: the slice rows of its two operands, l CH4 | j CH4 << 16
+// (at most 511 * 8 < 2^16), so that a butterfly needs no multiply to address them.
+__device__ inline uint32_t lds_rec(uint32_t rec, uint32_t CH4)
+{
+    return ((rec >> 10) & 1023u) * CH4 | (((rec & 1023u) * CH4) << 16);
+}
+
 struct TileSched {
     uint32_t tile, s, e, nk, obase, ocnt, nrec;
     int mlen;
@@ -267,7 +275,7 @@ struct TileSched {
 // open positions, voxel indices of the entries, and the records with (a, b) of every local merge.
 // Returns false if the workgroup has nothing to do.
 __device__ inline bool load_schedule(const FrameDesc &fd, Ctrl *ctrl, int k, uint32_t tile,
-                                     TileSched &ts, uint32_t *s_rec, float2 *s_ab,
+                                     uint32_t CH4, TileSched &ts, uint32_t *s_rec, float2 *s_ab,
                                      uint16_t *s_lst, uint16_t *s_opos, uint32_t *s_idx,
                                      unsigned long long *s_lmask)
 {
@@ -298,7 +306,7 @@ __device__ inline bool load_schedule(const FrameDesc &fd, Ctrl *ctrl, int k, uin
     ts.nrec = s_lst[SEG_N - 1];
     for (uint32_t q = tid; q < ts.nrec; q += NT) {
         const uint32_t rec = recs[(size_t)tile * RT + q];
-        s_rec[q] = rec;
+        s_rec[q] = lds_rec(rec, CH4);
         const uint32_t ij = s_idx[rec & 1023u], il = s_idx[(rec >> 10) & 1023u], ir = s_idx[rec >> 20];
         const float w0 = (float)(ij - il), w1 = (float)(ir - ij);
         const float sum = w0 + w1;
@@ -307,12 +315,15 @@ __device__ inline bool load_schedule(const FrameDesc &fd, Ctrl *ctrl, int k, uin
     return true;
 }
 
-// One butterfly on channels [4*c4, 4*c4+4) of merge record `rec`.
+
+// One butterfly on channels [4*c4, 4*c4+4) of merge record `rec` (in the form of lds_rec).
 __device__ inline void butterfly(float4 *s_y, uint32_t C4, uint32_t rec, float2 ab, uint32_t c4,
                                  bool inverse)
 {
-    const uint32_t j = rec & 1023u, l = (rec >> 10) & 1023u;
-    const float4 y0 = s_y[l * C4 + c4], y1 = s_y[j * C4 + c4];
+    // rec: the LDS rows of the merge's left and right operands, already times the slice width
+    // (see lds_rec)
+    const uint32_t yl = rec & 0xFFFFu, yj = rec >> 16;
+    const float4 y0 = s_y[yl + c4], y1 = s_y[yj + c4];
     float4 lo, hi;
     if (!inverse) {
         lo.x = ab.x * y0.x + ab.y * y1.x;
@@ -333,8 +344,8 @@ __device__ inline void butterfly(float4 *s_y, uint32_t C4, uint32_t rec, float2 
         hi.z = ab.y * y0.z + ab.x * y1.z;
         hi.w = ab.y * y0.w + ab.x * y1.w;
     }
-    s_y[l * C4 + c4] = lo;
-    s_y[j * C4 + c4] = hi;
+    s_y[yl + c4] = lo;
+    s_y[yj + c4] = hi;
 }
 
 // Per-thread roles: in a workgroup step, thread t handles channel chunk t % C4 of row t / C4
@@ -494,6 +505,7 @@ constexpr int UNROLL = 8;  // independent row loads in flight per thread
 // pieces per gathered row).
 constexpr uint32_t CH4_MAX = 4;
 constexpr uint32_t CH4_MAX1 = 8;  // the first level: two slices of up to 32 channels (112-byte row pieces)
+static_assert((RT - 1) * CH4_MAX1 < 65536u, "packed LDS rows of a merge record (lds_rec)");
 __host__ __device__ inline uint32_t channel_passes(uint32_t C4, int k)
 {
     const uint32_t cm = k == 1 ? CH4_MAX1 : CH4_MAX;
@@ -572,7 +584,7 @@ __global__ __launch_bounds__(RAHT_THREADS) void k_raht_fwd_up(TileMap m, int k)
     const uint32_t C = fd.C, C4 = fd.C4;
     const uint32_t NP = channel_passes(C4, k), CH4 = pass_chunks(C4, k);
     const SliceSplit hs = slice_split(blockIdx.x - m.start[f], NP);
-    if (!load_schedule(fd, ctrl, k, hs.tile, ts, s_rec, s_ab, s_lst, s_opos, s_idx, s_lmask))
+    if (!load_schedule(fd, ctrl, k, hs.tile, CH4, ts, s_rec, s_ab, s_lst, s_opos, s_idx, s_lmask))
         return;
     const Roles R(CH4);
     const uint32_t mlen = (uint32_t)ts.mlen;
@@ -740,13 +752,13 @@ __device__ inline void load_sched1(CFrame *d, const Item1 &it, Sched1 &S)
 // wait analysis would otherwise leave them pending and wait for them, and for every later load,
 // at their next write): threads without an entry to write store into the sink slot past the end
 // of each array.
-__device__ inline void commit_sched1(const Sched1 &S, const Item1 &it, uint32_t n, uint32_t *s_rec,
-                                     float2 *s_ab, uint32_t *s_lstw, uint32_t *s_oposw,
-                                     uint32_t *s_m0, unsigned long long *s_lmask)
+__device__ inline void commit_sched1(const Sched1 &S, const Item1 &it, uint32_t CH4, uint32_t n,
+                                     uint32_t *s_rec, float2 *s_ab, uint32_t *s_lstw,
+                                     uint32_t *s_oposw, uint32_t *s_m0, unsigned long long *s_lmask)
 {
     const uint32_t tid = threadIdx.x;
     s_lmask[min(tid, (uint32_t)NCLS)] = S.lm;
-    s_rec[tid] = S.rec;
+    s_rec[tid] = lds_rec(S.rec, CH4);
     // (a, b) of the merge: at the first level an entry's weight is its position difference
     const uint32_t j = S.rec & 1023u, l = (S.rec >> 10) & 1023u, r = S.rec >> 20;
     const float w0 = (float)(j - l), w1 = (float)(r - j);
@@ -851,7 +863,7 @@ __global__ __launch_bounds__(RAHT_THREADS) __attribute__((amdgpu_waves_per_eu(PE
         __syncthreads();  // the previous item is no longer read from LDS
         // ---- the current item's schedule and rows into LDS, the next item's first rows; on
         // every path, whether or not the item is ok (see commit_sched1)
-        commit_sched1(S, it0, n, s_rec, s_ab, s_lstw, s_oposw, s_m0, s_lmask);
+        commit_sched1(S, it0, CH4, n, s_rec, s_ab, s_lstw, s_oposw, s_m0, s_lmask);
         const uint32_t sink = RT * CH4;
 #pragma unroll
         for (int u = 0; u < NR1; ++u) {
@@ -1040,7 +1052,7 @@ __global__ __launch_bounds__(RAHT_THREADS) __attribute__((amdgpu_waves_per_eu(PE
         __syncthreads();  // the previous item is no longer read from LDS; s_st is written
         // ---- the current item's schedule and coefficient rows into LDS (branch-free, see
         // commit_sched1)
-        commit_sched1(S, it0, d->n, s_rec, s_ab, s_lstw, s_oposw, s_m0, s_lmask);
+        commit_sched1(S, it0, CH4, d->n, s_rec, s_ab, s_lstw, s_oposw, s_m0, s_lmask);
         {
             float st[4] = {1.f, 1.f, 1.f, 1.f};
             if (decode)
@@ -1135,7 +1147,7 @@ __global__ __launch_bounds__(RAHT_THREADS) void k_raht_inv_up(TileMap m, int k)
     const uint32_t C = fd.C, C4 = fd.C4;
     const uint32_t NP = channel_passes(C4, k), CH4 = pass_chunks(C4, k);
     const SliceSplit hs = slice_split(blockIdx.x - m.start[f], NP);
-    if (!load_schedule(fd, ctrl, k, hs.tile, ts, s_rec, s_ab, s_lst, s_opos, s_idx, s_lmask))
+    if (!load_schedule(fd, ctrl, k, hs.tile, CH4, ts, s_rec, s_ab, s_lst, s_opos, s_idx, s_lmask))
         return;
     const Roles R(CH4);
     const uint32_t mlen = (uint32_t)ts.mlen;
