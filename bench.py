@@ -60,8 +60,8 @@ def alg_bytes(stage, n, nv, C):
 KERNEL_SOURCES = ("paper_2606_05650_amd/csrc/k_raht.hip", "paper_2606_05650_amd/csrc/gsc_device.h",
                   "paper_2606_05650_amd/csrc/gsc_internal.h")
 PMC_TRAFFIC = {"workload": "frame1M_J12",
-               "sources_sha256": "5e082999cec9d88b8d739d76d2087f7e7108d3689e2f2680526923db9a97a2ac",
-               "raht_fwd1": 573368800, "raht_inv1": 468547229}
+               "sources_sha256": "69102b20e991a869407f9ef15ca5a1b4deab3bbb2f1d4d20a6ff5222aad108b6",
+               "raht_fwd1": 569680570, "raht_inv1": 468892394}
 KERNEL_NAMES = {"raht_fwd1": "k_raht_fwd1", "raht_inv1": "k_raht_inv1"}
 
 
