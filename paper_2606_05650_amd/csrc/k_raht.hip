@@ -33,9 +33,11 @@ constexpr int CROSS = NCHUNK;  // class of merges that cross chunks
 
 // Size of the entry sequence S_k; a size beyond its allocation (impossible when every tile
 // leaves at most 6J + 2 entries open) is reported and treated as empty.
-__device__ inline uint32_t seq_size(const FrameDesc &fd, Ctrl *ctrl, int k)
+template <class FD>
+__device__ inline uint32_t seq_size(FD &fd, Ctrl *ctrl, int k)
 {
-    const uint32_t nk = k == 1 ? ctrl->n_vox : ctrl->lvl_n[k];
+    // (written by earlier kernels: read through the constant address space)
+    const uint32_t nk = k == 1 ? cp(ctrl)->n_vox : cp(ctrl)->lvl_n[k];
     if (nk > fd.lv[k].cap) {
         set_error(ctrl, GSC_ERR_INTERNAL);
         return 0;
@@ -82,13 +84,13 @@ __global__ __launch_bounds__(PRE_BLOCK) void k_prelude(TileMap m, int k)
     __shared__ LbScratch<PRE_BLOCK / WAVE> s_lb;
 
     const uint32_t f = frame_of(m, blockIdx.x);
-    const FrameDesc &fd = *m.fd[f];
+    const CAS FrameDesc &fd = *cp(m.fd[f]);  // (not written while the kernel runs)
     Ctrl *ctrl = fd.ctrl;
     if (load_error(ctrl)) return;
     if ((uint32_t)k > fd.K) return;
     const uint32_t nk = seq_size(fd, ctrl, k);
     if (!seq_active(nk, k)) return;
-    const RahtLevel &lv = fd.lv[k];
+    auto &lv = fd.lv[k];
     const uint32_t tile = tile_index(m, f);
     const uint32_t s = tile * RT;
     if (s >= nk) return;  // uniform: the tile is past the end
@@ -233,7 +235,7 @@ __global__ __launch_bounds__(PRE_BLOCK) void k_prelude(TileMap m, int k)
     if (is_open) {
         if (rank < (uint32_t)OPEN_CAP) gp(lv.opos)[(size_t)tile * OPEN_CAP + rank] = (uint16_t)j;
         if ((uint32_t)k < fd.K) {
-            const RahtLevel &nx = fd.lv[k + 1];
+            auto &nx = fd.lv[k + 1];
             const uint32_t o = base + rank;
             if (o < nx.cap) {
                 gp(nx.s_idx)[o] = k == 1 ? s + j : gp(lv.s_idx)[s + j];
@@ -274,14 +276,15 @@ struct TileSched {
 // Loads the schedule of a tile of an upper level (k >= 2) into LDS: segment starts, level masks,
 // open positions, voxel indices of the entries, and the records with (a, b) of every local merge.
 // Returns false if the workgroup has nothing to do.
-__device__ inline bool load_schedule(const FrameDesc &fd, Ctrl *ctrl, int k, uint32_t tile,
+template <class FD>
+__device__ inline bool load_schedule(FD &fd, Ctrl *ctrl, int k, uint32_t tile,
                                      uint32_t CH4, TileSched &ts, uint32_t *s_rec, float2 *s_ab,
                                      uint16_t *s_lst, uint16_t *s_opos, uint32_t *s_idx,
                                      unsigned long long *s_lmask)
 {
     const uint32_t nk = seq_size(fd, ctrl, k);
     if (!seq_active(nk, k)) return false;
-    const RahtLevel &lv = fd.lv[k];
+    auto &lv = fd.lv[k];
     const uint32_t s = tile * RT;
     if (s >= nk) return false;
     const uint32_t tid = threadIdx.x, NT = blockDim.x;
@@ -576,7 +579,7 @@ __global__ __launch_bounds__(RAHT_THREADS) void k_raht_fwd_up(TileMap m, int k)
     __shared__ unsigned long long s_lmask[NCLS];
 
     const uint32_t f = frame_of(m, blockIdx.x);
-    const FrameDesc &fd = *m.fd[f];
+    const CAS FrameDesc &fd = *cp(m.fd[f]);  // (not written while the kernel runs)
     Ctrl *ctrl = fd.ctrl;
     if (load_error(ctrl)) return;
     if ((uint32_t)k > fd.K) return;
@@ -1139,7 +1142,7 @@ __global__ __launch_bounds__(RAHT_THREADS) void k_raht_inv_up(TileMap m, int k)
     __shared__ unsigned long long s_lmask[NCLS];
 
     const uint32_t f = frame_of(m, blockIdx.x);
-    const FrameDesc &fd = *m.fd[f];
+    const CAS FrameDesc &fd = *cp(m.fd[f]);  // (not written while the kernel runs)
     Ctrl *ctrl = fd.ctrl;
     if (load_error(ctrl)) return;
     if ((uint32_t)k > fd.K) return;
