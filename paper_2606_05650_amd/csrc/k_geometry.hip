@@ -183,7 +183,7 @@ __global__ __launch_bounds__(64) void k_finish(TileMap m)
 {
     const uint32_t f = blockIdx.x;
     if (f >= m.F) return;
-    const FrameDesc &fd = *m.fd[f];
+    const CAS FrameDesc &fd = *cp(m.fd[f]);  // (not written while the kernel runs)
     Ctrl *ctrl = fd.ctrl;
     const uint32_t t = threadIdx.x;
     const uint32_t J = fd.J, K = fd.K;
@@ -280,7 +280,7 @@ constexpr uint32_t BBOX_CHUNKS = BBOX_THREADS * BBOX_F4;  // per workgroup
 __global__ __launch_bounds__(BBOX_THREADS) void k_bbox(TileMap m)
 {
     const uint32_t f = frame_of(m, blockIdx.x);
-    const FrameDesc &fd = *m.fd[f];
+    const CAS FrameDesc &fd = *cp(m.fd[f]);  // (not written while the kernel runs)
     Ctrl *ctrl = fd.ctrl;
     const uint32_t b = blockIdx.x - m.start[f];
     const uint64_t nf = 3ull * fd.n;      // coordinates
@@ -381,7 +381,7 @@ constexpr int VOX_TILE = VOX_THREADS * VOX_PPT;
 __global__ __launch_bounds__(VOX_THREADS) void k_voxelize(TileMap m)
 {
     const uint32_t f = frame_of(m, blockIdx.x);
-    const FrameDesc &fd = *m.fd[f];
+    const CAS FrameDesc &fd = *cp(m.fd[f]);  // (not written while the kernel runs)
     Ctrl *ctrl = fd.ctrl;
     if (load_error(ctrl)) return;
     const uint32_t b = blockIdx.x - m.start[f];
@@ -489,7 +489,7 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_pass(TileMap m, int pass)
     __shared__ uint32_t s_vals[TILE];
 
     const uint32_t f = frame_of(m, blockIdx.x);
-    const FrameDesc &fd = *m.fd[f];
+    const CAS FrameDesc &fd = *cp(m.fd[f]);  // (not written while the kernel runs)
     Ctrl *ctrl = fd.ctrl;
     if (load_error(ctrl)) return;
     const uint32_t n = fd.n;
@@ -600,7 +600,7 @@ __global__ __launch_bounds__(DEDUP_THREADS) void k_dedup(TileMap m)
     __shared__ uint32_t s_cnt[DEDUP_KPT * NW + 1];
     __shared__ uint32_t s_hist[32];
     const uint32_t f = frame_of(m, blockIdx.x);
-    const FrameDesc &fd = *m.fd[f];
+    const CAS FrameDesc &fd = *cp(m.fd[f]);  // (not written while the kernel runs)
     Ctrl *ctrl = fd.ctrl;
     if (load_error(ctrl)) return;
     const uint32_t n = fd.n, J = fd.J;
@@ -701,7 +701,7 @@ __global__ __launch_bounds__(OCC_THREADS) void k_occupancy(TileMap m)
     __shared__ uint32_t s_tmp[OCC_THREADS / WAVE + 1];
 
     const uint32_t f = frame_of(m, blockIdx.x);
-    const FrameDesc &fd = *m.fd[f];
+    const CAS FrameDesc &fd = *cp(m.fd[f]);  // (not written while the kernel runs)
     Ctrl *ctrl = fd.ctrl;
     if (load_error(ctrl)) return;
     const uint32_t J = fd.J, nv = ctrl->n_vox;
@@ -820,8 +820,8 @@ hipError_t launch_occupancy(const TileMap &m, hipStream_t s)
 
 // Writes leaf v: its code, voxel coordinates and centre min + (v + 1/2) * cell (FP64, rounded
 // once to float).
-__device__ inline void emit_leaf(const FrameDesc &fd, const gsc_header *h, uint32_t v,
-                                 uint64_t code)
+template <class FD>
+__device__ inline void emit_leaf(FD &fd, const gsc_header *h, uint32_t v, uint64_t code)
 {
     gp(fd.leaf)[v] = code;
     if (fd.codes_out) gp(fd.codes_out)[v] = code;
@@ -837,7 +837,8 @@ __device__ inline void emit_leaf(const FrameDesc &fd, const gsc_header *h, uint3
 // Header checks: everything the decoder relies on must be self-consistent and fit the caller's
 // buffers. Performed by one wave, lane l checking level l's size against the next one and the
 // quantizer step of channel l; returns true (in every lane) when the header is usable.
-__device__ inline bool header_ok_wave(const FrameDesc &fd, const CAS gsc_header *h)
+template <class FD>
+__device__ inline bool header_ok_wave(FD &fd, const CAS gsc_header *h)
 {
     const uint32_t lane = lane_id();
     if (fd.in_bytes < GSC_HEADER_BYTES) return false;
@@ -896,7 +897,7 @@ __global__ __launch_bounds__(DEC_THREADS) void k_dec_expand(TileMap m)
     __shared__ uint32_t s_cnt[WAVE + 1];
     __shared__ LbScratch<DEC_THREADS / WAVE> s_lb;
     const uint32_t f = frame_of(m, blockIdx.x);
-    const FrameDesc &fd = *m.fd[f];
+    const CAS FrameDesc &fd = *cp(m.fd[f]);  // (not written while the kernel runs)
     Ctrl *ctrl = fd.ctrl;
     const uint32_t tile = tile_index(m, f), tid = threadIdx.x, w = tid / WAVE, lane = lane_id();
     const gsc_header *hg = reinterpret_cast<const gsc_header *>(fd.in_stream);
@@ -993,7 +994,7 @@ hipError_t launch_dec_expand(const TileMap &m, hipStream_t s)
 __global__ __launch_bounds__(LEAF_THREADS) void k_dec_leaves(TileMap m)
 {
     const uint32_t f = frame_of(m, blockIdx.x);
-    const FrameDesc &fd = *m.fd[f];
+    const CAS FrameDesc &fd = *cp(m.fd[f]);  // (not written while the kernel runs)
     Ctrl *ctrl = fd.ctrl;
     if (__builtin_amdgcn_readfirstlane(load_error(ctrl))) return;
     const gsc_header *hg = reinterpret_cast<const gsc_header *>(fd.in_stream);
