@@ -758,6 +758,29 @@ __global__ __launch_bounds__(OCC_THREADS) void k_occupancy(TileMap m)
         if (tid == 0) s_cnt[d] = total;
     }
     __syncthreads();
+    // the stream geometry, by the last wave beside the look-backs (it depends only on the depth
+    // histogram): |L_d| = hist_D[0] + ... + hist_D[d], level d's bytes start at the header size
+    // plus |L_0| + ... + |L_{d-1}|; s_off[J] is the end of the occupancy bytes
+    __shared__ uint64_t s_off[GSC_MAX_DEPTH + 1];
+    __shared__ int s_fits;
+    if (tid / WAVE == OCC_THREADS / WAVE - 1) {
+        const uint32_t lane = lane_id();
+        const uint32_t hd = lane <= J ? cp(ctrl)->hist_D[lane] : 0u;  // (written by the dedup kernel)
+        const uint64_t size = lane < J ? (uint64_t)wave_incl_scan(hd) : 0ull;
+        uint64_t incl = size;
+#pragma unroll
+        for (int o = 1; o < WAVE; o <<= 1) {
+            const uint64_t t = __shfl_up(incl, o, WAVE);
+            if (lane >= (uint32_t)o) incl += t;
+        }
+        const uint64_t off = GSC_HEADER_BYTES + incl - size;
+        if (lane <= J) s_off[lane] = off;
+        if (lane == J) {
+            const uint64_t total = align_up(off, 256) + (uint64_t)cp(ctrl)->n_vox * fd.C * 4;
+            s_fits = total <= fd.stream_cap;
+            if (!s_fits) set_error(ctrl, GSC_ERR_CAPACITY);
+        }
+    }
     // one wave per depth (wave w takes depths w, w + 16, ...): the look-backs of all depths
     // proceed side by side
     for (uint32_t d = tid / WAVE; d < J; d += OCC_THREADS / WAVE) {
@@ -767,16 +790,6 @@ __global__ __launch_bounds__(OCC_THREADS) void k_occupancy(TileMap m)
         const uint64_t agg = ((uint64_t)cnt << 8) | byte;
         const uint64_t pref = lookback_wave<OpSegOr>(fd.occ_status + d, J, tile, agg, ctrl);
         if (lane_id() == 0) s_pref[d] = pref;
-    }
-    __shared__ uint64_t s_off[GSC_MAX_DEPTH + 1];
-    __shared__ int s_fits;
-    __shared__ StreamGeom s_geom;
-    if (tid == 0) {
-        StreamGeom &g = s_geom;
-        stream_geom(ctrl, J, fd.C, &g);
-        for (uint32_t d = 0; d <= J; ++d) s_off[d] = g.occ_off[d];
-        s_fits = g.total <= fd.stream_cap;
-        if (!s_fits) set_error(ctrl, GSC_ERR_CAPACITY);
     }
     __syncthreads();
     if (!s_fits) return;
