@@ -112,7 +112,11 @@ __global__ __launch_bounds__(PRE_BLOCK) void k_prelude(TileMap m, int k)
     }
     s_rdl[j] = 0;
     if (j == 0) s_lvl_e = e < nk ? (k == 1 ? merge_level(codes[e - 1], codes[e]) : slvl[e]) : LVL_NONE;
-    for (uint32_t x = 1; x < (uint32_t)NLVL; ++x) {
+    // active lists of the levels that can hold a merge: an entry merges at a level of at most 3J
+    // (the tile's first entry of the sequence, LVL_NONE, is in every list and is never a right
+    // sibling)
+    const uint32_t nlvl = min(3u * fd.J + 1u, (uint32_t)NLVL);
+    for (uint32_t x = 1; x < nlvl; ++x) {
         const uint64_t b = __ballot(lvl >= x);
         if (lane == 0) s_mask[x][w] = b;
     }
