@@ -8,7 +8,6 @@
 #include "gsc_internal.h"
 
 namespace gsc {
-uint32_t bbox_blocks(uint32_t n);
 uint32_t voxelize_blocks(uint32_t n);
 uint32_t prelude_blocks(uint32_t tiles);
 }  // namespace gsc

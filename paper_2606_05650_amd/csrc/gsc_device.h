@@ -112,6 +112,19 @@ __device__ inline float wave_max(float v)
     return v;
 }
 
+__device__ inline uint32_t wave_umin(uint32_t v)
+{
+#pragma unroll
+    for (int o = 1; o < WAVE; o <<= 1) v = min(v, (uint32_t)__shfl_xor(v, o, WAVE));
+    return v;
+}
+__device__ inline uint32_t wave_umax(uint32_t v)
+{
+#pragma unroll
+    for (int o = 1; o < WAVE; o <<= 1) v = max(v, (uint32_t)__shfl_xor(v, o, WAVE));
+    return v;
+}
+
 // Exclusive scan over the NT threads of a block. `tmp` holds NT/64 + 1 words of LDS.
 // Returns the exclusive prefix of v; *total receives the block total. Ends with a barrier.
 template <int NT>

@@ -52,17 +52,29 @@ constexpr int NCLS = RT / 64 + 1;       // merge classes: local to one wave chun
 constexpr int SEG_N = NLVL * NCLS + 1;  // per-tile (level, class) segment starts + total
 constexpr int LSTART_N = SEG_N + 1;     // padded to an even count of u16
 
-constexpr uint32_t BBOX_SENTINEL_MIN = 0xFFFFFFFFu;
+// Bounding box: at most BBOX_GRID_MAX workgroups per frame, each leaving its partial minima and
+// maxima (order-preserving uints of the floats) in a slot of BBOX_SLOT words, which the
+// voxelize workgroups combine.
+constexpr int BBOX_THREADS = 256;
+constexpr int BBOX_F4 = 16;             // float4 chunks per thread and batch, loaded at once
+constexpr uint32_t BBOX_CHUNKS = BBOX_THREADS * BBOX_F4;  // float4 chunks per batch
+constexpr uint32_t BBOX_GRID_MAX = 512;
+constexpr uint32_t BBOX_SLOT = 8;       // min x,y,z, max x,y,z, 2 unused
+__host__ __device__ inline uint32_t bbox_blocks(uint32_t n)
+{
+    if (n == 0) return 1u;
+    const uint64_t batches = ((3ull * n + 3) / 4 + BBOX_CHUNKS - 1) / BBOX_CHUNKS;
+    return batches < BBOX_GRID_MAX ? (uint32_t)batches : BBOX_GRID_MAX;
+}
 
 // --------------------------------------------------------------- per-call control block
-// Zero-initialised by the first kernel of every call (except the bbox minima).
+// Zero-initialised by the first kernel of every call.
 struct Ctrl {
     uint32_t error;              // first device error (gsc_status), 0 = ok
     uint32_t n_vox;              // Nv
     uint32_t dec_unused;
     uint32_t n_in;
-    uint32_t bbox_ord[6];        // order-preserving uint of float: min x,y,z, max x,y,z
-    uint32_t reserved[96];
+    uint32_t reserved[102];
     uint32_t hist_D[32];         // voxels whose new-node depth is D, D = 0..J
     uint32_t lvl_n[MAXK + 2];    // sizes of the RAHT entry sequences, index k = 1..MAXK+1
     uint32_t level_sizes[32];    // |L_d|
@@ -145,6 +157,7 @@ struct FrameDesc {
     uint64_t *leaf;
     uint32_t *vh;
     uint32_t *first;         // encode: input row of every voxel's first member (sorted order)
+    uint32_t *bbox_part;     // encode: bounding-box workgroups' partial extrema (BBOX_SLOT each)
     uint32_t *sort_status;   // P x sort tiles x SORT_BINS
     uint64_t *dedup_status;
     uint64_t *occ_status;    // occ tiles x J
@@ -206,7 +219,7 @@ static_assert(sizeof(FrameDesc) <= DESC_BYTES, "descriptor too large");
 struct Layout {
     size_t total;
     size_t zero_off, zero_bytes;
-    size_t keys_a, keys_b, vals_a, vals_b, leaf, vh, first;
+    size_t keys_a, keys_b, vals_a, vals_b, leaf, vh, first, bbox_part;
     size_t sort_status, dedup_status, occ_status, dec_status, dec_par, dec_cbit;
     uint32_t dec_tiles;      // decoder: tiles of DEC_TILE occupancy bytes (all levels together)
     uint64_t dec_nodes;      // decoder: worst-case nodes of levels 1..J
@@ -289,6 +302,7 @@ __host__ __device__ inline bool make_layout(int64_t n, int J, int C, Layout *L)
     L->dec_par = off; off = align_up(off + nodes * 4, 256);
     L->dec_cbit = off; off = align_up(off + nodes, 256);
     L->first = off; off = align_up(off + N * 4, 256);
+    L->bbox_part = off; off = align_up(off + (size_t)BBOX_GRID_MAX * BBOX_SLOT * 4, 256);
     for (uint32_t k = 1; k <= K; ++k) {
         const uint32_t t = L->tiles[k];
         L->s_idx[k] = off; off = align_up(off + (size_t)L->cap[k] * 4, 256);
@@ -308,7 +322,7 @@ __host__ __device__ inline bool make_layout(int64_t n, int J, int C, Layout *L)
 
 // Launch helpers (defined next to their kernels). Each returns the launch status.
 hipError_t launch_setup(const SetupArgs &a, uint32_t zero_blocks, hipStream_t s);
-hipError_t launch_bbox(const TileMap &m, hipStream_t s);
+hipError_t launch_bbox(const TileMap &m, hipStream_t s);  // grid: bbox_blocks(n) per frame
 hipError_t launch_voxelize(const TileMap &m, hipStream_t s);
 hipError_t launch_sort_pass(const TileMap &m, int pass, int variant, hipStream_t s);
 hipError_t launch_dedup(const TileMap &m, hipStream_t s);

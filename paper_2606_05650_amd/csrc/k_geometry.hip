@@ -51,7 +51,6 @@ __global__ __launch_bounds__(256) void k_setup(SetupArgs a)
         if (a.keep) {
             if (!s_prev_ok) set_error(ctrl, GSC_ERR_INVALID_ARG);
         } else {
-            for (int a3 = 0; a3 < 3; ++a3) ctrl->bbox_ord[a3] = BBOX_SENTINEL_MIN;
             ctrl->n_in = fa.n;
             if (a.mode == MODE_FWD_F32 || a.mode == MODE_ADJ_F32) ctrl->n_vox = fa.n;
         }
@@ -136,6 +135,7 @@ __global__ __launch_bounds__(256) void k_setup(SetupArgs a)
         fd->leaf = reinterpret_cast<uint64_t *>(fa.ws + L.leaf);
         fd->vh = reinterpret_cast<uint32_t *>(fa.ws + L.vh);
         fd->first = reinterpret_cast<uint32_t *>(fa.ws + L.first);
+        fd->bbox_part = reinterpret_cast<uint32_t *>(fa.ws + L.bbox_part);
         fd->sort_status = reinterpret_cast<uint32_t *>(fa.ws + L.sort_status);
         fd->dedup_status = reinterpret_cast<uint64_t *>(fa.ws + L.dedup_status);
         fd->occ_status = reinterpret_cast<uint64_t *>(fa.ws + L.occ_status);
@@ -270,55 +270,62 @@ __device__ inline float ord2f(uint32_t o)
     return __uint_as_float(u);
 }
 
-constexpr int BBOX_THREADS = 256;
-constexpr int BBOX_F4 = 16;  // float4 chunks per thread, all loaded before any is used
-constexpr uint32_t BBOX_CHUNKS = BBOX_THREADS * BBOX_F4;  // per workgroup
-
 // The positions are read as one flat array of 3n floats in float4 chunks (chunk q holds the
-// coordinates 4q .. 4q+3, whose axes are (q + i) mod 3 since 4 = 1 mod 3); each thread issues
-// all of its loads at once, so a workgroup costs one load latency.
+// coordinates 4q .. 4q+3, whose axes are (q + i) mod 3 since 4 = 1 mod 3), in batches of
+// BBOX_CHUNKS chunks: workgroup b of G takes batches b, b + G, ...; each thread issues all of a
+// batch's loads at once. A workgroup leaves its extrema in its own slot: no atomics, whose
+// same-line updates serialize at the memory side.
 __global__ __launch_bounds__(BBOX_THREADS) void k_bbox(TileMap m)
 {
     const uint32_t f = frame_of(m, blockIdx.x);
     const CAS FrameDesc &fd = *cp(m.fd[f]);  // (not written while the kernel runs)
     Ctrl *ctrl = fd.ctrl;
     const uint32_t b = blockIdx.x - m.start[f];
+    const uint32_t G = m.start[f + 1] - m.start[f];  // = bbox_blocks(n)
     const uint64_t nf = 3ull * fd.n;      // coordinates
     const uint64_t nq = nf / 4;            // whole float4 chunks
+    const uint64_t nbatch = (nq + BBOX_CHUNKS - 1) / BBOX_CHUNKS;
     const GAS float *pos = gp(fd.pos);
     const bool vec = ((uintptr_t)fd.pos & 15u) == 0;
     float mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
     bool bad = false;
-    const uint64_t q0 = (uint64_t)b * BBOX_CHUNKS + threadIdx.x;
-    float4 v[BBOX_F4];
+    for (uint64_t c = b; c < nbatch; c += G) {
+        const uint64_t q0 = c * BBOX_CHUNKS + threadIdx.x;
+        // the chunk's first axis, (q0 + r * BBOX_THREADS) mod 3 = (q0 mod 3 + r) mod 3
+        const uint32_t a00 = (uint32_t)(q0 % 3u);
+        float4 v[BBOX_F4];
+        // the whole batch under one branch each: a per-load condition would wait for each load
+        // where its branch joins (clamped indices: every load in bounds, nq >= 1 here)
+        if (vec) {
 #pragma unroll
-    for (int r = 0; r < BBOX_F4; ++r) {
-        const uint64_t q = q0 + (uint64_t)r * BBOX_THREADS;
-        const uint64_t qc = q < nq ? q : (nq ? nq - 1 : 0);  // clamped: every load in bounds
-        if (nq == 0) {
-            v[r] = make_float4(0.f, 0.f, 0.f, 0.f);
-        } else if (vec) {
-            v[r] = gload4(pos + 4 * qc);
+            for (int r = 0; r < BBOX_F4; ++r) {
+                const uint64_t q = q0 + (uint64_t)r * BBOX_THREADS;
+                v[r] = gload4(pos + 4 * (q < nq ? q : nq - 1));
+            }
         } else {
-            v[r] = make_float4(pos[4 * qc], pos[4 * qc + 1], pos[4 * qc + 2], pos[4 * qc + 3]);
+#pragma unroll
+            for (int r = 0; r < BBOX_F4; ++r) {
+                const uint64_t q = q0 + (uint64_t)r * BBOX_THREADS;
+                const GAS float *e = pos + 4 * (q < nq ? q : nq - 1);
+                v[r] = make_float4(e[0], e[1], e[2], e[3]);
+            }
         }
-    }
-    // axes by selects on compile-time indices: a per-element axis index into mn/mx would move
-    // them to memory
+        // axes by selects on compile-time indices: a per-element axis index into mn/mx would
+        // move them to memory
 #pragma unroll
-    for (int r = 0; r < BBOX_F4; ++r) {
-        const uint64_t q = q0 + (uint64_t)r * BBOX_THREADS;
-        const bool ok = q < nq;
-        const uint32_t a0 = (uint32_t)(q % 3u);
-        const float e[4] = {v[r].x, v[r].y, v[r].z, v[r].w};
+        for (int r = 0; r < BBOX_F4; ++r) {
+            const bool ok = q0 + (uint64_t)r * BBOX_THREADS < nq;
+            const uint32_t a0 = (a00 + (uint32_t)r) % 3u;
+            const float e[4] = {v[r].x, v[r].y, v[r].z, v[r].w};
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            bad |= ok && !isfinite(e[i]);
+            for (int i = 0; i < 4; ++i) {
+                bad |= ok && !isfinite(e[i]);
 #pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                const bool mine = ok && (a0 + (uint32_t)i) % 3u == (uint32_t)a;
-                mn[a] = fminf(mn[a], mine ? e[i] : INFINITY);
-                mx[a] = fmaxf(mx[a], mine ? e[i] : -INFINITY);
+                for (int a = 0; a < 3; ++a) {
+                    const bool mine = ok && (a0 + (uint32_t)i) % 3u == (uint32_t)a;
+                    mn[a] = fminf(mn[a], mine ? e[i] : INFINITY);
+                    mx[a] = fmaxf(mx[a], mine ? e[i] : -INFINITY);
+                }
             }
         }
     }
@@ -335,30 +342,25 @@ __global__ __launch_bounds__(BBOX_THREADS) void k_bbox(TileMap m)
         }
     }
     if (__ballot(bad) && lane_id() == 0) set_error(ctrl, GSC_ERR_INVALID_ARG);
-    // wave reductions (shuffles), then one value per wave in LDS: no contended LDS atomics
+    // order-preserving uints (so that -0 < +0 as in an ordered comparison), reduced per wave
+    // with shuffles, then across the waves in LDS
     constexpr int NW = BBOX_THREADS / WAVE;
-    __shared__ float s_mn[NW][3], s_mx[NW][3];
+    __shared__ uint32_t s_o[NW][6];
     const uint32_t w = threadIdx.x / WAVE;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        const float lo = wave_min(mn[a]), hi = wave_max(mx[a]);
+        const uint32_t lo = wave_umin(f2ord(mn[a])), hi = wave_umax(f2ord(mx[a]));
         if (lane_id() == 0) {
-            s_mn[w][a] = lo;
-            s_mx[w][a] = hi;
+            s_o[w][a] = lo;
+            s_o[w][3 + a] = hi;
         }
     }
     __syncthreads();
-    if (threadIdx.x < 3) {
-        const uint32_t a = threadIdx.x;
-        float lo = INFINITY, hi = -INFINITY;
-        for (int ww = 0; ww < NW; ++ww) {
-            lo = fminf(lo, s_mn[ww][a]);
-            hi = fmaxf(hi, s_mx[ww][a]);
-        }
-        if (lo <= hi) {  // the workgroup saw a coordinate of axis a
-            atomicMin(&ctrl->bbox_ord[a], f2ord(lo));
-            atomicMax(&ctrl->bbox_ord[3 + a], f2ord(hi));
-        }
+    if (threadIdx.x < 6) {
+        const uint32_t j = threadIdx.x;
+        uint32_t o = s_o[0][j];
+        for (int ww = 1; ww < NW; ++ww) o = j < 3 ? min(o, s_o[ww][j]) : max(o, s_o[ww][j]);
+        gp(fd.bbox_part)[(size_t)b * BBOX_SLOT + j] = o;
     }
 }
 
@@ -367,7 +369,6 @@ hipError_t launch_bbox(const TileMap &m, hipStream_t s)
     hipLaunchKernelGGL(k_bbox, dim3(m.start[m.F]), dim3(BBOX_THREADS), 0, s, m);
     return hipGetLastError();
 }
-uint32_t bbox_blocks(uint32_t n) { return n ? (uint32_t)ceil_div(ceil_div(3ull * n, 4ull), (uint64_t)BBOX_CHUNKS) : 1u; }
 
 // ===================================================== voxelize + Morton + digit histograms
 // Voxelization (Sec. 2.1, Sec. 2.2 step (a)): v = min(2^J - 1, floor((p - min) / cell)) per axis
@@ -388,6 +389,55 @@ __global__ __launch_bounds__(VOX_THREADS) void k_voxelize(TileMap m)
     const uint32_t n = fd.n, J = fd.J, P = fd.P;
     __shared__ uint32_t s_hist[SORT_MAX_PASSES * SORT_BINS];
     for (uint32_t i = threadIdx.x; i < P * SORT_BINS; i += VOX_THREADS) s_hist[i] = 0;
+    {   // this workgroup's share of the sort's look-back status words (they lie outside the
+        // region the setup kernel zeroes, since only an encode sorts)
+        const uint32_t nb = n ? (n + VOX_TILE - 1) / VOX_TILE : 1u;
+        const uint64_t nq = (uint64_t)P * fd.sort_tiles * SORT_BINS / 4;
+        uint4 *z = reinterpret_cast<uint4 *>(fd.sort_status);
+        for (uint64_t i = (uint64_t)b * VOX_THREADS + threadIdx.x; i < nq; i += (uint64_t)nb * VOX_THREADS)
+            z[i] = make_uint4(0, 0, 0, 0);
+    }
+    const uint32_t p0 = b * VOX_TILE;
+    // Every load is issued before any is used, none under a condition (a loaded value used
+    // after a branch joins is waited for there): the thread's point coordinates (clamped
+    // indices; with no points, an in-bounds stand-in that is never used), then the bounding-box
+    // workgroups' partial extrema (clamped slots; read but unused when the caller gives the
+    // cube).
+    float c[VOX_PPT][3];
+    {
+        const GAS float *src = n ? gp(fd.pos) : reinterpret_cast<const GAS float *>(gp(fd.bbox_part));
+        const uint32_t ilast = n ? n - 1 : 0u;
+#pragma unroll
+        for (int r = 0; r < VOX_PPT; ++r) {
+            const uint32_t i = min(p0 + r * VOX_THREADS + threadIdx.x, ilast);
+#pragma unroll
+            for (int a = 0; a < 3; ++a) c[r][a] = src[(size_t)i * 3 + a];
+        }
+    }
+    constexpr int NW = VOX_THREADS / WAVE;
+    static_assert(BBOX_GRID_MAX <= 2 * VOX_THREADS, "two bounding-box slots per thread");
+    __shared__ uint32_t s_bb[NW][6];
+    {
+        const uint32_t G = bbox_blocks(n);
+        const GAS uint32_t *part = gp(fd.bbox_part);
+        uint32_t o[6];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const uint32_t slot = min(threadIdx.x + h * VOX_THREADS, G - 1);
+            const int4 x = gload4i(reinterpret_cast<const GAS int32_t *>(part + (size_t)slot * BBOX_SLOT));
+            const uint32_t y0 = part[(size_t)slot * BBOX_SLOT + 4], y1 = part[(size_t)slot * BBOX_SLOT + 5];
+            const uint32_t v[6] = {(uint32_t)x.x, (uint32_t)x.y, (uint32_t)x.z, (uint32_t)x.w, y0, y1};
+#pragma unroll
+            for (int j = 0; j < 6; ++j) o[j] = h == 0 ? v[j] : (j < 3 ? min(o[j], v[j]) : max(o[j], v[j]));
+        }
+        const uint32_t w = threadIdx.x / WAVE;
+#pragma unroll
+        for (int j = 0; j < 6; ++j) {
+            const uint32_t r = j < 3 ? wave_umin(o[j]) : wave_umax(o[j]);
+            if (lane_id() == 0) s_bb[w][j] = r;
+        }
+    }
+    __syncthreads();
     double lo[3], cell;
     if (fd.bbox_mode == 0) {
         double ext = 0.0;
@@ -396,8 +446,13 @@ __global__ __launch_bounds__(VOX_THREADS) void k_voxelize(TileMap m)
                 lo[a] = 0.0;
                 continue;
             }
-            lo[a] = (double)ord2f(ctrl->bbox_ord[a]);
-            const double hi = (double)ord2f(ctrl->bbox_ord[3 + a]);
+            uint32_t omin = s_bb[0][a], omax = s_bb[0][3 + a];
+            for (int ww = 1; ww < NW; ++ww) {
+                omin = min(omin, s_bb[ww][a]);
+                omax = max(omax, s_bb[ww][3 + a]);
+            }
+            lo[a] = (double)ord2f(omin);
+            const double hi = (double)ord2f(omax);
             ext = fmax(ext, hi - lo[a]);
         }
         cell = ext > 0.0 ? ldexp(ext, -(int)J) : 1.0;
@@ -409,25 +464,7 @@ __global__ __launch_bounds__(VOX_THREADS) void k_voxelize(TileMap m)
         for (int a = 0; a < 3; ++a) ctrl->bbox_min[a] = lo[a];
         ctrl->cell = cell;
     }
-    {   // this workgroup's share of the sort's look-back status words (they lie outside the
-        // region the setup kernel zeroes, since only an encode sorts)
-        const uint32_t nb = n ? (n + VOX_TILE - 1) / VOX_TILE : 1u;
-        const uint64_t nq = (uint64_t)P * fd.sort_tiles * SORT_BINS / 4;
-        uint4 *z = reinterpret_cast<uint4 *>(fd.sort_status);
-        for (uint64_t i = (uint64_t)b * VOX_THREADS + threadIdx.x; i < nq; i += (uint64_t)nb * VOX_THREADS)
-            z[i] = make_uint4(0, 0, 0, 0);
-    }
-    __syncthreads();
     const double top = (double)((1u << J) - 1u);
-    const uint32_t p0 = b * VOX_TILE;
-    // every coordinate of the thread's points is loaded before any is used (clamped indices)
-    float c[VOX_PPT][3];
-#pragma unroll
-    for (int r = 0; r < VOX_PPT; ++r) {
-        const uint32_t i = min(p0 + r * VOX_THREADS + threadIdx.x, n ? n - 1 : 0u);
-#pragma unroll
-        for (int a = 0; a < 3; ++a) c[r][a] = n ? gp(fd.pos)[(size_t)i * 3 + a] : 0.0f;
-    }
 #pragma unroll
     for (int r = 0; r < VOX_PPT; ++r) {
         const uint32_t i = p0 + r * VOX_THREADS + threadIdx.x;
