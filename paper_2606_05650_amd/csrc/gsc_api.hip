@@ -166,16 +166,25 @@ int max_K(const Frame *fr, int F)
     return K;
 }
 
+// Worst-case tiles of level 2 over the frames (the largest upper level).
+uint32_t upper_tiles(const Frame *fr, int F)
+{
+    uint32_t t = 0;
+    for (int f = 0; f < F; ++f) t += fr[f].L.K >= 2 ? fr[f].L.tiles[2] : 0u;
+    return t;
+}
+
 gsc_status run_prelude(const Frame *fr, int F, hipStream_t s)
 {
     StageScope sc(GSC_STAGE_PRELUDE, s);
     const int K = max_K(fr, F);
-    for (int k = 1; k <= K; ++k) {
-        TileMap m = make_map(fr, F, [k](const Frame &x) {
-            return (int)x.L.K >= k ? prelude_blocks(x.L.tiles[k]) : 0u;
-        });
-        if (m.start[F] == 0) continue;
-        GSC_LAUNCH(launch_prelude(m, k, s));
+    {
+        TileMap m = make_map(fr, F, [](const Frame &x) { return x.L.K >= 1 ? prelude_blocks(x.L.tiles[1]) : 0u; });
+        if (m.start[F] > 0) GSC_LAUNCH(launch_prelude(m, 1, s));
+    }
+    if (K >= 2) {
+        TileMap m = make_map(fr, F, [](const Frame &) { return 1u; });
+        GSC_LAUNCH(launch_prelude_up(m, K, upper_tiles(fr, F), s));
     }
     return GSC_OK;
 }
@@ -183,25 +192,17 @@ gsc_status run_prelude(const Frame *fr, int F, hipStream_t s)
 gsc_status run_forward(const Frame *fr, int F, const RahtCfg &cfg, hipStream_t s)
 {
     const int K = max_K(fr, F);
-    for (int k = 1; k <= K; ++k) {
-        TileMap m = make_map(fr, F, [k, &cfg](const Frame &x) { return (int)x.L.K >= k ? raht_blocks(x.L.tiles[k], k, cfg.C4) : 0u; });
-        if (m.start[F] == 0) continue;
-        if (k == 1) {
+    {
+        TileMap m = make_map(fr, F, [&cfg](const Frame &x) { return x.L.K >= 1 ? raht_blocks(x.L.tiles[1], 1, cfg.C4) : 0u; });
+        if (m.start[F] > 0) {
             StageScope sc(GSC_STAGE_RAHT_FWD1, s);
-            GSC_LAUNCH(launch_raht_fwd(m, k, cfg, s));
-        } else {
-            if (k == 2 && g_hooks[GSC_STAGE_RAHT_FWD_TOP].n_pairs > 0) {
-                // one scope over all upper levels
-                StageScope sc(GSC_STAGE_RAHT_FWD_TOP, s);
-                for (int kk = 2; kk <= K; ++kk) {
-                    TileMap mm = make_map(fr, F, [kk, &cfg](const Frame &x) { return (int)x.L.K >= kk ? raht_blocks(x.L.tiles[kk], kk, cfg.C4) : 0u; });
-                    if (mm.start[F] == 0) continue;
-                    GSC_LAUNCH(launch_raht_fwd(mm, kk, cfg, s));
-                }
-                break;
-            }
-            GSC_LAUNCH(launch_raht_fwd(m, k, cfg, s));
+            GSC_LAUNCH(launch_raht_fwd(m, 1, cfg, s));
         }
+    }
+    if (K >= 2) {
+        StageScope sc(GSC_STAGE_RAHT_FWD_TOP, s);
+        TileMap m = make_map(fr, F, [](const Frame &) { return 1u; });
+        GSC_LAUNCH(launch_raht_fwd_upper(m, K, upper_tiles(fr, F) * channel_slices_upper(cfg.C4), cfg, s));
     }
     return GSC_OK;
 }
@@ -209,13 +210,10 @@ gsc_status run_forward(const Frame *fr, int F, const RahtCfg &cfg, hipStream_t s
 gsc_status run_inverse(const Frame *fr, int F, const RahtCfg &cfg, hipStream_t s)
 {
     const int K = max_K(fr, F);
-    {
+    if (K >= 2) {
         StageScope sc(GSC_STAGE_RAHT_INV_TOP, s);
-        for (int k = K; k >= 2; --k) {
-            TileMap m = make_map(fr, F, [k, &cfg](const Frame &x) { return (int)x.L.K >= k ? raht_blocks(x.L.tiles[k], k, cfg.C4) : 0u; });
-            if (m.start[F] == 0) continue;
-            GSC_LAUNCH(launch_raht_inv(m, k, cfg, s));
-        }
+        TileMap m = make_map(fr, F, [](const Frame &) { return 1u; });
+        GSC_LAUNCH(launch_raht_inv_upper(m, K, upper_tiles(fr, F) * channel_slices_upper(cfg.C4), cfg, s));
     }
     TileMap m = make_map(fr, F, [&cfg](const Frame &x) { return raht_blocks(x.L.tiles[1], 1, cfg.C4); });
     if (m.start[F] > 0) {

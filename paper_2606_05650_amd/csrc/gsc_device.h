@@ -185,6 +185,45 @@ __device__ inline uint32_t group_excl_scan(uint32_t v, uint32_t *tmp, uint32_t *
 // workgroup); one dependent round costs about half a microsecond.
 constexpr uint32_t SPIN_LIMIT = 1u << 22;
 
+// Level ordering inside a persistent launch whose workgroups are all resident. A workgroup that
+// has written a level's outputs makes them visible device-wide (release: every wave writes its
+// stores back past its XCD's L2) and then stores the phase number in its own flag word; a
+// workgroup that reads the level waits until the flags of all np producers show the phase,
+// then acquires (the XCD's L2 and the CU's L1 are invalidated, so later loads see the
+// producers' data). One wave fences for the workgroup, after a workgroup barrier: a write-back
+// of the L2 per wave was measured to cost more than the levels' work. One flag per workgroup: the producers never contend on a counter, and the
+// consumer polls them all at once. A spin limit turns a stall into GSC_ERR_INTERNAL.
+__device__ inline void level_publish(uint32_t *flags, uint32_t phase)
+{
+    __syncthreads();  // (workgroup scope: the other waves' stores are ordered before wave 0's fence)
+    if (threadIdx.x == 0) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __hip_atomic_store(&flags[blockIdx.x], phase, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+// Producers b0, b0 + 1, ... (np of them, modulo G).
+__device__ inline void level_wait_range(const uint32_t *flags, uint32_t b0, uint32_t np, uint32_t G, uint32_t phase, Ctrl *ctrl)
+{
+    for (uint32_t t = threadIdx.x; t < np; t += blockDim.x) {
+        const uint32_t b = b0 + t < G ? b0 + t : b0 + t - G;
+        uint32_t spins = 0;
+        while (__hip_atomic_load(&flags[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < phase) {
+            if (++spins > SPIN_LIMIT) {
+                set_error(ctrl, GSC_ERR_INTERNAL);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // (caches shared by the workgroup)
+    __syncthreads();
+}
+__device__ inline void level_wait(const uint32_t *flags, uint32_t np, uint32_t phase, Ctrl *ctrl)
+{
+    level_wait_range(flags, 0, np, np, phase, ctrl);
+}
+
 // 64-bit status word: [63:62] flag (0 none, 1 aggregate, 2 inclusive), [61:0] value.
 constexpr uint64_t LB_AGG = 1ull << 62;
 constexpr uint64_t LB_INC = 2ull << 62;

@@ -52,6 +52,12 @@ constexpr int NCLS = RT / 64 + 1;       // merge classes: local to one wave chun
 constexpr int SEG_N = NLVL * NCLS + 1;  // per-tile (level, class) segment starts + total
 constexpr int LSTART_N = SEG_N + 1;     // padded to an even count of u16
 
+// Upper tiling levels (k >= 2) run as one persistent launch per phase (schedules, forward,
+// inverse) of at most UP_GRID_MAX workgroups, which order the levels through per-workgroup
+// phase flags.
+constexpr uint32_t UP_GRID_MAX = 1024;
+constexpr uint32_t PHASE_PRELUDE = 0, PHASE_FORWARD = 32, PHASE_INVERSE = 64;  // flag bases
+
 // Bounding box: at most BBOX_GRID_MAX workgroups per frame, each leaving its partial minima and
 // maxima (order-preserving uints of the floats) in a slot of BBOX_SLOT words, which the
 // voxelize workgroups combine.
@@ -158,6 +164,7 @@ struct FrameDesc {
     uint32_t *vh;
     uint32_t *first;         // encode: input row of every voxel's first member (sorted order)
     uint32_t *bbox_part;     // encode: bounding-box workgroups' partial extrema (BBOX_SLOT each)
+    uint32_t *lvl_flags;     // upper-level launches: the phase each workgroup has completed
     uint32_t *sort_status;   // P x sort tiles x SORT_BINS
     uint64_t *dedup_status;
     uint64_t *occ_status;    // occ tiles x J
@@ -219,7 +226,7 @@ static_assert(sizeof(FrameDesc) <= DESC_BYTES, "descriptor too large");
 struct Layout {
     size_t total;
     size_t zero_off, zero_bytes;
-    size_t keys_a, keys_b, vals_a, vals_b, leaf, vh, first, bbox_part;
+    size_t keys_a, keys_b, vals_a, vals_b, leaf, vh, first, bbox_part, lvl_flags;
     size_t sort_status, dedup_status, occ_status, dec_status, dec_par, dec_cbit;
     uint32_t dec_tiles;      // decoder: tiles of DEC_TILE occupancy bytes (all levels together)
     uint64_t dec_nodes;      // decoder: worst-case nodes of levels 1..J
@@ -303,6 +310,7 @@ __host__ __device__ inline bool make_layout(int64_t n, int J, int C, Layout *L)
     L->dec_cbit = off; off = align_up(off + nodes, 256);
     L->first = off; off = align_up(off + N * 4, 256);
     L->bbox_part = off; off = align_up(off + (size_t)BBOX_GRID_MAX * BBOX_SLOT * 4, 256);
+    L->lvl_flags = off; off = align_up(off + (size_t)UP_GRID_MAX * 4, 256);
     for (uint32_t k = 1; k <= K; ++k) {
         const uint32_t t = L->tiles[k];
         L->s_idx[k] = off; off = align_up(off + (size_t)L->cap[k] * 4, 256);
@@ -337,8 +345,14 @@ struct RahtCfg {
     bool vec, pow2;
 };
 uint32_t raht_blocks(uint32_t tiles, int k, int C4);  // workgroups of a transform launch
-hipError_t launch_raht_fwd(const TileMap &m, int k, const RahtCfg &cfg, hipStream_t s);
-hipError_t launch_raht_inv(const TileMap &m, int k, const RahtCfg &cfg, hipStream_t s);
+hipError_t launch_raht_fwd(const TileMap &m, int k, const RahtCfg &cfg, hipStream_t s);  // k == 1
+hipError_t launch_raht_inv(const TileMap &m, int k, const RahtCfg &cfg, hipStream_t s);  // k == 1
+// Upper levels 2 .. kmax in one persistent launch each (only m.F and m.fd are used);
+// items_max: the worst-case items of the largest level over the launch's frames.
+hipError_t launch_prelude_up(const TileMap &m, int kmax, uint32_t items_max, hipStream_t s);
+hipError_t launch_raht_fwd_upper(const TileMap &m, int kmax, uint32_t items_max, const RahtCfg &cfg, hipStream_t s);
+hipError_t launch_raht_inv_upper(const TileMap &m, int kmax, uint32_t items_max, const RahtCfg &cfg, hipStream_t s);
+uint32_t channel_slices_upper(int C4);  // channel slices of an upper-level tile
 hipError_t launch_finish(const TileMap &m, hipStream_t s);
 
 }  // namespace gsc

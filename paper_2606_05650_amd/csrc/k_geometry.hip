@@ -31,6 +31,10 @@ __global__ __launch_bounds__(256) void k_setup(SetupArgs a)
             z[i] = make_uint4(0, 0, 0, 0);
     }
     if (blockIdx.x != 0) return;
+    {   // the upper-level phase flags start at zero in every call, also one that keeps the state
+        uint32_t *fl = reinterpret_cast<uint32_t *>(fa.ws + s_L.lvl_flags);
+        for (uint32_t i = threadIdx.x; i < UP_GRID_MAX; i += blockDim.x) fl[i] = 0;
+    }
     Ctrl *ctrl = reinterpret_cast<Ctrl *>(fa.ws);
     FrameDesc *fd = reinterpret_cast<FrameDesc *>(fa.ws + DESC_OFF);
     __shared__ uint32_t s_prev_ok;
@@ -136,6 +140,7 @@ __global__ __launch_bounds__(256) void k_setup(SetupArgs a)
         fd->vh = reinterpret_cast<uint32_t *>(fa.ws + L.vh);
         fd->first = reinterpret_cast<uint32_t *>(fa.ws + L.first);
         fd->bbox_part = reinterpret_cast<uint32_t *>(fa.ws + L.bbox_part);
+        fd->lvl_flags = reinterpret_cast<uint32_t *>(fa.ws + L.lvl_flags);
         fd->sort_status = reinterpret_cast<uint32_t *>(fa.ws + L.sort_status);
         fd->dedup_status = reinterpret_cast<uint64_t *>(fa.ws + L.dedup_status);
         fd->occ_status = reinterpret_cast<uint64_t *>(fa.ws + L.occ_status);

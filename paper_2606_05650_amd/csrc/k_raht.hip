@@ -33,11 +33,15 @@ constexpr int CROSS = NCHUNK;  // class of merges that cross chunks
 
 // Size of the entry sequence S_k; a size beyond its allocation (impossible when every tile
 // leaves at most 6J + 2 entries open) is reported and treated as empty.
-template <class FD>
+// LIVE: the size may have been written during the running launch (a persistent upper-level
+// launch), so it is read with a device-coherent load; otherwise it was written by an earlier
+// kernel and is read through the constant address space.
+template <bool LIVE = false, class FD>
 __device__ inline uint32_t seq_size(FD &fd, Ctrl *ctrl, int k)
 {
-    // (written by earlier kernels: read through the constant address space)
-    const uint32_t nk = k == 1 ? cp(ctrl)->n_vox : cp(ctrl)->lvl_n[k];
+    const uint32_t nk = k == 1 ? cp(ctrl)->n_vox
+                       : LIVE ? __builtin_amdgcn_readfirstlane(__hip_atomic_load(&ctrl->lvl_n[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+                              : cp(ctrl)->lvl_n[k];
     if (nk > fd.lv[k].cap) {
         set_error(ctrl, GSC_ERR_INTERNAL);
         return 0;
@@ -73,7 +77,8 @@ __device__ inline uint64_t uniform64(uint64_t v)
 constexpr int PRE_TILES = 1;  // tiles per workgroup
 constexpr int PRE_BLOCK = PRE_TILES * PRE_THREADS;
 
-__global__ __launch_bounds__(PRE_BLOCK) void k_prelude(TileMap m, int k)
+template <bool LIVE>
+__device__ inline void prelude_tile(const TileMap &m, uint32_t f, int k, uint32_t tile)
 {
     static_assert(PRE_TILES == 1, "one tile per workgroup");
     __shared__ uint32_t s_lvl_e;
@@ -83,15 +88,13 @@ __global__ __launch_bounds__(PRE_BLOCK) void k_prelude(TileMap m, int k)
     __shared__ uint8_t s_rdl[RT];  // round of the chunk merge that last wrote an entry
     __shared__ LbScratch<PRE_BLOCK / WAVE> s_lb;
 
-    const uint32_t f = frame_of(m, blockIdx.x);
     const CAS FrameDesc &fd = *cp(m.fd[f]);  // (not written while the kernel runs)
     Ctrl *ctrl = fd.ctrl;
     if (load_error(ctrl)) return;
     if ((uint32_t)k > fd.K) return;
-    const uint32_t nk = seq_size(fd, ctrl, k);
+    const uint32_t nk = seq_size<LIVE>(fd, ctrl, k);
     if (!seq_active(nk, k)) return;
     auto &lv = fd.lv[k];
-    const uint32_t tile = tile_index(m, f);
     const uint32_t s = tile * RT;
     if (s >= nk) return;  // uniform: the tile is past the end
     const uint32_t e = min(nk, s + RT);
@@ -255,11 +258,82 @@ __global__ __launch_bounds__(PRE_BLOCK) void k_prelude(TileMap m, int k)
     }
 }
 
+// One workgroup per tile of the first level.
+__global__ __launch_bounds__(PRE_BLOCK) void k_prelude(TileMap m, int k)
+{
+    const uint32_t f = frame_of(m, blockIdx.x);
+    prelude_tile<false>(m, f, k, tile_index(m, f));
+}
+
 hipError_t launch_prelude(const TileMap &m, int k, hipStream_t s)
 {
     hipLaunchKernelGGL(k_prelude, dim3(m.start[m.F]), dim3(PRE_BLOCK), 0, s, m, k);
     return hipGetLastError();
 }
+
+// ------------------------------------------------- upper levels: one persistent launch each
+// The upper sequences are small and their true sizes are known only on the device (the bound of
+// 6J + 2 open entries per tile is far above what real frames leave), so a launch per level and
+// per worst-case tile would mostly start idle workgroups. Instead one launch of G resident
+// workgroups visits the levels in order; at each level workgroup b takes the level's items
+// b, b + G, ... (items over all frames of the launch, frame by frame), and the levels are
+// ordered with per-workgroup phase flags. Item counts never grow from one level to the next
+// (S_{k+1} is a subset of S_k's entries), so workgroups beyond a level's count leave.
+
+// Items of level k over the frames of the launch (each frame: its tiles of S_k times np), with
+// the frames' first items in s_fs[0..F]; uniform. lvl_n is read with device-coherent loads: a
+// schedule launch writes the next level's size while it runs.
+__device__ inline uint32_t level_items(const TileMap &m, int k, uint32_t np, uint32_t *s_fs)
+{
+    if (threadIdx.x < WAVE) {
+        uint32_t c = 0;
+        if (threadIdx.x < m.F) {
+            const CAS FrameDesc &fd = *cp(m.fd[threadIdx.x]);
+            if ((uint32_t)k <= fd.K) {
+                const uint32_t nk = __hip_atomic_load(&fd.ctrl->lvl_n[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (nk >= 2 && nk <= fd.lv[k].cap) c = (nk + RT - 1) / RT * np;
+            }
+        }
+        const uint32_t inc = wave_incl_scan(c);
+        s_fs[threadIdx.x + 1] = inc;
+        if (threadIdx.x == 0) s_fs[0] = 0;
+    }
+    __syncthreads();
+    const uint32_t total = s_fs[m.F];
+    __syncthreads();  // (s_fs is read again by the caller before it is rewritten)
+    return total;
+}
+__device__ inline uint32_t item_frame(const TileMap &m, const uint32_t *s_fs, uint32_t i)
+{
+    uint32_t f = 0;
+    while (f + 1 < m.F && s_fs[f + 1] <= i) ++f;
+    return f;
+}
+static_assert(GSC_MAX_BATCH <= WAVE, "one wave counts the frames' items");
+
+// Schedules of levels 2 .. kmax. A level's size is known only once the previous level is done,
+// so every remaining workgroup waits for the producers before it counts the next level's tiles.
+__global__ __launch_bounds__(PRE_BLOCK) void k_prelude_up(TileMap m, int kmax)
+{
+    __shared__ uint32_t s_fs[GSC_MAX_BATCH + 1];
+    const CAS FrameDesc &fd0 = *cp(m.fd[0]);
+    uint32_t *flags = fd0.lvl_flags;
+    uint32_t phase = PHASE_PRELUDE;
+    for (int k = 2; k <= kmax; ++k) {
+        const uint32_t items = level_items(m, k, 1, s_fs);
+        if (blockIdx.x >= items) return;  // nothing here, and the later levels are no larger
+        for (uint32_t i = blockIdx.x; i < items; i += gridDim.x) {
+            const uint32_t f = item_frame(m, s_fs, i);
+            prelude_tile<true>(m, f, k, i - s_fs[f]);
+            __syncthreads();
+        }
+        if (k == kmax) return;
+        const uint32_t np = min(items, gridDim.x);  // the workgroups that took an item
+        level_publish(flags, ++phase);
+        level_wait(flags, np, phase, fd0.ctrl);
+    }
+}
+
 uint32_t prelude_blocks(uint32_t tiles) { return ceil_div(tiles, PRE_TILES); }
 
 // =========================================================== shared transform pieces
@@ -567,35 +641,49 @@ uint32_t raht_blocks(uint32_t tiles, int k, int C4)
 {
     return (tiles + 7) / 8 * 8 * channel_passes((uint32_t)C4, k);
 }
+uint32_t channel_slices_upper(int C4) { return channel_passes((uint32_t)C4, 2); }
 
 // ============================================================== upper levels, forward
 // One workgroup per (tile, channel slice) of S_k, k >= 2: the entries' partial low-passes come
 // from S_{k-1}'s open-entry rows, each entry's coefficient row goes to its voxel's row.
-template <bool VEC, bool POW2>
-__global__ __launch_bounds__(RAHT_THREADS) void k_raht_fwd_up(TileMap m, int k)
-{
-    extern __shared__ float4 s_y[];
-    __shared__ uint32_t s_rec[RT];
-    __shared__ float2 s_ab[RT];
-    __shared__ uint16_t s_lst[LSTART_N];
-    __shared__ uint16_t s_opos[OPEN_CAP];
-    __shared__ uint32_t s_idx[RT + 1];
-    __shared__ unsigned long long s_lmask[NCLS];
+// LDS of an upper-level item: the slice rows (dynamic) and the tile's schedule.
+struct UpLds {
+    uint32_t rec[RT];
+    float2 ab[RT];
+    uint16_t lst[LSTART_N];
+    uint16_t opos[OPEN_CAP];
+    uint32_t idx[RT + 1];
+    unsigned long long lmask[NCLS];
+};
 
-    const uint32_t f = frame_of(m, blockIdx.x);
+// The schedule of an item (tile of S_k, k >= 2) into LDS; false if there is nothing to do. The
+// schedules were written by an earlier launch, so a workgroup loads its first item's schedule
+// before it waits for the previous level.
+__device__ inline bool up_schedule(const TileMap &m, uint32_t f, int k, uint32_t tile, TileSched &ts, UpLds &L)
+{
     const CAS FrameDesc &fd = *cp(m.fd[f]);  // (not written while the kernel runs)
     Ctrl *ctrl = fd.ctrl;
-    if (load_error(ctrl)) return;
-    if ((uint32_t)k > fd.K) return;
-    TileSched ts;
+    if (load_error(ctrl)) return false;
+    if ((uint32_t)k > fd.K) return false;
+    return load_schedule(fd, ctrl, k, tile, pass_chunks(fd.C4, k), ts, L.rec, L.ab, L.lst, L.opos, L.idx, L.lmask);
+}
+
+// One item (tile, channel slice p0) of S_k, k >= 2, whose schedule is in LDS.
+template <bool VEC, bool POW2>
+__device__ inline void fwd_up_item(const TileMap &m, uint32_t f, int k, uint32_t p0, const TileSched &ts,
+                                   float4 *s_y, UpLds &L)
+{
+    uint32_t *s_rec = L.rec, *s_idx = L.idx;
+    float2 *s_ab = L.ab;
+    uint16_t *s_lst = L.lst, *s_opos = L.opos;
+    unsigned long long *s_lmask = L.lmask;
+    const CAS FrameDesc &fd = *cp(m.fd[f]);  // (not written while the kernel runs)
+    Ctrl *ctrl = fd.ctrl;
     const uint32_t C = fd.C, C4 = fd.C4;
-    const uint32_t NP = channel_passes(C4, k), CH4 = pass_chunks(C4, k);
-    const SliceSplit hs = slice_split(blockIdx.x - m.start[f], NP);
-    if (!load_schedule(fd, ctrl, k, hs.tile, CH4, ts, s_rec, s_ab, s_lst, s_opos, s_idx, s_lmask))
-        return;
+    const uint32_t CH4 = pass_chunks(C4, k);
     const Roles R(CH4);
     const uint32_t mlen = (uint32_t)ts.mlen;
-    const uint32_t cb = hs.p0 * CH4, nch = min(CH4, C4 - cb);
+    const uint32_t cb = p0 * CH4, nch = min(CH4, C4 - cb);
     const uint32_t c4 = cb + R.c4;  // this thread's global channel chunk
     const bool live = R.act && R.c4 < nch;
     // ---- the entries' values of this channel slice
@@ -652,6 +740,96 @@ __global__ __launch_bounds__(RAHT_THREADS) void k_raht_fwd_up(TileMap m, int k)
         for (uint32_t o = R.row0; o < ts.ocnt; o += R.RPB)
             gstore4(dst + ((size_t)(ts.obase + o) * C4 + c4) * 4, s_y[s_opos[o] * CH4 + R.c4]);
     }
+}
+
+// Items of every level of a transform launch, counted once at the start (the schedule launches
+// have fixed the sizes): wave w counts levels 2 + w, 2 + w + NW, ...; s_fs[k][0..F] are the
+// frames' first items of level k and s_cnt[k] its items.
+struct UpCounts {
+    uint32_t cnt[MAXK + 1];
+    uint32_t fs[MAXK + 1][GSC_MAX_BATCH + 1];
+};
+__device__ inline void up_counts(const TileMap &m, int kmax, uint32_t np, UpCounts &U)
+{
+    const uint32_t w = threadIdx.x / WAVE, lane = lane_id();
+    for (int k = 2 + (int)w; k <= kmax; k += RAHT_THREADS / WAVE) {
+        uint32_t c = 0;
+        if (lane < m.F) {
+            const CAS FrameDesc &fd = *cp(m.fd[lane]);
+            if ((uint32_t)k <= fd.K) {
+                const uint32_t nk = cp(fd.ctrl)->lvl_n[k];
+                if (nk >= 2 && nk <= fd.lv[k].cap) c = (nk + RT - 1) / RT * np;
+            }
+        }
+        const uint32_t inc = wave_incl_scan(c);
+        U.fs[k][lane + 1] = inc;
+        if (lane == 0) U.fs[k][0] = 0;
+        if (lane == WAVE - 1) U.cnt[k] = inc;
+    }
+    __syncthreads();
+}
+
+// The launch's items in processing order: the levels one after the other (ascending for the
+// forward, descending for the inverse), each level's items frame by frame. Workgroup b takes
+// items b, b + G, ..., so the items of small levels go to workgroups that have no item in the
+// levels before them: such a workgroup loads its schedule at once and only waits, on the phase
+// flags of the previous level's workgroups (a contiguous range modulo G), before it reads that
+// level's rows. A workgroup publishes a level when it moves on from it (or leaves). Every wait is
+// on items earlier in this order, each workgroup takes its items in order and all are resident,
+// so the earliest unfinished item can always proceed.
+template <bool DESC, class Item>
+__device__ inline void up_levels(const TileMap &m, int kmax, uint32_t phase0, UpLds &L, UpCounts &U, Item item)
+{
+    const CAS FrameDesc &fd0 = *cp(m.fd[0]);
+    uint32_t *flags = fd0.lvl_flags;
+    const uint32_t NP = channel_passes(fd0.C4, 2);  // every frame of a launch has the same C
+    up_counts(m, kmax, NP, U);
+    const uint32_t nl = kmax >= 2 ? (uint32_t)kmax - 1 : 0u;  // level positions 0 .. nl-1
+    auto level_at = [&](uint32_t o) { return DESC ? kmax - (int)o : 2 + (int)o; };
+    const uint32_t G = gridDim.x;
+    uint32_t o = 0, base = 0;      // level position of the current item, its first global item
+    uint32_t cur = ~0u;            // level position of this workgroup's last item
+    uint32_t pbase = 0, pcnt = 0, ppos = 0;  // the previous non-empty level: first item, items, position
+    for (uint32_t g = blockIdx.x;; g += G) {
+        while (o < nl && g >= base + U.cnt[level_at(o)]) {
+            const uint32_t c = U.cnt[level_at(o)];
+            if (c) {
+                pbase = base;
+                pcnt = c;
+                ppos = o;
+            }
+            base += c;
+            ++o;
+        }
+        if (o >= nl) break;
+        const int k = level_at(o);
+        const uint32_t i = g - base;
+        if (cur != ~0u && cur != o) level_publish(flags, phase0 + cur + 1);
+        const uint32_t *fs = U.fs[k];
+        const uint32_t f = item_frame(m, fs, i), local = i - fs[f];
+        TileSched ts;
+        const bool ok = up_schedule(m, f, k, local / NP, ts, L);
+        if (cur != o) {
+            if (pcnt) level_wait_range(flags, pbase % G, min(pcnt, G), G, phase0 + ppos + 1, fd0.ctrl);
+            cur = o;
+        }
+        if (ok) item(f, k, local % NP, ts);
+        __syncthreads();
+    }
+    if (cur != ~0u) level_publish(flags, phase0 + cur + 1);
+}
+
+// Levels 2 .. kmax, ascending: a level reads the open-entry rows the previous level wrote (and
+// rewrites the coefficient rows of entries that previous levels left open).
+template <bool VEC, bool POW2>
+__global__ __launch_bounds__(RAHT_THREADS) void k_raht_fwd_upper(TileMap m, int kmax)
+{
+    extern __shared__ float4 s_y[];
+    __shared__ UpLds L;
+    __shared__ UpCounts U;
+    up_levels<false>(m, kmax, PHASE_FORWARD, L, U, [&](uint32_t f, int k, uint32_t p0, const TileSched &ts) {
+        fwd_up_item<VEC, POW2>(m, f, k, p0, ts, s_y, L);
+    });
 }
 
 // ============================================================ first level, persistent forward
@@ -1135,30 +1313,19 @@ __global__ __launch_bounds__(RAHT_THREADS) __attribute__((amdgpu_waves_per_eu(PE
 // voxels, open entries' low-passes from S_{k+1}; the entries' synthesized low-passes go to S_{k-1}'s
 // open-entry rows.
 template <bool VEC>
-__global__ __launch_bounds__(RAHT_THREADS) void k_raht_inv_up(TileMap m, int k)
+__device__ inline void inv_up_item(const TileMap &m, uint32_t f, int k, uint32_t p0, const TileSched &ts,
+                                   float4 *s_y, UpLds &L)
 {
-    extern __shared__ float4 s_y[];
-    __shared__ uint32_t s_rec[RT];
-    __shared__ float2 s_ab[RT];
-    __shared__ uint16_t s_lst[LSTART_N];
-    __shared__ uint16_t s_opos[OPEN_CAP];
-    __shared__ uint32_t s_idx[RT + 1];
-    __shared__ unsigned long long s_lmask[NCLS];
-
-    const uint32_t f = frame_of(m, blockIdx.x);
+    uint32_t *s_rec = L.rec, *s_idx = L.idx;
+    float2 *s_ab = L.ab;
+    uint16_t *s_lst = L.lst, *s_opos = L.opos;
+    unsigned long long *s_lmask = L.lmask;
     const CAS FrameDesc &fd = *cp(m.fd[f]);  // (not written while the kernel runs)
-    Ctrl *ctrl = fd.ctrl;
-    if (load_error(ctrl)) return;
-    if ((uint32_t)k > fd.K) return;
-    TileSched ts;
     const uint32_t C = fd.C, C4 = fd.C4;
-    const uint32_t NP = channel_passes(C4, k), CH4 = pass_chunks(C4, k);
-    const SliceSplit hs = slice_split(blockIdx.x - m.start[f], NP);
-    if (!load_schedule(fd, ctrl, k, hs.tile, CH4, ts, s_rec, s_ab, s_lst, s_opos, s_idx, s_lmask))
-        return;
+    const uint32_t CH4 = pass_chunks(C4, k);
     const Roles R(CH4);
     const uint32_t mlen = (uint32_t)ts.mlen;
-    const uint32_t cb = hs.p0 * CH4, nch = min(CH4, C4 - cb);
+    const uint32_t cb = p0 * CH4, nch = min(CH4, C4 - cb);
     const uint32_t c4 = cb + R.c4;
     const bool live = R.act && R.c4 < nch;
     // ---- coefficients of every entry (the high-pass stored at it)
@@ -1201,13 +1368,25 @@ __global__ __launch_bounds__(RAHT_THREADS) void k_raht_inv_up(TileMap m, int k)
         gstore4(dst + ((size_t)(ts.s + j) * C4 + c4) * 4, s_y[j * CH4 + R.c4]);
 }
 
+// Levels kmax .. 2, descending: a level reads the low-passes the level above handed down.
+template <bool VEC>
+__global__ __launch_bounds__(RAHT_THREADS) void k_raht_inv_upper(TileMap m, int kmax)
+{
+    extern __shared__ float4 s_y[];
+    __shared__ UpLds L;
+    __shared__ UpCounts U;
+    up_levels<true>(m, kmax, PHASE_INVERSE, L, U, [&](uint32_t f, int k, uint32_t p0, const TileSched &ts) {
+        inv_up_item<VEC>(m, f, k, p0, ts, s_y, L);
+    });
+}
+
 // Dynamic LDS of a transform launch: the slice of RT entries, plus one sink slot for writes that
 // are masked off by address rather than by branch.
 size_t raht_lds_bytes(int C4, int k) { return ((size_t)RT * pass_chunks((uint32_t)C4, k) + 1) * sizeof(float4); }
 
 // Workgroups of a persistent first-level launch over `items` items: at most PERSIST_PER_CU per
 // CU, a multiple of 8 NP, and as few as give every workgroup the same number of items, up to one.
-uint32_t persist_grid(uint32_t items, int C4)
+static uint32_t cu_count()
 {
     static int cus = 0;
     if (cus == 0) {
@@ -1216,6 +1395,12 @@ uint32_t persist_grid(uint32_t items, int C4)
             v = 256;
         cus = v;
     }
+    return (uint32_t)cus;
+}
+
+uint32_t persist_grid(uint32_t items, int C4)
+{
+    const uint32_t cus = cu_count();
     const uint32_t unit = 8 * channel_passes((uint32_t)C4, 1);
     const uint32_t gmax = ((uint32_t)PERSIST_PER_CU * (uint32_t)cus) / unit * unit;
     if (items <= gmax) return items;
@@ -1234,12 +1419,7 @@ hipError_t launch_raht_fwd(const TileMap &m, int k, const RahtCfg &cfg, hipStrea
         else hipLaunchKernelGGL((k_raht_fwd1<false, false>), grid, block, lds, s, m);
         return hipGetLastError();
     }
-    const dim3 grid(m.start[m.F]), block(RAHT_THREADS);
-    if (cfg.vec && cfg.pow2) hipLaunchKernelGGL((k_raht_fwd_up<true, true>), grid, block, lds, s, m, k);
-    else if (cfg.vec) hipLaunchKernelGGL((k_raht_fwd_up<true, false>), grid, block, lds, s, m, k);
-    else if (cfg.pow2) hipLaunchKernelGGL((k_raht_fwd_up<false, true>), grid, block, lds, s, m, k);
-    else hipLaunchKernelGGL((k_raht_fwd_up<false, false>), grid, block, lds, s, m, k);
-    return hipGetLastError();
+    return hipErrorInvalidValue;  // upper levels: launch_raht_fwd_upper
 }
 
 hipError_t launch_raht_inv(const TileMap &m, int k, const RahtCfg &cfg, hipStream_t s)
@@ -1251,9 +1431,60 @@ hipError_t launch_raht_inv(const TileMap &m, int k, const RahtCfg &cfg, hipStrea
         else hipLaunchKernelGGL((k_raht_inv1<false>), grid, block, lds, s, m);
         return hipGetLastError();
     }
-    const dim3 grid(m.start[m.F]), block(RAHT_THREADS);
-    if (cfg.vec) hipLaunchKernelGGL((k_raht_inv_up<true>), grid, block, lds, s, m, k);
-    else hipLaunchKernelGGL((k_raht_inv_up<false>), grid, block, lds, s, m, k);
+    return hipErrorInvalidValue;  // upper levels: launch_raht_inv_upper
+}
+
+// Workgroups of a persistent upper-level launch: all of them must be resident at once (they
+// wait on one another's phase flags), so at most what the occupancy calculator allows per CU
+// times the CUs, at most UP_GRID_MAX flags, and no more than the largest level's worst-case
+// items. Cached per (kernel, dynamic LDS).
+static uint32_t resident_grid(const void *kern, int threads, size_t lds, uint32_t items_max)
+{
+    struct Entry { const void *kern; size_t lds; int nb; };
+    static Entry cache[32];
+    static int used = 0;
+    int nb = 0;
+    for (int i = 0; i < used; ++i)
+        if (cache[i].kern == kern && cache[i].lds == lds) nb = cache[i].nb;
+    if (nb == 0) {
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, threads, lds) != hipSuccess || nb < 1) nb = 1;
+        if (used < 32) cache[used++] = Entry{kern, lds, nb};
+    }
+    uint32_t g = min((uint32_t)nb * cu_count(), UP_GRID_MAX);
+    g = min(g, items_max);
+    return g ? g : 1u;
+}
+
+hipError_t launch_prelude_up(const TileMap &m, int kmax, uint32_t items_max, hipStream_t s)
+{
+    const uint32_t grid = resident_grid(reinterpret_cast<const void *>(k_prelude_up), PRE_BLOCK, 0, items_max);
+    hipLaunchKernelGGL(k_prelude_up, dim3(grid), dim3(PRE_BLOCK), 0, s, m, kmax);
+    return hipGetLastError();
+}
+
+hipError_t launch_raht_fwd_upper(const TileMap &m, int kmax, uint32_t items_max, const RahtCfg &cfg, hipStream_t s)
+{
+    const size_t lds = raht_lds_bytes(cfg.C4, 2);
+    const void *kern = cfg.vec ? (cfg.pow2 ? reinterpret_cast<const void *>(k_raht_fwd_upper<true, true>)
+                                           : reinterpret_cast<const void *>(k_raht_fwd_upper<true, false>))
+                               : (cfg.pow2 ? reinterpret_cast<const void *>(k_raht_fwd_upper<false, true>)
+                                           : reinterpret_cast<const void *>(k_raht_fwd_upper<false, false>));
+    const dim3 grid(resident_grid(kern, RAHT_THREADS, lds, items_max)), block(RAHT_THREADS);
+    if (cfg.vec && cfg.pow2) hipLaunchKernelGGL((k_raht_fwd_upper<true, true>), grid, block, lds, s, m, kmax);
+    else if (cfg.vec) hipLaunchKernelGGL((k_raht_fwd_upper<true, false>), grid, block, lds, s, m, kmax);
+    else if (cfg.pow2) hipLaunchKernelGGL((k_raht_fwd_upper<false, true>), grid, block, lds, s, m, kmax);
+    else hipLaunchKernelGGL((k_raht_fwd_upper<false, false>), grid, block, lds, s, m, kmax);
+    return hipGetLastError();
+}
+
+hipError_t launch_raht_inv_upper(const TileMap &m, int kmax, uint32_t items_max, const RahtCfg &cfg, hipStream_t s)
+{
+    const size_t lds = raht_lds_bytes(cfg.C4, 2);
+    const void *kern = cfg.vec ? reinterpret_cast<const void *>(k_raht_inv_upper<true>)
+                               : reinterpret_cast<const void *>(k_raht_inv_upper<false>);
+    const dim3 grid(resident_grid(kern, RAHT_THREADS, lds, items_max)), block(RAHT_THREADS);
+    if (cfg.vec) hipLaunchKernelGGL((k_raht_inv_upper<true>), grid, block, lds, s, m, kmax);
+    else hipLaunchKernelGGL((k_raht_inv_upper<false>), grid, block, lds, s, m, kmax);
     return hipGetLastError();
 }
 
