@@ -27,7 +27,12 @@ namespace gsc {
 
 static_assert(RT == RAHT_THREADS && RT % WAVE == 0, "a tile is one 64-entry chunk per wave");
 static_assert(RT < 1024, "merge records pack three 10-bit positions");
-constexpr int PRE_THREADS = RT;
+// The schedule of a tile is built by RT / EPT threads, EPT entries each. The first level uses
+// two entries per thread: with half as many waves per tile, all first-level tiles of a
+// 1M-voxel frame fit on the GPU at once (the wave slots, not the work, limited that launch).
+// The upper levels are a short chain of few tiles, where a tile's latency counts: one entry
+// per thread.
+constexpr int PRE_EPT1 = 2, PRE_EPT_UP = 1;
 constexpr int NCHUNK = RT / WAVE;
 constexpr int CROSS = NCHUNK;  // class of merges that cross chunks
 
@@ -75,12 +80,15 @@ __device__ inline uint64_t uniform64(uint64_t v)
 // S_{k+1} with a decoupled look-back whose aggregate is published as soon as the tile's open
 // entries are known and whose prefix is resolved after the rest of the tile's work.
 constexpr int PRE_TILES = 1;  // tiles per workgroup
-constexpr int PRE_BLOCK = PRE_TILES * PRE_THREADS;
 
-template <bool LIVE>
+template <bool LIVE, int PRE_EPT>
 __device__ inline void prelude_tile(const TileMap &m, uint32_t f, int k, uint32_t tile)
 {
     static_assert(PRE_TILES == 1, "one tile per workgroup");
+    constexpr int PRE_THREADS = RT / PRE_EPT, PRE_BLOCK = PRE_THREADS;
+    constexpr int PRE_WAVES = PRE_THREADS / WAVE;
+    constexpr int PRE_SEG = (SEG_N + PRE_THREADS - 1) / PRE_THREADS;  // segment counts per thread
+    static_assert(PRE_EPT == 1 || PRE_EPT == 2, "one or two entries per thread");
     __shared__ uint32_t s_lvl_e;
     __shared__ uint64_t s_mask[NLVL][NCHUNK];
     __shared__ uint32_t s_cnt[SEG_N], s_fill[SEG_N];
@@ -102,155 +110,216 @@ __device__ inline void prelude_tile(const TileMap &m, uint32_t f, int k, uint32_
     const GAS uint64_t *codes = gp((fd.mode == MODE_FWD_F32 || fd.mode == MODE_ADJ_F32) ? fd.codes_in : fd.leaf);
     const GAS uint8_t *slvl = gp(lv.s_lvl);
 
-    const int j = (int)threadIdx.x;
-    const uint32_t w = (uint32_t)j / WAVE, lane = lane_id();
-    uint32_t lvl = 0;  // 0: no entry
-    if (j < mlen) {
-        const uint32_t i = s + j;
-        lvl = k == 1 ? (i == 0 ? LVL_NONE : merge_level(codes[i - 1], codes[i])) : slvl[i];
+    // thread t holds entries j(x) = t + x PRE_THREADS, x < PRE_EPT: entry j(x) lies in wave
+    // chunk w + x PRE_WAVES, and the chunk-wide steps (ballots, rounds) run once per chunk
+    const uint32_t t = threadIdx.x, w = t / WAVE, lane = lane_id();
+    int jj[PRE_EPT];
+    uint32_t lvl[PRE_EPT];  // 0: no entry
+#pragma unroll
+    for (int x = 0; x < PRE_EPT; ++x) jj[x] = (int)(t + x * PRE_THREADS);
+    // both entries' loads before any use, at clamped positions (a load under a per-entry
+    // condition would be waited for where its branch joins)
+    if (k == 1) {
+        uint64_t c0[PRE_EPT], c1[PRE_EPT];
+#pragma unroll
+        for (int x = 0; x < PRE_EPT; ++x) {
+            const uint32_t i = s + (uint32_t)min(jj[x], mlen - 1);
+            c0[x] = codes[i > 0 ? i - 1 : 0];
+            c1[x] = codes[i];
+        }
+#pragma unroll
+        for (int x = 0; x < PRE_EPT; ++x)
+            lvl[x] = jj[x] < mlen ? (s + jj[x] == 0 ? LVL_NONE : merge_level(c0[x], c1[x])) : 0u;
+    } else {
+        uint32_t l[PRE_EPT];
+#pragma unroll
+        for (int x = 0; x < PRE_EPT; ++x) l[x] = slvl[s + (uint32_t)min(jj[x], mlen - 1)];
+#pragma unroll
+        for (int x = 0; x < PRE_EPT; ++x) lvl[x] = jj[x] < mlen ? l[x] : 0u;
     }
-    for (uint32_t x = j; x < (uint32_t)SEG_N; x += PRE_THREADS) {
-        s_cnt[x] = 0;
-        s_fill[x] = 0;
+    for (uint32_t q = t; q < (uint32_t)SEG_N; q += PRE_THREADS) {
+        s_cnt[q] = 0;
+        s_fill[q] = 0;
     }
-    s_rdl[j] = 0;
-    if (j == 0) s_lvl_e = e < nk ? (k == 1 ? merge_level(codes[e - 1], codes[e]) : slvl[e]) : LVL_NONE;
+#pragma unroll
+    for (int x = 0; x < PRE_EPT; ++x) s_rdl[jj[x]] = 0;
+    if (t == 0) s_lvl_e = e < nk ? (k == 1 ? merge_level(codes[e - 1], codes[e]) : slvl[e]) : LVL_NONE;
     // active lists of the levels that can hold a merge: an entry merges at a level of at most 3J
     // (the tile's first entry of the sequence, LVL_NONE, is in every list and is never a right
     // sibling)
     const uint32_t nlvl = min(3u * fd.J + 1u, (uint32_t)NLVL);
-    for (uint32_t x = 1; x < nlvl; ++x) {
-        const uint64_t b = __ballot(lvl >= x);
-        if (lane == 0) s_mask[x][w] = b;
+    for (uint32_t q = 1; q < nlvl; ++q) {
+#pragma unroll
+        for (int x = 0; x < PRE_EPT; ++x) {
+            const uint64_t b = __ballot(lvl[x] >= q);
+            if (lane == 0) s_mask[q][w + x * PRE_WAVES] = b;
+        }
     }
     __syncthreads();
 
     const uint32_t lvl_e = s_lvl_e;
-    bool is_local = false, is_open = false;
-    int left = -1, right = mlen;
-    uint32_t cls = CROSS;
-    if (j < mlen) {
-        if (lvl >= 1 && lvl < (uint32_t)NLVL) {
-            const uint64_t below = lanemask_lt();
-            const uint64_t above = ~below & ~(1ull << lane);
-            uint64_t mm = s_mask[lvl][w] & below;
-            if (mm) {
-                left = (int)(w * WAVE) + msb64(mm);
-            } else {
-                for (int ww = (int)w - 1; ww >= 0; --ww) {
-                    const uint64_t t = s_mask[lvl][ww];
-                    if (t) {
-                        left = ww * WAVE + msb64(t);
-                        break;
+    bool is_local[PRE_EPT], is_open[PRE_EPT];
+    int left[PRE_EPT], right[PRE_EPT];
+    uint32_t cls[PRE_EPT];
+#pragma unroll
+    for (int x = 0; x < PRE_EPT; ++x) {
+        const uint32_t wc = w + x * PRE_WAVES;  // the entry's chunk
+        const uint32_t lv_ = lvl[x];
+        is_local[x] = is_open[x] = false;
+        left[x] = -1;
+        right[x] = mlen;
+        cls[x] = CROSS;
+        if (jj[x] < mlen) {
+            if (lv_ >= 1 && lv_ < (uint32_t)NLVL) {
+                const uint64_t below = lanemask_lt();
+                const uint64_t above = ~below & ~(1ull << lane);
+                uint64_t mm = s_mask[lv_][wc] & below;
+                if (mm) {
+                    left[x] = (int)(wc * WAVE) + msb64(mm);
+                } else {
+                    for (int ww = (int)wc - 1; ww >= 0; --ww) {
+                        const uint64_t b = s_mask[lv_][ww];
+                        if (b) {
+                            left[x] = ww * WAVE + msb64(b);
+                            break;
+                        }
                     }
                 }
-            }
-            mm = s_mask[lvl][w] & above;
-            if (mm) {
-                right = (int)(w * WAVE) + (__ffsll((long long)mm) - 1);
-            } else {
-                for (int ww = (int)w + 1; ww < NCHUNK; ++ww) {
-                    const uint64_t t = s_mask[lvl][ww];
-                    if (t) {
-                        right = ww * WAVE + (__ffsll((long long)t) - 1);
-                        break;
+                mm = s_mask[lv_][wc] & above;
+                if (mm) {
+                    right[x] = (int)(wc * WAVE) + (__ffsll((long long)mm) - 1);
+                } else {
+                    for (int ww = (int)wc + 1; ww < NCHUNK; ++ww) {
+                        const uint64_t b = s_mask[lv_][ww];
+                        if (b) {
+                            right[x] = ww * WAVE + (__ffsll((long long)b) - 1);
+                            break;
+                        }
                     }
                 }
+                is_local[x] = left[x] >= 0 && (right[x] < mlen || lvl_e > lv_);
+                is_open[x] = !is_local[x];
+                if (is_local[x] && left[x] / WAVE == (int)wc && (right[x] - 1) / WAVE == (int)wc) cls[x] = wc;
+            } else {
+                is_open[x] = true;  // entry 0 of the sequence never merges as a right sibling
             }
-            is_local = left >= 0 && (right < mlen || lvl_e > lvl);
-            is_open = !is_local;
-            if (is_local && left / WAVE == (int)w && (right - 1) / WAVE == (int)w) cls = w;
-        } else {
-            is_open = true;  // entry 0 of the sequence never merges as a right sibling
         }
     }
-    // ---- open entries in order: ranks in the tile, the tile's count published at once (its
-    // prefix is resolved at the end, after the rest of the work)
-    uint32_t total;
-    const uint32_t rank = block_excl_scan<PRE_BLOCK>(is_open ? 1u : 0u, s_tmp, &total);
+    // ---- open entries in order: ranks in the tile (the entries j(0) of all threads come before
+    // the entries j(1): one scan of the two flags packed in one word), the tile's count published
+    // at once (its prefix is resolved at the end, after the rest of the work)
+    static_assert(PRE_THREADS < 65536, "two 16-bit counts per scanned word");
+    uint32_t ptot;
+    const uint32_t pex = block_excl_scan<PRE_BLOCK>((is_open[0] ? 1u : 0u) | ((PRE_EPT > 1 && is_open[PRE_EPT - 1] ? 1u : 0u) << 16), s_tmp, &ptot);
+    const uint32_t total = (ptot & 0xFFFFu) + (ptot >> 16);
+    uint32_t rank[PRE_EPT];
+    rank[0] = pex & 0xFFFFu;
+    if (PRE_EPT > 1) rank[PRE_EPT - 1] = (ptot & 0xFFFFu) + (pex >> 16);
     lookback_block_publish<OpSum>(lv.status, 1, tile, total);
-    // ---- rounds: the chunk's own merges by its wave (levels ascending, no workgroup barrier)
-    const bool mine = is_local && cls != CROSS;  // (then cls is this thread's own chunk)
-    uint32_t rnd = 0;
-    {
-        uint64_t lm = mine ? 1ull << lvl : 0ull;
+    // ---- rounds: each chunk's own merges by its wave (levels ascending, no workgroup barrier)
+    bool mine[PRE_EPT];
+    uint32_t rnd[PRE_EPT];
+#pragma unroll
+    for (int x = 0; x < PRE_EPT; ++x) {
+        mine[x] = is_local[x] && cls[x] != CROSS;  // (then cls is the entry's own chunk)
+        rnd[x] = 0;
+        uint64_t lm = mine[x] ? 1ull << lvl[x] : 0ull;
 #pragma unroll
         for (int o = 1; o < WAVE; o <<= 1) lm |= __shfl_xor(lm, o, WAVE);
         lm = uniform64(lm);
         while (lm) {
-            const uint32_t x = (uint32_t)(__ffsll((long long)lm) - 1);
-            lm &= ~(1ull << x);
-            if (mine && lvl == x) {
-                rnd = 1u + max((uint32_t)s_rdl[left], (uint32_t)s_rdl[j]);
-                s_rdl[left] = (uint8_t)rnd;
+            const uint32_t q = (uint32_t)(__ffsll((long long)lm) - 1);
+            lm &= ~(1ull << q);
+            if (mine[x] && lvl[x] == q) {
+                rnd[x] = 1u + max((uint32_t)s_rdl[left[x]], (uint32_t)s_rdl[jj[x]]);
+                s_rdl[left[x]] = (uint8_t)rnd[x];
             }
             __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
             __builtin_amdgcn_wave_barrier();
         }
     }
-    // ---- segment counts: a chunk's merges are counted by its own wave with ballots (only wave w
-    // holds class-w merges; the rank in the ballot is the record's place in its segment);
+    // ---- segment counts: a chunk's merges are counted by its own wave with ballots (only one
+    // wave holds a chunk's merges; the rank in the ballot is the record's place in its segment);
     // crossing merges keep their binary level as their round (a round of their own would cost a
     // workgroup barrier per level) and are counted with LDS atomics
-    uint32_t wrank = 0;
-    {
-        uint64_t rm = mine ? 1ull << rnd : 0ull;
+    uint32_t wrank[PRE_EPT];
+#pragma unroll
+    for (int x = 0; x < PRE_EPT; ++x) {
+        wrank[x] = 0;
+        uint64_t rm = mine[x] ? 1ull << rnd[x] : 0ull;
 #pragma unroll
         for (int o = 1; o < WAVE; o <<= 1) rm |= __shfl_xor(rm, o, WAVE);
         rm = uniform64(rm);
         while (rm) {
             const uint32_t r = (uint32_t)(__ffsll((long long)rm) - 1);
             rm &= ~(1ull << r);
-            const uint64_t bal = __ballot(mine && rnd == r);
-            if (mine && rnd == r) wrank = (uint32_t)__popcll(bal & lanemask_lt());
-            if (lane == 0) s_cnt[r * NCLS + w] = (uint32_t)__popcll(bal);
+            const uint64_t bal = __ballot(mine[x] && rnd[x] == r);
+            if (mine[x] && rnd[x] == r) wrank[x] = (uint32_t)__popcll(bal & lanemask_lt());
+            if (lane == 0) s_cnt[r * NCLS + w + x * PRE_WAVES] = (uint32_t)__popcll(bal);
         }
     }
-    if (is_local && cls == CROSS) {
-        rnd = lvl;
-        atomicAdd(&s_cnt[rnd * NCLS + CROSS], 1u);
+#pragma unroll
+    for (int x = 0; x < PRE_EPT; ++x) {
+        if (is_local[x] && cls[x] == CROSS) {
+            rnd[x] = lvl[x];
+            atomicAdd(&s_cnt[rnd[x] * NCLS + CROSS], 1u);
+        }
     }
     __syncthreads();
-    if (j < WAVE) {  // round masks of the classes: lane x tests round x
+    if (t < WAVE) {  // round masks of the classes: lane q tests round q
 #pragma unroll
         for (uint32_t c = 0; c < (uint32_t)NCLS; ++c) {
-            const uint64_t b = __ballot(s_cnt[j * NCLS + c] != 0);
-            if (j == 0) gp(lv.lmask)[(size_t)tile * NCLS + c] = b;
+            const uint64_t b = __ballot(s_cnt[t * NCLS + c] != 0);
+            if (t == 0) gp(lv.lmask)[(size_t)tile * NCLS + c] = b;
         }
     }
-    {   // segment starts: exclusive scan of the SEG_N counts (two per thread)
-        const uint32_t i0 = 2 * j, i1 = 2 * j + 1;
-        const uint32_t a0 = i0 < (uint32_t)SEG_N ? s_cnt[i0] : 0u;
-        const uint32_t a1 = i1 < (uint32_t)SEG_N ? s_cnt[i1] : 0u;
-        const uint32_t ex = group_excl_scan<PRE_BLOCK, PRE_THREADS>(a0 + a1, s_tmp, nullptr);
-        if (i0 < (uint32_t)SEG_N) s_cnt[i0] = ex;
-        if (i1 < (uint32_t)SEG_N) s_cnt[i1] = ex + a0;
+    {   // segment starts: exclusive scan of the SEG_N counts (PRE_SEG per thread)
+        uint32_t a[PRE_SEG], sum = 0;
+#pragma unroll
+        for (int q = 0; q < PRE_SEG; ++q) {
+            const uint32_t i = PRE_SEG * t + q;
+            a[q] = i < (uint32_t)SEG_N ? s_cnt[i] : 0u;
+            sum += a[q];
+        }
+        uint32_t ex = group_excl_scan<PRE_BLOCK, PRE_THREADS>(sum, s_tmp, nullptr);
+#pragma unroll
+        for (int q = 0; q < PRE_SEG; ++q) {
+            const uint32_t i = PRE_SEG * t + q;
+            if (i < (uint32_t)SEG_N) s_cnt[i] = ex;
+            ex += a[q];
+        }
     }
     __syncthreads();
-    if (is_local) {
-        const uint32_t seg = rnd * NCLS + cls;
-        const uint32_t slot = s_cnt[seg] + (mine ? wrank : atomicAdd(&s_fill[seg], 1u));
-        if (slot < (uint32_t)RT)
-            gp(lv.rec)[(size_t)tile * RT + slot] =
-                (uint32_t)j | ((uint32_t)left << 10) | ((uint32_t)right << 20);
+#pragma unroll
+    for (int x = 0; x < PRE_EPT; ++x) {
+        if (is_local[x]) {
+            const uint32_t seg = rnd[x] * NCLS + cls[x];
+            const uint32_t slot = s_cnt[seg] + (mine[x] ? wrank[x] : atomicAdd(&s_fill[seg], 1u));
+            if (slot < (uint32_t)RT)
+                gp(lv.rec)[(size_t)tile * RT + slot] =
+                    (uint32_t)jj[x] | ((uint32_t)left[x] << 10) | ((uint32_t)right[x] << 20);
+        }
     }
-    for (uint32_t x = j; x < (uint32_t)LSTART_N; x += PRE_THREADS)
-        gp(lv.lstart)[(size_t)tile * LSTART_N + x] = x < (uint32_t)SEG_N ? (uint16_t)s_cnt[x] : 0;
+    for (uint32_t q = t; q < (uint32_t)LSTART_N; q += PRE_THREADS)
+        gp(lv.lstart)[(size_t)tile * LSTART_N + q] = q < (uint32_t)SEG_N ? (uint16_t)s_cnt[q] : 0;
 
     // ---- the open entries' places in S_{k+1}
     const uint32_t base = (uint32_t)lookback_block_resolve<OpSum, PRE_BLOCK>(lv.status, 1, tile, total, ctrl, s_lb);
-    if (is_open) {
-        if (rank < (uint32_t)OPEN_CAP) gp(lv.opos)[(size_t)tile * OPEN_CAP + rank] = (uint16_t)j;
-        if ((uint32_t)k < fd.K) {
-            auto &nx = fd.lv[k + 1];
-            const uint32_t o = base + rank;
-            if (o < nx.cap) {
-                gp(nx.s_idx)[o] = k == 1 ? s + j : gp(lv.s_idx)[s + j];
-                gp(nx.s_lvl)[o] = (uint8_t)lvl;
+#pragma unroll
+    for (int x = 0; x < PRE_EPT; ++x) {
+        if (is_open[x]) {
+            if (rank[x] < (uint32_t)OPEN_CAP) gp(lv.opos)[(size_t)tile * OPEN_CAP + rank[x]] = (uint16_t)jj[x];
+            if ((uint32_t)k < fd.K) {
+                auto &nx = fd.lv[k + 1];
+                const uint32_t o = base + rank[x];
+                if (o < nx.cap) {
+                    gp(nx.s_idx)[o] = k == 1 ? s + jj[x] : gp(lv.s_idx)[s + jj[x]];
+                    gp(nx.s_lvl)[o] = (uint8_t)lvl[x];
+                }
             }
         }
     }
-    if (j == 0) {
+    if (t == 0) {
         if (total > open_max((int)fd.J)) set_error(ctrl, GSC_ERR_INTERNAL);
         lv.obase[tile] = base;
         lv.ocnt[tile] = min(total, (uint32_t)OPEN_CAP);
@@ -259,15 +328,16 @@ __device__ inline void prelude_tile(const TileMap &m, uint32_t f, int k, uint32_
 }
 
 // One workgroup per tile of the first level.
-__global__ __launch_bounds__(PRE_BLOCK) void k_prelude(TileMap m, int k)
+constexpr int PRE_BLOCK1 = RT / PRE_EPT1, PRE_BLOCK_UP = RT / PRE_EPT_UP;
+__global__ __launch_bounds__(PRE_BLOCK1) void k_prelude(TileMap m, int k)
 {
     const uint32_t f = frame_of(m, blockIdx.x);
-    prelude_tile<false>(m, f, k, tile_index(m, f));
+    prelude_tile<false, PRE_EPT1>(m, f, k, tile_index(m, f));
 }
 
 hipError_t launch_prelude(const TileMap &m, int k, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_prelude, dim3(m.start[m.F]), dim3(PRE_BLOCK), 0, s, m, k);
+    hipLaunchKernelGGL(k_prelude, dim3(m.start[m.F]), dim3(PRE_BLOCK1), 0, s, m, k);
     return hipGetLastError();
 }
 
@@ -313,7 +383,7 @@ static_assert(GSC_MAX_BATCH <= WAVE, "one wave counts the frames' items");
 
 // Schedules of levels 2 .. kmax. A level's size is known only once the previous level is done,
 // so every remaining workgroup waits for the producers before it counts the next level's tiles.
-__global__ __launch_bounds__(PRE_BLOCK) void k_prelude_up(TileMap m, int kmax)
+__global__ __launch_bounds__(PRE_BLOCK_UP) void k_prelude_up(TileMap m, int kmax)
 {
     __shared__ uint32_t s_fs[GSC_MAX_BATCH + 1];
     const CAS FrameDesc &fd0 = *cp(m.fd[0]);
@@ -324,7 +394,7 @@ __global__ __launch_bounds__(PRE_BLOCK) void k_prelude_up(TileMap m, int kmax)
         if (blockIdx.x >= items) return;  // nothing here, and the later levels are no larger
         for (uint32_t i = blockIdx.x; i < items; i += gridDim.x) {
             const uint32_t f = item_frame(m, s_fs, i);
-            prelude_tile<true>(m, f, k, i - s_fs[f]);
+            prelude_tile<true, PRE_EPT_UP>(m, f, k, i - s_fs[f]);
             __syncthreads();
         }
         if (k == kmax) return;
@@ -1457,8 +1527,8 @@ static uint32_t resident_grid(const void *kern, int threads, size_t lds, uint32_
 
 hipError_t launch_prelude_up(const TileMap &m, int kmax, uint32_t items_max, hipStream_t s)
 {
-    const uint32_t grid = resident_grid(reinterpret_cast<const void *>(k_prelude_up), PRE_BLOCK, 0, items_max);
-    hipLaunchKernelGGL(k_prelude_up, dim3(grid), dim3(PRE_BLOCK), 0, s, m, kmax);
+    const uint32_t grid = resident_grid(reinterpret_cast<const void *>(k_prelude_up), PRE_BLOCK_UP, 0, items_max);
+    hipLaunchKernelGGL(k_prelude_up, dim3(grid), dim3(PRE_BLOCK_UP), 0, s, m, kmax);
     return hipGetLastError();
 }
 
