@@ -435,28 +435,44 @@ __device__ inline bool load_schedule(FD &fd, Ctrl *ctrl, int k, uint32_t tile,
     auto &lv = fd.lv[k];
     const uint32_t s = tile * RT;
     if (s >= nk) return false;
-    const uint32_t tid = threadIdx.x, NT = blockDim.x;
+    const uint32_t tid = threadIdx.x;  // RAHT_THREADS threads, one per entry
     ts.tile = tile;
     ts.s = s;
     ts.e = min(nk, s + RT);
     ts.nk = nk;
     ts.mlen = (int)(ts.e - s);
     ts.final_level = nk <= (uint32_t)RT;
-    ts.obase = lv.obase[tile];
-    ts.ocnt = lv.ocnt[tile];
     const GAS uint16_t *lstart = gp(lv.lstart), *opos = gp(lv.opos);
     const GAS uint32_t *sidx = gp(lv.s_idx), *recs = gp(lv.rec);
-    for (uint32_t x = tid; x < (uint32_t)LSTART_N; x += NT) s_lst[x] = lstart[(size_t)tile * LSTART_N + x];
-    for (uint32_t o = tid; o < ts.ocnt; o += NT) s_opos[o] = opos[(size_t)tile * OPEN_CAP + o];
-    if (tid < (uint32_t)NCLS) s_lmask[tid] = gp(lv.lmask)[(size_t)tile * NCLS + tid];
+    // Every load is issued at once, at clamped in-bounds slots, and none waits on another (one
+    // memory round trip): the counts, the segment starts, the masks, all OPEN_CAP open
+    // positions, the voxel indices and all RT record slots; slots past the tile's counts are
+    // read but not used.
+    static_assert(RAHT_THREADS == RT && LSTART_N <= 2 * RAHT_THREADS && OPEN_CAP <= RAHT_THREADS, "one entry per thread");
+    const uint32_t obase = lv.obase[tile], ocnt = lv.ocnt[tile];
+    const size_t lb = (size_t)tile * LSTART_N;
+    const uint16_t ls0 = lstart[lb + tid], ls1 = lstart[lb + min(tid + (uint32_t)RT, (uint32_t)LSTART_N - 1)];
+    const uint16_t op = opos[(size_t)tile * OPEN_CAP + min(tid, (uint32_t)OPEN_CAP - 1)];
+    const unsigned long long lmk = gp(lv.lmask)[(size_t)tile * NCLS + min(tid, (uint32_t)NCLS - 1)];
+    const uint32_t jl = min(tid, (uint32_t)ts.mlen - 1);
+    const uint32_t vi = sidx[s + jl];
+    const uint32_t rec = recs[(size_t)tile * RT + tid];
+    const uint32_t ve = sidx[min(ts.e, nk - 1)], nv = ctrl->n_vox;
+    const uint32_t vend = ts.e < nk ? ve : nv;
+    ts.obase = obase;
+    ts.ocnt = ocnt;
+    s_lst[tid] = ls0;
+    if (tid + RT < (uint32_t)LSTART_N) s_lst[tid + RT] = ls1;
+    if (tid < (uint32_t)OPEN_CAP) s_opos[tid] = op;
+    if (tid < (uint32_t)NCLS) s_lmask[tid] = lmk;
     // voxel indices, clamped to the frame's capacity like every row index read from the workspace
     const uint32_t cap = fd.n;
-    for (int j = tid; j < ts.mlen; j += NT) s_idx[j] = min(sidx[s + j], cap ? cap - 1 : 0u);
-    if (tid == 0) s_idx[ts.mlen] = min(ts.e < nk ? sidx[ts.e] : ctrl->n_vox, cap);
+    if (tid < (uint32_t)ts.mlen) s_idx[tid] = min(vi, cap ? cap - 1 : 0u);
+    if (tid == 0) s_idx[ts.mlen] = min(vend, cap);
     __syncthreads();
     ts.nrec = s_lst[SEG_N - 1];
-    for (uint32_t q = tid; q < ts.nrec; q += NT) {
-        const uint32_t rec = recs[(size_t)tile * RT + q];
+    if (tid < ts.nrec) {
+        const uint32_t q = tid;
         s_rec[q] = lds_rec(rec, CH4);
         const uint32_t ij = s_idx[rec & 1023u], il = s_idx[(rec >> 10) & 1023u], ir = s_idx[rec >> 20];
         const float w0 = (float)(ij - il), w1 = (float)(ir - ij);
