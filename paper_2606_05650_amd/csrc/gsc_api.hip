@@ -10,6 +10,7 @@
 namespace gsc {
 uint32_t voxelize_blocks(uint32_t n);
 uint32_t prelude_blocks(uint32_t tiles);
+uint32_t dec_leaves_blocks(uint32_t n);
 }  // namespace gsc
 
 using namespace gsc;
@@ -317,7 +318,7 @@ gsc_status decode_frames(const Frame *fr, int F, int J, int C, hipStream_t s)
             GSC_LAUNCH(launch_dec_expand(m, s));
         }
         {
-            TileMap m = make_map(fr, F, [](const Frame &x) { return ceil_div(x.a.n ? x.a.n : 1, LEAF_THREADS); });
+            TileMap m = make_map(fr, F, [](const Frame &x) { return dec_leaves_blocks(x.a.n); });
             GSC_LAUNCH(launch_dec_leaves(m, s));
         }
     }

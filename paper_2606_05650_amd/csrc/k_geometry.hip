@@ -380,8 +380,8 @@ hipError_t launch_bbox(const TileMap &m, hipStream_t s)
 // in FP64 (bounding cube: per-axis minimum, cell = largest extent / 2^J, or 1 when the frame
 // has no extent), then the Morton code of (x, y, z). The histograms of every radix digit of
 // the codes are accumulated for the sort passes.
-constexpr int VOX_THREADS = 256;
-constexpr int VOX_PPT = 16;  // few workgroups: each merges its digit histograms into the global ones
+constexpr int VOX_THREADS = 512;
+constexpr int VOX_PPT = 8;  // few workgroups: each merges its digit histograms into the global ones
 constexpr int VOX_TILE = VOX_THREADS * VOX_PPT;
 
 __global__ __launch_bounds__(VOX_THREADS) void k_voxelize(TileMap m)
@@ -1046,6 +1046,11 @@ hipError_t launch_dec_expand(const TileMap &m, hipStream_t s)
 
 // One thread per leaf: the leaf's code from the child bits on its path to the root (level J's bit
 // least significant), then its voxel coordinates and centre.
+// LEAF_PPT leaves per thread (leaves b LEAF_TILE + t + x LEAF_THREADS), their walks interleaved:
+// one leaf per thread would need two rounds of workgroups at 1M, and a leaf's walk is a chain of
+// dependent loads that a second, independent chain hides.
+constexpr int LEAF_PPT = 2;
+constexpr uint32_t LEAF_TILE = LEAF_THREADS * LEAF_PPT;
 __global__ __launch_bounds__(LEAF_THREADS) void k_dec_leaves(TileMap m)
 {
     const uint32_t f = frame_of(m, blockIdx.x);
@@ -1055,23 +1060,41 @@ __global__ __launch_bounds__(LEAF_THREADS) void k_dec_leaves(TileMap m)
     const gsc_header *hg = reinterpret_cast<const gsc_header *>(fd.in_stream);
     const CAS gsc_header *h = cp(hg);
     const uint32_t J = fd.J, nv = h->n_vox;
-    const uint32_t v = tile_index(m, f) * LEAF_THREADS + threadIdx.x;
-    if (v >= nv) return;
+    const uint32_t v0 = tile_index(m, f) * LEAF_TILE + threadIdx.x;
+    if (v0 >= nv) return;
     const GAS uint32_t *par = gp(fd.dec_par);
     const GAS uint8_t *cbit = gp(fd.dec_cbit);
     uint64_t qL = 0;  // Q(L): nodes of levels 1..L-1
     for (uint32_t L = 1; L < J; ++L) qL += h->level_sizes[L];
-    uint64_t code = 0;
-    uint32_t x = v;
+    uint64_t code[LEAF_PPT];
+    uint32_t x[LEAF_PPT];
+#pragma unroll
+    for (int i = 0; i < LEAF_PPT; ++i) {
+        code[i] = 0;
+        x[i] = min(v0 + i * LEAF_THREADS, nv - 1);  // (a leaf past the end walks the last one's path)
+    }
     for (uint32_t L = J; L >= 1; --L) {
         const uint32_t size = h->level_sizes[L];
-        const uint64_t g = qL + min(x, size - 1);  // (clamped: never an access outside the nodes)
-        code |= (uint64_t)cbit[g] << (3 * (J - L));
-        x = par[g];
+        uint64_t g[LEAF_PPT];
+        uint32_t cb[LEAF_PPT];
+#pragma unroll
+        for (int i = 0; i < LEAF_PPT; ++i) g[i] = qL + min(x[i], size - 1);  // (clamped: never an access outside the nodes)
+#pragma unroll
+        for (int i = 0; i < LEAF_PPT; ++i) {
+            cb[i] = cbit[g[i]];
+            x[i] = par[g[i]];
+        }
+#pragma unroll
+        for (int i = 0; i < LEAF_PPT; ++i) code[i] |= (uint64_t)cb[i] << (3 * (J - L));
         if (L > 1) qL -= h->level_sizes[L - 1];
     }
-    emit_leaf(fd, hg, v, code);
+#pragma unroll
+    for (int i = 0; i < LEAF_PPT; ++i) {
+        const uint32_t v = v0 + i * LEAF_THREADS;
+        if (v < nv) emit_leaf(fd, hg, v, code[i]);
+    }
 }
+uint32_t dec_leaves_blocks(uint32_t n) { return ceil_div(n ? n : 1u, LEAF_TILE); }
 
 hipError_t launch_dec_leaves(const TileMap &m, hipStream_t s)
 {
