@@ -16,21 +16,21 @@ constexpr int WAVE = 64;
 
 constexpr int SORT_BITS = 8;            // radix digit width
 constexpr int SORT_BINS = 1 << SORT_BITS;
-constexpr int SORT_THREADS = 256;       // 4 waves
+constexpr int SORT_THREADS = 512;       // 8 waves; threads below SORT_BINS also hold a digit each
 // Tiling variants of a sort pass (keys per thread, look-back window), chosen per call by the
 // autotuner's table; the workspace is laid out for the smallest tile.
 struct SortVariant {
     int kpt, win;
 };
 constexpr int SORT_VARIANTS = GSC_SORT_VARIANTS;
-constexpr SortVariant SORT_VARIANT[SORT_VARIANTS] = {{16, 16}, {8, 16}, {24, 16}, {16, 64}};
+constexpr SortVariant SORT_VARIANT[SORT_VARIANTS] = {{8, 16}, {4, 16}, {12, 16}, {8, 64}};
 constexpr int SORT_DEFAULT_VARIANT = 0;
-constexpr int SORT_KPT_MIN = 8;
+constexpr int SORT_KPT_MIN = 4;
 __host__ __device__ constexpr int sort_tile(int variant) { return SORT_THREADS * SORT_VARIANT[variant].kpt; }
 constexpr int SORT_MAX_PASSES = 8;      // ceil(63 / 8)
 
-constexpr int DEDUP_THREADS = 256;
-constexpr int DEDUP_KPT = 16;
+constexpr int DEDUP_THREADS = 512;
+constexpr int DEDUP_KPT = 8;
 constexpr int DEDUP_TILE = DEDUP_THREADS * DEDUP_KPT;
 
 constexpr int OCC_THREADS = 1024;        // 16 waves: the per-depth look-backs run side by side
@@ -40,7 +40,7 @@ constexpr int OCC_TILE = OCC_THREADS * OCC_VPT;
 constexpr int DEC_THREADS = 256;
 constexpr int DEC_PPT = 16;             // occupancy bytes per thread
 constexpr int DEC_TILE = DEC_THREADS * DEC_PPT;
-constexpr int LEAF_THREADS = 256;       // one leaf per thread
+constexpr int LEAF_THREADS = 256;       // two leaves per thread (k_dec_leaves)
 
 constexpr int RT = 512;                 // RAHT tile: entries (eight 64-entry wave chunks)
 constexpr int RAHT_THREADS = 512;       // one wave per chunk

@@ -500,7 +500,7 @@ uint32_t voxelize_blocks(uint32_t n) { return n ? ceil_div(n, VOX_TILE) : 1u; }
 
 // ============================================================ one-sweep radix sort pass
 // Stable LSD pass over digit `pass` of (key, index) pairs. Each workgroup ranks a tile of
-// SORT_THREADS * KPT keys in LDS: wave w owns a contiguous quarter of the tile and walks it in order,
+// SORT_THREADS * KPT keys in LDS: wave w owns a contiguous 1/NW of the tile and walks it in order,
 // 64 keys at a time; lanes holding the same digit are found with SORT_BITS ballots and ranked
 // among themselves, so equal digits keep input order. The tile's digit counts are combined
 // with its predecessors' through a per-digit decoupled look-back, keys are staged in LDS in
@@ -571,23 +571,29 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_pass(TileMap m, int pass)
         __builtin_amdgcn_wave_barrier();
     }
     __syncthreads();
-    // per digit (one thread per digit): wave prefixes, tile count (published at once), digit
-    // start in the tile, digit start in the output
-    uint32_t *status_d = fd.sort_status + (size_t)pass * fd.sort_tiles * SORT_BINS + tid;
-    uint32_t tile_cnt, hist_excl;
+    // per digit (thread d < SORT_BINS holds digit d): wave prefixes, tile count (published at
+    // once), digit start in the tile, digit start in the output
+    static_assert(SORT_THREADS >= SORT_BINS, "one thread per digit");
+    const bool dig = tid < (uint32_t)SORT_BINS;
+    const uint32_t d = dig ? tid : 0u;
+    uint32_t *status_d = fd.sort_status + (size_t)pass * fd.sort_tiles * SORT_BINS + d;
+    uint32_t tile_cnt = 0, hist_excl;
     {
-        const uint32_t d = tid;
-        uint32_t run = 0;
+        const uint32_t gh = ctrl->sort_hist[pass * SORT_BINS + d];
+        if (dig) {
+            uint32_t run = 0;
 #pragma unroll
-        for (int ww = 0; ww < NW; ++ww) {
-            const uint32_t c = s_wcnt[ww][d];
-            s_wcnt[ww][d] = run;
-            run += c;
+            for (int ww = 0; ww < NW; ++ww) {
+                const uint32_t c = s_wcnt[ww][d];
+                s_wcnt[ww][d] = run;
+                run += c;
+            }
+            tile_cnt = run;
+            lookback32_publish(status_d, SORT_BINS, tile, tile_cnt);
         }
-        tile_cnt = run;
-        lookback32_publish(status_d, SORT_BINS, tile, tile_cnt);
-        hist_excl = block_excl_scan<SORT_THREADS>(ctrl->sort_hist[pass * SORT_BINS + d], s_tmp, nullptr);
-        s_lstart[d] = block_excl_scan<SORT_THREADS>(tile_cnt, s_tmp, nullptr);
+        hist_excl = block_excl_scan<SORT_THREADS>(dig ? gh : 0u, s_tmp, nullptr);
+        const uint32_t ls = block_excl_scan<SORT_THREADS>(tile_cnt, s_tmp, nullptr);
+        if (dig) s_lstart[d] = ls;
     }
     __syncthreads();
     // keys to LDS in tile-local digit order: the keys leave the registers before the look-back,
@@ -599,7 +605,7 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_pass(TileMap m, int pass)
         s_keys[q] = key[j];
         s_vals[q] = val[j];
     }
-    s_gbase[tid] = hist_excl + lookback32_resolve<WIN>(status_d, SORT_BINS, tile, tile_cnt, ctrl);
+    if (dig) s_gbase[d] = hist_excl + lookback32_resolve<WIN>(status_d, SORT_BINS, tile, tile_cnt, ctrl);
     __syncthreads();
     const uint32_t nvalid = min((uint32_t)TILE, n - base);
     for (uint32_t q = tid; q < nvalid; q += SORT_THREADS) {
