@@ -61,8 +61,8 @@ constexpr uint32_t PHASE_PRELUDE = 0, PHASE_FORWARD = 32, PHASE_INVERSE = 64;  /
 // Bounding box: at most BBOX_GRID_MAX workgroups per frame, each leaving its partial minima and
 // maxima (order-preserving uints of the floats) in a slot of BBOX_SLOT words, which the
 // voxelize workgroups combine.
-constexpr int BBOX_THREADS = 256;
-constexpr int BBOX_F4 = 16;             // float4 chunks per thread and batch, loaded at once
+constexpr int BBOX_THREADS = 512;
+constexpr int BBOX_F4 = 8;              // float4 chunks per thread and batch, loaded at once
 constexpr uint32_t BBOX_CHUNKS = BBOX_THREADS * BBOX_F4;  // float4 chunks per batch
 constexpr uint32_t BBOX_GRID_MAX = 512;
 constexpr uint32_t BBOX_SLOT = 8;       // min x,y,z, max x,y,z, 2 unused

@@ -296,8 +296,9 @@ __global__ __launch_bounds__(BBOX_THREADS) void k_bbox(TileMap m)
     bool bad = false;
     for (uint64_t c = b; c < nbatch; c += G) {
         const uint64_t q0 = c * BBOX_CHUNKS + threadIdx.x;
-        // the chunk's first axis, (q0 + r * BBOX_THREADS) mod 3 = (q0 mod 3 + r) mod 3
+        // the chunk's first axis, (q0 + r * BBOX_THREADS) mod 3 = (q0 mod 3 + r * (BBOX_THREADS mod 3)) mod 3
         const uint32_t a00 = (uint32_t)(q0 % 3u);
+        constexpr uint32_t TM3 = (uint32_t)BBOX_THREADS % 3u;
         float4 v[BBOX_F4];
         // the whole batch under one branch each: a per-load condition would wait for each load
         // where its branch joins (clamped indices: every load in bounds, nq >= 1 here)
@@ -320,7 +321,7 @@ __global__ __launch_bounds__(BBOX_THREADS) void k_bbox(TileMap m)
 #pragma unroll
         for (int r = 0; r < BBOX_F4; ++r) {
             const bool ok = q0 + (uint64_t)r * BBOX_THREADS < nq;
-            const uint32_t a0 = (a00 + (uint32_t)r) % 3u;
+            const uint32_t a0 = (a00 + (uint32_t)r * TM3) % 3u;
             const float e[4] = {v[r].x, v[r].y, v[r].z, v[r].w};
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
