@@ -60,8 +60,8 @@ def alg_bytes(stage, n, nv, C):
 KERNEL_SOURCES = ("paper_2606_05650_amd/csrc/k_raht.hip", "paper_2606_05650_amd/csrc/gsc_device.h",
                   "paper_2606_05650_amd/csrc/gsc_internal.h")
 PMC_TRAFFIC = {"workload": "frame1M_J12",
-               "sources_sha256": "907512d088f879c0ee8a84dd877c68e75fa36f820404be7bdaeba7e7c45364b6",
-               "raht_fwd1": 570635085, "raht_inv1": 469119635}
+               "sources_sha256": "37c3d268be6c06ac5883fa279d235b689d5796c1ecf55392c7b7c80064c26c0a",
+               "raht_fwd1": 570300275, "raht_inv1": 469026899}
 KERNEL_NAMES = {"raht_fwd1": "k_raht_fwd1", "raht_inv1": "k_raht_inv1"}
 
 
