@@ -837,7 +837,9 @@ __global__ __launch_bounds__(OCC_THREADS) void k_occupancy(TileMap m)
         const uint32_t byte = cnt ? (s_bytes[d][(cnt - 1) >> 2] >> (8u * ((cnt - 1) & 3u))) & 0xFFu
                                   : s_carry[d];
         const uint64_t agg = ((uint64_t)cnt << 8) | byte;
-        const uint64_t pref = lookback_wave<OpSegOr>(fd.occ_status + d, J, tile, agg, ctrl);
+        // status words depth-major (depth d's words of consecutive tiles are adjacent: a round of
+        // the wave's look-back reads 64 of them in four cache lines, not one line per tile)
+        const uint64_t pref = lookback_wave<OpSegOr>(fd.occ_status + (size_t)d * fd.occ_tiles, 1, tile, agg, ctrl);
         if (lane_id() == 0) s_pref[d] = pref;
     }
     __syncthreads();
