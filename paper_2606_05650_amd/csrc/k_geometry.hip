@@ -1031,17 +1031,18 @@ __global__ __launch_bounds__(DEC_THREADS) void k_dec_expand(TileMap m)
         if (q == lc.start && P != q_level_next) bad = true;    // the level's first child
         if (q + 1 == B && P + (uint64_t)__popc(bytes[r]) != total_nodes) bad = true;
         const uint32_t p = (uint32_t)(q - lc.start);            // the parent's index in its level
+        // the byte's children, set bits only (a wave takes as many steps as its fullest byte
+        // has children, mostly one or two below the top levels, instead of eight)
         uint64_t c = P;
-        for (uint32_t i = 0; i < 8; ++i) {
-            if (bytes[r] >> i & 1u) {
-                if (c < total_nodes) {
-                    par[c] = p;
-                    cbit[c] = (uint8_t)i;
-                } else {
-                    bad = true;
-                }
-                ++c;
+        for (uint32_t bits = bytes[r]; bits; bits &= bits - 1u) {
+            const uint32_t i = (uint32_t)__ffs(bits) - 1u;
+            if (c < total_nodes) {
+                par[c] = p;
+                cbit[c] = (uint8_t)i;
+            } else {
+                bad = true;
             }
+            ++c;
         }
     }
     if (bad) set_error(ctrl, GSC_ERR_CORRUPT_STREAM);
