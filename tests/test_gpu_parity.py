@@ -38,6 +38,17 @@ def test_frame_roundtrip(n, J, seed):
     roundtrip(pos, attr, J, UNIFORM if J == 10 else GROUPED)
 
 
+def test_deep_uniform_frame_many_levels():
+    """Uniform points at depth 21 (63-bit codes): every 512-entry tile leaves entries open, and
+    two upper tiling levels carry entries (about 3600 and 90 at 200K), which the persistent
+    upper-level launches take in order through their phase flags."""
+    rng = np.random.default_rng(21)
+    n = 200_000
+    pos = rng.random((n, 3), dtype=np.float32)
+    attr = synth.sample_attributes(rng, n)
+    roundtrip(pos, attr, 21, GROUPED)
+
+
 @pytest.mark.parametrize("C", [1, 3, 5, 64])
 def test_channel_counts(C):
     pos, _ = synth.make_frame(3000, seed=10 + C)
