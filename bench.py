@@ -162,8 +162,13 @@ def frame_bench(args):
     occ_bytes = int(gsc.parse_header(sbuf[:gsc.HEADER_BYTES].cpu().numpy())["occ_bytes"])
 
     K = args.steps
-    timer = StageTimer(gsc, torch, K)
+    # the timed steps run without instrumentation; the per-stage times come from K more steps
+    # with the library's stage events recorded
     dt = timed(step, K, torch)
+    timer = StageTimer(gsc, torch, K)
+    for _ in range(K):
+        step()
+    torch.cuda.synchronize()
     stage_ms = timer.stop()
     # the roofline kernel is timed again with a 512 MiB write before every step, so that the
     # 256 MB last-level cache holds none of its inputs when the step starts
@@ -193,6 +198,7 @@ def frame_bench(args):
     out = base_record(args, value, ms, cfg)
     out["frames_per_s"] = round(1e3 / ms, 2)
     out["stage_ms"] = {k: round(v, 4) for k, v in stage_ms.items()}
+    out["stage_ms_note"] = "HIP events recorded by the library around each stage, in a separate pass of the same steps (the timed steps run without them)"
     out["roofline"] = roof
     sort_b, occ_b = phase_bytes(n, nv, J, occ_bytes)
     raht_b = alg_bytes("raht_fwd1", n, nv, C) + alg_bytes("raht_inv1", n, nv, C)
