@@ -517,7 +517,8 @@ __device__ inline void butterfly(float4 *s_y, uint32_t C4, uint32_t rec, float2 
 
 // Per-thread roles: in a workgroup step, thread t handles channel chunk t % C4 of row t / C4
 // (RPB rows per step); in a wave step, lane L handles chunk L % C4 of merge L / C4 (MPW
-// merges per step). A slice has C4 <= CH4_MAX = 4 chunks, so RPB >= 128 and MPW >= 16.
+// merges per step). A slice has C4 <= max(CH4_MAX, CH4_MAX1) = 8 chunks, so RPB >= 64 and
+// MPW >= 8.
 struct Roles {
     uint32_t C4, RPB, row0, c4, MPW, wq, wc4, w;
     bool act, wact;
@@ -667,10 +668,11 @@ __device__ inline int32_t quant1(float y, float step, float inv_step, double omt
 constexpr int UNROLL = 8;  // independent row loads in flight per thread
 
 // The channels of a tile are transformed in slices taken by different workgroups (see
-// slice_split): on the upper levels slices of at most CH4_MAX float4 chunks (16 channels,
-// 32 KB of LDS), on the first level at most CH4_MAX1 (measured faster there: fewer, wider row
+// slice_split): on the upper levels slices of at most CH4_MAX float4 chunks (28 channels,
+// 56 KB of LDS: two slices at 56 channels, measured slightly faster there than four of 16 or
+// eight of 8), on the first level at most CH4_MAX1 (measured faster there: fewer, wider row
 // pieces per gathered row).
-constexpr uint32_t CH4_MAX = 4;
+constexpr uint32_t CH4_MAX = 7;
 constexpr uint32_t CH4_MAX1 = 8;  // the first level: two slices of up to 32 channels (112-byte row pieces)
 static_assert((RT - 1) * CH4_MAX1 < 65536u, "packed LDS rows of a merge record (lds_rec)");
 __host__ __device__ inline uint32_t channel_passes(uint32_t C4, int k)
