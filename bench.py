@@ -60,8 +60,8 @@ def alg_bytes(stage, n, nv, C):
 KERNEL_SOURCES = ("paper_2606_05650_amd/csrc/k_raht.hip", "paper_2606_05650_amd/csrc/gsc_device.h",
                   "paper_2606_05650_amd/csrc/gsc_internal.h")
 PMC_TRAFFIC = {"workload": "frame1M_J12",
-               "sources_sha256": "37c3d268be6c06ac5883fa279d235b689d5796c1ecf55392c7b7c80064c26c0a",
-               "raht_fwd1": 570300275, "raht_inv1": 469026899}
+               "sources_sha256": "c8945a0dd993396ac54222ad1801ca6b37328b41c079b6989e24f5761c2bd7e2",
+               "raht_fwd1": 569479474, "raht_inv1": 469154647}
 KERNEL_NAMES = {"raht_fwd1": "k_raht_fwd1", "raht_inv1": "k_raht_inv1"}
 
 
