@@ -182,7 +182,11 @@ int64_t orc_octree_levels(const uint64_t *leaf, int64_t nv, int J, uint64_t *nod
     for (int d = J - 1; d >= 0; --d) {
         int64_t m = sizes[d + 1];
         uint64_t *nxt = (uint64_t *)malloc((size_t)(m > 0 ? m : 1) * sizeof(uint64_t));
-        if (!nxt) return -2;
+        if (!nxt) {
+            for (int e = d + 1; e <= J; ++e) free(lv[e]);
+            free(lv);
+            return -2;
+        }
         int64_t k = 0;
         for (int64_t i = 0; i < m; ++i) {
             uint64_t par = lv[d + 1][i] >> 3; /* Parent(c) = c >> 3 */
@@ -295,7 +299,12 @@ int64_t orc_octree_decode(const uint8_t *occ, int64_t occ_bytes, const int64_t *
     uint64_t *Ld = (uint64_t *)malloc((size_t)maxm * sizeof(uint64_t));
     uint64_t *Ln = (uint64_t *)malloc((size_t)maxm * sizeof(uint64_t));
     int64_t *offs = (int64_t *)malloc((size_t)maxm * sizeof(int64_t));
-    if (!Ld || !Ln || !offs) return -2;
+    if (!Ld || !Ln || !offs) {
+        free(Ld);
+        free(Ln);
+        free(offs);
+        return -2;
+    }
     int64_t M = 1, ptr = 0, rc = 0;
     Ld[0] = 0; /* implicit root */
     for (int d = 0; d < J && rc == 0; ++d) {
@@ -367,7 +376,11 @@ int64_t orc_raht_prelude(const uint64_t *M, int64_t nv, int J, int64_t *I, int64
     const int L = 3 * J;
     int64_t *cur = (int64_t *)malloc((size_t)(nv > 0 ? nv : 1) * sizeof(int64_t));
     uint8_t *fl = (uint8_t *)malloc((size_t)(nv > 0 ? nv : 1));
-    if (!cur || !fl) return -2;
+    if (!cur || !fl) {
+        free(cur);
+        free(fl);
+        return -2;
+    }
     int64_t m = nv;
     for (int64_t k = 0; k < nv; ++k) cur[k] = k;
     int64_t w = 0, rc = 0;
@@ -421,9 +434,13 @@ static int orc_raht_apply(const uint64_t *M, int64_t nv, int J, double *Y, int C
     int64_t *W = (int64_t *)malloc((size_t)cap * sizeof(int64_t));
     uint8_t *F = (uint8_t *)malloc((size_t)cap);
     int64_t lev_off[3 * ORC_MAX_DEPTH + 1];
-    if (!I || !W || !F) return -2;
-    int64_t tot = orc_raht_prelude(M, nv, J, I, W, F, lev_off, cap);
-    if (tot < 0) return (int)tot;
+    int64_t tot = (I && W && F) ? orc_raht_prelude(M, nv, J, I, W, F, lev_off, cap) : -2;
+    if (tot < 0) {
+        free(I);
+        free(W);
+        free(F);
+        return (int)tot;
+    }
     for (int s = 0; s < L; ++s) {
         int l = inverse ? (L - s) : (s + 1);
         int64_t b0 = lev_off[l - 1], b1 = lev_off[l];
@@ -509,26 +526,35 @@ int orc_encode_frame(const float *pos, const float *attr, int64_t n, int J, int 
     uint64_t *keys = (uint64_t *)malloc(nn * sizeof(uint64_t));
     double *A = vattr ? vattr : (double *)malloc(nn * (size_t)C * sizeof(double));
     double *Yw = Y ? Y : (double *)malloc(nn * (size_t)C * sizeof(double));
-    if (!vox || !keys || !A || !Yw) return -2;
-    int rc = orc_voxelize(pos, n, J, bbox_mode, bbox_min, cell, vox);
-    if (rc) return rc;
+    int64_t nv = 0, nb = 0;
+    int rc = -2;
+    if (!vox || !keys || !A || !Yw) goto done;
+    rc = orc_voxelize(pos, n, J, bbox_mode, bbox_min, cell, vox);
+    if (rc) goto done;
     for (int64_t i = 0; i < n; ++i)
         keys[i] = orc_morton_encode(vox[i * 3], vox[i * 3 + 1], vox[i * 3 + 2], J);
-    int64_t nv = orc_sort_merge(keys, attr, n, C, leaf, A, NULL, NULL);
-    if (nv < 0) return (int)nv;
-    int64_t nb = orc_octree_encode(leaf, nv, J, level_sizes, occ, occ_cap);
-    if (nb < 0) return (int)nb;
+    nv = orc_sort_merge(keys, attr, n, C, leaf, A, NULL, NULL);
+    if (nv < 0) {
+        rc = (int)nv;
+        goto done;
+    }
+    nb = orc_octree_encode(leaf, nv, J, level_sizes, occ, occ_cap);
+    if (nb < 0) {
+        rc = (int)nb;
+        goto done;
+    }
     memcpy(Yw, A, (size_t)nv * (size_t)C * sizeof(double));
     rc = orc_raht_forward(leaf, nv, J, Yw, C);
-    if (rc) return rc;
+    if (rc) goto done;
     orc_quantize(Yw, nv, C, step, tau, Q);
     res[0] = nv;
     res[1] = nb;
+done:
     free(vox);
     free(keys);
     if (!vattr) free(A);
     if (!Y) free(Yw);
-    return 0;
+    return rc;
 }
 
 /* Whole-frame decode: octree expansion -> voxel centres -> dequantize -> inverse RAHT.        */
@@ -573,30 +599,36 @@ int orc_ste_grad(const float *pos, const float *attr, int64_t n, int J, int C, c
     uint64_t *keys = (uint64_t *)malloc((size_t)n * sizeof(uint64_t));
     int64_t *count = (int64_t *)calloc((size_t)n, sizeof(int64_t));
     double *G = (double *)malloc((size_t)n * (size_t)C * sizeof(double));
-    if (!vox || !keys || !count || !G) return -2;
-    int rc = orc_voxelize(pos, n, J, bbox_mode, bbox_min, cell, vox);
-    if (rc) return rc;
+    int64_t nv = 0;
+    size_t rows = 0;
+    double inv_nc = 0.0, dist = 0.0, rate = 0.0;
+    int rc = -2;
+    if (!vox || !keys || !count || !G) goto done;
+    rc = orc_voxelize(pos, n, J, bbox_mode, bbox_min, cell, vox);
+    if (rc) goto done;
     for (int64_t i = 0; i < n; ++i)
         keys[i] = orc_morton_encode(vox[i * 3], vox[i * 3 + 1], vox[i * 3 + 2], J);
-    int64_t nv = orc_sort_merge(keys, attr, n, C, leaf, aref, NULL, voxel_of);
-    if (nv < 0) return (int)nv;
+    nv = orc_sort_merge(keys, attr, n, C, leaf, aref, NULL, voxel_of);
+    if (nv < 0) {
+        rc = (int)nv;
+        goto done;
+    }
     for (int64_t i = 0; i < n; ++i) count[voxel_of[i]] += 1;
-    const size_t rows = (size_t)nv * (size_t)C;
+    rows = (size_t)nv * (size_t)C;
 
     /* y = T a, yhat = Q(y) step, ahat = T^T yhat */
     memcpy(yhat, aref, rows * sizeof(double));
-    if ((rc = orc_raht_forward(leaf, nv, J, yhat, C))) return rc;
+    if ((rc = orc_raht_forward(leaf, nv, J, yhat, C))) goto done;
     for (int64_t v = 0; v < nv; ++v)
         for (int c = 0; c < C; ++c) {
             const double st = (double)step[c];
             yhat[v * C + c] = (double)orc_quantize1(yhat[v * C + c], st, tau) * st;
         }
     memcpy(ahat, yhat, rows * sizeof(double));
-    if ((rc = orc_raht_inverse(leaf, nv, J, ahat, C))) return rc;
+    if ((rc = orc_raht_inverse(leaf, nv, J, ahat, C))) goto done;
 
     /* the loss */
-    const double inv_nc = 1.0 / ((double)nv * (double)C);
-    double dist = 0.0, rate = 0.0;
+    inv_nc = 1.0 / ((double)nv * (double)C);
     for (size_t k = 0; k < rows; ++k) {
         const double e = ahat[k] - aref[k];
         dist += e * e;
@@ -608,13 +640,13 @@ int orc_ste_grad(const float *pos, const float *attr, int64_t n, int J, int C, c
 
     /* g_y = T g_ahat + g_yhat, g_a = T^T g_y */
     for (size_t k = 0; k < rows; ++k) G[k] = 2.0 * inv_nc * (ahat[k] - aref[k]);
-    if ((rc = orc_raht_forward(leaf, nv, J, G, C))) return rc;
+    if ((rc = orc_raht_forward(leaf, nv, J, G, C))) goto done;
     for (size_t k = 0; k < rows; ++k) {
         const double yh = yhat[k], st = (double)step[k % (size_t)C];
         const double sg = yh > 0.0 ? 1.0 : (yh < 0.0 ? -1.0 : 0.0);
         G[k] += lambda * sg / (log(2.0) * (st + fabs(yh)));
     }
-    if ((rc = orc_raht_inverse(leaf, nv, J, G, C))) return rc;
+    if ((rc = orc_raht_inverse(leaf, nv, J, G, C))) goto done;
 
     /* back through the voxel mean */
     for (int64_t i = 0; i < n; ++i) {
@@ -622,9 +654,10 @@ int orc_ste_grad(const float *pos, const float *attr, int64_t n, int J, int C, c
         for (int c = 0; c < C; ++c) grad[i * C + c] = G[v * C + c] / (double)count[v];
     }
     res[0] = nv;
+done:
     free(vox);
     free(keys);
     free(count);
     free(G);
-    return 0;
+    return rc;
 }

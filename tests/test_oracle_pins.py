@@ -162,6 +162,55 @@ def test_voxelize_edges():
     assert vox.tolist() == [[0, 7, 4]]
 
 
+# ------------------------------------------------------------------------- voxel centres
+def test_voxel_centres_worked_example():
+    """Sec. 2.1 places a merged Gaussian at its voxel's centre. On the Sec. 2.2 example grid
+    (J = 2, the unit cube, cell 1/4) the voxel with code 33 = (1, 0, 2) has its centre at
+    (1.5, 0.5, 2.5) cells. A shifted, non-cubic origin with another cell size moves every axis
+    by its own origin."""
+    vox, pos = orc.voxel_centres(np.array([33], np.uint64), 2, np.zeros(3), 0.25)
+    assert vox.tolist() == [[1, 0, 2]]
+    assert pos.tolist() == [[0.375, 0.125, 0.625]]
+    code = brute.morton_by_bits(3, 1, 0, 3)
+    vox, pos = orc.voxel_centres(np.array([code], np.uint64), 3,
+                                 np.array([-1.0, 2.0, 0.5]), 0.5)
+    assert vox.tolist() == [[3, 1, 0]]
+    assert pos.tolist() == [[-1.0 + 1.75, 2.0 + 0.75, 0.5 + 0.25]]
+
+
+@pytest.mark.parametrize("J", [2, 9, 14, 21])
+def test_voxel_centres_exact_and_inside_their_voxel(J):
+    """Random frames: every centre equals min + (v + 1/2) cell in exact rational arithmetic,
+    rounded once (v taken from the points by the exact-rational voxelization, not from the
+    oracle's Morton decode); it lies exactly halfway between its voxel's two faces on every
+    axis; and voxelizing the centres on the same grid gives back their voxels."""
+    from fractions import Fraction
+    rng = np.random.default_rng(40 + J)
+    pos = (rng.random((400, 3)) * np.array([3.0, 1.0, 0.5]) - 1.0).astype(np.float32)
+    vox0, bmin, cell = orc.voxelize(pos, J)
+    keys = orc.morton_encode_array(vox0, J)
+    leaf = np.unique(keys)
+    vox, cen = orc.voxel_centres(leaf, J, bmin, cell)
+    byk = {int(k): i for i, k in enumerate(leaf.tolist())}
+    fc = Fraction(cell)
+    for i in range(0, 400, 3):
+        v = [brute.voxel_exact(pos[i, a], bmin[a], cell, J) for a in range(3)]
+        r = byk[brute.morton_by_bits(v[0], v[1], v[2], J)]
+        assert vox[r].tolist() == v
+        for a in range(3):
+            lo_face = Fraction(float(bmin[a])) + v[a] * fc
+            exact = lo_face + fc / 2
+            assert cen[r, a] == float(exact)
+            assert exact - lo_face == (lo_face + fc) - exact
+    back, _, _ = orc.voxelize(cen.astype(np.float64).astype(np.float32), J, bbox=(bmin, cell))
+    # the float32 rounding of a centre can only move it within its voxel's interior when the
+    # cell spans many float32 ulps; check those rows
+    span = cell / np.maximum(np.abs(cen), 1e-30) > 2.0 ** -20
+    ok = span.all(axis=1)
+    assert ok.sum() >= min(50, leaf.size)
+    assert np.array_equal(back[ok], vox[ok])
+
+
 def test_sort_merge_bruteforce():
     rng = np.random.default_rng(12)
     n, C = 400, 5
