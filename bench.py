@@ -11,7 +11,7 @@ figure of the dominant kernel (timed live with HIP events on the library's strea
 FP64 CPU oracle timed on the host on the same workload.
 
 Other workloads (--workload):
-  frame100k_J10, frame4M_J14   single frames as above (4M adds per-phase GB/s; --errors adds
+  frame100k_J10, frame4M_J14   single frames as above (every single-frame line also carries
                                the FP32-versus-FP64 coefficient error per channel group)
   seq30_J12                    the 30-frame sequence: per-frame launches, one batch, the batch
                                as a replayed HIP graph, and the graph with autotuned sort tiles
@@ -78,6 +78,32 @@ def pmc_traffic(stage, workload):
     if workload != PMC_TRAFFIC["workload"] or sources_sha256() != PMC_TRAFFIC["sources_sha256"]:
         return None
     return PMC_TRAFFIC[stage]
+
+
+def alg_bytes_roundtrip(n, nv, C, occ_bytes):
+    """Algorithmic bytes of one encode + decode: the encoder reads positions (12 B) and
+    attribute rows (4C B) of the n Gaussians and writes the stream (header, occupancy bytes,
+    padding, Nv int32 coefficient rows); the decoder reads the stream and writes Nv positions and
+    attribute rows."""
+    stream = 1024 + occ_bytes + (-(1024 + occ_bytes)) % 256 + nv * 4 * C
+    return n * (12 + 4 * C) + 2 * stream + nv * (12 + 4 * C)
+
+
+def cpu_info():
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count()
+    return {"cpu_model": model, "nproc": os.cpu_count(), "cpus_available": avail}
 
 
 def phase_bytes(n, nv, J, occ_bytes):
@@ -206,25 +232,45 @@ def frame_bench(args):
     out["phase_gbs"] = {"sort": round(sort_b / stage_ms["sort"] / 1e6, 1),
                         "occupancy": round(occ_b / stage_ms["occupancy"] / 1e6, 1),
                         "raht": round(raht_b / raht_ms / 1e6, 1)}
-    if args.errors:
-        out["coef_error"] = coefficient_errors(tp, ta, pos, attr, p, J, steps_q, nv)
+    # the whole step against the HBM peak: every input read once, every output written once
+    rt = alg_bytes_roundtrip(n, nv, C, occ_bytes)
+    roof["pipeline"] = {"alg_bytes_per_step": rt, "achieved": round(rt / dt / 1e9, 1),
+                        "unit": "GB/s", "frac": round(rt / dt / 1e9 / HBM_PEAK_GBS, 4),
+                        "ms_per_step": round(ms, 4)}
+    roof["stage_frac"] = {
+        "sort": round(sort_b / stage_ms["sort"] / 1e6 / HBM_PEAK_GBS, 4),
+        "occupancy": round(occ_b / stage_ms["occupancy"] / 1e6 / HBM_PEAK_GBS, 4),
+        "raht_fwd1": round(alg_bytes("raht_fwd1", n, nv, C) / stage_ms["raht_fwd1"] / 1e6 / HBM_PEAK_GBS, 4),
+        "raht_inv1": round(alg_bytes("raht_inv1", n, nv, C) / stage_ms["raht_inv1"] / 1e6 / HBM_PEAK_GBS, 4)}
+    ref = None
     if not args.no_cpu_baseline:
+        # the oracle as it stands, single-threaded, on the same frame: encode + decode passes
+        # until about cpu_seconds have elapsed (at least one)
         from oracle import oracle as orc
-        t0 = time.perf_counter()
-        for _ in range(args.cpu_reps):
-            ref = orc.encode_frame(pos, attr, J, steps_q, 0.5)
-            orc.decode_frame(ref["occ"], ref["level_sizes"], J, ref["Q"], steps_q,
-                             ref["bbox_min"], ref["cell"])
-        t = time.perf_counter() - t0
-        out["cpu_baseline"] = {"value": round(n * args.cpu_reps / t / 1e6, 4),
+        reps, t0 = 0, time.perf_counter()
+        while True:
+            r = orc.encode_frame(pos, attr, J, steps_q, 0.5, want_y=(reps == 0))
+            orc.decode_frame(r["occ"], r["level_sizes"], J, r["Q"], steps_q, r["bbox_min"],
+                             r["cell"])
+            if reps == 0:
+                ref = r
+            reps += 1
+            t = time.perf_counter() - t0
+            if t >= args.cpu_seconds:
+                break
+        out["cpu_baseline"] = {"value": round(n * reps / t / 1e6, 4),
                                "unit": "M Gaussians/s", "cores": 1, "kind": "oracle",
-                               "sample": f"{args.cpu_reps} encode+decode of the same {n}-Gaussian "
-                                         f"frame ({t:.1f} s, single-threaded FP64 C)"}
+                               "sample": f"{reps} encode+decode of the same {n}-Gaussian frame "
+                                         f"({t:.1f} s, single-threaded FP64 C)", **cpu_info()}
+    if not args.no_errors:
+        out["coef_error"] = coefficient_errors(tp, ta, pos, attr, p, J, steps_q, nv, ref)
     print(json.dumps(out))
 
 
-def coefficient_errors(tp, ta, pos, attr, p, J, steps_q, nv):
-    """Max over the channels of a group of max_i |y32 - y64| / max_i |y64| (and in steps)."""
+def coefficient_errors(tp, ta, pos, attr, p, J, steps_q, nv, ref=None):
+    """Max over the channels of a group of max_i |y32 - y64| / max_i |y64| (and in steps): the
+    FP32 coefficients of one more GPU encode of the frame against the oracle's FP64 ones (ref:
+    an oracle encode of the same frame with want_y, else one is run here)."""
     import numpy as np
     import torch
     from oracle import oracle as orc
@@ -233,10 +279,12 @@ def coefficient_errors(tp, ta, pos, attr, p, J, steps_q, nv):
     coef = torch.empty((tp.shape[0], C), dtype=torch.float32, device=tp.device)
     gsc.encode_frame(tp, ta, p, coef_f32=coef).check()
     y32 = coef[:nv].cpu().numpy().astype(np.float64)
-    y64 = orc.encode_frame(pos, attr, J, steps_q, 0.5, want_y=True)["Y"]
+    if ref is None:
+        ref = orc.encode_frame(pos, attr, J, steps_q, 0.5, want_y=True)
+    y64 = ref["Y"]
     err = np.abs(y32 - y64).max(axis=0)
     rel = err / np.maximum(np.abs(y64).max(axis=0), 1e-300)
-    out = {}
+    out = {"max_rel": float(rel.max()), "bar": 1e-5}
     for name, sl in synth.channel_group_slices().items():
         out[name] = {"max_rel": float(rel[sl].max()),
                      "max_abs_in_steps": float((err[sl] / steps_q[sl]).max())}
@@ -415,10 +463,12 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="frame1M_J12")
-    ap.add_argument("--cpu-reps", type=int, default=2)
+    ap.add_argument("--cpu-seconds", type=float, default=10.0,
+                    help="single frames: oracle encode+decode passes until this many seconds")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--errors", action="store_true",
-                    help="single frames: FP32-versus-FP64 coefficient error per channel group")
+    ap.add_argument("--no-errors", action="store_true",
+                    help="single frames: skip the FP32-versus-FP64 coefficient error per channel "
+                         "group (reported by default)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run plain 512 MiB device-to-device copies (the reference kernel "
                          "for scaling the FETCH_SIZE / WRITE_SIZE counters)")

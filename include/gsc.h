@@ -10,9 +10,20 @@
  *   frees memory, and never synchronizes the stream.
  * - `stream` is a hipStream_t passed as void* (NULL = the null stream). Every call only
  *   enqueues work on that stream and returns; results are valid once the stream has been
- *   synchronized. Calls are re-entrant as long as concurrent calls use distinct workspaces.
- * - Argument errors are returned synchronously as a gsc_status and nothing is enqueued.
- *   Errors found on the device (a corrupt stream, a capacity overflow) are written as a
+ *   synchronized.
+ * - Concurrency: calls on one device must not run at the same time on different streams. Three
+ *   kernels of a call (the upper RAHT levels) keep all their workgroups resident and order their
+ *   levels by waiting on one another; a concurrent call's kernels can take the slots they wait
+ *   for, and the call then fails with GSC_ERR_INTERNAL after a bounded wait. Serialize calls on a
+ *   device (one stream, or events between streams); frames coded together belong in one batch
+ *   call. The host side is thread-safe: the only process-wide state (the sort tuning table and
+ *   per-device launch limits) is guarded.
+ * - Argument errors are returned synchronously as a gsc_status and nothing is enqueued. Device
+ *   buffers of one call (or of all frames of a batch) must not overlap where either is written:
+ *   every entry point compares the byte ranges it will touch ([ptr, ptr + bytes) of each input,
+ *   output, workspace and info array, sized from the arguments) and returns GSC_ERR_INVALID_ARG
+ *   for an overlap. Read-only inputs may overlap each other.
+ * - Errors found on the device (a corrupt stream, a capacity overflow) are written as a
  *   gsc_status code to the device info word of the call (see gsc_info) and every later kernel
  *   of the same call returns without writing outputs.
  * - Integers in device buffers are little-endian. Float attributes are IEEE binary32.
@@ -62,7 +73,17 @@ typedef struct gsc_params {
     int32_t bbox_mode;
     double bbox_min[3];
     double cell;
+    uint32_t flags;          /* GSC_FLAG_* below; 0 = defaults */
+    uint32_t reserved;       /* must be 0 */
 } gsc_params;
+
+/* flags: GSC_FLAG_FP64_WEIGHTS computes every butterfly's rotation (a, b) = (sqrt(w0/(w0+w1)),
+ * sqrt(w1/(w0+w1))) of Eq. 1 in FP64 and rounds it once to FP32 (default: FP32 division and
+ * square root, within about one FP32 ulp of the same value; the butterflies themselves are FP32
+ * either way). The flag is recorded in the stream header and the decoder follows it. Weights
+ * are integer leaf counts, exact in FP32 up to 2^24 voxels. */
+#define GSC_FLAG_FP64_WEIGHTS 0x1u
+#define GSC_FLAGS_KNOWN 0x1u
 
 /* Layout of the encoded stream (the first GSC_HEADER_BYTES of every stream).
  * Byte layout: [header][occupancy bytes: levels 0..J-1, each in Morton order, one byte per
@@ -77,7 +98,7 @@ typedef struct gsc_header {
     uint32_t n_vox;          /* occupied voxels Nv = |L_J|                     */
     uint32_t level_sizes[22];/* |L_0| .. |L_J| (Alg. 1 step 3), rest zero      */
     uint32_t error;          /* 0, or the gsc_status the encoder failed with   */
-    uint32_t reserved0;
+    uint32_t flags;          /* gsc_params.flags of the encoder                */
     double bbox_min[3];      /* voxel grid origin                              */
     double cell;             /* voxel edge length                              */
     float quant_step[64];    /* per-channel steps, C used                      */
@@ -114,13 +135,19 @@ gsc_status gsc_stream_capacity(int64_t n_max, int32_t J, int32_t C, size_t *byte
  *   d_info   device int32[GSC_INFO_WORDS] written with the device status and sizes.
  *   d_coef_f32 optional [n][C] float: the unquantized coefficients (rows 0..Nv-1), or NULL.
  *   d_leaf_codes optional [n] uint64: the sorted voxel Morton codes L_J, or NULL.
+ *   d_perm optional [n] uint32: the stable sorted order of the Gaussians by Morton code
+ *     (Alg. 1 step 1; equal codes keep their input order): d_perm[k] is the input row of the
+ *     k-th Gaussian in sorted order, or NULL.
+ *   d_voxel_of optional [n] uint32: the voxel (row of the decoded frame, 0..Nv-1) each input
+ *     Gaussian was merged into, or NULL.
  * Positions must be finite. n may be 0 (an empty stream). Duplicates (Gaussians in one
  * voxel) are replaced by one voxel whose attributes are their mean (Sec. 2.1).
  * ---------------------------------------------------------------------------------------- */
 gsc_status gsc_encode_frame(const float *d_pos, const float *d_attr, int64_t n,
                             const gsc_params *params, void *d_stream, size_t stream_cap,
                             void *d_ws, size_t ws_bytes, int32_t *d_info, float *d_coef_f32,
-                            uint64_t *d_leaf_codes, void *stream);
+                            uint64_t *d_leaf_codes, uint32_t *d_perm, uint32_t *d_voxel_of,
+                            void *stream);
 
 /* ------------------------------------------------------------------------------------------
  * gsc_decode_frame -- decode one stream (Sec. 2.3 and Alg. 2-3 octree expansion and Morton

@@ -48,6 +48,12 @@ uint64_t orc_morton_encode(uint32_t x, uint32_t y, uint32_t z, int J)
     return m;
 }
 
+/* The code of every row of vox[n][3] (the same interleave, applied row by row). */
+void orc_morton_encode_n(const uint32_t *vox, int64_t n, int J, uint64_t *out)
+{
+    for (int64_t i = 0; i < n; ++i) out[i] = orc_morton_encode(vox[3 * i], vox[3 * i + 1], vox[3 * i + 2], J);
+}
+
 /* Inverse of the interleave: every third bit, starting at bit 0 for x, 1 for y, 2 for z. */
 void orc_morton_decode(uint64_t m, int J, uint32_t *xyz)
 {

@@ -39,6 +39,8 @@ def lib():
                                        ctypes.c_uint64, ctypes.c_double, ctypes.c_void_p)
         L.orc_morton_encode.restype = u64
         L.orc_morton_encode.argtypes = [u32, u32, u32, i32]
+        L.orc_morton_encode_n.restype = None
+        L.orc_morton_encode_n.argtypes = [vp, i64, i32, vp]
         L.orc_morton_decode.restype = None
         L.orc_morton_decode.argtypes = [u64, i32, vp]
         L.orc_voxelize.restype = i32
@@ -107,8 +109,18 @@ def morton_decode(code, J):
 
 def morton_encode_array(vox, J):
     vox = _c(vox, np.uint32).reshape(-1, 3)
-    f = lib().orc_morton_encode
-    return np.array([f(int(a), int(b), int(c), int(J)) for a, b, c in vox], dtype=np.uint64)
+    out = np.zeros(vox.shape[0], dtype=np.uint64)
+    lib().orc_morton_encode_n(_p(vox), vox.shape[0], int(J), _p(out))
+    return out
+
+
+def sort_order(pos, J, bbox=None):
+    """The stable sorted order of the Gaussians by Morton code and each one's voxel:
+    (perm int64[n], voxel_of int64[n]) (voxelize, Morton, then sort_merge)."""
+    vox, _, _ = voxelize(pos, J, bbox)
+    keys = morton_encode_array(vox, J)
+    _, _, perm, vof = sort_merge(keys)
+    return perm, vof
 
 
 def voxelize(pos, J, bbox=None):

@@ -3,6 +3,7 @@
 #include <math.h>
 #include <string.h>
 
+#include <algorithm>
 #include <atomic>
 
 #include "gsc_internal.h"
@@ -33,6 +34,7 @@ gsc_status check_params(const gsc_params *p)
         if (!(p->quant_step[c] > 0.0f) || !isfinite(p->quant_step[c])) return GSC_ERR_INVALID_ARG;
     if (!(p->tau >= 0.0f && p->tau < 1.0f)) return GSC_ERR_INVALID_ARG;
     if (p->bbox_mode != 0 && p->bbox_mode != 1) return GSC_ERR_INVALID_ARG;
+    if ((p->flags & ~GSC_FLAGS_KNOWN) != 0 || p->reserved != 0) return GSC_ERR_INVALID_ARG;
     if (p->bbox_mode == 1) {
         if (!(p->cell > 0.0) || !isfinite(p->cell)) return GSC_ERR_INVALID_ARG;
         for (int a = 0; a < 3; ++a)
@@ -42,6 +44,46 @@ gsc_status check_params(const gsc_params *p)
 }
 
 constexpr int64_t N_LIMIT = (1ll << 30) - 1;  // sort status words hold 30-bit counts
+
+// Device byte ranges one call touches, checked for overlaps before anything is enqueued: two
+// ranges may share bytes only when neither is written. Sorted by start and swept once, keeping
+// the furthest end of any range and of any written range seen so far.
+struct Span {
+    uintptr_t p;
+    uint64_t n;
+    bool w;
+};
+struct Spans {
+    static constexpr int CAP = GSC_MAX_BATCH * 12;
+    Span s[CAP];
+    int k = 0;
+    bool full = false;
+    void add(const void *p, uint64_t n, bool w)
+    {
+        if (!p || n == 0) return;
+        if (k == CAP) {
+            full = true;
+            return;
+        }
+        s[k++] = Span{(uintptr_t)p, n, w};
+    }
+    void rd(const void *p, uint64_t n) { add(p, n, false); }
+    void wr(const void *p, uint64_t n) { add(p, n, true); }
+    bool disjoint()
+    {
+        if (full) return false;
+        std::sort(s, s + k, [](const Span &a, const Span &b) { return a.p < b.p; });
+        uint64_t end_any = 0, end_w = 0;
+        for (int i = 0; i < k; ++i) {
+            const uint64_t b = (uint64_t)s[i].p, e = b + s[i].n;
+            if (e < b) return false;  // wraps around the address space
+            if (b < end_w || (s[i].w && b < end_any)) return false;
+            end_any = std::max(end_any, e);
+            if (s[i].w) end_w = std::max(end_w, e);
+        }
+        return true;
+    }
+};
 
 uint64_t stream_capacity(int64_t n, int J, int C)
 {
@@ -148,6 +190,7 @@ SetupArgs make_proto(uint32_t J, uint32_t C, uint32_t mode, const gsc_params *p)
     a.C = C;
     a.mode = mode;
     if (p) {
+        a.flags = p->flags;
         a.bbox_mode = (uint32_t)p->bbox_mode;
         a.tau = p->tau;
         for (int i = 0; i < 3; ++i) a.bbox_min[i] = p->bbox_min[i];
@@ -414,7 +457,19 @@ gsc_status prepare_encode_batch(const gsc_frame_desc *frames, int32_t F, const g
         a.ws = static_cast<uint8_t *>(d.d_ws);
         a.info = d.d_info;
     }
-    return GSC_OK;
+    static thread_local Spans sp;
+    sp.k = 0;
+    sp.full = false;
+    const uint64_t row = (uint64_t)params->C * 4;
+    for (int f = 0; f < F; ++f) {
+        const gsc_frame_desc &d = frames[f];
+        sp.rd(d.d_pos, (uint64_t)d.n * 12);
+        sp.rd(d.d_attr, (uint64_t)d.n * row);
+        sp.wr(d.d_stream, stream_capacity(d.n, params->J, params->C));
+        sp.wr(d.d_ws, fr[f].L.total);
+        sp.wr(d.d_info, GSC_INFO_WORDS * 4);
+    }
+    return sp.disjoint() ? GSC_OK : GSC_ERR_INVALID_ARG;
 }
 }  // namespace
 
@@ -490,7 +545,8 @@ gsc_status gsc_tune_get(int32_t J, int64_t n, int32_t *variant)
 gsc_status gsc_encode_frame(const float *d_pos, const float *d_attr, int64_t n,
                             const gsc_params *params, void *d_stream, size_t stream_cap,
                             void *d_ws, size_t ws_bytes, int32_t *d_info, float *d_coef_f32,
-                            uint64_t *d_leaf_codes, void *stream)
+                            uint64_t *d_leaf_codes, uint32_t *d_perm, uint32_t *d_voxel_of,
+                            void *stream)
 {
     gsc_status st = check_params(params);
     if (st != GSC_OK) return st;
@@ -501,6 +557,20 @@ gsc_status gsc_encode_frame(const float *d_pos, const float *d_attr, int64_t n,
     if (!layout_for(n, params->J, params->C, &fr.L)) return GSC_ERR_INVALID_ARG;
     if (ws_bytes < fr.L.total) return GSC_ERR_WORKSPACE;
     if (stream_cap < stream_capacity(n, params->J, params->C)) return GSC_ERR_CAPACITY;
+    {
+        Spans sp;
+        const uint64_t rows = (uint64_t)n * params->C * 4;
+        sp.rd(d_pos, (uint64_t)n * 12);
+        sp.rd(d_attr, rows);
+        sp.wr(d_stream, stream_capacity(n, params->J, params->C));
+        sp.wr(d_ws, fr.L.total);
+        sp.wr(d_info, GSC_INFO_WORDS * 4);
+        sp.wr(d_coef_f32, rows);
+        sp.wr(d_leaf_codes, (uint64_t)n * 8);
+        sp.wr(d_perm, (uint64_t)n * 4);
+        sp.wr(d_voxel_of, (uint64_t)n * 4);
+        if (!sp.disjoint()) return GSC_ERR_INVALID_ARG;
+    }
     memset(&fr.a, 0, sizeof(fr.a));
     fr.a.n = (uint32_t)n;
     fr.a.pos = d_pos;
@@ -511,6 +581,8 @@ gsc_status gsc_encode_frame(const float *d_pos, const float *d_attr, int64_t n,
     fr.a.info = d_info;
     fr.a.coef_f32 = d_coef_f32;
     fr.a.codes_out = d_leaf_codes;
+    fr.a.perm_out = d_perm;
+    fr.a.voxel_of_out = d_voxel_of;
     return encode_frames(&fr, 1, params, static_cast<hipStream_t>(stream));
 }
 
@@ -538,6 +610,18 @@ gsc_status gsc_decode_batch(const gsc_stream_desc *streams, int32_t F, int32_t J
         a.pos_out = d.d_pos_out;
         a.attr_out = d.d_attr_out;
     }
+    static thread_local Spans sp;
+    sp.k = 0;
+    sp.full = false;
+    for (int f = 0; f < F; ++f) {
+        const gsc_stream_desc &d = streams[f];
+        sp.rd(d.d_stream, d.stream_bytes);
+        sp.wr(d.d_pos_out, (uint64_t)d.n_cap * 12);
+        sp.wr(d.d_attr_out, (uint64_t)d.n_cap * C * 4);
+        sp.wr(d.d_ws, fr[f].L.total);
+        sp.wr(d.d_info, GSC_INFO_WORDS * 4);
+    }
+    if (!sp.disjoint()) return GSC_ERR_INVALID_ARG;
     return decode_frames(fr, F, J, C, static_cast<hipStream_t>(stream));
 }
 
@@ -553,6 +637,17 @@ gsc_status gsc_decode_frame(const void *d_stream, size_t stream_bytes, int32_t J
     Frame fr;
     if (!layout_for(n_cap, J, C, &fr.L)) return GSC_ERR_INVALID_ARG;
     if (ws_bytes < fr.L.total) return GSC_ERR_WORKSPACE;
+    {
+        Spans sp;
+        sp.rd(d_stream, stream_bytes);
+        sp.wr(d_pos_out, (uint64_t)n_cap * 12);
+        sp.wr(d_vox_out, (uint64_t)n_cap * 12);
+        sp.wr(d_attr_out, (uint64_t)n_cap * C * 4);
+        sp.wr(d_leaf_codes, (uint64_t)n_cap * 8);
+        sp.wr(d_ws, fr.L.total);
+        sp.wr(d_info, GSC_INFO_WORDS * 4);
+        if (!sp.disjoint()) return GSC_ERR_INVALID_ARG;
+    }
     memset(&fr.a, 0, sizeof(fr.a));
     fr.a.n = (uint32_t)n_cap;
     fr.a.in_stream = static_cast<const uint8_t *>(d_stream);
@@ -579,6 +674,15 @@ static gsc_status raht_f32(const uint64_t *d_codes, int64_t nv, int32_t J, int32
     Frame fr;
     if (!layout_for(nv, J, C, &fr.L)) return GSC_ERR_INVALID_ARG;
     if (ws_bytes < fr.L.total) return GSC_ERR_WORKSPACE;
+    {
+        Spans sp;
+        sp.rd(d_codes, (uint64_t)nv * 8);
+        sp.rd(d_in, (uint64_t)nv * C * 4);
+        sp.wr(d_out, (uint64_t)nv * C * 4);
+        sp.wr(d_ws, fr.L.total);
+        sp.wr(d_info, GSC_INFO_WORDS * 4);
+        if (!sp.disjoint()) return GSC_ERR_INVALID_ARG;
+    }
     memset(&fr.a, 0, sizeof(fr.a));
     fr.a.n = (uint32_t)nv;
     fr.a.codes_in = d_codes;
@@ -618,6 +722,20 @@ gsc_status gsc_ste_forward(const float *d_pos, const float *d_attr, int64_t n,
     if (!layout_for(n, params->J, params->C, &fr.L)) return GSC_ERR_INVALID_ARG;
     if (ws_bytes < fr.L.total) return GSC_ERR_WORKSPACE;
     if (stream_cap < stream_capacity(n, params->J, params->C)) return GSC_ERR_CAPACITY;
+    {
+        Spans sp;
+        const uint64_t rows = (uint64_t)n * params->C * 4;
+        sp.rd(d_pos, (uint64_t)n * 12);
+        sp.rd(d_attr, rows);
+        sp.wr(d_stream, stream_capacity(n, params->J, params->C));
+        sp.wr(d_ws, fr.L.total);
+        sp.wr(d_info, GSC_INFO_WORDS * 4);
+        sp.wr(d_yhat, rows);
+        sp.wr(d_ahat, rows);
+        sp.wr(d_aref, rows);
+        sp.wr(d_leaf_codes, (uint64_t)n * 8);
+        if (!sp.disjoint()) return GSC_ERR_INVALID_ARG;
+    }
     memset(&fr.a, 0, sizeof(fr.a));
     fr.a.n = (uint32_t)n;
     fr.a.pos = d_pos;
@@ -648,6 +766,17 @@ gsc_status gsc_ste_backward(int64_t n, int32_t J, int32_t C, const float *d_grad
     Frame fr;
     if (!layout_for(n, J, C, &fr.L)) return GSC_ERR_INVALID_ARG;
     if (ws_bytes < fr.L.total) return GSC_ERR_WORKSPACE;
+    {
+        // the gradient inputs hold Nv <= n rows (Nv is known on the device only): their first
+        // row is checked
+        Spans sp;
+        sp.rd(d_grad_yhat, (uint64_t)C * 4);
+        sp.rd(d_grad_ahat, (uint64_t)C * 4);
+        sp.wr(d_grad_attr, (uint64_t)n * C * 4);
+        sp.wr(d_ws, fr.L.total);
+        sp.wr(d_info, GSC_INFO_WORDS * 4);
+        if (!sp.disjoint()) return GSC_ERR_INVALID_ARG;
+    }
     memset(&fr.a, 0, sizeof(fr.a));
     fr.a.n = (uint32_t)n;
     fr.a.attr = d_grad_yhat;

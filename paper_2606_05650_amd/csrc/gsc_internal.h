@@ -147,6 +147,9 @@ struct FrameDesc {
     uint64_t stream_cap;
     float *coef_f32;         // optional unquantized coefficients / transform output rows
     uint64_t *codes_out;     // optional leaf codes
+    uint32_t *perm_out;      // optional stable sorted order of the Gaussians
+    uint32_t *voxel_of_out;  // optional voxel of every Gaussian
+    uint32_t flags;          // GSC_FLAG_* of the call (decode: taken from the stream header)
     // decode
     const uint8_t *in_stream;
     uint64_t in_bytes;
@@ -195,6 +198,8 @@ struct FrameArgs {
     int32_t *info;
     float *coef_f32;
     uint64_t *codes_out;
+    uint32_t *perm_out;
+    uint32_t *voxel_of_out;
     const uint8_t *in_stream;
     uint64_t in_bytes;
     float *pos_out;
@@ -210,6 +215,7 @@ struct SetupArgs {
     uint32_t J, C, mode, bbox_mode;
     uint32_t ste;
     uint32_t keep;       // reuse the workspace state of a previous call (no zeroing)
+    uint32_t flags;      // GSC_FLAG_* (encode)
     float tau;
     double bbox_min[3];
     double cell;

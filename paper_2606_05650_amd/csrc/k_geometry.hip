@@ -123,6 +123,9 @@ __global__ __launch_bounds__(256) void k_setup(SetupArgs a)
         fd->stream_cap = fa.stream_cap;
         fd->coef_f32 = fa.coef_f32;
         fd->codes_out = fa.codes_out;
+        fd->perm_out = fa.perm_out;
+        fd->voxel_of_out = fa.voxel_of_out;
+        if (!a.keep) fd->flags = a.flags;  // (a kept straight-through forward keeps its flags)
         fd->in_stream = fa.in_stream;
         fd->in_bytes = fa.in_bytes;
         fd->pos_out = fa.pos_out;
@@ -234,7 +237,7 @@ __global__ __launch_bounds__(64) void k_finish(TileMap m)
             h->n_in = fd.n;
             h->n_vox = nv;
             h->error = err;
-            h->reserved0 = 0;
+            h->flags = fd.flags;
             h->cell = ctrl->cell;
             h->tau = fd.tau;
             h->reserved1 = 0;
@@ -714,6 +717,21 @@ __global__ __launch_bounds__(DEDUP_THREADS) void k_dedup(TileMap m)
                 if (fd.codes_out) gp(fd.codes_out)[v] = k;
                 gp(fd.vh)[v] = base + i;
                 gp(fd.first)[v] = pv[r];
+            }
+        }
+    }
+    if (fd.perm_out || fd.voxel_of_out) {
+        // optional maps: the sorted order (sorted position -> input row) and, for every input
+        // row, its voxel = the heads up to and including its sorted position, minus one
+        GAS uint32_t *perm = gp(fd.perm_out), *vof = gp(fd.voxel_of_out);
+#pragma unroll
+        for (int r = 0; r < DEDUP_KPT; ++r) {
+            const uint32_t i = r * DEDUP_THREADS + tid;
+            const uint64_t bal = __ballot((hbits >> r) & 1u);
+            if (i < len) {
+                const uint32_t v = vbase + s_cnt[r * NW + w] + (uint32_t)__popcll(bal & (lanemask_lt() | (1ull << lane))) - 1u;
+                if (perm) perm[base + i] = pv[r];
+                if (vof && pv[r] < n) vof[pv[r]] = v;
             }
         }
     }

@@ -21,6 +21,8 @@
 // that chunk. Each wave first performs the merges of its own chunk, level by level, ordered by
 // the wave's own instruction stream; then the few merges that cross chunks run level by level
 // with workgroup barriers (the inverse runs the two phases in the opposite order).
+#include <mutex>
+
 #include "gsc_device.h"
 
 namespace gsc {
@@ -62,6 +64,28 @@ __device__ inline uint64_t uniform64(uint64_t v)
     const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
     const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
     return ((uint64_t)hi << 32) | lo;
+}
+
+// The rotation (a, b) = (sqrt(w0/(w0+w1)), sqrt(w1/(w0+w1))) of a merge of weights w0, w1
+// (Eq. 1): FP32 division and square root, or (GSC_FLAG_FP64_WEIGHTS) FP64 rounded once to FP32.
+__device__ inline float2 rotation(uint32_t w0, uint32_t w1, bool fp64)
+{
+    if (fp64) {
+        const double sum = (double)w0 + (double)w1;
+        return make_float2((float)sqrt((double)w0 / sum), (float)sqrt((double)w1 / sum));
+    }
+    const float f0 = (float)w0, f1 = (float)w1, sum = f0 + f1;
+    return make_float2(sqrtf(f0 / sum), sqrtf(f1 / sum));
+}
+
+// Whether a frame's rotations are computed in FP64: the encoder's flag, which a decoder reads
+// from the stream header.
+template <class FD>
+__device__ inline bool fp64_weights(FD &fd)
+{
+    if (fd.mode == MODE_DECODE)
+        return (cp(reinterpret_cast<const gsc_header *>(fd.in_stream))->flags & GSC_FLAG_FP64_WEIGHTS) != 0;
+    return (fd.flags & GSC_FLAG_FP64_WEIGHTS) != 0;
 }
 
 // ============================================================================ prelude
@@ -471,13 +495,12 @@ __device__ inline bool load_schedule(FD &fd, Ctrl *ctrl, int k, uint32_t tile,
     if (tid == 0) s_idx[ts.mlen] = min(vend, cap);
     __syncthreads();
     ts.nrec = s_lst[SEG_N - 1];
+    const bool fp64 = fp64_weights(fd);
     if (tid < ts.nrec) {
         const uint32_t q = tid;
         s_rec[q] = lds_rec(rec, CH4);
         const uint32_t ij = s_idx[rec & 1023u], il = s_idx[(rec >> 10) & 1023u], ir = s_idx[rec >> 20];
-        const float w0 = (float)(ij - il), w1 = (float)(ir - ij);
-        const float sum = w0 + w1;
-        s_ab[q] = make_float2(sqrtf(w0 / sum), sqrtf(w1 / sum));
+        s_ab[q] = rotation(ij - il, ir - ij, fp64);
     }
     return true;
 }
@@ -1026,7 +1049,7 @@ __device__ inline void load_sched1(CFrame *d, const Item1 &it, Sched1 &S)
 // at their next write): threads without an entry to write store into the sink slot past the end
 // of each array.
 __device__ inline void commit_sched1(const Sched1 &S, const Item1 &it, uint32_t CH4, uint32_t n,
-                                     uint32_t *s_rec, float2 *s_ab, uint32_t *s_lstw,
+                                     bool fp64, uint32_t *s_rec, float2 *s_ab, uint32_t *s_lstw,
                                      uint32_t *s_oposw, uint32_t *s_m0, unsigned long long *s_lmask)
 {
     const uint32_t tid = threadIdx.x;
@@ -1034,9 +1057,7 @@ __device__ inline void commit_sched1(const Sched1 &S, const Item1 &it, uint32_t 
     s_rec[tid] = lds_rec(S.rec, CH4);
     // (a, b) of the merge: at the first level an entry's weight is its position difference
     const uint32_t j = S.rec & 1023u, l = (S.rec >> 10) & 1023u, r = S.rec >> 20;
-    const float w0 = (float)(j - l), w1 = (float)(r - j);
-    const float sum = w0 + w1;
-    s_ab[tid] = make_float2(sqrtf(w0 / sum), sqrtf(w1 / sum));
+    s_ab[tid] = rotation(j - l, r - j, fp64);
     s_lstw[min(tid, (uint32_t)LSTART_N / 2)] = S.lst;
     s_oposw[min(tid, (uint32_t)OPEN_CAP / 2)] = S.opos;
     s_m0[tid <= it.mlen ? tid : RT + 1] = min(S.m0, n);
@@ -1136,7 +1157,7 @@ __global__ __launch_bounds__(RAHT_THREADS) __attribute__((amdgpu_waves_per_eu(PE
         __syncthreads();  // the previous item is no longer read from LDS
         // ---- the current item's schedule and rows into LDS, the next item's first rows; on
         // every path, whether or not the item is ok (see commit_sched1)
-        commit_sched1(S, it0, CH4, n, s_rec, s_ab, s_lstw, s_oposw, s_m0, s_lmask);
+        commit_sched1(S, it0, CH4, n, fp64_weights(*d), s_rec, s_ab, s_lstw, s_oposw, s_m0, s_lmask);
         const uint32_t sink = RT * CH4;
 #pragma unroll
         for (int u = 0; u < NR1; ++u) {
@@ -1325,7 +1346,7 @@ __global__ __launch_bounds__(RAHT_THREADS) __attribute__((amdgpu_waves_per_eu(PE
         __syncthreads();  // the previous item is no longer read from LDS; s_st is written
         // ---- the current item's schedule and coefficient rows into LDS (branch-free, see
         // commit_sched1)
-        commit_sched1(S, it0, CH4, d->n, s_rec, s_ab, s_lstw, s_oposw, s_m0, s_lmask);
+        commit_sched1(S, it0, CH4, d->n, fp64_weights(*d), s_rec, s_ab, s_lstw, s_oposw, s_m0, s_lmask);
         {
             float st[4] = {1.f, 1.f, 1.f, 1.f};
             if (decode)
@@ -1472,18 +1493,31 @@ __global__ __launch_bounds__(RAHT_THREADS) void k_raht_inv_upper(TileMap m, int 
 // are masked off by address rather than by branch.
 size_t raht_lds_bytes(int C4, int k) { return ((size_t)RT * pass_chunks((uint32_t)C4, k) + 1) * sizeof(float4); }
 
+// Launch limits of the current device, queried once per device and kept in a table that every
+// host thread may read and fill (guarded by one mutex).
+constexpr int MAX_DEVICES = 64;
+static std::mutex g_limits_mu;
+static int g_cus[MAX_DEVICES];  // compute units per device, 0 = not queried yet
+
+static int current_device()
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAX_DEVICES) dev = 0;
+    return dev;
+}
+
 // Workgroups of a persistent first-level launch over `items` items: at most PERSIST_PER_CU per
 // CU, a multiple of 8 NP, and as few as give every workgroup the same number of items, up to one.
 static uint32_t cu_count()
 {
-    static int cus = 0;
-    if (cus == 0) {
-        int dev = 0, v = 0;
-        if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v <= 0)
-            v = 256;
-        cus = v;
+    const int dev = current_device();
+    std::lock_guard<std::mutex> lock(g_limits_mu);
+    if (g_cus[dev] == 0) {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v <= 0) v = 256;
+        g_cus[dev] = v;
     }
-    return (uint32_t)cus;
+    return (uint32_t)g_cus[dev];
 }
 
 uint32_t persist_grid(uint32_t items, int C4)
@@ -1528,15 +1562,19 @@ hipError_t launch_raht_inv(const TileMap &m, int k, const RahtCfg &cfg, hipStrea
 // items. Cached per (kernel, dynamic LDS).
 static uint32_t resident_grid(const void *kern, int threads, size_t lds, uint32_t items_max)
 {
-    struct Entry { const void *kern; size_t lds; int nb; };
-    static Entry cache[32];
+    struct Entry { int dev; const void *kern; size_t lds; int nb; };
+    static Entry cache[64];
     static int used = 0;
+    const int dev = current_device();
     int nb = 0;
-    for (int i = 0; i < used; ++i)
-        if (cache[i].kern == kern && cache[i].lds == lds) nb = cache[i].nb;
-    if (nb == 0) {
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, threads, lds) != hipSuccess || nb < 1) nb = 1;
-        if (used < 32) cache[used++] = Entry{kern, lds, nb};
+    {
+        std::lock_guard<std::mutex> lock(g_limits_mu);
+        for (int i = 0; i < used; ++i)
+            if (cache[i].dev == dev && cache[i].kern == kern && cache[i].lds == lds) nb = cache[i].nb;
+        if (nb == 0) {
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, threads, lds) != hipSuccess || nb < 1) nb = 1;
+            if (used < 64) cache[used++] = Entry{dev, kern, lds, nb};
+        }
     }
     uint32_t g = min((uint32_t)nb * cu_count(), UP_GRID_MAX);
     g = min(g, items_max);

@@ -38,7 +38,11 @@ class Params(ctypes.Structure):
     _fields_ = [("J", ctypes.c_int32), ("C", ctypes.c_int32),
                 ("quant_step", ctypes.c_float * MAX_CHANNELS), ("tau", ctypes.c_float),
                 ("bbox_mode", ctypes.c_int32), ("bbox_min", ctypes.c_double * 3),
-                ("cell", ctypes.c_double)]
+                ("cell", ctypes.c_double), ("flags", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32)]
+
+
+FLAG_FP64_WEIGHTS = 0x1
 
 
 class FrameDescC(ctypes.Structure):
@@ -58,7 +62,7 @@ class StreamDescC(ctypes.Structure):
 # Byte layout of the stream header (gsc_header in include/gsc.h), little-endian.
 HEADER_DTYPE = np.dtype([
     ("magic", "<u4"), ("version", "<u4"), ("J", "<u4"), ("C", "<u4"), ("n_in", "<u4"),
-    ("n_vox", "<u4"), ("level_sizes", "<u4", (22,)), ("error", "<u4"), ("reserved0", "<u4"),
+    ("n_vox", "<u4"), ("level_sizes", "<u4", (22,)), ("error", "<u4"), ("flags", "<u4"),
     ("bbox_min", "<f8", (3,)), ("cell", "<f8"), ("quant_step", "<f4", (64,)), ("tau", "<f4"),
     ("reserved1", "<u4"), ("occ_offset", "<u8"), ("occ_bytes", "<u8"), ("coef_offset", "<u8"),
     ("coef_bytes", "<u8"), ("total_bytes", "<u8")])
@@ -80,7 +84,7 @@ def lib():
         L.gsc_stream_capacity.argtypes = [i64, i32, i32, ctypes.POINTER(sz)]
         L.gsc_encode_frame.restype = i32
         L.gsc_encode_frame.argtypes = [vp, vp, i64, ctypes.POINTER(Params), vp, sz, vp, sz, vp, vp,
-                                       vp, vp]
+                                       vp, vp, vp, vp]
         L.gsc_decode_frame.restype = i32
         L.gsc_decode_frame.argtypes = [vp, sz, i32, i32, i64, vp, vp, vp, vp, vp, sz, vp, vp]
         L.gsc_encode_batch.restype = i32
@@ -137,9 +141,10 @@ def stream_capacity(n, J, C):
     return out.value
 
 
-def make_params(J, C, steps, tau=0.5, bbox=None):
+def make_params(J, C, steps, tau=0.5, bbox=None, flags=0):
     p = Params()
     p.J, p.C = int(J), int(C)
+    p.flags = int(flags)
     steps = np.broadcast_to(np.asarray(steps, dtype=np.float32), (C,))
     for c in range(C):
         p.quant_step[c] = float(steps[c])
@@ -186,6 +191,28 @@ def assert_disjoint(ranges):
 
 def _nbytes(t):
     return t.numel() * t.element_size()
+
+
+def _check_tensor(t, name, dtype, rows=None, cols=None, numel=None):
+    """Raise unless t (if given) is a contiguous CUDA tensor of the dtype the C ABI reads or
+    writes through its pointer, with at least `rows` rows of exactly `cols` columns (or at
+    least `numel` elements)."""
+    if t is None:
+        return
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{name}: a CUDA tensor is required")
+    if t.dtype != dtype:
+        raise TypeError(f"{name}: dtype {t.dtype}, expected {dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name}: must be contiguous")
+    if rows is not None:
+        if t.dim() < 1 or t.shape[0] < rows:
+            raise ValueError(f"{name}: needs at least {rows} rows, has shape {tuple(t.shape)}")
+        if cols is not None and (t.dim() != 2 or t.shape[1] != cols):
+            raise ValueError(f"{name}: needs {cols} columns, has shape {tuple(t.shape)}")
+    if numel is not None and t.numel() < numel:
+        raise ValueError(f"{name}: needs at least {numel} elements, has {t.numel()}")
 
 
 def _dev_u8(nbytes, device):
@@ -235,12 +262,16 @@ class Workspace:
 
 
 def encode_frame(pos, attr, params, *, ws=None, stream_buf=None, info=None, coef_f32=None,
-                 leaf_codes=None, stream=None):
-    """Encode one frame. pos: [n,3] float32 cuda, attr: [n,C] float32 cuda (contiguous)."""
+                 leaf_codes=None, perm=None, voxel_of=None, stream=None):
+    """Encode one frame. pos: [n,3] float32 cuda, attr: [n,C] float32 cuda (contiguous).
+    Optional outputs: coef_f32 [n,C] float32, leaf_codes [n] int64 (uint64 codes), perm and
+    voxel_of [n] int32 (the stable sorted order and each Gaussian's voxel)."""
     torch = _torch()
     n = int(pos.shape[0])
     C = int(params.C)
     dev = pos.device
+    _check_tensor(pos, "pos", torch.float32, n, 3)
+    _check_tensor(attr, "attr", torch.float32, n, C)
     if ws is None:
         ws = Workspace(max(n, 1), params.J, C, dev)
     cap = stream_capacity(n, params.J, C)
@@ -248,9 +279,16 @@ def encode_frame(pos, attr, params, *, ws=None, stream_buf=None, info=None, coef
         stream_buf = _dev_u8(cap, dev)
     if info is None:
         info = torch.zeros(INFO_WORDS, dtype=torch.int32, device=dev)
+    _check_tensor(stream_buf, "stream_buf", torch.uint8, numel=cap)
+    _check_tensor(info, "info", torch.int32, numel=INFO_WORDS)
+    _check_tensor(coef_f32, "coef_f32", torch.float32, n, C)
+    _check_tensor(leaf_codes, "leaf_codes", torch.int64, n)
+    _check_tensor(perm, "perm", torch.int32, n)
+    _check_tensor(voxel_of, "voxel_of", torch.int32, n)
     rc = lib().gsc_encode_frame(_ptr(pos), _ptr(attr), n, ctypes.byref(params), _ptr(stream_buf),
                                 stream_buf.numel(), _ptr(ws.buf), ws.bytes, _ptr(info),
-                                _ptr(coef_f32), _ptr(leaf_codes), _stream(stream))
+                                _ptr(coef_f32), _ptr(leaf_codes), _ptr(perm), _ptr(voxel_of),
+                                _stream(stream))
     _check(rc, "gsc_encode_frame")
     return Encoded(stream_buf, info, int(params.J), C, ws)
 
@@ -291,6 +329,10 @@ def decode_frame(stream_buf, J, C, n_cap, *, stream_bytes=None, ws=None, want_vo
     if info is None:
         info = torch.zeros(INFO_WORDS, dtype=torch.int32, device=dev)
     nbytes = stream_buf.numel() if stream_bytes is None else int(stream_bytes)
+    _check_tensor(stream_buf, "stream_buf", torch.uint8, numel=nbytes)
+    _check_tensor(pos_out, "pos_out", torch.float32, n_cap, 3)
+    _check_tensor(attr_out, "attr_out", torch.float32, n_cap, C)
+    _check_tensor(info, "info", torch.int32, numel=INFO_WORDS)
     rc = lib().gsc_decode_frame(_ptr(stream_buf), nbytes, int(J), int(C), n_cap, _ptr(pos_out),
                                 _ptr(vox), _ptr(attr_out), _ptr(codes), _ptr(ws.buf), ws.bytes,
                                 _ptr(info), _stream(stream))
@@ -311,6 +353,8 @@ def _encode_descs(frames, params, workspaces):
     for f, (pos, attr) in enumerate(frames):
         n = int(pos.shape[0])
         dev = pos.device
+        _check_tensor(pos, f"frames[{f}] pos", torch.float32, n, 3)
+        _check_tensor(attr, f"frames[{f}] attr", torch.float32, n, int(params.C))
         ws = workspaces[f] if workspaces is not None else Workspace(max(n, 1), params.J, params.C,
                                                                     dev)
         cap = stream_capacity(n, params.J, params.C)
@@ -402,12 +446,16 @@ def _raht(codes, X, J, ws, out, info, stream, adjoint):
     torch = _torch()
     nv, C = int(X.shape[0]), int(X.shape[1])
     dev = X.device
+    _check_tensor(X, "input rows", torch.float32, nv, C)
+    _check_tensor(codes, "codes", torch.int64, nv)
     if ws is None:
         ws = Workspace(max(nv, 1), J, C, dev)
     if out is None:
         out = torch.empty_like(X)
     if info is None:
         info = torch.zeros(INFO_WORDS, dtype=torch.int32, device=dev)
+    _check_tensor(out, "out", torch.float32, nv, C)
+    _check_tensor(info, "info", torch.int32, numel=INFO_WORDS)
     fn = lib().gsc_raht_adjoint if adjoint else lib().gsc_raht_forward
     rc = fn(_ptr(codes), nv, int(J), C, _ptr(X), _ptr(out), _ptr(ws.buf), ws.bytes, _ptr(info),
             _stream(stream))
@@ -444,6 +492,13 @@ def ste_forward(pos, attr, params, *, ws=None, stream_buf=None, info=None, yhat=
     yhat = torch.empty(rows, dtype=torch.float32, device=dev) if yhat is None else yhat
     ahat = torch.empty(rows, dtype=torch.float32, device=dev) if ahat is None else ahat
     aref = torch.empty(rows, dtype=torch.float32, device=dev) if aref is None else aref
+    _check_tensor(pos, "pos", torch.float32, n, 3)
+    _check_tensor(attr, "attr", torch.float32, n, C)
+    _check_tensor(stream_buf, "stream_buf", torch.uint8, numel=cap)
+    _check_tensor(info, "info", torch.int32, numel=INFO_WORDS)
+    for name, t in (("yhat", yhat), ("ahat", ahat), ("aref", aref)):
+        _check_tensor(t, name, torch.float32, n, C)
+    _check_tensor(leaf_codes, "leaf_codes", torch.int64, n)
     rc = lib().gsc_ste_forward(_ptr(pos), _ptr(attr), n, ctypes.byref(params), _ptr(stream_buf),
                                stream_buf.numel(), _ptr(ws.buf), ws.bytes, _ptr(info), _ptr(yhat),
                                _ptr(ahat), _ptr(aref), _ptr(leaf_codes), _stream(stream))
@@ -460,6 +515,11 @@ def ste_backward(fwd, grad_yhat, grad_ahat, *, out=None, info=None, stream=None)
         out = torch.empty((max(fwd.n, 1), e.C), dtype=torch.float32, device=dev)
     if info is None:
         info = torch.zeros(INFO_WORDS, dtype=torch.int32, device=dev)
+    # the gradients hold one row per occupied voxel (Nv <= n, known once the forward is done)
+    _check_tensor(grad_yhat, "grad_yhat", torch.float32, 1, e.C)
+    _check_tensor(grad_ahat, "grad_ahat", torch.float32, 1, e.C)
+    _check_tensor(out, "out", torch.float32, fwd.n, e.C)
+    _check_tensor(info, "info", torch.int32, numel=INFO_WORDS)
     rc = lib().gsc_ste_backward(fwd.n, e.J, e.C, _ptr(grad_yhat), _ptr(grad_ahat), _ptr(out),
                                 _ptr(e.ws.buf), e.ws.bytes, _ptr(info), _stream(stream))
     _check(rc, "gsc_ste_backward")

@@ -26,14 +26,16 @@ def _dev():
     return torch.device("cuda:0")
 
 
-def gpu_encode(pos, attr, J, steps, tau=0.5, bbox=None):
+def gpu_encode(pos, attr, J, steps, tau=0.5, bbox=None, flags=0):
     dev = _dev()
     n, C = attr.shape
-    p = gsc.make_params(J, C, steps, tau, bbox)
+    p = gsc.make_params(J, C, steps, tau, bbox, flags=flags)
     coef = torch.full((max(n, 1), C), np.nan, dtype=torch.float32, device=dev)
     codes = torch.zeros(max(n, 1), dtype=torch.int64, device=dev)
+    perm = torch.full((max(n, 1),), -1, dtype=torch.int32, device=dev)
+    vof = torch.full((max(n, 1),), -1, dtype=torch.int32, device=dev)
     enc = gsc.encode_frame(torch.from_numpy(pos).to(dev), torch.from_numpy(attr).to(dev), p,
-                           coef_f32=coef, leaf_codes=codes)
+                           coef_f32=coef, leaf_codes=codes, perm=perm, voxel_of=vof)
     torch.cuda.synchronize()
     enc.check()
     blob = np.frombuffer(enc.to_bytes(), dtype=np.uint8)
@@ -43,19 +45,24 @@ def gpu_encode(pos, attr, J, steps, tau=0.5, bbox=None):
                 occ=blob[1024:1024 + int(h["occ_bytes"])],
                 Q=blob[int(h["coef_offset"]):int(h["total_bytes"])].view(np.int32).reshape(nv, C),
                 Y=coef[:nv].cpu().numpy().astype(np.float64),
-                codes=codes[:nv].cpu().numpy().view(np.uint64))
+                codes=codes[:nv].cpu().numpy().view(np.uint64),
+                perm=perm[:n].cpu().numpy(), voxel_of=vof[:n].cpu().numpy())
 
 
-def check_encode(g, ref, J, steps, tau, n_in):
+def check_encode(g, ref, J, steps, tau, n_in, flags=0):
     nv = ref["nv"]
     assert g["nv"] == nv
     assert np.array_equal(g["codes"], ref["leaf"]), "Morton codes differ"
+    if "perm" in ref:  # the stable sort (Alg. 1 step 1) and the Gaussian -> voxel map
+        assert np.array_equal(g["perm"].astype(np.int64), ref["perm"]), "sorted order differs"
+        assert np.array_equal(g["voxel_of"].astype(np.int64), ref["voxel_of"]), "voxel map differs"
+    assert int(g["h"]["flags"]) == flags
     assert list(g["h"]["level_sizes"][:J + 1]) == list(ref["level_sizes"])
     assert np.array_equal(g["occ"], ref["occ"]), "occupancy bytes differ"
     assert np.array_equal(g["h"]["bbox_min"], ref["bbox_min"]) and g["h"]["cell"] == ref["cell"]
     C = g["Q"].shape[1] if nv else int(g["h"]["C"])
     # every header byte but the coefficients equals the oracle's stream in the documented layout
-    packed = pack_stream(ref, J, C, steps, tau, n_in)
+    packed = pack_stream(ref, J, C, steps, tau, n_in, flags)
     co = int(g["h"]["coef_offset"])
     assert g["blob"].size == packed.size and np.array_equal(g["blob"][:co], packed[:co])
     if nv == 0:
@@ -78,13 +85,13 @@ def check_encode(g, ref, J, steps, tau, n_in):
         assert np.all(dist <= bound)
 
 
-def check_decode(g, ref, J, steps, tau, n_in):
+def check_decode(g, ref, J, steps, tau, n_in, flags=0):
     """Decodes the GPU's own stream (geometry) and the oracle's stream (geometry and
     attributes) on the GPU; compares with the oracle's decode of the oracle's stream."""
     dev = _dev()
     nv = g["nv"]
     C = int(g["h"]["C"])
-    packed = pack_stream(ref, J, C, steps, tau, n_in)
+    packed = pack_stream(ref, J, C, steps, tau, n_in, flags)
     decs = []
     for stream in (g["enc"].stream, torch.from_numpy(packed).to(dev)):
         d = gsc.decode_frame(stream, J, C, max(nv, 1), want_vox=True, want_codes=True)
@@ -108,11 +115,13 @@ def check_decode(g, ref, J, steps, tau, n_in):
     assert rel.max() <= REL_TOL, f"decoded attribute error {rel.max():.3g}"
 
 
-def roundtrip(pos, attr, J, steps, tau=0.5, bbox=None):
-    print(f"case n={pos.shape[0]} C={attr.shape[1]} J={J} tau={tau} bbox={bbox is not None}",
-          flush=True)
+def roundtrip(pos, attr, J, steps, tau=0.5, bbox=None, flags=0, sort_order=True):
+    print(f"case n={pos.shape[0]} C={attr.shape[1]} J={J} tau={tau} bbox={bbox is not None} "
+          f"flags={flags}", flush=True)
     ref = orc.encode_frame(pos, attr, J, steps, tau, bbox=bbox, want_y=True)
-    g = gpu_encode(pos, attr, J, steps, tau, bbox)
-    check_encode(g, ref, J, steps, tau, pos.shape[0])
-    check_decode(g, ref, J, steps, tau, pos.shape[0])
+    if sort_order:
+        ref["perm"], ref["voxel_of"] = orc.sort_order(pos, J, bbox)
+    g = gpu_encode(pos, attr, J, steps, tau, bbox, flags)
+    check_encode(g, ref, J, steps, tau, pos.shape[0], flags)
+    check_decode(g, ref, J, steps, tau, pos.shape[0], flags)
     return g, ref

@@ -15,7 +15,7 @@ MAGIC = 0x31435347
 VERSION = 1
 
 
-def pack_stream(ref, J, C, steps, tau, n_in):
+def pack_stream(ref, J, C, steps, tau, n_in, flags=0):
     """ref: the dict of oracle.encode_frame. Returns the stream as a uint8 array."""
     nv = int(ref["nv"])
     occ = np.asarray(ref["occ"], dtype=np.uint8)
@@ -25,6 +25,7 @@ def pack_stream(ref, J, C, steps, tau, n_in):
     h = np.zeros(1, dtype=HEADER_DTYPE)
     h["magic"], h["version"], h["J"], h["C"] = MAGIC, VERSION, J, C
     h["n_in"], h["n_vox"] = n_in, nv
+    h["flags"] = flags
     sizes = np.zeros(22, dtype=np.uint32)
     sizes[:J + 1] = ref["level_sizes"]
     h["level_sizes"] = sizes

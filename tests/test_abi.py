@@ -54,7 +54,7 @@ def _encode_rc(n=10, J=5, C=4, steps=0.1, tau=0.5, ws_bytes=None, cap=None, null
     return L.gsc_encode_frame(fake, fake, n, ctypes.byref(p) if p else None, fake,
                               cap if cap is not None else 1 << 40, None if null_ws else fake,
                               ws_bytes if ws_bytes is not None else ws_need, fake, None, None,
-                              None)
+                              None, None, None)
 
 
 def test_encode_argument_checks():
@@ -70,6 +70,7 @@ def test_encode_argument_checks():
     assert _encode_rc(ws_bytes=100) == 3
     assert _encode_rc(cap=100) == 4
     assert _encode_rc(bbox=((0, 0, 0), 0.0)) == 1
+    assert _encode_rc(flags=0x2) == 1            # an unknown flag
 
 
 def test_decode_and_transform_argument_checks():
@@ -118,7 +119,9 @@ def test_header_layout_matches_c_struct():
     assert d.fields["quant_step"][1] == 152
     assert d.fields["occ_offset"][1] == 416
     assert d.itemsize == 456 <= gsc.HEADER_BYTES
-    assert ctypes.sizeof(gsc.Params) == 304
+    assert d.fields["flags"][1] == 116
+    assert ctypes.sizeof(gsc.Params) == 312
+    assert gsc.Params.flags.offset == 304
 
 
 def test_batch_buffer_overlap_is_rejected():
@@ -127,3 +130,104 @@ def test_batch_buffer_overlap_is_rejected():
     gsc.assert_disjoint([(0x1000, 0x100), (0x1100, 0x10), (0x2000, 0x1000)])
     with pytest.raises(ValueError):
         gsc.assert_disjoint([(0x1000, 0x200), (0x1100, 0x10)])
+
+
+# ------------------------------------------------------------------ overlapping buffers
+# Fake device addresses, far apart unless a case places two of them on purpose: every call
+# below is rejected by the host-side range check before anything is enqueued.
+_B = 1 << 36
+
+
+def _addr(k, off=0):
+    return ctypes.c_void_p(_B * (k + 1) + off)
+
+
+def _encode_frame_rc(n=1000, J=8, C=4, **over):
+    L = gsc.lib()
+    p = gsc.make_params(J, C, 0.1)
+    ws = gsc.workspace_size(n, J, C)
+    cap = gsc.stream_capacity(n, J, C)
+    a = dict(pos=_addr(0), attr=_addr(1), stream=_addr(2), ws=_addr(3), info=_addr(4),
+             coef=None, codes=None, perm=None, vof=None)
+    a.update(over)
+    return L.gsc_encode_frame(a["pos"], a["attr"], n, ctypes.byref(p), a["stream"], cap, a["ws"],
+                              ws, a["info"], a["coef"], a["codes"], a["perm"], a["vof"], None)
+
+
+def test_encode_rejects_overlapping_buffers():
+    n, C = 1000, 4
+    ws = gsc.workspace_size(n, 8, C)
+    # the workspace's last byte is the stream's first
+    assert _encode_frame_rc(stream=_addr(3, ws - 1)) == 1
+    # the info words inside the stream
+    assert _encode_frame_rc(info=_addr(2, 4096)) == 1
+    # an optional output over the attribute input
+    assert _encode_frame_rc(coef=_addr(1, 64)) == 1
+    assert _encode_frame_rc(perm=_addr(5), vof=_addr(5, 4 * n - 4)) == 1
+    assert _encode_frame_rc(codes=_addr(0, 12 * n - 8)) == 1      # leaf codes over positions
+
+
+def test_decode_and_transform_reject_overlapping_buffers():
+    L = gsc.lib()
+    n, J, C = 1000, 8, 4
+    ws = gsc.workspace_size(n, J, C)
+    # decoded attributes over the stream being decoded
+    assert L.gsc_decode_frame(_addr(0), 8192, J, C, n, _addr(1), None, _addr(0, 1024), None,
+                              _addr(3), ws, _addr(4), None) == 1
+    # voxel coordinates over the positions
+    assert L.gsc_decode_frame(_addr(0), 8192, J, C, n, _addr(1), _addr(1, 12 * n - 4), _addr(2),
+                              None, _addr(3), ws, _addr(4), None) == 1
+    # transform output over the workspace
+    assert L.gsc_raht_forward(_addr(0), n, J, C, _addr(1), _addr(3, 16), _addr(3), ws, _addr(4),
+                              None) == 1
+    # transform output over the codes
+    assert L.gsc_raht_adjoint(_addr(0), n, J, C, _addr(1), _addr(0, 8 * n - 8), _addr(3), ws,
+                              _addr(4), None) == 1
+
+
+def test_batch_rejects_buffers_shared_between_frames():
+    L = gsc.lib()
+    J, C, n = 8, 4, 500
+    p = gsc.make_params(J, C, 0.1)
+    ws = gsc.workspace_size(n, J, C)
+    cap = gsc.stream_capacity(n, J, C)
+    descs = (gsc.FrameDescC * 2)()
+    for f in range(2):
+        d = descs[f]
+        d.d_pos, d.d_attr, d.n = _addr(10 * f).value, _addr(10 * f + 1).value, n
+        d.d_stream, d.stream_cap = _addr(10 * f + 2).value, cap
+        d.d_ws, d.ws_bytes, d.d_info = _addr(10 * f + 3).value, ws, _addr(10 * f + 4).value
+    descs[1].d_ws = descs[0].d_ws           # two frames on one workspace
+    assert L.gsc_encode_batch(descs, 2, ctypes.byref(p), None) == 1
+    descs[1].d_ws = _addr(13).value
+    descs[1].d_info = descs[0].d_stream + 100   # frame 1's info inside frame 0's stream
+    assert L.gsc_encode_batch(descs, 2, ctypes.byref(p), None) == 1
+    sd = (gsc.StreamDescC * 2)()
+    for f in range(2):
+        d = sd[f]
+        d.d_stream, d.stream_bytes, d.n_cap = _addr(10 * f).value, cap, n
+        d.d_pos_out, d.d_attr_out = _addr(10 * f + 1).value, _addr(10 * f + 2).value
+        d.d_ws, d.ws_bytes, d.d_info = _addr(10 * f + 3).value, ws, _addr(10 * f + 4).value
+    sd[1].d_attr_out = sd[0].d_stream + 8     # frame 1's output over frame 0's input stream
+    assert L.gsc_decode_batch(sd, 2, J, C, None) == 1
+
+
+def test_straight_through_rejects_overlapping_buffers():
+    L = gsc.lib()
+    J, C, n = 8, 4, 100
+    p = gsc.make_params(J, C, 0.1)
+    ws = gsc.workspace_size(n, J, C)
+    cap = gsc.stream_capacity(n, J, C)
+    # ahat starts inside yhat (not at the same address)
+    assert L.gsc_ste_forward(_addr(0), _addr(1), n, ctypes.byref(p), _addr(2), cap, _addr(3), ws,
+                             _addr(4), _addr(5), _addr(5, 16), None, None, None) == 1
+    # the gradient output over the workspace
+    assert L.gsc_ste_backward(n, J, C, _addr(0), _addr(1), _addr(3, ws - 4), _addr(3), ws,
+                              _addr(4), None) == 1
+
+
+def test_binding_validates_tensors():
+    torch = pytest.importorskip("torch")
+    p = gsc.make_params(8, 4, 0.1)
+    with pytest.raises(ValueError):   # host tensors are refused before any call
+        gsc.encode_frame(torch.zeros((10, 3)), torch.zeros((10, 4)), p)

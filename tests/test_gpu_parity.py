@@ -87,6 +87,28 @@ def test_frame_1M_depth12_full():
     roundtrip(pos, attr, 12, GROUPED)
 
 
+@pytest.mark.slow
+@pytest.mark.parametrize("flags", [0, gsc.FLAG_FP64_WEIGHTS])
+def test_frame_4M_depth14(flags):
+    """The 4M-Gaussian frame at depth 14 (42-bit codes): codes, the sorted order, the voxel
+    map, every occupancy byte, positions and coefficients against the oracle, with the FP32 and
+    the FP64 computation of the butterfly rotations. Prints the tiling levels used."""
+    pos, attr = synth.make_frame(4_000_000, seed=5)
+    g, ref = roundtrip(pos, attr, 14, GROUPED, flags=flags)
+    info = g["enc"].host_info()
+    scale = np.abs(ref["Y"]).max(axis=0)
+    rel = (np.abs(g["Y"] - ref["Y"]).max(axis=0) / scale).max()
+    print(f"4M/J14 flags={flags}: Nv={g['nv']} tiling levels={int(info[4])} "
+          f"max relative coefficient error {rel:.3g}", flush=True)
+    assert int(info[4]) >= 2
+
+
+def test_fp64_rotation_flag():
+    """GSC_FLAG_FP64_WEIGHTS: recorded in the header, followed by the decoder, same bars."""
+    pos, attr = synth.make_frame(30_000, seed=31)
+    roundtrip(pos, attr, 11, GROUPED, flags=gsc.FLAG_FP64_WEIGHTS)
+
+
 def test_corrupt_streams_are_rejected():
     dev = _dev()
     pos, attr = synth.make_frame(3000, seed=15)

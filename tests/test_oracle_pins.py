@@ -57,6 +57,9 @@ def test_morton_matches_bit_string(J):
         assert c == brute.morton_by_bits(x, y, z, J)
         assert c < (1 << (3 * J))
         assert orc.morton_decode(c, J) == (x, y, z)
+    vox = rng.integers(0, 1 << J, size=(300, 3), dtype=np.uint32)
+    want = [brute.morton_by_bits(int(a), int(b), int(c), J) for a, b, c in vox]
+    assert orc.morton_encode_array(vox, J).tolist() == want
 
 
 # --------------------------------------------------------------------------------- octree
