@@ -55,7 +55,9 @@ typedef enum gsc_status {
     GSC_ERR_CAPACITY = 4,       /* output buffer smaller than required                   */
     GSC_ERR_CORRUPT_STREAM = 5, /* header or occupancy bytes inconsistent (device-side)  */
     GSC_ERR_HIP = 6,            /* a HIP launch failed                                   */
-    GSC_ERR_INTERNAL = 7        /* a device-side invariant failed (a bug; please report) */
+    GSC_ERR_INTERNAL = 7,       /* a device-side invariant failed (a bug; please report) */
+    GSC_ERR_SCRATCH = 8         /* frame needs more than GSC_STATIC_SCRATCH_BYTES of
+                                   workspace (gsc_encode_frame_noalloc only)             */
 } gsc_status;
 
 /* Coding parameters of one frame.
@@ -148,6 +150,28 @@ gsc_status gsc_encode_frame(const float *d_pos, const float *d_attr, int64_t n,
                             void *d_ws, size_t ws_bytes, int32_t *d_info, float *d_coef_f32,
                             uint64_t *d_leaf_codes, uint32_t *d_perm, uint32_t *d_voxel_of,
                             void *stream);
+
+/* ------------------------------------------------------------------------------------------
+ * gsc_encode_frame_noalloc -- gsc_encode_frame without a workspace argument, for callers that
+ * cannot allocate device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc). The workspace is a static device array of GSC_STATIC_SCRATCH_BYTES
+ * that the library's code object holds on every device it runs on, from its load until the
+ * process ends; its device address is looked up once per device (hipGetSymbolAddress, on the
+ * first call made with that device current). The call allocates and frees nothing; the caller
+ * still passes every input and output exactly as for gsc_encode_frame, and the outputs are
+ * identical to that call's.
+ *   Limit: frames whose gsc_workspace_size(n, J, C) exceeds GSC_STATIC_SCRATCH_BYTES return
+ *   GSC_ERR_SCRATCH before anything is enqueued (about 530K Gaussians at J = 12, C = 56).
+ *   Concurrency: every call on a device shares that device's one array, which keeps the last
+ *   call's contents (the call clears what must start at zero itself). Calls whose work
+ *   overlaps on one device race and corrupt each other's results: order them on one stream
+ *   (or with events), and do not run this entry point at the same time as itself.
+ * ---------------------------------------------------------------------------------------- */
+#define GSC_STATIC_SCRATCH_BYTES (64u << 20)
+gsc_status gsc_encode_frame_noalloc(const float *d_pos, const float *d_attr, int64_t n,
+                                    const gsc_params *params, void *d_stream, size_t stream_cap,
+                                    int32_t *d_info, float *d_coef_f32, uint64_t *d_leaf_codes,
+                                    uint32_t *d_perm, uint32_t *d_voxel_of, void *stream);
 
 /* ------------------------------------------------------------------------------------------
  * gsc_decode_frame -- decode one stream (Sec. 2.3 and Alg. 2-3 octree expansion and Morton

@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <mutex>
 
 #include "gsc_internal.h"
 
@@ -389,6 +390,7 @@ const char *gsc_status_string(gsc_status s)
     case GSC_ERR_CORRUPT_STREAM: return "corrupt stream";
     case GSC_ERR_HIP: return "HIP launch failed";
     case GSC_ERR_INTERNAL: return "internal error";
+    case GSC_ERR_SCRATCH: return "frame too large for the static scratch";
     }
     return "unknown status";
 }
@@ -584,6 +586,58 @@ gsc_status gsc_encode_frame(const float *d_pos, const float *d_attr, int64_t n,
     fr.a.perm_out = d_perm;
     fr.a.voxel_of_out = d_voxel_of;
     return encode_frames(&fr, 1, params, static_cast<hipStream_t>(stream));
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ static scratch
+// The workspace of gsc_encode_frame_noalloc: one array per device, part of the library's code
+// object, held from the library's load on that device until the process ends. In host code
+// `scratch` only names the symbol; the kernels get the device address that
+// hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) uint8_t scratch[GSC_STATIC_SCRATCH_BYTES];
+
+namespace {
+constexpr int SCRATCH_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[SCRATCH_DEVICES];
+
+// The current device's copy of `scratch`: looked up on the first call made with that device
+// current and kept (a failed lookup is tried again by the next call). nullptr when the device
+// or the lookup fails.
+void *scratch_ptr()
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= SCRATCH_DEVICES) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) == hipSuccess) g_scratch_ptr[dev] = p;
+    }
+    return g_scratch_ptr[dev];
+}
+}  // namespace
+
+extern "C" {
+
+gsc_status gsc_encode_frame_noalloc(const float *d_pos, const float *d_attr, int64_t n,
+                                    const gsc_params *params, void *d_stream, size_t stream_cap,
+                                    int32_t *d_info, float *d_coef_f32, uint64_t *d_leaf_codes,
+                                    uint32_t *d_perm, uint32_t *d_voxel_of, void *stream)
+{
+    gsc_status st = check_params(params);
+    if (st != GSC_OK) return st;
+    if (n < 0 || n > N_LIMIT) return GSC_ERR_INVALID_ARG;
+    Layout L;
+    if (!layout_for(n, params->J, params->C, &L)) return GSC_ERR_INVALID_ARG;
+    if (L.total > GSC_STATIC_SCRATCH_BYTES) return GSC_ERR_SCRATCH;
+    void *ws = scratch_ptr();
+    if (!ws) return GSC_ERR_HIP;
+    // every region of the workspace that must start at zero is cleared by the call's setup
+    // kernel, so the contents an earlier call left do not matter
+    return gsc_encode_frame(d_pos, d_attr, n, params, d_stream, stream_cap, ws,
+                            GSC_STATIC_SCRATCH_BYTES, d_info, d_coef_f32, d_leaf_codes, d_perm,
+                            d_voxel_of, stream);
 }
 
 gsc_status gsc_decode_batch(const gsc_stream_desc *streams, int32_t F, int32_t J, int32_t C,

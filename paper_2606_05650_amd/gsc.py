@@ -22,10 +22,11 @@ MAX_CHANNELS = 64
 MAX_BATCH = 64
 HEADER_BYTES = 1024
 INFO_WORDS = 8
+STATIC_SCRATCH_BYTES = 64 << 20  # GSC_STATIC_SCRATCH_BYTES
 
 STATUS = {0: "GSC_OK", 1: "GSC_ERR_INVALID_ARG", 2: "GSC_ERR_DEPTH", 3: "GSC_ERR_WORKSPACE",
           4: "GSC_ERR_CAPACITY", 5: "GSC_ERR_CORRUPT_STREAM", 6: "GSC_ERR_HIP",
-          7: "GSC_ERR_INTERNAL"}
+          7: "GSC_ERR_INTERNAL", 8: "GSC_ERR_SCRATCH"}
 
 
 class GscError(RuntimeError):
@@ -85,6 +86,9 @@ def lib():
         L.gsc_encode_frame.restype = i32
         L.gsc_encode_frame.argtypes = [vp, vp, i64, ctypes.POINTER(Params), vp, sz, vp, sz, vp, vp,
                                        vp, vp, vp, vp]
+        L.gsc_encode_frame_noalloc.restype = i32
+        L.gsc_encode_frame_noalloc.argtypes = [vp, vp, i64, ctypes.POINTER(Params), vp, sz, vp,
+                                               vp, vp, vp, vp, vp]
         L.gsc_decode_frame.restype = i32
         L.gsc_decode_frame.argtypes = [vp, sz, i32, i32, i64, vp, vp, vp, vp, vp, sz, vp, vp]
         L.gsc_encode_batch.restype = i32
@@ -291,6 +295,36 @@ def encode_frame(pos, attr, params, *, ws=None, stream_buf=None, info=None, coef
                                 _stream(stream))
     _check(rc, "gsc_encode_frame")
     return Encoded(stream_buf, info, int(params.J), C, ws)
+
+
+def encode_frame_noalloc(pos, attr, params, *, stream_buf=None, info=None, coef_f32=None,
+                         leaf_codes=None, perm=None, voxel_of=None, stream=None):
+    """encode_frame on the library's static per-device scratch instead of a workspace (for
+    frames whose workspace fits GSC_STATIC_SCRATCH_BYTES). The outputs, when not given, are
+    allocated here; the C call itself allocates nothing."""
+    torch = _torch()
+    n = int(pos.shape[0])
+    C = int(params.C)
+    dev = pos.device
+    _check_tensor(pos, "pos", torch.float32, n, 3)
+    _check_tensor(attr, "attr", torch.float32, n, C)
+    cap = stream_capacity(n, params.J, C)
+    if stream_buf is None:
+        stream_buf = _dev_u8(cap, dev)
+    if info is None:
+        info = torch.zeros(INFO_WORDS, dtype=torch.int32, device=dev)
+    _check_tensor(stream_buf, "stream_buf", torch.uint8, numel=cap)
+    _check_tensor(info, "info", torch.int32, numel=INFO_WORDS)
+    _check_tensor(coef_f32, "coef_f32", torch.float32, n, C)
+    _check_tensor(leaf_codes, "leaf_codes", torch.int64, n)
+    _check_tensor(perm, "perm", torch.int32, n)
+    _check_tensor(voxel_of, "voxel_of", torch.int32, n)
+    rc = lib().gsc_encode_frame_noalloc(_ptr(pos), _ptr(attr), n, ctypes.byref(params),
+                                        _ptr(stream_buf), stream_buf.numel(), _ptr(info),
+                                        _ptr(coef_f32), _ptr(leaf_codes), _ptr(perm),
+                                        _ptr(voxel_of), _stream(stream))
+    _check(rc, "gsc_encode_frame_noalloc")
+    return Encoded(stream_buf, info, int(params.J), C, None)
 
 
 @dataclass

@@ -15,7 +15,7 @@ def test_library_exports_every_declared_symbol():
     assert {"gsc_encode_frame", "gsc_decode_frame", "gsc_encode_batch", "gsc_workspace_size",
             "gsc_stream_capacity", "gsc_status_string", "gsc_decode_batch", "gsc_raht_forward",
             "gsc_raht_adjoint", "gsc_ste_forward", "gsc_ste_backward",
-            "gsc_profile_events"} <= set(names)
+            "gsc_profile_events", "gsc_encode_frame_noalloc"} <= set(names)
     for name in names:
         assert hasattr(L, name), name
 
@@ -71,6 +71,29 @@ def test_encode_argument_checks():
     assert _encode_rc(cap=100) == 4
     assert _encode_rc(bbox=((0, 0, 0), 0.0)) == 1
     assert _encode_rc(flags=0x2) == 1            # an unknown flag
+
+
+def test_noalloc_encode_limits():
+    # the static-scratch encode rejects, before anything is enqueued, a frame whose workspace
+    # exceeds GSC_STATIC_SCRATCH_BYTES, and checks its other arguments like gsc_encode_frame
+    L = gsc.lib()
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced: every case fails validation first
+    J, C = 12, 56
+    lo, hi = 1, 2_000_000
+    while lo < hi:  # the largest frame that fits
+        m = (lo + hi + 1) // 2
+        lo, hi = (m, hi) if gsc.workspace_size(m, J, C) <= gsc.STATIC_SCRATCH_BYTES else (lo, m - 1)
+    assert 400_000 < lo < 600_000
+    p = gsc.make_params(J, C, 0.1)
+    args = lambda n, pp=p: (fake, fake, n, ctypes.byref(pp), fake, 1 << 40, fake, None, None,
+                            None, None, None)
+    assert L.gsc_encode_frame_noalloc(*args(lo + 1)) == 8
+    assert gsc.status_string(8) == "frame too large for the static scratch"
+    assert L.gsc_encode_frame_noalloc(*args(-1)) == 1
+    bad = gsc.make_params(J, C, 0.0)
+    assert L.gsc_encode_frame_noalloc(*args(10, bad)) == 1
+    assert L.gsc_encode_frame_noalloc(fake, fake, 10, None, fake, 1 << 40, fake, None, None,
+                                      None, None, None) == 1
 
 
 def test_decode_and_transform_argument_checks():
