@@ -33,8 +33,9 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 METRIC = "M Gaussians/s encode+decode (and frames/s at 1M), % HBM roofline vs CPU oracle"
+# (stages 6 and 8, the upper RAHT levels, run inside the launches of stages 5 and 7)
 STAGES = {"encode": 0, "decode": 1, "sort": 2, "occupancy": 3, "prelude": 4, "raht_fwd1": 5,
-          "raht_fwd_top": 6, "raht_inv1": 7, "raht_inv_top": 8, "octree_dec": 9}
+          "raht_inv1": 7, "octree_dec": 9}
 
 
 # Algorithmic bytes (each input read once, each output written once; float32/int32 rows of C
@@ -62,7 +63,7 @@ KERNEL_SOURCES = ("paper_2606_05650_amd/csrc/k_raht.hip", "paper_2606_05650_amd/
 PMC_TRAFFIC = {"workload": "frame1M_J12",
                "sources_sha256": "c8945a0dd993396ac54222ad1801ca6b37328b41c079b6989e24f5761c2bd7e2",
                "raht_fwd1": 569479474, "raht_inv1": 469154647}
-KERNEL_NAMES = {"raht_fwd1": "k_raht_fwd1", "raht_inv1": "k_raht_inv1"}
+KERNEL_NAMES = {"raht_fwd1": "k_raht_fwd", "raht_inv1": "k_raht_inv"}
 
 
 def sources_sha256():
@@ -228,7 +229,7 @@ def frame_bench(args):
     out["roofline"] = roof
     sort_b, occ_b = phase_bytes(n, nv, J, occ_bytes)
     raht_b = alg_bytes("raht_fwd1", n, nv, C) + alg_bytes("raht_inv1", n, nv, C)
-    raht_ms = sum(stage_ms[s] for s in ("raht_fwd1", "raht_fwd_top", "raht_inv1", "raht_inv_top"))
+    raht_ms = sum(stage_ms[s] for s in ("raht_fwd1", "raht_inv1"))
     out["phase_gbs"] = {"sort": round(sort_b / stage_ms["sort"] / 1e6, 1),
                         "occupancy": round(occ_b / stage_ms["occupancy"] / 1e6, 1),
                         "raht": round(raht_b / raht_ms / 1e6, 1)}

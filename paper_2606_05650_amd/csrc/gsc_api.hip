@@ -219,52 +219,40 @@ uint32_t upper_tiles(const Frame *fr, int F)
     return t;
 }
 
+// The first level's schedule (the upper levels' schedules are built by the transform launches).
 gsc_status run_prelude(const Frame *fr, int F, hipStream_t s)
 {
     StageScope sc(GSC_STAGE_PRELUDE, s);
-    const int K = max_K(fr, F);
-    {
-        TileMap m = make_map(fr, F, [](const Frame &x) { return x.L.K >= 1 ? prelude_blocks(x.L.tiles[1]) : 0u; });
-        if (m.start[F] > 0) GSC_LAUNCH(launch_prelude(m, 1, s));
-    }
-    if (K >= 2) {
-        TileMap m = make_map(fr, F, [](const Frame &) { return 1u; });
-        GSC_LAUNCH(launch_prelude_up(m, K, upper_tiles(fr, F), s));
-    }
+    TileMap m = make_map(fr, F, [](const Frame &x) { return x.L.K >= 1 ? prelude_blocks(x.L.tiles[1]) : 0u; });
+    if (m.start[F] > 0) GSC_LAUNCH(launch_prelude(m, 1, s));
     return GSC_OK;
 }
 
+// The forward transform of every tiling level of every frame, with the upper levels' schedules:
+// one persistent launch.
 gsc_status run_forward(const Frame *fr, int F, const RahtCfg &cfg, hipStream_t s)
 {
-    const int K = max_K(fr, F);
-    {
-        TileMap m = make_map(fr, F, [&cfg](const Frame &x) { return x.L.K >= 1 ? raht_blocks(x.L.tiles[1], 1, cfg.C4) : 0u; });
-        if (m.start[F] > 0) {
-            StageScope sc(GSC_STAGE_RAHT_FWD1, s);
-            GSC_LAUNCH(launch_raht_fwd(m, 1, cfg, s));
-        }
-    }
-    if (K >= 2) {
-        StageScope sc(GSC_STAGE_RAHT_FWD_TOP, s);
-        TileMap m = make_map(fr, F, [](const Frame &) { return 1u; });
-        GSC_LAUNCH(launch_raht_fwd_upper(m, K, upper_tiles(fr, F) * channel_slices_upper(cfg.C4), cfg, s));
-    }
+    TileMap m = make_map(fr, F, [&cfg](const Frame &x) { return x.L.K >= 1 ? raht_blocks(x.L.tiles[1], 1, cfg.C4) : 0u; });
+    if (m.start[F] == 0) return GSC_OK;
+    StageScope sc(GSC_STAGE_RAHT_FWD1, s);
+    GSC_LAUNCH(launch_raht_fwd(m, max_K(fr, F), cfg, s));
     return GSC_OK;
 }
 
-gsc_status run_inverse(const Frame *fr, int F, const RahtCfg &cfg, hipStream_t s)
+// The inverse: the upper levels in one launch (which first builds their schedules when `prelude`
+// is set, i.e. when no forward of this workspace has built them), then the first level.
+gsc_status run_inverse(const Frame *fr, int F, const RahtCfg &cfg, bool prelude, hipStream_t s)
 {
     const int K = max_K(fr, F);
     if (K >= 2) {
         StageScope sc(GSC_STAGE_RAHT_INV_TOP, s);
         TileMap m = make_map(fr, F, [](const Frame &) { return 1u; });
-        GSC_LAUNCH(launch_raht_inv_upper(m, K, upper_tiles(fr, F) * channel_slices_upper(cfg.C4), cfg, s));
+        GSC_LAUNCH(launch_raht_inv_up(m, K, upper_tiles(fr, F) * channel_slices_upper(cfg.C4), prelude, cfg, s));
     }
     TileMap m = make_map(fr, F, [&cfg](const Frame &x) { return raht_blocks(x.L.tiles[1], 1, cfg.C4); });
-    if (m.start[F] > 0) {
-        StageScope sc(GSC_STAGE_RAHT_INV1, s);
-        GSC_LAUNCH(launch_raht_inv(m, 1, cfg, s));
-    }
+    if (m.start[F] == 0) return GSC_OK;
+    StageScope sc(GSC_STAGE_RAHT_INV1, s);
+    GSC_LAUNCH(launch_raht_inv(m, cfg, s));
     return GSC_OK;
 }
 
@@ -345,7 +333,7 @@ gsc_status encode_frames(const Frame *fr, int F, const gsc_params *p, hipStream_
     const RahtCfg cfg = raht_cfg(fr, F, p->C, p->quant_step);
     if ((st = run_prelude(fr, F, s)) != GSC_OK) return st;
     if ((st = run_forward(fr, F, cfg, s)) != GSC_OK) return st;
-    if (ste && (st = run_inverse(fr, F, cfg, s)) != GSC_OK) return st;
+    if (ste && (st = run_inverse(fr, F, cfg, false, s)) != GSC_OK) return st;
     return run_finish(fr, F, s);
 }
 
@@ -368,7 +356,7 @@ gsc_status decode_frames(const Frame *fr, int F, int J, int C, hipStream_t s)
     }
     const RahtCfg cfg = raht_cfg(fr, F, C, nullptr);
     if ((st = run_prelude(fr, F, s)) != GSC_OK) return st;
-    if ((st = run_inverse(fr, F, cfg, s)) != GSC_OK) return st;
+    if ((st = run_inverse(fr, F, cfg, true, s)) != GSC_OK) return st;
     return run_finish(fr, F, s);
 }
 
@@ -751,7 +739,7 @@ static gsc_status raht_f32(const uint64_t *d_codes, int64_t nv, int32_t J, int32
         if ((st = run_prelude(&fr, 1, s)) != GSC_OK) return st;
         const RahtCfg cfg = raht_cfg(&fr, 1, C, nullptr);
         if (adjoint)
-            st = run_inverse(&fr, 1, cfg, s);
+            st = run_inverse(&fr, 1, cfg, true, s);
         else
             st = run_forward(&fr, 1, cfg, s);
         if (st != GSC_OK) return st;
@@ -845,7 +833,7 @@ gsc_status gsc_ste_backward(int64_t n, int32_t J, int32_t C, const float *d_grad
     if ((st = run_setup(&fr, 1, proto, s)) != GSC_OK) return st;
     if (n > 0) {
         const RahtCfg cfg = raht_cfg(&fr, 1, C, nullptr);
-        if ((st = run_inverse(&fr, 1, cfg, s)) != GSC_OK) return st;
+        if ((st = run_inverse(&fr, 1, cfg, false, s)) != GSC_OK) return st;
     }
     return run_finish(&fr, 1, s);
 }

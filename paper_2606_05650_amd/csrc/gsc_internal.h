@@ -56,7 +56,14 @@ constexpr int LSTART_N = SEG_N + 1;     // padded to an even count of u16
 // inverse) of at most UP_GRID_MAX workgroups, which order the levels through per-workgroup
 // phase flags.
 constexpr uint32_t UP_GRID_MAX = 1024;
-constexpr uint32_t PHASE_PRELUDE = 0, PHASE_FORWARD = 32, PHASE_INVERSE = 64;  // flag bases
+constexpr uint32_t PHASE_PRELUDE = 0;  // flag base of the schedule launch
+// Counters of the transform launches, in DONE_WORDS words after the flags, zeroed by every
+// call: the finished items of every tiling level (forward: DONE_FWD + k, inverse: DONE_INV + k),
+// the first-level item tickets of each XCD (TK_FWD + x, TK_INV + x), the upper items' tickets
+// of the forward (TK_UPF), and the workgroups done with the upper levels' schedules (PRE_DONE).
+constexpr uint32_t DONE_WORDS = 128, DONE_FWD = 0, DONE_INV = 32, TK_FWD = 64, TK_INV = 72, TK_UPF = 80,
+                   PRE_DONE = 81;
+static_assert(MAXK + 1 <= 32, "one completion counter per tiling level and direction");
 
 // Bounding box: at most BBOX_GRID_MAX workgroups per frame, each leaving its partial minima and
 // maxima (order-preserving uints of the floats) in a slot of BBOX_SLOT words, which the
@@ -316,7 +323,7 @@ __host__ __device__ inline bool make_layout(int64_t n, int J, int C, Layout *L)
     L->dec_cbit = off; off = align_up(off + nodes, 256);
     L->first = off; off = align_up(off + N * 4, 256);
     L->bbox_part = off; off = align_up(off + (size_t)BBOX_GRID_MAX * BBOX_SLOT * 4, 256);
-    L->lvl_flags = off; off = align_up(off + (size_t)UP_GRID_MAX * 4, 256);
+    L->lvl_flags = off; off = align_up(off + (size_t)(UP_GRID_MAX + DONE_WORDS) * 4, 256);
     for (uint32_t k = 1; k <= K; ++k) {
         const uint32_t t = L->tiles[k];
         L->s_idx[k] = off; off = align_up(off + (size_t)L->cap[k] * 4, 256);
@@ -350,15 +357,18 @@ struct RahtCfg {
     int C4;
     bool vec, pow2;
 };
-uint32_t raht_blocks(uint32_t tiles, int k, int C4);  // workgroups of a transform launch
-hipError_t launch_raht_fwd(const TileMap &m, int k, const RahtCfg &cfg, hipStream_t s);  // k == 1
-hipError_t launch_raht_inv(const TileMap &m, int k, const RahtCfg &cfg, hipStream_t s);  // k == 1
-// Upper levels 2 .. kmax in one persistent launch each (only m.F and m.fd are used);
-// items_max: the worst-case items of the largest level over the launch's frames.
-hipError_t launch_prelude_up(const TileMap &m, int kmax, uint32_t items_max, hipStream_t s);
-hipError_t launch_raht_fwd_upper(const TileMap &m, int kmax, uint32_t items_max, const RahtCfg &cfg, hipStream_t s);
-hipError_t launch_raht_inv_upper(const TileMap &m, int kmax, uint32_t items_max, const RahtCfg &cfg, hipStream_t s);
-uint32_t channel_slices_upper(int C4);  // channel slices of an upper-level tile
+uint32_t raht_blocks(uint32_t tiles, int k, int C4);  // first-level items of a frame
+uint32_t channel_slices_upper(int C4);                // channel slices of an upper-level tile
+// The forward transform of all tiling levels, with the upper levels' schedules, in one persistent
+// launch; the first-level inverse (after launch_raht_inv_up). m maps the first-level items to
+// frames; kmax is the largest tiling level over the frames.
+hipError_t launch_raht_fwd(const TileMap &m, int kmax, const RahtCfg &cfg, hipStream_t s);
+hipError_t launch_raht_inv(const TileMap &m, const RahtCfg &cfg, hipStream_t s);
+// The upper levels' inverse (2 .. kmax; only m.F and m.fd are used) in one persistent launch,
+// before launch_raht_inv; with `prelude`, the launch first builds the upper levels' schedules.
+// items_max: the worst-case items of the largest upper level over the launch's frames.
+hipError_t launch_raht_inv_up(const TileMap &m, int kmax, uint32_t items_max, bool prelude, const RahtCfg &cfg,
+                              hipStream_t s);
 hipError_t launch_finish(const TileMap &m, hipStream_t s);
 
 }  // namespace gsc

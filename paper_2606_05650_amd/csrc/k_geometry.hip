@@ -31,9 +31,10 @@ __global__ __launch_bounds__(256) void k_setup(SetupArgs a)
             z[i] = make_uint4(0, 0, 0, 0);
     }
     if (blockIdx.x != 0) return;
-    {   // the upper-level phase flags start at zero in every call, also one that keeps the state
+    {   // the upper-level phase flags and the transforms' completion counters start at zero in
+        // every call, also one that keeps the state
         uint32_t *fl = reinterpret_cast<uint32_t *>(fa.ws + s_L.lvl_flags);
-        for (uint32_t i = threadIdx.x; i < UP_GRID_MAX; i += blockDim.x) fl[i] = 0;
+        for (uint32_t i = threadIdx.x; i < UP_GRID_MAX + DONE_WORDS; i += blockDim.x) fl[i] = 0;
     }
     Ctrl *ctrl = reinterpret_cast<Ctrl *>(fa.ws);
     FrameDesc *fd = reinterpret_cast<FrameDesc *>(fa.ws + DESC_OFF);

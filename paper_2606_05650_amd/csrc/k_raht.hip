@@ -352,7 +352,7 @@ __device__ inline void prelude_tile(const TileMap &m, uint32_t f, int k, uint32_
 }
 
 // One workgroup per tile of the first level.
-constexpr int PRE_BLOCK1 = RT / PRE_EPT1, PRE_BLOCK_UP = RT / PRE_EPT_UP;
+constexpr int PRE_BLOCK1 = RT / PRE_EPT1;
 __global__ __launch_bounds__(PRE_BLOCK1) void k_prelude(TileMap m, int k)
 {
     const uint32_t f = frame_of(m, blockIdx.x);
@@ -405,26 +405,34 @@ __device__ inline uint32_t item_frame(const TileMap &m, const uint32_t *s_fs, ui
 }
 static_assert(GSC_MAX_BATCH <= WAVE, "one wave counts the frames' items");
 
-// Schedules of levels 2 .. kmax. A level's size is known only once the previous level is done,
-// so every remaining workgroup waits for the producers before it counts the next level's tiles.
-__global__ __launch_bounds__(PRE_BLOCK_UP) void k_prelude_up(TileMap m, int kmax)
+// Schedules of the upper levels 2 .. kmax (the prelude of every tile of S_k, k >= 2), by the
+// first Gp workgroups of a persistent launch (all resident). A level's size is known only once
+// the previous level is done, so the group's workgroups wait for the previous level's producers
+// (phase flags) before they count its tiles; a workgroup without a tile at a level leaves the
+// group (the later levels are no larger). A workgroup that leaves releases its writes and adds
+// itself to the group's counter, which reaches Gp once every level's schedule is written.
+__device__ inline void up_prelude_group(const TileMap &m, int kmax, uint32_t Gp, uint32_t *s_fs, GAS uint32_t *pre_done)
 {
-    __shared__ uint32_t s_fs[GSC_MAX_BATCH + 1];
     const CAS FrameDesc &fd0 = *cp(m.fd[0]);
     uint32_t *flags = fd0.lvl_flags;
     uint32_t phase = PHASE_PRELUDE;
     for (int k = 2; k <= kmax; ++k) {
         const uint32_t items = level_items(m, k, 1, s_fs);
-        if (blockIdx.x >= items) return;  // nothing here, and the later levels are no larger
-        for (uint32_t i = blockIdx.x; i < items; i += gridDim.x) {
+        if (blockIdx.x >= items) break;
+        for (uint32_t i = blockIdx.x; i < items; i += Gp) {
             const uint32_t f = item_frame(m, s_fs, i);
             prelude_tile<true, PRE_EPT_UP>(m, f, k, i - s_fs[f]);
             __syncthreads();
         }
-        if (k == kmax) return;
-        const uint32_t np = min(items, gridDim.x);  // the workgroups that took an item
+        if (k == kmax) break;
+        const uint32_t np = min(items, Gp);  // the workgroups that took an item
         level_publish(flags, ++phase);
         level_wait(flags, np, phase, fd0.ctrl);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __hip_atomic_fetch_add(pre_done, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 
@@ -454,7 +462,8 @@ __device__ inline bool load_schedule(FD &fd, Ctrl *ctrl, int k, uint32_t tile,
                                      uint16_t *s_lst, uint16_t *s_opos, uint32_t *s_idx,
                                      unsigned long long *s_lmask)
 {
-    const uint32_t nk = seq_size(fd, ctrl, k);
+    // (the size may have been written by schedule workgroups of the same launch)
+    const uint32_t nk = seq_size<true>(fd, ctrl, k);
     if (!seq_active(nk, k)) return false;
     auto &lv = fd.lv[k];
     const uint32_t s = tile * RT;
@@ -754,69 +763,235 @@ uint32_t raht_blocks(uint32_t tiles, int k, int C4)
 }
 uint32_t channel_slices_upper(int C4) { return channel_passes((uint32_t)C4, 2); }
 
-// ============================================================== upper levels, forward
-// One workgroup per (tile, channel slice) of S_k, k >= 2: the entries' partial low-passes come
-// from S_{k-1}'s open-entry rows, each entry's coefficient row goes to its voxel's row.
-// LDS of an upper-level item: the slice rows (dynamic) and the tile's schedule.
-struct UpLds {
-    uint32_t rec[RT];
-    float2 ab[RT];
-    uint16_t lst[LSTART_N];
-    uint16_t opos[OPEN_CAP];
-    uint32_t idx[RT + 1];
-    unsigned long long lmask[NCLS];
+// ================================================= hand-over between tiling levels
+// Every tiling level of a direction runs in one persistent launch, so the open entries' rows
+// pass from one level to the next between workgroups of the same launch, possibly on different
+// XCDs. They are written and read with device-coherent 64-bit accesses, which bypass the XCDs'
+// non-coherent L2 caches, so neither side needs a cache write-back or invalidation. A producer
+// waits until its stores have completed before it adds its items to its level's completion
+// counter; a consumer reads the rows only after it has seen the count it needs.
+__device__ inline void st_coh4(GAS float *p, const float4 &v)
+{
+    GAS uint64_t *q = reinterpret_cast<GAS uint64_t *>(p);
+    __hip_atomic_store(q, ((uint64_t)__float_as_uint(v.y) << 32) | __float_as_uint(v.x), __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(q + 1, ((uint64_t)__float_as_uint(v.w) << 32) | __float_as_uint(v.z), __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline float4 ld_coh4(const GAS float *p)
+{
+    const GAS uint64_t *q = reinterpret_cast<const GAS uint64_t *>(p);
+    const uint64_t a = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint64_t b = __hip_atomic_load(q + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return make_float4(__uint_as_float((uint32_t)a), __uint_as_float((uint32_t)(a >> 32)),
+                       __uint_as_float((uint32_t)b), __uint_as_float((uint32_t)(b >> 32)));
+}
+
+// Counter word w of a transform launch (DONE_FWD + k, TK_INV + x, ...), in the workspace of the
+// launch's first frame; the completion counters count a level's finished items over all frames.
+__device__ inline GAS uint32_t *ctr_word(const TileMap &m, uint32_t w)
+{
+    return gp(cp(m.fd[0])->lvl_flags) + UP_GRID_MAX + w;
+}
+__device__ inline GAS uint32_t *done_ctr(const TileMap &m, uint32_t base, int k)
+{
+    return ctr_word(m, base + (uint32_t)k);
+}
+// Adds v items once every store of the workgroup has completed (each wave waits for its own
+// stores before the barrier).
+__device__ inline void done_add(GAS uint32_t *c, uint32_t v)
+{
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (threadIdx.x == 0 && v) __hip_atomic_fetch_add(c, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline bool done_reached(const GAS uint32_t *c, uint32_t target)
+{
+    return __hip_atomic_load(c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= target;
+}
+// Waits (thread 0, then a barrier) until a level's counter reaches `target`. Every item a wait
+// depends on comes earlier in the launch's order, each workgroup takes its items in order and
+// all workgroups are resident, so the earliest unfinished item can always proceed; a spin limit
+// turns a stall into GSC_ERR_INTERNAL.
+__device__ inline void done_wait(const GAS uint32_t *c, uint32_t target, Ctrl *ctrl)
+{
+    if (threadIdx.x == 0) {
+        uint32_t spins = 0;
+        while (!done_reached(c, target)) {
+            if (++spins > SPIN_LIMIT) {
+                set_error(ctrl, GSC_ERR_INTERNAL);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+    }
+    __syncthreads();
+}
+
+// ------------------------------------------------------------ the upper items of a launch
+// Items of upper level k (k >= 2) of frame f: the tiles of S_k times the channel slices NP. The
+// sizes of levels k >= 3 are written by the schedule workgroups of the same launch, so they are
+// read with device-coherent loads (never through the scalar cache), after those workgroups are done.
+__device__ inline uint32_t up_frame_items(const TileMap &m, uint32_t f, int k, uint32_t NP)
+{
+    const CAS FrameDesc &fd = *cp(m.fd[f]);
+    if ((uint32_t)k > fd.K) return 0u;
+    const uint32_t nk = __hip_atomic_load(&fd.ctrl->lvl_n[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return (nk >= 2 && nk <= fd.lv[k].cap) ? (nk + RT - 1) / RT * NP : 0u;
+}
+static_assert(GSC_MAX_BATCH <= WAVE, "one wave counts the frames' items");
+
+// s_ucnt[k] = items of level k over the launch's frames (k = 2..kmax; s_ucnt[kmax + 1] = 0),
+// counted by wave 0. Returns their sum (after a barrier).
+__device__ inline uint32_t up_totals(const TileMap &m, int kmax, uint32_t NP, uint32_t *s_ucnt)
+{
+    if (threadIdx.x < WAVE) {
+        const uint32_t lane = lane_id();
+        for (int k = 2; k <= kmax; ++k) {
+            const uint32_t inc = wave_incl_scan(lane < m.F ? up_frame_items(m, lane, k, NP) : 0u);
+            if (lane == WAVE - 1) s_ucnt[k] = inc;
+        }
+        if (lane == 0) s_ucnt[kmax + 1 > 1 ? kmax + 1 : 1] = 0;
+    }
+    __syncthreads();
+    uint32_t u = 0;
+    for (int k = 2; k <= kmax; ++k) u += s_ucnt[k];
+    return u;
+}
+
+struct UpItem {
+    int k;
+    uint32_t f, tile, p;
+};
+// Upper item g (counted over the launch's upper items) in processing order: the levels
+// ascending (forward) or descending (inverse), each level frame by frame, the channel slices
+// of a tile adjacent. Every wave computes the same (uniform) result.
+__device__ inline UpItem up_item(const TileMap &m, int kmax, bool desc, uint32_t NP, const uint32_t *s_ucnt, uint32_t g)
+{
+    UpItem u;
+    u.k = 0;
+    u.f = u.tile = u.p = 0;
+    for (int o = 0; 2 + o <= kmax; ++o) {
+        const int k = desc ? kmax - o : 2 + o;
+        const uint32_t c = s_ucnt[k];
+        if (g < c) {
+            const uint32_t lane = lane_id();
+            const uint32_t cf = lane < m.F ? up_frame_items(m, lane, k, NP) : 0u;
+            const uint32_t inc = wave_incl_scan(cf);
+            const uint64_t b = __ballot(inc > g);
+            const uint32_t f = __builtin_amdgcn_readfirstlane((uint32_t)(__ffsll((long long)b) - 1));
+            const uint32_t before = __builtin_amdgcn_readfirstlane((uint32_t)__shfl(inc - cf, (int)f, WAVE));
+            const uint32_t local = g - before;
+            u.k = k;
+            u.f = f;
+            u.tile = local / NP;
+            u.p = local % NP;
+            return u;
+        }
+        g -= c;
+    }
+    return u;
+}
+
+// ------------------------------------------------------------------ open-entry sets
+// The open entries of a tile as a bit set over its RT positions (om[w] bit b: position 64 w + b)
+// and the number of open entries before each word (pre[w]); the open entry whose range holds
+// position j (the nearest open entry at or before j; a tile's first entry is always open) has
+// index pre[w] + popcount(om[w] & bits 0..b) - 1.
+struct OpenSet {
+    unsigned long long *om;  // NCHUNK words
+    uint32_t *pre;           // NCHUNK + 1 words
+};
+__device__ inline bool os_open(const OpenSet &s, uint32_t j) { return (s.om[j >> 6] >> (j & 63)) & 1ull; }
+__device__ inline uint32_t os_cover(const OpenSet &s, uint32_t j)
+{
+    const uint32_t w = j >> 6;
+    const unsigned long long upto = (2ull << (j & 63)) - 1ull;  // bits 0 .. j % 64
+    return s.pre[w] + (uint32_t)__popcll(s.om[w] & upto) - 1u;
+}
+// Sets the bits of open positions p (one per calling thread with `on`); om must be zero.
+__device__ inline void os_set(const OpenSet &s, uint32_t p, bool on)
+{
+    if (on) atomicOr(&s.om[p >> 6], 1ull << (p & 63));
+}
+// pre from om (wave 0, after the bits are set and a barrier; visible after the next barrier).
+__device__ inline void os_prefix(const OpenSet &s)
+{
+    if (threadIdx.x < WAVE) {
+        const uint32_t lane = lane_id();
+        const uint32_t c = lane < (uint32_t)NCHUNK ? (uint32_t)__popcll(s.om[lane]) : 0u;
+        const uint32_t inc = wave_incl_scan(c);
+        if (lane <= (uint32_t)NCHUNK) s.pre[lane] = inc - c;
+    }
+}
+
+// The inverse of a tile runs with the low-pass of every open entry taken as zero; the part of
+// the result that the low-passes carry is added afterwards. With only the low-pass L_o of open
+// entry o nonzero, every inverse butterfly hands each of its two parts sqrt(w_part / w_node) of
+// its node's value (Eq. 1 with a zero high-pass), so entry j of o's range (o up to the next
+// open entry) receives L_o sqrt(w_j / W_o), w_j being the entry's weight (leaves under it) and
+// W_o the range's. s_L holds the low-passes of opens ob .. ob + nb - 1 (this slice's chunks);
+// weight(a, b) is the number of leaves under entries a .. b - 1.
+constexpr uint32_t LCAP = 32;  // open entries whose low-passes are staged in LDS at a time
+template <class WeightFn>
+__device__ inline void add_open_share(float4 *s_y, const Roles &R, uint32_t CH4, bool live, uint32_t mlen,
+                                      const OpenSet &os, const uint16_t *s_opos, uint32_t ocnt,
+                                      const float4 *s_L, uint32_t ob, uint32_t nb, bool fp64, WeightFn weight)
+{
+    if (!live) return;
+    for (uint32_t j = R.row0; j < mlen; j += R.RPB) {
+        const uint32_t o = os_cover(os, j);
+        if (o < ob || o >= ob + nb) continue;
+        const uint32_t p0 = s_opos[o], p1 = o + 1 < ocnt ? s_opos[o + 1] : mlen;
+        const uint32_t wj = weight(j, j + 1), wo = weight(p0, p1);
+        const float fac = fp64 ? (float)sqrt((double)wj / (double)wo) : sqrtf((float)wj / (float)wo);
+        const float4 L = s_L[(o - ob) * CH4 + R.c4];
+        float4 &y = s_y[j * CH4 + R.c4];
+        y.x += fac * L.x;
+        y.y += fac * L.y;
+        y.z += fac * L.z;
+        y.w += fac * L.w;
+    }
+}
+
+// LDS arrays of an upper-level item (aliases of the first level's arrays).
+struct UpArrays {
+    uint32_t *rec;
+    float2 *ab;
+    uint16_t *lst;
+    uint16_t *opos;
+    uint32_t *idx;
+    unsigned long long *lmask;
+    OpenSet os;
+    float4 *L;  // (inverse)
 };
 
-// The schedule of an item (tile of S_k, k >= 2) into LDS; false if there is nothing to do. The
-// schedules were written by an earlier launch, so a workgroup loads its first item's schedule
-// before it waits for the previous level.
-__device__ inline bool up_schedule(const TileMap &m, uint32_t f, int k, uint32_t tile, TileSched &ts, UpLds &L)
+// The schedule of an item (tile of S_k, k >= 2) into LDS; false if there is nothing to do.
+__device__ inline bool up_schedule(const TileMap &m, uint32_t f, int k, uint32_t tile, TileSched &ts, const UpArrays &A)
 {
     const CAS FrameDesc &fd = *cp(m.fd[f]);  // (not written while the kernel runs)
     Ctrl *ctrl = fd.ctrl;
     if (load_error(ctrl)) return false;
     if ((uint32_t)k > fd.K) return false;
-    return load_schedule(fd, ctrl, k, tile, pass_chunks(fd.C4, k), ts, L.rec, L.ab, L.lst, L.opos, L.idx, L.lmask);
+    return load_schedule(fd, ctrl, k, tile, pass_chunks(fd.C4, k), ts, A.rec, A.ab, A.lst, A.opos, A.idx, A.lmask);
 }
 
-// One item (tile, channel slice p0) of S_k, k >= 2, whose schedule is in LDS.
-template <bool VEC, bool POW2>
-__device__ inline void fwd_up_item(const TileMap &m, uint32_t f, int k, uint32_t p0, const TileSched &ts,
-                                   float4 *s_y, UpLds &L)
+// The quantized (or float) coefficient rows of entries that are not open, at their voxel rows:
+// an open entry's coefficient is written by the level that completes its merge (so that every
+// row is written exactly once in the launch), except at the final level, where the open entry
+// is the sequence's first one and holds the DC.
+template <bool VEC, bool POW2, class RowOf, class YAt>
+__device__ inline void store_coefs(const CAS FrameDesc &fd, const float *s_st, const float *s_ist, const Roles &R,
+                                   uint32_t c4, uint32_t mlen, bool final_level, const OpenSet &os, RowOf row_of,
+                                   YAt y_at)
 {
-    uint32_t *s_rec = L.rec, *s_idx = L.idx;
-    float2 *s_ab = L.ab;
-    uint16_t *s_lst = L.lst, *s_opos = L.opos;
-    unsigned long long *s_lmask = L.lmask;
-    const CAS FrameDesc &fd = *cp(m.fd[f]);  // (not written while the kernel runs)
-    Ctrl *ctrl = fd.ctrl;
-    const uint32_t C = fd.C, C4 = fd.C4;
-    const uint32_t CH4 = pass_chunks(C4, k);
-    const Roles R(CH4);
-    const uint32_t mlen = (uint32_t)ts.mlen;
-    const uint32_t cb = p0 * CH4, nch = min(CH4, C4 - cb);
-    const uint32_t c4 = cb + R.c4;  // this thread's global channel chunk
-    const bool live = R.act && R.c4 < nch;
-    // ---- the entries' values of this channel slice
-    if (live) {
-        const GAS float *vsrc = gp(fd.lv[k - 1].vbuf);
-        load_slice(s_y, R, CH4, mlen, [&](uint32_t j) { return gload4(vsrc + ((size_t)(ts.s + j) * C4 + c4) * 4); });
-    }
-    __syncthreads();
-    // ---- all local merges: within wave chunks, then across chunks (levels ascending)
-    const uint64_t wmask = s_lmask[R.w], xmask = s_lmask[CROSS];
-    wave_phase(s_y, R, s_rec, s_ab, s_lst, wmask, nch, false, R.w);
-    __syncthreads();
-    cross_phase(s_y, R, s_rec, s_ab, s_lst, xmask, nch, false);
-    // ---- outputs: coefficient rows of every entry at its voxel (an open entry's row is
-    // rewritten by the level that completes its merge), open entries' partial low-passes to
-    // S_{k+1}
-    if (!live) return;
-    GAS float *coef_f32 = gp(fd.coef_f32);
+    const uint32_t C = fd.C;
+    GAS float *cf = gp(fd.coef_f32);
     if (fd.mode == MODE_ENCODE) {
+        const CAS Ctrl *ctrl = cp(fd.ctrl);
         uint64_t off = GSC_HEADER_BYTES, run = 0;
-        for (uint32_t d = 0; d < fd.J; ++d) {
-            run += ctrl->hist_D[d];
+        for (uint32_t dd = 0; dd < fd.J; ++dd) {
+            run += ctrl->hist_D[dd];
             off += run;
         }
         GAS int32_t *coef = gp(reinterpret_cast<int32_t *>(fd.stream + align_up(off, 256)));
@@ -825,122 +1000,140 @@ __device__ inline void fwd_up_item(const TileMap &m, uint32_t f, int k, uint32_t
         const bool deq = fd.ste == STE_FORWARD;  // float output: q * step instead of y
         float st[4], ist[4];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const uint32_t c = min(4 * c4 + i, C - 1);
-            st[i] = fd.step[c];
-            ist[i] = fd.inv_step[c];
+        for (int q = 0; q < 4; ++q) {
+            const uint32_t c = min(4 * c4 + q, C - 1);
+            st[q] = s_st[c];
+            ist[q] = s_ist[c];
         }
         for (uint32_t j = R.row0; j < mlen; j += R.RPB) {
-            const float4 y = s_y[j * CH4 + R.c4];
-            const uint64_t row = s_idx[j];
+            if (!final_level && os_open(os, j)) continue;
+            const float4 y = y_at(j);
+            const uint64_t row = row_of(j);
             const int4 q = make_int4(quant1<POW2>(y.x, st[0], ist[0], omt, thr), quant1<POW2>(y.y, st[1], ist[1], omt, thr),
                                      quant1<POW2>(y.z, st[2], ist[2], omt, thr), quant1<POW2>(y.w, st[3], ist[3], omt, thr));
             stq4<VEC>(coef, row, C, c4, q);
-            if (coef_f32)
-                st4<VEC>(coef_f32, row, C, c4,
-                         deq ? make_float4((float)q.x * st[0], (float)q.y * st[1], (float)q.z * st[2],
-                                           (float)q.w * st[3])
+            if (cf)
+                st4<VEC>(cf, row, C, c4,
+                         deq ? make_float4((float)q.x * st[0], (float)q.y * st[1], (float)q.z * st[2], (float)q.w * st[3])
                              : y);
         }
     } else {  // MODE_FWD_F32: float coefficient rows
-        for (uint32_t j = R.row0; j < mlen; j += R.RPB)
-            st4<VEC>(coef_f32, s_idx[j], C, c4, s_y[j * CH4 + R.c4]);
+        for (uint32_t j = R.row0; j < mlen; j += R.RPB) {
+            if (!final_level && os_open(os, j)) continue;
+            st4<VEC>(cf, row_of(j), C, c4, y_at(j));
+        }
     }
+}
+
+// ============================================================== upper levels, forward
+// One item (tile, channel slice p0) of S_k, k >= 2, whose schedule is in LDS: the entries'
+// partial low-passes come from the rows S_{k-1}'s open entries handed over, each entry's
+// coefficient row goes to its voxel's row, the open entries' partial low-passes to S_{k+1}.
+template <bool VEC, bool POW2>
+__device__ inline void fwd_up_item(const TileMap &m, uint32_t f, int k, uint32_t p0, const TileSched &ts,
+                                   float4 *s_y, const UpArrays &A, const float *s_st, const float *s_ist)
+{
+    const CAS FrameDesc &fd = *cp(m.fd[f]);  // (not written while the kernel runs)
+    const uint32_t C4 = fd.C4;
+    const uint32_t CH4 = pass_chunks(C4, k);
+    const Roles R(CH4);
+    const uint32_t mlen = (uint32_t)ts.mlen;
+    const uint32_t cb = p0 * CH4, nch = min(CH4, C4 - cb);
+    const uint32_t c4 = cb + R.c4;  // this thread's global channel chunk
+    const bool live = R.act && R.c4 < nch;
+    os_set(A.os, A.opos[min(threadIdx.x, (uint32_t)OPEN_CAP - 1)], threadIdx.x < ts.ocnt);
+    // ---- the entries' values of this channel slice
+    if (live) {
+        const GAS float *vsrc = gp(fd.lv[k - 1].vbuf);
+        load_slice(s_y, R, CH4, mlen, [&](uint32_t j) { return ld_coh4(vsrc + ((size_t)(ts.s + j) * C4 + c4) * 4); });
+    }
+    __syncthreads();
+    // ---- all local merges: within wave chunks, then across chunks (levels ascending)
+    const uint64_t wmask = A.lmask[R.w], xmask = A.lmask[CROSS];
+    wave_phase(s_y, R, A.rec, A.ab, A.lst, wmask, nch, false, R.w);
+    __syncthreads();
+    cross_phase(s_y, R, A.rec, A.ab, A.lst, xmask, nch, false);
+    if (!live) return;
+    store_coefs<VEC, POW2>(fd, s_st, s_ist, R, c4, mlen, ts.final_level, A.os,
+                           [&](uint32_t j) -> uint64_t { return A.idx[j]; },
+                           [&](uint32_t j) { return s_y[j * CH4 + R.c4]; });
     if (!ts.final_level) {
         GAS float *dst = gp(fd.lv[k].vbuf);
         for (uint32_t o = R.row0; o < ts.ocnt; o += R.RPB)
-            gstore4(dst + ((size_t)(ts.obase + o) * C4 + c4) * 4, s_y[s_opos[o] * CH4 + R.c4]);
+            st_coh4(dst + ((size_t)(ts.obase + o) * C4 + c4) * 4, s_y[A.opos[o] * CH4 + R.c4]);
     }
 }
 
-// Items of every level of a transform launch, counted once at the start (the schedule launches
-// have fixed the sizes): wave w counts levels 2 + w, 2 + w + NW, ...; s_fs[k][0..F] are the
-// frames' first items of level k and s_cnt[k] its items.
-struct UpCounts {
-    uint32_t cnt[MAXK + 1];
-    uint32_t fs[MAXK + 1][GSC_MAX_BATCH + 1];
-};
-__device__ inline void up_counts(const TileMap &m, int kmax, uint32_t np, UpCounts &U)
+// ============================================================== upper levels, inverse
+// One item of S_k, k >= 2: coefficient rows from the entries' voxels; the tile is inverted with
+// its open entries' low-passes taken as zero, then the low-passes S_{k+1} handed down (once all
+// of S_{k+1}'s items are done) add their shares; the entries' synthesized values go to S_{k-1}'s
+// open-entry rows.
+template <bool VEC>
+__device__ inline void inv_up_item(const TileMap &m, uint32_t f, int k, uint32_t p0, const TileSched &ts,
+                                   float4 *s_y, const UpArrays &A, const GAS uint32_t *above_done, uint32_t above_items)
 {
-    const uint32_t w = threadIdx.x / WAVE, lane = lane_id();
-    for (int k = 2 + (int)w; k <= kmax; k += RAHT_THREADS / WAVE) {
-        uint32_t c = 0;
-        if (lane < m.F) {
-            const CAS FrameDesc &fd = *cp(m.fd[lane]);
-            if ((uint32_t)k <= fd.K) {
-                const uint32_t nk = cp(fd.ctrl)->lvl_n[k];
-                if (nk >= 2 && nk <= fd.lv[k].cap) c = (nk + RT - 1) / RT * np;
-            }
+    const CAS FrameDesc &fd = *cp(m.fd[f]);  // (not written while the kernel runs)
+    const uint32_t C = fd.C, C4 = fd.C4;
+    const uint32_t CH4 = pass_chunks(C4, k);
+    const Roles R(CH4);
+    const uint32_t mlen = (uint32_t)ts.mlen;
+    const uint32_t cb = p0 * CH4, nch = min(CH4, C4 - cb);
+    const uint32_t c4 = cb + R.c4;
+    const bool live = R.act && R.c4 < nch;
+    const bool opens = !ts.final_level && ts.ocnt > 0;
+    os_set(A.os, A.opos[min(threadIdx.x, (uint32_t)OPEN_CAP - 1)], opens && threadIdx.x < ts.ocnt);
+    // ---- coefficients of every entry (the high-pass stored at it)
+    if (live) {
+        if (fd.mode == MODE_DECODE) {
+            const gsc_header *h = reinterpret_cast<const gsc_header *>(fd.in_stream);
+            const GAS int32_t *coef = gp(reinterpret_cast<const int32_t *>(fd.in_stream + h->coef_offset));
+            float st[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) st[i] = 4 * c4 + i < C ? h->quant_step[4 * c4 + i] : 0.0f;
+            load_slice(s_y, R, CH4, mlen, [&](uint32_t j) {
+                const int4 q = ldq4<VEC>(coef, A.idx[j], C, c4);
+                return make_float4((float)q.x * st[0], (float)q.y * st[1], (float)q.z * st[2], (float)q.w * st[3]);
+            });
+        } else {  // float coefficient rows: the straight-through forward synthesizes from its
+                  // dequantized coefficients; the transform and gradient modes read the caller's
+            const GAS float *fin = gp(fd.mode == MODE_ENCODE ? fd.coef_f32 : fd.attr);
+            load_slice(s_y, R, CH4, mlen, [&](uint32_t j) { return ld4<VEC>(fin, A.idx[j], C, c4); });
         }
-        const uint32_t inc = wave_incl_scan(c);
-        U.fs[k][lane + 1] = inc;
-        if (lane == 0) U.fs[k][0] = 0;
-        if (lane == WAVE - 1) U.cnt[k] = inc;
     }
     __syncthreads();
-}
-
-// The launch's items in processing order: the levels one after the other (ascending for the
-// forward, descending for the inverse), each level's items frame by frame. Workgroup b takes
-// items b, b + G, ..., so the items of small levels go to workgroups that have no item in the
-// levels before them: such a workgroup loads its schedule at once and only waits, on the phase
-// flags of the previous level's workgroups (a contiguous range modulo G), before it reads that
-// level's rows. A workgroup publishes a level when it moves on from it (or leaves). Every wait is
-// on items earlier in this order, each workgroup takes its items in order and all are resident,
-// so the earliest unfinished item can always proceed.
-template <bool DESC, class Item>
-__device__ inline void up_levels(const TileMap &m, int kmax, uint32_t phase0, UpLds &L, UpCounts &U, Item item)
-{
-    const CAS FrameDesc &fd0 = *cp(m.fd[0]);
-    uint32_t *flags = fd0.lvl_flags;
-    const uint32_t NP = channel_passes(fd0.C4, 2);  // every frame of a launch has the same C
-    up_counts(m, kmax, NP, U);
-    const uint32_t nl = kmax >= 2 ? (uint32_t)kmax - 1 : 0u;  // level positions 0 .. nl-1
-    auto level_at = [&](uint32_t o) { return DESC ? kmax - (int)o : 2 + (int)o; };
-    const uint32_t G = gridDim.x;
-    uint32_t o = 0, base = 0;      // level position of the current item, its first global item
-    uint32_t cur = ~0u;            // level position of this workgroup's last item
-    uint32_t pbase = 0, pcnt = 0, ppos = 0;  // the previous non-empty level: first item, items, position
-    for (uint32_t g = blockIdx.x;; g += G) {
-        while (o < nl && g >= base + U.cnt[level_at(o)]) {
-            const uint32_t c = U.cnt[level_at(o)];
-            if (c) {
-                pbase = base;
-                pcnt = c;
-                ppos = o;
-            }
-            base += c;
-            ++o;
-        }
-        if (o >= nl) break;
-        const int k = level_at(o);
-        const uint32_t i = g - base;
-        if (cur != ~0u && cur != o) level_publish(flags, phase0 + cur + 1);
-        const uint32_t *fs = U.fs[k];
-        const uint32_t f = item_frame(m, fs, i), local = i - fs[f];
-        TileSched ts;
-        const bool ok = up_schedule(m, f, k, local / NP, ts, L);
-        if (cur != o) {
-            if (pcnt) level_wait_range(flags, pbase % G, min(pcnt, G), G, phase0 + ppos + 1, fd0.ctrl);
-            cur = o;
-        }
-        if (ok) item(f, k, local % NP, ts);
+    // ---- open entries start from a zero low-pass
+    if (opens) {
+        os_prefix(A.os);
+        if (live)
+            for (uint32_t o = R.row0; o < ts.ocnt; o += R.RPB) s_y[A.opos[o] * CH4 + R.c4] = make_float4(0.f, 0.f, 0.f, 0.f);
         __syncthreads();
     }
-    if (cur != ~0u) level_publish(flags, phase0 + cur + 1);
-}
-
-// Levels 2 .. kmax, ascending: a level reads the open-entry rows the previous level wrote (and
-// rewrites the coefficient rows of entries that previous levels left open).
-template <bool VEC, bool POW2>
-__global__ __launch_bounds__(RAHT_THREADS) void k_raht_fwd_upper(TileMap m, int kmax)
-{
-    extern __shared__ float4 s_y[];
-    __shared__ UpLds L;
-    __shared__ UpCounts U;
-    up_levels<false>(m, kmax, PHASE_FORWARD, L, U, [&](uint32_t f, int k, uint32_t p0, const TileSched &ts) {
-        fwd_up_item<VEC, POW2>(m, f, k, p0, ts, s_y, L);
-    });
+    // ---- all local merges undone: across chunks, then within chunks (levels descending)
+    const uint64_t wmask = A.lmask[R.w], xmask = A.lmask[CROSS];
+    cross_phase(s_y, R, A.rec, A.ab, A.lst, xmask, nch, true);
+    wave_phase(s_y, R, A.rec, A.ab, A.lst, wmask, nch, true, R.w);
+    __syncthreads();
+    // ---- the open entries' low-passes, handed down by S_{k+1}
+    if (opens) {
+        done_wait(above_done, above_items, fd.ctrl);
+        const GAS float *src = gp(fd.lv[k].vbuf);
+        const bool fp64 = fp64_weights(fd);
+        for (uint32_t ob = 0; ob < ts.ocnt; ob += LCAP) {
+            const uint32_t nb = min(LCAP, ts.ocnt - ob);
+            for (uint32_t q = threadIdx.x; q < nb * nch; q += RAHT_THREADS) {
+                const uint32_t o = q / nch, c = q - o * nch;
+                A.L[o * CH4 + c] = ld_coh4(src + ((size_t)(ts.obase + ob + o) * C4 + cb + c) * 4);
+            }
+            __syncthreads();
+            add_open_share(s_y, R, CH4, live, mlen, A.os, A.opos, ts.ocnt, A.L, ob, nb, fp64,
+                           [&](uint32_t a, uint32_t b) { return A.idx[b] - A.idx[a]; });
+            __syncthreads();
+        }
+    }
+    if (!live) return;
+    GAS float *dst = gp(fd.lv[k - 1].vbuf);
+    for (uint32_t j = R.row0; j < mlen; j += R.RPB) st_coh4(dst + ((size_t)(ts.s + j) * C4 + c4) * 4, s_y[j * CH4 + R.c4]);
 }
 
 // ============================================================ first level, persistent forward
@@ -1082,22 +1275,42 @@ __device__ inline void load_rows1(const GAS float *src, uint32_t C, const Roles 
     for (int u = 0; u < NR1; ++u) D[u] = ld4<VEC>(src, row[u], C, c4);
 }
 
+
+
+// The forward transform of every tiling level in one launch. The first Gp workgroups first build
+// the upper levels' schedules (up_prelude_group; Gp = the second level's tiles, at most the grid),
+// which the upper levels need only at the end. Then every workgroup takes its first-level items
+// (persistent and prefetching, as described above). A workgroup out of first-level items adds
+// them to level 1's completion counter and takes the upper levels' items (ascending) from a
+// counter; an item of level k >= 2 waits until level k - 1 is complete (all its open-entry rows
+// handed over) and runs the tile as one (non-prefetching) item.
 template <bool VEC, bool POW2>
-__global__ __launch_bounds__(RAHT_THREADS) __attribute__((amdgpu_waves_per_eu(PERSIST_PER_CU * RAHT_THREADS / WAVE / 4))) void k_raht_fwd1(TileMap m)
+__global__ __launch_bounds__(RAHT_THREADS) __attribute__((amdgpu_waves_per_eu(PERSIST_PER_CU * RAHT_THREADS / WAVE / 4))) void k_raht_fwd(TileMap m, int kmax)
 {
     extern __shared__ float4 s_y[];
     __shared__ uint32_t s_rec[RT];
     __shared__ float2 s_ab[RT];
     __shared__ uint32_t s_lstw[LSTART_N / 2 + 1];   // u16 segment starts, in pairs; + sink
     __shared__ uint32_t s_oposw[OPEN_CAP / 2 + 1];  // u16 open positions, in pairs; + sink
-    __shared__ uint32_t s_m0[RT + 2];               // run starts; + sink
+    __shared__ uint32_t s_m0[RT + 2];               // run starts; + sink (upper items: voxel indices)
     __shared__ uint32_t s_row[RT];
     __shared__ float s_st[GSC_MAX_CHANNELS], s_ist[GSC_MAX_CHANNELS];
     __shared__ unsigned long long s_lmask[NCLS + 1];  // + sink
+    __shared__ unsigned long long s_om[2][NCHUNK];    // open-entry sets of two consecutive items
+    __shared__ uint32_t s_opre[NCHUNK + 1];
+    __shared__ uint32_t s_ucnt[MAXK + 2];
+    __shared__ uint32_t s_fs[GSC_MAX_BATCH + 1];
+    __shared__ uint32_t s_tk[1];
     const uint16_t *s_lst = reinterpret_cast<const uint16_t *>(s_lstw);
     const uint16_t *s_opos = reinterpret_cast<const uint16_t *>(s_oposw);
 
-    const uint32_t tid = threadIdx.x, G = gridDim.x, items = m.start[m.F];
+    const uint32_t tid = threadIdx.x, items = m.start[m.F];
+    // ---- the upper levels' schedules, by the first Gp workgroups
+    uint32_t Gp = 0;
+    if (kmax >= 2) {
+        Gp = min(level_items(m, 2, 1, s_fs), gridDim.x);
+        if (blockIdx.x < Gp) up_prelude_group(m, kmax, Gp, s_fs, ctr_word(m, PRE_DONE));
+    }
     Frame1 fc;
     fc.f = ~0u;
     fc.nk = 0;
@@ -1127,23 +1340,29 @@ __global__ __launch_bounds__(RAHT_THREADS) __attribute__((amdgpu_waves_per_eu(PE
         if (R.act && R.c4 < nch)
             load_rows1<VEC>(gp(d->attr), d->C, R, it.p * CH4 + R.c4, it.mlen, enc, s_row, it.s, D);
     };
-    Item1 it0 = item1(m, blockIdx.x, fc);
-    Item1 it1 = item1(m, blockIdx.x + G, fc);
+    // first-level item i goes to workgroup (Gp + i) % G: the schedule workgroups come last in the
+    // round-robin, so they take one item fewer when the items do not fill the last round
+    const uint32_t G = gridDim.x;
+    const uint32_t b1 = blockIdx.x >= Gp ? blockIdx.x - Gp : blockIdx.x + G - Gp;  // first item
+    Item1 it0 = item1(m, b1, fc);
+    Item1 it1 = item1(m, b1 + G, fc);
     Sched1 S;
     float4 D[NR1];
     uint32_t F1 = 0;
-    // prologue: the quantizer steps (shared by the frames of a launch) into LDS, the first
-    // item's rows, schedule and row loads
+    // prologue: the quantizer steps (shared by the frames of a launch) into LDS, the open-entry
+    // sets cleared, the first item's rows, schedule and row loads
     if (tid < GSC_MAX_CHANNELS) {
         s_st[tid] = cp(m.fd[0])->step[tid];
         s_ist[tid] = cp(m.fd[0])->inv_step[tid];
     }
+    if (tid < 2 * NCHUNK) (&s_om[0][0])[tid] = 0;
     if (it0.ok && cp(m.fd[it0.f])->mode == MODE_ENCODE) s_row[tid] = row_clamp(it0, first_row(it0));
     if (it1.ok && cp(m.fd[it1.f])->mode == MODE_ENCODE) F1 = first_row(it1);
     __syncthreads();
     if (it0.ok) prefetch(it0, S, D);
 
-    for (uint32_t i = blockIdx.x; i < items; i += G) {
+    uint32_t par = 0, n1 = 0;  // which open-entry set the current item uses; items done
+    for (uint32_t i = b1; i < items; i += G, ++n1, par ^= 1u) {
         CFrame *d = cp(m.fd[it0.f]);
         const bool encode = d->mode == MODE_ENCODE;
         uint32_t CH4, nch;
@@ -1154,10 +1373,17 @@ __global__ __launch_bounds__(RAHT_THREADS) __attribute__((amdgpu_waves_per_eu(PE
         const uint32_t C = d->C, n = d->n;
         const uint32_t obase = S.obase, ocnt = S.ocnt;
         const bool dup = S.m_end - S.m_beg != it0.mlen;  // a voxel of the tile has several Gaussians
+        const OpenSet os{s_om[par], s_opre};
         __syncthreads();  // the previous item is no longer read from LDS
         // ---- the current item's schedule and rows into LDS, the next item's first rows; on
-        // every path, whether or not the item is ok (see commit_sched1)
+        // every path, whether or not the item is ok (see commit_sched1); the item's open
+        // entries into its set (the other set is cleared for the next item)
         commit_sched1(S, it0, CH4, n, fp64_weights(*d), s_rec, s_ab, s_lstw, s_oposw, s_m0, s_lmask);
+        if (tid < NCHUNK) s_om[par ^ 1u][tid] = 0;
+        if (it0.ok && tid < (uint32_t)OPEN_CAP / 2) {
+            os_set(os, S.opos & 0xFFFFu, 2 * tid < ocnt);
+            os_set(os, S.opos >> 16, 2 * tid + 1 < ocnt);
+        }
         const uint32_t sink = RT * CH4;
 #pragma unroll
         for (int u = 0; u < NR1; ++u) {
@@ -1216,62 +1442,106 @@ __global__ __launch_bounds__(RAHT_THREADS) __attribute__((amdgpu_waves_per_eu(PE
             __syncthreads();
             cross_phase(s_y, R, s_rec, s_ab, s_lst, xmask, nch, false);
             if (live) {
-                GAS float *cf = gp(d->coef_f32);
-                if (encode) {
-                    const CAS Ctrl *ctrl = cp(d->ctrl);
-                    uint64_t off = GSC_HEADER_BYTES, run = 0;
-                    for (uint32_t dd = 0; dd < d->J; ++dd) {
-                        run += ctrl->hist_D[dd];
-                        off += run;
-                    }
-                    GAS int32_t *coef = gp(reinterpret_cast<int32_t *>(d->stream + align_up(off, 256)));
-                    const double omt = 1.0 - (double)d->tau;
-                    const float thr = ceil_float(omt);
-                    const bool deq = d->ste == STE_FORWARD;  // float output: q * step instead of y
-                    float st[4], ist[4];
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        const uint32_t c = min(4 * c4 + q, C - 1);
-                        st[q] = s_st[c];
-                        ist[q] = s_ist[c];
-                    }
-                    for (uint32_t j = R.row0, yi = y0; j < mlen; j += R.RPB, yi += ystep) {
-                        const float4 y = s_y[yi];
-                        const int4 q = make_int4(quant1<POW2>(y.x, st[0], ist[0], omt, thr), quant1<POW2>(y.y, st[1], ist[1], omt, thr),
-                                                 quant1<POW2>(y.z, st[2], ist[2], omt, thr), quant1<POW2>(y.w, st[3], ist[3], omt, thr));
-                        stq4<VEC>(coef, s + j, C, c4, q);
-                        if (cf)
-                            st4<VEC>(cf, s + j, C, c4,
-                                     deq ? make_float4((float)q.x * st[0], (float)q.y * st[1], (float)q.z * st[2],
-                                                       (float)q.w * st[3])
-                                         : y);
-                    }
-                } else {  // MODE_FWD_F32: float coefficient rows
-                    for (uint32_t j = R.row0, yi = y0; j < mlen; j += R.RPB, yi += ystep) st4<VEC>(cf, s + j, C, c4, s_y[yi]);
-                }
+                store_coefs<VEC, POW2>(*d, s_st, s_ist, R, c4, mlen, it0.final_level, os,
+                                       [&](uint32_t j) -> uint64_t { return s + j; },
+                                       [&](uint32_t j) { return s_y[j * CH4 + R.c4]; });
                 if (!it0.final_level) {
                     GAS float *dst = gp(d->lv[1].vbuf);
                     const uint32_t C4 = d->C4;
                     for (uint32_t o = R.row0; o < ocnt; o += R.RPB)
-                        gstore4(dst + ((size_t)(obase + o) * C4 + c4) * 4, s_y[s_opos[o] * CH4 + R.c4]);
+                        st_coh4(dst + ((size_t)(obase + o) * C4 + c4) * 4, s_y[s_opos[o] * CH4 + R.c4]);
                 }
             }
         }
         it0 = it1;
         it1 = it2;
     }
+    if (kmax < 2) return;
+    // ---- the upper levels, ascending
+    done_add(done_ctr(m, DONE_FWD, 1), n1);  // this workgroup's first-level open rows are written
+    const uint32_t NP = channel_passes(cp(m.fd[0])->C4, 2);  // every frame of a launch has the same C
+    if (tid < 2 * NCHUNK) (&s_om[0][0])[tid] = 0;
+    Ctrl *ctrl0 = cp(m.fd[0])->ctrl;
+    // the upper levels' schedules and sizes are written (by the first Gp workgroups)
+    done_wait(ctr_word(m, PRE_DONE), Gp, ctrl0);
+    if (tid == 0) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    __syncthreads();
+    const uint32_t U = up_totals(m, kmax, NP, s_ucnt);
+    const UpArrays A{s_rec, s_ab, reinterpret_cast<uint16_t *>(s_lstw), reinterpret_cast<uint16_t *>(s_oposw),
+                     s_m0, s_lmask, OpenSet{s_om[0], s_opre}, nullptr};
+    GAS uint32_t *utk = ctr_word(m, TK_UPF);
+    for (;;) {
+        if (tid == 0) s_tk[0] = __hip_atomic_fetch_add(utk, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __syncthreads();  // (also: the previous item's LDS is no longer read)
+        const uint32_t g = __builtin_amdgcn_readfirstlane(s_tk[0]);
+        if (g >= U) break;
+        const UpItem u = up_item(m, kmax, false, NP, s_ucnt, g);
+        TileSched ts;
+        const bool ok = up_schedule(m, u.f, u.k, u.tile, ts, A);
+        // the entries' rows are handed over by level k - 1: wait until all of its items are done
+        done_wait(done_ctr(m, DONE_FWD, u.k - 1), u.k == 2 ? items : s_ucnt[u.k - 1], ctrl0);
+        if (ok) fwd_up_item<VEC, POW2>(m, u.f, u.k, u.p, ts, s_y, A, s_st, s_ist);
+        done_add(done_ctr(m, DONE_FWD, u.k), 1);
+        if (tid < NCHUNK) s_om[0][tid] = 0;
+    }
+}
+
+// ============================================================ upper levels, inverse (launch)
+// The inverse of the upper levels kmax .. 2 in one persistent launch (all workgroups resident),
+// before the first level's: with `prelude`, the whole grid first builds the upper levels'
+// schedules. The items run in descending level order (workgroup b takes items b, b + G, ...);
+// every item inverts its tile with the open entries' low-passes taken as zero and only then waits
+// for the level above, so the tiles of all levels are inverted side by side and only the shares
+// of the low-passes (add_open_share) follow the levels' order.
+template <bool VEC>
+__global__ __launch_bounds__(RAHT_THREADS) void k_raht_inv_up(TileMap m, int kmax, int prelude)
+{
+    extern __shared__ float4 s_y[];
+    __shared__ uint32_t s_rec[RT];
+    __shared__ float2 s_ab[RT];
+    __shared__ uint16_t s_lst[LSTART_N];
+    __shared__ uint16_t s_opos[OPEN_CAP];
+    __shared__ uint32_t s_idx[RT + 1];
+    __shared__ unsigned long long s_lmask[NCLS];
+    __shared__ unsigned long long s_om[NCHUNK];
+    __shared__ uint32_t s_opre[NCHUNK + 1];
+    __shared__ float4 s_L[LCAP * CH4_MAX];
+    __shared__ uint32_t s_ucnt[MAXK + 2];
+    __shared__ uint32_t s_fs[GSC_MAX_BATCH + 1];
+    const uint32_t tid = threadIdx.x, G = gridDim.x;
+    Ctrl *ctrl0 = cp(m.fd[0])->ctrl;
+    if (tid < NCHUNK) s_om[tid] = 0;
+    if (prelude) {
+        const uint32_t Gp = min(level_items(m, 2, 1, s_fs), G);
+        if (blockIdx.x < Gp) up_prelude_group(m, kmax, Gp, s_fs, ctr_word(m, PRE_DONE));
+        done_wait(ctr_word(m, PRE_DONE), Gp, ctrl0);
+        if (tid == 0) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        __syncthreads();
+    }
+    const uint32_t NP = channel_passes(cp(m.fd[0])->C4, 2);  // every frame of a launch has the same C
+    const uint32_t U = up_totals(m, kmax, NP, s_ucnt);
+    const UpArrays A{s_rec, s_ab, s_lst, s_opos, s_idx, s_lmask, OpenSet{s_om, s_opre}, s_L};
+    for (uint32_t g = blockIdx.x; g < U; g += G) {
+        const UpItem u = up_item(m, kmax, true, NP, s_ucnt, g);
+        __syncthreads();  // the previous item's LDS is no longer read
+        TileSched ts;
+        const bool ok = up_schedule(m, u.f, u.k, u.tile, ts, A);
+        if (ok) inv_up_item<VEC>(m, u.f, u.k, u.p, ts, s_y, A, done_ctr(m, DONE_INV, u.k + 1), s_ucnt[u.k + 1]);
+        done_add(done_ctr(m, DONE_INV, u.k), 1);
+        if (tid < NCHUNK) s_om[tid] = 0;
+    }
 }
 
 // ============================================================ first level, persistent inverse
-// The same persistent, prefetching scheme for the first level of the inverse: while one item's
-// merges are undone and its rows stored, the next item's schedule, coefficient rows (read as raw
-// 32-bit words, dequantized when they are committed to LDS) and the low-passes of its open
-// entries (from S_2) are in flight in registers.
+// The same persistent, prefetching scheme for the first level of the inverse (after the upper
+// levels' launch): while one item's merges are undone and its rows stored, the next item's
+// schedule, coefficient rows (read as raw 32-bit words, dequantized when they are committed to
+// LDS) and the low-passes of its open entries (from S_2) are in flight in registers.
 // open entries per thread: ceil(OPEN_CAP / RPB) for the narrowest rows per step
 constexpr int NO1 = (OPEN_CAP + RT / (int)CH4_MAX1 - 1) / (RT / (int)CH4_MAX1);
 
 template <bool VEC>
-__global__ __launch_bounds__(RAHT_THREADS) __attribute__((amdgpu_waves_per_eu(PERSIST_PER_CU * RAHT_THREADS / WAVE / 4))) void k_raht_inv1(TileMap m)
+__global__ __launch_bounds__(RAHT_THREADS) __attribute__((amdgpu_waves_per_eu(PERSIST_PER_CU * RAHT_THREADS / WAVE / 4))) void k_raht_inv(TileMap m)
 {
     extern __shared__ float4 s_y[];
     __shared__ uint32_t s_rec[RT];
@@ -1417,84 +1687,16 @@ __global__ __launch_bounds__(RAHT_THREADS) __attribute__((amdgpu_waves_per_eu(PE
     }
 }
 
-// ============================================================== upper levels, inverse
-// One workgroup per (tile, channel slice) of S_k, k >= 2: coefficient rows from the entries'
-// voxels, open entries' low-passes from S_{k+1}; the entries' synthesized low-passes go to S_{k-1}'s
-// open-entry rows.
-template <bool VEC>
-__device__ inline void inv_up_item(const TileMap &m, uint32_t f, int k, uint32_t p0, const TileSched &ts,
-                                   float4 *s_y, UpLds &L)
+// Dynamic LDS of a transform launch: the slice of RT entries of the widest tiling level, plus
+// one sink slot for writes that are masked off by address rather than by branch.
+size_t raht_lds_bytes(int C4)
 {
-    uint32_t *s_rec = L.rec, *s_idx = L.idx;
-    float2 *s_ab = L.ab;
-    uint16_t *s_lst = L.lst, *s_opos = L.opos;
-    unsigned long long *s_lmask = L.lmask;
-    const CAS FrameDesc &fd = *cp(m.fd[f]);  // (not written while the kernel runs)
-    const uint32_t C = fd.C, C4 = fd.C4;
-    const uint32_t CH4 = pass_chunks(C4, k);
-    const Roles R(CH4);
-    const uint32_t mlen = (uint32_t)ts.mlen;
-    const uint32_t cb = p0 * CH4, nch = min(CH4, C4 - cb);
-    const uint32_t c4 = cb + R.c4;
-    const bool live = R.act && R.c4 < nch;
-    // ---- coefficients of every entry (the high-pass stored at it)
-    if (live) {
-        if (fd.mode == MODE_DECODE) {
-            const gsc_header *h = reinterpret_cast<const gsc_header *>(fd.in_stream);
-            const GAS int32_t *coef = gp(reinterpret_cast<const int32_t *>(fd.in_stream + h->coef_offset));
-            float st[4];
-#pragma unroll
-            for (int i = 0; i < 4; ++i) st[i] = 4 * c4 + i < C ? h->quant_step[4 * c4 + i] : 0.0f;
-            load_slice(s_y, R, CH4, mlen, [&](uint32_t j) {
-                const int4 q = ldq4<VEC>(coef, s_idx[j], C, c4);
-                return make_float4((float)q.x * st[0], (float)q.y * st[1], (float)q.z * st[2],
-                                   (float)q.w * st[3]);
-            });
-        } else {  // float coefficient rows: the straight-through forward synthesizes from its
-                  // dequantized coefficients; the transform and gradient modes read the caller's
-            const GAS float *fin = gp(fd.mode == MODE_ENCODE ? fd.coef_f32 : fd.attr);
-            load_slice(s_y, R, CH4, mlen, [&](uint32_t j) { return ld4<VEC>(fin, s_idx[j], C, c4); });
-        }
-    }
-    __syncthreads();
-    // ---- open entries take the low-pass handed down by the next sequence
-    if (!ts.final_level) {
-        if (live) {
-            const GAS float *src = gp(fd.lv[k].vbuf);
-            for (uint32_t o = R.row0; o < ts.ocnt; o += R.RPB)
-                s_y[s_opos[o] * CH4 + R.c4] = gload4(src + ((size_t)(ts.obase + o) * C4 + c4) * 4);
-        }
-        __syncthreads();
-    }
-    // ---- all local merges undone: across chunks, then within chunks (levels descending)
-    const uint64_t wmask = s_lmask[R.w], xmask = s_lmask[CROSS];
-    cross_phase(s_y, R, s_rec, s_ab, s_lst, xmask, nch, true);
-    wave_phase(s_y, R, s_rec, s_ab, s_lst, wmask, nch, true, R.w);
-    __syncthreads();
-    if (!live) return;
-    GAS float *dst = gp(fd.lv[k - 1].vbuf);
-    for (uint32_t j = R.row0; j < mlen; j += R.RPB)
-        gstore4(dst + ((size_t)(ts.s + j) * C4 + c4) * 4, s_y[j * CH4 + R.c4]);
+    const uint32_t a = pass_chunks((uint32_t)C4, 1), b = pass_chunks((uint32_t)C4, 2);
+    return ((size_t)RT * (a > b ? a : b) + 1) * sizeof(float4);
 }
 
-// Levels kmax .. 2, descending: a level reads the low-passes the level above handed down.
-template <bool VEC>
-__global__ __launch_bounds__(RAHT_THREADS) void k_raht_inv_upper(TileMap m, int kmax)
-{
-    extern __shared__ float4 s_y[];
-    __shared__ UpLds L;
-    __shared__ UpCounts U;
-    up_levels<true>(m, kmax, PHASE_INVERSE, L, U, [&](uint32_t f, int k, uint32_t p0, const TileSched &ts) {
-        inv_up_item<VEC>(m, f, k, p0, ts, s_y, L);
-    });
-}
-
-// Dynamic LDS of a transform launch: the slice of RT entries, plus one sink slot for writes that
-// are masked off by address rather than by branch.
-size_t raht_lds_bytes(int C4, int k) { return ((size_t)RT * pass_chunks((uint32_t)C4, k) + 1) * sizeof(float4); }
-
-// Launch limits of the current device, queried once per device and kept in a table that every
-// host thread may read and fill (guarded by one mutex).
+// Launch limits of the current device, queried once per (device, kernel, dynamic LDS) and kept
+// in tables that every host thread may read and fill (guarded by one mutex).
 constexpr int MAX_DEVICES = 64;
 static std::mutex g_limits_mu;
 static int g_cus[MAX_DEVICES];  // compute units per device, 0 = not queried yet
@@ -1506,8 +1708,6 @@ static int current_device()
     return dev;
 }
 
-// Workgroups of a persistent first-level launch over `items` items: at most PERSIST_PER_CU per
-// CU, a multiple of 8 NP, and as few as give every workgroup the same number of items, up to one.
 static uint32_t cu_count()
 {
     const int dev = current_device();
@@ -1520,97 +1720,96 @@ static uint32_t cu_count()
     return (uint32_t)g_cus[dev];
 }
 
-uint32_t persist_grid(uint32_t items, int C4)
+// Workgroups of `kern` that fit on one CU at once (occupancy calculator), cached.
+static uint32_t blocks_per_cu(const void *kern, int threads, size_t lds)
 {
-    const uint32_t cus = cu_count();
+    struct Entry {
+        int dev;
+        const void *kern;
+        size_t lds;
+        int nb;
+    };
+    static Entry cache[64];
+    static int used = 0;
+    const int dev = current_device();
+    std::lock_guard<std::mutex> lock(g_limits_mu);
+    for (int i = 0; i < used; ++i)
+        if (cache[i].dev == dev && cache[i].kern == kern && cache[i].lds == lds) return (uint32_t)cache[i].nb;
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, threads, lds) != hipSuccess || nb < 0) nb = 0;
+    if (used < 64) cache[used++] = Entry{dev, kern, lds, nb};
+    return (uint32_t)nb;
+}
+
+// Workgroups of a persistent launch whose workgroups wait on one another: every one of them must
+// be resident at once, so at most what the occupancy calculator allows per CU (and `per_cu_max`)
+// times the CUs, a multiple of 8 (the XCDs), and at most `want`. 0 if none fits.
+static uint32_t resident_grid(const void *kern, size_t lds, uint32_t per_cu_max, uint32_t want)
+{
+    uint32_t per_cu = blocks_per_cu(kern, RAHT_THREADS, lds);
+    if (per_cu > per_cu_max) per_cu = per_cu_max;
+    const uint32_t g = per_cu * cu_count() / 8 * 8;
+    return want < g ? (want + 7) / 8 * 8 : g;
+}
+
+// Workgroups of a persistent first-level launch over `items` items: resident at once (as above),
+// a multiple of 8 NP (an item and its partner slice, items i and i + 8 of a group of 8 NP, run
+// at the same time on one XCD), and as few as give every workgroup the same number of items, up
+// to one. 0 if none fits.
+static uint32_t persist_grid(uint32_t items, int C4, const void *kern, size_t lds)
+{
+    uint32_t per_cu = blocks_per_cu(kern, RAHT_THREADS, lds);
+    if (per_cu > (uint32_t)PERSIST_PER_CU) per_cu = PERSIST_PER_CU;
     const uint32_t unit = 8 * channel_passes((uint32_t)C4, 1);
-    const uint32_t gmax = ((uint32_t)PERSIST_PER_CU * (uint32_t)cus) / unit * unit;
+    const uint32_t gmax = per_cu * cu_count() / unit * unit;
+    if (gmax == 0) return 0;
     if (items <= gmax) return items;
     const uint32_t rounds = ceil_div(items, gmax);
     return ceil_div(ceil_div(items, rounds), unit) * unit;
 }
 
-hipError_t launch_raht_fwd(const TileMap &m, int k, const RahtCfg &cfg, hipStream_t s)
+hipError_t launch_raht_fwd(const TileMap &m, int kmax, const RahtCfg &cfg, hipStream_t s)
 {
-    const size_t lds = raht_lds_bytes(cfg.C4, k);
-    if (k == 1) {
-        const dim3 grid(persist_grid(m.start[m.F], cfg.C4)), block(RAHT_THREADS);
-        if (cfg.vec && cfg.pow2) hipLaunchKernelGGL((k_raht_fwd1<true, true>), grid, block, lds, s, m);
-        else if (cfg.vec) hipLaunchKernelGGL((k_raht_fwd1<true, false>), grid, block, lds, s, m);
-        else if (cfg.pow2) hipLaunchKernelGGL((k_raht_fwd1<false, true>), grid, block, lds, s, m);
-        else hipLaunchKernelGGL((k_raht_fwd1<false, false>), grid, block, lds, s, m);
-        return hipGetLastError();
-    }
-    return hipErrorInvalidValue;  // upper levels: launch_raht_fwd_upper
-}
-
-hipError_t launch_raht_inv(const TileMap &m, int k, const RahtCfg &cfg, hipStream_t s)
-{
-    const size_t lds = raht_lds_bytes(cfg.C4, k);
-    if (k == 1) {
-        const dim3 grid(persist_grid(m.start[m.F], cfg.C4)), block(RAHT_THREADS);
-        if (cfg.vec) hipLaunchKernelGGL((k_raht_inv1<true>), grid, block, lds, s, m);
-        else hipLaunchKernelGGL((k_raht_inv1<false>), grid, block, lds, s, m);
-        return hipGetLastError();
-    }
-    return hipErrorInvalidValue;  // upper levels: launch_raht_inv_upper
-}
-
-// Workgroups of a persistent upper-level launch: all of them must be resident at once (they
-// wait on one another's phase flags), so at most what the occupancy calculator allows per CU
-// times the CUs, at most UP_GRID_MAX flags, and no more than the largest level's worst-case
-// items. Cached per (kernel, dynamic LDS).
-static uint32_t resident_grid(const void *kern, int threads, size_t lds, uint32_t items_max)
-{
-    struct Entry { int dev; const void *kern; size_t lds; int nb; };
-    static Entry cache[64];
-    static int used = 0;
-    const int dev = current_device();
-    int nb = 0;
-    {
-        std::lock_guard<std::mutex> lock(g_limits_mu);
-        for (int i = 0; i < used; ++i)
-            if (cache[i].dev == dev && cache[i].kern == kern && cache[i].lds == lds) nb = cache[i].nb;
-        if (nb == 0) {
-            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, threads, lds) != hipSuccess || nb < 1) nb = 1;
-            if (used < 64) cache[used++] = Entry{dev, kern, lds, nb};
-        }
-    }
-    uint32_t g = min((uint32_t)nb * cu_count(), UP_GRID_MAX);
-    g = min(g, items_max);
-    return g ? g : 1u;
-}
-
-hipError_t launch_prelude_up(const TileMap &m, int kmax, uint32_t items_max, hipStream_t s)
-{
-    const uint32_t grid = resident_grid(reinterpret_cast<const void *>(k_prelude_up), PRE_BLOCK_UP, 0, items_max);
-    hipLaunchKernelGGL(k_prelude_up, dim3(grid), dim3(PRE_BLOCK_UP), 0, s, m, kmax);
+    const size_t lds = raht_lds_bytes(cfg.C4);
+    const void *kern = cfg.vec ? (cfg.pow2 ? reinterpret_cast<const void *>(k_raht_fwd<true, true>)
+                                           : reinterpret_cast<const void *>(k_raht_fwd<true, false>))
+                               : (cfg.pow2 ? reinterpret_cast<const void *>(k_raht_fwd<false, true>)
+                                           : reinterpret_cast<const void *>(k_raht_fwd<false, false>));
+    const uint32_t g = persist_grid(m.start[m.F], cfg.C4, kern, lds);
+    if (g == 0) return hipErrorInvalidConfiguration;
+    const dim3 grid(g), block(RAHT_THREADS);
+    if (cfg.vec && cfg.pow2) hipLaunchKernelGGL((k_raht_fwd<true, true>), grid, block, lds, s, m, kmax);
+    else if (cfg.vec) hipLaunchKernelGGL((k_raht_fwd<true, false>), grid, block, lds, s, m, kmax);
+    else if (cfg.pow2) hipLaunchKernelGGL((k_raht_fwd<false, true>), grid, block, lds, s, m, kmax);
+    else hipLaunchKernelGGL((k_raht_fwd<false, false>), grid, block, lds, s, m, kmax);
     return hipGetLastError();
 }
 
-hipError_t launch_raht_fwd_upper(const TileMap &m, int kmax, uint32_t items_max, const RahtCfg &cfg, hipStream_t s)
+hipError_t launch_raht_inv_up(const TileMap &m, int kmax, uint32_t items_max, bool prelude, const RahtCfg &cfg,
+                              hipStream_t s)
 {
-    const size_t lds = raht_lds_bytes(cfg.C4, 2);
-    const void *kern = cfg.vec ? (cfg.pow2 ? reinterpret_cast<const void *>(k_raht_fwd_upper<true, true>)
-                                           : reinterpret_cast<const void *>(k_raht_fwd_upper<true, false>))
-                               : (cfg.pow2 ? reinterpret_cast<const void *>(k_raht_fwd_upper<false, true>)
-                                           : reinterpret_cast<const void *>(k_raht_fwd_upper<false, false>));
-    const dim3 grid(resident_grid(kern, RAHT_THREADS, lds, items_max)), block(RAHT_THREADS);
-    if (cfg.vec && cfg.pow2) hipLaunchKernelGGL((k_raht_fwd_upper<true, true>), grid, block, lds, s, m, kmax);
-    else if (cfg.vec) hipLaunchKernelGGL((k_raht_fwd_upper<true, false>), grid, block, lds, s, m, kmax);
-    else if (cfg.pow2) hipLaunchKernelGGL((k_raht_fwd_upper<false, true>), grid, block, lds, s, m, kmax);
-    else hipLaunchKernelGGL((k_raht_fwd_upper<false, false>), grid, block, lds, s, m, kmax);
+    const size_t lds = raht_lds_bytes(cfg.C4);
+    const void *kern = cfg.vec ? reinterpret_cast<const void *>(k_raht_inv_up<true>)
+                               : reinterpret_cast<const void *>(k_raht_inv_up<false>);
+    uint32_t g = resident_grid(kern, lds, 4, items_max > 0 ? items_max : 1u);
+    if (g > UP_GRID_MAX) g = UP_GRID_MAX;  // (one phase flag per workgroup)
+    if (g == 0) return hipErrorInvalidConfiguration;
+    const dim3 grid(g), block(RAHT_THREADS);
+    if (cfg.vec) hipLaunchKernelGGL((k_raht_inv_up<true>), grid, block, lds, s, m, kmax, prelude ? 1 : 0);
+    else hipLaunchKernelGGL((k_raht_inv_up<false>), grid, block, lds, s, m, kmax, prelude ? 1 : 0);
     return hipGetLastError();
 }
 
-hipError_t launch_raht_inv_upper(const TileMap &m, int kmax, uint32_t items_max, const RahtCfg &cfg, hipStream_t s)
+hipError_t launch_raht_inv(const TileMap &m, const RahtCfg &cfg, hipStream_t s)
 {
-    const size_t lds = raht_lds_bytes(cfg.C4, 2);
-    const void *kern = cfg.vec ? reinterpret_cast<const void *>(k_raht_inv_upper<true>)
-                               : reinterpret_cast<const void *>(k_raht_inv_upper<false>);
-    const dim3 grid(resident_grid(kern, RAHT_THREADS, lds, items_max)), block(RAHT_THREADS);
-    if (cfg.vec) hipLaunchKernelGGL((k_raht_inv_upper<true>), grid, block, lds, s, m, kmax);
-    else hipLaunchKernelGGL((k_raht_inv_upper<false>), grid, block, lds, s, m, kmax);
+    const size_t lds = raht_lds_bytes(cfg.C4);
+    const void *kern = cfg.vec ? reinterpret_cast<const void *>(k_raht_inv<true>)
+                               : reinterpret_cast<const void *>(k_raht_inv<false>);
+    const uint32_t g = persist_grid(m.start[m.F], cfg.C4, kern, lds);
+    if (g == 0) return hipErrorInvalidConfiguration;
+    const dim3 grid(g), block(RAHT_THREADS);
+    if (cfg.vec) hipLaunchKernelGGL((k_raht_inv<true>), grid, block, lds, s, m);
+    else hipLaunchKernelGGL((k_raht_inv<false>), grid, block, lds, s, m);
     return hipGetLastError();
 }
 
