@@ -17,6 +17,8 @@ Other workloads (--workload):
                                as a replayed HIP graph, and the graph with autotuned sort tiles
   diff500k_J11                 the straight-through differentiable coder: forward + rate-
                                distortion loss + backward, next to a plain encode + decode
+  rlgr_frame1M_J12             the block entropy coder on the 1M frame's quantized
+                               coefficients: time and size per block length
 """
 from __future__ import annotations
 
@@ -445,6 +447,71 @@ def ste_bench(args):
     print(json.dumps(out))
 
 
+# ------------------------------------------------------------------ block entropy coder
+def rlgr_bench(args):
+    """The block entropy coder (Sec. 3.4) on the quantized coefficients of the 1M-Gaussian frame:
+    GPU encode and decode time and stream size per block length, next to one block per channel
+    (the sequential coder, from the CPU oracle) and the oracle's time at the chosen block."""
+    import numpy as np
+    import torch
+    from paper_2606_05650_amd import gsc, synth
+
+    n, J, table = synth.WORKLOADS["frame1M_J12"]
+    steps_q = synth.quant_steps(table)
+    pos, attr = synth.make_frame(n, seed=2)
+    C = attr.shape[1]
+    dev = torch.device("cuda:0")
+    enc = gsc.encode_frame(torch.from_numpy(pos).to(dev), torch.from_numpy(attr).to(dev),
+                           gsc.make_params(J, C, steps_q))
+    torch.cuda.synchronize()
+    enc.check()
+    blob = np.frombuffer(enc.to_bytes(), dtype=np.uint8)
+    h = gsc.parse_header(blob)
+    nv = int(h["n_vox"])
+    Q = blob[int(h["coef_offset"]):int(h["total_bytes"])].view(np.int32).reshape(nv, C)
+    tq = torch.from_numpy(np.ascontiguousarray(Q)).to(dev)
+    raw = Q.nbytes
+    rows = []
+    for B in (256, 512, 1024, 2048, 4096, 8192):
+        cap = gsc.rlgr_capacity(nv, C, B)
+        out = torch.empty(cap, dtype=torch.uint8, device=dev)
+        ws = torch.empty(gsc.rlgr_workspace_size(nv, B), dtype=torch.uint8, device=dev)
+        info = torch.zeros(gsc.INFO_WORDS, dtype=torch.int32, device=dev)
+        qd = torch.empty_like(tq)
+        wsd = torch.empty(8, dtype=torch.uint8, device=dev)
+        infod = torch.zeros(gsc.INFO_WORDS, dtype=torch.int32, device=dev)
+        s = gsc.rlgr_encode(tq, B, out=out, ws=ws, info=info)
+        torch.cuda.synchronize()
+        s.check()
+        nbytes = s.nbytes()
+        for _ in range(args.warmup):
+            gsc.rlgr_encode(tq, B, out=out, ws=ws, info=info)
+            gsc.rlgr_decode(out, nv, C, B, nbytes=nbytes, q=qd, ws=wsd, info=infod)
+        te = timed(lambda: gsc.rlgr_encode(tq, B, out=out, ws=ws, info=info), args.steps, torch)
+        td = timed(lambda: gsc.rlgr_decode(out, nv, C, B, nbytes=nbytes, q=qd, ws=wsd, info=infod),
+                   args.steps, torch)
+        assert int(infod[0].item()) == 0 and torch.equal(qd, tq), "entropy coder round trip"
+        rows.append({"block": B, "bytes": nbytes, "bits_per_coef": round(8 * nbytes / Q.size, 3),
+                     "enc_ms": round(te * 1e3, 4), "dec_ms": round(td * 1e3, 4),
+                     "enc_gbs_raw": round(raw / te / 1e9, 1), "dec_gbs_raw": round(raw / td / 1e9, 1)})
+    out = {"workload": "rlgr_frame1M_J12", "coefficients": int(Q.size), "raw_bytes": raw,
+           "blocks": rows}
+    if not args.no_cpu_baseline:
+        from oracle import oracle as orc
+        # one block per channel: the sequential coder, the size every blocking is compared with
+        off, w = orc.rlgr_encode(Q, nv)
+        seq = 32 + 4 * len(off) + 4 * int(off[-1])
+        for r in rows:
+            r["delta_size_vs_one_block_per_channel"] = round(r["bytes"] / seq - 1.0, 5)
+        t0 = time.perf_counter()
+        orc.rlgr_encode(Q, 512)
+        t = time.perf_counter() - t0
+        out["one_block_per_channel_bytes"] = seq
+        out["cpu_baseline"] = {"encode_ms_block512": round(t * 1e3, 1), "cores": 1, "kind": "oracle",
+                               "sample": "one encode of the frame's coefficients (single-threaded C)"}
+    print(json.dumps(out))
+
+
 def copy_calibration(args):
     """Plain copies of a 512 MiB buffer: each launch reads and writes exactly 536,870,912 bytes."""
     import torch
@@ -485,6 +552,8 @@ def main():
         seq_bench(args)
     elif args.workload == "diff500k_J11":
         ste_bench(args)
+    elif args.workload == "rlgr_frame1M_J12":
+        rlgr_bench(args)
     else:
         frame_bench(args)
 

@@ -302,6 +302,52 @@ gsc_status gsc_ste_backward(int64_t n, int32_t J, int32_t C, const float *d_grad
                             size_t ws_bytes, int32_t *d_info, void *stream);
 
 /* ------------------------------------------------------------------------------------------
+ * Block-parallel entropy coding of quantized coefficients (Sec. 3.4 "Quantization and Entropy
+ * Coding": run-length / adaptive Golomb-Rice coding of independent blocks of consecutive
+ * coefficients of one channel, coded in parallel).
+ *   Input/output coefficients: [nv][C] int32, row-major (the coefficient section of an encoded
+ *   stream is such a matrix: row 0 the DC, row i the high-pass stored at voxel i).
+ *   Blocks: channel c's nv values, in row order, cut into blocks of B values (the last one
+ *   shorter); block b = j * C + c holds rows j*B .. j*B + B - 1 of channel c, coded from a fresh
+ *   coder state into a whole number of 32-bit words (bits from the most significant down).
+ *   Coder (the paper names the method, not its parameters): adaptive run mode and Golomb-Rice
+ *   parameters held with 3 fractional bits (both start at 8, kept in 0..80); run mode sends a 0
+ *   bit per 2^k zeros (kp += 4), a 1 and the remaining count in k bits, then the sign and the
+ *   Golomb-Rice code of |v| - 1 of the value that ends the run (kp -= 6); otherwise each value
+ *   is sent as the Golomb-Rice code of 2v or -2v - 1 (kp += 3 after a zero, -= 3 otherwise).
+ *   The Golomb-Rice code of u is u >> kr ones, a 0 and the kr low bits, or, when u >> kr >= 24,
+ *   24 ones and u in 32 bits; krp -= 2 when u >> kr = 0 and += u >> kr when it is above 1.
+ *   Stream: gsc_rlgr_header, then the blocks' first words uint32[nblocks + 1] (the last entry
+ *   is total_words), then the total_words code words. Little-endian.
+ * gsc_rlgr_capacity: worst-case stream bytes for nv x C values (68 bits per value plus a word
+ *   per block, the header and the table). gsc_rlgr_workspace_size: device scratch bytes.
+ * gsc_rlgr_encode: d_q [nv][C] -> d_out (out_cap bytes). d_info[0] device status (
+ *   GSC_ERR_CAPACITY if the code does not fit out_cap), d_info[2..3] the stream bytes (uint64).
+ * gsc_rlgr_decode: d_in (in_bytes) -> d_q [nv][C]; nv, C and B must match the header;
+ *   GSC_ERR_CORRUPT_STREAM in d_info[0] for a header or a block that does not decode to exactly
+ *   its values within its words (the rows of such a block are then unspecified).
+ * B is 1 .. 65536; C 1 .. 64; nv < 2^30.
+ * ---------------------------------------------------------------------------------------- */
+#define GSC_RLGR_MAGIC 0x31474C52u /* "RLG1" */
+typedef struct gsc_rlgr_header {
+    uint32_t magic;          /* GSC_RLGR_MAGIC                     */
+    uint32_t version;        /* GSC_VERSION                        */
+    uint32_t nv, C, B;       /* rows, channels, block length       */
+    uint32_t nblocks;        /* C * ceil(nv / B)                   */
+    uint32_t total_words;    /* code words after the table         */
+    uint32_t reserved;
+} gsc_rlgr_header;
+
+gsc_status gsc_rlgr_capacity(int64_t nv, int32_t C, int32_t B, size_t *bytes);
+gsc_status gsc_rlgr_workspace_size(int64_t nv, int32_t B, size_t *bytes);
+gsc_status gsc_rlgr_encode(const int32_t *d_q, int64_t nv, int32_t C, int32_t B, void *d_out,
+                           size_t out_cap, void *d_ws, size_t ws_bytes, int32_t *d_info,
+                           void *stream);
+gsc_status gsc_rlgr_decode(const void *d_in, size_t in_bytes, int64_t nv, int32_t C, int32_t B,
+                           int32_t *d_q, void *d_ws, size_t ws_bytes, int32_t *d_info,
+                           void *stream);
+
+/* ------------------------------------------------------------------------------------------
  * Diagnostics: gsc_profile_events -- record caller-created HIP events around one stage of every
  * later call on the calling process (all threads share this setting). `events` holds n_pairs
  * (start, end) pairs of hipEvent_t (as void*); the i-th launch of the stage records pair

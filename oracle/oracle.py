@@ -14,10 +14,11 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "gsc_oracle.c")
+_SRC_RLGR = os.path.join(_HERE, "rlgr_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 GCC_CMD = ["gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fPIC", "-shared", "-o", _LIB, _SRC,
-           "-lm"]
+           _SRC_RLGR, "-lm"]
 
 
 def build_oracle() -> str:
@@ -32,7 +33,8 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        if (not os.path.exists(_LIB)) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        if (not os.path.exists(_LIB)) or os.path.getmtime(_LIB) < max(
+                os.path.getmtime(_SRC), os.path.getmtime(_SRC_RLGR)):
             build_oracle()
         L = ctypes.CDLL(_LIB)
         i64, i32, u32, u64, dbl, vp = (ctypes.c_int64, ctypes.c_int, ctypes.c_uint32,
@@ -78,6 +80,12 @@ def lib():
         L.orc_ste_grad.restype = i32
         L.orc_ste_grad.argtypes = [vp, vp, i64, i32, i32, vp, dbl, dbl, i32, vp, vp, vp, vp, vp,
                                    vp, vp, vp, vp, vp]
+        L.orc_rlgr_blocks.restype = i64
+        L.orc_rlgr_blocks.argtypes = [i64, i32, i32]
+        L.orc_rlgr_encode.restype = i64
+        L.orc_rlgr_encode.argtypes = [vp, i64, i32, i32, vp, vp, i64]
+        L.orc_rlgr_decode.restype = i32
+        L.orc_rlgr_decode.argtypes = [vp, vp, i64, i32, i32, vp]
         _lib = L
     return _lib
 
@@ -344,3 +352,35 @@ def ste_grad(pos, attr, J, step, tau=0.5, lam=0.01, bbox=None):
     return dict(nv=nv, leaf=leaf[:nv], voxel_of=vof[:n], aref=aref[:nv], yhat=yhat[:nv],
                 ahat=ahat[:nv], grad=grad[:n], loss=float(loss[0]), dist=float(loss[1]),
                 rate=float(loss[2]), bbox_min=bmin, cell=float(cell[0]))
+
+
+# ------------------------------------------------------------------------- entropy coder
+def rlgr_blocks(nv, C, B):
+    return int(_check(lib().orc_rlgr_blocks(int(nv), int(C), int(B)), "rlgr_blocks"))
+
+
+def rlgr_encode(Q, B):
+    """Block-parallel RLGR of Q [nv][C] int32 (Sec. 3.4) with blocks of B values per channel.
+    Returns (off int64[NB + 1] block word offsets, words uint32[off[-1]])."""
+    Q = _c(Q, np.int32)
+    nv, C = Q.shape
+    NB = rlgr_blocks(nv, C, B)
+    off = np.zeros(NB + 1, dtype=np.int64)
+    total = _check(lib().orc_rlgr_encode(_p(Q), nv, C, int(B), _p(off), None, 0), "rlgr size")
+    words = np.zeros(max(total, 1), dtype=np.uint32)
+    _check(lib().orc_rlgr_encode(_p(Q), nv, C, int(B), _p(off), _p(words), total), "rlgr_encode")
+    return off, words[:total]
+
+
+def rlgr_decode(off, words, nv, C, B):
+    """Inverse of rlgr_encode; raises ValueError on a block that does not decode exactly."""
+    off = _c(off, np.int64)
+    words = _c(words, np.uint32)
+    if words.size == 0:
+        words = np.zeros(1, dtype=np.uint32)
+    Q = np.zeros((max(int(nv), 1), int(C)), dtype=np.int32)
+    rc = lib().orc_rlgr_decode(_p(off), _p(words), int(nv), int(C), int(B), _p(Q))
+    if rc == -3:
+        raise ValueError("corrupt entropy-coded block")
+    _check(rc, "rlgr_decode")
+    return Q[:int(nv)]

@@ -853,3 +853,91 @@ gsc_status gsc_raht_adjoint(const uint64_t *d_codes, int64_t nv, int32_t J, int3
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------- block entropy coder
+namespace {
+constexpr int64_t RLGR_NV_LIMIT = (1ll << 30) - 1;
+constexpr int32_t RLGR_B_MAX = 65536;
+
+gsc_status rlgr_shape(int64_t nv, int32_t C, int32_t B)
+{
+    if (C < 1 || C > GSC_MAX_CHANNELS) return GSC_ERR_DEPTH;
+    if (nv < 0 || nv > RLGR_NV_LIMIT || B < 1 || B > RLGR_B_MAX) return GSC_ERR_INVALID_ARG;
+    return GSC_OK;
+}
+uint64_t rlgr_blocks(int64_t nv, int32_t C, int32_t B) { return (uint64_t)((nv + B - 1) / B) * (uint64_t)C; }
+uint64_t rlgr_table_bytes(int64_t nv, int32_t C, int32_t B)
+{
+    return sizeof(gsc_rlgr_header) + 4ull * (rlgr_blocks(nv, C, B) + 1);
+}
+}  // namespace
+
+extern "C" {
+
+gsc_status gsc_rlgr_capacity(int64_t nv, int32_t C, int32_t B, size_t *bytes)
+{
+    if (!bytes) return GSC_ERR_INVALID_ARG;
+    gsc_status st = rlgr_shape(nv, C, B);
+    if (st != GSC_OK) return st;
+    // at most 1 + 10 + 1 + 24 + 32 = 68 bits per value, and one partial word per block
+    *bytes = (size_t)(rlgr_table_bytes(nv, C, B) + 4ull * (((uint64_t)nv * C * 68 + 31) / 32 + rlgr_blocks(nv, C, B)));
+    return GSC_OK;
+}
+
+gsc_status gsc_rlgr_workspace_size(int64_t nv, int32_t B, size_t *bytes)
+{
+    if (!bytes) return GSC_ERR_INVALID_ARG;
+    gsc_status st = rlgr_shape(nv, 1, B);
+    if (st != GSC_OK) return st;
+    *bytes = (size_t)(8ull * ((uint64_t)(nv + B - 1) / B + 1));
+    return GSC_OK;
+}
+
+gsc_status gsc_rlgr_encode(const int32_t *d_q, int64_t nv, int32_t C, int32_t B, void *d_out,
+                           size_t out_cap, void *d_ws, size_t ws_bytes, int32_t *d_info,
+                           void *stream)
+{
+    gsc_status st = rlgr_shape(nv, C, B);
+    if (st != GSC_OK) return st;
+    if (!d_out || !d_ws || !d_info || (nv > 0 && !d_q)) return GSC_ERR_INVALID_ARG;
+    size_t need = 0;
+    gsc_rlgr_workspace_size(nv, B, &need);
+    if (ws_bytes < need) return GSC_ERR_WORKSPACE;
+    if (out_cap < rlgr_table_bytes(nv, C, B)) return GSC_ERR_CAPACITY;
+    {
+        Spans sp;
+        sp.rd(d_q, (uint64_t)nv * C * 4);
+        sp.wr(d_out, out_cap);
+        sp.wr(d_ws, need);
+        sp.wr(d_info, GSC_INFO_WORDS * 4);
+        if (!sp.disjoint()) return GSC_ERR_INVALID_ARG;
+    }
+    GSC_LAUNCH(launch_rlgr_encode(d_q, (uint32_t)nv, (uint32_t)C, (uint32_t)B, static_cast<uint8_t *>(d_out),
+                                  out_cap, static_cast<uint64_t *>(d_ws), d_info, static_cast<hipStream_t>(stream)));
+    return GSC_OK;
+}
+
+gsc_status gsc_rlgr_decode(const void *d_in, size_t in_bytes, int64_t nv, int32_t C, int32_t B,
+                           int32_t *d_q, void *d_ws, size_t ws_bytes, int32_t *d_info,
+                           void *stream)
+{
+    gsc_status st = rlgr_shape(nv, C, B);
+    if (st != GSC_OK) return st;
+    if (!d_in || !d_ws || !d_info || (nv > 0 && !d_q)) return GSC_ERR_INVALID_ARG;
+    if (ws_bytes < 8) return GSC_ERR_WORKSPACE;
+    if (in_bytes < rlgr_table_bytes(nv, C, B)) return GSC_ERR_CAPACITY;
+    {
+        Spans sp;
+        sp.rd(d_in, in_bytes);
+        sp.wr(d_q, (uint64_t)nv * C * 4);
+        sp.wr(d_ws, 8);
+        sp.wr(d_info, GSC_INFO_WORDS * 4);
+        if (!sp.disjoint()) return GSC_ERR_INVALID_ARG;
+    }
+    GSC_LAUNCH(launch_rlgr_decode(static_cast<const uint8_t *>(d_in), in_bytes, (uint32_t)nv, (uint32_t)C,
+                                  (uint32_t)B, d_q, static_cast<uint64_t *>(d_ws), d_info,
+                                  static_cast<hipStream_t>(stream)));
+    return GSC_OK;
+}
+
+}  // extern "C"

@@ -111,6 +111,14 @@ def lib():
         L.gsc_raht_forward.argtypes = [vp, i64, i32, i32, vp, vp, vp, sz, vp, vp]
         L.gsc_raht_adjoint.restype = i32
         L.gsc_raht_adjoint.argtypes = [vp, i64, i32, i32, vp, vp, vp, sz, vp, vp]
+        L.gsc_rlgr_capacity.restype = i32
+        L.gsc_rlgr_capacity.argtypes = [i64, i32, i32, ctypes.POINTER(sz)]
+        L.gsc_rlgr_workspace_size.restype = i32
+        L.gsc_rlgr_workspace_size.argtypes = [i64, i32, ctypes.POINTER(sz)]
+        L.gsc_rlgr_encode.restype = i32
+        L.gsc_rlgr_encode.argtypes = [vp, i64, i32, i32, vp, sz, vp, sz, vp, vp]
+        L.gsc_rlgr_decode.restype = i32
+        L.gsc_rlgr_decode.argtypes = [vp, sz, i64, i32, i32, vp, vp, sz, vp, vp]
         L.gsc_status_string.restype = ctypes.c_char_p
         L.gsc_status_string.argtypes = [i32]
         _lib = L
@@ -558,3 +566,93 @@ def ste_backward(fwd, grad_yhat, grad_ahat, *, out=None, info=None, stream=None)
                                 _ptr(e.ws.buf), e.ws.bytes, _ptr(info), _stream(stream))
     _check(rc, "gsc_ste_backward")
     return out, info
+
+
+# ----------------------------------------------------------------- block entropy coder
+RLGR_MAGIC = 0x31474C52
+RLGR_HEADER_DTYPE = np.dtype([("magic", "<u4"), ("version", "<u4"), ("nv", "<u4"), ("C", "<u4"),
+                              ("B", "<u4"), ("nblocks", "<u4"), ("total_words", "<u4"),
+                              ("reserved", "<u4")])
+
+
+def rlgr_capacity(nv, C, B):
+    out = ctypes.c_size_t()
+    _check(lib().gsc_rlgr_capacity(int(nv), int(C), int(B), ctypes.byref(out)), "rlgr_capacity")
+    return out.value
+
+
+def rlgr_workspace_size(nv, B):
+    out = ctypes.c_size_t()
+    _check(lib().gsc_rlgr_workspace_size(int(nv), int(B), ctypes.byref(out)),
+           "rlgr_workspace_size")
+    return out.value
+
+
+@dataclass
+class RlgrStream:
+    buf: "object"    # uint8 device tensor (capacity bytes)
+    info: "object"   # int32 device tensor [GSC_INFO_WORDS]
+    nv: int
+    C: int
+    B: int
+    ws: "object" = None
+
+    def check(self):
+        i = self.info.cpu().numpy()
+        if i[0] != 0:
+            raise GscError(i[0], "device")
+        return self
+
+    def nbytes(self):
+        i = self.info.cpu().numpy()
+        return int(np.uint32(i[2])) | (int(np.uint32(i[3])) << 32)
+
+    def to_bytes(self):
+        return self.buf[:self.nbytes()].cpu().numpy().tobytes()
+
+
+def rlgr_encode(q, B, *, out=None, ws=None, info=None, stream=None):
+    """Block-parallel run-length / Golomb-Rice coding of q [nv, C] int32 (cuda, contiguous)
+    with blocks of B values per channel."""
+    torch = _torch()
+    nv, C = int(q.shape[0]), int(q.shape[1])
+    dev = q.device
+    _check_tensor(q, "q", torch.int32, nv, C)
+    cap = rlgr_capacity(nv, C, B)
+    if out is None:
+        out = _dev_u8(cap, dev)
+    if ws is None:
+        ws = _dev_u8(rlgr_workspace_size(nv, B), dev)
+    if info is None:
+        info = torch.zeros(INFO_WORDS, dtype=torch.int32, device=dev)
+    _check_tensor(out, "out", torch.uint8)
+    _check_tensor(ws, "ws", torch.uint8, numel=rlgr_workspace_size(nv, B))
+    _check_tensor(info, "info", torch.int32, numel=INFO_WORDS)
+    rc = lib().gsc_rlgr_encode(_ptr(q), nv, C, int(B), _ptr(out), out.numel(), _ptr(ws),
+                               ws.numel(), _ptr(info), _stream(stream))
+    _check(rc, "gsc_rlgr_encode")
+    return RlgrStream(out, info, nv, C, int(B), ws)
+
+
+def rlgr_decode(buf, nv, C, B, *, nbytes=None, q=None, ws=None, info=None, stream=None):
+    """Inverse of rlgr_encode: the stream in `buf` (uint8 cuda) -> q [nv, C] int32."""
+    torch = _torch()
+    dev = buf.device
+    nv, C = int(nv), int(C)
+    if q is None:
+        q = torch.empty((max(nv, 1), C), dtype=torch.int32, device=dev)
+    if ws is None:
+        ws = _dev_u8(8, dev)
+    if info is None:
+        info = torch.zeros(INFO_WORDS, dtype=torch.int32, device=dev)
+    _check_tensor(buf, "buf", torch.uint8)
+    _check_tensor(q, "q", torch.int32, nv, C)
+    _check_tensor(ws, "ws", torch.uint8, numel=8)
+    _check_tensor(info, "info", torch.int32, numel=INFO_WORDS)
+    n = buf.numel() if nbytes is None else int(nbytes)
+    if n > buf.numel():
+        raise ValueError("nbytes exceeds the buffer")
+    rc = lib().gsc_rlgr_decode(_ptr(buf), n, nv, C, int(B), _ptr(q), _ptr(ws), ws.numel(),
+                               _ptr(info), _stream(stream))
+    _check(rc, "gsc_rlgr_decode")
+    return q, info

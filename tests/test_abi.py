@@ -15,7 +15,8 @@ def test_library_exports_every_declared_symbol():
     assert {"gsc_encode_frame", "gsc_decode_frame", "gsc_encode_batch", "gsc_workspace_size",
             "gsc_stream_capacity", "gsc_status_string", "gsc_decode_batch", "gsc_raht_forward",
             "gsc_raht_adjoint", "gsc_ste_forward", "gsc_ste_backward",
-            "gsc_profile_events", "gsc_encode_frame_noalloc"} <= set(names)
+            "gsc_profile_events", "gsc_encode_frame_noalloc", "gsc_rlgr_encode", "gsc_rlgr_decode",
+            "gsc_rlgr_capacity", "gsc_rlgr_workspace_size"} <= set(names)
     for name in names:
         assert hasattr(L, name), name
 
@@ -254,3 +255,25 @@ def test_binding_validates_tensors():
     p = gsc.make_params(8, 4, 0.1)
     with pytest.raises(ValueError):   # host tensors are refused before any call
         gsc.encode_frame(torch.zeros((10, 3)), torch.zeros((10, 4)), p)
+
+
+def test_rlgr_sizes_and_argument_checks():
+    # worst case: 68 bits per value, a partial word per block, the header and the block table
+    nv, C, B = 1000, 56, 512
+    nb = -(-nv // B) * C
+    assert gsc.rlgr_capacity(nv, C, B) == 32 + 4 * (nb + 1) + 4 * ((nv * C * 68 + 31) // 32 + nb)
+    assert gsc.rlgr_workspace_size(nv, B) == 8 * (-(-nv // B) + 1)
+    L = gsc.lib()
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced: every case fails validation first
+    ws = gsc.rlgr_workspace_size(nv, B)
+    cap = gsc.rlgr_capacity(nv, C, B)
+    enc = lambda n=nv, c=C, b=B, w=ws, k=cap, q=fake: L.gsc_rlgr_encode(q, n, c, b, fake, k, fake, w, fake, None)
+    assert enc(c=0) == 2 and enc(c=65) == 2
+    assert enc(b=0) == 1 and enc(b=65537) == 1 and enc(n=-1) == 1
+    assert enc(w=8) == 3
+    assert enc(k=32) == 4
+    assert enc(q=None) == 1
+    dec = lambda n=nv, c=C, b=B, k=cap: L.gsc_rlgr_decode(fake, k, n, c, b, fake, fake, 8, fake, None)
+    assert dec(k=16) == 4 and dec(c=0) == 2 and dec(b=0) == 1
+    with pytest.raises(gsc.GscError):
+        gsc.rlgr_capacity(10, 0, 512)
