@@ -318,7 +318,7 @@ gsc_status encode_frames(const Frame *fr, int F, const gsc_params *p, hipStream_
             const uint32_t tile = (uint32_t)sort_tile(var);
             TileMap m = make_map(fr, F, [tile](const Frame &x) { return ceil_div(x.a.n, tile); });
             if (m.start[F] > 0)
-                for (int pass = 0; pass < P; ++pass) GSC_LAUNCH(launch_sort_pass(m, pass, var, s));
+                for (int pass = 0; pass < P; ++pass) GSC_LAUNCH(launch_sort_pass(m, pass, var, sort_bits(p->J), s));
         }
         {
             TileMap m = make_map(fr, F, [](const Frame &x) { return x.a.n ? x.L.dedup_tiles : 0u; });

@@ -14,9 +14,11 @@ namespace gsc {
 // ---------------------------------------------------------------------------- tile sizes
 constexpr int WAVE = 64;
 
-constexpr int SORT_BITS = 8;            // radix digit width
-constexpr int SORT_BINS = 1 << SORT_BITS;
-constexpr int SORT_THREADS = 512;       // 8 waves; threads below SORT_BINS also hold a digit each
+// Radix digits of 8 bits, or of 9 bits when that saves a pass over the 3J-bit codes (J = 3, 6,
+// 9, 11, 12, 14, 15, 17, 18, 20, 21): 36-bit codes at J = 12 take four passes instead of five.
+constexpr int SORT_BITS_MAX = 9;
+constexpr int SORT_BINS_MAX = 1 << SORT_BITS_MAX;
+constexpr int SORT_THREADS = 512;       // 8 waves; thread d < 2^bits also holds digit d
 // Tiling variants of a sort pass (keys per thread, look-back window), chosen per call by the
 // autotuner's table; the workspace is laid out for the smallest tile.
 struct SortVariant {
@@ -27,7 +29,8 @@ constexpr SortVariant SORT_VARIANT[SORT_VARIANTS] = {{8, 16}, {4, 16}, {12, 16},
 constexpr int SORT_DEFAULT_VARIANT = 0;
 constexpr int SORT_KPT_MIN = 4;
 __host__ __device__ constexpr int sort_tile(int variant) { return SORT_THREADS * SORT_VARIANT[variant].kpt; }
-constexpr int SORT_MAX_PASSES = 8;      // ceil(63 / 8)
+// histogram words of all passes: at most 8 passes of 256 digits or 7 of 512 (63-bit codes)
+constexpr int SORT_HIST_WORDS = 7 * 512;
 
 constexpr int DEDUP_THREADS = 512;
 constexpr int DEDUP_KPT = 8;
@@ -95,7 +98,7 @@ struct Ctrl {
     uint64_t occ_bytes, coef_offset, total_bytes;
     double bbox_min[3];
     double cell;
-    uint32_t sort_hist[SORT_MAX_PASSES * SORT_BINS];
+    uint32_t sort_hist[SORT_HIST_WORDS];
 };
 constexpr size_t CTRL_BYTES = 16384;
 static_assert(sizeof(Ctrl) <= CTRL_BYTES, "control block too large");
@@ -175,7 +178,8 @@ struct FrameDesc {
     uint32_t *first;         // encode: input row of every voxel's first member (sorted order)
     uint32_t *bbox_part;     // encode: bounding-box workgroups' partial extrema (BBOX_SLOT each)
     uint32_t *lvl_flags;     // upper-level launches: the phase each workgroup has completed
-    uint32_t *sort_status;   // P x sort tiles x SORT_BINS
+    uint32_t *sort_status;   // P x sort tiles x 2^sort_bits
+    uint32_t sort_bits;      // radix digit width (8 or 9)
     uint64_t *dedup_status;
     uint64_t *occ_status;    // occ tiles x J
     uint64_t *dec_status;    // decoder: look-back status of the occupancy-byte tiles
@@ -253,7 +257,11 @@ __host__ __device__ inline uint32_t ceil_div(uint64_t a, uint64_t b)
 {
     return (uint32_t)((a + b - 1) / b);
 }
-__host__ __device__ inline int sort_passes(int J) { return (3 * J + SORT_BITS - 1) / SORT_BITS; }
+__host__ __device__ inline int sort_bits(int J)
+{
+    return (3 * J + 8) / 9 < (3 * J + 7) / 8 ? 9 : 8;
+}
+__host__ __device__ inline int sort_passes(int J) { return (3 * J + sort_bits(J) - 1) / sort_bits(J); }
 __host__ __device__ inline uint32_t open_max(int J) { return 6u * (uint32_t)J + 2u; }
 __host__ __device__ inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
@@ -294,7 +302,7 @@ __host__ __device__ inline bool make_layout(int64_t n, int J, int C, Layout *L)
     // the sort's status words (zeroed by the voxelize kernel of an encode, which precedes the
     // sort), then the zero region: every other look-back status word and nothing else
     L->sort_status = off;
-    off = align_up(off + (size_t)L->P * L->sort_tiles * SORT_BINS * 4, 256);
+    off = align_up(off + (size_t)L->P * L->sort_tiles * ((size_t)1 << sort_bits(J)) * 4, 256);
     L->zero_off = off;
     L->dedup_status = off;
     off = align_up(off + (size_t)L->dedup_tiles * 8, 256);
@@ -345,7 +353,7 @@ __host__ __device__ inline bool make_layout(int64_t n, int J, int C, Layout *L)
 hipError_t launch_setup(const SetupArgs &a, uint32_t zero_blocks, hipStream_t s);
 hipError_t launch_bbox(const TileMap &m, hipStream_t s);  // grid: bbox_blocks(n) per frame
 hipError_t launch_voxelize(const TileMap &m, hipStream_t s);
-hipError_t launch_sort_pass(const TileMap &m, int pass, int variant, hipStream_t s);
+hipError_t launch_sort_pass(const TileMap &m, int pass, int variant, int bits, hipStream_t s);
 hipError_t launch_dedup(const TileMap &m, hipStream_t s);
 hipError_t launch_occupancy(const TileMap &m, hipStream_t s);
 hipError_t launch_dec_expand(const TileMap &m, hipStream_t s);

@@ -109,6 +109,7 @@ __global__ __launch_bounds__(256) void k_setup(SetupArgs a)
         fd->C = a.C;
         fd->C4 = (a.C + 3) / 4;
         fd->P = L.P;
+        fd->sort_bits = (uint32_t)sort_bits((int)a.J);
         fd->mode = a.mode;
         fd->ste = (a.keep && !s_prev_ok) ? STE_NONE : a.ste;
         fd->bbox_mode = a.bbox_mode;
@@ -396,13 +397,13 @@ __global__ __launch_bounds__(VOX_THREADS) void k_voxelize(TileMap m)
     Ctrl *ctrl = fd.ctrl;
     if (load_error(ctrl)) return;
     const uint32_t b = blockIdx.x - m.start[f];
-    const uint32_t n = fd.n, J = fd.J, P = fd.P;
-    __shared__ uint32_t s_hist[SORT_MAX_PASSES * SORT_BINS];
-    for (uint32_t i = threadIdx.x; i < P * SORT_BINS; i += VOX_THREADS) s_hist[i] = 0;
+    const uint32_t n = fd.n, J = fd.J, P = fd.P, bits = fd.sort_bits, bins = 1u << bits;
+    __shared__ uint32_t s_hist[SORT_HIST_WORDS];
+    for (uint32_t i = threadIdx.x; i < P * bins; i += VOX_THREADS) s_hist[i] = 0;
     {   // this workgroup's share of the sort's look-back status words (they lie outside the
         // region the setup kernel zeroes, since only an encode sorts)
         const uint32_t nb = n ? (n + VOX_TILE - 1) / VOX_TILE : 1u;
-        const uint64_t nq = (uint64_t)P * fd.sort_tiles * SORT_BINS / 4;
+        const uint64_t nq = (uint64_t)P * fd.sort_tiles * bins / 4;
         uint4 *z = reinterpret_cast<uint4 *>(fd.sort_status);
         for (uint64_t i = (uint64_t)b * VOX_THREADS + threadIdx.x; i < nq; i += (uint64_t)nb * VOX_THREADS)
             z[i] = make_uint4(0, 0, 0, 0);
@@ -489,10 +490,10 @@ __global__ __launch_bounds__(VOX_THREADS) void k_voxelize(TileMap m)
         const uint64_t key = morton3(v[0], v[1], v[2]);
         gp(fd.keys_a)[i] = key;
         for (uint32_t p = 0; p < P; ++p)
-            atomicAdd(&s_hist[p * SORT_BINS + ((key >> (p * SORT_BITS)) & (SORT_BINS - 1))], 1u);
+            atomicAdd(&s_hist[p * bins + ((key >> (p * bits)) & (bins - 1))], 1u);
     }
     __syncthreads();
-    for (uint32_t i = threadIdx.x; i < P * SORT_BINS; i += VOX_THREADS)
+    for (uint32_t i = threadIdx.x; i < P * bins; i += VOX_THREADS)
         if (s_hist[i]) atomicAdd(&ctrl->sort_hist[i], s_hist[i]);
 }
 
@@ -506,15 +507,16 @@ uint32_t voxelize_blocks(uint32_t n) { return n ? ceil_div(n, VOX_TILE) : 1u; }
 // ============================================================ one-sweep radix sort pass
 // Stable LSD pass over digit `pass` of (key, index) pairs. Each workgroup ranks a tile of
 // SORT_THREADS * KPT keys in LDS: wave w owns a contiguous 1/NW of the tile and walks it in order,
-// 64 keys at a time; lanes holding the same digit are found with SORT_BITS ballots and ranked
+// 64 keys at a time; lanes holding the same digit are found with one ballot per digit bit and ranked
 // among themselves, so equal digits keep input order. The tile's digit counts are combined
 // with its predecessors' through a per-digit decoupled look-back, keys are staged in LDS in
 // digit order and written out in runs.
+template <int BITS>
 __device__ inline uint64_t match_digit(uint32_t d)
 {
     uint64_t peers = ~0ull;
 #pragma unroll
-    for (int bit = 0; bit < SORT_BITS; ++bit) {
+    for (int bit = 0; bit < BITS; ++bit) {
         const bool on = (d >> bit) & 1u;
         const uint64_t mm = __ballot(on);
         peers &= on ? mm : ~mm;
@@ -522,11 +524,12 @@ __device__ inline uint64_t match_digit(uint32_t d)
     return peers;
 }
 
-template <int KPT, int WIN>
+template <int KPT, int WIN, int BITS>
 __global__ __launch_bounds__(SORT_THREADS) void k_sort_pass(TileMap m, int pass)
 {
     constexpr int TILE = SORT_THREADS * KPT;
     constexpr int NW = SORT_THREADS / WAVE;
+    constexpr int SORT_BINS = 1 << BITS;
     __shared__ uint32_t s_tile;
     __shared__ uint32_t s_wcnt[NW][SORT_BINS];
     __shared__ uint32_t s_gbase[SORT_BINS];
@@ -551,7 +554,7 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_pass(TileMap m, int pass)
     const GAS uint32_t *vin = gp((pass & 1) ? fd.vals_b : fd.vals_a);
     GAS uint64_t *kout = gp((pass & 1) ? fd.keys_a : fd.keys_b);
     GAS uint32_t *vout = gp((pass & 1) ? fd.vals_a : fd.vals_b);
-    const uint32_t shift = (uint32_t)pass * SORT_BITS;
+    const uint32_t shift = (uint32_t)pass * BITS;
 
     uint64_t key[KPT];
     uint32_t val[KPT];
@@ -567,7 +570,7 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_pass(TileMap m, int pass)
 #pragma unroll
     for (int j = 0; j < KPT; ++j) {
         const uint32_t d = (uint32_t)(key[j] >> shift) & (SORT_BINS - 1);
-        const uint64_t peers = match_digit(d);
+        const uint64_t peers = match_digit<BITS>(d);
         const uint32_t cnt = s_wcnt[w][d];
         __builtin_amdgcn_wave_barrier();
         const bool leader = lane == (uint32_t)(__ffsll((long long)peers) - 1);
@@ -624,17 +627,25 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_pass(TileMap m, int pass)
     }
 }
 
-hipError_t launch_sort_pass(const TileMap &m, int pass, int variant, hipStream_t s)
+template <int BITS>
+static hipError_t launch_sort_pass_bits(const TileMap &m, int pass, int variant, hipStream_t s)
 {
     const dim3 grid(m.start[m.F]), block(SORT_THREADS);
     switch (variant) {
-    case 0: hipLaunchKernelGGL((k_sort_pass<SORT_VARIANT[0].kpt, SORT_VARIANT[0].win>), grid, block, 0, s, m, pass); break;
-    case 1: hipLaunchKernelGGL((k_sort_pass<SORT_VARIANT[1].kpt, SORT_VARIANT[1].win>), grid, block, 0, s, m, pass); break;
-    case 2: hipLaunchKernelGGL((k_sort_pass<SORT_VARIANT[2].kpt, SORT_VARIANT[2].win>), grid, block, 0, s, m, pass); break;
-    case 3: hipLaunchKernelGGL((k_sort_pass<SORT_VARIANT[3].kpt, SORT_VARIANT[3].win>), grid, block, 0, s, m, pass); break;
+    case 0: hipLaunchKernelGGL((k_sort_pass<SORT_VARIANT[0].kpt, SORT_VARIANT[0].win, BITS>), grid, block, 0, s, m, pass); break;
+    case 1: hipLaunchKernelGGL((k_sort_pass<SORT_VARIANT[1].kpt, SORT_VARIANT[1].win, BITS>), grid, block, 0, s, m, pass); break;
+    case 2: hipLaunchKernelGGL((k_sort_pass<SORT_VARIANT[2].kpt, SORT_VARIANT[2].win, BITS>), grid, block, 0, s, m, pass); break;
+    case 3: hipLaunchKernelGGL((k_sort_pass<SORT_VARIANT[3].kpt, SORT_VARIANT[3].win, BITS>), grid, block, 0, s, m, pass); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+hipError_t launch_sort_pass(const TileMap &m, int pass, int variant, int bits, hipStream_t s)
+{
+    if (bits == 9) return launch_sort_pass_bits<9>(m, pass, variant, s);
+    if (bits == 8) return launch_sort_pass_bits<8>(m, pass, variant, s);
+    return hipErrorInvalidValue;
 }
 
 // ================================================================= unique + merge map
