@@ -395,7 +395,7 @@ def seq_bench(args):
 def ste_bench(args):
     import torch
     from paper_2606_05650_amd import gsc, synth
-    from paper_2606_05650_amd.ste import SteCoder, rd_loss
+    from paper_2606_05650_amd.ste import SteCoder, SteCoderPadded, rd_loss
 
     n, J, table = synth.WORKLOADS["diff500k_J11"]
     lam = 0.01
@@ -409,6 +409,14 @@ def ste_bench(args):
     p = gsc.make_params(J, C, steps_q)
 
     def ste_step():
+        # the layer that never waits for the device (rows past Nv zero, Nv on the device)
+        ta.grad = None
+        yhat, ahat, aref, nv = SteCoderPadded.apply(ta, tp, p)
+        loss, _, _ = rd_loss(yhat, ahat, aref, steps_t, lam, nv=nv)
+        loss.backward()
+
+    def ste_step_sync():
+        # the layer that cuts its outputs to Nv rows (one host synchronization per step)
         ta.grad = None
         yhat, ahat, aref = SteCoder.apply(ta, tp, p)
         loss, _, _ = rd_loss(yhat, ahat, aref, steps_t, lam)
@@ -427,13 +435,16 @@ def ste_bench(args):
     K, W = args.steps, args.warmup
     for _ in range(W):
         ste_step()
+        ste_step_sync()
         plain()
     t_ste = timed(ste_step, K, torch)
+    t_sync = timed(ste_step_sync, K, torch)
     t_plain = timed(plain, K, torch)
     cfg = {"workload": "diff500k_J11", "gaussians": n, "depth": J, "channels": C,
            "lambda": lam, "parallelism": "single GPU"}
     out = base_record(args, n / t_ste / 1e6, t_ste * 1e3, cfg)
     out["step"] = "straight-through forward + rate-distortion loss + backward to the attributes"
+    out["synchronizing_layer_ms"] = round(t_sync * 1e3, 4)
     out["plain_encode_decode_ms"] = round(t_plain * 1e3, 4)
     out["plain_m_gaussians_per_s"] = round(n / t_plain / 1e6, 2)
     if not args.no_cpu_baseline:

@@ -11,10 +11,11 @@
  * - `stream` is a hipStream_t passed as void* (NULL = the null stream). Every call only
  *   enqueues work on that stream and returns; results are valid once the stream has been
  *   synchronized.
- * - Concurrency: calls on one device must not run at the same time on different streams. Three
- *   kernels of a call (the upper RAHT levels) keep all their workgroups resident and order their
- *   levels by waiting on one another; a concurrent call's kernels can take the slots they wait
- *   for, and the call then fails with GSC_ERR_INTERNAL after a bounded wait. Serialize calls on a
+ * - Concurrency: calls on one device must not run at the same time on different streams. The
+ *   transform launches that run the upper RAHT levels (the forward, and the inverse of the upper
+ *   levels) keep all their workgroups resident and order the levels by waiting on one another;
+ *   a concurrent call's kernels can take the slots they wait for, and the call then fails with
+ *   GSC_ERR_INTERNAL after a bounded wait. Serialize calls on a
  *   device (one stream, or events between streams); frames coded together belong in one batch
  *   call. The host side is thread-safe: the only process-wide state (the sort tuning table and
  *   per-device launch limits) is guarded.

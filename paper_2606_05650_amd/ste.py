@@ -5,7 +5,13 @@ the Nv occupied voxels in Morton order, the dequantized coefficients yhat, the d
 attributes ahat = T^T yhat and the voxel means aref (not differentiable). Its backward runs
 gsc_ste_backward: the quantizer passes gradients unchanged, the transform's adjoint (the
 inverse RAHT) maps them back to voxels, and each Gaussian receives its voxel's gradient divided
-by the voxel's member count.
+by the voxel's member count. Nv is only known once the encoder has run, so this form waits for
+the device to cut the outputs to Nv rows.
+
+SteCoderPadded.apply(attr, pos, params) is the same layer without that wait, for training loops
+and graph capture: it returns n rows (rows past Nv are zero) and Nv as a one-element device
+tensor. Nothing in its forward or backward synchronizes the host. A device-detected error
+(corrupt input, capacity) leaves Nv = 0, which makes rd_loss's distortion NaN.
 
 rd_loss is the rate-distortion objective of the differentiable workload: the mean squared error
 of the decoded attributes against the voxel means plus lambda times the rate proxy
@@ -18,6 +24,20 @@ import torch
 from . import gsc
 
 
+def _backward(ctx, g_yhat, g_ahat):
+    fwd = ctx.fwd
+    C = fwd.encoded.C
+    dev = fwd.yhat.device
+    z = None
+    if g_yhat is None or g_ahat is None:
+        z = torch.zeros((max(fwd.n, 1), C), dtype=torch.float32, device=dev)
+    gy = z if g_yhat is None else g_yhat.float().contiguous()
+    ga = z if g_ahat is None else g_ahat.float().contiguous()
+    # the kernels read rows < Nv of the gradients (Nv from the workspace, on the device)
+    grad, _info = gsc.ste_backward(fwd, gy, ga)
+    return grad[:fwd.n]
+
+
 class SteCoder(torch.autograd.Function):
     @staticmethod
     def forward(ctx, attr, pos, params):
@@ -26,27 +46,64 @@ class SteCoder(torch.autograd.Function):
         fwd = gsc.ste_forward(pos.contiguous(), attr.detach().contiguous(), params)
         fwd.encoded.check()                 # synchronizes: Nv sizes the outputs
         nv = fwd.encoded.n_vox()
-        ctx.fwd, ctx.nv = fwd, nv
+        ctx.fwd = fwd
         aref = fwd.aref[:nv]
         ctx.mark_non_differentiable(aref)
         return fwd.yhat[:nv], fwd.ahat[:nv], aref
 
     @staticmethod
     def backward(ctx, g_yhat, g_ahat, _g_aref):
-        fwd, nv = ctx.fwd, ctx.nv
-        C = fwd.encoded.C
-        dev = fwd.yhat.device
-        z = None
-        if g_yhat is None or g_ahat is None:
-            z = torch.zeros((max(nv, 1), C), dtype=torch.float32, device=dev)
-        gy = z if g_yhat is None else g_yhat.float().contiguous()
-        ga = z if g_ahat is None else g_ahat.float().contiguous()
-        grad, info = gsc.ste_backward(fwd, gy, ga)
-        return grad[:fwd.n], None, None
+        return _backward(ctx, g_yhat, g_ahat), None, None
 
 
-def rd_loss(yhat, ahat, aref, steps, lam):
-    """(loss, distortion, rate): mean((ahat - aref)^2) + lam * sum(log2(1 + |yhat| / steps))."""
-    dist = ((ahat - aref) ** 2).mean()
-    rate = lam * torch.log2(1.0 + yhat.abs() / steps).sum()
+class SteCoderPadded(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, attr, pos, params):
+        if not attr.is_cuda:
+            raise ValueError("SteCoderPadded runs on the GPU only")
+        fwd = gsc.ste_forward(pos.contiguous(), attr.detach().contiguous(), params)
+        n = fwd.n
+        info = fwd.encoded.info
+        # Nv on the device (0 after a device-detected error); rows past it are masked to zero
+        nv = torch.where(info[0:1] == 0, info[1:2], torch.zeros_like(info[1:2])).to(torch.int64)
+        keep = (torch.arange(n, device=attr.device) < nv).unsqueeze(1)
+        ctx.fwd = fwd
+        out = [torch.where(keep, t[:n], torch.zeros((), dtype=t.dtype, device=t.device))
+               for t in (fwd.yhat, fwd.ahat, fwd.aref)]
+        ctx.mark_non_differentiable(out[2], nv)
+        return out[0], out[1], out[2], nv
+
+    @staticmethod
+    def backward(ctx, g_yhat, g_ahat, _g_aref, _g_nv):
+        return _backward(ctx, g_yhat, g_ahat), None, None
+
+
+def staged_sum(x, width=256):
+    """The sum of every element of x, taken in stages of `width` contiguous values per output
+    (zero-padded). Each stage is a reduction whose outputs each come from one workgroup, so no
+    stage needs the cross-workgroup semaphores that a single large reduction clears with a
+    memset: the sum stays free of memset nodes when it is captured into a HIP graph."""
+    x = x.reshape(-1)
+    while x.numel() > 1:
+        pad = (-x.numel()) % width
+        if pad:
+            x = torch.nn.functional.pad(x, (0, pad))
+        x = x.view(-1, width).sum(dim=1)
+    return x.reshape(())
+
+
+def rd_loss(yhat, ahat, aref, steps, lam, nv=None):
+    """(loss, distortion, rate): mean((ahat - aref)^2) + lam * sum(log2(1 + |yhat| / steps)).
+
+    With nv (SteCoderPadded's device count) the rows are the padded ones: the mean is taken over
+    the nv voxel rows (the zero rows past them add nothing to either term), and both sums are
+    staged (staged_sum), so that the whole step can be captured into a graph."""
+    sq = (ahat - aref) ** 2
+    r = torch.log2(1.0 + yhat.abs() / steps)
+    if nv is None:
+        dist = sq.mean()
+        rate = lam * r.sum()
+    else:
+        dist = staged_sum(sq) / (nv.to(sq.dtype) * sq.shape[1]).reshape(())
+        rate = lam * staged_sum(r)
     return dist + rate, dist, rate

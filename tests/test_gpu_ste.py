@@ -165,3 +165,61 @@ def test_ste_backward_repeatable_and_checks_workspace():
     _, i3 = gsc.ste_backward(plain, gy, ga, out=out)
     torch.cuda.synchronize()
     assert int(i3[0]) == 1 and bool((out == 7.0).all())
+
+
+def test_padded_layer_matches_without_host_synchronization():
+    """SteCoderPadded gives SteCoder's outputs, loss and gradient, and a whole training step with
+    it (forward, loss, backward) makes no host synchronization: torch's sync-debug mode, set to
+    raise, lets it through (it raises on the synchronizing layer)."""
+    from paper_2606_05650_amd.ste import SteCoder, SteCoderPadded, rd_loss
+    dev = _dev()
+    pos, attr = synth.make_frame(20_000, seed=43)
+    J, lam = 9, 0.01
+    n, C = attr.shape
+    print(f"case n={n} J={J} padded layer", flush=True)
+    p = gsc.make_params(J, C, GROUPED)
+    tp = torch.from_numpy(pos).to(dev)
+    steps = torch.from_numpy(GROUPED).to(dev)
+    ta = torch.from_numpy(attr).to(dev).requires_grad_(True)
+    yhat, ahat, aref = SteCoder.apply(ta, tp, p)
+    loss, _, _ = rd_loss(yhat, ahat, aref, steps, lam)
+    loss.backward()
+    torch.cuda.synchronize()
+    nv = yhat.shape[0]
+    want_loss, want_grad = float(loss), ta.grad.clone()
+
+    tb = torch.from_numpy(attr).to(dev).requires_grad_(True)
+
+    def step():
+        y, a, r, nvt = SteCoderPadded.apply(tb, tp, p)
+        l, _, _ = rd_loss(y, a, r, steps, lam, nv=nvt)
+        l.backward()
+        return y, a, r, nvt, l
+
+    y, a, r, nvt, l = step()
+    torch.cuda.synchronize()
+    assert int(nvt.item()) == nv
+    assert y.shape == (n, C)
+    assert torch.equal(y[:nv], yhat.detach()) and torch.equal(a[:nv], ahat.detach())
+    assert torch.equal(r[:nv], aref)
+    assert not y[nv:].any() and not a[nv:].any() and not r[nv:].any()
+    assert abs(float(l) - want_loss) <= 1e-5 * abs(want_loss)
+    torch.testing.assert_close(tb.grad, want_grad, rtol=1e-5, atol=1e-9)
+    first_grad = tb.grad.clone()
+
+    # the same step again with every torch-side host synchronization turned into an error
+    tb.grad = None
+    torch.cuda.set_sync_debug_mode("error")
+    try:
+        out = step()
+        with pytest.raises(RuntimeError):
+            tb.grad = None
+            SteCoder.apply(tb, tp, p)  # cuts its outputs to Nv rows: synchronizes
+    finally:
+        torch.cuda.set_sync_debug_mode("default")
+    torch.cuda.synchronize()
+    assert int(out[3].item()) == nv and float(out[4]) == float(l)
+    tb.grad = None
+    step()
+    torch.cuda.synchronize()
+    assert torch.equal(tb.grad, first_grad)
