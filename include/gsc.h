@@ -360,12 +360,12 @@ typedef enum gsc_stage {
     GSC_STAGE_DECODE = 1,      /* a whole gsc_decode_frame / gsc_decode_batch call           */
     GSC_STAGE_SORT = 2,        /* voxelize + all radix sort passes + unique                  */
     GSC_STAGE_OCCUPANCY = 3,   /* the occupancy-byte kernel                                  */
-    GSC_STAGE_PRELUDE = 4,     /* all RAHT prelude launches of a call                        */
-    GSC_STAGE_RAHT_FWD1 = 5,   /* first-level forward RAHT (merge + transform + quantize)    */
-    GSC_STAGE_RAHT_FWD_TOP = 6,/* forward RAHT of the upper tiling levels                    */
+    GSC_STAGE_PRELUDE = 4,     /* the first-level RAHT schedule launch (encoder, transforms) */
+    GSC_STAGE_RAHT_FWD1 = 5,   /* the forward RAHT launch: merge, every level, quantize      */
+    GSC_STAGE_RAHT_FWD_TOP = 6,/* (unused: the upper levels run in the forward launch)       */
     GSC_STAGE_RAHT_INV1 = 7,   /* first-level inverse RAHT (dequantize + transform + rows)   */
     GSC_STAGE_RAHT_INV_TOP = 8,/* inverse RAHT of the upper tiling levels                    */
-    GSC_STAGE_OCTREE_DEC = 9,  /* octree expansion + Morton decode + voxel centres           */
+    GSC_STAGE_OCTREE_DEC = 9,  /* octree expansion, Morton decode, centres, level-1 schedule */
     GSC_STAGE_COUNT = 10
 } gsc_stage;
 

@@ -12,7 +12,6 @@
 namespace gsc {
 uint32_t voxelize_blocks(uint32_t n);
 uint32_t prelude_blocks(uint32_t tiles);
-uint32_t dec_leaves_blocks(uint32_t n);
 }  // namespace gsc
 
 using namespace gsc;
@@ -229,19 +228,21 @@ gsc_status run_prelude(const Frame *fr, int F, hipStream_t s)
 }
 
 // The forward transform of every tiling level of every frame, with the upper levels' schedules:
-// one persistent launch.
-gsc_status run_forward(const Frame *fr, int F, const RahtCfg &cfg, hipStream_t s)
+// one persistent launch. With `last`, the launch also ends the call (the finish step) if it
+// runs; *ended says whether it did.
+gsc_status run_forward(const Frame *fr, int F, const RahtCfg &cfg, bool last, bool *ended, hipStream_t s)
 {
     TileMap m = make_map(fr, F, [&cfg](const Frame &x) { return x.L.K >= 1 ? raht_blocks(x.L.tiles[1], 1, cfg.C4) : 0u; });
     if (m.start[F] == 0) return GSC_OK;
     StageScope sc(GSC_STAGE_RAHT_FWD1, s);
-    GSC_LAUNCH(launch_raht_fwd(m, max_K(fr, F), cfg, s));
+    GSC_LAUNCH(launch_raht_fwd(m, max_K(fr, F), last, cfg, s));
+    *ended = last;
     return GSC_OK;
 }
 
 // The inverse: the upper levels in one launch (which first builds their schedules when `prelude`
 // is set, i.e. when no forward of this workspace has built them), then the first level.
-gsc_status run_inverse(const Frame *fr, int F, const RahtCfg &cfg, bool prelude, hipStream_t s)
+gsc_status run_inverse(const Frame *fr, int F, const RahtCfg &cfg, bool prelude, bool *ended, hipStream_t s)
 {
     const int K = max_K(fr, F);
     if (K >= 2) {
@@ -252,12 +253,15 @@ gsc_status run_inverse(const Frame *fr, int F, const RahtCfg &cfg, bool prelude,
     TileMap m = make_map(fr, F, [&cfg](const Frame &x) { return raht_blocks(x.L.tiles[1], 1, cfg.C4); });
     if (m.start[F] == 0) return GSC_OK;
     StageScope sc(GSC_STAGE_RAHT_INV1, s);
-    GSC_LAUNCH(launch_raht_inv(m, cfg, s));
+    GSC_LAUNCH(launch_raht_inv(m, true, cfg, s));  // (always a call's last launch)
+    *ended = true;
     return GSC_OK;
 }
 
-gsc_status run_finish(const Frame *fr, int F, hipStream_t s)
+// The finish step, unless the call's last transform launch has done it.
+gsc_status run_finish(const Frame *fr, int F, bool ended, hipStream_t s)
 {
+    if (ended) return GSC_OK;
     TileMap m = make_map(fr, F, [](const Frame &) { return 1u; });
     GSC_LAUNCH(launch_finish(m, s));
     return GSC_OK;
@@ -332,9 +336,10 @@ gsc_status encode_frames(const Frame *fr, int F, const gsc_params *p, hipStream_
     }
     const RahtCfg cfg = raht_cfg(fr, F, p->C, p->quant_step);
     if ((st = run_prelude(fr, F, s)) != GSC_OK) return st;
-    if ((st = run_forward(fr, F, cfg, s)) != GSC_OK) return st;
-    if (ste && (st = run_inverse(fr, F, cfg, false, s)) != GSC_OK) return st;
-    return run_finish(fr, F, s);
+    bool ended = false;
+    if ((st = run_forward(fr, F, cfg, !ste, &ended, s)) != GSC_OK) return st;
+    if (ste && (st = run_inverse(fr, F, cfg, false, &ended, s)) != GSC_OK) return st;
+    return run_finish(fr, F, ended, s);
 }
 
 gsc_status decode_frames(const Frame *fr, int F, int J, int C, hipStream_t s)
@@ -349,15 +354,15 @@ gsc_status decode_frames(const Frame *fr, int F, int J, int C, hipStream_t s)
             TileMap m = make_map(fr, F, [](const Frame &x) { return x.L.dec_tiles; });
             GSC_LAUNCH(launch_dec_expand(m, s));
         }
-        {
-            TileMap m = make_map(fr, F, [](const Frame &x) { return dec_leaves_blocks(x.a.n); });
-            GSC_LAUNCH(launch_dec_leaves(m, s));
+        {   // the leaves and the first level's schedule
+            TileMap m = make_map(fr, F, [](const Frame &x) { return x.L.K >= 1 ? prelude_blocks(x.L.tiles[1]) : 0u; });
+            if (m.start[F] > 0) GSC_LAUNCH(launch_dec_prelude(m, s));
         }
     }
     const RahtCfg cfg = raht_cfg(fr, F, C, nullptr);
-    if ((st = run_prelude(fr, F, s)) != GSC_OK) return st;
-    if ((st = run_inverse(fr, F, cfg, true, s)) != GSC_OK) return st;
-    return run_finish(fr, F, s);
+    bool ended = false;
+    if ((st = run_inverse(fr, F, cfg, true, &ended, s)) != GSC_OK) return st;
+    return run_finish(fr, F, ended, s);
 }
 
 bool layout_for(int64_t n, int J, int C, Layout *L) { return make_layout(n, J, C, L); }
@@ -735,16 +740,17 @@ static gsc_status raht_f32(const uint64_t *d_codes, int64_t nv, int32_t J, int32
     hipStream_t s = static_cast<hipStream_t>(stream);
     const SetupArgs proto = make_proto((uint32_t)J, (uint32_t)C, adjoint ? MODE_ADJ_F32 : MODE_FWD_F32, nullptr);
     if ((st = run_setup(&fr, 1, proto, s)) != GSC_OK) return st;
+    bool ended = false;
     if (nv > 0) {
         if ((st = run_prelude(&fr, 1, s)) != GSC_OK) return st;
         const RahtCfg cfg = raht_cfg(&fr, 1, C, nullptr);
         if (adjoint)
-            st = run_inverse(&fr, 1, cfg, true, s);
+            st = run_inverse(&fr, 1, cfg, true, &ended, s);
         else
-            st = run_forward(&fr, 1, cfg, s);
+            st = run_forward(&fr, 1, cfg, true, &ended, s);
         if (st != GSC_OK) return st;
     }
-    return run_finish(&fr, 1, s);
+    return run_finish(&fr, 1, ended, s);
 }
 
 gsc_status gsc_ste_forward(const float *d_pos, const float *d_attr, int64_t n,
@@ -831,11 +837,12 @@ gsc_status gsc_ste_backward(int64_t n, int32_t J, int32_t C, const float *d_grad
     proto.ste = STE_FORWARD;  // the workspace keeps holding the forward's schedule
     proto.keep = 1;
     if ((st = run_setup(&fr, 1, proto, s)) != GSC_OK) return st;
+    bool ended = false;
     if (n > 0) {
         const RahtCfg cfg = raht_cfg(&fr, 1, C, nullptr);
-        if ((st = run_inverse(&fr, 1, cfg, false, s)) != GSC_OK) return st;
+        if ((st = run_inverse(&fr, 1, cfg, false, &ended, s)) != GSC_OK) return st;
     }
-    return run_finish(&fr, 1, s);
+    return run_finish(&fr, 1, ended, s);
 }
 
 gsc_status gsc_raht_forward(const uint64_t *d_codes, int64_t nv, int32_t J, int32_t C,

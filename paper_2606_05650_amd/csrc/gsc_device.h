@@ -538,4 +538,110 @@ __device__ inline int32_t quantize_pow2(float y, float inv_step, float thr)
     return y < 0.0f ? -q : q;
 }
 
+// ------------------------------------------------------------------ end of a call
+// Stream geometry from the new-node depth histogram: |L_d| = #{v : D_v <= d}; level d's bytes
+// start at GSC_HEADER_BYTES + sum_{d' < d} |L_d'|; the coefficients at the next multiple of 256.
+struct StreamGeom {
+    uint32_t level_sizes[GSC_MAX_DEPTH + 1];
+    uint64_t occ_off[GSC_MAX_DEPTH + 1];
+    uint64_t occ_bytes, coef_offset, total;
+};
+// LDS of one wave finishing one frame (indexed by depth or level: in registers it would live in
+// scratch).
+struct FinishScratch {
+    uint32_t hist[GSC_MAX_DEPTH + 2], lvl[MAXK + 2];
+    uint32_t err, nv;
+    StreamGeom g;
+};
+__device__ inline void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+// One wave (lane t) ends frame fd's call: the device status goes to the info words and (encode)
+// the stream header is written. The counters are loaded by all lanes at once and the header
+// fields written in parallel: a single lane would pay one memory latency per dependent step.
+__device__ inline void finish_frame(const CAS FrameDesc &fd, uint32_t t, FinishScratch &S)
+{
+    Ctrl *ctrl = fd.ctrl;
+    const uint32_t J = fd.J, K = fd.K;
+    if (t <= GSC_MAX_DEPTH) S.hist[t] = t <= J ? ctrl->hist_D[t] : 0u;
+    if (t <= MAXK) S.lvl[t] = t <= K ? ctrl->lvl_n[t] : 0u;
+    if (t == 0) {
+        S.err = load_error(ctrl);
+        S.nv = ctrl->n_vox;
+    }
+    wave_sync();
+    const uint32_t err = S.err, nv = S.nv;
+    uint64_t total = 0;
+    StreamGeom &g = S.g;
+    if (fd.mode == MODE_ENCODE) {
+        if (t == 0) {
+            uint32_t run = 0;
+            uint64_t off = GSC_HEADER_BYTES;
+            for (uint32_t d = 0; d <= J; ++d) {
+                run += S.hist[d];
+                g.level_sizes[d] = run;
+                g.occ_off[d] = off;
+                if (d < J) off += run;
+            }
+            g.occ_bytes = off - GSC_HEADER_BYTES;
+            g.coef_offset = align_up(off, 256);
+            g.total = g.coef_offset + (uint64_t)nv * fd.C * 4;
+        }
+        wave_sync();
+        total = g.total;
+        gsc_header *h = reinterpret_cast<gsc_header *>(fd.stream);
+        for (uint32_t b = sizeof(gsc_header) + t; b < GSC_HEADER_BYTES; b += WAVE) fd.stream[b] = 0;
+        for (uint64_t b = GSC_HEADER_BYTES + g.occ_bytes + t; b < g.coef_offset; b += WAVE) fd.stream[b] = 0;
+        if (t < 22) h->level_sizes[t] = t <= J ? g.level_sizes[t] : 0u;
+        h->quant_step[t] = t < fd.C ? fd.step[t] : 0.0f;
+        if (t < 3) h->bbox_min[t] = ctrl->bbox_min[t];
+        if (t == 0) {
+            h->magic = GSC_MAGIC;
+            h->version = GSC_VERSION;
+            h->J = J;
+            h->C = fd.C;
+            h->n_in = fd.n;
+            h->n_vox = nv;
+            h->error = err;
+            h->flags = fd.flags;
+            h->cell = ctrl->cell;
+            h->tau = fd.tau;
+            h->reserved1 = 0;
+            h->occ_offset = GSC_HEADER_BYTES;
+            h->occ_bytes = g.occ_bytes;
+            h->coef_offset = g.coef_offset;
+            h->coef_bytes = (uint64_t)nv * fd.C * 4;
+            h->total_bytes = g.total;
+        }
+    }
+    if (fd.info && t == 0) {
+        fd.info[0] = (int32_t)err;
+        fd.info[1] = (int32_t)nv;
+        fd.info[2] = (int32_t)(uint32_t)(total & 0xFFFFFFFFu);
+        fd.info[3] = (int32_t)(uint32_t)(total >> 32);
+        uint32_t used = 0;
+        for (uint32_t k = 1; k <= K; ++k)
+            if (k == 1 ? nv >= 1 : S.lvl[k] >= 2) used = k;
+        fd.info[4] = (int32_t)used;
+    }
+}
+
+// ------------------------------------------------------------------ decoded leaves
+// Writes decoded leaf v: its voxel centre min + (coordinate + 1/2) * cell (FP64, rounded once to
+// float) and, when asked for, its code and voxel coordinates.
+template <class FD>
+__device__ inline void emit_leaf(FD &fd, const gsc_header *h, uint32_t v, uint64_t code)
+{
+    if (fd.codes_out) gp(fd.codes_out)[v] = code;
+    const uint32_t xyz[3] = {compact3(code), compact3(code >> 1), compact3(code >> 2)};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (fd.vox_out) gp(fd.vox_out)[(size_t)v * 3 + a] = xyz[a];
+        const double c = __dadd_rn(h->bbox_min[a], __dmul_rn(__dadd_rn((double)xyz[a], 0.5), h->cell));
+        gp(fd.pos_out)[(size_t)v * 3 + a] = (float)c;
+    }
+}
+
 }  // namespace gsc

@@ -43,7 +43,6 @@ constexpr int OCC_TILE = OCC_THREADS * OCC_VPT;
 constexpr int DEC_THREADS = 256;
 constexpr int DEC_PPT = 16;             // occupancy bytes per thread
 constexpr int DEC_TILE = DEC_THREADS * DEC_PPT;
-constexpr int LEAF_THREADS = 256;       // two leaves per thread (k_dec_leaves)
 
 constexpr int RT = 512;                 // RAHT tile: entries (eight 64-entry wave chunks)
 constexpr int RAHT_THREADS = 512;       // one wave per chunk
@@ -62,10 +61,11 @@ constexpr uint32_t UP_GRID_MAX = 1024;
 constexpr uint32_t PHASE_PRELUDE = 0;  // flag base of the schedule launch
 // Counters of the transform launches, in DONE_WORDS words after the flags, zeroed by every
 // call: the finished items of every tiling level (forward: DONE_FWD + k, inverse: DONE_INV + k),
-// the first-level item tickets of each XCD (TK_FWD + x, TK_INV + x), the upper items' tickets
-// of the forward (TK_UPF), and the workgroups done with the upper levels' schedules (PRE_DONE).
-constexpr uint32_t DONE_WORDS = 128, DONE_FWD = 0, DONE_INV = 32, TK_FWD = 64, TK_INV = 72, TK_UPF = 80,
-                   PRE_DONE = 81;
+// the upper items' tickets of the forward (TK_UPF), the workgroups done with the upper levels'
+// schedules (PRE_DONE), and the workgroups that have ended the first-level forward and inverse
+// launches (FIN_FWD, FIN_INV).
+constexpr uint32_t DONE_WORDS = 128, DONE_FWD = 0, DONE_INV = 32, TK_UPF = 80, PRE_DONE = 81, FIN_FWD = 82,
+                   FIN_INV = 83;
 static_assert(MAXK + 1 <= 32, "one completion counter per tiling level and direction");
 
 // Bounding box: at most BBOX_GRID_MAX workgroups per frame, each leaving its partial minima and
@@ -357,7 +357,8 @@ hipError_t launch_sort_pass(const TileMap &m, int pass, int variant, int bits, h
 hipError_t launch_dedup(const TileMap &m, hipStream_t s);
 hipError_t launch_occupancy(const TileMap &m, hipStream_t s);
 hipError_t launch_dec_expand(const TileMap &m, hipStream_t s);
-hipError_t launch_dec_leaves(const TileMap &m, hipStream_t s);
+// the decoder's leaves and first-level schedule (one workgroup per first-level tile)
+hipError_t launch_dec_prelude(const TileMap &m, hipStream_t s);
 hipError_t launch_prelude(const TileMap &m, int k, hipStream_t s);
 // Compile-time specializations of the transform kernels: vec = C % 4 == 0 and every row
 // pointer 16-byte aligned; pow2 = every quantization step a power of two.
@@ -370,8 +371,9 @@ uint32_t channel_slices_upper(int C4);                // channel slices of an up
 // The forward transform of all tiling levels, with the upper levels' schedules, in one persistent
 // launch; the first-level inverse (after launch_raht_inv_up). m maps the first-level items to
 // frames; kmax is the largest tiling level over the frames.
-hipError_t launch_raht_fwd(const TileMap &m, int kmax, const RahtCfg &cfg, hipStream_t s);
-hipError_t launch_raht_inv(const TileMap &m, const RahtCfg &cfg, hipStream_t s);
+// finish: the launch is the call's last and ends it (its last workgroup runs finish_frame)
+hipError_t launch_raht_fwd(const TileMap &m, int kmax, bool finish, const RahtCfg &cfg, hipStream_t s);
+hipError_t launch_raht_inv(const TileMap &m, bool finish, const RahtCfg &cfg, hipStream_t s);
 // The upper levels' inverse (2 .. kmax; only m.F and m.fd are used) in one persistent launch,
 // before launch_raht_inv; with `prelude`, the launch first builds the upper levels' schedules.
 // items_max: the worst-case items of the largest upper level over the launch's frames.

@@ -164,102 +164,15 @@ hipError_t launch_setup(const SetupArgs &a, uint32_t zero_blocks, hipStream_t s)
     return hipGetLastError();
 }
 
-// Stream geometry from the new-node depth histogram: |L_d| = #{v : D_v <= d}; level d's bytes
-// start at GSC_HEADER_BYTES + sum_{d' < d} |L_d'|; the coefficients at the next multiple of 256.
-struct StreamGeom {
-    uint32_t level_sizes[GSC_MAX_DEPTH + 1];
-    uint64_t occ_off[GSC_MAX_DEPTH + 1];
-    uint64_t occ_bytes, coef_offset, total;
-};
-__device__ inline void stream_geom(const Ctrl *ctrl, uint32_t J, uint32_t C, StreamGeom *g)
-{
-    uint32_t run = 0;
-    uint64_t off = GSC_HEADER_BYTES;
-    for (uint32_t d = 0; d <= J; ++d) {
-        run += ctrl->hist_D[d];
-        g->level_sizes[d] = run;
-        g->occ_off[d] = off;
-        if (d < J) off += run;
-    }
-    g->occ_bytes = off - GSC_HEADER_BYTES;
-    g->coef_offset = align_up(off, 256);
-    g->total = g->coef_offset + (uint64_t)ctrl->n_vox * C * 4;
-}
-
-// One block of 64 threads per frame: copy the device status to the info words, and (encode)
-// write the stream header. The counters are loaded by all threads at once and the header
-// fields written in parallel: a single thread would pay one memory latency per dependent step.
+// One block (one wave) per frame ends the call (finish_frame): used when the call's last launch
+// is not a transform launch, which otherwise does it in its last workgroup.
 __global__ __launch_bounds__(64) void k_finish(TileMap m)
 {
+    static_assert(WAVE == 64, "one wave per frame");
     const uint32_t f = blockIdx.x;
     if (f >= m.F) return;
-    const CAS FrameDesc &fd = *cp(m.fd[f]);  // (not written while the kernel runs)
-    Ctrl *ctrl = fd.ctrl;
-    const uint32_t t = threadIdx.x;
-    const uint32_t J = fd.J, K = fd.K;
-    __shared__ uint32_t s_hist[GSC_MAX_DEPTH + 2], s_lvl[MAXK + 2];
-    __shared__ uint32_t s_err, s_nv;
-    __shared__ StreamGeom g;  // in LDS: indexed by depth, it would otherwise live in scratch
-    if (t <= GSC_MAX_DEPTH) s_hist[t] = t <= J ? ctrl->hist_D[t] : 0u;
-    if (t <= MAXK) s_lvl[t] = t <= K ? ctrl->lvl_n[t] : 0u;
-    if (t == 0) {
-        s_err = load_error(ctrl);
-        s_nv = ctrl->n_vox;
-    }
-    __syncthreads();
-    const uint32_t err = s_err, nv = s_nv;
-    uint64_t total = 0;
-    if (fd.mode == MODE_ENCODE) {
-        if (t == 0) {
-            uint32_t run = 0;
-            uint64_t off = GSC_HEADER_BYTES;
-            for (uint32_t d = 0; d <= J; ++d) {
-                run += s_hist[d];
-                g.level_sizes[d] = run;
-                g.occ_off[d] = off;
-                if (d < J) off += run;
-            }
-            g.occ_bytes = off - GSC_HEADER_BYTES;
-            g.coef_offset = align_up(off, 256);
-            g.total = g.coef_offset + (uint64_t)nv * fd.C * 4;
-        }
-        __syncthreads();
-        total = g.total;
-        gsc_header *h = reinterpret_cast<gsc_header *>(fd.stream);
-        for (uint32_t b = sizeof(gsc_header) + t; b < GSC_HEADER_BYTES; b += 64) fd.stream[b] = 0;
-        for (uint64_t b = GSC_HEADER_BYTES + g.occ_bytes + t; b < g.coef_offset; b += 64) fd.stream[b] = 0;
-        if (t < 22) h->level_sizes[t] = t <= J ? g.level_sizes[t] : 0u;
-        h->quant_step[t] = t < fd.C ? fd.step[t] : 0.0f;
-        if (t < 3) h->bbox_min[t] = ctrl->bbox_min[t];
-        if (t == 0) {
-            h->magic = GSC_MAGIC;
-            h->version = GSC_VERSION;
-            h->J = J;
-            h->C = fd.C;
-            h->n_in = fd.n;
-            h->n_vox = nv;
-            h->error = err;
-            h->flags = fd.flags;
-            h->cell = ctrl->cell;
-            h->tau = fd.tau;
-            h->reserved1 = 0;
-            h->occ_offset = GSC_HEADER_BYTES;
-            h->occ_bytes = g.occ_bytes;
-            h->coef_offset = g.coef_offset;
-            h->coef_bytes = (uint64_t)nv * fd.C * 4;
-            h->total_bytes = g.total;
-        }
-    }
-    if (fd.info && t == 0) {
-        fd.info[0] = (int32_t)err;
-        fd.info[1] = (int32_t)nv;
-        fd.info[2] = (int32_t)(uint32_t)(total & 0xFFFFFFFFu);
-        fd.info[3] = (int32_t)(uint32_t)(total >> 32);
-        uint32_t used = 0;
-        for (uint32_t k = 1; k <= K; ++k)
-            if (k == 1 ? nv >= 1 : s_lvl[k] >= 2) used = k;
-        fd.info[4] = (int32_t)used;
-    }
+    __shared__ FinishScratch S;
+    finish_frame(*cp(m.fd[f]), threadIdx.x, S);
 }
 
 hipError_t launch_finish(const TileMap &m, hipStream_t s)
@@ -909,24 +822,8 @@ hipError_t launch_occupancy(const TileMap &m, hipStream_t s)
 // stream is node P(q), the number of set bits in the bytes before it: one prefix sum over all
 // bytes places every child. `k_dec_expand` writes for every node its parent's index in the
 // parent's level and its child bit i (its code is the parent's code times 8 plus i);
-// `k_dec_leaves` then builds each leaf's code from the child bits along its path to the root,
+// `k_dec_prelude` then builds each leaf's code from the child bits along its path to the root,
 // most significant first, which is the code the level-by-level expansion produces.
-
-// Writes leaf v: its code, voxel coordinates and centre min + (v + 1/2) * cell (FP64, rounded
-// once to float).
-template <class FD>
-__device__ inline void emit_leaf(FD &fd, const gsc_header *h, uint32_t v, uint64_t code)
-{
-    gp(fd.leaf)[v] = code;
-    if (fd.codes_out) gp(fd.codes_out)[v] = code;
-    const uint32_t xyz[3] = {compact3(code), compact3(code >> 1), compact3(code >> 2)};
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        if (fd.vox_out) gp(fd.vox_out)[(size_t)v * 3 + a] = xyz[a];
-        const double c = __dadd_rn(h->bbox_min[a], __dmul_rn(__dadd_rn((double)xyz[a], 0.5), h->cell));
-        gp(fd.pos_out)[(size_t)v * 3 + a] = (float)c;
-    }
-}
 
 // Header checks: everything the decoder relies on must be self-consistent and fit the caller's
 // buffers. Performed by one wave, lane l checking level l's size against the next one and the
@@ -1084,62 +981,5 @@ hipError_t launch_dec_expand(const TileMap &m, hipStream_t s)
     return hipGetLastError();
 }
 
-// One thread per leaf: the leaf's code from the child bits on its path to the root (level J's bit
-// least significant), then its voxel coordinates and centre.
-// LEAF_PPT leaves per thread (leaves b LEAF_TILE + t + x LEAF_THREADS), their walks interleaved:
-// one leaf per thread would need two rounds of workgroups at 1M, and a leaf's walk is a chain of
-// dependent loads that a second, independent chain hides.
-constexpr int LEAF_PPT = 2;
-constexpr uint32_t LEAF_TILE = LEAF_THREADS * LEAF_PPT;
-__global__ __launch_bounds__(LEAF_THREADS) void k_dec_leaves(TileMap m)
-{
-    const uint32_t f = frame_of(m, blockIdx.x);
-    const CAS FrameDesc &fd = *cp(m.fd[f]);  // (not written while the kernel runs)
-    Ctrl *ctrl = fd.ctrl;
-    if (__builtin_amdgcn_readfirstlane(load_error(ctrl))) return;
-    const gsc_header *hg = reinterpret_cast<const gsc_header *>(fd.in_stream);
-    const CAS gsc_header *h = cp(hg);
-    const uint32_t J = fd.J, nv = h->n_vox;
-    const uint32_t v0 = tile_index(m, f) * LEAF_TILE + threadIdx.x;
-    if (v0 >= nv) return;
-    const GAS uint32_t *par = gp(fd.dec_par);
-    const GAS uint8_t *cbit = gp(fd.dec_cbit);
-    uint64_t qL = 0;  // Q(L): nodes of levels 1..L-1
-    for (uint32_t L = 1; L < J; ++L) qL += h->level_sizes[L];
-    uint64_t code[LEAF_PPT];
-    uint32_t x[LEAF_PPT];
-#pragma unroll
-    for (int i = 0; i < LEAF_PPT; ++i) {
-        code[i] = 0;
-        x[i] = min(v0 + i * LEAF_THREADS, nv - 1);  // (a leaf past the end walks the last one's path)
-    }
-    for (uint32_t L = J; L >= 1; --L) {
-        const uint32_t size = h->level_sizes[L];
-        uint64_t g[LEAF_PPT];
-        uint32_t cb[LEAF_PPT];
-#pragma unroll
-        for (int i = 0; i < LEAF_PPT; ++i) g[i] = qL + min(x[i], size - 1);  // (clamped: never an access outside the nodes)
-#pragma unroll
-        for (int i = 0; i < LEAF_PPT; ++i) {
-            cb[i] = cbit[g[i]];
-            x[i] = par[g[i]];
-        }
-#pragma unroll
-        for (int i = 0; i < LEAF_PPT; ++i) code[i] |= (uint64_t)cb[i] << (3 * (J - L));
-        if (L > 1) qL -= h->level_sizes[L - 1];
-    }
-#pragma unroll
-    for (int i = 0; i < LEAF_PPT; ++i) {
-        const uint32_t v = v0 + i * LEAF_THREADS;
-        if (v < nv) emit_leaf(fd, hg, v, code[i]);
-    }
-}
-uint32_t dec_leaves_blocks(uint32_t n) { return ceil_div(n ? n : 1u, LEAF_TILE); }
-
-hipError_t launch_dec_leaves(const TileMap &m, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_dec_leaves, dim3(m.start[m.F]), dim3(LEAF_THREADS), 0, s, m);
-    return hipGetLastError();
-}
 
 }  // namespace gsc

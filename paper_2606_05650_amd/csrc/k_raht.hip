@@ -42,13 +42,14 @@ constexpr int CROSS = NCHUNK;  // class of merges that cross chunks
 // leaves at most 6J + 2 entries open) is reported and treated as empty.
 // LIVE: the size may have been written during the running launch (a persistent upper-level
 // launch), so it is read with a device-coherent load; otherwise it was written by an earlier
-// kernel and is read through the constant address space.
+// kernel and is read through the constant address space. The sizes of S_1 and S_2 always come
+// from earlier launches (the first level's schedule is a launch of its own).
 template <bool LIVE = false, class FD>
 __device__ inline uint32_t seq_size(FD &fd, Ctrl *ctrl, int k)
 {
     const uint32_t nk = k == 1 ? cp(ctrl)->n_vox
-                       : LIVE ? __builtin_amdgcn_readfirstlane(__hip_atomic_load(&ctrl->lvl_n[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
-                              : cp(ctrl)->lvl_n[k];
+                       : (LIVE && k >= 3) ? __builtin_amdgcn_readfirstlane(__hip_atomic_load(&ctrl->lvl_n[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+                                          : cp(ctrl)->lvl_n[k];
     if (nk > fd.lv[k].cap) {
         set_error(ctrl, GSC_ERR_INTERNAL);
         return 0;
@@ -105,8 +106,10 @@ __device__ inline bool fp64_weights(FD &fd)
 // entries are known and whose prefix is resolved after the rest of the tile's work.
 constexpr int PRE_TILES = 1;  // tiles per workgroup
 
+// lc (first level only, or null): the codes of entries s - 1 .. s + RT of the tile starting at
+// entry s, in LDS (lc[j] = code of entry s - 1 + j); otherwise they are read from the leaf codes.
 template <bool LIVE, int PRE_EPT>
-__device__ inline void prelude_tile(const TileMap &m, uint32_t f, int k, uint32_t tile)
+__device__ inline void prelude_tile(const TileMap &m, uint32_t f, int k, uint32_t tile, const uint64_t *lc = nullptr)
 {
     static_assert(PRE_TILES == 1, "one tile per workgroup");
     constexpr int PRE_THREADS = RT / PRE_EPT, PRE_BLOCK = PRE_THREADS;
@@ -148,8 +151,8 @@ __device__ inline void prelude_tile(const TileMap &m, uint32_t f, int k, uint32_
 #pragma unroll
         for (int x = 0; x < PRE_EPT; ++x) {
             const uint32_t i = s + (uint32_t)min(jj[x], mlen - 1);
-            c0[x] = codes[i > 0 ? i - 1 : 0];
-            c1[x] = codes[i];
+            c0[x] = lc ? lc[i - s] : codes[i > 0 ? i - 1 : 0];
+            c1[x] = lc ? lc[i - s + 1] : codes[i];
         }
 #pragma unroll
         for (int x = 0; x < PRE_EPT; ++x)
@@ -167,7 +170,9 @@ __device__ inline void prelude_tile(const TileMap &m, uint32_t f, int k, uint32_
     }
 #pragma unroll
     for (int x = 0; x < PRE_EPT; ++x) s_rdl[jj[x]] = 0;
-    if (t == 0) s_lvl_e = e < nk ? (k == 1 ? merge_level(codes[e - 1], codes[e]) : slvl[e]) : LVL_NONE;
+    if (t == 0)
+        s_lvl_e = e < nk ? (k == 1 ? (lc ? merge_level(lc[RT], lc[RT + 1]) : merge_level(codes[e - 1], codes[e])) : slvl[e])
+                         : LVL_NONE;
     // active lists of the levels that can hold a merge: an entry merges at a level of at most 3J
     // (the tile's first entry of the sequence, LVL_NONE, is in every list and is never a right
     // sibling)
@@ -359,6 +364,75 @@ __global__ __launch_bounds__(PRE_BLOCK1) void k_prelude(TileMap m, int k)
     prelude_tile<false, PRE_EPT1>(m, f, k, tile_index(m, f));
 }
 
+// The decoder's leaves and first-level schedule in one launch. A workgroup takes the RT leaves
+// of one tile (two per thread, entries t and t + PRE_BLOCK1 as in the schedule) and the leaves
+// just before and after the tile (threads 0 and 1): each leaf's code from the child bits on its
+// path to the root (level J's bit least significant; J dependent loads of the node's child bit
+// and parent, written by the octree decoding launch, the three walks of a thread interleaved),
+// which is the code the level-by-level expansion produces (Alg. 2-3). The leaves' centres (and
+// codes and voxel coordinates when asked for) are written, and the codes go through LDS to the
+// tile's schedule (prelude_tile).
+__global__ __launch_bounds__(PRE_BLOCK1) void k_dec_prelude(TileMap m)
+{
+    static_assert(PRE_EPT1 == 2, "two leaves per thread");
+    __shared__ uint64_t s_code[RT + 2];
+    const uint32_t f = frame_of(m, blockIdx.x);
+    const uint32_t tile = tile_index(m, f);
+    const CAS FrameDesc &fd = *cp(m.fd[f]);  // (not written while the kernel runs)
+    if (__builtin_amdgcn_readfirstlane(load_error(fd.ctrl))) return;
+    const gsc_header *hg = reinterpret_cast<const gsc_header *>(fd.in_stream);
+    const CAS gsc_header *h = cp(hg);
+    const uint32_t J = fd.J, nv = h->n_vox;  // (checked by the octree decoding launch)
+    const uint32_t s = tile * RT;
+    if (s >= nv) return;
+    const uint32_t t = threadIdx.x;
+    const GAS uint32_t *par = gp(fd.dec_par);
+    const GAS uint8_t *cbit = gp(fd.dec_cbit);
+    // leaves v[0], v[1] of the tile; v[2]: s - 1 (thread 0) or s + RT (thread 1), else a repeat
+    uint32_t v[3], x[3];
+    uint64_t code[3];
+    v[0] = s + t;
+    v[1] = s + t + PRE_BLOCK1;
+    v[2] = t == 0 ? (s > 0 ? s - 1 : s) : (t == 1 ? s + RT : v[0]);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        code[i] = 0;
+        x[i] = min(v[i], nv - 1);  // (a leaf past the end walks the last one's path)
+    }
+    uint64_t qL = 0;  // Q(L): nodes of levels 1..L-1
+    for (uint32_t L = 1; L < J; ++L) qL += h->level_sizes[L];
+    for (uint32_t L = J; L >= 1; --L) {
+        const uint32_t size = h->level_sizes[L];
+        uint64_t g[3];
+        uint32_t cb[3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) g[i] = qL + min(x[i], size - 1);  // (clamped: never an access outside the nodes)
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            cb[i] = cbit[g[i]];
+            x[i] = par[g[i]];
+        }
+#pragma unroll
+        for (int i = 0; i < 3; ++i) code[i] |= (uint64_t)cb[i] << (3 * (J - L));
+        if (L > 1) qL -= h->level_sizes[L - 1];
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        if (v[i] < nv) emit_leaf(fd, hg, v[i], code[i]);
+        s_code[1 + t + i * PRE_BLOCK1] = code[i];
+    }
+    if (t == 0) s_code[0] = code[2];
+    if (t == 1) s_code[RT + 1] = code[2];
+    __syncthreads();
+    prelude_tile<false, PRE_EPT1>(m, f, 1, tile, s_code);
+}
+
+hipError_t launch_dec_prelude(const TileMap &m, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_dec_prelude, dim3(m.start[m.F]), dim3(PRE_BLOCK1), 0, s, m);
+    return hipGetLastError();
+}
+
 hipError_t launch_prelude(const TileMap &m, int k, hipStream_t s)
 {
     hipLaunchKernelGGL(k_prelude, dim3(m.start[m.F]), dim3(PRE_BLOCK1), 0, s, m, k);
@@ -375,8 +449,8 @@ hipError_t launch_prelude(const TileMap &m, int k, hipStream_t s)
 // (S_{k+1} is a subset of S_k's entries), so workgroups beyond a level's count leave.
 
 // Items of level k over the frames of the launch (each frame: its tiles of S_k times np), with
-// the frames' first items in s_fs[0..F]; uniform. lvl_n is read with device-coherent loads: a
-// schedule launch writes the next level's size while it runs.
+// the frames' first items in s_fs[0..F]; uniform. lvl_n[k], k >= 3, is read with device-coherent
+// loads: the running launch writes it (S_2's size comes from the first level's schedule launch).
 __device__ inline uint32_t level_items(const TileMap &m, int k, uint32_t np, uint32_t *s_fs)
 {
     if (threadIdx.x < WAVE) {
@@ -384,7 +458,8 @@ __device__ inline uint32_t level_items(const TileMap &m, int k, uint32_t np, uin
         if (threadIdx.x < m.F) {
             const CAS FrameDesc &fd = *cp(m.fd[threadIdx.x]);
             if ((uint32_t)k <= fd.K) {
-                const uint32_t nk = __hip_atomic_load(&fd.ctrl->lvl_n[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                const uint32_t nk = k >= 3 ? __hip_atomic_load(&fd.ctrl->lvl_n[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                                           : cp(fd.ctrl)->lvl_n[k];
                 if (nk >= 2 && nk <= fd.lv[k].cap) c = (nk + RT - 1) / RT * np;
             }
         }
@@ -787,7 +862,7 @@ __device__ inline float4 ld_coh4(const GAS float *p)
                        __uint_as_float((uint32_t)b), __uint_as_float((uint32_t)(b >> 32)));
 }
 
-// Counter word w of a transform launch (DONE_FWD + k, TK_INV + x, ...), in the workspace of the
+// Counter word w of a transform launch (DONE_FWD + k, TK_UPF, ...), in the workspace of the
 // launch's first frame; the completion counters count a level's finished items over all frames.
 __device__ inline GAS uint32_t *ctr_word(const TileMap &m, uint32_t w)
 {
@@ -828,6 +903,27 @@ __device__ inline void done_wait(const GAS uint32_t *c, uint32_t target, Ctrl *c
     __syncthreads();
 }
 
+// The last workgroup of a transform launch to end (counted on counter word w) ends every frame's
+// call (finish_frame, one wave per frame), so that a call whose last launch this is needs no
+// finish launch. Each wave has waited for its memory operations (device errors are reported by
+// atomics) before the workgroup is counted; the last one acquires before it reads the counters.
+// The transform's LDS (s_y) is free by then and holds the scratch.
+__device__ inline void finish_if_last(const TileMap &m, uint32_t w, float4 *s_y)
+{
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    uint32_t *s_last = reinterpret_cast<uint32_t *>(s_y);
+    if (threadIdx.x == 0)
+        s_last[0] = __hip_atomic_fetch_add(ctr_word(m, w), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1u == gridDim.x;
+    __syncthreads();
+    if (!s_last[0]) return;
+    if (threadIdx.x == 0) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    __syncthreads();
+    FinishScratch *S = reinterpret_cast<FinishScratch *>(s_y + 1);
+    const uint32_t wv = threadIdx.x / WAVE;
+    for (uint32_t f = wv; f < m.F; f += RAHT_THREADS / WAVE) finish_frame(*cp(m.fd[f]), lane_id(), S[wv]);
+}
+
 // ------------------------------------------------------------ the upper items of a launch
 // Items of upper level k (k >= 2) of frame f: the tiles of S_k times the channel slices NP. The
 // sizes of levels k >= 3 are written by the schedule workgroups of the same launch, so they are
@@ -836,20 +932,31 @@ __device__ inline uint32_t up_frame_items(const TileMap &m, uint32_t f, int k, u
 {
     const CAS FrameDesc &fd = *cp(m.fd[f]);
     if ((uint32_t)k > fd.K) return 0u;
-    const uint32_t nk = __hip_atomic_load(&fd.ctrl->lvl_n[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint32_t nk = k >= 3 ? __hip_atomic_load(&fd.ctrl->lvl_n[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                               : cp(fd.ctrl)->lvl_n[k];
     return (nk >= 2 && nk <= fd.lv[k].cap) ? (nk + RT - 1) / RT * NP : 0u;
 }
 static_assert(GSC_MAX_BATCH <= WAVE, "one wave counts the frames' items");
 
 // s_ucnt[k] = items of level k over the launch's frames (k = 2..kmax; s_ucnt[kmax + 1] = 0),
-// counted by wave 0. Returns their sum (after a barrier).
+// counted by wave 0. Returns their sum (after a barrier). The sizes of UP_BATCH levels are
+// loaded before any is used (one round trip for every level of a usual frame).
+constexpr int UP_BATCH = 8;
 __device__ inline uint32_t up_totals(const TileMap &m, int kmax, uint32_t NP, uint32_t *s_ucnt)
 {
     if (threadIdx.x < WAVE) {
         const uint32_t lane = lane_id();
-        for (int k = 2; k <= kmax; ++k) {
-            const uint32_t inc = wave_incl_scan(lane < m.F ? up_frame_items(m, lane, k, NP) : 0u);
-            if (lane == WAVE - 1) s_ucnt[k] = inc;
+        for (int k0 = 2; k0 <= kmax; k0 += UP_BATCH) {
+            uint32_t c[UP_BATCH];
+#pragma unroll
+            for (int q = 0; q < UP_BATCH; ++q)
+                c[q] = (k0 + q <= kmax && lane < m.F) ? up_frame_items(m, lane, k0 + q, NP) : 0u;
+#pragma unroll
+            for (int q = 0; q < UP_BATCH; ++q) {
+                if (k0 + q > kmax) break;
+                const uint32_t inc = wave_incl_scan(c[q]);
+                if (lane == WAVE - 1) s_ucnt[k0 + q] = inc;
+            }
         }
         if (lane == 0) s_ucnt[kmax + 1 > 1 ? kmax + 1 : 1] = 0;
     }
@@ -874,6 +981,12 @@ __device__ inline UpItem up_item(const TileMap &m, int kmax, bool desc, uint32_t
     for (int o = 0; 2 + o <= kmax; ++o) {
         const int k = desc ? kmax - o : 2 + o;
         const uint32_t c = s_ucnt[k];
+        if (g < c && m.F == 1) {  // one frame: its items are the level's
+            u.k = k;
+            u.tile = g / NP;
+            u.p = g % NP;
+            return u;
+        }
         if (g < c) {
             const uint32_t lane = lane_id();
             const uint32_t cf = lane < m.F ? up_frame_items(m, lane, k, NP) : 0u;
@@ -976,14 +1089,14 @@ __device__ inline bool up_schedule(const TileMap &m, uint32_t f, int k, uint32_t
     return load_schedule(fd, ctrl, k, tile, pass_chunks(fd.C4, k), ts, A.rec, A.ab, A.lst, A.opos, A.idx, A.lmask);
 }
 
-// The quantized (or float) coefficient rows of entries that are not open, at their voxel rows:
-// an open entry's coefficient is written by the level that completes its merge (so that every
-// row is written exactly once in the launch), except at the final level, where the open entry
-// is the sequence's first one and holds the DC.
-template <bool VEC, bool POW2, class RowOf, class YAt>
+// The quantized (or float) coefficient rows at their voxel rows, of the entries j that `skip`
+// lets through. Open entries are skipped by every caller: an open entry's coefficient is written
+// by the level that completes its merge (so that every row is written exactly once in the
+// launch), except at the final level, where the open entry is the sequence's first one and holds
+// the DC.
+template <bool VEC, bool POW2, class RowOf, class YAt, class Skip>
 __device__ inline void store_coefs(const CAS FrameDesc &fd, const float *s_st, const float *s_ist, const Roles &R,
-                                   uint32_t c4, uint32_t mlen, bool final_level, const OpenSet &os, RowOf row_of,
-                                   YAt y_at)
+                                   uint32_t c4, uint32_t mlen, Skip skip, RowOf row_of, YAt y_at)
 {
     const uint32_t C = fd.C;
     GAS float *cf = gp(fd.coef_f32);
@@ -1006,7 +1119,7 @@ __device__ inline void store_coefs(const CAS FrameDesc &fd, const float *s_st, c
             ist[q] = s_ist[c];
         }
         for (uint32_t j = R.row0; j < mlen; j += R.RPB) {
-            if (!final_level && os_open(os, j)) continue;
+            if (skip(j)) continue;
             const float4 y = y_at(j);
             const uint64_t row = row_of(j);
             const int4 q = make_int4(quant1<POW2>(y.x, st[0], ist[0], omt, thr), quant1<POW2>(y.y, st[1], ist[1], omt, thr),
@@ -1019,7 +1132,7 @@ __device__ inline void store_coefs(const CAS FrameDesc &fd, const float *s_st, c
         }
     } else {  // MODE_FWD_F32: float coefficient rows
         for (uint32_t j = R.row0; j < mlen; j += R.RPB) {
-            if (!final_level && os_open(os, j)) continue;
+            if (skip(j)) continue;
             st4<VEC>(cf, row_of(j), C, c4, y_at(j));
         }
     }
@@ -1054,7 +1167,8 @@ __device__ inline void fwd_up_item(const TileMap &m, uint32_t f, int k, uint32_t
     __syncthreads();
     cross_phase(s_y, R, A.rec, A.ab, A.lst, xmask, nch, false);
     if (!live) return;
-    store_coefs<VEC, POW2>(fd, s_st, s_ist, R, c4, mlen, ts.final_level, A.os,
+    store_coefs<VEC, POW2>(fd, s_st, s_ist, R, c4, mlen,
+                           [&](uint32_t j) { return !ts.final_level && os_open(A.os, j); },
                            [&](uint32_t j) -> uint64_t { return A.idx[j]; },
                            [&](uint32_t j) { return s_y[j * CH4 + R.c4]; });
     if (!ts.final_level) {
@@ -1285,7 +1399,7 @@ __device__ inline void load_rows1(const GAS float *src, uint32_t C, const Roles 
 // counter; an item of level k >= 2 waits until level k - 1 is complete (all its open-entry rows
 // handed over) and runs the tile as one (non-prefetching) item.
 template <bool VEC, bool POW2>
-__global__ __launch_bounds__(RAHT_THREADS) __attribute__((amdgpu_waves_per_eu(PERSIST_PER_CU * RAHT_THREADS / WAVE / 4))) void k_raht_fwd(TileMap m, int kmax)
+__global__ __launch_bounds__(RAHT_THREADS) __attribute__((amdgpu_waves_per_eu(PERSIST_PER_CU * RAHT_THREADS / WAVE / 4))) void k_raht_fwd(TileMap m, int kmax, int finish)
 {
     extern __shared__ float4 s_y[];
     __shared__ uint32_t s_rec[RT];
@@ -1392,9 +1506,10 @@ __global__ __launch_bounds__(RAHT_THREADS) __attribute__((amdgpu_waves_per_eu(PE
         }
         s_row[tid] = row_clamp(it1, F1);
         __syncthreads();
-        // ---- prefetch: the next item's schedule and rows, the first rows of the one after
-        const Item1 it2 = item1(m, i + 2 * G, fc);
+        // ---- prefetch: the next item's schedule and rows (issued first), then the item after it
+        // and its first rows
         if (it1.ok) prefetch(it1, S, D);
+        const Item1 it2 = item1(m, i + 2 * G, fc);
         if (it2.ok && cp(m.fd[it2.f])->mode == MODE_ENCODE) F1 = first_row(it2);
         // ---- the current item
         if (it0.ok) {
@@ -1442,7 +1557,8 @@ __global__ __launch_bounds__(RAHT_THREADS) __attribute__((amdgpu_waves_per_eu(PE
             __syncthreads();
             cross_phase(s_y, R, s_rec, s_ab, s_lst, xmask, nch, false);
             if (live) {
-                store_coefs<VEC, POW2>(*d, s_st, s_ist, R, c4, mlen, it0.final_level, os,
+                const bool fl = it0.final_level;
+                store_coefs<VEC, POW2>(*d, s_st, s_ist, R, c4, mlen, [&](uint32_t j) { return !fl && os_open(os, j); },
                                        [&](uint32_t j) -> uint64_t { return s + j; },
                                        [&](uint32_t j) { return s_y[j * CH4 + R.c4]; });
                 if (!it0.final_level) {
@@ -1456,43 +1572,45 @@ __global__ __launch_bounds__(RAHT_THREADS) __attribute__((amdgpu_waves_per_eu(PE
         it0 = it1;
         it1 = it2;
     }
-    if (kmax < 2) return;
-    // ---- the upper levels, ascending
-    done_add(done_ctr(m, DONE_FWD, 1), n1);  // this workgroup's first-level open rows are written
-    const uint32_t NP = channel_passes(cp(m.fd[0])->C4, 2);  // every frame of a launch has the same C
-    if (tid < 2 * NCHUNK) (&s_om[0][0])[tid] = 0;
-    Ctrl *ctrl0 = cp(m.fd[0])->ctrl;
-    // the upper levels' schedules and sizes are written (by the first Gp workgroups)
-    done_wait(ctr_word(m, PRE_DONE), Gp, ctrl0);
-    if (tid == 0) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    __syncthreads();
-    const uint32_t U = up_totals(m, kmax, NP, s_ucnt);
-    const UpArrays A{s_rec, s_ab, reinterpret_cast<uint16_t *>(s_lstw), reinterpret_cast<uint16_t *>(s_oposw),
-                     s_m0, s_lmask, OpenSet{s_om[0], s_opre}, nullptr};
-    GAS uint32_t *utk = ctr_word(m, TK_UPF);
-    for (;;) {
-        if (tid == 0) s_tk[0] = __hip_atomic_fetch_add(utk, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __syncthreads();  // (also: the previous item's LDS is no longer read)
-        const uint32_t g = __builtin_amdgcn_readfirstlane(s_tk[0]);
-        if (g >= U) break;
-        const UpItem u = up_item(m, kmax, false, NP, s_ucnt, g);
-        TileSched ts;
-        const bool ok = up_schedule(m, u.f, u.k, u.tile, ts, A);
-        // the entries' rows are handed over by level k - 1: wait until all of its items are done
-        done_wait(done_ctr(m, DONE_FWD, u.k - 1), u.k == 2 ? items : s_ucnt[u.k - 1], ctrl0);
-        if (ok) fwd_up_item<VEC, POW2>(m, u.f, u.k, u.p, ts, s_y, A, s_st, s_ist);
-        done_add(done_ctr(m, DONE_FWD, u.k), 1);
-        if (tid < NCHUNK) s_om[0][tid] = 0;
+    if (kmax >= 2) {
+        // ---- the upper levels, ascending
+        done_add(done_ctr(m, DONE_FWD, 1), n1);  // this workgroup's first-level open rows are written
+        const uint32_t NP = channel_passes(cp(m.fd[0])->C4, 2);  // every frame of a launch has the same C
+        if (tid < 2 * NCHUNK) (&s_om[0][0])[tid] = 0;
+        Ctrl *ctrl0 = cp(m.fd[0])->ctrl;
+        // the upper levels' schedules and sizes are written (by the first Gp workgroups)
+        done_wait(ctr_word(m, PRE_DONE), Gp, ctrl0);
+        if (tid == 0) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        __syncthreads();
+        const uint32_t U = up_totals(m, kmax, NP, s_ucnt);
+        const UpArrays A{s_rec, s_ab, reinterpret_cast<uint16_t *>(s_lstw), reinterpret_cast<uint16_t *>(s_oposw),
+                         s_m0, s_lmask, OpenSet{s_om[0], s_opre}, nullptr};
+        GAS uint32_t *utk = ctr_word(m, TK_UPF);
+        for (;;) {
+            if (tid == 0) s_tk[0] = __hip_atomic_fetch_add(utk, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __syncthreads();  // (also: the previous item's LDS is no longer read)
+            const uint32_t g = __builtin_amdgcn_readfirstlane(s_tk[0]);
+            if (g >= U) break;
+            const UpItem u = up_item(m, kmax, false, NP, s_ucnt, g);
+            TileSched ts;
+            const bool ok = up_schedule(m, u.f, u.k, u.tile, ts, A);
+            // the entries' rows are handed over by level k - 1: wait until all of its items are done
+            done_wait(done_ctr(m, DONE_FWD, u.k - 1), u.k == 2 ? items : s_ucnt[u.k - 1], ctrl0);
+            if (ok) fwd_up_item<VEC, POW2>(m, u.f, u.k, u.p, ts, s_y, A, s_st, s_ist);
+            done_add(done_ctr(m, DONE_FWD, u.k), 1);
+            if (tid < NCHUNK) s_om[0][tid] = 0;
+        }
     }
+    if (finish) finish_if_last(m, FIN_FWD, s_y);
 }
 
 // ============================================================ upper levels, inverse (launch)
 // The inverse of the upper levels kmax .. 2 in one persistent launch (all workgroups resident),
-// before the first level's: with `prelude`, the whole grid first builds the upper levels'
-// schedules. The items run in descending level order (workgroup b takes items b, b + G, ...);
-// every item inverts its tile with the open entries' low-passes taken as zero and only then waits
-// for the level above, so the tiles of all levels are inverted side by side and only the shares
-// of the low-passes (add_open_share) follow the levels' order.
+// before the first level's: with `prelude`, the first Gp workgroups first build the upper
+// levels' schedules. The items run in descending level order (workgroup b takes items b, b + G,
+// ...); every item inverts its tile with the open entries' low-passes taken as zero and only
+// then waits for the level above, so the tiles of all levels are inverted side by side and only
+// the shares of the low-passes (add_open_share) follow the levels' order.
 template <bool VEC>
 __global__ __launch_bounds__(RAHT_THREADS) void k_raht_inv_up(TileMap m, int kmax, int prelude)
 {
@@ -1541,7 +1659,7 @@ __global__ __launch_bounds__(RAHT_THREADS) void k_raht_inv_up(TileMap m, int kma
 constexpr int NO1 = (OPEN_CAP + RT / (int)CH4_MAX1 - 1) / (RT / (int)CH4_MAX1);
 
 template <bool VEC>
-__global__ __launch_bounds__(RAHT_THREADS) __attribute__((amdgpu_waves_per_eu(PERSIST_PER_CU * RAHT_THREADS / WAVE / 4))) void k_raht_inv(TileMap m)
+__global__ __launch_bounds__(RAHT_THREADS) __attribute__((amdgpu_waves_per_eu(PERSIST_PER_CU * RAHT_THREADS / WAVE / 4))) void k_raht_inv(TileMap m, int finish)
 {
     extern __shared__ float4 s_y[];
     __shared__ uint32_t s_rec[RT];
@@ -1644,9 +1762,9 @@ __global__ __launch_bounds__(RAHT_THREADS) __attribute__((amdgpu_waves_per_eu(PE
                 s_y[w ? s_opos[min(o, (uint32_t)OPEN_CAP - 1)] * CH4 + R.c4 : sink] = O[u];
             }
         }
-        // ---- prefetch the next item
-        const Item1 it2 = item1(m, i + 2 * G, fc);
+        // ---- prefetch the next item (issued first), then the item after it
         if (it1.ok) prefetch(it1, S, D, O);
+        const Item1 it2 = item1(m, i + 2 * G, fc);
         // ---- the current item: all local merges undone, across chunks, then within chunks
         if (it0.ok) {
             __syncthreads();  // the open-entry writes
@@ -1685,6 +1803,7 @@ __global__ __launch_bounds__(RAHT_THREADS) __attribute__((amdgpu_waves_per_eu(PE
         it0 = it1;
         it1 = it2;
     }
+    if (finish) finish_if_last(m, FIN_INV, s_y);
 }
 
 // Dynamic LDS of a transform launch: the slice of RT entries of the widest tiling level, plus
@@ -1768,7 +1887,7 @@ static uint32_t persist_grid(uint32_t items, int C4, const void *kern, size_t ld
     return ceil_div(ceil_div(items, rounds), unit) * unit;
 }
 
-hipError_t launch_raht_fwd(const TileMap &m, int kmax, const RahtCfg &cfg, hipStream_t s)
+hipError_t launch_raht_fwd(const TileMap &m, int kmax, bool finish, const RahtCfg &cfg, hipStream_t s)
 {
     const size_t lds = raht_lds_bytes(cfg.C4);
     const void *kern = cfg.vec ? (cfg.pow2 ? reinterpret_cast<const void *>(k_raht_fwd<true, true>)
@@ -1778,10 +1897,11 @@ hipError_t launch_raht_fwd(const TileMap &m, int kmax, const RahtCfg &cfg, hipSt
     const uint32_t g = persist_grid(m.start[m.F], cfg.C4, kern, lds);
     if (g == 0) return hipErrorInvalidConfiguration;
     const dim3 grid(g), block(RAHT_THREADS);
-    if (cfg.vec && cfg.pow2) hipLaunchKernelGGL((k_raht_fwd<true, true>), grid, block, lds, s, m, kmax);
-    else if (cfg.vec) hipLaunchKernelGGL((k_raht_fwd<true, false>), grid, block, lds, s, m, kmax);
-    else if (cfg.pow2) hipLaunchKernelGGL((k_raht_fwd<false, true>), grid, block, lds, s, m, kmax);
-    else hipLaunchKernelGGL((k_raht_fwd<false, false>), grid, block, lds, s, m, kmax);
+    const int fin = finish ? 1 : 0;
+    if (cfg.vec && cfg.pow2) hipLaunchKernelGGL((k_raht_fwd<true, true>), grid, block, lds, s, m, kmax, fin);
+    else if (cfg.vec) hipLaunchKernelGGL((k_raht_fwd<true, false>), grid, block, lds, s, m, kmax, fin);
+    else if (cfg.pow2) hipLaunchKernelGGL((k_raht_fwd<false, true>), grid, block, lds, s, m, kmax, fin);
+    else hipLaunchKernelGGL((k_raht_fwd<false, false>), grid, block, lds, s, m, kmax, fin);
     return hipGetLastError();
 }
 
@@ -1800,7 +1920,7 @@ hipError_t launch_raht_inv_up(const TileMap &m, int kmax, uint32_t items_max, bo
     return hipGetLastError();
 }
 
-hipError_t launch_raht_inv(const TileMap &m, const RahtCfg &cfg, hipStream_t s)
+hipError_t launch_raht_inv(const TileMap &m, bool finish, const RahtCfg &cfg, hipStream_t s)
 {
     const size_t lds = raht_lds_bytes(cfg.C4);
     const void *kern = cfg.vec ? reinterpret_cast<const void *>(k_raht_inv<true>)
@@ -1808,8 +1928,9 @@ hipError_t launch_raht_inv(const TileMap &m, const RahtCfg &cfg, hipStream_t s)
     const uint32_t g = persist_grid(m.start[m.F], cfg.C4, kern, lds);
     if (g == 0) return hipErrorInvalidConfiguration;
     const dim3 grid(g), block(RAHT_THREADS);
-    if (cfg.vec) hipLaunchKernelGGL((k_raht_inv<true>), grid, block, lds, s, m);
-    else hipLaunchKernelGGL((k_raht_inv<false>), grid, block, lds, s, m);
+    const int fin = finish ? 1 : 0;
+    if (cfg.vec) hipLaunchKernelGGL((k_raht_inv<true>), grid, block, lds, s, m, fin);
+    else hipLaunchKernelGGL((k_raht_inv<false>), grid, block, lds, s, m, fin);
     return hipGetLastError();
 }
 

@@ -127,20 +127,36 @@ __device__ inline GAS uint32_t *rl_words(uint8_t *out, uint32_t NB)
     return gp(reinterpret_cast<uint32_t *>(out + sizeof(gsc_rlgr_header))) + NB + 1;
 }
 
-// Codes this thread's block of row j (count or write), streaming the rows through LDS.
+// Codes this thread's block of row j (count or write), streaming the rows through LDS. Each
+// chunk's values are loaded into registers one chunk ahead (every load of a chunk issued before
+// any is used), so the loads of chunk i + 1 are in flight while chunk i is coded. A chunk load
+// is unconditional and its positions clamped: past the last chunk it re-reads the last one.
+constexpr int RLGR_PER = RLGR_ROWS * RLGR_THREADS / RLGR_THREADS;  // values per thread and chunk (C <= 64)
 template <bool W>
 __device__ inline void rl_encode_row(const RlgrArgs &a, uint32_t j, RlgrEnc<W> &enc, int32_t *s_tile)
 {
     const uint32_t tid = threadIdx.x, C = a.C;
     const uint32_t r0 = j * a.B, r1 = min(r0 + a.B, a.nv);
     const GAS int32_t *q = gp(a.q);
+    int32_t v[RLGR_PER];
+    auto load = [&](uint32_t rc) {
+        const uint32_t nval = min((uint32_t)RLGR_ROWS, r1 - rc) * C;
+        const GAS int32_t *src = q + (size_t)rc * C;
+#pragma unroll
+        for (int u = 0; u < RLGR_PER; ++u) v[u] = src[min(tid + (uint32_t)u * RLGR_THREADS, nval - 1)];
+    };
+    load(r0);  // (r0 < r1: a block row holds at least one value)
     for (uint32_t rc = r0; rc < r1; rc += RLGR_ROWS) {
         const uint32_t nr = min((uint32_t)RLGR_ROWS, r1 - rc);
         const uint32_t nval = nr * C;
-        const GAS int32_t *src = q + (size_t)rc * C;
         __syncthreads();  // the previous chunk is no longer read
-        for (uint32_t e = tid; e < nval; e += RLGR_THREADS) s_tile[e] = src[e];
+#pragma unroll
+        for (int u = 0; u < RLGR_PER; ++u) {
+            const uint32_t e = tid + (uint32_t)u * RLGR_THREADS;
+            if (e < nval) s_tile[e] = v[u];
+        }
         __syncthreads();
+        load(rc + RLGR_ROWS < r1 ? rc + RLGR_ROWS : rc);
         if (tid < C)
             for (uint32_t r = 0; r < nr; ++r) enc.value(s_tile[r * C + tid]);
     }
