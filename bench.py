@@ -63,8 +63,8 @@ def alg_bytes(stage, n, nv, C):
 KERNEL_SOURCES = ("paper_2606_05650_amd/csrc/k_raht.hip", "paper_2606_05650_amd/csrc/gsc_device.h",
                   "paper_2606_05650_amd/csrc/gsc_internal.h")
 PMC_TRAFFIC = {"workload": "frame1M_J12",
-               "sources_sha256": "c8945a0dd993396ac54222ad1801ca6b37328b41c079b6989e24f5761c2bd7e2",
-               "raht_fwd1": 569479474, "raht_inv1": 469154647}
+               "sources_sha256": "92e853d73d50373f2e013d79557836c194a7940809c9b7b7370dd859c2274521",
+               "raht_fwd1": 597962765, "raht_inv1": 466694892}
 KERNEL_NAMES = {"raht_fwd1": "k_raht_fwd", "raht_inv1": "k_raht_inv"}
 
 

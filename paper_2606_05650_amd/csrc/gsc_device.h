@@ -566,7 +566,8 @@ __device__ inline void finish_frame(const CAS FrameDesc &fd, uint32_t t, FinishS
     Ctrl *ctrl = fd.ctrl;
     const uint32_t J = fd.J, K = fd.K;
     if (t <= GSC_MAX_DEPTH) S.hist[t] = t <= J ? ctrl->hist_D[t] : 0u;
-    if (t <= MAXK) S.lvl[t] = t <= K ? ctrl->lvl_n[t] : 0u;
+    // (the upper levels' sizes may have been written by the launch that runs this: coherent loads)
+    if (t <= MAXK) S.lvl[t] = t <= K ? __hip_atomic_load(&ctrl->lvl_n[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0u;
     if (t == 0) {
         S.err = load_error(ctrl);
         S.nv = ctrl->n_vox;

@@ -906,8 +906,9 @@ __device__ inline void done_wait(const GAS uint32_t *c, uint32_t target, Ctrl *c
 // The last workgroup of a transform launch to end (counted on counter word w) ends every frame's
 // call (finish_frame, one wave per frame), so that a call whose last launch this is needs no
 // finish launch. Each wave has waited for its memory operations (device errors are reported by
-// atomics) before the workgroup is counted; the last one acquires before it reads the counters.
-// The transform's LDS (s_y) is free by then and holds the scratch.
+// atomics) before the workgroup is counted; what finish_frame reads was written by earlier
+// launches, or is read with coherent loads (errors, level sizes), so no cache-wide acquire is
+// needed. The transform's LDS (s_y) is free by then and holds the scratch.
 __device__ inline void finish_if_last(const TileMap &m, uint32_t w, float4 *s_y)
 {
     __builtin_amdgcn_s_waitcnt(0);
@@ -917,8 +918,6 @@ __device__ inline void finish_if_last(const TileMap &m, uint32_t w, float4 *s_y)
         s_last[0] = __hip_atomic_fetch_add(ctr_word(m, w), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1u == gridDim.x;
     __syncthreads();
     if (!s_last[0]) return;
-    if (threadIdx.x == 0) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    __syncthreads();
     FinishScratch *S = reinterpret_cast<FinishScratch *>(s_y + 1);
     const uint32_t wv = threadIdx.x / WAVE;
     for (uint32_t f = wv; f < m.F; f += RAHT_THREADS / WAVE) finish_frame(*cp(m.fd[f]), lane_id(), S[wv]);
