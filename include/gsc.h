@@ -349,6 +349,39 @@ gsc_status gsc_rlgr_decode(const void *d_in, size_t in_bytes, int64_t nv, int32_
                            void *stream);
 
 /* ------------------------------------------------------------------------------------------
+ * Colour decorrelation before the transform (Sec. 4 "Improving Compression"): every SH
+ * function's RGB triple goes to YUV, and each YUV channel gets its own per-frame Karhunen-Loeve
+ * transform (KLT) over its 15 AC SH coefficients; the DC coefficients get the YUV step only.
+ * A caller runs gsc_color_forward on the attribute rows before gsc_encode_frame and
+ * gsc_color_inverse on the decoded rows, keeping the frame's three KLT matrices (2700 bytes) as
+ * side information.
+ *   Layout: [n][C] float32 rows; the 48 SH channels start at column sh0 (sh0 + 48 <= C): the DC
+ *   of R, G, B, then the 15 AC functions of R, of G and of B (the storage order of degree-3
+ *   Gaussian splats). The output keeps that layout with Y, U, V in place of R, G, B and KLT
+ *   coefficient j in place of function j; columns outside [sh0, sh0 + 48) are copied.
+ *   YUV (the paper gives no coefficients): the BT.601 definition, Kr = 0.299, Kb = 0.114,
+ *   Umax = 0.436, Vmax = 0.615: Y = Kr R + (1 - Kr - Kb) G + Kb B, U = Umax (B - Y) / (1 - Kb),
+ *   V = Vmax (R - Y) / (1 - Kr).
+ *   KLT of channel c: the eigenvectors of the covariance (about the mean, over the n rows) of
+ *   its 15 AC values, in decreasing eigenvalue order, each with its largest-magnitude component
+ *   positive; d_klt[c][i][j] is component i of vector j; coefficients a = E^T x, inverse
+ *   x = E a; with fewer than two rows every E is the identity.
+ * gsc_color_workspace_size: device scratch bytes for n rows.
+ * gsc_color_forward: d_attr -> d_out, d_klt float[3][15][15]; d_eig (double[3][15], may be
+ *   NULL) the eigenvalues; d_info[0] = 0, d_info[1] = n once done.
+ * gsc_color_inverse: d_coef (forward's layout) and d_klt -> d_out (RGB rows).
+ * Inputs and outputs must not overlap; n < 2^31; C <= 64.
+ * ---------------------------------------------------------------------------------------- */
+#define GSC_COLOR_SH_CHANNELS 48
+#define GSC_COLOR_KLT_FLOATS (3 * 15 * 15)
+gsc_status gsc_color_workspace_size(int64_t n, size_t *bytes);
+gsc_status gsc_color_forward(const float *d_attr, int64_t n, int32_t C, int32_t sh0, float *d_out,
+                             float *d_klt, double *d_eig, void *d_ws, size_t ws_bytes,
+                             int32_t *d_info, void *stream);
+gsc_status gsc_color_inverse(const float *d_coef, int64_t n, int32_t C, int32_t sh0,
+                             const float *d_klt, float *d_out, void *stream);
+
+/* ------------------------------------------------------------------------------------------
  * Diagnostics: gsc_profile_events -- record caller-created HIP events around one stage of every
  * later call on the calling process (all threads share this setting). `events` holds n_pairs
  * (start, end) pairs of hipEvent_t (as void*); the i-th launch of the stage records pair

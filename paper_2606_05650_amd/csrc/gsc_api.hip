@@ -947,4 +947,60 @@ gsc_status gsc_rlgr_decode(const void *d_in, size_t in_bytes, int64_t nv, int32_
     return GSC_OK;
 }
 
+gsc_status gsc_color_workspace_size(int64_t n, size_t *bytes)
+{
+    if (!bytes || n < 0 || n > 0x7FFFFFFFll) return GSC_ERR_INVALID_ARG;
+    *bytes = color_workspace_bytes((uint32_t)n);
+    return GSC_OK;
+}
+
+static gsc_status color_shape(int64_t n, int32_t C, int32_t sh0)
+{
+    if (n < 0 || n > 0x7FFFFFFFll || C < 1 || C > GSC_MAX_CHANNELS || sh0 < 0 || sh0 + GSC_COLOR_SH_CHANNELS > C)
+        return GSC_ERR_INVALID_ARG;
+    return GSC_OK;
+}
+
+gsc_status gsc_color_forward(const float *d_attr, int64_t n, int32_t C, int32_t sh0, float *d_out,
+                             float *d_klt, double *d_eig, void *d_ws, size_t ws_bytes,
+                             int32_t *d_info, void *stream)
+{
+    gsc_status st = color_shape(n, C, sh0);
+    if (st != GSC_OK) return st;
+    if (!d_klt || !d_ws || !d_info || (n > 0 && (!d_attr || !d_out))) return GSC_ERR_INVALID_ARG;
+    const size_t need = color_workspace_bytes((uint32_t)n);
+    if (ws_bytes < need) return GSC_ERR_WORKSPACE;
+    {
+        Spans sp;
+        sp.rd(d_attr, (uint64_t)n * C * 4);
+        sp.wr(d_out, (uint64_t)n * C * 4);
+        sp.wr(d_klt, GSC_COLOR_KLT_FLOATS * 4);
+        sp.wr(d_eig, 3 * 15 * 8);
+        sp.wr(d_ws, need);
+        sp.wr(d_info, GSC_INFO_WORDS * 4);
+        if (!sp.disjoint()) return GSC_ERR_INVALID_ARG;
+    }
+    GSC_LAUNCH(launch_color_forward(d_attr, d_out, (uint32_t)n, (uint32_t)C, (uint32_t)sh0, d_klt, d_eig,
+                                    static_cast<double *>(d_ws), d_info, static_cast<hipStream_t>(stream)));
+    return GSC_OK;
+}
+
+gsc_status gsc_color_inverse(const float *d_coef, int64_t n, int32_t C, int32_t sh0,
+                             const float *d_klt, float *d_out, void *stream)
+{
+    gsc_status st = color_shape(n, C, sh0);
+    if (st != GSC_OK) return st;
+    if (!d_klt || (n > 0 && (!d_coef || !d_out))) return GSC_ERR_INVALID_ARG;
+    {
+        Spans sp;
+        sp.rd(d_coef, (uint64_t)n * C * 4);
+        sp.rd(d_klt, GSC_COLOR_KLT_FLOATS * 4);
+        sp.wr(d_out, (uint64_t)n * C * 4);
+        if (!sp.disjoint()) return GSC_ERR_INVALID_ARG;
+    }
+    GSC_LAUNCH(launch_color_inverse(d_coef, d_out, (uint32_t)n, (uint32_t)C, (uint32_t)sh0, d_klt,
+                                    static_cast<hipStream_t>(stream)));
+    return GSC_OK;
+}
+
 }  // extern "C"

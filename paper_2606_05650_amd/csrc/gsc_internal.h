@@ -381,6 +381,12 @@ hipError_t launch_raht_inv_up(const TileMap &m, int kmax, uint32_t items_max, bo
                               hipStream_t s);
 hipError_t launch_finish(const TileMap &m, hipStream_t s);
 // Block entropy coder (k_rlgr.hip); ws: 8 (ceil(nv / B) + 1) bytes.
+// colour decorrelation (k_color.hip)
+size_t color_workspace_bytes(uint32_t n);
+hipError_t launch_color_forward(const float *in, float *out, uint32_t n, uint32_t C, uint32_t sh0, float *klt,
+                                double *eig, double *part, int32_t *info, hipStream_t s);
+hipError_t launch_color_inverse(const float *in, float *out, uint32_t n, uint32_t C, uint32_t sh0, const float *klt,
+                                hipStream_t s);
 hipError_t launch_rlgr_encode(const int32_t *q, uint32_t nv, uint32_t C, uint32_t B, uint8_t *out,
                               uint64_t out_cap, uint64_t *ws, int32_t *info, hipStream_t s);
 hipError_t launch_rlgr_decode(const uint8_t *in, uint64_t in_bytes, uint32_t nv, uint32_t C, uint32_t B,

@@ -119,6 +119,12 @@ def lib():
         L.gsc_rlgr_encode.argtypes = [vp, i64, i32, i32, vp, sz, vp, sz, vp, vp]
         L.gsc_rlgr_decode.restype = i32
         L.gsc_rlgr_decode.argtypes = [vp, sz, i64, i32, i32, vp, vp, sz, vp, vp]
+        L.gsc_color_workspace_size.restype = i32
+        L.gsc_color_workspace_size.argtypes = [i64, ctypes.POINTER(sz)]
+        L.gsc_color_forward.restype = i32
+        L.gsc_color_forward.argtypes = [vp, i64, i32, i32, vp, vp, vp, vp, sz, vp, vp]
+        L.gsc_color_inverse.restype = i32
+        L.gsc_color_inverse.argtypes = [vp, i64, i32, i32, vp, vp, vp]
         L.gsc_status_string.restype = ctypes.c_char_p
         L.gsc_status_string.argtypes = [i32]
         _lib = L
@@ -656,3 +662,65 @@ def rlgr_decode(buf, nv, C, B, *, nbytes=None, q=None, ws=None, info=None, strea
                                _ptr(info), _stream(stream))
     _check(rc, "gsc_rlgr_decode")
     return q, info
+
+
+# ----------------------------------------------------------------- colour decorrelation
+COLOR_SH_CHANNELS = 48
+COLOR_KLT_SHAPE = (3, 15, 15)
+
+
+def color_workspace_size(n):
+    out = ctypes.c_size_t()
+    _check(lib().gsc_color_workspace_size(int(n), ctypes.byref(out)), "color_workspace_size")
+    return out.value
+
+
+@dataclass
+class ColorForward:
+    out: "object"    # [n, C] float32: YUV DC and KLT coefficients in the SH columns
+    klt: "object"    # [3, 15, 15] float32: E[c][i][j], component i of basis vector j
+    eig: "object"    # [3, 15] float64: the eigenvalues, decreasing
+    info: "object"   # int32 [GSC_INFO_WORDS]
+
+
+def color_forward(attr, sh0=8, *, out=None, klt=None, eig=None, ws=None, info=None, stream=None):
+    """YUV on every SH function, then a per-frame KLT per YUV channel over the AC coefficients
+    (attr: [n, C] float32 cuda, contiguous; the 48 SH channels start at column sh0)."""
+    torch = _torch()
+    n, C = int(attr.shape[0]), int(attr.shape[1])
+    dev = attr.device
+    _check_tensor(attr, "attr", torch.float32, n, C)
+    if out is None:
+        out = torch.empty((max(n, 1), C), dtype=torch.float32, device=dev)
+    if klt is None:
+        klt = torch.empty(COLOR_KLT_SHAPE, dtype=torch.float32, device=dev)
+    if eig is None:
+        eig = torch.empty((3, 15), dtype=torch.float64, device=dev)
+    need = color_workspace_size(n)
+    if ws is None:
+        ws = _dev_u8(need, dev)
+    if info is None:
+        info = torch.zeros(INFO_WORDS, dtype=torch.int32, device=dev)
+    _check_tensor(out, "out", torch.float32, n, C)
+    _check_tensor(klt, "klt", torch.float32, numel=3 * 15 * 15)
+    _check_tensor(eig, "eig", torch.float64, numel=45)
+    _check_tensor(ws, "ws", torch.uint8, numel=need)
+    _check_tensor(info, "info", torch.int32, numel=INFO_WORDS)
+    rc = lib().gsc_color_forward(_ptr(attr), n, C, int(sh0), _ptr(out), _ptr(klt), _ptr(eig),
+                                 _ptr(ws), ws.numel(), _ptr(info), _stream(stream))
+    _check(rc, "gsc_color_forward")
+    return ColorForward(out, klt, eig, info)
+
+
+def color_inverse(coef, klt, sh0=8, *, out=None, stream=None):
+    """The decoder's side of color_forward: coef [n, C] and the frame's KLT matrices -> RGB rows."""
+    torch = _torch()
+    n, C = int(coef.shape[0]), int(coef.shape[1])
+    _check_tensor(coef, "coef", torch.float32, n, C)
+    _check_tensor(klt, "klt", torch.float32, numel=3 * 15 * 15)
+    if out is None:
+        out = torch.empty((max(n, 1), C), dtype=torch.float32, device=coef.device)
+    _check_tensor(out, "out", torch.float32, n, C)
+    rc = lib().gsc_color_inverse(_ptr(coef), n, C, int(sh0), _ptr(klt), _ptr(out), _stream(stream))
+    _check(rc, "gsc_color_inverse")
+    return out

@@ -109,6 +109,41 @@ def sample_attributes(rng, n) -> np.ndarray:
     return a.astype(np.float32)
 
 
+def sample_correlated_sh(rng, n) -> np.ndarray:
+    """n x 48 float32 SH coefficients whose colours and functions are correlated, as in trained
+    splats (the correlation the colour decorrelation of Sec. 4 removes): per SH function f a
+    shared luminance value with standard deviation s_f (0.5 for the DC; 0.08, 0.05, 0.03 for the
+    AC functions of degree 1, 2, 3) plus per-colour deviations of 0.3 s_f; the AC luminances
+    and the per-colour deviations are mixed across functions by fixed (seed 12345) 15 x 15
+    matrices with decaying spectra (one for the luminance, one per colour), so each YUV
+    channel's AC covariance has well separated eigenvalues. Columns: DC of R, G, B, then the 15
+    AC functions of R, of G and of B."""
+    deg = np.array([1] * 3 + [2] * 5 + [3] * 7)
+    s_ac = np.array([0.08, 0.05, 0.03])[deg - 1]
+    mrng = np.random.default_rng(12345)
+
+    def mixing(hi, lo):
+        q, _ = np.linalg.qr(mrng.normal(size=(15, 15)))
+        return q @ np.diag(np.geomspace(hi, lo, 15)) @ q.T
+
+    mix = mixing(2.0, 0.3)
+    mix_c = [mixing(1.5, 0.2) for _ in range(3)]
+    lum_dc = rng.normal(0.0, 0.5, size=(n, 1))
+    lum_ac = (rng.normal(size=(n, 15)) * s_ac) @ mix.T
+    sh = np.empty((n, 48))
+    sh[:, 0:3] = lum_dc + rng.normal(0.0, 0.15, size=(n, 3))
+    for c in range(3):
+        sh[:, 3 + 15 * c:18 + 15 * c] = lum_ac + (rng.normal(size=(n, 15)) * (0.3 * s_ac)) @ mix_c[c].T
+    return sh.astype(np.float32)
+
+
+def make_color_frame(n: int, seed, n_surf: int = 20):
+    """make_frame with correlated SH coefficients (sample_correlated_sh) in columns 8..55."""
+    pos, attr = make_frame(n, seed, n_surf)
+    attr[:, 8:56] = sample_correlated_sh(np.random.default_rng((seed, 1)), n)
+    return pos, attr
+
+
 def make_frame(n: int, seed, n_surf: int = 20):
     """One frame: (positions n x 3 float32 in [0,1]^3, attributes n x 56 float32)."""
     rng = np.random.default_rng(seed)

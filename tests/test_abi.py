@@ -16,7 +16,8 @@ def test_library_exports_every_declared_symbol():
             "gsc_stream_capacity", "gsc_status_string", "gsc_decode_batch", "gsc_raht_forward",
             "gsc_raht_adjoint", "gsc_ste_forward", "gsc_ste_backward",
             "gsc_profile_events", "gsc_encode_frame_noalloc", "gsc_rlgr_encode", "gsc_rlgr_decode",
-            "gsc_rlgr_capacity", "gsc_rlgr_workspace_size"} <= set(names)
+            "gsc_rlgr_capacity", "gsc_rlgr_workspace_size", "gsc_color_workspace_size",
+            "gsc_color_forward", "gsc_color_inverse"} <= set(names)
     for name in names:
         assert hasattr(L, name), name
 
@@ -277,3 +278,22 @@ def test_rlgr_sizes_and_argument_checks():
     assert dec(k=16) == 4 and dec(c=0) == 2 and dec(b=0) == 1
     with pytest.raises(gsc.GscError):
         gsc.rlgr_capacity(10, 0, 512)
+
+
+def test_color_sizes_and_argument_checks():
+    # one block of 512 threads per 8 waves' rows; at most 256 blocks of 768 FP64 partial sums
+    assert gsc.color_workspace_size(0) == 768 * 8
+    assert gsc.color_workspace_size(1_000_000) <= 256 * 768 * 8
+    L = gsc.lib()
+    fake = [ctypes.c_void_p(0x1000000 * (i + 1)) for i in range(6)]  # disjoint, never dereferenced
+    n, C = 1000, 56
+    ws = gsc.color_workspace_size(n)
+    fwd = lambda n=n, c=C, s0=8, w=ws, a=fake[0], o=fake[1], k=fake[2]: L.gsc_color_forward(
+        a, n, c, s0, o, k, None, fake[3], w, fake[4], None)
+    assert fwd(c=65) == 1 and fwd(c=47) == 1 and fwd(s0=9) == 1 and fwd(s0=-1) == 1 and fwd(n=-1) == 1
+    assert fwd(w=ws - 1) == 3
+    assert fwd(k=None) == 1 and fwd(a=None) == 1
+    assert fwd(o=fake[0]) == 1                      # output over the input
+    assert fwd(k=ctypes.c_void_p(0x1000000 + 8)) == 1  # basis inside the input rows
+    inv = lambda n=n, c=C, s0=8, a=fake[0], k=fake[2], o=fake[1]: L.gsc_color_inverse(a, n, c, s0, k, o, None)
+    assert inv(s0=9) == 1 and inv(k=None) == 1 and inv(o=fake[0]) == 1
