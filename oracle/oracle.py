@@ -15,10 +15,11 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "gsc_oracle.c")
 _SRC_RLGR = os.path.join(_HERE, "rlgr_oracle.c")
+_SRC_RANS = os.path.join(_HERE, "rans_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 GCC_CMD = ["gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fPIC", "-shared", "-o", _LIB, _SRC,
-           _SRC_RLGR, "-lm"]
+           _SRC_RLGR, _SRC_RANS, "-lm"]
 
 
 def build_oracle() -> str:
@@ -34,7 +35,7 @@ def lib():
     global _lib
     if _lib is None:
         if (not os.path.exists(_LIB)) or os.path.getmtime(_LIB) < max(
-                os.path.getmtime(_SRC), os.path.getmtime(_SRC_RLGR)):
+                os.path.getmtime(_SRC), os.path.getmtime(_SRC_RLGR), os.path.getmtime(_SRC_RANS)):
             build_oracle()
         L = ctypes.CDLL(_LIB)
         i64, i32, u32, u64, dbl, vp = (ctypes.c_int64, ctypes.c_int, ctypes.c_uint32,
@@ -86,6 +87,14 @@ def lib():
         L.orc_rlgr_encode.argtypes = [vp, i64, i32, i32, vp, vp, i64]
         L.orc_rlgr_decode.restype = i32
         L.orc_rlgr_decode.argtypes = [vp, vp, i64, i32, i32, vp]
+        L.orc_rans_table.restype = i32
+        L.orc_rans_table.argtypes = [vp, i64, vp]
+        L.orc_rans_chunks.restype = i64
+        L.orc_rans_chunks.argtypes = [i64, i32]
+        L.orc_rans_encode.restype = i64
+        L.orc_rans_encode.argtypes = [vp, i64, i32, vp, vp, vp, i64]
+        L.orc_rans_decode.restype = i32
+        L.orc_rans_decode.argtypes = [vp, vp, i64, i32, vp, vp]
         _lib = L
     return _lib
 
@@ -384,3 +393,37 @@ def rlgr_decode(off, words, nv, C, B):
         raise ValueError("corrupt entropy-coded block")
     _check(rc, "rlgr_decode")
     return Q[:int(nv)]
+
+
+# ------------------------------------------------------------------ occupancy-byte rANS coder
+def rans_table(data):
+    """A1: the frequency table (uint16[256], summing to 4096) of a byte string."""
+    d = _c(np.frombuffer(bytes(data), dtype=np.uint8) if not isinstance(data, np.ndarray) else data, np.uint8)
+    f = np.zeros(256, dtype=np.uint16)
+    _check(lib().orc_rans_table(_p(d), d.size, _p(f)), "rans_table")
+    return f
+
+
+def rans_encode(data, K, freq=None):
+    """A2: (freq, chunk offsets int64[nc + 1], coded bytes uint8) of a byte string in chunks of
+    K bytes; the table is the stream's own (A1) unless given."""
+    d = _c(np.frombuffer(bytes(data), dtype=np.uint8) if not isinstance(data, np.ndarray) else data, np.uint8)
+    f = rans_table(d) if freq is None else _c(freq, np.uint16)
+    nc = int(_check(lib().orc_rans_chunks(d.size, int(K)), "rans_chunks"))
+    off = np.zeros(nc + 1, dtype=np.int64)
+    total = _check(lib().orc_rans_encode(_p(d), d.size, int(K), _p(f), _p(off), None, 0), "rans size")
+    out = np.zeros(max(total, 1), dtype=np.uint8)
+    _check(lib().orc_rans_encode(_p(d), d.size, int(K), _p(f), _p(off), _p(out), total), "rans_encode")
+    return f, off, out[:total]
+
+
+def rans_decode(freq, off, coded, n, K):
+    """A3: the n bytes the chunks decode to; raises ValueError on a chunk that does not decode
+    exactly."""
+    out = np.zeros(max(int(n), 1), dtype=np.uint8)
+    cd = _c(coded, np.uint8) if len(coded) else np.zeros(1, dtype=np.uint8)
+    rc = lib().orc_rans_decode(_p(_c(off, np.int64)), _p(cd), int(n), int(K), _p(_c(freq, np.uint16)), _p(out))
+    if rc == -3:
+        raise ValueError("corrupt rANS chunk")
+    _check(rc, "rans_decode")
+    return out[:int(n)]
