@@ -19,6 +19,9 @@ Other workloads (--workload):
                                distortion loss + backward, next to a plain encode + decode
   rlgr_frame1M_J12             the block entropy coder on the 1M frame's quantized
                                coefficients: time and size per block length
+  color_frame1M                the colour decorrelation (YUV + per-channel KLT of the SH
+                               coefficients) on a 1M frame with correlated SH: time, HBM
+                               fraction and the coded size with and without it
 """
 from __future__ import annotations
 
@@ -524,6 +527,94 @@ def rlgr_bench(args):
     print(json.dumps(out))
 
 
+def color_bench(args):
+    """The colour decorrelation (Sec. 4) on a 1M-Gaussian frame with correlated SH coefficients:
+    GPU forward (Gram matrices, eigenvectors, per-row transform) and inverse time against the
+    HBM peak, the round-trip error, and the effect on the coded size: the frame encoded with the
+    grouped steps and its coefficients entropy-coded with blocks of 512, with and without the
+    colour step, next to the SH reconstruction error of each (voxels holding one Gaussian)."""
+    import numpy as np
+    import torch
+    from paper_2606_05650_amd import gsc, synth
+
+    n, J, table = synth.WORKLOADS["frame1M_J12"]
+    steps_q = synth.quant_steps(table)
+    pos, attr = synth.make_color_frame(n, seed=2)
+    C = attr.shape[1]
+    dev = torch.device("cuda:0")
+    tp, ta = torch.from_numpy(pos).to(dev), torch.from_numpy(attr).to(dev)
+    out, back = torch.empty_like(ta), torch.empty_like(ta)
+    klt = torch.empty((3, 15, 15), dtype=torch.float32, device=dev)
+    eig = torch.empty((3, 15), dtype=torch.float64, device=dev)
+    ws = torch.empty(gsc.color_workspace_size(n), dtype=torch.uint8, device=dev)
+    info = torch.zeros(gsc.INFO_WORDS, dtype=torch.int32, device=dev)
+
+    def fwd():
+        gsc.color_forward(ta, out=out, klt=klt, eig=eig, ws=ws, info=info)
+
+    def inv():
+        gsc.color_inverse(out, klt, out=back)
+
+    for _ in range(args.warmup):
+        fwd()
+        inv()
+    tf = timed(fwd, args.steps, torch)
+    ti = timed(inv, args.steps, torch)
+    # the Gram pass reads every row's 45 AC values; the transform reads and writes every row
+    bytes_f, bytes_i = n * (45 * 4 + 2 * 4 * C), n * 2 * 4 * C
+    rt_err = ((back - ta).abs().max() / ta.abs().max()).item()
+
+    p = gsc.make_params(J, C, steps_q)
+    perm = torch.empty(n, dtype=torch.int32, device=dev)
+    vof = torch.empty(n, dtype=torch.int32, device=dev)
+
+    def coded(rows):
+        e = gsc.encode_frame(tp, rows, p, perm=perm, voxel_of=vof)
+        torch.cuda.synchronize()
+        e.check()
+        blob = np.frombuffer(e.to_bytes(), dtype=np.uint8)
+        h = gsc.parse_header(blob)
+        nv = int(h["n_vox"])
+        Q = blob[int(h["coef_offset"]):int(h["total_bytes"])].view(np.int32).reshape(nv, C)
+        s_ = gsc.rlgr_encode(torch.from_numpy(np.ascontiguousarray(Q)).to(dev), 512)
+        d = gsc.decode_frame(e.stream, J, C, n)
+        torch.cuda.synchronize()
+        s_.check()
+        d.check()
+        return int(h["occ_bytes"]), s_.nbytes(), d.attr[:nv], nv
+
+    occ0, b0, dec0, nv = coded(ta)
+    occ1, b1, dec1, _ = coded(out)
+    rgb1 = gsc.color_inverse(dec1.contiguous(), klt)[:nv]
+    v = vof.cpu().numpy().astype(np.int64)
+    cnt = np.bincount(v, minlength=nv)
+    single = np.nonzero(cnt[v] == 1)[0]          # Gaussians alone in their voxel
+    vox = torch.from_numpy(v[single]).to(dev)
+    src = ta[torch.from_numpy(single).to(dev)][:, 8:56]
+    rmse = lambda dec: (dec[vox][:, 8:56] - src).pow(2).mean().sqrt().item()
+    res = {"workload": "color_frame1M", "gaussians": n, "channels": C,
+           "forward_ms": round(tf * 1e3, 4), "inverse_ms": round(ti * 1e3, 4),
+           "forward_gbs": round(bytes_f / tf / 1e9, 1), "inverse_gbs": round(bytes_i / ti / 1e9, 1),
+           "forward_frac_hbm": round(bytes_f / tf / 1e9 / HBM_PEAK_GBS, 4),
+           "inverse_frac_hbm": round(bytes_i / ti / 1e9 / HBM_PEAK_GBS, 4),
+           "round_trip_max_rel_error": rt_err,
+           "eigenvalues_first3": [[round(float(x), 8) for x in row[:3]] for row in eig.cpu().numpy()],
+           "coded_bytes": {"rgb": occ0 + b0, "yuv_klt": occ1 + b1, "occupancy": occ0,
+                           "coefficients_rgb": b0, "coefficients_yuv_klt": b1},
+           "sh_rmse": {"rgb": round(rmse(dec0), 6), "yuv_klt": round(rmse(rgb1), 6)},
+           "steps": "grouped (scale 1/32, rotation 1/128, opacity 1/32, SH DC 1/64, SH rest 1/16) "
+                    "on the stored channels, with and without the colour step",
+           "data": "synthetic, correlated SH coefficients"}
+    if not args.no_cpu_baseline:
+        from oracle import color_oracle as co
+        t0 = time.perf_counter()
+        co.color_forward(attr, 8)
+        t = time.perf_counter() - t0
+        res["cpu_baseline"] = {"forward_ms": round(t * 1e3, 1), "kind": "oracle",
+                               "sample": "one forward of the frame (numpy FP64)"}
+    print(json.dumps(res))
+
+
 def copy_calibration(args):
     """Plain copies of a 512 MiB buffer: each launch reads and writes exactly 536,870,912 bytes."""
     import torch
@@ -566,6 +657,8 @@ def main():
         ste_bench(args)
     elif args.workload == "rlgr_frame1M_J12":
         rlgr_bench(args)
+    elif args.workload == "color_frame1M":
+        color_bench(args)
     else:
         frame_bench(args)
 

@@ -349,6 +349,47 @@ gsc_status gsc_rlgr_decode(const void *d_in, size_t in_bytes, int64_t nv, int32_
                            void *stream);
 
 /* ------------------------------------------------------------------------------------------
+ * Entropy coding of the occupancy bytes (an own range-ANS coder in place of the closed ANS
+ * library the paper uses for the geometry, Sec. 2.2 and Sec. 5). Any byte string; the codec's
+ * occupancy section is bytes [occ_offset, occ_offset + occ_bytes) of an encoded stream.
+ *   Model: one static table per stream over the 256 byte values with frequencies out of 4096:
+ *   f_s = 1 + floor(c_s (4096 - P) / T) for a byte present c_s times among the T input bytes (P
+ *   distinct bytes), the remainder to the most frequent byte (the smallest on a tie).
+ *   Coder: 32-bit rANS with byte renormalisation (state in [2^23, 2^31)); the input is cut into
+ *   chunks of K bytes (the last one shorter), each coded on its own from the state 2^23 with its
+ *   symbols taken last to first and stored in reverse emission order (its final state first,
+ *   most significant byte first), so a decoder reads each chunk forward and must end in the
+ *   state 2^23 with every byte of the chunk consumed.
+ *   Stream: gsc_rans_header, the table uint16[256], the chunks' first bytes uint32[nchunks + 1]
+ *   (counted from the data; the last entry is `total`), then the data. Little-endian.
+ * gsc_rans_capacity / gsc_rans_workspace_size: worst-case stream bytes (2 bytes per input byte
+ *   and 4 per chunk, plus the header, table and offsets) and device scratch bytes.
+ * gsc_rans_encode: d_in (n bytes) -> d_out (out_cap bytes); d_info[0] the device status
+ *   (GSC_ERR_CAPACITY if the code does not fit), d_info[2..3] the stream bytes (uint64).
+ * gsc_rans_decode: d_in (in_bytes) -> d_out (n bytes); n and K must match the header;
+ *   GSC_ERR_CORRUPT_STREAM in d_info[0] for a header, table or chunk that does not decode as
+ *   above (the bytes of such a chunk are then unspecified). d_ws: 8 bytes.
+ * K is 1 .. 2^20; n < 2^31. Inputs and outputs must not overlap.
+ * ---------------------------------------------------------------------------------------- */
+#define GSC_RANS_MAGIC 0x314E4152u /* "RAN1" */
+typedef struct gsc_rans_header {
+    uint32_t magic;          /* GSC_RANS_MAGIC                      */
+    uint32_t version;        /* GSC_VERSION                         */
+    uint64_t n;              /* input bytes                         */
+    uint32_t K;              /* chunk length                        */
+    uint32_t nchunks;        /* ceil(n / K)                         */
+    uint32_t total;          /* data bytes after the offsets        */
+    uint32_t reserved;
+} gsc_rans_header;
+
+gsc_status gsc_rans_capacity(int64_t n, int32_t K, size_t *bytes);
+gsc_status gsc_rans_workspace_size(int64_t n, int32_t K, size_t *bytes);
+gsc_status gsc_rans_encode(const void *d_in, int64_t n, int32_t K, void *d_out, size_t out_cap,
+                           void *d_ws, size_t ws_bytes, int32_t *d_info, void *stream);
+gsc_status gsc_rans_decode(const void *d_in, size_t in_bytes, int64_t n, int32_t K, void *d_out,
+                           void *d_ws, size_t ws_bytes, int32_t *d_info, void *stream);
+
+/* ------------------------------------------------------------------------------------------
  * Colour decorrelation before the transform (Sec. 4 "Improving Compression"): every SH
  * function's RGB triple goes to YUV, and each YUV channel gets its own per-frame Karhunen-Loeve
  * transform (KLT) over its 15 AC SH coefficients; the DC coefficients get the YUV step only.

@@ -1003,4 +1003,72 @@ gsc_status gsc_color_inverse(const float *d_coef, int64_t n, int32_t C, int32_t 
     return GSC_OK;
 }
 
+static gsc_status rans_shape(int64_t n, int32_t K)
+{
+    if (n < 0 || n > 0x7FFFFFFFll || K < 1 || K > (1 << 20)) return GSC_ERR_INVALID_ARG;
+    return GSC_OK;
+}
+
+gsc_status gsc_rans_capacity(int64_t n, int32_t K, size_t *bytes)
+{
+    gsc_status st = rans_shape(n, K);
+    if (st != GSC_OK || !bytes) return GSC_ERR_INVALID_ARG;
+    *bytes = (size_t)rans_capacity_bytes((uint64_t)n, (uint32_t)K);
+    return GSC_OK;
+}
+
+gsc_status gsc_rans_workspace_size(int64_t n, int32_t K, size_t *bytes)
+{
+    gsc_status st = rans_shape(n, K);
+    if (st != GSC_OK || !bytes) return GSC_ERR_INVALID_ARG;
+    *bytes = (size_t)rans_workspace_bytes((uint64_t)n, (uint32_t)K);
+    return GSC_OK;
+}
+
+gsc_status gsc_rans_encode(const void *d_in, int64_t n, int32_t K, void *d_out, size_t out_cap,
+                           void *d_ws, size_t ws_bytes, int32_t *d_info, void *stream)
+{
+    gsc_status st = rans_shape(n, K);
+    if (st != GSC_OK) return st;
+    if (!d_out || !d_ws || !d_info || (n > 0 && !d_in)) return GSC_ERR_INVALID_ARG;
+    const uint64_t need = rans_workspace_bytes((uint64_t)n, (uint32_t)K);
+    if (ws_bytes < need) return GSC_ERR_WORKSPACE;
+    const uint64_t nc = rans_chunks((uint64_t)n, (uint32_t)K);
+    if (out_cap < sizeof(gsc_rans_header) + 512 + 4 * (nc + 1)) return GSC_ERR_CAPACITY;
+    {
+        Spans sp;
+        sp.rd(d_in, (uint64_t)n);
+        sp.wr(d_out, out_cap);
+        sp.wr(d_ws, need);
+        sp.wr(d_info, GSC_INFO_WORDS * 4);
+        if (!sp.disjoint()) return GSC_ERR_INVALID_ARG;
+    }
+    GSC_LAUNCH(launch_rans_encode(static_cast<const uint8_t *>(d_in), (uint64_t)n, (uint32_t)K,
+                                  static_cast<uint8_t *>(d_out), out_cap, d_ws, d_info,
+                                  static_cast<hipStream_t>(stream)));
+    return GSC_OK;
+}
+
+gsc_status gsc_rans_decode(const void *d_in, size_t in_bytes, int64_t n, int32_t K, void *d_out,
+                           void *d_ws, size_t ws_bytes, int32_t *d_info, void *stream)
+{
+    gsc_status st = rans_shape(n, K);
+    if (st != GSC_OK) return st;
+    if (!d_in || !d_ws || !d_info || (n > 0 && !d_out)) return GSC_ERR_INVALID_ARG;
+    if (ws_bytes < 8) return GSC_ERR_WORKSPACE;
+    const uint64_t nc = rans_chunks((uint64_t)n, (uint32_t)K);
+    if (in_bytes < sizeof(gsc_rans_header) + 512 + 4 * (nc + 1)) return GSC_ERR_CAPACITY;
+    {
+        Spans sp;
+        sp.rd(d_in, in_bytes);
+        sp.wr(d_out, (uint64_t)n);
+        sp.wr(d_ws, 8);
+        sp.wr(d_info, GSC_INFO_WORDS * 4);
+        if (!sp.disjoint()) return GSC_ERR_INVALID_ARG;
+    }
+    GSC_LAUNCH(launch_rans_decode(static_cast<const uint8_t *>(d_in), in_bytes, (uint64_t)n, (uint32_t)K,
+                                  static_cast<uint8_t *>(d_out), d_ws, d_info, static_cast<hipStream_t>(stream)));
+    return GSC_OK;
+}
+
 }  // extern "C"

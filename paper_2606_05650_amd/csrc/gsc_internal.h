@@ -381,6 +381,14 @@ hipError_t launch_raht_inv_up(const TileMap &m, int kmax, uint32_t items_max, bo
                               hipStream_t s);
 hipError_t launch_finish(const TileMap &m, hipStream_t s);
 // Block entropy coder (k_rlgr.hip); ws: 8 (ceil(nv / B) + 1) bytes.
+// occupancy-byte rANS coder (k_rans.hip)
+uint64_t rans_chunks(uint64_t n, uint32_t K);
+uint64_t rans_workspace_bytes(uint64_t n, uint32_t K);
+uint64_t rans_capacity_bytes(uint64_t n, uint32_t K);
+hipError_t launch_rans_encode(const uint8_t *in, uint64_t n, uint32_t K, uint8_t *out, uint64_t cap, void *ws,
+                              int32_t *info, hipStream_t s);
+hipError_t launch_rans_decode(const uint8_t *in, uint64_t in_bytes, uint64_t n, uint32_t K, uint8_t *out, void *ws,
+                              int32_t *info, hipStream_t s);
 // colour decorrelation (k_color.hip)
 size_t color_workspace_bytes(uint32_t n);
 hipError_t launch_color_forward(const float *in, float *out, uint32_t n, uint32_t C, uint32_t sh0, float *klt,

@@ -21,6 +21,7 @@ MAX_DEPTH = 21
 MAX_CHANNELS = 64
 MAX_BATCH = 64
 HEADER_BYTES = 1024
+VERSION = 1         # GSC_VERSION
 INFO_WORDS = 8
 STATIC_SCRATCH_BYTES = 64 << 20  # GSC_STATIC_SCRATCH_BYTES
 
@@ -119,6 +120,14 @@ def lib():
         L.gsc_rlgr_encode.argtypes = [vp, i64, i32, i32, vp, sz, vp, sz, vp, vp]
         L.gsc_rlgr_decode.restype = i32
         L.gsc_rlgr_decode.argtypes = [vp, sz, i64, i32, i32, vp, vp, sz, vp, vp]
+        L.gsc_rans_capacity.restype = i32
+        L.gsc_rans_capacity.argtypes = [i64, i32, ctypes.POINTER(sz)]
+        L.gsc_rans_workspace_size.restype = i32
+        L.gsc_rans_workspace_size.argtypes = [i64, i32, ctypes.POINTER(sz)]
+        L.gsc_rans_encode.restype = i32
+        L.gsc_rans_encode.argtypes = [vp, i64, i32, vp, sz, vp, sz, vp, vp]
+        L.gsc_rans_decode.restype = i32
+        L.gsc_rans_decode.argtypes = [vp, sz, i64, i32, vp, vp, sz, vp, vp]
         L.gsc_color_workspace_size.restype = i32
         L.gsc_color_workspace_size.argtypes = [i64, ctypes.POINTER(sz)]
         L.gsc_color_forward.restype = i32
@@ -724,3 +733,84 @@ def color_inverse(coef, klt, sh0=8, *, out=None, stream=None):
     rc = lib().gsc_color_inverse(_ptr(coef), n, C, int(sh0), _ptr(klt), _ptr(out), _stream(stream))
     _check(rc, "gsc_color_inverse")
     return out
+
+
+# ----------------------------------------------------------------- occupancy-byte rANS coder
+RANS_MAGIC = 0x314E4152
+RANS_HEADER_DTYPE = np.dtype([("magic", "<u4"), ("version", "<u4"), ("n", "<u8"), ("K", "<u4"),
+                              ("nchunks", "<u4"), ("total", "<u4"), ("reserved", "<u4")])
+
+
+def rans_capacity(n, K):
+    out = ctypes.c_size_t()
+    _check(lib().gsc_rans_capacity(int(n), int(K), ctypes.byref(out)), "rans_capacity")
+    return out.value
+
+
+def rans_workspace_size(n, K):
+    out = ctypes.c_size_t()
+    _check(lib().gsc_rans_workspace_size(int(n), int(K), ctypes.byref(out)), "rans_workspace_size")
+    return out.value
+
+
+@dataclass
+class RansStream:
+    buf: "object"    # uint8 device tensor (capacity bytes)
+    info: "object"   # int32 device tensor [GSC_INFO_WORDS]
+    n: int
+    K: int
+    ws: "object" = None
+
+    def check(self):
+        i = self.info.cpu().numpy()
+        if i[0] != 0:
+            raise GscError(i[0], "device")
+        return self
+
+    def nbytes(self):
+        i = self.info.cpu().numpy()
+        return int(np.uint32(i[2])) | (int(np.uint32(i[3])) << 32)
+
+    def to_bytes(self):
+        return self.buf[:self.nbytes()].cpu().numpy().tobytes()
+
+
+def rans_encode(data, K, *, out=None, ws=None, info=None, stream=None):
+    """Range-ANS coding of a byte string (uint8 cuda tensor, contiguous) in chunks of K bytes."""
+    torch = _torch()
+    n = int(data.numel())
+    dev = data.device
+    _check_tensor(data, "data", torch.uint8, numel=n)
+    cap = rans_capacity(n, K)
+    need = rans_workspace_size(n, K)
+    out = _dev_u8(cap, dev) if out is None else out
+    ws = _dev_u8(need, dev) if ws is None else ws
+    info = torch.zeros(INFO_WORDS, dtype=torch.int32, device=dev) if info is None else info
+    _check_tensor(out, "out", torch.uint8)
+    _check_tensor(ws, "ws", torch.uint8, numel=need)
+    _check_tensor(info, "info", torch.int32, numel=INFO_WORDS)
+    rc = lib().gsc_rans_encode(_ptr(data), n, int(K), _ptr(out), out.numel(), _ptr(ws), ws.numel(),
+                               _ptr(info), _stream(stream))
+    _check(rc, "gsc_rans_encode")
+    return RansStream(out, info, n, int(K), ws)
+
+
+def rans_decode(buf, n, K, *, nbytes=None, out=None, ws=None, info=None, stream=None):
+    """Inverse of rans_encode: the stream in `buf` (uint8 cuda) -> n bytes (uint8 cuda)."""
+    torch = _torch()
+    dev = buf.device
+    n = int(n)
+    out = torch.empty(max(n, 1), dtype=torch.uint8, device=dev) if out is None else out
+    ws = torch.empty(8, dtype=torch.uint8, device=dev) if ws is None else ws
+    info = torch.zeros(INFO_WORDS, dtype=torch.int32, device=dev) if info is None else info
+    nb = buf.numel() if nbytes is None else int(nbytes)
+    if nb > buf.numel():
+        raise ValueError("nbytes exceeds the buffer")
+    _check_tensor(buf, "buf", torch.uint8)
+    _check_tensor(out, "out", torch.uint8, numel=n)
+    _check_tensor(ws, "ws", torch.uint8, numel=8)
+    _check_tensor(info, "info", torch.int32, numel=INFO_WORDS)
+    rc = lib().gsc_rans_decode(_ptr(buf), nb, n, int(K), _ptr(out), _ptr(ws), ws.numel(), _ptr(info),
+                               _stream(stream))
+    _check(rc, "gsc_rans_decode")
+    return out, info

@@ -17,7 +17,8 @@ def test_library_exports_every_declared_symbol():
             "gsc_raht_adjoint", "gsc_ste_forward", "gsc_ste_backward",
             "gsc_profile_events", "gsc_encode_frame_noalloc", "gsc_rlgr_encode", "gsc_rlgr_decode",
             "gsc_rlgr_capacity", "gsc_rlgr_workspace_size", "gsc_color_workspace_size",
-            "gsc_color_forward", "gsc_color_inverse"} <= set(names)
+            "gsc_color_forward", "gsc_color_inverse", "gsc_rans_capacity",
+            "gsc_rans_workspace_size", "gsc_rans_encode", "gsc_rans_decode"} <= set(names)
     for name in names:
         assert hasattr(L, name), name
 
@@ -297,3 +298,24 @@ def test_color_sizes_and_argument_checks():
     assert fwd(k=ctypes.c_void_p(0x1000000 + 8)) == 1  # basis inside the input rows
     inv = lambda n=n, c=C, s0=8, a=fake[0], k=fake[2], o=fake[1]: L.gsc_color_inverse(a, n, c, s0, k, o, None)
     assert inv(s0=9) == 1 and inv(k=None) == 1 and inv(o=fake[0]) == 1
+
+
+def test_rans_sizes_and_argument_checks():
+    n, K = 100_000, 512
+    nc = -(-n // K)
+    # header, table, offsets and at most 2 bytes per input byte plus 4 per chunk
+    assert gsc.rans_capacity(n, K) == 32 + 512 + 4 * (nc + 1) + 2 * n + 4 * nc
+    assert gsc.rans_capacity(0, K) == 32 + 512 + 4
+    L = gsc.lib()
+    fake = [ctypes.c_void_p(0x10000000 * (i + 1)) for i in range(4)]  # disjoint, never dereferenced
+    ws = gsc.rans_workspace_size(n, K)
+    cap = gsc.rans_capacity(n, K)
+    enc = lambda n=n, k=K, w=ws, c=cap, a=fake[0], o=fake[1]: L.gsc_rans_encode(a, n, k, o, c, fake[2], w, fake[3], None)
+    assert enc(k=0) == 1 and enc(k=(1 << 20) + 1) == 1 and enc(n=-1) == 1 and enc(a=None) == 1
+    assert enc(w=ws - 1) == 3
+    assert enc(c=32) == 4
+    assert enc(o=fake[0]) == 1  # the stream over the input
+    dec = lambda n=n, k=K, c=cap, w=8, o=fake[1]: L.gsc_rans_decode(fake[0], c, n, k, o, fake[2], w, fake[3], None)
+    assert dec(c=100) == 4 and dec(w=4) == 3 and dec(k=0) == 1 and dec(o=fake[0]) == 1
+    with pytest.raises(gsc.GscError):
+        gsc.rans_capacity(10, 0)
