@@ -22,6 +22,8 @@ Other workloads (--workload):
   color_frame1M                the colour decorrelation (YUV + per-channel KLT of the SH
                                coefficients) on a 1M frame with correlated SH: time, HBM
                                fraction and the coded size with and without it
+  rans_frame1M_J12             the occupancy-byte rANS coder on the 1M frame's occupancy
+                               bytes: time and size per chunk length
 """
 from __future__ import annotations
 
@@ -615,6 +617,62 @@ def color_bench(args):
     print(json.dumps(res))
 
 
+def rans_bench(args):
+    """The occupancy-byte rANS coder on the 1M-Gaussian frame's occupancy bytes: GPU encode and
+    decode time and the coded size per chunk length, next to the order-0 entropy of the bytes
+    and the oracle's encode time."""
+    import numpy as np
+    import torch
+    from paper_2606_05650_amd import gsc, synth
+
+    n, J, table = synth.WORKLOADS["frame1M_J12"]
+    pos, attr = synth.make_frame(n, seed=2)
+    dev = torch.device("cuda:0")
+    enc = gsc.encode_frame(torch.from_numpy(pos).to(dev), torch.from_numpy(attr).to(dev),
+                           gsc.make_params(J, attr.shape[1], synth.quant_steps(table)))
+    torch.cuda.synchronize()
+    enc.check()
+    blob = np.frombuffer(enc.to_bytes(), dtype=np.uint8)
+    h = gsc.parse_header(blob)
+    occ = np.ascontiguousarray(blob[int(h["occ_offset"]):int(h["occ_offset"]) + int(h["occ_bytes"])])
+    cnt = np.bincount(occ, minlength=256).astype(np.float64)
+    p = cnt[cnt > 0] / occ.size
+    entropy_bytes = float(-(p * np.log2(p)).sum() * occ.size / 8)
+    t_occ = torch.from_numpy(occ).to(dev)
+    rows = []
+    for K in (256, 512, 1024, 4096, 16384):
+        out = torch.empty(gsc.rans_capacity(occ.size, K), dtype=torch.uint8, device=dev)
+        ws = torch.empty(gsc.rans_workspace_size(occ.size, K), dtype=torch.uint8, device=dev)
+        info = torch.zeros(gsc.INFO_WORDS, dtype=torch.int32, device=dev)
+        dec = torch.empty(occ.size, dtype=torch.uint8, device=dev)
+        wsd = torch.empty(8, dtype=torch.uint8, device=dev)
+        infod = torch.zeros(gsc.INFO_WORDS, dtype=torch.int32, device=dev)
+        s_ = gsc.rans_encode(t_occ, K, out=out, ws=ws, info=info)
+        torch.cuda.synchronize()
+        s_.check()
+        nbytes = s_.nbytes()
+        for _ in range(args.warmup):
+            gsc.rans_encode(t_occ, K, out=out, ws=ws, info=info)
+            gsc.rans_decode(out, occ.size, K, nbytes=nbytes, out=dec, ws=wsd, info=infod)
+        te = timed(lambda: gsc.rans_encode(t_occ, K, out=out, ws=ws, info=info), args.steps, torch)
+        td = timed(lambda: gsc.rans_decode(out, occ.size, K, nbytes=nbytes, out=dec, ws=wsd, info=infod),
+                   args.steps, torch)
+        assert int(infod[0].item()) == 0 and torch.equal(dec, t_occ), "rANS round trip"
+        rows.append({"chunk": K, "bytes": nbytes, "ratio": round(nbytes / occ.size, 4),
+                     "enc_ms": round(te * 1e3, 4), "dec_ms": round(td * 1e3, 4),
+                     "enc_gbs": round(occ.size / te / 1e9, 2), "dec_gbs": round(occ.size / td / 1e9, 2)})
+    res = {"workload": "rans_frame1M_J12", "occupancy_bytes": int(occ.size),
+           "order0_entropy_bytes": round(entropy_bytes), "chunks": rows}
+    if not args.no_cpu_baseline:
+        from oracle import oracle as orc
+        t0 = time.perf_counter()
+        orc.rans_encode(occ, 4096)
+        t = time.perf_counter() - t0
+        res["cpu_baseline"] = {"encode_ms_chunk4096": round(t * 1e3, 1), "cores": 1, "kind": "oracle",
+                               "sample": "one encode of the frame's occupancy bytes (single-threaded C)"}
+    print(json.dumps(res))
+
+
 def copy_calibration(args):
     """Plain copies of a 512 MiB buffer: each launch reads and writes exactly 536,870,912 bytes."""
     import torch
@@ -659,6 +717,8 @@ def main():
         rlgr_bench(args)
     elif args.workload == "color_frame1M":
         color_bench(args)
+    elif args.workload == "rans_frame1M_J12":
+        rans_bench(args)
     else:
         frame_bench(args)
 

@@ -12,9 +12,9 @@
 //     over the frame's rows, in decreasing eigenvalue order, each with its largest-magnitude
 //     component positive; coefficients a = E^T x, inverse x = E a; fewer than two rows: E = I.
 //
-// Three launches: the Gram matrices of the three channels (with a constant-one feature for the
-// sums) on the matrix cores, the eigenvectors (FP64 Jacobi, one wave per channel), and the
-// per-row transform with rows staged through LDS.
+// Launches: the Gram matrices of the three channels (with a constant-one feature for the sums) on
+// the matrix cores, their per-block partials folded in a fixed order, the eigenvectors (FP64
+// Jacobi, one wave per channel), and the per-row transform with rows staged through LDS.
 #include "gsc_device.h"
 
 namespace gsc {
@@ -29,7 +29,7 @@ constexpr int COL_STAT_WAVES = COL_STAT_THREADS / WAVE;
 constexpr int COL_GROUPS = 16;         // 4-row MFMA groups summed in FP32 before joining the FP64 sums
 constexpr int COL_UNROLL = 4;          // groups whose loads are issued together
 constexpr uint32_t COL_ROWS_ALIGN = 4 * COL_GROUPS;
-constexpr int COL_APPLY_THREADS = 256;  // one row per thread
+constexpr int COL_APPLY_ROWS = WAVE;  // rows of a workgroup, one per thread
 
 struct ColorArgs {
     const float *in;     // [n][C]
@@ -112,6 +112,29 @@ __global__ __launch_bounds__(COL_STAT_THREADS) void k_color_stats(ColorArgs a)
     }
 }
 
+// The blocks' partials folded into COL_FOLD groups (group g: blocks g, g + COL_FOLD, ..., summed
+// in that order), so that the eigenvector launch adds COL_FOLD values per entry, not one per block.
+constexpr int COL_FOLD = 8;
+constexpr int COL_FOLD_THREADS = 256;
+__global__ __launch_bounds__(COL_FOLD_THREADS) void k_color_fold(ColorArgs a)
+{
+    const uint32_t gid = blockIdx.x * COL_FOLD_THREADS + threadIdx.x;
+    if (gid >= (uint32_t)(COL_FOLD * COL_ENT)) return;
+    const uint32_t g = gid / COL_ENT, e = gid % COL_ENT;
+    const GAS double *part = gp(a.part);
+    double s = 0.0;
+    uint32_t b = g;
+    for (; b + 3 * COL_FOLD < a.blocks; b += 4 * COL_FOLD) {
+        double v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v[u] = part[(size_t)(b + u * COL_FOLD) * COL_ENT + e];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) s += v[u];
+    }
+    for (; b < a.blocks; b += COL_FOLD) s += part[(size_t)b * COL_ENT + e];
+    gp(a.part)[(size_t)(a.blocks + g) * COL_ENT + e] = s;  // (after the blocks' partials)
+}
+
 // ------------------------------------------------------------------------------ eigenvectors
 constexpr int COL_BASIS_THREADS = 1024;
 constexpr int JACOBI_SWEEPS_MAX = 30;
@@ -126,7 +149,7 @@ __device__ inline void wsync()
 // wave: each step applies 8 rotations on disjoint index pairs (round-robin order, 15 steps per
 // sweep), rows first, then columns, then the eigenvector matrix V (starting as I). A rotation
 // zeroes A[p][q] (the symmetric Schur decomposition of Golub and Van Loan). Sweeps stop when
-// the off-diagonal energy is below 1e-30 of the diagonal's, or after JACOBI_SWEEPS_MAX.
+// the off-diagonal energy is below 1e-26 of the diagonal's, or after JACOBI_SWEEPS_MAX.
 __device__ inline void jacobi16(double (*A)[COL_F], double (*V)[COL_F], double *s_c, double *s_s, uint32_t *s_pq)
 {
     const uint32_t lane = lane_id();
@@ -143,7 +166,7 @@ __device__ inline void jacobi16(double (*A)[COL_F], double (*V)[COL_F], double *
             off += __shfl_xor(off, o, WAVE);
             dia += __shfl_xor(dia, o, WAVE);
         }
-        if (off <= 1e-30 * dia || off == 0.0) break;
+        if (off <= 1e-26 * dia || off == 0.0) break;
         for (int step = 0; step < COL_F - 1; ++step) {
             if (lane < 8) {
                 // players: 0 fixed, the others rotated by the step; pair i = (players[i], players[15 - i])
@@ -211,7 +234,7 @@ __device__ inline void jacobi16(double (*A)[COL_F], double (*V)[COL_F], double *
     }
 }
 
-// One workgroup: the blocks' Gram partials summed in block order (FP64), each channel's
+// One workgroup: the folded Gram partials summed in group order (FP64), each channel's
 // covariance about the mean, its eigenvectors (wave c: channel c), sorted by decreasing
 // eigenvalue with the canonical sign, written as E[c] (and the eigenvalues).
 __global__ __launch_bounds__(COL_BASIS_THREADS) void k_color_basis(ColorArgs a)
@@ -221,18 +244,14 @@ __global__ __launch_bounds__(COL_BASIS_THREADS) void k_color_basis(ColorArgs a)
     __shared__ double s_c[3][8], s_s[3][8];
     __shared__ uint32_t s_pq[3][8];
     const uint32_t t = threadIdx.x;
-    const GAS double *part = gp(a.part);
+    const GAS double *fold = gp(a.part) + (size_t)a.blocks * COL_ENT;  // k_color_fold's groups
     if (t < (uint32_t)COL_ENT) {
+        double v[COL_FOLD];
+#pragma unroll
+        for (int g = 0; g < COL_FOLD; ++g) v[g] = a.blocks ? fold[(size_t)g * COL_ENT + t] : 0.0;
         double s = 0.0;
-        uint32_t b = 0;
-        for (; b + 8 <= a.blocks; b += 8) {
-            double v[8];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) v[u] = part[(size_t)(b + u) * COL_ENT + t];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) s += v[u];
-        }
-        for (; b < a.blocks; ++b) s += part[(size_t)b * COL_ENT + t];
+        for (int g = 0; g < COL_FOLD; ++g) s += v[g];
         s_g[t] = s;
     }
     __syncthreads();
@@ -283,24 +302,37 @@ __global__ __launch_bounds__(COL_BASIS_THREADS) void k_color_basis(ColorArgs a)
 }
 
 // ------------------------------------------------------------------------------ per row
-// A workgroup stages COL_APPLY_THREADS rows in LDS with coalesced loads, each thread transforms
-// one row (forward: YUV, then a_c = E_c^T x_c; inverse: x_c = E_c a_c, then RGB), and the rows
-// leave with coalesced stores. Columns outside the SH range are copied.
-template <bool INV>
-__global__ __launch_bounds__(COL_APPLY_THREADS) void k_color_apply(ColorArgs a)
+// A workgroup (one wave) stages COL_APPLY_ROWS rows in LDS (rows padded to an odd stride, so
+// that the threads' accesses to one column of their rows fall in distinct banks) with coalesced
+// loads (16-byte ones when the rows allow), each thread transforms one row (forward: YUV, then
+// a_c = E_c^T x_c; inverse: x_c = E_c a_c, then RGB), and the rows leave with coalesced stores.
+// Columns outside the SH range are copied.
+template <bool INV, bool VEC>
+__global__ __launch_bounds__(COL_APPLY_ROWS) void k_color_apply(ColorArgs a)
 {
     extern __shared__ float s_rows[];
     __shared__ float s_E[3 * COL_AC * COL_AC];
-    const uint32_t t = threadIdx.x;
-    for (uint32_t i = t; i < 3u * COL_AC * COL_AC; i += COL_APPLY_THREADS) s_E[i] = gp(a.klt)[i];
-    const uint32_t row0 = blockIdx.x * COL_APPLY_THREADS;
-    const uint32_t nr = min((uint32_t)COL_APPLY_THREADS, a.n - row0);
-    const uint32_t nval = nr * a.C;
-    const GAS float *src = gp(a.in) + (size_t)row0 * a.C;
-    for (uint32_t i = t; i < nval; i += COL_APPLY_THREADS) s_rows[i] = src[i];
+    const uint32_t t = threadIdx.x, C = a.C, P = C | 1u;  // padded row stride (odd)
+    for (uint32_t i = t; i < 3u * COL_AC * COL_AC; i += COL_APPLY_ROWS) s_E[i] = gp(a.klt)[i];
+    const uint32_t row0 = blockIdx.x * COL_APPLY_ROWS;
+    const uint32_t nr = min((uint32_t)COL_APPLY_ROWS, a.n - row0);
+    const uint32_t nval = nr * C;
+    const GAS float *src = gp(a.in) + (size_t)row0 * C;
+    if (VEC) {  // C % 4 == 0 and 16-byte aligned rows: a float4 never straddles two rows
+        for (uint32_t i = t; i < nval / 4; i += COL_APPLY_ROWS) {
+            const float4 v = gload4(src + 4 * i);
+            float *d = s_rows + ((4 * i) / C) * P + (4 * i) % C;
+            d[0] = v.x;
+            d[1] = v.y;
+            d[2] = v.z;
+            d[3] = v.w;
+        }
+    } else {
+        for (uint32_t i = t; i < nval; i += COL_APPLY_ROWS) s_rows[(i / C) * P + i % C] = src[i];
+    }
     __syncthreads();
     if (t < nr) {
-        float *x = s_rows + t * a.C + a.sh0;
+        float *x = s_rows + t * P + a.sh0;
         const float *M = INV ? a.mi : a.m;
         // DC: the 3x3 step only
         {
@@ -349,8 +381,15 @@ __global__ __launch_bounds__(COL_APPLY_THREADS) void k_color_apply(ColorArgs a)
         }
     }
     __syncthreads();
-    GAS float *dst = gp(a.out) + (size_t)row0 * a.C;
-    for (uint32_t i = t; i < nval; i += COL_APPLY_THREADS) dst[i] = s_rows[i];
+    GAS float *dst = gp(a.out) + (size_t)row0 * C;
+    if (VEC) {
+        for (uint32_t i = t; i < nval / 4; i += COL_APPLY_ROWS) {
+            const float *sr = s_rows + ((4 * i) / C) * P + (4 * i) % C;
+            gstore4(dst + 4 * i, make_float4(sr[0], sr[1], sr[2], sr[3]));
+        }
+    } else {
+        for (uint32_t i = t; i < nval; i += COL_APPLY_ROWS) dst[i] = s_rows[(i / C) * P + i % C];
+    }
 }
 
 // ------------------------------------------------------------------------------ launches
@@ -368,8 +407,17 @@ uint32_t color_stat_blocks(uint32_t n)
 }
 size_t color_workspace_bytes(uint32_t n)
 {
-    const uint32_t b = color_stat_blocks(n);
-    return (size_t)(b ? b : 1u) * COL_ENT * sizeof(double);
+    return (size_t)(color_stat_blocks(n) + COL_FOLD) * COL_ENT * sizeof(double);
+}
+
+template <bool INV>
+static void launch_apply(const ColorArgs &a, hipStream_t s)
+{
+    const bool vec = a.C % 4 == 0 && ((uintptr_t)a.in & 15u) == 0 && ((uintptr_t)a.out & 15u) == 0;
+    const dim3 grid((a.n + COL_APPLY_ROWS - 1) / COL_APPLY_ROWS), block(COL_APPLY_ROWS);
+    const size_t lds = (size_t)COL_APPLY_ROWS * (a.C | 1u) * sizeof(float);
+    if (vec) hipLaunchKernelGGL((k_color_apply<INV, true>), grid, block, lds, s, a);
+    else hipLaunchKernelGGL((k_color_apply<INV, false>), grid, block, lds, s, a);
 }
 
 static void yuv_matrices(float *m, float *mi)
@@ -405,11 +453,13 @@ hipError_t launch_color_forward(const float *in, float *out, uint32_t n, uint32_
     a.rows_per_wave = color_rows_per_wave(n);
     a.blocks = color_stat_blocks(n);
     yuv_matrices(a.m, a.mi);
-    if (a.blocks > 0) hipLaunchKernelGGL(k_color_stats, dim3(a.blocks), dim3(COL_STAT_THREADS), 0, s, a);
+    if (a.blocks > 0) {
+        hipLaunchKernelGGL(k_color_stats, dim3(a.blocks), dim3(COL_STAT_THREADS), 0, s, a);
+        hipLaunchKernelGGL(k_color_fold, dim3((COL_FOLD * COL_ENT + COL_FOLD_THREADS - 1) / COL_FOLD_THREADS),
+                           dim3(COL_FOLD_THREADS), 0, s, a);
+    }
     hipLaunchKernelGGL(k_color_basis, dim3(1), dim3(COL_BASIS_THREADS), 0, s, a);
-    if (n > 0)
-        hipLaunchKernelGGL(k_color_apply<false>, dim3((n + COL_APPLY_THREADS - 1) / COL_APPLY_THREADS),
-                           dim3(COL_APPLY_THREADS), (size_t)COL_APPLY_THREADS * C * sizeof(float), s, a);
+    if (n > 0) launch_apply<false>(a, s);
     return hipGetLastError();
 }
 
@@ -429,9 +479,7 @@ hipError_t launch_color_inverse(const float *in, float *out, uint32_t n, uint32_
     a.rows_per_wave = 0;
     a.blocks = 0;
     yuv_matrices(a.m, a.mi);
-    if (n > 0)
-        hipLaunchKernelGGL(k_color_apply<true>, dim3((n + COL_APPLY_THREADS - 1) / COL_APPLY_THREADS),
-                           dim3(COL_APPLY_THREADS), (size_t)COL_APPLY_THREADS * C * sizeof(float), s, a);
+    if (n > 0) launch_apply<true>(a, s);
     return hipGetLastError();
 }
 

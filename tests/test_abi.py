@@ -282,9 +282,9 @@ def test_rlgr_sizes_and_argument_checks():
 
 
 def test_color_sizes_and_argument_checks():
-    # one block of 512 threads per 8 waves' rows; at most 256 blocks of 768 FP64 partial sums
-    assert gsc.color_workspace_size(0) == 768 * 8
-    assert gsc.color_workspace_size(1_000_000) <= 256 * 768 * 8
+    # at most 256 blocks of 768 FP64 partial sums, then 8 folded groups of them
+    assert gsc.color_workspace_size(0) == 8 * 768 * 8
+    assert gsc.color_workspace_size(1_000_000) <= (256 + 8) * 768 * 8
     L = gsc.lib()
     fake = [ctypes.c_void_p(0x1000000 * (i + 1)) for i in range(6)]  # disjoint, never dereferenced
     n, C = 1000, 56
