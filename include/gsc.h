@@ -358,8 +358,9 @@ gsc_status gsc_rlgr_decode(const void *d_in, size_t in_bytes, int64_t nv, int32_
  *   Coder: 32-bit rANS with byte renormalisation (state in [2^23, 2^31)); the input is cut into
  *   chunks of K bytes (the last one shorter), each coded on its own from the state 2^23 with its
  *   symbols taken last to first and stored in reverse emission order (its final state first,
- *   most significant byte first), so a decoder reads each chunk forward and must end in the
- *   state 2^23 with every byte of the chunk consumed.
+ *   most significant byte first), so a decoder reads each chunk forward; it accepts a chunk
+ *   whose first state is at least 2^23 (an encoder's always is) and that ends in the state 2^23
+ *   with every byte of the chunk consumed.
  *   Stream: gsc_rans_header, the table uint16[256], the chunks' first bytes uint32[nchunks + 1]
  *   (counted from the data; the last entry is `total`), then the data. Little-endian.
  * gsc_rans_capacity / gsc_rans_workspace_size: worst-case stream bytes (2 bytes per input byte
@@ -369,7 +370,11 @@ gsc_status gsc_rlgr_decode(const void *d_in, size_t in_bytes, int64_t nv, int32_
  * gsc_rans_decode: d_in (in_bytes) -> d_out (n bytes); n and K must match the header;
  *   GSC_ERR_CORRUPT_STREAM in d_info[0] for a header, table or chunk that does not decode as
  *   above (the bytes of such a chunk are then unspecified). d_ws: 8 bytes.
- * K is 1 .. 2^20; n < 2^31. Inputs and outputs must not overlap.
+ * K is 1 .. 2^20; n < 2^31. Inputs and outputs must not overlap. The stream (d_out of the
+ * encoder, d_in of the decoder) and d_ws must be 8-byte aligned, d_info 4-byte aligned
+ * (GSC_ERR_INVALID_ARG otherwise); the raw bytes (the encoder's d_in, the decoder's d_out) may
+ * start anywhere. The kernels read only whole aligned words that hold at least one byte of
+ * their buffer, and read the bytes of a word that reaches outside it one by one.
  * ---------------------------------------------------------------------------------------- */
 #define GSC_RANS_MAGIC 0x314E4152u /* "RAN1" */
 typedef struct gsc_rans_header {

@@ -24,8 +24,10 @@
  *       renormalisation bytes in the order it needs them.
  *   A3  Decoding a chunk: x from its first four bytes; per symbol, slot = x mod 2^12, s the byte
  *       with start_s <= slot < start_s + f_s, x = f_s (x >> 12) + slot - start_s, and while
- *       x < L, x = 256 x + the next byte. A chunk is accepted only if it ends in the state L
- *       with every one of its bytes consumed.
+ *       x < L, x = 256 x + the next byte. A chunk is accepted only if its first state is at
+ *       least L (an encoder's final state always is) and it ends in the state L with every one
+ *       of its bytes consumed. (So an accepted chunk never holds more than 2 bytes per symbol
+ *       plus 4.)
  *
  * Every function returns a negative value on a bad argument (-1), a capacity overflow (-2) or a
  * chunk that does not decode as A3 requires (-3).
@@ -144,6 +146,7 @@ int orc_rans_decode(const int64_t *off, const uint8_t *data, int64_t n, int K, c
         int64_t p = p0;
         uint32_t x = 0;
         for (int k = 0; k < 4; ++k) x = (x << 8) | data[p++];
+        if (x < RANS_L) return -3;
         for (int64_t i = b; i < e; ++i) {
             const uint32_t slot = x & (RANS_M - 1u);
             const uint32_t s = sym[slot];

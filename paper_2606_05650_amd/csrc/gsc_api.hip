@@ -1031,6 +1031,7 @@ gsc_status gsc_rans_encode(const void *d_in, int64_t n, int32_t K, void *d_out, 
     gsc_status st = rans_shape(n, K);
     if (st != GSC_OK) return st;
     if (!d_out || !d_ws || !d_info || (n > 0 && !d_in)) return GSC_ERR_INVALID_ARG;
+    if ((((uintptr_t)d_out | (uintptr_t)d_ws) & 7u) || ((uintptr_t)d_info & 3u)) return GSC_ERR_INVALID_ARG;
     const uint64_t need = rans_workspace_bytes((uint64_t)n, (uint32_t)K);
     if (ws_bytes < need) return GSC_ERR_WORKSPACE;
     const uint64_t nc = rans_chunks((uint64_t)n, (uint32_t)K);
@@ -1055,6 +1056,7 @@ gsc_status gsc_rans_decode(const void *d_in, size_t in_bytes, int64_t n, int32_t
     gsc_status st = rans_shape(n, K);
     if (st != GSC_OK) return st;
     if (!d_in || !d_ws || !d_info || (n > 0 && !d_out)) return GSC_ERR_INVALID_ARG;
+    if ((((uintptr_t)d_in | (uintptr_t)d_ws) & 7u) || ((uintptr_t)d_info & 3u)) return GSC_ERR_INVALID_ARG;
     if (ws_bytes < 8) return GSC_ERR_WORKSPACE;
     const uint64_t nc = rans_chunks((uint64_t)n, (uint32_t)K);
     if (in_bytes < sizeof(gsc_rans_header) + 512 + 4 * (nc + 1)) return GSC_ERR_CAPACITY;

@@ -317,5 +317,13 @@ def test_rans_sizes_and_argument_checks():
     assert enc(o=fake[0]) == 1  # the stream over the input
     dec = lambda n=n, k=K, c=cap, w=8, o=fake[1]: L.gsc_rans_decode(fake[0], c, n, k, o, fake[2], w, fake[3], None)
     assert dec(c=100) == 4 and dec(w=4) == 3 and dec(k=0) == 1 and dec(o=fake[0]) == 1
+    # the stream and the workspace 8-byte aligned; the raw bytes anywhere (no launch is reached
+    # with a misaligned pointer; an aligned call would launch, so only rejections are tried here)
+    odd = lambda p, d: ctypes.c_void_p(p.value + d)
+    assert enc(o=odd(fake[1], 4)) == 1
+    assert L.gsc_rans_encode(fake[0], n, K, fake[1], cap, odd(fake[2], 1), ws, fake[3], None) == 1
+    assert L.gsc_rans_encode(fake[0], n, K, fake[1], cap, fake[2], ws, odd(fake[3], 2), None) == 1
+    assert L.gsc_rans_decode(odd(fake[0], 2), cap, n, K, fake[1], fake[2], 8, fake[3], None) == 1
+    assert L.gsc_rans_decode(fake[0], cap, n, K, fake[1], odd(fake[2], 4), 8, fake[3], None) == 1
     with pytest.raises(gsc.GscError):
         gsc.rans_capacity(10, 0)

@@ -56,6 +56,30 @@ def test_random_bytes_match_oracle(n, alphabet, K):
     _roundtrip(data, K)
 
 
+@pytest.mark.parametrize("shift", [1, 2, 3, 5])
+def test_unaligned_bytes(shift):
+    """The raw bytes may start anywhere: the encoder's input and the decoder's output taken as
+    views at a byte offset into larger buffers (the stream itself stays aligned)."""
+    dev = _dev()
+    rng = np.random.default_rng(40 + shift)
+    for n, K in ((5, 3), (1000, 7), (20_011, 333), (65_536, 4096)):
+        data = rng.choice(7, size=n, p=[0.4, 0.2, 0.15, 0.1, 0.1, 0.04, 0.01]).astype(np.uint8)
+        print(f"case shift={shift} n={n} K={K}", flush=True)
+        big = torch.zeros(n + 16, dtype=torch.uint8, device=dev)
+        big[shift:shift + n] = torch.from_numpy(data).to(dev)
+        s = gsc.rans_encode(big[shift:shift + n], K)
+        torch.cuda.synchronize()
+        s.check()
+        assert s.to_bytes() == _oracle_stream(data, K)
+        out_big = torch.full((n + 16,), 0xA5, dtype=torch.uint8, device=dev)
+        out, info = gsc.rans_decode(s.buf, n, K, out=out_big[shift:shift + n])
+        torch.cuda.synchronize()
+        assert int(info[0].item()) == 0
+        ob = out_big.cpu().numpy()
+        assert np.array_equal(ob[shift:shift + n], data)
+        assert np.all(ob[:shift] == 0xA5) and np.all(ob[shift + n:] == 0xA5)  # nothing written outside
+
+
 def test_empty_input():
     _roundtrip(np.zeros(0, dtype=np.uint8), 128)
 
@@ -107,3 +131,21 @@ def test_damaged_streams_are_rejected():
         out, info = gsc.rans_decode(torch.from_numpy(good.copy()).to(dev), n_, K_)
         torch.cuda.synchronize()
         assert int(info[0].item()) == 5
+
+
+def test_first_state_below_the_bound_is_rejected():
+    """The oracle's pin of the same rule: one byte 0 under the table {0: 4096} stored as the chunk
+    00 00 80 00 00 (first state 2^15) instead of the encoder's 00 80 00 00."""
+    dev = _dev()
+    good = np.frombuffer(_oracle_stream(np.zeros(1, dtype=np.uint8), 1), dtype=np.uint8)
+    hsz = 32
+    h = np.frombuffer(good[:hsz].tobytes(), dtype=gsc.RANS_HEADER_DTYPE).copy()
+    assert good[hsz + 520:].tolist() == [0x00, 0x80, 0x00, 0x00]
+    h["total"] = 5
+    crafted = np.concatenate([np.frombuffer(h.tobytes(), dtype=np.uint8), good[hsz:hsz + 512],
+                              np.array([0, 5], dtype="<u4").view(np.uint8),
+                              np.array([0x00, 0x00, 0x80, 0x00, 0x00], dtype=np.uint8)])
+    for blob, want in ((good, 0), (crafted, 5)):
+        out, info = gsc.rans_decode(torch.from_numpy(blob.copy()).to(dev), 1, 1)
+        torch.cuda.synchronize()
+        assert int(info[0].item()) == want

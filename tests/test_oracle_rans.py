@@ -113,3 +113,16 @@ def test_empty_and_damaged():
     flipped[0] ^= 0x40                   # the first chunk's state
     with pytest.raises(ValueError):
         orc.rans_decode(f, off, flipped, len(d), 512)
+
+
+def test_first_state_below_the_renormalisation_bound_is_rejected():
+    """One byte 0 under the table {0: 4096}: the encoder writes the chunk 00 80 00 00 (its final
+    state 2^23). The chunk 00 00 80 00 00 starts in the state 2^15 and would still end in 2^23
+    with every byte read (the decoded state stays 2^15, one byte 00 brings it to 2^23); a decoder
+    must reject it, since an encoder's first stored state is never below 2^23."""
+    f, off, out = orc.rans_encode(b"\x00", 1)
+    assert int(f[0]) == 4096 and out.tobytes() == bytes([0x00, 0x80, 0x00, 0x00])
+    assert orc.rans_decode(f, off, out, 1, 1).tobytes() == b"\x00"
+    crafted = np.array([0x00, 0x00, 0x80, 0x00, 0x00], dtype=np.uint8)
+    with pytest.raises(ValueError):
+        orc.rans_decode(f, np.array([0, 5], dtype=np.int64), crafted, 1, 1)
