@@ -9,9 +9,10 @@ by the voxel's member count. Nv is only known once the encoder has run, so this 
 the device to cut the outputs to Nv rows.
 
 SteCoderPadded.apply(attr, pos, params) is the same layer without that wait, for training loops
-and graph capture: it returns n rows (rows past Nv are zero) and Nv as a one-element device
-tensor. Nothing in its forward or backward synchronizes the host. A device-detected error
-(corrupt input, capacity) leaves Nv = 0, which makes rd_loss's distortion NaN.
+that must not stall on the device: it returns n rows (its outputs start zeroed and the kernels
+write rows below Nv only, so rows past Nv are zero) and Nv as a one-element device tensor.
+Nothing in its forward or backward synchronizes the host. A device-detected error (corrupt
+input, capacity) leaves Nv = 0, which makes rd_loss's distortion NaN.
 
 rd_loss is the rate-distortion objective of the differentiable workload: the mean squared error
 of the decoded attributes against the voxel means plus lambda times the rate proxy
@@ -61,15 +62,16 @@ class SteCoderPadded(torch.autograd.Function):
     def forward(ctx, attr, pos, params):
         if not attr.is_cuda:
             raise ValueError("SteCoderPadded runs on the GPU only")
-        fwd = gsc.ste_forward(pos.contiguous(), attr.detach().contiguous(), params)
-        n = fwd.n
+        n = int(pos.shape[0])
+        rows = (max(n, 1), int(params.C))
+        # zeroed outputs: the kernels write rows below Nv only
+        z = [torch.zeros(rows, dtype=torch.float32, device=attr.device) for _ in range(3)]
+        fwd = gsc.ste_forward(pos.contiguous(), attr.detach().contiguous(), params, yhat=z[0], ahat=z[1], aref=z[2])
         info = fwd.encoded.info
-        # Nv on the device (0 after a device-detected error); rows past it are masked to zero
+        # Nv on the device (0 after a device-detected error)
         nv = torch.where(info[0:1] == 0, info[1:2], torch.zeros_like(info[1:2])).to(torch.int64)
-        keep = (torch.arange(n, device=attr.device) < nv).unsqueeze(1)
         ctx.fwd = fwd
-        out = [torch.where(keep, t[:n], torch.zeros((), dtype=t.dtype, device=t.device))
-               for t in (fwd.yhat, fwd.ahat, fwd.aref)]
+        out = [t[:n] for t in z]
         ctx.mark_non_differentiable(out[2], nv)
         return out[0], out[1], out[2], nv
 
@@ -78,32 +80,16 @@ class SteCoderPadded(torch.autograd.Function):
         return _backward(ctx, g_yhat, g_ahat), None, None
 
 
-def staged_sum(x, width=256):
-    """The sum of every element of x, taken in stages of `width` contiguous values per output
-    (zero-padded). Each stage is a reduction whose outputs each come from one workgroup, so no
-    stage needs the cross-workgroup semaphores that a single large reduction clears with a
-    memset: the sum stays free of memset nodes when it is captured into a HIP graph."""
-    x = x.reshape(-1)
-    while x.numel() > 1:
-        pad = (-x.numel()) % width
-        if pad:
-            x = torch.nn.functional.pad(x, (0, pad))
-        x = x.view(-1, width).sum(dim=1)
-    return x.reshape(())
-
-
 def rd_loss(yhat, ahat, aref, steps, lam, nv=None):
     """(loss, distortion, rate): mean((ahat - aref)^2) + lam * sum(log2(1 + |yhat| / steps)).
 
     With nv (SteCoderPadded's device count) the rows are the padded ones: the mean is taken over
-    the nv voxel rows (the zero rows past them add nothing to either term), and both sums are
-    staged (staged_sum), so that the whole step can be captured into a graph."""
+    the nv voxel rows (the zero rows past them add nothing to either term), with no host wait."""
     sq = (ahat - aref) ** 2
     r = torch.log2(1.0 + yhat.abs() / steps)
     if nv is None:
         dist = sq.mean()
-        rate = lam * r.sum()
     else:
-        dist = staged_sum(sq) / (nv.to(sq.dtype) * sq.shape[1]).reshape(())
-        rate = lam * staged_sum(r)
+        dist = sq.sum() / (nv.to(sq.dtype) * sq.shape[1]).reshape(())
+    rate = lam * r.sum()
     return dist + rate, dist, rate
