@@ -175,14 +175,25 @@ __device__ inline void prelude_tile(const TileMap &m, uint32_t f, int k, uint32_
                          : LVL_NONE;
     // active lists of the levels that can hold a merge: an entry merges at a level of at most 3J
     // (the tile's first entry of the sequence, LVL_NONE, is in every list and is never a right
-    // sibling)
+    // sibling). s_mask[q][c] has bit i set when entry i of chunk c has a level >= q. Levels are
+    // below 128, so seven ballots give the bit planes of a chunk's levels; lane q compares every
+    // entry's level with q on those planes (most significant bit first: an entry is below q
+    // from the first bit where the two differ and q has a one) and stores the list of level q.
+    static_assert(NLVL <= WAVE && LVL_NONE < 128, "one lane per level; seven bit planes");
     const uint32_t nlvl = min(3u * fd.J + 1u, (uint32_t)NLVL);
-    for (uint32_t q = 1; q < nlvl; ++q) {
 #pragma unroll
-        for (int x = 0; x < PRE_EPT; ++x) {
-            const uint64_t b = __ballot(lvl[x] >= q);
-            if (lane == 0) s_mask[q][w + x * PRE_WAVES] = b;
+    for (int x = 0; x < PRE_EPT; ++x) {
+        uint64_t plane[7];
+#pragma unroll
+        for (int bit = 0; bit < 7; ++bit) plane[bit] = __ballot((lvl[x] >> bit) & 1u);
+        uint64_t below = 0, same = ~0ull;  // entries below lane's q; entries equal so far
+#pragma unroll
+        for (int bit = 6; bit >= 0; --bit) {
+            const uint64_t qm = ((lane >> bit) & 1u) ? ~0ull : 0ull;
+            below |= same & ~plane[bit] & qm;
+            same &= ~(plane[bit] ^ qm);
         }
+        if (lane >= 1 && lane < nlvl) s_mask[lane][w + x * PRE_WAVES] = ~below;
     }
     __syncthreads();
 
