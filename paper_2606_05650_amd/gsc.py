@@ -461,6 +461,46 @@ def tune_get(J, n):
     return v.value
 
 
+SORT_DEFAULT_VARIANT = 0
+_N_LIMIT = (1 << 30) - 1  # the largest frame the library takes
+_MAX_DEPTH = 21
+
+
+def tune_table():
+    """The process's tuned sort tilings: {(J, size class c): variant} for every depth and frame
+    size class (frames of 2^(c-1) < n <= 2^c Gaussians) whose tiling differs from the default."""
+    out = {}
+    for J in range(1, _MAX_DEPTH + 1):
+        for c in range(0, 31):
+            n = min(1 << c, _N_LIMIT)
+            if c > 0 and n <= (1 << (c - 1)):
+                break
+            v = tune_get(J, n)
+            if v != SORT_DEFAULT_VARIANT:
+                out[(J, c)] = v
+    return out
+
+
+def save_tuning(path):
+    """Writes tune_table() to a JSON file (a list of {"J", "size_class", "variant"})."""
+    import json
+    rows = [{"J": J, "size_class": c, "variant": v} for (J, c), v in sorted(tune_table().items())]
+    with open(path, "w") as f:
+        json.dump({"version": VERSION, "sort_variants": SORT_VARIANTS, "entries": rows}, f, indent=1)
+
+
+def load_tuning(path):
+    """Sets the sort tilings saved by save_tuning (entries of another library version or variant
+    count are refused)."""
+    import json
+    with open(path) as f:
+        d = json.load(f)
+    if d.get("version") != VERSION or d.get("sort_variants") != SORT_VARIANTS:
+        raise ValueError("tuning file of another library version or variant set")
+    for e in d["entries"]:
+        tune_set(int(e["J"]), min(1 << int(e["size_class"]), _N_LIMIT), int(e["variant"]))
+
+
 def decode_batch(encoded, n_caps, *, workspaces=None, stream=None):
     """encoded: list of Encoded. Returns a list of Decoded (pos, attr only)."""
     torch = _torch()

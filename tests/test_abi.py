@@ -327,3 +327,25 @@ def test_rans_sizes_and_argument_checks():
     assert L.gsc_rans_decode(fake[0], cap, n, K, fake[1], odd(fake[2], 4), 8, fake[3], None) == 1
     with pytest.raises(gsc.GscError):
         gsc.rans_capacity(10, 0)
+
+
+def test_tuning_table_round_trips_through_a_file(tmp_path):
+    """The autotuner's table (host memory only, no GPU needed): entries set, saved, cleared,
+    loaded back; the sizes of one class share an entry."""
+    gsc.tune_set(12, 1_000_000, 2)
+    gsc.tune_set(14, 4_000_000, 3)
+    gsc.tune_set(10, 100_000, 0)          # the default: not listed
+    try:
+        t = gsc.tune_table()
+        assert t[(12, 20)] == 2 and t[(14, 22)] == 3 and (10, 17) not in t
+        assert gsc.tune_get(12, 600_000) == 2  # same size class (2^19 < n <= 2^20)
+        path = tmp_path / "tune.json"
+        gsc.save_tuning(str(path))
+        gsc.tune_set(12, 1_000_000, -1)
+        gsc.tune_set(14, 4_000_000, -1)
+        assert gsc.tune_table() == {}
+        gsc.load_tuning(str(path))
+        assert gsc.tune_table() == t
+    finally:
+        gsc.tune_set(12, 1_000_000, -1)
+        gsc.tune_set(14, 4_000_000, -1)
