@@ -68,8 +68,8 @@ def alg_bytes(stage, n, nv, C):
 KERNEL_SOURCES = ("paper_2606_05650_amd/csrc/k_raht.hip", "paper_2606_05650_amd/csrc/gsc_device.h",
                   "paper_2606_05650_amd/csrc/gsc_internal.h")
 PMC_TRAFFIC = {"workload": "frame1M_J12",
-               "sources_sha256": "03ab9d018b6e290ab6ea4f7f7bc76e916b24810b867a650f96b4376420d3ff13",
-               "raht_fwd1": 597863831, "raht_inv1": 466884584}
+               "sources_sha256": "4a8021af4a17d55915ea9d3b44e245d3f5cc41a5d87ebf57dba19cd16046b1e3",
+               "raht_fwd1": 596135916, "raht_inv1": 466824592}
 KERNEL_NAMES = {"raht_fwd1": "k_raht_fwd", "raht_inv1": "k_raht_inv"}
 
 
