@@ -727,16 +727,58 @@ __global__ __launch_bounds__(OCC_THREADS) void k_occupancy(TileMap m)
             Dv[i] = 0xFFFFu;  // not a voxel: never a head, never contributes
         }
     }
-    for (uint32_t d = 0; d < J; ++d) {
-        uint32_t my = 0;
+    // The heads of every depth ranked at once. Voxel j = 2 t + i of the tile (thread t, slot i) is
+    // a head at depth d when Dv <= d; its node's byte is number H - 1 of the tile at that depth,
+    // H counting the heads up to and including it. Per wave, five ballots per slot give the bit
+    // planes of the voxels' head depths (a non-voxel counts as depth 31, never a head); lane d
+    // compares them with d (most significant bit first) into the wave's head masks of depth d
+    // and stores their count, so one barrier and a prefix over the 16 waves replace a block scan
+    // per depth.
+    static_assert(OCC_VPT == 2 && GSC_MAX_DEPTH < 31 && GSC_MAX_DEPTH <= WAVE, "two slots, five planes");
+    __shared__ uint32_t s_wcnt[GSC_MAX_DEPTH][OCC_THREADS / WAVE];
+    const uint32_t lane = lane_id(), wv = tid / WAVE;
+    uint64_t le[OCC_VPT];  // lane d < J: the wave's voxels of slot i that are heads at depth d
 #pragma unroll
-        for (int i = 0; i < OCC_VPT; ++i) my += Dv[i] <= d ? 1u : 0u;
-        uint32_t total;
-        uint32_t run = block_excl_scan<OCC_THREADS>(my, s_tmp, &total);
+    for (int i = 0; i < OCC_VPT; ++i) {
+        const uint32_t dv = min(Dv[i], 31u);
+        uint64_t plane[5];
+#pragma unroll
+        for (int bit = 0; bit < 5; ++bit) plane[bit] = __ballot((dv >> bit) & 1u);
+        uint64_t above = 0, same = ~0ull;  // voxels deeper than lane's d; equal so far
+#pragma unroll
+        for (int bit = 4; bit >= 0; --bit) {
+            const uint64_t qm = ((lane >> bit) & 1u) ? ~0ull : 0ull;
+            above |= same & plane[bit] & ~qm;
+            same &= ~(plane[bit] ^ qm);
+        }
+        le[i] = ~above;
+    }
+    if (lane < J) s_wcnt[lane][wv] = (uint32_t)(__popcll(le[0]) + __popcll(le[1]));
+    __syncthreads();
+    uint32_t pre = 0, total = 0;  // lane d < J: heads of depth d in the waves before / in the tile
+    if (lane < J) {
+        for (uint32_t w2 = 0; w2 < OCC_THREADS / WAVE; ++w2) {
+            const uint32_t c = s_wcnt[lane][w2];
+            pre += w2 < wv ? c : 0u;
+            total += c;
+        }
+        if (wv == 0) s_cnt[lane] = total;
+    }
+    const uint64_t lt = lanemask_lt(), me = 1ull << lane;
+    for (uint32_t d = 0; d < J; ++d) {
+        // (readlane returns an int: each half goes through uint32_t, so the low one is not
+        // sign-extended into the high one)
+        auto lane64 = [d](uint64_t v) -> uint64_t {
+            return (uint64_t)(uint32_t)__builtin_amdgcn_readlane((uint32_t)v, d) |
+                   ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((uint32_t)(v >> 32), d) << 32);
+        };
+        const uint64_t m0 = lane64(le[0]), m1 = lane64(le[1]);
+        const uint32_t p = __builtin_amdgcn_readlane(pre, d);
+        uint32_t run = p + (uint32_t)__popcll(m0 & lt) + (uint32_t)__popcll(m1 & lt);
         const uint32_t sh = 3u * (J - d - 1u);
 #pragma unroll
         for (int i = 0; i < OCC_VPT; ++i) {
-            if (Dv[i] <= d) ++run;
+            run += ((i == 0 ? m0 : m1) & me) ? 1u : 0u;
             if (Dv[i] <= d + 1u) {
                 const uint32_t bit = 1u << (uint32_t)((cv[i] >> sh) & 7u);
                 if (run == 0) {
@@ -747,7 +789,6 @@ __global__ __launch_bounds__(OCC_THREADS) void k_occupancy(TileMap m)
                 }
             }
         }
-        if (tid == 0) s_cnt[d] = total;
     }
     __syncthreads();
     // the stream geometry, by the last wave beside the look-backs (it depends only on the depth
