@@ -141,6 +141,10 @@ def test_other_layouts():
     only = np.ascontiguousarray(attr[:, 8:56])  # C = 48, sh0 = 0
     _check_forward(only, 0)
     _check_inverse(only, 0)
+    # C = 51 (not a multiple of 4: the kernels' scalar row path), SH at columns 3..50
+    odd = np.ascontiguousarray(np.concatenate([attr[:, 5:8], attr[:, 8:56]], axis=1))
+    _check_forward(odd, 3)
+    _check_inverse(odd, 3)
 
 
 def test_empty_frame():
