@@ -80,6 +80,19 @@ def test_unaligned_bytes(shift):
         assert np.all(ob[:shift] == 0xA5) and np.all(ob[shift + n:] == 0xA5)  # nothing written outside
 
 
+def test_largest_chunks_and_extreme_tables():
+    """Chunks of the largest length (2^20 bytes, the coder's limit) on uniform bytes (every byte
+    at frequency 16, about one output byte per input byte), and a table where one byte has
+    frequency 1 (12 bits of code each time it occurs) next to one that takes the rest."""
+    rng = np.random.default_rng(77)
+    _roundtrip(rng.integers(0, 256, size=(1 << 20) + 3).astype(np.uint8), 1 << 20)
+    data = np.zeros(200_000, dtype=np.uint8)
+    data[rng.choice(data.size, size=7, replace=False)] = 255
+    want = _roundtrip(data, 5000)
+    f = np.frombuffer(want[32:32 + 512], dtype="<u2")
+    assert f[255] == 1 and f[0] == 4095
+
+
 def test_empty_input():
     _roundtrip(np.zeros(0, dtype=np.uint8), 128)
 
