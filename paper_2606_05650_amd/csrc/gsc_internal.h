@@ -29,6 +29,10 @@ constexpr SortVariant SORT_VARIANT[SORT_VARIANTS] = {{8, 16}, {4, 16}, {12, 16},
 constexpr int SORT_DEFAULT_VARIANT = 0;
 constexpr int SORT_KPT_MIN = 4;
 __host__ __device__ constexpr int sort_tile(int variant) { return SORT_THREADS * SORT_VARIANT[variant].kpt; }
+// tiles per look-back group: a pass's status words are P x tiles x 2^bits tile words followed by
+// P x groups x 2^bits group words
+constexpr uint32_t SORT_LB_GROUP = 16;
+__host__ __device__ constexpr uint32_t sort_groups(uint32_t tiles) { return (tiles + SORT_LB_GROUP - 1) / SORT_LB_GROUP; }
 // histogram words of all passes: at most 8 passes of 256 digits or 7 of 512 (63-bit codes)
 constexpr int SORT_HIST_WORDS = 7 * 512;
 
@@ -178,7 +182,7 @@ struct FrameDesc {
     uint32_t *first;         // encode: input row of every voxel's first member (sorted order)
     uint32_t *bbox_part;     // encode: bounding-box workgroups' partial extrema (BBOX_SLOT each)
     uint32_t *lvl_flags;     // upper-level launches: the phase each workgroup has completed
-    uint32_t *sort_status;   // P x sort tiles x 2^sort_bits
+    uint32_t *sort_status;   // P x (sort tiles + look-back groups) x 2^sort_bits
     uint32_t sort_bits;      // radix digit width (8 or 9)
     uint64_t *dedup_status;
     uint64_t *occ_status;    // occ tiles x J
@@ -302,7 +306,7 @@ __host__ __device__ inline bool make_layout(int64_t n, int J, int C, Layout *L)
     // the sort's status words (zeroed by the voxelize kernel of an encode, which precedes the
     // sort), then the zero region: every other look-back status word and nothing else
     L->sort_status = off;
-    off = align_up(off + (size_t)L->P * L->sort_tiles * ((size_t)1 << sort_bits(J)) * 4, 256);
+    off = align_up(off + (size_t)L->P * (L->sort_tiles + sort_groups(L->sort_tiles)) * ((size_t)1 << sort_bits(J)) * 4, 256);
     L->zero_off = off;
     L->dedup_status = off;
     off = align_up(off + (size_t)L->dedup_tiles * 8, 256);

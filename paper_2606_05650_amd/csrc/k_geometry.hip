@@ -316,7 +316,7 @@ __global__ __launch_bounds__(VOX_THREADS) void k_voxelize(TileMap m)
     {   // this workgroup's share of the sort's look-back status words (they lie outside the
         // region the setup kernel zeroes, since only an encode sorts)
         const uint32_t nb = n ? (n + VOX_TILE - 1) / VOX_TILE : 1u;
-        const uint64_t nq = (uint64_t)P * fd.sort_tiles * bins / 4;
+        const uint64_t nq = (uint64_t)P * (fd.sort_tiles + sort_groups(fd.sort_tiles)) * bins / 4;
         uint4 *z = reinterpret_cast<uint4 *>(fd.sort_status);
         for (uint64_t i = (uint64_t)b * VOX_THREADS + threadIdx.x; i < nq; i += (uint64_t)nb * VOX_THREADS)
             z[i] = make_uint4(0, 0, 0, 0);
@@ -447,7 +447,7 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_pass(TileMap m, int pass)
     __shared__ uint32_t s_wcnt[NW][SORT_BINS];
     __shared__ uint32_t s_gbase[SORT_BINS];
     __shared__ uint32_t s_lstart[SORT_BINS];
-    __shared__ uint32_t s_tmp[NW + 1];
+    __shared__ uint32_t s_tmp[2 * NW];
     __shared__ uint64_t s_keys[TILE];
     __shared__ uint32_t s_vals[TILE];
 
@@ -498,6 +498,7 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_pass(TileMap m, int pass)
     const bool dig = tid < (uint32_t)SORT_BINS;
     const uint32_t d = dig ? tid : 0u;
     uint32_t *status_d = fd.sort_status + (size_t)pass * fd.sort_tiles * SORT_BINS + d;
+    uint32_t *gstatus_d = fd.sort_status + ((size_t)fd.P * fd.sort_tiles + (size_t)pass * sort_groups(fd.sort_tiles)) * SORT_BINS + d;
     uint32_t tile_cnt = 0, hist_excl;
     {
         const uint32_t gh = ctrl->sort_hist[pass * SORT_BINS + d];
@@ -512,9 +513,26 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_pass(TileMap m, int pass)
             tile_cnt = run;
             lookback32_publish(status_d, SORT_BINS, tile, tile_cnt);
         }
-        hist_excl = block_excl_scan<SORT_THREADS>(dig ? gh : 0u, s_tmp, nullptr);
-        const uint32_t ls = block_excl_scan<SORT_THREADS>(tile_cnt, s_tmp, nullptr);
-        if (dig) s_lstart[d] = ls;
+        // the exclusive scans of the frame's digit counts and of the tile's, side by side
+        const uint32_t vh = dig ? gh : 0u;
+        const uint32_t ih = wave_incl_scan(vh), ic = wave_incl_scan(tile_cnt);
+        if (lane == WAVE - 1) {
+            s_tmp[w] = ih;
+            s_tmp[NW + w] = ic;
+        }
+        __syncthreads();
+        if (tid < 2) {
+            uint32_t run = 0;
+#pragma unroll
+            for (int i = 0; i < NW; ++i) {
+                const uint32_t c = s_tmp[tid * NW + i];
+                s_tmp[tid * NW + i] = run;
+                run += c;
+            }
+        }
+        __syncthreads();
+        hist_excl = s_tmp[w] + ih - vh;
+        if (dig) s_lstart[d] = s_tmp[NW + w] + ic - tile_cnt;
     }
     __syncthreads();
     // keys to LDS in tile-local digit order: the keys leave the registers before the look-back,
@@ -526,7 +544,7 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_pass(TileMap m, int pass)
         s_keys[q] = key[j];
         s_vals[q] = val[j];
     }
-    if (dig) s_gbase[d] = hist_excl + lookback32_resolve<WIN>(status_d, SORT_BINS, tile, tile_cnt, ctrl);
+    if (dig) s_gbase[d] = hist_excl + lookback32_resolve<WIN>(status_d, gstatus_d, SORT_BINS, SORT_LB_GROUP, tile, tile_cnt, ctrl);
     __syncthreads();
     const uint32_t nvalid = min((uint32_t)TILE, n - base);
     for (uint32_t q = tid; q < nvalid; q += SORT_THREADS) {

@@ -21,7 +21,7 @@ def _outputs(n, C, dev):
 def test_noalloc_encode_matches_workspace_encode():
     dev = torch.device("cuda:0")
     steps = synth.quant_steps(synth.STEPS_GROUPED)
-    for n, J, seed in [(520_000, 12, 71), (60_000, 10, 72)]:
+    for n, J, seed in [(500_000, 12, 71), (60_000, 10, 72)]:
         print(f"noalloc encode n={n} J={J} seed={seed}", flush=True)
         assert gsc.workspace_size(n, J, 56) <= gsc.STATIC_SCRATCH_BYTES
         pos, attr = synth.make_frame(n, seed=seed)
