@@ -408,11 +408,13 @@ __device__ inline uint64_t lookback_block(uint64_t *status, uint32_t stride, uin
 
 // 32-bit status words for the radix sort: [31:30] flag, [29:0] count (n < 2^30). A tile first
 // publishes its aggregate (tile 0 its inclusive count), then resolves its exclusive prefix in
-// two levels: the tiles form groups of `group`, and the last tile of a group also publishes the
-// group's total (and later the inclusive count through the group's end) in a second array. A
-// tile adds its own group's earlier tiles (one window), then the earlier groups' words, so that
-// with every tile publishing at once it needs about 1 + (t / group) / WIN dependent rounds of
-// device-scope loads instead of t / WIN. A tile waits only on tiles of lower index.
+// two levels: the tiles form groups of `group` (at most WIN + 1), and the last tile of a group
+// also publishes the group's total (and later the inclusive count through the group's end) in a
+// second array. A tile adds its own group's earlier tiles, then the earlier groups' words; the
+// first window of each is loaded at once, so that with every tile publishing at the same time a
+// tile needs about two dependent rounds of device-scope loads (the second one because the
+// groups' totals follow their last tiles' first round) instead of t / WIN. A tile waits only on
+// tiles of lower index.
 constexpr uint32_t LB32_AGG = 1u << 30, LB32_INC = 2u << 30, LB32_VAL = (1u << 30) - 1u;
 
 __device__ inline void lookback32_publish(uint32_t *status, uint32_t stride, uint32_t tile, uint32_t agg)
@@ -420,37 +422,56 @@ __device__ inline void lookback32_publish(uint32_t *status, uint32_t stride, uin
     st_relaxed32(&status[(size_t)tile * stride], (tile == 0 ? LB32_INC : LB32_AGG) | agg);
 }
 
+// Loads status words hi, hi - 1, ..., down to lo (at most WIN of them; 0 past lo).
+template <int WIN>
+__device__ __attribute__((always_inline)) inline void lookback32_load(const uint32_t *status, uint32_t stride, int64_t hi,
+                                                                     int64_t lo, uint32_t (&w)[WIN])
+{
+#pragma unroll
+    for (int i = 0; i < WIN; ++i) w[i] = (hi - i >= lo) ? ld_relaxed32(&status[(size_t)(hi - i) * stride]) : 0u;
+}
+
+// Adds the loaded words of hi, hi - 1, ... (down to lo) to acc up to the first inclusive word
+// (inc) or the first unpublished one (stalled); returns the number of words added.
+template <int WIN>
+__device__ __attribute__((always_inline)) inline int lookback32_take(const uint32_t (&w)[WIN], int64_t hi, int64_t lo,
+                                                                    uint32_t &acc, bool &inc, bool &stalled)
+{
+    int used = 0;
+    bool stop = false;
+    inc = stalled = false;
+#pragma unroll
+    for (int i = 0; i < WIN; ++i) {  // predicated (no break) so w stays in registers
+        const uint32_t flag = w[i] >> 30;
+        const bool in = !stop && hi - i >= lo;
+        if (in && flag != 0) {
+            acc += w[i] & LB32_VAL;
+            ++used;
+        }
+        if (in && flag == 0) stalled = true;
+        if (in && flag != 1) {
+            inc = inc || flag == 2;
+            stop = true;
+        }
+    }
+    return used;
+}
+
 // Adds the values of status words hi, hi - 1, ..., lo (WIN per round, waiting for unpublished
 // ones) to acc, or of the words down to the first inclusive one; returns true if it met an
 // inclusive word (or gave up at the spin limit, with GSC_ERR_INTERNAL set).
 template <int WIN>
-__device__ inline bool lookback32_walk(const uint32_t *status, uint32_t stride, int64_t hi, int64_t lo,
-                                       uint32_t &acc, Ctrl *ctrl)
+__device__ __attribute__((always_inline)) inline bool lookback32_walk(const uint32_t *status, uint32_t stride, int64_t hi,
+                                                                     int64_t lo, uint32_t &acc, Ctrl *ctrl)
 {
     int64_t j = hi;
     uint32_t spins = 0;
     while (j >= lo) {
         uint32_t w[WIN];
-#pragma unroll
-        for (int i = 0; i < WIN; ++i) w[i] = (j - i >= lo) ? ld_relaxed32(&status[(size_t)(j - i) * stride]) : 0u;
-        int used = 0;
-        bool stalled = false, stop = false, inc = false;
-#pragma unroll
-        for (int i = 0; i < WIN; ++i) {  // predicated (no break) so w stays in registers
-            const uint32_t flag = w[i] >> 30;
-            const bool in = !stop && j - i >= lo;
-            if (in && flag != 0) {
-                acc += w[i] & LB32_VAL;
-                ++used;
-            }
-            if (in && flag == 0) stalled = true;
-            if (in && flag != 1) {
-                inc = inc || flag == 2;
-                stop = true;
-            }
-        }
+        lookback32_load<WIN>(status, stride, j, lo, w);
+        bool inc, stalled;
+        j -= lookback32_take<WIN>(w, j, lo, acc, inc, stalled);
         if (inc) return true;
-        j -= used;
         if (stalled) {
             if (++spins > SPIN_LIMIT) {
                 set_error(ctrl, GSC_ERR_INTERNAL);
@@ -463,18 +484,26 @@ __device__ inline bool lookback32_walk(const uint32_t *status, uint32_t stride, 
 }
 
 template <int WIN>
-__device__ inline uint32_t lookback32_resolve(uint32_t *status, uint32_t *gstatus, uint32_t stride, uint32_t group,
-                                              uint32_t tile, uint32_t agg, Ctrl *ctrl)
+__device__ __attribute__((always_inline)) inline uint32_t lookback32_resolve(uint32_t *status, uint32_t *gstatus,
+                                                                            uint32_t stride, uint32_t group, uint32_t tile,
+                                                                            uint32_t agg, Ctrl *ctrl)
 {
     if (tile == 0) return 0;
     const uint32_t g = tile / group, g0 = g * group;
     const bool last = tile - g0 == group - 1;
+    // the group's earlier tiles (at most WIN) and the first window of the earlier groups, at once
+    uint32_t wa[WIN], wb[WIN];
+    lookback32_load<WIN>(status, stride, (int64_t)tile - 1, (int64_t)g0, wa);
+    if (g > 0) lookback32_load<WIN>(gstatus, stride, (int64_t)g - 1, 0, wb);
     uint32_t acc = 0;
-    // the group's earlier tiles (in group 0 this always ends at tile 0's inclusive word)
-    bool done = lookback32_walk<WIN>(status, stride, (int64_t)tile - 1, (int64_t)g0, acc, ctrl);
-    if (!done) {
+    bool inc, stalled;
+    const int ua = lookback32_take<WIN>(wa, (int64_t)tile - 1, (int64_t)g0, acc, inc, stalled);
+    // (in group 0 this always ends at tile 0's inclusive word)
+    bool done = inc || (stalled && lookback32_walk<WIN>(status, stride, (int64_t)tile - 1 - ua, (int64_t)g0, acc, ctrl));
+    if (!done && g > 0) {
         if (last) st_relaxed32(&gstatus[(size_t)g * stride], LB32_AGG | (acc + agg));
-        lookback32_walk<WIN>(gstatus, stride, (int64_t)g - 1, 0, acc, ctrl);
+        const int ub = lookback32_take<WIN>(wb, (int64_t)g - 1, 0, acc, inc, stalled);
+        if (!inc) lookback32_walk<WIN>(gstatus, stride, (int64_t)g - 1 - ub, 0, acc, ctrl);
     }
     st_relaxed32(&status[(size_t)tile * stride], LB32_INC | (acc + agg));
     if (last) st_relaxed32(&gstatus[(size_t)g * stride], LB32_INC | (acc + agg));

@@ -443,7 +443,6 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_pass(TileMap m, int pass)
     constexpr int TILE = SORT_THREADS * KPT;
     constexpr int NW = SORT_THREADS / WAVE;
     constexpr int SORT_BINS = 1 << BITS;
-    __shared__ uint32_t s_tile;
     __shared__ uint32_t s_wcnt[NW][SORT_BINS];
     __shared__ uint32_t s_gbase[SORT_BINS];
     __shared__ uint32_t s_lstart[SORT_BINS];
@@ -454,54 +453,59 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_pass(TileMap m, int pass)
     const uint32_t f = frame_of(m, blockIdx.x);
     const CAS FrameDesc &fd = *cp(m.fd[f]);  // (not written while the kernel runs)
     Ctrl *ctrl = fd.ctrl;
-    if (load_error(ctrl)) return;
     const uint32_t n = fd.n;
     const uint32_t tid = threadIdx.x, w = tid / WAVE, lane = lane_id();
-    if (tid == 0) s_tile = tile_index(m, f);
-    for (uint32_t i = tid; i < NW * SORT_BINS; i += SORT_THREADS) (&s_wcnt[0][0])[i] = 0;
-    __syncthreads();
-    const uint32_t tile = s_tile;
+    const uint32_t tile = __builtin_amdgcn_readfirstlane(tile_index(m, f));
     const uint32_t base = tile * TILE;
-    if (base >= n) return;
     const GAS uint64_t *kin = gp((pass & 1) ? fd.keys_b : fd.keys_a);
     const GAS uint32_t *vin = gp((pass & 1) ? fd.vals_b : fd.vals_a);
     GAS uint64_t *kout = gp((pass & 1) ? fd.keys_a : fd.keys_b);
     GAS uint32_t *vout = gp((pass & 1) ? fd.vals_a : fd.vals_b);
     const uint32_t shift = (uint32_t)pass * BITS;
 
+    // The tile's keys and indices (clamped slots, so that every load is issued at once; the
+    // buffers hold at least one entry) and this thread's digit count of the frame are loaded
+    // before the tile's range and the error word are checked.
+    static_assert(SORT_THREADS >= SORT_BINS, "one thread per digit");
+    static_assert(SORT_LB_GROUP <= (uint32_t)WIN + 1, "a group's earlier tiles fit one look-back window");
+    const bool dig = tid < (uint32_t)SORT_BINS;
+    const uint32_t d = dig ? tid : 0u;
     uint64_t key[KPT];
     uint32_t val[KPT];
     uint32_t rank[KPT];
     const uint32_t wbase = base + w * (KPT * WAVE);
 #pragma unroll
     for (int j = 0; j < KPT; ++j) {
-        const uint32_t p = wbase + j * WAVE + lane;
-        const bool valid = p < n;
-        key[j] = valid ? kin[p] : ~0ull;
-        val[j] = pass == 0 ? p : (valid ? vin[p] : 0u);
+        const uint32_t p = min(wbase + j * WAVE + lane, n ? n - 1 : 0u);
+        key[j] = kin[p];
+        val[j] = pass == 0 ? p : vin[p];
     }
+    const uint32_t gh = ctrl->sort_hist[pass * SORT_BINS + d];
+    for (uint32_t i = tid; i < NW * SORT_BINS; i += SORT_THREADS) (&s_wcnt[0][0])[i] = 0;
+    if (base >= n || load_error(ctrl)) return;
 #pragma unroll
     for (int j = 0; j < KPT; ++j) {
-        const uint32_t d = (uint32_t)(key[j] >> shift) & (SORT_BINS - 1);
-        const uint64_t peers = match_digit<BITS>(d);
-        const uint32_t cnt = s_wcnt[w][d];
+        if (wbase + j * WAVE + lane >= n) key[j] = ~0ull;  // past the end: ranked last, not written
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < KPT; ++j) {
+        const uint32_t dk = (uint32_t)(key[j] >> shift) & (SORT_BINS - 1);
+        const uint64_t peers = match_digit<BITS>(dk);
+        const uint32_t cnt = s_wcnt[w][dk];
         __builtin_amdgcn_wave_barrier();
         const bool leader = lane == (uint32_t)(__ffsll((long long)peers) - 1);
-        if (leader) s_wcnt[w][d] = cnt + (uint32_t)__popcll(peers);
+        if (leader) s_wcnt[w][dk] = cnt + (uint32_t)__popcll(peers);
         rank[j] = cnt + (uint32_t)__popcll(peers & lanemask_lt());
         __builtin_amdgcn_wave_barrier();
     }
     __syncthreads();
     // per digit (thread d < SORT_BINS holds digit d): wave prefixes, tile count (published at
     // once), digit start in the tile, digit start in the output
-    static_assert(SORT_THREADS >= SORT_BINS, "one thread per digit");
-    const bool dig = tid < (uint32_t)SORT_BINS;
-    const uint32_t d = dig ? tid : 0u;
     uint32_t *status_d = fd.sort_status + (size_t)pass * fd.sort_tiles * SORT_BINS + d;
     uint32_t *gstatus_d = fd.sort_status + ((size_t)fd.P * fd.sort_tiles + (size_t)pass * sort_groups(fd.sort_tiles)) * SORT_BINS + d;
     uint32_t tile_cnt = 0, hist_excl;
     {
-        const uint32_t gh = ctrl->sort_hist[pass * SORT_BINS + d];
         if (dig) {
             uint32_t run = 0;
 #pragma unroll
@@ -539,8 +543,8 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_pass(TileMap m, int pass)
     // whose window takes their place
 #pragma unroll
     for (int j = 0; j < KPT; ++j) {
-        const uint32_t d = (uint32_t)(key[j] >> shift) & (SORT_BINS - 1);
-        const uint32_t q = s_lstart[d] + s_wcnt[w][d] + rank[j];
+        const uint32_t dk = (uint32_t)(key[j] >> shift) & (SORT_BINS - 1);
+        const uint32_t q = s_lstart[dk] + s_wcnt[w][dk] + rank[j];
         s_keys[q] = key[j];
         s_vals[q] = val[j];
     }
@@ -549,8 +553,8 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_pass(TileMap m, int pass)
     const uint32_t nvalid = min((uint32_t)TILE, n - base);
     for (uint32_t q = tid; q < nvalid; q += SORT_THREADS) {
         const uint64_t k = s_keys[q];
-        const uint32_t d = (uint32_t)(k >> shift) & (SORT_BINS - 1);
-        const uint32_t o = s_gbase[d] + (q - s_lstart[d]);
+        const uint32_t dk = (uint32_t)(k >> shift) & (SORT_BINS - 1);
+        const uint32_t o = s_gbase[dk] + (q - s_lstart[dk]);
         if (o < n) {
             kout[o] = k;
             vout[o] = s_vals[q];
