@@ -407,19 +407,23 @@ __device__ inline uint64_t lookback_block(uint64_t *status, uint32_t stride, uin
 }
 
 // 32-bit status words for the radix sort: [31:30] flag, [29:0] count (n < 2^30). A tile first
-// publishes its aggregate (tile 0 its inclusive count), then resolves its exclusive prefix in
-// two levels: the tiles form groups of `group` (at most WIN + 1), and the last tile of a group
-// also publishes the group's total (and later the inclusive count through the group's end) in a
-// second array. A tile adds its own group's earlier tiles, then the earlier groups' words; the
-// first window of each is loaded at once, so that with every tile publishing at the same time a
-// tile needs about two dependent rounds of device-scope loads (the second one because the
-// groups' totals follow their last tiles' first round) instead of t / WIN. A tile waits only on
-// tiles of lower index.
+// publishes its aggregate (tile 0 its inclusive count) and adds it, with one arrival, to its
+// group's word (groups of `group` tiles, at most WIN + 1); then it resolves its exclusive prefix
+// from its own group's earlier tiles and the earlier groups' words, the first window of each
+// loaded at once. A group word is a sum while arrivals ([29:25]) are fewer than `group`, the
+// group's total once they are all in, and the inclusive count through the group's end once the
+// group's last tile has resolved (it stores that only after every arrival, so that no addition
+// lands on it). With every tile publishing at about the same time, a tile needs about one round
+// of device-scope loads instead of t / WIN. A tile waits only on tiles of lower index.
 constexpr uint32_t LB32_AGG = 1u << 30, LB32_INC = 2u << 30, LB32_VAL = (1u << 30) - 1u;
+constexpr uint32_t LB32_ARRIVAL = 1u << 25, LB32_GSUM = LB32_ARRIVAL - 1u;
 
-__device__ inline void lookback32_publish(uint32_t *status, uint32_t stride, uint32_t tile, uint32_t agg)
+__device__ inline void lookback32_publish(uint32_t *status, uint32_t *gstatus, uint32_t stride, uint32_t group,
+                                          uint32_t tile, uint32_t agg)
 {
     st_relaxed32(&status[(size_t)tile * stride], (tile == 0 ? LB32_INC : LB32_AGG) | agg);
+    __hip_atomic_fetch_add(&gstatus[(size_t)(tile / group) * stride], LB32_ARRIVAL | agg, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Loads status words hi, hi - 1, ..., down to lo (at most WIN of them; 0 past lo).
@@ -432,10 +436,12 @@ __device__ __attribute__((always_inline)) inline void lookback32_load(const uint
 }
 
 // Adds the loaded words of hi, hi - 1, ... (down to lo) to acc up to the first inclusive word
-// (inc) or the first unpublished one (stalled); returns the number of words added.
+// (inc) or the first one not ready (stalled); returns the number of words added. Tile words are
+// ready once published; group words (group > 0) once every arrival is in or inclusive.
 template <int WIN>
 __device__ __attribute__((always_inline)) inline int lookback32_take(const uint32_t (&w)[WIN], int64_t hi, int64_t lo,
-                                                                    uint32_t &acc, bool &inc, bool &stalled)
+                                                                    uint32_t group, uint32_t &acc, bool &inc,
+                                                                    bool &stalled)
 {
     int used = 0;
     bool stop = false;
@@ -443,26 +449,30 @@ __device__ __attribute__((always_inline)) inline int lookback32_take(const uint3
 #pragma unroll
     for (int i = 0; i < WIN; ++i) {  // predicated (no break) so w stays in registers
         const uint32_t flag = w[i] >> 30;
+        const bool is_inc = flag == 2;
+        const bool ready = group ? (is_inc || (w[i] >> 25) == group) : flag != 0;
+        const uint32_t v = is_inc ? (w[i] & LB32_VAL) : group ? (w[i] & LB32_GSUM) : (w[i] & LB32_VAL);
         const bool in = !stop && hi - i >= lo;
-        if (in && flag != 0) {
-            acc += w[i] & LB32_VAL;
+        if (in && ready) {
+            acc += v;
             ++used;
         }
-        if (in && flag == 0) stalled = true;
-        if (in && flag != 1) {
-            inc = inc || flag == 2;
+        if (in && !ready) stalled = true;
+        if (in && (!ready || is_inc)) {
+            inc = inc || is_inc;
             stop = true;
         }
     }
     return used;
 }
 
-// Adds the values of status words hi, hi - 1, ..., lo (WIN per round, waiting for unpublished
-// ones) to acc, or of the words down to the first inclusive one; returns true if it met an
+// Adds the values of status words hi, hi - 1, ..., lo (WIN per round, waiting for words not
+// ready) to acc, or of the words down to the first inclusive one; returns true if it met an
 // inclusive word (or gave up at the spin limit, with GSC_ERR_INTERNAL set).
 template <int WIN>
 __device__ __attribute__((always_inline)) inline bool lookback32_walk(const uint32_t *status, uint32_t stride, int64_t hi,
-                                                                     int64_t lo, uint32_t &acc, Ctrl *ctrl)
+                                                                     int64_t lo, uint32_t group, uint32_t &acc,
+                                                                     Ctrl *ctrl)
 {
     int64_t j = hi;
     uint32_t spins = 0;
@@ -470,7 +480,7 @@ __device__ __attribute__((always_inline)) inline bool lookback32_walk(const uint
         uint32_t w[WIN];
         lookback32_load<WIN>(status, stride, j, lo, w);
         bool inc, stalled;
-        j -= lookback32_take<WIN>(w, j, lo, acc, inc, stalled);
+        j -= lookback32_take<WIN>(w, j, lo, group, acc, inc, stalled);
         if (inc) return true;
         if (stalled) {
             if (++spins > SPIN_LIMIT) {
@@ -488,25 +498,37 @@ __device__ __attribute__((always_inline)) inline uint32_t lookback32_resolve(uin
                                                                             uint32_t stride, uint32_t group, uint32_t tile,
                                                                             uint32_t agg, Ctrl *ctrl)
 {
-    if (tile == 0) return 0;
     const uint32_t g = tile / group, g0 = g * group;
-    const bool last = tile - g0 == group - 1;
-    // the group's earlier tiles (at most WIN) and the first window of the earlier groups, at once
-    uint32_t wa[WIN], wb[WIN];
-    lookback32_load<WIN>(status, stride, (int64_t)tile - 1, (int64_t)g0, wa);
-    if (g > 0) lookback32_load<WIN>(gstatus, stride, (int64_t)g - 1, 0, wb);
     uint32_t acc = 0;
-    bool inc, stalled;
-    const int ua = lookback32_take<WIN>(wa, (int64_t)tile - 1, (int64_t)g0, acc, inc, stalled);
-    // (in group 0 this always ends at tile 0's inclusive word)
-    bool done = inc || (stalled && lookback32_walk<WIN>(status, stride, (int64_t)tile - 1 - ua, (int64_t)g0, acc, ctrl));
-    if (!done && g > 0) {
-        if (last) st_relaxed32(&gstatus[(size_t)g * stride], LB32_AGG | (acc + agg));
-        const int ub = lookback32_take<WIN>(wb, (int64_t)g - 1, 0, acc, inc, stalled);
-        if (!inc) lookback32_walk<WIN>(gstatus, stride, (int64_t)g - 1 - ub, 0, acc, ctrl);
+    if (tile > 0) {
+        // the group's earlier tiles (at most WIN) and the first window of the earlier groups, at once
+        uint32_t wa[WIN], wb[WIN];
+        lookback32_load<WIN>(status, stride, (int64_t)tile - 1, (int64_t)g0, wa);
+        if (g > 0) lookback32_load<WIN>(gstatus, stride, (int64_t)g - 1, 0, wb);
+        bool inc, stalled;
+        const int ua = lookback32_take<WIN>(wa, (int64_t)tile - 1, (int64_t)g0, 0, acc, inc, stalled);
+        // (in group 0 this always ends at tile 0's inclusive word)
+        const bool done =
+            inc || (stalled && lookback32_walk<WIN>(status, stride, (int64_t)tile - 1 - ua, (int64_t)g0, 0, acc, ctrl));
+        if (!done && g > 0) {
+            const int ub = lookback32_take<WIN>(wb, (int64_t)g - 1, 0, group, acc, inc, stalled);
+            if (!inc) lookback32_walk<WIN>(gstatus, stride, (int64_t)g - 1 - ub, 0, group, acc, ctrl);
+        }
+        st_relaxed32(&status[(size_t)tile * stride], LB32_INC | (acc + agg));
     }
-    st_relaxed32(&status[(size_t)tile * stride], LB32_INC | (acc + agg));
-    if (last) st_relaxed32(&gstatus[(size_t)g * stride], LB32_INC | (acc + agg));
+    if (tile - g0 == group - 1) {
+        // the group's word becomes its inclusive count once every tile of the group has added to it
+        uint32_t *gw = &gstatus[(size_t)g * stride];
+        uint32_t spins = 0;
+        while ((ld_relaxed32(gw) >> 25) != group) {
+            if (++spins > SPIN_LIMIT) {
+                set_error(ctrl, GSC_ERR_INTERNAL);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+        st_relaxed32(gw, LB32_INC | (acc + agg));
+    }
     return acc;
 }
 

@@ -468,6 +468,7 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_pass(TileMap m, int pass)
     // before the tile's range and the error word are checked.
     static_assert(SORT_THREADS >= SORT_BINS, "one thread per digit");
     static_assert(SORT_LB_GROUP <= (uint32_t)WIN + 1, "a group's earlier tiles fit one look-back window");
+    static_assert(SORT_LB_GROUP < 32 && (uint64_t)SORT_LB_GROUP * TILE <= LB32_GSUM, "a group word's arrivals and sum fit");
     const bool dig = tid < (uint32_t)SORT_BINS;
     const uint32_t d = dig ? tid : 0u;
     uint64_t key[KPT];
@@ -515,7 +516,7 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_pass(TileMap m, int pass)
                 run += c;
             }
             tile_cnt = run;
-            lookback32_publish(status_d, SORT_BINS, tile, tile_cnt);
+            lookback32_publish(status_d, gstatus_d, SORT_BINS, SORT_LB_GROUP, tile, tile_cnt);
         }
         // the exclusive scans of the frame's digit counts and of the tile's, side by side
         const uint32_t vh = dig ? gh : 0u;
