@@ -308,25 +308,15 @@ __global__ __launch_bounds__(VOX_THREADS) void k_voxelize(TileMap m)
     const uint32_t f = frame_of(m, blockIdx.x);
     const CAS FrameDesc &fd = *cp(m.fd[f]);  // (not written while the kernel runs)
     Ctrl *ctrl = fd.ctrl;
-    if (load_error(ctrl)) return;
     const uint32_t b = blockIdx.x - m.start[f];
     const uint32_t n = fd.n, J = fd.J, P = fd.P, bits = fd.sort_bits, bins = 1u << bits;
     __shared__ uint32_t s_hist[SORT_HIST_WORDS];
-    for (uint32_t i = threadIdx.x; i < P * bins; i += VOX_THREADS) s_hist[i] = 0;
-    {   // this workgroup's share of the sort's look-back status words (they lie outside the
-        // region the setup kernel zeroes, since only an encode sorts)
-        const uint32_t nb = n ? (n + VOX_TILE - 1) / VOX_TILE : 1u;
-        const uint64_t nq = (uint64_t)P * (fd.sort_tiles + sort_groups(fd.sort_tiles)) * bins / 4;
-        uint4 *z = reinterpret_cast<uint4 *>(fd.sort_status);
-        for (uint64_t i = (uint64_t)b * VOX_THREADS + threadIdx.x; i < nq; i += (uint64_t)nb * VOX_THREADS)
-            z[i] = make_uint4(0, 0, 0, 0);
-    }
     const uint32_t p0 = b * VOX_TILE;
     // Every load is issued before any is used, none under a condition (a loaded value used
-    // after a branch joins is waited for there): the thread's point coordinates (clamped
-    // indices; with no points, an in-bounds stand-in that is never used), then the bounding-box
-    // workgroups' partial extrema (clamped slots; read but unused when the caller gives the
-    // cube).
+    // after a branch joins is waited for there), and before the error word is checked: the
+    // thread's point coordinates (clamped indices; with no points, an in-bounds stand-in that is
+    // never used), then the bounding-box workgroups' partial extrema (clamped slots; read but
+    // unused when the caller gives the cube).
     float c[VOX_PPT][3];
     {
         const GAS float *src = n ? gp(fd.pos) : reinterpret_cast<const GAS float *>(gp(fd.bbox_part));
@@ -338,6 +328,16 @@ __global__ __launch_bounds__(VOX_THREADS) void k_voxelize(TileMap m)
             for (int a = 0; a < 3; ++a) c[r][a] = src[(size_t)i * 3 + a];
         }
     }
+    for (uint32_t i = threadIdx.x; i < P * bins; i += VOX_THREADS) s_hist[i] = 0;
+    {   // this workgroup's share of the sort's look-back status words (they lie outside the
+        // region the setup kernel zeroes, since only an encode sorts)
+        const uint32_t nb = n ? (n + VOX_TILE - 1) / VOX_TILE : 1u;
+        const uint64_t nq = (uint64_t)P * (fd.sort_tiles + sort_groups(fd.sort_tiles)) * bins / 4;
+        uint4 *z = reinterpret_cast<uint4 *>(fd.sort_status);
+        for (uint64_t i = (uint64_t)b * VOX_THREADS + threadIdx.x; i < nq; i += (uint64_t)nb * VOX_THREADS)
+            z[i] = make_uint4(0, 0, 0, 0);
+    }
+    const uint32_t err = load_error(ctrl);
     constexpr int NW = VOX_THREADS / WAVE;
     static_assert(BBOX_GRID_MAX <= 2 * VOX_THREADS, "two bounding-box slots per thread");
     __shared__ uint32_t s_bb[NW][6];
@@ -361,6 +361,7 @@ __global__ __launch_bounds__(VOX_THREADS) void k_voxelize(TileMap m)
             if (lane_id() == 0) s_bb[w][j] = r;
         }
     }
+    if (err) return;
     __syncthreads();
     double lo[3], cell;
     if (fd.bbox_mode == 0) {
@@ -595,35 +596,37 @@ __global__ __launch_bounds__(DEDUP_THREADS) void k_dedup(TileMap m)
 {
     constexpr int NW = DEDUP_THREADS / WAVE;
     static_assert(DEDUP_KPT * NW == WAVE, "one wave scans the (row, wave) head counts");
-    __shared__ uint32_t s_tile;
     __shared__ uint64_t s_k[DEDUP_TILE + 1];   // s_k[1 + i] = key base + i; s_k[0] = key base - 1
     __shared__ uint32_t s_cnt[DEDUP_KPT * NW + 1];
     __shared__ uint32_t s_hist[32];
     const uint32_t f = frame_of(m, blockIdx.x);
     const CAS FrameDesc &fd = *cp(m.fd[f]);  // (not written while the kernel runs)
     Ctrl *ctrl = fd.ctrl;
-    if (load_error(ctrl)) return;
     const uint32_t n = fd.n, J = fd.J;
     const uint32_t tid = threadIdx.x, w = tid / WAVE, lane = lane_id();
-    if (tid == 0) s_tile = tile_index(m, f);
-    if (tid < 32) s_hist[tid] = 0;
-    __syncthreads();
-    const uint32_t tile = s_tile;
+    const uint32_t tile = __builtin_amdgcn_readfirstlane(tile_index(m, f));
     const uint32_t base = tile * DEDUP_TILE;
-    if (base >= n) return;
-    const uint32_t len = min((uint32_t)DEDUP_TILE, n - base);
     const GAS uint64_t *K = gp((fd.P & 1) ? fd.keys_b : fd.keys_a);  // output of the last sort pass
     const GAS uint32_t *V = gp((fd.P & 1) ? fd.vals_b : fd.vals_a);
     // striped (coalesced) loads: position i = r * DEDUP_THREADS + tid; the sorted input rows
-    // are kept for the voxels' first members
+    // are kept for the voxels' first members. They are issued at clamped positions (the buffers
+    // hold at least one entry) before the tile's range and the error word are checked.
+    const uint32_t last = n ? n - 1 : 0u;
+    uint64_t kv[DEDUP_KPT];
     uint32_t pv[DEDUP_KPT];
 #pragma unroll
     for (int r = 0; r < DEDUP_KPT; ++r) {
-        const uint32_t i = r * DEDUP_THREADS + tid;
-        s_k[1 + i] = K[base + min(i, len - 1)];
-        pv[r] = V[base + min(i, len - 1)];
+        const uint32_t i = min(base + r * DEDUP_THREADS + tid, last);
+        kv[r] = K[i];
+        pv[r] = V[i];
     }
-    if (tid == 0) s_k[0] = base > 0 ? K[base - 1] : 0ull;
+    const uint64_t kprev = K[base > 0 ? min(base - 1, last) : 0u];
+    if (tid < 32) s_hist[tid] = 0;
+    if (base >= n || load_error(ctrl)) return;
+    const uint32_t len = min((uint32_t)DEDUP_TILE, n - base);
+#pragma unroll
+    for (int r = 0; r < DEDUP_KPT; ++r) s_k[1 + r * DEDUP_THREADS + tid] = kv[r];
+    if (tid == 0) s_k[0] = base > 0 ? kprev : 0ull;
     __syncthreads();
     // heads: a position starts a voxel when its key differs from the previous one
     uint32_t hbits = 0;
@@ -707,7 +710,6 @@ hipError_t launch_dedup(const TileMap &m, hipStream_t s)
 // per-depth decoupled look-back over (head count, open byte).
 __global__ __launch_bounds__(OCC_THREADS) void k_occupancy(TileMap m)
 {
-    __shared__ uint32_t s_tile;
     __shared__ uint64_t s_code[OCC_TILE + 1];
     __shared__ uint32_t s_bytes[GSC_MAX_DEPTH][OCC_TILE / 4];
     __shared__ uint32_t s_carry[GSC_MAX_DEPTH];
@@ -718,22 +720,32 @@ __global__ __launch_bounds__(OCC_THREADS) void k_occupancy(TileMap m)
     const uint32_t f = frame_of(m, blockIdx.x);
     const CAS FrameDesc &fd = *cp(m.fd[f]);  // (not written while the kernel runs)
     Ctrl *ctrl = fd.ctrl;
-    if (load_error(ctrl)) return;
-    const uint32_t J = fd.J, nv = ctrl->n_vox;
+    const uint32_t J = fd.J;
     const uint32_t tid = threadIdx.x;
-    if (tid == 0) s_tile = tile_index(m, f);
+    const uint32_t tile = __builtin_amdgcn_readfirstlane(tile_index(m, f));
+    const uint32_t s = tile * OCC_TILE;
+    // s_code[j] = L[s - 1 + j]: loaded at positions clamped to the buffer (it holds at least one
+    // entry), together with the voxel count and the error word, before any of them is used
+    const GAS uint64_t *leaf = gp(fd.leaf);
+    constexpr int OCC_LPT = (OCC_TILE + 1 + OCC_THREADS - 1) / OCC_THREADS;
+    const uint32_t lmax = fd.n ? fd.n - 1 : 0u;
+    uint64_t lc[OCC_LPT];
+#pragma unroll
+    for (int r = 0; r < OCC_LPT; ++r) {
+        const uint32_t j = min(tid + r * OCC_THREADS, (uint32_t)OCC_TILE);  // (entries past the tile: one line)
+        lc[r] = leaf[min(s + j > 0 ? s + j - 1 : 0u, lmax)];
+    }
+    const uint32_t nv = ctrl->n_vox;
     for (uint32_t i = tid; i < GSC_MAX_DEPTH * (OCC_TILE / 4); i += OCC_THREADS)
         (&s_bytes[0][0])[i] = 0;
     if (tid < GSC_MAX_DEPTH) s_carry[tid] = 0;
-    __syncthreads();
-    const uint32_t tile = s_tile;
-    const uint32_t s = tile * OCC_TILE;
-    if (s >= nv) return;
+    if (s >= nv || load_error(ctrl)) return;
     const uint32_t e = min(nv, s + OCC_TILE);
-    // s_code[j] = L[s - 1 + j]
-    const GAS uint64_t *leaf = gp(fd.leaf);
-    for (uint32_t j = tid; j < e - s + 1; j += OCC_THREADS)
-        s_code[j] = (s + j >= 1) ? leaf[s + j - 1] : 0ull;
+#pragma unroll
+    for (int r = 0; r < OCC_LPT; ++r) {
+        const uint32_t j = tid + r * OCC_THREADS;
+        if (j < e - s + 1) s_code[j] = s + j >= 1 ? lc[r] : 0ull;
+    }
     __syncthreads();
 
     uint32_t Dv[OCC_VPT];

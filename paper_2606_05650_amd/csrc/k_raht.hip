@@ -125,10 +125,10 @@ __device__ inline void prelude_tile(const TileMap &m, uint32_t f, int k, uint32_
 
     const CAS FrameDesc &fd = *cp(m.fd[f]);  // (not written while the kernel runs)
     Ctrl *ctrl = fd.ctrl;
-    if (load_error(ctrl)) return;
     if ((uint32_t)k > fd.K) return;
+    const uint32_t err = load_error(ctrl);  // (in flight while the sequence's size is read)
     const uint32_t nk = seq_size<LIVE>(fd, ctrl, k);
-    if (!seq_active(nk, k)) return;
+    if (err || !seq_active(nk, k)) return;
     auto &lv = fd.lv[k];
     const uint32_t s = tile * RT;
     if (s >= nk) return;  // uniform: the tile is past the end
@@ -390,12 +390,12 @@ __global__ __launch_bounds__(PRE_BLOCK1) void k_dec_prelude(TileMap m)
     const uint32_t f = frame_of(m, blockIdx.x);
     const uint32_t tile = tile_index(m, f);
     const CAS FrameDesc &fd = *cp(m.fd[f]);  // (not written while the kernel runs)
-    if (__builtin_amdgcn_readfirstlane(load_error(fd.ctrl))) return;
     const gsc_header *hg = reinterpret_cast<const gsc_header *>(fd.in_stream);
     const CAS gsc_header *h = cp(hg);
     const uint32_t J = fd.J, nv = h->n_vox;  // (checked by the octree decoding launch)
+    const uint32_t err = load_error(fd.ctrl);  // (after the header's loads: waited for with them)
     const uint32_t s = tile * RT;
-    if (s >= nv) return;
+    if (__builtin_amdgcn_readfirstlane(err) || s >= nv) return;
     const uint32_t t = threadIdx.x;
     const GAS uint32_t *par = gp(fd.dec_par);
     const GAS uint8_t *cbit = gp(fd.dec_cbit);
