@@ -235,8 +235,9 @@ gsc_status gsc_decode_batch(const gsc_stream_desc *streams, int32_t F, int32_t J
  * and look-back window width). Which one is fastest depends on the frame size: few large tiles
  * shorten the chain of tiles whose prefixes must be resolved, many small tiles fill more
  * compute units. The choice is kept in a process-wide table keyed by the depth J and the size
- * class ceil(log2(n_max)) of the largest frame of a call; untuned entries use the default.
- * All variants produce identical streams.
+ * class ceil(log2(n_max)) of the largest frame of a call; untuned entries use the default
+ * (variant 1, 2048-key tiles, for n_max <= 2^18; variant 0, 4096-key tiles, above). All variants
+ * produce identical streams.
  *
  * gsc_autotune -- times every variant on the caller's batch (each timed as reps encodes of the
  *   whole batch after one warm-up, exactly as gsc_encode_batch runs it, on `stream`), stores

@@ -135,7 +135,7 @@ int sort_variant_for(int J, uint64_t nmax)
 {
     if (g_force_variant >= 0) return g_force_variant;
     const int v = g_tune[J][size_class(nmax)].load(std::memory_order_relaxed);
-    return v > 0 ? v - 1 : SORT_DEFAULT_VARIANT;
+    return v > 0 ? v - 1 : sort_default_variant(nmax);
 }
 
 // ------------------------------------------------------------------- launch plumbing

@@ -26,7 +26,12 @@ struct SortVariant {
 };
 constexpr int SORT_VARIANTS = GSC_SORT_VARIANTS;
 constexpr SortVariant SORT_VARIANT[SORT_VARIANTS] = {{8, 16}, {4, 16}, {12, 16}, {8, 64}};
+// untuned tiling: 2048-key tiles for frames of at most 2^18 Gaussians (more workgroups for a
+// small sort), 4096-key tiles above
 constexpr int SORT_DEFAULT_VARIANT = 0;
+constexpr int SORT_SMALL_VARIANT = 1;
+constexpr uint64_t SORT_SMALL_MAX = 1ull << 18;
+inline int sort_default_variant(uint64_t n) { return n <= SORT_SMALL_MAX ? SORT_SMALL_VARIANT : SORT_DEFAULT_VARIANT; }
 constexpr int SORT_KPT_MIN = 4;
 __host__ __device__ constexpr int sort_tile(int variant) { return SORT_THREADS * SORT_VARIANT[variant].kpt; }
 // tiles per look-back group: a pass's status words are P x tiles x 2^bits tile words followed by

@@ -461,7 +461,13 @@ def tune_get(J, n):
     return v.value
 
 
-SORT_DEFAULT_VARIANT = 0
+SORT_DEFAULT_VARIANT = 0  # untuned tiling above 2^18 Gaussians (2048-key tiles, variant 1, below)
+SORT_SMALL_VARIANT, SORT_SMALL_MAX = 1, 1 << 18
+
+
+def sort_default_variant(n):
+    """The sort tiling used for frames of n Gaussians when nothing is tuned."""
+    return SORT_SMALL_VARIANT if n <= SORT_SMALL_MAX else SORT_DEFAULT_VARIANT
 _N_LIMIT = (1 << 30) - 1  # the largest frame the library takes
 _MAX_DEPTH = 21
 
@@ -476,7 +482,7 @@ def tune_table():
             if c > 0 and n <= (1 << (c - 1)):
                 break
             v = tune_get(J, n)
-            if v != SORT_DEFAULT_VARIANT:
+            if v != sort_default_variant(n):
                 out[(J, c)] = v
     return out
 

@@ -332,9 +332,12 @@ def test_rans_sizes_and_argument_checks():
 def test_tuning_table_round_trips_through_a_file(tmp_path):
     """The autotuner's table (host memory only, no GPU needed): entries set, saved, cleared,
     loaded back; the sizes of one class share an entry."""
+    # untuned sizes: 2048-key tiles up to 2^18 Gaussians, 4096-key tiles above
+    assert gsc.tune_get(10, 100_000) == 1 and gsc.tune_get(12, 1_000_000) == 0
+    assert gsc.sort_default_variant(1 << 18) == 1 and gsc.sort_default_variant((1 << 18) + 1) == 0
     gsc.tune_set(12, 1_000_000, 2)
     gsc.tune_set(14, 4_000_000, 3)
-    gsc.tune_set(10, 100_000, 0)          # the default: not listed
+    gsc.tune_set(10, 100_000, gsc.sort_default_variant(100_000))  # the default: not listed
     try:
         t = gsc.tune_table()
         assert t[(12, 20)] == 2 and t[(14, 22)] == 3 and (10, 17) not in t
@@ -349,3 +352,4 @@ def test_tuning_table_round_trips_through_a_file(tmp_path):
     finally:
         gsc.tune_set(12, 1_000_000, -1)
         gsc.tune_set(14, 4_000_000, -1)
+        gsc.tune_set(10, 100_000, -1)
