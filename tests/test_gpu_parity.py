@@ -38,6 +38,22 @@ def test_frame_roundtrip(n, J, seed):
     roundtrip(pos, attr, J, UNIFORM if J == 10 else GROUPED)
 
 
+@pytest.mark.parametrize("n,J", [
+    (16 * 2048, 12),        # 16 sort tiles of 2048 keys: exactly one look-back group
+    (16 * 2048 + 1, 10),    # 17 tiles: a second group of one tile (8-bit digits)
+    (33 * 2048 + 5, 12),    # 34 tiles: two full groups and a partial one
+    (1 << 18, 11),          # 128 tiles: the largest frame on 2048-key tiles, eight groups
+    ((1 << 18) + 1, 12),    # 65 tiles of 4096 keys: four groups and one tile
+])
+def test_sort_lookback_groups(n, J):
+    """The sort's two-level look-back (groups of 16 tiles, group totals summed at publication)
+    at group boundaries: the sorted order bit-exact against the oracle's stable sort, and the
+    whole round trip."""
+    assert gsc.tune_get(J, n) == gsc.sort_default_variant(n)
+    pos, attr = synth.make_frame(n, seed=n % 97)
+    roundtrip(pos, attr, J, GROUPED)
+
+
 def test_deep_uniform_frame_many_levels():
     """Uniform points at depth 21 (63-bit codes): every 512-entry tile leaves entries open, and
     two upper tiling levels carry entries (about 3600 and 90 at 200K), which the persistent
