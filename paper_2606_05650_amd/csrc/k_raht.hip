@@ -256,27 +256,37 @@ __device__ inline void prelude_tile(const TileMap &m, uint32_t f, int k, uint32_
     rank[0] = pex & 0xFFFFu;
     if (PRE_EPT > 1) rank[PRE_EPT - 1] = (ptot & 0xFFFFu) + (pex >> 16);
     lookback_block_publish<OpSum>(lv.status, 1, tile, total);
-    // ---- rounds: each chunk's own merges by its wave (levels ascending, no workgroup barrier)
+    // ---- rounds: each chunk's own merges by its wave (levels ascending, no workgroup barrier).
+    // A local merge's partner lies in the entry's own chunk, so the wave's chunks (one per entry
+    // slot) touch disjoint entries and walk the union of their levels in one loop.
     bool mine[PRE_EPT];
     uint32_t rnd[PRE_EPT];
+    uint64_t lm = 0;
 #pragma unroll
     for (int x = 0; x < PRE_EPT; ++x) {
         mine[x] = is_local[x] && cls[x] != CROSS;  // (then cls is the entry's own chunk)
         rnd[x] = 0;
-        uint64_t lm = mine[x] ? 1ull << lvl[x] : 0ull;
+        lm |= mine[x] ? 1ull << lvl[x] : 0ull;
+    }
 #pragma unroll
-        for (int o = 1; o < WAVE; o <<= 1) lm |= __shfl_xor(lm, o, WAVE);
-        lm = uniform64(lm);
-        while (lm) {
-            const uint32_t q = (uint32_t)(__ffsll((long long)lm) - 1);
-            lm &= ~(1ull << q);
+    for (int o = 1; o < WAVE; o <<= 1) lm |= __shfl_xor(lm, o, WAVE);
+    lm = uniform64(lm);
+    while (lm) {
+        const uint32_t q = (uint32_t)(__ffsll((long long)lm) - 1);
+        lm &= ~(1ull << q);
+        uint32_t prev[PRE_EPT];
+#pragma unroll
+        for (int x = 0; x < PRE_EPT; ++x)
+            prev[x] = mine[x] && lvl[x] == q ? max((uint32_t)s_rdl[left[x]], (uint32_t)s_rdl[jj[x]]) : 0u;
+#pragma unroll
+        for (int x = 0; x < PRE_EPT; ++x) {
             if (mine[x] && lvl[x] == q) {
-                rnd[x] = 1u + max((uint32_t)s_rdl[left[x]], (uint32_t)s_rdl[jj[x]]);
+                rnd[x] = 1u + prev[x];
                 s_rdl[left[x]] = (uint8_t)rnd[x];
             }
-            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-            __builtin_amdgcn_wave_barrier();
         }
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        __builtin_amdgcn_wave_barrier();
     }
     // ---- segment counts: a chunk's merges are counted by its own wave with ballots (only one
     // wave holds a chunk's merges; the rank in the ballot is the record's place in its segment);
