@@ -68,8 +68,8 @@ def alg_bytes(stage, n, nv, C):
 KERNEL_SOURCES = ("paper_2606_05650_amd/csrc/k_raht.hip", "paper_2606_05650_amd/csrc/gsc_device.h",
                   "paper_2606_05650_amd/csrc/gsc_internal.h")
 PMC_TRAFFIC = {"workload": "frame1M_J12",
-               "sources_sha256": "9a9f4f3ce128ce2860d22a92586f68c15bb21f635f2ae672bdc642f14230a4ba",
-               "raht_fwd1": 596720338, "raht_inv1": 467468554}
+               "sources_sha256": "9e55ad53cd1a33a3aeff009d200e738ce696785f0fce1bc41efb158629f7a588",
+               "raht_fwd1": 596994381, "raht_inv1": 467301521}
 KERNEL_NAMES = {"raht_fwd1": "k_raht_fwd", "raht_inv1": "k_raht_inv"}
 
 
