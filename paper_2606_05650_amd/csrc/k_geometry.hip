@@ -969,6 +969,20 @@ __global__ __launch_bounds__(DEC_THREADS) void k_dec_expand(TileMap m)
     const uint32_t tile = tile_index(m, f), tid = threadIdx.x, w = tid / WAVE, lane = lane_id();
     const gsc_header *hg = reinterpret_cast<const gsc_header *>(fd.in_stream);
     const CAS gsc_header *h = cp(hg);  // (the stream is not written while it is decoded)
+    // The tile's bytes are loaded before the header is checked, at positions clamped to the
+    // caller's stream (a checked header's occupancy bytes lie inside it, so the clamp changes no
+    // byte that is used); a stream shorter than the header fails the check and loads nothing.
+    const uint64_t s = (uint64_t)tile * DEC_TILE;
+    const GAS uint8_t *occ = gp(fd.in_stream + GSC_HEADER_BYTES);
+    uint32_t raw[DEC_PPT];
+    if (fd.in_bytes > GSC_HEADER_BYTES) {
+        const uint64_t qmax = fd.in_bytes - GSC_HEADER_BYTES - 1;
+#pragma unroll
+        for (int r = 0; r < DEC_PPT; ++r) raw[r] = occ[min(s + r * DEC_THREADS + tid, qmax)];
+    } else {
+#pragma unroll
+        for (int r = 0; r < DEC_PPT; ++r) raw[r] = 0u;
+    }
     __shared__ int s_ok;
     if (w == 0) {
         const bool ok = header_ok_wave(fd, h);
@@ -985,17 +999,15 @@ __global__ __launch_bounds__(DEC_THREADS) void k_dec_expand(TileMap m)
         ctrl->n_vox = nv;
         for (uint32_t d = 0; d <= J; ++d) ctrl->level_sizes[d] = h->level_sizes[d];
     }
-    const uint64_t s = (uint64_t)tile * DEC_TILE;
     if (s >= B) return;
     uint64_t total_nodes = 0;  // |L_1| + ... + |L_J|
     for (uint32_t d = 1; d <= J; ++d) total_nodes += h->level_sizes[d];
-    const GAS uint8_t *occ = gp(fd.in_stream + GSC_HEADER_BYTES);
     uint32_t bytes[DEC_PPT], wex[DEC_PPT];
     bool bad = false;
 #pragma unroll
     for (int r = 0; r < DEC_PPT; ++r) {
         const uint64_t q = s + r * DEC_THREADS + tid;
-        bytes[r] = q < B ? occ[q] : 0u;
+        bytes[r] = q < B ? raw[r] : 0u;
     }
 #pragma unroll
     for (int r = 0; r < DEC_PPT; ++r) {

@@ -80,12 +80,14 @@ __device__ inline float2 rotation(uint32_t w0, uint32_t w1, bool fp64)
 }
 
 // Whether a frame's rotations are computed in FP64: the encoder's flag, which a decoder reads
-// from the stream header.
+// from the stream header (only from a stream that holds one: a shorter stream fails the header
+// check, and the items that still ask here are not transformed).
 template <class FD>
 __device__ inline bool fp64_weights(FD &fd)
 {
     if (fd.mode == MODE_DECODE)
-        return (cp(reinterpret_cast<const gsc_header *>(fd.in_stream))->flags & GSC_FLAG_FP64_WEIGHTS) != 0;
+        return fd.in_bytes >= GSC_HEADER_BYTES &&
+               (cp(reinterpret_cast<const gsc_header *>(fd.in_stream))->flags & GSC_FLAG_FP64_WEIGHTS) != 0;
     return (fd.flags & GSC_FLAG_FP64_WEIGHTS) != 0;
 }
 
@@ -402,7 +404,9 @@ __global__ __launch_bounds__(PRE_BLOCK1) void k_dec_prelude(TileMap m)
     const CAS FrameDesc &fd = *cp(m.fd[f]);  // (not written while the kernel runs)
     const gsc_header *hg = reinterpret_cast<const gsc_header *>(fd.in_stream);
     const CAS gsc_header *h = cp(hg);
-    const uint32_t J = fd.J, nv = h->n_vox;  // (checked by the octree decoding launch)
+    // (checked by the octree decoding launch, which flags a stream shorter than the header: the
+    // count is read only from a stream that holds it)
+    const uint32_t J = fd.J, nv = fd.in_bytes >= GSC_HEADER_BYTES ? h->n_vox : 0u;
     const uint32_t err = load_error(fd.ctrl);  // (after the header's loads: waited for with them)
     const uint32_t s = tile * RT;
     if (__builtin_amdgcn_readfirstlane(err) || s >= nv) return;
@@ -1749,7 +1753,9 @@ __global__ __launch_bounds__(RAHT_THREADS) __attribute__((amdgpu_waves_per_eu(PE
         if (decode && it0.f != stf) {  // the frame's dequantization steps (once per frame)
             stf = it0.f;
             const CAS gsc_header *h = cp(reinterpret_cast<const gsc_header *>(d->in_stream));
-            if (tid < GSC_MAX_CHANNELS) s_st[tid] = h->quant_step[tid];
+            // (read only from a stream that holds a header: a shorter one fails the header check
+            // and none of its items is transformed)
+            if (tid < GSC_MAX_CHANNELS) s_st[tid] = d->in_bytes >= GSC_HEADER_BYTES ? h->quant_step[tid] : 0.0f;
         }
         __syncthreads();  // the previous item is no longer read from LDS; s_st is written
         // ---- the current item's schedule and coefficient rows into LDS (branch-free, see

@@ -149,6 +149,8 @@ def test_corrupt_streams_are_rejected():
     assert dec(bad) == 5
     assert dec(g["blob"], J=8) == 5         # depth mismatch
     assert dec(g["blob"][:2000]) == 5       # truncated
+    assert dec(g["blob"][:600]) == 5        # shorter than the header
+    assert dec(g["blob"][:16]) == 5         # shorter than the header's counts
 
 
 def test_transform_entry_points():
