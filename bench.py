@@ -68,8 +68,8 @@ def alg_bytes(stage, n, nv, C):
 KERNEL_SOURCES = ("paper_2606_05650_amd/csrc/k_raht.hip", "paper_2606_05650_amd/csrc/gsc_device.h",
                   "paper_2606_05650_amd/csrc/gsc_internal.h")
 PMC_TRAFFIC = {"workload": "frame1M_J12",
-               "sources_sha256": "9e55ad53cd1a33a3aeff009d200e738ce696785f0fce1bc41efb158629f7a588",
-               "raht_fwd1": 596994381, "raht_inv1": 467301521}
+               "sources_sha256": "d29633f7d6991844d930cd0d178fbbd3ae820d7fef3f80175d0fd3e50ae06bb6",
+               "raht_fwd1": 597703626, "raht_inv1": 468213737}
 KERNEL_NAMES = {"raht_fwd1": "k_raht_fwd", "raht_inv1": "k_raht_inv"}
 
 
