@@ -68,8 +68,8 @@ def alg_bytes(stage, n, nv, C):
 KERNEL_SOURCES = ("paper_2606_05650_amd/csrc/k_raht.hip", "paper_2606_05650_amd/csrc/gsc_device.h",
                   "paper_2606_05650_amd/csrc/gsc_internal.h")
 PMC_TRAFFIC = {"workload": "frame1M_J12",
-               "sources_sha256": "d29633f7d6991844d930cd0d178fbbd3ae820d7fef3f80175d0fd3e50ae06bb6",
-               "raht_fwd1": 597703626, "raht_inv1": 468213737}
+               "sources_sha256": "e5ef60489b8f98077173a7bf11525a09bc02247b87950c071075f9a9ffd07f4f",
+               "raht_fwd1": 598568584, "raht_inv1": 468114153}
 KERNEL_NAMES = {"raht_fwd1": "k_raht_fwd", "raht_inv1": "k_raht_inv"}
 
 

@@ -40,6 +40,9 @@ constexpr uint32_t SORT_LB_GROUP = 16;
 __host__ __device__ constexpr uint32_t sort_groups(uint32_t tiles) { return (tiles + SORT_LB_GROUP - 1) / SORT_LB_GROUP; }
 // histogram words of all passes: at most 8 passes of 256 digits or 7 of 512 (63-bit codes)
 constexpr int SORT_HIST_WORDS = 7 * 512;
+// copies of the digit histograms: the voxelize workgroup b adds into copy b mod 8 (245 device-scope
+// additions per word at 1M in one copy serialize), and a sort pass sums a digit's copies
+constexpr uint32_t SORT_HIST_COPIES = 8;
 
 constexpr int DEDUP_THREADS = 512;
 constexpr int DEDUP_KPT = 8;
@@ -107,7 +110,6 @@ struct Ctrl {
     uint64_t occ_bytes, coef_offset, total_bytes;
     double bbox_min[3];
     double cell;
-    uint32_t sort_hist[SORT_HIST_WORDS];
 };
 constexpr size_t CTRL_BYTES = 16384;
 static_assert(sizeof(Ctrl) <= CTRL_BYTES, "control block too large");
@@ -188,6 +190,7 @@ struct FrameDesc {
     uint32_t *bbox_part;     // encode: bounding-box workgroups' partial extrema (BBOX_SLOT each)
     uint32_t *lvl_flags;     // upper-level launches: the phase each workgroup has completed
     uint32_t *sort_status;   // P x (sort tiles + look-back groups) x 2^sort_bits
+    uint32_t *sort_hist;     // SORT_HIST_COPIES x P x 2^sort_bits digit counts (zeroed by setup)
     uint32_t sort_bits;      // radix digit width (8 or 9)
     uint64_t *dedup_status;
     uint64_t *occ_status;    // occ tiles x J
@@ -244,7 +247,7 @@ struct SetupArgs {
 };
 
 // ------------------------------------------------------------------ workspace layout
-// [Ctrl][FrameDesc][zero region: lookback status words][buffers ...]
+// [Ctrl][FrameDesc][sort status words][zero region: digit histograms, look-back status words][buffers ...]
 constexpr size_t DESC_OFF = CTRL_BYTES;
 constexpr size_t DESC_BYTES = 8192;
 static_assert(sizeof(FrameDesc) <= DESC_BYTES, "descriptor too large");
@@ -253,7 +256,7 @@ struct Layout {
     size_t total;
     size_t zero_off, zero_bytes;
     size_t keys_a, keys_b, vals_a, vals_b, leaf, vh, first, bbox_part, lvl_flags;
-    size_t sort_status, dedup_status, occ_status, dec_status, dec_par, dec_cbit;
+    size_t sort_status, sort_hist, dedup_status, occ_status, dec_status, dec_par, dec_cbit;
     uint32_t dec_tiles;      // decoder: tiles of DEC_TILE occupancy bytes (all levels together)
     uint64_t dec_nodes;      // decoder: worst-case nodes of levels 1..J
     uint32_t sort_tiles, dedup_tiles, occ_tiles, P, K;
@@ -309,10 +312,13 @@ __host__ __device__ inline bool make_layout(int64_t n, int J, int C, Layout *L)
     L->K = K;
     size_t off = DESC_OFF + DESC_BYTES;
     // the sort's status words (zeroed by the voxelize kernel of an encode, which precedes the
-    // sort), then the zero region: every other look-back status word and nothing else
+    // sort), then the zero region: the sort's digit histograms, every other look-back status
+    // word and nothing else
     L->sort_status = off;
     off = align_up(off + (size_t)L->P * (L->sort_tiles + sort_groups(L->sort_tiles)) * ((size_t)1 << sort_bits(J)) * 4, 256);
     L->zero_off = off;
+    L->sort_hist = off;
+    off = align_up(off + (size_t)SORT_HIST_COPIES * L->P * ((size_t)1 << sort_bits(J)) * 4, 256);
     L->dedup_status = off;
     off = align_up(off + (size_t)L->dedup_tiles * 8, 256);
     L->occ_status = off;

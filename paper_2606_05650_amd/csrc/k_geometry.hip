@@ -147,6 +147,7 @@ __global__ __launch_bounds__(256) void k_setup(SetupArgs a)
         fd->bbox_part = reinterpret_cast<uint32_t *>(fa.ws + L.bbox_part);
         fd->lvl_flags = reinterpret_cast<uint32_t *>(fa.ws + L.lvl_flags);
         fd->sort_status = reinterpret_cast<uint32_t *>(fa.ws + L.sort_status);
+        fd->sort_hist = reinterpret_cast<uint32_t *>(fa.ws + L.sort_hist);
         fd->dedup_status = reinterpret_cast<uint64_t *>(fa.ws + L.dedup_status);
         fd->occ_status = reinterpret_cast<uint64_t *>(fa.ws + L.occ_status);
         fd->dec_status = reinterpret_cast<uint64_t *>(fa.ws + L.dec_status);
@@ -300,7 +301,7 @@ hipError_t launch_bbox(const TileMap &m, hipStream_t s)
 // has no extent), then the Morton code of (x, y, z). The histograms of every radix digit of
 // the codes are accumulated for the sort passes.
 constexpr int VOX_THREADS = 512;
-constexpr int VOX_PPT = 8;  // few workgroups: each merges its digit histograms into the global ones
+constexpr int VOX_PPT = 8;  // few workgroups: each adds its digit histograms into one of the copies
 constexpr int VOX_TILE = VOX_THREADS * VOX_PPT;
 
 __global__ __launch_bounds__(VOX_THREADS) void k_voxelize(TileMap m)
@@ -407,8 +408,9 @@ __global__ __launch_bounds__(VOX_THREADS) void k_voxelize(TileMap m)
             atomicAdd(&s_hist[p * bins + ((key >> (p * bits)) & (bins - 1))], 1u);
     }
     __syncthreads();
+    uint32_t *hist = fd.sort_hist + (size_t)(blockIdx.x % SORT_HIST_COPIES) * P * bins;
     for (uint32_t i = threadIdx.x; i < P * bins; i += VOX_THREADS)
-        if (s_hist[i]) atomicAdd(&ctrl->sort_hist[i], s_hist[i]);
+        if (s_hist[i]) atomicAdd(&hist[i], s_hist[i]);
 }
 
 hipError_t launch_voxelize(const TileMap &m, hipStream_t s)
@@ -482,7 +484,9 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_pass(TileMap m, int pass)
         key[j] = kin[p];
         val[j] = pass == 0 ? p : vin[p];
     }
-    const uint32_t gh = ctrl->sort_hist[pass * SORT_BINS + d];
+    uint32_t gh = 0;  // the frame's count of digit d: the sum of its histogram copies
+#pragma unroll
+    for (uint32_t c = 0; c < SORT_HIST_COPIES; ++c) gh += fd.sort_hist[((size_t)c * fd.P + pass) * SORT_BINS + d];
     for (uint32_t i = tid; i < NW * SORT_BINS; i += SORT_THREADS) (&s_wcnt[0][0])[i] = 0;
     if (base >= n || load_error(ctrl)) return;
 #pragma unroll
