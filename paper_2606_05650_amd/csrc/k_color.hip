@@ -29,7 +29,8 @@ constexpr int COL_STAT_WAVES = COL_STAT_THREADS / WAVE;
 constexpr int COL_GROUPS = 16;         // 4-row MFMA groups summed in FP32 before joining the FP64 sums
 constexpr int COL_UNROLL = 4;          // groups whose loads are issued together
 constexpr uint32_t COL_ROWS_ALIGN = 4 * COL_GROUPS;
-constexpr int COL_APPLY_ROWS = WAVE;  // rows of a workgroup, one per thread
+constexpr int COL_APPLY_ROWS = WAVE;  // rows of a chunk, one per thread
+constexpr uint32_t COL_APPLY_GRID = 2048;  // workgroups of a per-row launch (eight per CU)
 
 struct ColorArgs {
     const float *in;     // [n][C]
@@ -302,93 +303,131 @@ __global__ __launch_bounds__(COL_BASIS_THREADS) void k_color_basis(ColorArgs a)
 }
 
 // ------------------------------------------------------------------------------ per row
-// A workgroup (one wave) stages COL_APPLY_ROWS rows in LDS (rows padded to an odd stride, so
-// that the threads' accesses to one column of their rows fall in distinct banks) with coalesced
-// loads (16-byte ones when the rows allow), each thread transforms one row (forward: YUV, then
-// a_c = E_c^T x_c; inverse: x_c = E_c a_c, then RGB), and the rows leave with coalesced stores.
-// Columns outside the SH range are copied.
+// A workgroup (one wave) takes the chunks of COL_APPLY_ROWS rows b, b + G, ... (G workgroups,
+// a few per CU). A chunk is staged in LDS (rows padded to an odd stride, so that the threads'
+// accesses to one column of their rows fall in distinct banks) from registers loaded one chunk
+// ahead with coalesced loads (16-byte ones when the rows allow): the next chunk's loads are in
+// flight while each thread transforms one row of the current one (forward: YUV, then
+// a_c = E_c^T x_c; inverse: x_c = E_c a_c, then RGB) and the rows leave with coalesced stores.
+// Columns outside the SH range are copied. The loads are unconditional at clamped positions
+// (past the last chunk a workgroup re-reads its own, and never uses it).
+constexpr int COL_APPLY_VPT = GSC_MAX_CHANNELS;  // values per thread and chunk (C <= 64)
 template <bool INV, bool VEC>
-__global__ __launch_bounds__(COL_APPLY_ROWS) void k_color_apply(ColorArgs a)
+__global__ __launch_bounds__(COL_APPLY_ROWS) __attribute__((amdgpu_waves_per_eu(VEC ? 2 : 1))) void k_color_apply(ColorArgs a)
 {
     extern __shared__ float s_rows[];
     __shared__ float s_E[3 * COL_AC * COL_AC];
     const uint32_t t = threadIdx.x, C = a.C, P = C | 1u;  // padded row stride (odd)
-    for (uint32_t i = t; i < 3u * COL_AC * COL_AC; i += COL_APPLY_ROWS) s_E[i] = gp(a.klt)[i];
-    const uint32_t row0 = blockIdx.x * COL_APPLY_ROWS;
-    const uint32_t nr = min((uint32_t)COL_APPLY_ROWS, a.n - row0);
-    const uint32_t nval = nr * C;
-    const GAS float *src = gp(a.in) + (size_t)row0 * C;
-    if (VEC) {  // C % 4 == 0 and 16-byte aligned rows: a float4 never straddles two rows
-        for (uint32_t i = t; i < nval / 4; i += COL_APPLY_ROWS) {
-            const float4 v = gload4(src + 4 * i);
-            float *d = s_rows + ((4 * i) / C) * P + (4 * i) % C;
-            d[0] = v.x;
-            d[1] = v.y;
-            d[2] = v.z;
-            d[3] = v.w;
-        }
-    } else {
-        for (uint32_t i = t; i < nval; i += COL_APPLY_ROWS) s_rows[(i / C) * P + i % C] = src[i];
-    }
-    __syncthreads();
-    if (t < nr) {
-        float *x = s_rows + t * P + a.sh0;
-        const float *M = INV ? a.mi : a.m;
-        // DC: the 3x3 step only
-        {
-            const float d0 = x[0], d1 = x[1], d2 = x[2];
+    const uint32_t nchunk = (a.n + COL_APPLY_ROWS - 1) / COL_APPLY_ROWS;
+    uint32_t ch = blockIdx.x;
+    if (ch >= nchunk) return;  // (uniform: the grid has at most one workgroup per chunk)
+    constexpr int NL = VEC ? COL_APPLY_VPT / 4 : COL_APPLY_VPT;  // loads per thread and chunk
+    float4 r4[VEC ? NL : 1];
+    float r1[VEC ? 1 : NL];
+    auto load = [&](uint32_t c) {
+        const uint32_t row0 = c * COL_APPLY_ROWS, nval = min((uint32_t)COL_APPLY_ROWS, a.n - row0) * C;
+        const GAS float *src = gp(a.in) + (size_t)row0 * C;
+        if (VEC) {  // C % 4 == 0 and 16-byte aligned rows: a float4 never straddles two rows
 #pragma unroll
-            for (int c = 0; c < 3; ++c) x[c] = M[3 * c] * d0 + M[3 * c + 1] * d1 + M[3 * c + 2] * d2;
-        }
-        float v[3][COL_AC];
-#pragma unroll
-        for (int c = 0; c < 3; ++c)
-#pragma unroll
-            for (int k = 0; k < COL_AC; ++k) v[c][k] = x[3 + COL_AC * c + k];
-        if (!INV) {
-            // YUV per function, then each channel's KLT
-            float y[3][COL_AC];
-#pragma unroll
-            for (int k = 0; k < COL_AC; ++k)
-#pragma unroll
-                for (int c = 0; c < 3; ++c) y[c][k] = M[3 * c] * v[0][k] + M[3 * c + 1] * v[1][k] + M[3 * c + 2] * v[2][k];
-#pragma unroll
-            for (int c = 0; c < 3; ++c)
-#pragma unroll
-                for (int j = 0; j < COL_AC; ++j) {
-                    float s = 0.f;
-#pragma unroll
-                    for (int i = 0; i < COL_AC; ++i) s += s_E[(c * COL_AC + i) * COL_AC + j] * y[c][i];
-                    x[3 + COL_AC * c + j] = s;
-                }
+            for (int u = 0; u < NL; ++u) r4[u] = gload4(src + 4 * min(t + (uint32_t)u * COL_APPLY_ROWS, nval / 4 - 1));
         } else {
-            // each channel's KLT undone, then RGB per function
-            float y[3][COL_AC];
+#pragma unroll
+            for (int u = 0; u < NL; ++u) r1[u] = src[min(t + (uint32_t)u * COL_APPLY_ROWS, nval - 1)];
+        }
+    };
+    load(ch);
+    for (uint32_t i = t; i < 3u * COL_AC * COL_AC; i += COL_APPLY_ROWS) s_E[i] = gp(a.klt)[i];
+    for (; ch < nchunk; ch += gridDim.x) {
+        const uint32_t row0 = ch * COL_APPLY_ROWS;
+        const uint32_t nr = min((uint32_t)COL_APPLY_ROWS, a.n - row0);
+        const uint32_t nval = nr * C;
+        __syncthreads();  // the previous chunk's rows are no longer read from LDS
+        if (VEC) {
+#pragma unroll
+            for (int u = 0; u < NL; ++u) {
+                const uint32_t i = t + (uint32_t)u * COL_APPLY_ROWS;
+                if (i < nval / 4) {
+                    float *d = s_rows + ((4 * i) / C) * P + (4 * i) % C;
+                    d[0] = r4[u].x;
+                    d[1] = r4[u].y;
+                    d[2] = r4[u].z;
+                    d[3] = r4[u].w;
+                }
+            }
+        } else {
+#pragma unroll
+            for (int u = 0; u < NL; ++u) {
+                const uint32_t i = t + (uint32_t)u * COL_APPLY_ROWS;
+                if (i < nval) s_rows[(i / C) * P + i % C] = r1[u];
+            }
+        }
+        __syncthreads();
+        load(ch + gridDim.x < nchunk ? ch + gridDim.x : ch);  // the next chunk's rows
+        if (t < nr) {
+            float *x = s_rows + t * P + a.sh0;
+            const float *M = INV ? a.mi : a.m;
+            // DC: the 3x3 step only
+            {
+                const float d0 = x[0], d1 = x[1], d2 = x[2];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) x[c] = M[3 * c] * d0 + M[3 * c + 1] * d1 + M[3 * c + 2] * d2;
+            }
+            float v[3][COL_AC];
 #pragma unroll
             for (int c = 0; c < 3; ++c)
 #pragma unroll
-                for (int i = 0; i < COL_AC; ++i) {
-                    float s = 0.f;
+                for (int k = 0; k < COL_AC; ++k) v[c][k] = x[3 + COL_AC * c + k];
+            if (!INV) {
+                // YUV per function (in place: function k's three values only), then each
+                // channel's KLT
 #pragma unroll
-                    for (int j = 0; j < COL_AC; ++j) s += s_E[(c * COL_AC + i) * COL_AC + j] * v[c][j];
-                    y[c][i] = s;
+                for (int k = 0; k < COL_AC; ++k) {
+                    const float r = v[0][k], g = v[1][k], b = v[2][k];
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) v[c][k] = M[3 * c] * r + M[3 * c + 1] * g + M[3 * c + 2] * b;
                 }
-#pragma unroll
-            for (int k = 0; k < COL_AC; ++k)
 #pragma unroll
                 for (int c = 0; c < 3; ++c)
-                    x[3 + COL_AC * c + k] = M[3 * c] * y[0][k] + M[3 * c + 1] * y[1][k] + M[3 * c + 2] * y[2][k];
+#pragma unroll
+                    for (int j = 0; j < COL_AC; ++j) {
+                        float s = 0.f;
+#pragma unroll
+                        for (int i = 0; i < COL_AC; ++i) s += s_E[(c * COL_AC + i) * COL_AC + j] * v[c][i];
+                        x[3 + COL_AC * c + j] = s;
+                    }
+            } else {
+                // each channel's KLT undone (one channel's 15 values at a time, back into v), then
+                // RGB per function
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    float y[COL_AC];
+#pragma unroll
+                    for (int i = 0; i < COL_AC; ++i) {
+                        float s = 0.f;
+#pragma unroll
+                        for (int j = 0; j < COL_AC; ++j) s += s_E[(c * COL_AC + i) * COL_AC + j] * v[c][j];
+                        y[i] = s;
+                    }
+#pragma unroll
+                    for (int i = 0; i < COL_AC; ++i) v[c][i] = y[i];
+                }
+#pragma unroll
+                for (int k = 0; k < COL_AC; ++k)
+#pragma unroll
+                    for (int c = 0; c < 3; ++c)
+                        x[3 + COL_AC * c + k] = M[3 * c] * v[0][k] + M[3 * c + 1] * v[1][k] + M[3 * c + 2] * v[2][k];
+            }
         }
-    }
-    __syncthreads();
-    GAS float *dst = gp(a.out) + (size_t)row0 * C;
-    if (VEC) {
-        for (uint32_t i = t; i < nval / 4; i += COL_APPLY_ROWS) {
-            const float *sr = s_rows + ((4 * i) / C) * P + (4 * i) % C;
-            gstore4(dst + 4 * i, make_float4(sr[0], sr[1], sr[2], sr[3]));
+        __syncthreads();
+        GAS float *dst = gp(a.out) + (size_t)row0 * C;
+        if (VEC) {
+            for (uint32_t i = t; i < nval / 4; i += COL_APPLY_ROWS) {
+                const float *sr = s_rows + ((4 * i) / C) * P + (4 * i) % C;
+                gstore4(dst + 4 * i, make_float4(sr[0], sr[1], sr[2], sr[3]));
+            }
+        } else {
+            for (uint32_t i = t; i < nval; i += COL_APPLY_ROWS) dst[i] = s_rows[(i / C) * P + i % C];
         }
-    } else {
-        for (uint32_t i = t; i < nval; i += COL_APPLY_ROWS) dst[i] = s_rows[(i / C) * P + i % C];
     }
 }
 
@@ -414,7 +453,8 @@ template <bool INV>
 static void launch_apply(const ColorArgs &a, hipStream_t s)
 {
     const bool vec = a.C % 4 == 0 && ((uintptr_t)a.in & 15u) == 0 && ((uintptr_t)a.out & 15u) == 0;
-    const dim3 grid((a.n + COL_APPLY_ROWS - 1) / COL_APPLY_ROWS), block(COL_APPLY_ROWS);
+    const uint32_t chunks = (a.n + COL_APPLY_ROWS - 1) / COL_APPLY_ROWS;
+    const dim3 grid(chunks < COL_APPLY_GRID ? chunks : COL_APPLY_GRID), block(COL_APPLY_ROWS);
     const size_t lds = (size_t)COL_APPLY_ROWS * (a.C | 1u) * sizeof(float);
     if (vec) hipLaunchKernelGGL((k_color_apply<INV, true>), grid, block, lds, s, a);
     else hipLaunchKernelGGL((k_color_apply<INV, false>), grid, block, lds, s, a);
