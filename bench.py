@@ -68,8 +68,8 @@ def alg_bytes(stage, n, nv, C):
 KERNEL_SOURCES = ("paper_2606_05650_amd/csrc/k_raht.hip", "paper_2606_05650_amd/csrc/gsc_device.h",
                   "paper_2606_05650_amd/csrc/gsc_internal.h")
 PMC_TRAFFIC = {"workload": "frame1M_J12",
-               "sources_sha256": "e5ef60489b8f98077173a7bf11525a09bc02247b87950c071075f9a9ffd07f4f",
-               "raht_fwd1": 598568584, "raht_inv1": 468114153}
+               "sources_sha256": "dad95ac0f3de1e7abc5656ae28dd6e92bdf63bc4274d9ef0f04169a914054597",
+               "raht_fwd1": 597987115, "raht_inv1": 468067301}
 KERNEL_NAMES = {"raht_fwd1": "k_raht_fwd", "raht_inv1": "k_raht_inv"}
 
 

@@ -170,14 +170,21 @@ gsc_status run_setup(const Frame *fr, int F, const SetupArgs &proto, hipStream_t
         SetupArgs a = proto;
         a.count = (uint32_t)((F - f0) < SETUP_MAX ? (F - f0) : SETUP_MAX);
         uint64_t zmax = 0;
+        uint32_t bmax = 0;  // the bounding-box workgroups of an encode that finds the cube
+        const bool bbox = a.mode == MODE_ENCODE && a.bbox_mode == 0 && !a.keep;
         for (uint32_t i = 0; i < a.count; ++i) {
-            a.f[i] = fr[f0 + i].a;
-            if (fr[f0 + i].L.zero_bytes > zmax) zmax = fr[f0 + i].L.zero_bytes;
+            const Frame &x = fr[f0 + i];
+            a.f[i] = x.a;
+            a.f[i].zero_off = x.L.zero_off;
+            a.f[i].zero_bytes = x.L.zero_bytes;
+            a.f[i].bbox_off = x.L.bbox_part;
+            if (x.L.zero_bytes > zmax) zmax = x.L.zero_bytes;
+            if (bbox && bbox_blocks(x.a.n) > bmax) bmax = bbox_blocks(x.a.n);
         }
-        uint32_t zb = ceil_div(zmax / 16 + 1, 256 * 4);
+        uint32_t zb = ceil_div(zmax / 16 + 1, SETUP_THREADS * 4);
         if (zb < 1) zb = 1;
         if (zb > 1024) zb = 1024;
-        GSC_LAUNCH(launch_setup(a, zb, s));
+        GSC_LAUNCH(launch_setup(a, zb > bmax + 1 ? zb : bmax + 1, s));
     }
     return GSC_OK;
 }
@@ -306,10 +313,6 @@ gsc_status encode_frames(const Frame *fr, int F, const gsc_params *p, hipStream_
     if (st != GSC_OK) return st;
     {
         StageScope sc(GSC_STAGE_SORT, s);
-        if (p->bbox_mode == 0) {
-            TileMap m = make_map(fr, F, [](const Frame &x) { return bbox_blocks(x.a.n); });
-            GSC_LAUNCH(launch_bbox(m, s));
-        }
         {
             TileMap m = make_map(fr, F, [](const Frame &x) { return voxelize_blocks(x.a.n); });
             GSC_LAUNCH(launch_voxelize(m, s));

@@ -80,14 +80,14 @@ constexpr uint32_t DONE_WORDS = 128, DONE_FWD = 0, DONE_INV = 32, TK_UPF = 80, P
                    FIN_INV = 83;
 static_assert(MAXK + 1 <= 32, "one completion counter per tiling level and direction");
 
-// Bounding box: at most BBOX_GRID_MAX workgroups per frame, each leaving its partial minima and
-// maxima (order-preserving uints of the floats) in a slot of BBOX_SLOT words, which the
-// voxelize workgroups combine.
+// Bounding box: at most BBOX_GRID_MAX workgroups per frame (blocks 1.. of the setup launch),
+// each leaving its partial minima and maxima (order-preserving uints of the floats) and a
+// non-finite flag in a slot of BBOX_SLOT words, which the voxelize workgroups combine.
 constexpr int BBOX_THREADS = 512;
 constexpr int BBOX_F4 = 8;              // float4 chunks per thread and batch, loaded at once
 constexpr uint32_t BBOX_CHUNKS = BBOX_THREADS * BBOX_F4;  // float4 chunks per batch
 constexpr uint32_t BBOX_GRID_MAX = 512;
-constexpr uint32_t BBOX_SLOT = 8;       // min x,y,z, max x,y,z, 2 unused
+constexpr uint32_t BBOX_SLOT = 8;       // min x,y,z, max x,y,z, a coordinate not finite, 1 unused
 __host__ __device__ inline uint32_t bbox_blocks(uint32_t n)
 {
     if (n == 0) return 1u;
@@ -231,8 +231,11 @@ struct FrameArgs {
     const uint64_t *codes_in;
     float *aref;
     const float *grad_add;
+    // filled from the frame's layout by the host: the zero region and the bounding-box slots
+    uint64_t zero_off, zero_bytes, bbox_off;
 };
 constexpr int SETUP_MAX = 16;
+constexpr int SETUP_THREADS = BBOX_THREADS;  // the setup blocks also take the bounding-box partials
 struct SetupArgs {
     uint32_t count;
     uint32_t J, C, mode, bbox_mode;
@@ -366,7 +369,6 @@ __host__ __device__ inline bool make_layout(int64_t n, int J, int C, Layout *L)
 
 // Launch helpers (defined next to their kernels). Each returns the launch status.
 hipError_t launch_setup(const SetupArgs &a, uint32_t zero_blocks, hipStream_t s);
-hipError_t launch_bbox(const TileMap &m, hipStream_t s);  // grid: bbox_blocks(n) per frame
 hipError_t launch_voxelize(const TileMap &m, hipStream_t s);
 hipError_t launch_sort_pass(const TileMap &m, int pass, int variant, int bits, hipStream_t s);
 hipError_t launch_dedup(const TileMap &m, hipStream_t s);

@@ -7,30 +7,36 @@
 namespace gsc {
 
 // ====================================================================== setup / finish
-// grid (zero_blocks, F): block (b, f) zeroes its share of frame f's look-back status words;
-// block (0, f) also builds the frame descriptor and initialises the control block.
-__global__ __launch_bounds__(256) void k_setup(SetupArgs a)
+// grid (blocks, F), SETUP_THREADS threads: block (b, f) zeroes its share of frame f's zero
+// region (look-back status words, digit histograms); in an encode that finds the bounding cube,
+// blocks 1 .. bbox_blocks(n) also take the frame's bounding-box partials (bbox_partial); block
+// (0, f) builds the frame descriptor and initialises the control block. The zero region and the
+// bounding-box slots come from the host's layout, so only block 0 computes it.
+__device__ inline void bbox_partial(const float *pos_, uint32_t n, uint32_t b, uint32_t G, GAS uint32_t *slot);
+
+__global__ __launch_bounds__(SETUP_THREADS) void k_setup(SetupArgs a)
 {
     const uint32_t f = blockIdx.y;
     if (f >= a.count) return;
     const FrameArgs &fa = a.f[f];
-    __shared__ size_t s_zero_off, s_zero_bytes;
-    __shared__ Layout s_L;
-    if (threadIdx.x == 0) {
-        make_layout((int64_t)fa.n, (int)a.J, (int)a.C, &s_L);
-        s_zero_off = s_L.zero_off;
-        s_zero_bytes = s_L.zero_bytes;
-    }
-    __syncthreads();
     // zero the look-back status region (16-byte stores; the region is 256-byte aligned)
     if (!a.keep) {
-        uint4 *z = reinterpret_cast<uint4 *>(fa.ws + s_zero_off);
-        const size_t nq = s_zero_bytes / 16;
+        uint4 *z = reinterpret_cast<uint4 *>(fa.ws + fa.zero_off);
+        const size_t nq = fa.zero_bytes / 16;
         const size_t stride = (size_t)gridDim.x * blockDim.x;
         for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < nq; i += stride)
             z[i] = make_uint4(0, 0, 0, 0);
     }
+    if (a.mode == MODE_ENCODE && a.bbox_mode == 0 && !a.keep) {
+        const uint32_t G = bbox_blocks(fa.n);
+        if (blockIdx.x >= 1 && blockIdx.x <= G)
+            bbox_partial(fa.pos, fa.n, blockIdx.x - 1, G,
+                         gp(reinterpret_cast<uint32_t *>(fa.ws + fa.bbox_off)) + (size_t)(blockIdx.x - 1) * BBOX_SLOT);
+    }
     if (blockIdx.x != 0) return;
+    __shared__ Layout s_L;
+    if (threadIdx.x == 0) make_layout((int64_t)fa.n, (int)a.J, (int)a.C, &s_L);
+    __syncthreads();
     {   // the upper-level phase flags and the transforms' completion counters start at zero in
         // every call, also one that keeps the state
         uint32_t *fl = reinterpret_cast<uint32_t *>(fa.ws + s_L.lvl_flags);
@@ -158,10 +164,10 @@ __global__ __launch_bounds__(256) void k_setup(SetupArgs a)
     }
 }
 
-hipError_t launch_setup(const SetupArgs &a, uint32_t zero_blocks, hipStream_t s)
+hipError_t launch_setup(const SetupArgs &a, uint32_t blocks, hipStream_t s)
 {
-    dim3 grid(zero_blocks, a.count);
-    hipLaunchKernelGGL(k_setup, grid, dim3(256), 0, s, a);
+    dim3 grid(blocks, a.count);
+    hipLaunchKernelGGL(k_setup, grid, dim3(SETUP_THREADS), 0, s, a);
     return hipGetLastError();
 }
 
@@ -197,20 +203,17 @@ __device__ inline float ord2f(uint32_t o)
 // The positions are read as one flat array of 3n floats in float4 chunks (chunk q holds the
 // coordinates 4q .. 4q+3, whose axes are (q + i) mod 3 since 4 = 1 mod 3), in batches of
 // BBOX_CHUNKS chunks: workgroup b of G takes batches b, b + G, ...; each thread issues all of a
-// batch's loads at once. A workgroup leaves its extrema in its own slot: no atomics, whose
-// same-line updates serialize at the memory side.
-__global__ __launch_bounds__(BBOX_THREADS) void k_bbox(TileMap m)
+// batch's loads at once. A workgroup (BBOX_THREADS threads, all calling) leaves its extrema in
+// its own slot, words 0-5, and in word 6 whether it met a coordinate that is not finite: no
+// atomics (their same-line updates serialize at the memory side), and no error word, which the
+// setup kernel that runs this clears at the same time.
+__device__ inline void bbox_partial(const float *pos_, uint32_t n, uint32_t b, uint32_t G, GAS uint32_t *slot)
 {
-    const uint32_t f = frame_of(m, blockIdx.x);
-    const CAS FrameDesc &fd = *cp(m.fd[f]);  // (not written while the kernel runs)
-    Ctrl *ctrl = fd.ctrl;
-    const uint32_t b = blockIdx.x - m.start[f];
-    const uint32_t G = m.start[f + 1] - m.start[f];  // = bbox_blocks(n)
-    const uint64_t nf = 3ull * fd.n;      // coordinates
+    const uint64_t nf = 3ull * n;         // coordinates
     const uint64_t nq = nf / 4;            // whole float4 chunks
     const uint64_t nbatch = (nq + BBOX_CHUNKS - 1) / BBOX_CHUNKS;
-    const GAS float *pos = gp(fd.pos);
-    const bool vec = ((uintptr_t)fd.pos & 15u) == 0;
+    const GAS float *pos = gp(pos_);
+    const bool vec = ((uintptr_t)pos_ & 15u) == 0;
     float mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
     bool bad = false;
     for (uint64_t c = b; c < nbatch; c += G) {
@@ -266,12 +269,15 @@ __global__ __launch_bounds__(BBOX_THREADS) void k_bbox(TileMap m)
             mx[a] = fmaxf(mx[a], ak == (uint32_t)a ? e : -INFINITY);
         }
     }
-    if (__ballot(bad) && lane_id() == 0) set_error(ctrl, GSC_ERR_INVALID_ARG);
     // order-preserving uints (so that -0 < +0 as in an ordered comparison), reduced per wave
     // with shuffles, then across the waves in LDS
     constexpr int NW = BBOX_THREADS / WAVE;
-    __shared__ uint32_t s_o[NW][6];
+    __shared__ uint32_t s_o[NW][7];
     const uint32_t w = threadIdx.x / WAVE;
+    {
+        const uint64_t bw = __ballot(bad);
+        if (lane_id() == 0) s_o[w][6] = bw ? 1u : 0u;
+    }
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         const uint32_t lo = wave_umin(f2ord(mn[a])), hi = wave_umax(f2ord(mx[a]));
@@ -281,18 +287,12 @@ __global__ __launch_bounds__(BBOX_THREADS) void k_bbox(TileMap m)
         }
     }
     __syncthreads();
-    if (threadIdx.x < 6) {
+    if (threadIdx.x < 7) {
         const uint32_t j = threadIdx.x;
         uint32_t o = s_o[0][j];
-        for (int ww = 1; ww < NW; ++ww) o = j < 3 ? min(o, s_o[ww][j]) : max(o, s_o[ww][j]);
-        gp(fd.bbox_part)[(size_t)b * BBOX_SLOT + j] = o;
+        for (int ww = 1; ww < NW; ++ww) o = j < 3 ? min(o, s_o[ww][j]) : max(o, s_o[ww][j]);  // (flag: max)
+        slot[j] = o;
     }
-}
-
-hipError_t launch_bbox(const TileMap &m, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_bbox, dim3(m.start[m.F]), dim3(BBOX_THREADS), 0, s, m);
-    return hipGetLastError();
 }
 
 // ===================================================== voxelize + Morton + digit histograms
@@ -341,29 +341,38 @@ __global__ __launch_bounds__(VOX_THREADS) void k_voxelize(TileMap m)
     const uint32_t err = load_error(ctrl);
     constexpr int NW = VOX_THREADS / WAVE;
     static_assert(BBOX_GRID_MAX <= 2 * VOX_THREADS, "two bounding-box slots per thread");
-    __shared__ uint32_t s_bb[NW][6];
+    __shared__ uint32_t s_bb[NW][7];
     {
         const uint32_t G = bbox_blocks(n);
         const GAS uint32_t *part = gp(fd.bbox_part);
-        uint32_t o[6];
+        uint32_t o[7];  // minima, maxima, and whether a slot met a coordinate that is not finite
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             const uint32_t slot = min(threadIdx.x + h * VOX_THREADS, G - 1);
             const int4 x = gload4i(reinterpret_cast<const GAS int32_t *>(part + (size_t)slot * BBOX_SLOT));
-            const uint32_t y0 = part[(size_t)slot * BBOX_SLOT + 4], y1 = part[(size_t)slot * BBOX_SLOT + 5];
-            const uint32_t v[6] = {(uint32_t)x.x, (uint32_t)x.y, (uint32_t)x.z, (uint32_t)x.w, y0, y1};
+            const uint32_t y0 = part[(size_t)slot * BBOX_SLOT + 4], y1 = part[(size_t)slot * BBOX_SLOT + 5],
+                           y2 = part[(size_t)slot * BBOX_SLOT + 6];
+            const uint32_t v[7] = {(uint32_t)x.x, (uint32_t)x.y, (uint32_t)x.z, (uint32_t)x.w, y0, y1, y2};
 #pragma unroll
-            for (int j = 0; j < 6; ++j) o[j] = h == 0 ? v[j] : (j < 3 ? min(o[j], v[j]) : max(o[j], v[j]));
+            for (int j = 0; j < 7; ++j) o[j] = h == 0 ? v[j] : (j < 3 ? min(o[j], v[j]) : max(o[j], v[j]));
         }
         const uint32_t w = threadIdx.x / WAVE;
 #pragma unroll
-        for (int j = 0; j < 6; ++j) {
+        for (int j = 0; j < 7; ++j) {
             const uint32_t r = j < 3 ? wave_umin(o[j]) : wave_umax(o[j]);
             if (lane_id() == 0) s_bb[w][j] = r;
         }
     }
     if (err) return;
     __syncthreads();
+    if (fd.bbox_mode == 0) {  // (the slots are written only when the cube is found here)
+        uint32_t nonfinite = 0;
+        for (int ww = 0; ww < NW; ++ww) nonfinite |= s_bb[ww][6];
+        if (nonfinite) {
+            if (b == 0 && threadIdx.x == 0) set_error(ctrl, GSC_ERR_INVALID_ARG);
+            return;
+        }
+    }
     double lo[3], cell;
     if (fd.bbox_mode == 0) {
         double ext = 0.0;

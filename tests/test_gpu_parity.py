@@ -153,6 +153,23 @@ def test_corrupt_streams_are_rejected():
     assert dec(g["blob"][:16]) == 5         # shorter than the header's counts
 
 
+def test_nonfinite_positions_are_rejected():
+    """A position that is not finite makes an encode that finds the bounding cube fail with
+    GSC_ERR_INVALID_ARG (device status), whether it lies in the float4 batches or in the last
+    coordinates that do not fill one (3n mod 4 of them); a finite frame then encodes as usual."""
+    dev = _dev()
+    for n, row, axis in [(5000, 1234, 1), (5001, 5000, 2)]:
+        pos, attr = synth.make_frame(n, seed=21)
+        p = gsc.make_params(10, attr.shape[1], GROUPED)
+        for bad_val in (np.nan, np.inf, -np.inf):
+            bad = pos.copy()
+            bad[row, axis] = bad_val
+            e = gsc.encode_frame(torch.from_numpy(bad).to(dev), torch.from_numpy(attr).to(dev), p)
+            torch.cuda.synchronize()
+            assert int(e.host_info()[0]) == 1, (n, bad_val)
+    roundtrip(*synth.make_frame(5001, seed=21), 10, GROUPED)
+
+
 def test_transform_entry_points():
     dev = _dev()
     rng = np.random.default_rng(16)
