@@ -115,11 +115,11 @@ def cpu_info():
 
 
 def phase_bytes(n, nv, J, occ_bytes):
-    """Algorithmic bytes of the sort stage (bounding box, voxelize, radix sort passes, unique)
-    and of the occupancy stage."""
+    """Algorithmic bytes of the sort stage (voxelize, radix sort passes, unique; the bounding
+    box runs in the setup launch, outside the stage) and of the occupancy stage."""
     bits = 9 if (3 * J + 8) // 9 < (3 * J + 7) // 8 else 8  # the radix digit width
     P = (3 * J + bits - 1) // bits
-    sort = 12 * n + (12 * n + 8 * n) + (P * 24 * n - 4 * n) + (8 * n + 12 * nv)
+    sort = (12 * n + 8 * n) + (P * 24 * n - 4 * n) + (8 * n + 12 * nv)
     occ = 8 * nv + occ_bytes
     return sort, occ
 
