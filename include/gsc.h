@@ -241,7 +241,8 @@ gsc_status gsc_decode_batch(const gsc_stream_desc *streams, int32_t F, int32_t J
  *
  * gsc_autotune -- times every variant on the caller's batch (each timed as reps encodes of the
  *   whole batch after one warm-up, exactly as gsc_encode_batch runs it, on `stream`), stores
- *   the fastest in the table for this batch's key and returns it in *chosen (optional);
+ *   the fastest in the table for this batch's key (the default instead, unless the fastest is
+ *   at least 2 % faster than it) and returns it in *chosen (optional);
  *   times_ms (optional, GSC_SORT_VARIANTS floats) receives the mean time of each. Arguments
  *   and buffers as for gsc_encode_batch; the frames are encoded (the outputs of the last run
  *   remain). SYNCHRONOUS: it waits for the stream, so it must not be called while the stream

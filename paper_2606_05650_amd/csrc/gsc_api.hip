@@ -482,6 +482,8 @@ gsc_status gsc_encode_batch(const gsc_frame_desc *frames, int32_t F, const gsc_p
     return encode_frames(fr, F, params, static_cast<hipStream_t>(stream));
 }
 
+constexpr float SORT_TUNE_MARGIN = 0.02f;  // the autotuner keeps the default unless another is 2 % faster
+
 gsc_status gsc_autotune(const gsc_frame_desc *frames, int32_t F, const gsc_params *params,
                         int32_t reps, int32_t *chosen, float *times_ms, void *stream)
 {
@@ -496,8 +498,7 @@ gsc_status gsc_autotune(const gsc_frame_desc *frames, int32_t F, const gsc_param
         (void)hipEventDestroy(e0);
         return GSC_ERR_HIP;
     }
-    float best = 0.0f;
-    int best_v = -1;
+    float t[SORT_VARIANTS] = {};
     for (int v = 0; v < SORT_VARIANTS && st == GSC_OK; ++v) {
         g_force_variant = v;
         st = encode_frames(fr, F, params, s);  // warm-up
@@ -509,10 +510,7 @@ gsc_status gsc_autotune(const gsc_frame_desc *frames, int32_t F, const gsc_param
             st = GSC_ERR_HIP;
         ms /= (float)reps;
         if (times_ms) times_ms[v] = ms;
-        if (st == GSC_OK && (best_v < 0 || ms < best)) {
-            best = ms;
-            best_v = v;
-        }
+        t[v] = ms;
     }
     g_force_variant = -1;
     (void)hipEventDestroy(e0);
@@ -520,6 +518,13 @@ gsc_status gsc_autotune(const gsc_frame_desc *frames, int32_t F, const gsc_param
     if (st != GSC_OK) return st;
     uint64_t nmax = 0;
     for (int f = 0; f < F; ++f) nmax = fr[f].a.n > nmax ? fr[f].a.n : nmax;
+    // the fastest tiling, unless it beats the size's default by less than the margin (a near
+    // tie is timing noise, and the default is the tiling measured best for the size)
+    int best_v = 0;
+    for (int v = 1; v < SORT_VARIANTS; ++v)
+        if (t[v] < t[best_v]) best_v = v;
+    const int d = sort_default_variant(nmax);
+    if (!(t[best_v] < (1.0f - SORT_TUNE_MARGIN) * t[d])) best_v = d;
     g_tune[params->J][size_class(nmax)].store(best_v + 1, std::memory_order_relaxed);
     if (chosen) *chosen = best_v;
     return GSC_OK;

@@ -463,6 +463,7 @@ def tune_get(J, n):
 
 SORT_DEFAULT_VARIANT = 0  # untuned tiling above 2^18 Gaussians (2048-key tiles, variant 1, below)
 SORT_SMALL_VARIANT, SORT_SMALL_MAX = 1, 1 << 18
+SORT_TUNE_MARGIN = 0.02  # autotune keeps the default unless another tiling is this much faster
 
 
 def sort_default_variant(n):

@@ -145,7 +145,11 @@ def test_autotune_picks_a_variant():
     try:
         v, times, outs = gsc.autotune(tens, p, reps=2)
         assert 0 <= v < gsc.SORT_VARIANTS and all(t > 0 for t in times)
-        assert times[v] == min(times)
+        d = gsc.sort_default_variant(nmax)  # kept unless the fastest beats it by the margin
+        if min(times) < (1 - gsc.SORT_TUNE_MARGIN) * times[d]:
+            assert times[v] == min(times)
+        else:
+            assert v == d
         assert gsc.tune_get(J, nmax) == v
         torch.cuda.synchronize()
         ref = gsc.encode_batch(tens, p)
